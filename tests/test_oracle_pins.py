@@ -1,0 +1,350 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: an
+independent algorithm, a hand-derived closed form, an invariance, finite
+differences, a series expansion, or a brute-force minimum.
+"""
+import copy
+
+import numpy as np
+import pytest
+import scipy.optimize
+
+from oracle import etdm as O
+from oracle import lbfgs as LB
+from oracle import scf
+from workloads import Instance, Workload, make_config, tiny_complex, tiny_real
+from workloads.gen import chain_hamiltonian, haar_orthogonal, rng_for
+
+
+def rand_skew_hermitian(M, rng, scale=0.7, real=False):
+    X = rng.standard_normal((M, M)) * scale
+    if not real:
+        X = X + 1j * rng.standard_normal((M, M)) * scale
+    return 0.5 * (X - X.conj().T)
+
+
+# ---------------------------------------------------------------------------
+# matrix exponential (Eq. ed, Eq. uinv)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M,real", [(1, False), (2, True), (7, False), (16, True), (33, False)])
+def test_expm_unitary_det_and_pade(M, real):
+    rng = np.random.default_rng(M)
+    A = rand_skew_hermitian(M, rng, real=real)
+    U = O.expm_eig(A)
+    assert np.abs(U.conj().T @ U - np.eye(M)).max() < 1e-14 * M
+    # det exp(A) = exp(Tr A): +1 for real A, unit modulus in general
+    assert abs(np.linalg.det(U) - np.exp(np.trace(A))) < 1e-13 * M
+    # independent algorithm: scaling and squaring with Pade (Eq. ss)
+    assert np.abs(U - O.expm_pade(A)).max() < 1e-13 * M
+
+
+def test_expm_plane_rotation_closed_form():
+    for th in (0.0, 1e-9, 0.3, -1.2, 3.0, 7.5):
+        A = np.array([[0.0, th], [-th, 0.0]])
+        U = O.expm_eig(A)
+        ref = np.array([[np.cos(th), np.sin(th)], [-np.sin(th), np.cos(th)]])
+        assert np.abs(U - ref).max() < 1e-15 * max(1.0, abs(th))
+
+
+@pytest.mark.parametrize("N,Nv,scale", [(3, 5, 0.4), (5, 3, 0.4), (4, 4, 1.5), (1, 6, 0.0),
+                                         (6, 2, 2.0), (16, 48, 0.05)])
+def test_hutter_closed_form_matches_eigh(N, Nv, scale):
+    """Corrected Eq. uinv equals Eq. ed, including N > Nv (rank-deficient P) and B = 0."""
+    B = np.random.default_rng(N * 10 + Nv).standard_normal((N, Nv)) * scale
+    U1 = O.expm_ov(B)
+    U2 = O.expm_eig(O.ov_generator(B))
+    assert np.abs(U1 - U2).max() < 1e-14 * (N + Nv)
+    assert np.abs(U1.T @ U1 - np.eye(N + Nv)).max() < 1e-14 * (N + Nv)
+
+
+def test_hutter_as_printed_is_not_exp():
+    """Reading of the garbled Eq. uinv: cos(P) in the top-left block (as printed)
+    is not the exponential; cos(P^{1/2}) is."""
+    B = np.random.default_rng(3).standard_normal((3, 4)) * 0.8
+    U = O.expm_eig(O.ov_generator(B))
+    s, X = np.linalg.eigh(B @ B.T)
+    printed_top_left = (X * np.cos(s)) @ X.T
+    assert np.abs(printed_top_left - U[:3, :3]).max() > 1e-2
+
+
+# ---------------------------------------------------------------------------
+# energy and gradient
+# ---------------------------------------------------------------------------
+
+def two_level_workload(a, b, c, U_hub):
+    H0 = np.array([[a, b], [b, c]])
+    inst = Instance(M=2, N=1, f=np.array([2.0, 0.0]), C0=np.eye(2), A=np.zeros((1, 1)), H0=H0)
+    return Workload(0, "two-level", "real_ov", U_hub, False, [inst])
+
+
+@pytest.mark.parametrize("th", [0.0, 0.2, -0.7, 1.3, 2.9])
+def test_two_level_closed_form(th):
+    """Hand-derived: orbital (cos th, -sin th), E = 2 <H0> + U/2 (n1^2 + n2^2),
+    dE/dth = 2 (c - a) sin 2th - 4 b cos 2th - 2 U sin 4th."""
+    a, b, c, Uh = -0.7, 0.3, 0.9, 0.5
+    wl = two_level_workload(a, b, c, Uh)
+    E, g = O.energy_grad(wl, [np.array([[th]])])
+    cs, sn = np.cos(th), np.sin(th)
+    E_ref = 2 * (a * cs * cs - 2 * b * cs * sn + c * sn * sn) + 0.5 * Uh * ((2 * cs * cs) ** 2 + (2 * sn * sn) ** 2)
+    g_ref = 2 * (c - a) * np.sin(2 * th) - 4 * b * np.cos(2 * th) - 2 * Uh * np.sin(4 * th)
+    assert abs(E - E_ref) < 1e-14
+    assert abs(g[0][0, 0] - g_ref) < 1e-14
+    E2, g2 = O.energy_grad_ov_workload(wl, [np.array([[th]])])
+    assert abs(E2 - E_ref) < 1e-14 and abs(g2[0][0, 0] - g_ref) < 1e-14
+
+
+def test_energy_at_zero_equals_reference_density():
+    wl = tiny_real(10, 3, seed=4)
+    inst = wl.instances[0]
+    rho0 = inst.C0 @ np.diag(inst.f) @ inst.C0.T
+    n = np.diag(rho0)
+    E_ref = np.sum(rho0 * inst.H0) + 0.5 * wl.hubbard_U * np.sum(n ** 2)
+    assert abs(O.energy(wl, O.zero_params(wl)) - E_ref) < 1e-13 * abs(E_ref)
+
+
+def _as_complex_full(wl):
+    w = copy.deepcopy(wl)
+    w.kind = "complex_full"
+    for inst in w.instances:
+        inst.C0 = inst.C0.astype(np.complex128)
+        inst.H0 = inst.H0.astype(np.complex128)
+    return w
+
+
+def test_occupied_occupied_invariance():
+    """For a unitary-invariant functional with equal occupations, rotations inside
+    the occupied (or virtual) block leave E unchanged (Sec. 3.4)."""
+    wl = _as_complex_full(tiny_real(9, 4, seed=2))
+    rng = np.random.default_rng(0)
+    A = np.zeros((9, 9), dtype=np.complex128)
+    A[:4, :4] = rand_skew_hermitian(4, rng, 0.8)
+    A[4:, 4:] = rand_skew_hermitian(5, rng, 0.8)
+    E0 = O.energy(wl, O.zero_params(wl))
+    assert abs(O.energy(wl, [np.triu(A)]) - E0) < 1e-13 * abs(E0)
+
+
+def test_gauge_covariance_of_ov_gradient():
+    """E(C0 W, Voo^T B Vvv) = E(C0, B) and g' = Voo^T g Vvv for W = blockdiag(Voo, Vvv)."""
+    wl = tiny_real(11, 4, seed=5, scale=0.3)
+    B = wl.instances[0].A
+    E, (g,) = O.energy_grad(wl, [B])
+    rng = np.random.default_rng(1)
+    Voo = haar_orthogonal(4, rng)
+    Vvv = haar_orthogonal(7, rng)
+    W = np.zeros((11, 11))
+    W[:4, :4], W[4:, 4:] = Voo, Vvv
+    wl2 = copy.deepcopy(wl)
+    wl2.instances[0].C0 = wl.instances[0].C0 @ W
+    E2, (g2,) = O.energy_grad(wl2, [Voo.T @ B @ Vvv])
+    assert abs(E2 - E) < 1e-13 * abs(E)
+    assert np.abs(g2 - Voo.T @ g @ Vvv).max() < 1e-13 * np.abs(g).max()
+
+
+def test_gradient_at_zero_is_commutator():
+    """At A = 0 the gradient is L^T exactly (Eq. app_grad): dE/dB_ij = -2 f_occ (H_MO)_{i,N+j}."""
+    wl = tiny_real(12, 5, seed=7)
+    inst = wl.instances[0]
+    E, (g,) = O.energy_grad(wl, O.zero_params(wl))
+    rho0 = inst.C0 @ np.diag(inst.f) @ inst.C0.T
+    H = inst.H0 + wl.hubbard_U * np.diag(np.diag(rho0))
+    H_MO = inst.C0.T @ H @ inst.C0
+    assert np.abs(g - (-2.0 * 2.0 * H_MO[:5, 5:])).max() < 1e-14
+
+
+def _fd_directional(wl, params, d, h):
+    kind = wl.kind
+    v = O.flatten(kind, params)
+
+    def E(t):
+        return O.energy(wl, O.unflatten(kind, wl, v + t * d))
+    # Richardson-extrapolated central difference (error O(h^4))
+    d1 = (E(h) - E(-h)) / (2 * h)
+    d2 = (E(h / 2) - E(-h / 2)) / h
+    return (4 * d2 - d1) / 3
+
+
+@pytest.mark.parametrize("case", ["real_ov", "real_ov_rankdef", "complex_fd_coupled", "complex_integer"])
+def test_gradient_matches_finite_differences(case):
+    if case == "real_ov":
+        wl = tiny_real(13, 4, seed=8, scale=0.35)
+    elif case == "real_ov_rankdef":
+        wl = tiny_real(7, 5, seed=9, scale=0.5)
+    elif case == "complex_fd_coupled":
+        wl = tiny_complex(8, nk_side=2, kT=0.3)
+        for inst in wl.instances:
+            inst.A = inst.A * 6.0  # larger rotations than the parity point
+    else:
+        wl = tiny_complex(6, nk_side=1, kT=0.01)
+    params = O.parity_params(wl)
+    E, grads = O.energy_grad(wl, params)
+    gv = O.flatten(wl.kind, grads)
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        d = rng.standard_normal(gv.size)
+        fd = _fd_directional(wl, params, d, 1e-3)
+        assert abs(fd - gv @ d) < 2e-9 * (np.abs(gv).sum() + 1.0)
+
+
+def test_gradient_per_entry_finite_differences_tiny():
+    wl = tiny_real(5, 2, seed=12, scale=0.6)
+    params = O.parity_params(wl)
+    _, (g,) = O.energy_grad(wl, params)
+    for i in range(2):
+        for j in range(3):
+            d = np.zeros_like(g)
+            d[i, j] = 1.0
+            fd = _fd_directional(wl, params, d.ravel(), 1e-3)
+            assert abs(fd - g[i, j]) < 1e-9
+
+
+def test_printed_divided_difference_sign_gives_minus_gradient():
+    """Reading of Sec. 3.4: D = (exp(-ix) - 1)/(ix) as printed yields -dE/dA; the
+    oracle uses D = (1 - exp(-ix))/(ix) = integral_0^1 exp(-itx) dt (Eq. gradients)."""
+    wl = tiny_real(8, 3, seed=13, scale=0.4)
+    A, L, Y = O.y_matrix(wl, O.parity_params(wl), 0)
+    w, V = O.eig_iA(A)
+    x = w[:, None] - w[None, :]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        Dp = np.where(np.abs(x) > 0, (np.exp(-1j * x) - 1.0) / (1j * np.where(x == 0, 1, x)), -1.0)
+    Yp = V @ ((V.conj().T @ L @ V) * Dp) @ V.conj().T
+    assert np.abs(Yp + Y).max() < 1e-12 * np.abs(Y).max()
+
+
+@pytest.mark.parametrize("complex_case", [False, True])
+def test_y_matches_bch_series(complex_case):
+    """Y equals the commutator series of Eq. grad_expansion."""
+    wl = tiny_complex(6, nk_side=1, kT=0.2) if complex_case else tiny_real(9, 3, seed=14, scale=0.3)
+    A, L, Y = O.y_matrix(wl, O.parity_params(wl), 0)
+    if complex_case:
+        A, L, Y = O.y_matrix(wl, [p * 8.0 for p in O.parity_params(wl)], 0)
+    Ys = O.bch_series_Y(A, L)
+    assert np.abs(Ys - Y).max() < 1e-13 * np.abs(Y).max()
+
+
+@pytest.mark.parametrize("M,N,scale", [(6, 2, 0.5), (7, 5, 0.8), (12, 4, 0.05), (20, 4, 1.0),
+                                       (9, 3, 0.0), (30, 6, 2.5)])
+def test_structured_ov_equals_dense(M, N, scale):
+    wl = tiny_real(M, N, seed=M + N, scale=max(scale, 1e-300))
+    if scale == 0.0:
+        wl.instances[0].A[:] = 0.0
+    p = O.parity_params(wl)
+    E, (g,) = O.energy_grad(wl, p)
+    E2, (g2,) = O.energy_grad_ov_workload(wl, p)
+    assert abs(E - E2) < 1e-13 * abs(E)
+    assert np.abs(g - g2).max() < 1e-12 * max(np.abs(g).max(), 1e-300)
+
+
+def test_pair_integrals_limits_and_closed_forms():
+    """mu1, mu2 vs their limits at 0 (-1/6, 1/3) and closed forms away from 0."""
+    sig = np.array([0.0, 1e-8, 0.7, 2.3, 7.6])
+    mu1, mu2 = O.ov_pair_integrals(sig)
+    assert abs(mu1[0, 0] + 1.0 / 6.0) < 1e-15 and abs(mu2[0, 0] - 1.0 / 3.0) < 1e-15
+    sk, sl = sig[2:, None], sig[None, 2:]
+    sincf = lambda x: np.sinc(x / np.pi)
+    Kc = 0.5 * (sincf(sk - sl) + sincf(sk + sl))
+    Ks = 0.5 * (sincf(sk - sl) - sincf(sk + sl))
+    assert np.abs(mu1[2:, 2:] - (Kc - sincf(sk)) / sl ** 2).max() < 1e-14
+    assert np.abs(mu2[2:, 2:] - Ks / (sk * sl)).max() < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# minima
+# ---------------------------------------------------------------------------
+
+def test_minimum_without_interaction_is_ky_fan_sum():
+    """U = 0: min E = sum_i f_i(desc) eps_i(asc) (von Neumann trace bound)."""
+    wl = tiny_real(14, 4, seed=15)
+    wl.hubbard_U = 0.0
+    st, _ = LB.minimize(wl)
+    ev = np.linalg.eigvalsh(wl.instances[0].H0)
+    assert np.linalg.norm(st.g) < 1e-8
+    assert abs(st.f - 2.0 * ev[:4].sum()) < 1e-10
+
+
+def test_minimum_complex_fractional_occupations_ky_fan():
+    wl = tiny_complex(8, nk_side=2, kT=0.3, hubbard_U=0.0)
+    st, _ = LB.minimize(wl)
+    ref = sum(i.weight * np.sort(i.f)[::-1] @ np.linalg.eigvalsh(i.H0) for i in wl.instances)
+    assert np.linalg.norm(st.g) < 1e-8
+    assert abs(st.f - ref) < 1e-10
+
+
+def test_brute_force_minimum_three_levels():
+    """M = 3, N = 1 with the Hubbard term: the occupied orbital is a point on S^2;
+    a dense angular grid plus local polish gives the global minimum."""
+    H0 = chain_hamiltonian(3, rng_for(300, 0, 0))
+    Uh = 0.5
+
+    def E_of(c):
+        c = c / np.linalg.norm(c)
+        return 2.0 * c @ H0 @ c + 0.5 * Uh * np.sum((2.0 * c * c) ** 2)
+    best = None
+    for th in np.linspace(0, np.pi, 181):
+        for ph in np.linspace(0, 2 * np.pi, 361):
+            c = np.array([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+            e = E_of(c)
+            if best is None or e < best[0]:
+                best = (e, c)
+    res = scipy.optimize.minimize(E_of, best[1], method="BFGS", options=dict(gtol=1e-12))
+    C0 = haar_orthogonal(3, rng_for(300, 0, 1))
+    inst = Instance(M=3, N=1, f=np.array([2.0, 0.0, 0.0]), C0=C0, A=np.zeros((1, 2)), H0=H0)
+    wl = Workload(300, "3-level", "real_ov", Uh, False, [inst])
+    st, _ = LB.minimize(wl)
+    assert abs(st.f - res.fun) < 1e-10
+
+
+def test_brute_force_minimum_grassmannian_4_2():
+    """M = 4, N = 2 with the Hubbard term: multistart over 2-frames in R^4."""
+    H0 = chain_hamiltonian(4, rng_for(301, 0, 0))
+    Uh = 0.5
+
+    def E_of(x):
+        Q, _ = np.linalg.qr(x.reshape(4, 2))
+        rho = 2.0 * Q @ Q.T
+        return np.sum(rho * H0) + 0.5 * Uh * np.sum(np.diag(rho) ** 2)
+    rng = np.random.default_rng(0)
+    best = min((scipy.optimize.minimize(E_of, rng.standard_normal(8), method="BFGS",
+                                        options=dict(gtol=1e-12)).fun for _ in range(40)))
+    C0 = haar_orthogonal(4, rng_for(301, 0, 1))
+    inst = Instance(M=4, N=2, f=np.array([2.0, 2.0, 0.0, 0.0]), C0=C0, A=np.zeros((2, 2)), H0=H0)
+    wl = Workload(301, "4-level", "real_ov", Uh, False, [inst])
+    st, _ = LB.minimize(wl)
+    assert abs(st.f - best) < 1e-10
+
+
+def test_config1_lbfgs_reaches_scf_fixed_point():
+    """Config 1: L-BFGS from A = 0 to |g| < 1e-8 lands on the Roothaan SCF fixed point."""
+    wl = make_config(1)
+    inst = wl.instances[0]
+    rho0 = inst.C0 @ np.diag(inst.f) @ inst.C0.T
+    E_scf, rho_scf, _ = scf.scf_minimum(inst.H0, inst.N, 2.0, wl.hubbard_U, rho0)
+    st, hist = LB.minimize(wl)
+    assert np.linalg.norm(st.g) < 1e-8
+    assert abs(st.f - E_scf) < 1e-10
+    B = O.unflatten("real_ov", wl, st.x)[0]
+    C = wl.instances[0].C0 @ O.expm_eig(O.ov_generator(B))
+    rho = 2.0 * C[:, :16] @ C[:, :16].T
+    assert np.abs(rho - rho_scf).max() < 1e-7
+    # energies never increase along accepted steps
+    Es = [h["E"] for h in hist]
+    assert all(b <= a + 1e-12 for a, b in zip(Es, Es[1:]))
+
+
+def test_planted_mistakes_are_caught():
+    """A dropped Hubbard term or a transposed gradient fails the finite-difference pin."""
+    wl = tiny_real(9, 3, seed=16, scale=0.3)
+    p = O.parity_params(wl)
+    E, (g,) = O.energy_grad(wl, p)
+    d = np.random.default_rng(2).standard_normal(g.size)
+    fd = _fd_directional(wl, p, d, 1e-3)
+    assert abs(fd - g.ravel() @ d) < 1e-8
+    wl0 = copy.deepcopy(wl)
+    wl0.hubbard_U = 0.0
+    _, (g0,) = O.energy_grad(wl0, p)
+    assert abs(fd - g0.ravel() @ d) > 1e-4
+    # a mirrored index convention (g from Y_ij instead of Y_ji) flips the sign
+    A, L, Y = O.y_matrix(wl, p, 0)
+    g_bad = 2.0 * Y[:3, 3:]
+    assert abs(fd - g_bad.ravel() @ d) > 1e-4
