@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Throughput of the ETDM energy+gradient path on one MI355X.
+
+One "step" is one evaluation of E and the full gradient for every instance of
+the workload (all steps of the hot path).  The default workload is the batch of
+148 ragged G2-like molecules (M ~ U[20, 400], N = round(M/5)) with FP32 MFMA
+contractions and FP64 eigensolver / reductions.  Inputs are resident in HBM
+before the timed region starts.
+
+Prints ONE JSON line (rank 0, N = 1):
+  value            evaluations per second (whole job)
+  roofline         dominant stage: algorithmic flops (or bytes) per launch over its
+                   average HIP-event duration in the timed region, vs MI355X peak
+  cpu_baseline     the FP64 oracle on the host cores, one full evaluation
+  parity           |dE| per electron and relative |dg| of this run vs the oracle
+  fp64_path        the same kernels in FP64 mode, and the speedup over it
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ETDM energy+gradient evals/sec, MFMA TFLOP/s vs peak, at stated |dE|"
+PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
+HBM_PEAK_GBS = 8000.0
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16"}
+WORKLOADS = {
+    1: "config 1: chain Hamiltonian M=64 N=16, real, one molecule",
+    2: "config 2: 148 ragged G2-like molecules, M~U[20,400], N=round(M/5), real, Hubbard U=0.5",
+    3: "config 3: 64-water box M=1472 N=256, block-sparse H0, real",
+    4: "config 4: crystal 4x4x4 k-grid, M=208, complex, Fermi-Dirac f, k-coupled Hubbard",
+    5: "config 5: 576-water box M=13248 N=2304, block-sparse H0, real",
+}
+DEFAULT_PREC = {1: "fp64", 2: "fp32", 3: "bf16x6", 4: "fp64", 5: "bf16x6"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    return ap.parse_args()
+
+
+def build_handle(wl, precision):
+    import torch
+    from paper_2101_12597_amd import Handle
+    from workloads.pack import pack
+    pk = pack(wl, use_bsr=wl.instances[0].H0_bsr is not None)
+    dev = torch.device("cuda:0")
+    H0 = torch.from_numpy(pk["H0"]).to(dev)
+    C0 = torch.from_numpy(pk["C0"]).to(dev)
+    h = Handle(pk["M"], pk["N"], wl.kind, precision, wl.hubbard_U, H0, C0, pk["f"],
+               couple=wl.couple, weights=pk["weights"], bsr=pk["bsr"])
+    A = torch.from_numpy(pk["A"]).to(dev)
+    E = torch.empty(h.n_inst + 1, dtype=torch.float64, device=dev)
+    G = torch.empty_like(A)
+    del H0, C0
+    torch.cuda.synchronize()
+    return h, A, E, G
+
+
+def timed_run(h, A, E, G, steps, warmup, time_stage=None):
+    import torch
+    for _ in range(warmup):
+        h.energy_grad(A, E, G)
+    h.sync_status()
+    if time_stage is not None:
+        h.reset_timing()
+        h.set_timing(1 << time_stage)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h.energy_grad(A, E, G)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h.sync_status()
+    stages = h.stage_info() if time_stage is not None else None
+    h.set_timing(0)
+    return (t1 - t0) / steps, stages
+
+
+def stage_profile(h, A, E, G, reps=5):
+    """Per-stage HIP-event times over a few evaluations (all stages timed)."""
+    import torch
+    h.reset_timing()
+    h.set_timing(-1)
+    for _ in range(reps):
+        h.energy_grad(A, E, G)
+    torch.cuda.synchronize()
+    info = h.stage_info()
+    h.set_timing(0)
+    h.reset_timing()
+    return info
+
+
+def oracle_reference(wl, params):
+    """Per-instance E and g from the FP64 oracle (definition path), and its wall time."""
+    import copy
+    import numpy as np
+    from oracle import etdm as O
+    t0 = time.perf_counter()
+    Es, gs = [], []
+    for inst, p in zip(wl.instances, params):
+        sub = copy.copy(wl)
+        sub.instances = [inst]
+        if wl.couple:
+            break
+        e, (g,) = O.energy_grad(sub, [p])
+        Es.append(e)
+        gs.append(g)
+    if wl.couple:
+        e, gs = O.energy_grad(wl, params)
+        Es = [e]
+    return np.array(Es), gs, time.perf_counter() - t0
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [d.get("num_threads", 0) for d in threadpool_info() if d.get("user_api") == "blas"]
+        return max(n) if n else os.cpu_count()
+    except Exception:
+        return os.cpu_count()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}); "
+              "the multi-GPU layout is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from oracle import etdm as O  # only for the parity numbers and the CPU baseline leg
+    from workloads import make_config
+    from workloads.pack import unpack_params
+
+    cfg = args.config
+    prec = args.precision or DEFAULT_PREC[cfg]
+    wl = make_config(cfg)
+    params = O.parity_params(wl)
+    h, A, E, G = build_handle(wl, prec)
+
+    # which stage dominates: time every stage over a few evaluations
+    for _ in range(max(1, args.warmup)):
+        h.energy_grad(A, E, G)
+    h.sync_status()
+    prof = stage_profile(h, A, E, G)
+    dom = max(prof, key=lambda r: r["total_ms"])
+
+    sec, stages = timed_run(h, A, E, G, args.steps, args.warmup, time_stage=dom["index"])
+    dstage = stages[dom["index"]]
+    avg_ms = dstage["total_ms"] / max(dstage["launches"], 1)
+    total_flops = sum(r["flops"] for r in prof)
+
+    # parity of this run against the FP64 oracle at the same inputs
+    h.energy_grad(A, E, G)
+    h.sync_status()
+    E_gpu = E.cpu().numpy()
+    g_gpu = unpack_params(wl, G.cpu().numpy())
+    Es, gs, t_oracle = oracle_reference(wl, params)
+    if wl.couple:
+        dE = abs(E_gpu[-1] - Es[0]) / wl.n_electrons
+        g_all, r_all = np.concatenate([x.ravel() for x in g_gpu]), np.concatenate([x.ravel() for x in gs])
+        dg = float(np.linalg.norm(g_all - r_all) / np.linalg.norm(r_all))
+    else:
+        dE = max(abs(E_gpu[k] - Es[k]) / max(inst.f.sum(), 1.0) for k, inst in enumerate(wl.instances))
+        dg = max(float(np.linalg.norm(g_gpu[k] - gs[k]) / max(np.linalg.norm(gs[k]), 1e-300))
+                 for k in range(len(wl.instances)))
+
+    is_gemm = dom["name"].startswith("gemm") or dom["name"].startswith("zgemm")
+    if is_gemm:
+        gemm_prec = "fp64" if dom["name"] in ("gemm_funcs_mu", "gemm_Gam1", "gemm_Gam", "gemm_Y1",
+                                              "gemm_Y2") else prec
+        peak = PEAKS_TFLOPS[gemm_prec]
+        achieved = dom["flops"] / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
+    elif dom["name"].startswith("eigh") or dom["name"] == "z_eigh":
+        peak = 78.6  # FP64 vector ALU peak: 256 CUs x 2.4 GHz x 128 FP64 flops/clk
+        achieved = dom["flops"] / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
+    else:
+        achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom["name"]
+    roof["avg_launch_ms"] = avg_ms
+    roof["launches_timed"] = dstage["launches"]
+
+    out = {
+        "metric": METRIC,
+        "value": 1.0 / sec,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[prec],
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[cfg], "precision": prec, "instances": len(wl.instances),
+                   "electrons": wl.n_electrons},
+        "tflops": total_flops / sec / 1e12,
+        "roofline": roof,
+        "parity": {"max_dE_per_electron": dE, "max_rel_dg": dg,
+                   "target_dE_per_electron": 1e-8, "target_rel_dg": 1e-6},
+        "stages_ms": {r["name"]: round(r["total_ms"] / max(r["launches"], 1), 5) for r in prof if r["launches"]},
+    }
+    if not args.no_fp64_compare and prec != "fp64":
+        h64, A64, E64, G64 = build_handle(wl, "fp64")
+        sec64, _ = timed_run(h64, A64, E64, G64, max(5, args.steps // 2), 2)
+        out["fp64_path"] = {"value": 1.0 / sec64, "ms_per_step": sec64 * 1e3, "speedup": sec64 / sec}
+        h64.close()
+    if not args.no_cpu_baseline:
+        reps, total = 1, t_oracle
+        while total < 10.0 and reps < 8:
+            _, _, t = oracle_reference(wl, params)
+            total += t
+            reps += 1
+        out["cpu_baseline"] = {
+            "value": reps / total, "unit": "evals/s", "cores": blas_threads(), "kind": "oracle",
+            "sample": f"{reps} full evaluation(s) of all {len(wl.instances)} instances with the FP64 "
+                      "oracle's definition path (eigendecomposition of iA), NumPy/OpenBLAS",
+        }
+    h.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

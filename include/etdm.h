@@ -1,0 +1,190 @@
+/*
+ * etdm.h — C ABI of the MI355X (gfx950) library for the hot path of
+ * exponential-transformation direct minimization (ETDM).
+ *
+ * One call of etdm_energy_grad evaluates, for every instance of a batch
+ * (independent molecules, or the k-points of one crystal):
+ *
+ *   U = exp(A)            from the eigendecomposition of iA      (Sec. 3.4, Eq. ed)
+ *   C = C0 U              current orbitals                        (Sec. 2, Eq. unit_transf)
+ *   rho = C F C^dagger    density matrix                          (Sec. 2)
+ *   H(rho), E(rho)        model functional, see below
+ *   H_MO = C^dagger H C,  L = w [F, H_MO]                         (Sec. 2, def. of L_mk)
+ *   dE/dA                 Eq. gradients, back-transformed through the eigenbasis
+ *                         of iA with the divided-difference factors of its
+ *                         eigenvalues (Sec. 3.4)
+ *
+ * Model functional (stands in for the Kohn-Sham functional):
+ *   E = sum_k w_k Tr(rho_k H0_k) + (U_hub/2) sum_mu n_mu^2,
+ *   n = diag(rho_k) per instance, or sum_k w_k diag(rho_k) when `couple` is set,
+ *   H_k = H0_k + U_hub diag(n).
+ *
+ * Parametrizations (Sec. 2 and Sec. 3.4):
+ *   ETDM_REAL_OV       real A = [[0, B], [-B^T, 0]] (Hutter's occupied-virtual form,
+ *                      exact for a unitary-invariant functional with equal
+ *                      occupations f_occ on the first N columns and 0 elsewhere).
+ *                      A is passed as B (N x (M-N), row-major, float64).
+ *   ETDM_COMPLEX_FULL  complex skew-Hermitian A (M x M, row-major, interleaved
+ *                      complex float64).  Only the upper triangle including the
+ *                      diagonal is read; Re of the diagonal is ignored (Sec. 2).
+ *
+ * Gradient layout (same layout as A):
+ *   REAL_OV            G[i][j] = dE/dB_ij
+ *   COMPLEX_FULL       G[i][j] = dE/dRe a_ij + i dE/dIm a_ij for i <= j, 0 below
+ *                      (Sec. 2, the real-variable derivatives built from the
+ *                      derivative with respect to a_ij).
+ *
+ * Memory: every matrix pointer passed to a call is a DEVICE pointer unless
+ * stated otherwise; all descriptor arrays are HOST pointers.  Batches are packed
+ * back to back in instance order (instance i starts after all elements of
+ * instances < i).  Calls are asynchronous on the given HIP stream (a
+ * hipStream_t passed as void*, NULL = default stream); argument errors are
+ * returned synchronously; device-side failures (eigensolver not converged,
+ * non-finite values) set a status word that etdm_sync_status reports.
+ * The handle owns device copies of C0, H0 and f plus all workspaces; no call
+ * after etdm_create allocates device memory.  A handle must not be used from
+ * two threads at once.  No function throws or aborts.
+ */
+#ifndef ETDM_H
+#define ETDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct etdm_handle etdm_handle;
+
+typedef enum {
+  ETDM_OK = 0,
+  ETDM_E_ARG = -1,        /* invalid argument (null pointer, bad enum, bad occupations) */
+  ETDM_E_SHAPE = -2,      /* inconsistent sizes */
+  ETDM_E_HIP = -3,        /* a HIP runtime call failed */
+  ETDM_E_NOMEM = -4,      /* device allocation failed in etdm_create */
+  ETDM_E_EIGH = -5,       /* FP64 Jacobi eigensolver hit its sweep limit */
+  ETDM_E_NONFINITE = -6,  /* NaN/Inf in the energy or gradient */
+  ETDM_E_LINESEARCH = -7, /* line search found no acceptable step */
+  ETDM_E_STATE = -8       /* call sequence error (e.g. L-BFGS not initialised) */
+} etdm_status;
+
+typedef enum { ETDM_REAL_OV = 0, ETDM_COMPLEX_FULL = 1 } etdm_kind;
+
+/* Arithmetic of the dense contractions.  The eigendecomposition, the spectral
+ * and divided-difference factors and the energy reduction are FP64 in every mode. */
+typedef enum {
+  ETDM_FP64 = 0,   /* FP64 MFMA */
+  ETDM_FP32 = 1,   /* operands rounded to FP32, FP32 MFMA, FP64 flush every K chunk */
+  ETDM_BF16X3 = 2, /* 2-way BF16 split (hi+lo), 3 products, FP32 MFMA accumulation */
+  ETDM_BF16X6 = 3  /* 3-way BF16 split (hi+mid+lo), 6 products */
+} etdm_precision;
+
+typedef struct {
+  int32_t n_inst;         /* number of instances (molecules or k-points), >= 1 */
+  const int32_t *M;       /* host [n_inst]: basis size, >= 1 */
+  const int32_t *N;       /* host [n_inst]: REAL_OV: occupied count 0 <= N <= M;
+                             COMPLEX_FULL: ignored */
+  int32_t kind;           /* etdm_kind */
+  int32_t precision;      /* etdm_precision (COMPLEX_FULL supports ETDM_FP64 only) */
+  double hubbard_U;       /* U_hub of the model functional */
+  int32_t couple;         /* 1: Hubbard term on sum_k w_k diag(rho_k) (needs equal M) */
+  const double *weights;  /* host [n_inst] k-point weights, NULL = all 1 */
+  int32_t h0_format;      /* 0: dense H0 (M x M per instance);
+                             1: block-sparse rows (REAL_OV only) */
+  int32_t bsr_block;      /* block size when h0_format = 1 (M divisible by it) */
+  const int32_t *bsr_row_ptr; /* host, per instance (M/bs + 1) entries, concatenated */
+  const int32_t *bsr_col_idx; /* host, per instance row_ptr[last] entries, concatenated */
+} etdm_desc;
+
+/* Create a handle.  H0: device, dense float64 (REAL_OV) or complex float64
+ * (COMPLEX_FULL) M x M per instance, or (h0_format = 1) the concatenated
+ * bs x bs row-major blocks in row_ptr/col_idx order.  H0 must be Hermitian.
+ * C0: device, M x M per instance, orthonormal columns (float64 or complex).
+ * f: host [sum M] occupations.  All inputs are copied; the caller keeps
+ * ownership.  `stream` orders the copies. */
+etdm_status etdm_create(etdm_handle **h, const etdm_desc *d, const void *H0, const void *C0,
+                        const double *f, void *stream);
+etdm_status etdm_destroy(etdm_handle *h);
+
+/* U = exp(A) per instance (Eq. ed; for REAL_OV the same U in Hutter's closed
+ * form, Eq. uinv).  A: device, parameter layout above.  U: device, M x M per
+ * instance (float64 for REAL_OV, complex for COMPLEX_FULL). */
+etdm_status etdm_expm(etdm_handle *h, const void *A, void *U, void *stream);
+
+/* E and dE/dA (Eq. gradients).  A, G: device, parameter layout.  E: device
+ * float64 [n_inst + 1] = per-instance energies (weighted, Hubbard included per
+ * instance; with `couple` the Hubbard energy is in the total only) followed
+ * by the batch total. */
+etdm_status etdm_energy_grad(etdm_handle *h, const void *A, double *E, void *G, void *stream);
+
+/* Replace the reference orbitals C0 <- C0 exp(A) (Sec. 3.4, reference update).
+ * Erases the L-BFGS memory. */
+etdm_status etdm_set_reference(etdm_handle *h, const void *A, void *stream);
+
+/* L-BFGS settings (Sec. 3.1-3.3).  etdm_lbfgs_defaults fills the paper's values:
+ * m = 3, c1 = 1e-4, c2 = 0.9, delta = 0.1, sigma = 0.9, eps = 1e-6,
+ * gamma = 0.25, beta0 = 1, reset_every = 20, max_ls = 20. */
+typedef struct {
+  int32_t m;
+  double c1, c2, delta, sigma, eps, gamma, beta0;
+  int32_t reset_every; /* reference reset period in iterations, 0 = never */
+  int32_t max_ls;      /* energy+gradient evaluations per line search */
+} etdm_lbfgs_params;
+
+typedef struct {
+  int32_t iter;      /* iterations done so far */
+  int32_t n_evals;   /* energy+gradient evaluations so far (all line searches) */
+  double alpha;      /* accepted step length */
+  double E;          /* total energy after the step */
+  double gnorm;      /* Euclidean norm of the gradient after the step */
+  int32_t flags;     /* bit 0: reference reset before this step,
+                        bit 1: steepest-descent fallback (memory erased),
+                        bit 2: line search failed (state unchanged) */
+} etdm_lbfgs_info;
+
+void etdm_lbfgs_defaults(etdm_lbfgs_params *p);
+
+/* One L-BFGS iteration on the whole batch as one vector of free variables.
+ * A: device, in/out (current parameters); E: device [n_inst + 1] out; G:
+ * device out (gradient at the new A).  On the first call (or after
+ * etdm_set_reference) the state is initialised from A.  When a reference reset
+ * happens (every reset_every iterations) C0 <- C0 exp(A) and A is set to 0
+ * before the step.  params may be NULL (defaults).  info: host, out.
+ * Synchronizes `stream` once per line-search probe to read three numbers. */
+etdm_status etdm_lbfgs_step(etdm_handle *h, const etdm_lbfgs_params *params, void *A, double *E,
+                            void *G, etdm_lbfgs_info *info, void *stream);
+
+/* Wait for `stream` and report a device-side failure recorded since the last call. */
+etdm_status etdm_sync_status(etdm_handle *h, void *stream);
+
+const char *etdm_status_string(etdm_status s);
+/* Human-readable detail of the last error on this handle ("" if none). */
+const char *etdm_last_error(const etdm_handle *h);
+
+/* Tracing: per-stage HIP-event timing of the launch sequences.  A "stage" is
+ * one launch (or grouped launch) of the path: a GEMM group, the eigensolver,
+ * an elementwise pass.  `mask` selects stages by index (bit i = stage i,
+ * -1 = all, 0 = off); events are recorded on the stream of each call around
+ * every selected stage.  Timing adds two event records per selected stage. */
+etdm_status etdm_set_timing(etdm_handle *h, int64_t mask);
+/* Clear the accumulated times and launch counts. */
+etdm_status etdm_reset_timing(etdm_handle *h);
+/* Number of stages of this handle's path. */
+int32_t etdm_stage_count(const etdm_handle *h);
+/* Stage i: its name (static string), launches timed so far, their total
+ * duration in ms (waits for the recorded events), and the algorithmic flops
+ * and minimum HBM bytes of one launch (operands read once, results written
+ * once, float64 storage).  Any output pointer may be NULL. */
+etdm_status etdm_stage_info(etdm_handle *h, int32_t i, const char **name, int64_t *launches,
+                            double *total_ms, double *flops, double *bytes);
+
+/* Number of parameters of one A (or G) array in float64 units:
+ * REAL_OV sum N(M-N); COMPLEX_FULL 2 sum M^2. */
+int64_t etdm_param_count(const etdm_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ETDM_H */

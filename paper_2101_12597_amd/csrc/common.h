@@ -1,0 +1,63 @@
+// Internal declarations shared by the HIP kernels and the host orchestration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace etdm {
+
+// ---------------------------------------------------------------------------
+// grouped GEMM problems (row-major operands)
+//   C = alpha * op(A) op(B) + alpha2 * op(A2) op(B2) + beta * D
+// op(A) is m x k, op(B) is k x n (second segment: k2).  All problems of one
+// launch share the transposition flags.  Every workgroup computes one 64 x 64
+// tile; tile_begin is the prefix sum of tiles over the problem list.
+// ---------------------------------------------------------------------------
+struct GemmProb {
+  const double* A;
+  const double* B;
+  const double* A2;
+  const double* B2;
+  const double* D;
+  double* C;
+  int64_t lda, ldb, lda2, ldb2, ldd, ldc;
+  int32_t m, n, k, k2;
+  double alpha, alpha2, beta;
+  int32_t tiles_n, tile_begin;
+};
+
+enum GemmPrec : int32_t { GP_FP64 = 0, GP_FP32 = 1, GP_BF16X3 = 2, GP_BF16X6 = 3 };
+enum GemmOp : int32_t { OP_N = 0, OP_T = 1, OP_C = 2 };  // C = conjugate transpose
+
+constexpr int GEMM_BM = 64;
+constexpr int GEMM_BN = 64;
+
+// Real grouped GEMM; opA/opB in {OP_N, OP_T}.
+void launch_gemm(const GemmProb* d_probs, int nprob, int total_tiles, int opA, int opB, int prec,
+                 hipStream_t s);
+// Complex (interleaved re,im float64) grouped GEMM; the double pointers in the
+// problems address complex elements, leading dimensions count complex elements,
+// alpha/alpha2/beta are real.  opA/opB in {OP_N, OP_T, OP_C}.
+void launch_zgemm(const GemmProb* d_probs, int nprob, int total_tiles, int opA, int opB,
+                  hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Jacobi eigensolver (FP64), one workgroup per matrix
+// ---------------------------------------------------------------------------
+struct EighProb {
+  double* A;    // n x n (real) or complex n x n; destroyed (diagonalized in place)
+  double* V;    // n x n eigenvectors (columns), same element type as A
+  double* w;    // n eigenvalues (unsorted)
+  int32_t n;
+  int32_t lds;  // 1: the kernel stages A and V in LDS (real, n <= EIGH_LDS_MAX)
+};
+constexpr int EIGH_LDS_MAX = 88;
+// dynamic LDS bytes of the staged real solver for size n
+size_t eigh_lds_bytes(int n);
+void launch_eigh_real(const EighProb* d_probs, int nprob, bool lds, int nmax, int* d_status, hipStream_t s);
+void launch_eigh_complex(const EighProb* d_probs, int nprob, int nmax, int* d_status, hipStream_t s);
+
+// device status bits
+enum : int { ST_EIGH = 1, ST_NONFINITE = 2 };
+
+}  // namespace etdm

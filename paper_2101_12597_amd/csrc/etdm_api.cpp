@@ -1,0 +1,1343 @@
+// Host side of the ETDM library: handle, workspace layout, the launch
+// sequences of the energy+gradient path, the matrix exponential, reference
+// resets and the L-BFGS driver (Sec. 3.1-3.4).  All device memory is allocated
+// in etdm_create; the call paths only launch kernels and copy between buffers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "etdm.h"
+#include "common.h"
+#include "ov.h"
+
+using namespace etdm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int LB_MMAX = 8;
+
+// Gauss-Legendre nodes and weights on [0, 1] by Newton iteration on the
+// Legendre polynomial P_n (three-term recurrence), mapped from [-1, 1].
+void gauss_legendre01(int n, double* t, double* w) {
+  auto legendre = [n](double x, double& pn, double& dpn) {
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    pn = p1;
+    dpn = n * (x * p1 - p0) / (x * x - 1.0);
+  };
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5)), pn, dpn;
+    for (int it = 0; it < 100; ++it) {
+      legendre(x, pn, dpn);
+      const double dx = pn / dpn;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    legendre(x, pn, dpn);
+    t[i] = 0.5 * (x + 1.0);
+    w[i] = 1.0 / ((1.0 - x * x) * dpn * dpn);  // half of the [-1, 1] weight 2 / ((1 - x^2) P_n'^2)
+  }
+}
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// One grouped GEMM launch.  Problems are added at plan time and uploaded once.
+struct Stage {
+  std::vector<GemmProb> probs;
+  GemmProb* d = nullptr;
+  int tiles = 0;
+  int opA = OP_N, opB = OP_N, prec = GP_FP64;
+  bool cplx = false;
+  void init(int a, int b, int p, bool c = false) {
+    opA = a;
+    opB = b;
+    prec = p;
+    cplx = c;
+  }
+  void add(GemmProb p) {
+    if (p.m <= 0 || p.n <= 0) return;
+    p.tiles_n = ceil_div(p.n, GEMM_BN);
+    p.tile_begin = tiles;
+    tiles += p.tiles_n * ceil_div(p.m, GEMM_BM);
+    probs.push_back(p);
+  }
+  void launch(hipStream_t s) const {
+    if (probs.empty()) return;
+    if (cplx) launch_zgemm(d, (int)probs.size(), tiles, opA, opB, s);
+    else launch_gemm(d, (int)probs.size(), tiles, opA, opB, prec, s);
+  }
+};
+
+GemmProb prob(int m, int n, int k, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+              int64_t ldc, double alpha = 1.0) {
+  GemmProb p;
+  std::memset(&p, 0, sizeof(p));
+  p.m = m;
+  p.n = n;
+  p.k = k;
+  p.A = A;
+  p.lda = lda;
+  p.B = B;
+  p.ldb = ldb;
+  p.C = C;
+  p.ldc = ldc;
+  p.alpha = alpha;
+  p.alpha2 = 1.0;
+  return p;
+}
+
+GemmProb with_second(GemmProb p, int k2, const double* A2, int64_t lda2, const double* B2, int64_t ldb2,
+                     double alpha2) {
+  p.k2 = k2;
+  p.A2 = A2;
+  p.lda2 = lda2;
+  p.B2 = B2;
+  p.ldb2 = ldb2;
+  p.alpha2 = alpha2;
+  return p;
+}
+
+GemmProb with_addend(GemmProb p, const double* D, int64_t ldd, double beta) {
+  p.D = D;
+  p.ldd = ldd;
+  p.beta = beta;
+  return p;
+}
+
+struct OvBuf {
+  double *C0, *H0, *f, *B, *G, *U;
+  double *P, *X, *s, *Xcsw, *F3, *T1s, *T2, *T3s, *T3, *mu1, *mu2;
+  double *Q1, *Cocc, *Z1, *Cvirt, *T, *d, *e, *Lov, *R, *Gam1, *Gam, *Nm, *Y1, *Y2;
+  double *HC0, *n0, *eps;
+};
+
+struct ZBuf {
+  double *C0, *H0, *f, *A, *G;
+  double *Hk, *V, *w, *Vp, *Ue, *C, *T, *d, *e, *L, *LV, *W1, *Y;
+  double *n0, *eps;
+};
+
+// Accumulated HIP-event timing of one stage of the launch sequence.
+struct StageTimer {
+  const char* name = "";
+  double flops = 0.0, bytes = 0.0;  // algorithmic work of one launch
+  int64_t launches = 0;
+  double total_ms = 0.0;
+  std::vector<hipEvent_t> ev0, ev1;
+  std::vector<char> pending;
+  int next = 0;
+};
+
+// stage indices of the two paths
+enum OvStage { O_PQ, O_EIGL, O_EIGG, O_SPEC, O_F3MU, O_CZ, O_VT, O_ROWS, O_ENERGY, O_LOV, O_R, O_GAM1, O_GAM,
+               O_PAIR, O_Y1, O_Y2, O_G, O_SCAN, O_COUNT };
+const char* kOvNames[O_COUNT] = {"gemm_P_Q1",  "eigh_lds",    "eigh_global", "spectral_tables", "gemm_funcs_mu",
+                                 "gemm_Cocc_Z1", "gemm_Cvirt_H0C", "rows_density_hubbard", "energy_reduce",
+                                 "gemm_Lov",   "gemm_R",      "gemm_Gam1",   "gemm_Gam",        "pair_hadamard",
+                                 "gemm_Y1",    "gemm_Y2",     "gemm_grad",   "nonfinite_scan"};
+enum ZStage { Z_IA, Z_EIG, Z_PHASE, Z_UE, Z_C, Z_T, Z_ROWS, Z_HUBN, Z_APPLY, Z_ENERGY, Z_HMO, Z_COMM, Z_LV, Z_LT,
+              Z_DD, Z_W1, Z_Y, Z_GRAD, Z_COUNT };
+const char* kZNames[Z_COUNT] = {"z_build_iA", "z_eigh",   "z_phase",  "zgemm_expA", "zgemm_C",   "zgemm_H0C",
+                                "z_rows",     "z_hub_n",  "z_hub_apply", "z_energy", "zgemm_HMO", "z_commutator",
+                                "zgemm_LV",   "zgemm_VhLV", "z_divdiff", "zgemm_W1",  "zgemm_Y",   "z_grad"};
+
+}  // namespace
+
+struct etdm_handle {
+  int n_inst = 0, kind = 0, prec = 0, couple = 0, h0_format = 0;
+  double U = 0.0;
+  std::vector<int> M, N;
+  std::vector<double> w, focc;
+  std::vector<int64_t> par_off;  // parameter offsets (doubles) of each instance
+  int64_t n_param = 0, n_U = 0;
+  char* base = nullptr;
+  size_t bytes = 0;
+  std::vector<OvBuf> ov;
+  std::vector<ZBuf> zb;
+  double *par_ws = nullptr, *grad_ws = nullptr, *U_ws = nullptr, *E_ws = nullptr, *nvec = nullptr;
+  int* status = nullptr;
+  double *gl_t = nullptr, *gl_w = nullptr;
+  // device descriptor arrays (allocated separately)
+  std::vector<void*> dev_allocs;
+  int *b_spec = nullptr, *b_rows = nullptr, *b_pair = nullptr, *b_mat = nullptr;
+  int tot_spec = 0, tot_rows = 0, tot_pair = 0, tot_mat = 0;
+  OvSpec* d_spec = nullptr;
+  OvRows* d_rows = nullptr;
+  OvEnergy* d_energy = nullptr;
+  OvPair* d_pair = nullptr;
+  ZInst* d_z = nullptr;
+  EighProb *d_eig_lds = nullptr, *d_eig_glb = nullptr;
+  int n_eig_lds = 0, n_eig_glb = 0, eig_nmax = 1;
+  const double** d_n0ptr = nullptr;
+  double* d_wts = nullptr;
+  // grouped GEMM launches
+  Stage s_PQ, s_F3mu, s_CZ, s_VT, s_Lov, s_R, s_Gam1, s_Gam, s_Y1, s_Y2, s_G;  // real: energy+gradient
+  Stage s_Uov, s_Uvv, s_HC0;                                                   // real: expm, preconditioner
+  Stage z_Ue, z_C, z_T, z_HMO, z_LV, z_Lt, z_W1, z_Y, z_HC0;                   // complex
+  // L-BFGS state
+  bool lb_init = false;
+  int lb_iter = 0, lb_evals = 0, lb_count = 0, lb_head = 0, lb_m = 3;
+  double lb_E = 0.0, lb_beta = 1.0;
+  double *x = nullptr, *g = nullptr, *p = nullptr, *q = nullptr, *xt = nullptr, *gt = nullptr;
+  double *hd = nullptr, *wv = nullptr, *S = nullptr, *Yv = nullptr, *partial = nullptr, *sc = nullptr;
+  // tracing
+  std::vector<StageTimer> timers;
+  int64_t tmask = 0;
+  std::string err;
+};
+
+namespace {
+
+// device scalar slots of the L-BFGS driver
+enum { SC_T = 0, SC_T2 = 1, SC_DPHI = 2, SC_E = 3, SC_SY = 4, SC_YY = 5, SC_GG = 6, SC_YS0 = 8,
+       SC_AL0 = 16, SC_COEF = 24, SC_COUNT = 32 };
+
+etdm_status fail(etdm_handle* h, etdm_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+#define HIPCHK(h, call)                                                               \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(h, ETDM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHECK(call)                          \
+  do {                                       \
+    etdm_status st_ = (call);                \
+    if (st_ != ETDM_OK) return st_;          \
+  } while (0)
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+constexpr int TIMER_RING = 64;
+
+void timer_collect(StageTimer& t, int i) {
+  if (!t.pending[i]) return;
+  float ms = 0.f;
+  hipEventSynchronize(t.ev1[i]);
+  if (hipEventElapsedTime(&ms, t.ev0[i], t.ev1[i]) == hipSuccess) {
+    t.total_ms += ms;
+    ++t.launches;
+  }
+  t.pending[i] = 0;
+}
+
+// Records HIP events around one stage when the stage is selected for timing.
+struct Timed {
+  etdm_handle* h;
+  int id;
+  hipStream_t s;
+  bool on;
+  int slot = 0;
+  Timed(etdm_handle* h_, int id_, hipStream_t s_) : h(h_), id(id_), s(s_) {
+    on = id < (int)h->timers.size() && ((h->tmask >> id) & 1) && !h->timers[id].ev0.empty();
+    if (!on) return;
+    StageTimer& t = h->timers[id];
+    slot = t.next;
+    timer_collect(t, slot);
+    hipEventRecord(t.ev0[slot], s);
+  }
+  ~Timed() {
+    if (!on) return;
+    StageTimer& t = h->timers[id];
+    hipEventRecord(t.ev1[slot], s);
+    t.pending[slot] = 1;
+    t.next = (slot + 1) % TIMER_RING;
+  }
+};
+
+double stage_flops(const Stage& st) {
+  double f = 0.0;
+  for (const GemmProb& p : st.probs) f += (st.cplx ? 8.0 : 2.0) * p.m * (double)p.n * (p.k + p.k2);
+  return f;
+}
+
+double stage_bytes(const Stage& st) {
+  const double e = st.cplx ? 16.0 : 8.0;
+  double b = 0.0;
+  for (const GemmProb& p : st.probs)
+    b += e * ((double)p.m * (p.k + p.k2) + (double)(p.k + p.k2) * p.n + (double)p.m * p.n * (p.beta != 0.0 ? 2 : 1));
+  return b;
+}
+
+struct Planner {
+  char* base;
+  size_t off = 0;
+  double* take(int64_t n_doubles) {
+    char* p = base + off;
+    off += ((size_t)std::max<int64_t>(n_doubles, 1) * sizeof(double) + ALIGN - 1) / ALIGN * ALIGN;
+    return reinterpret_cast<double*>(p);
+  }
+};
+
+// Lay out every workspace buffer; with base == nullptr it only measures.
+size_t plan_buffers(etdm_handle* h, char* base) {
+  Planner pl{base};
+  const bool real = h->kind == ETDM_REAL_OV;
+  h->par_ws = pl.take(h->n_param);
+  h->grad_ws = pl.take(h->n_param);
+  h->U_ws = real ? pl.take(h->n_U) : nullptr;
+  h->E_ws = pl.take(h->n_inst + 1);
+  h->status = reinterpret_cast<int*>(pl.take(1));
+  h->gl_t = pl.take(OV_NQ);
+  h->gl_w = pl.take(OV_NQ);
+  int maxM = 0;
+  for (int i = 0; i < h->n_inst; ++i) maxM = std::max(maxM, h->M[i]);
+  h->nvec = pl.take(maxM);
+  int64_t uoff = 0;
+  if (real) {
+    h->ov.resize(h->n_inst);
+    for (int i = 0; i < h->n_inst; ++i) {
+      const int64_t M = h->M[i], N = h->N[i], Nv = M - N;
+      OvBuf& b = h->ov[i];
+      b.B = h->par_ws + h->par_off[i];
+      b.G = h->grad_ws + h->par_off[i];
+      b.U = h->U_ws + uoff;
+      uoff += M * M;
+      b.C0 = pl.take(M * M);
+      b.H0 = pl.take(M * M);
+      b.f = pl.take(M);
+      b.P = pl.take(N * N);
+      b.X = pl.take(N * N);
+      b.s = pl.take(N);
+      b.Xcsw = pl.take(3 * N * N);
+      b.F3 = pl.take(3 * N * N);
+      b.T1s = pl.take(N * OV_NQ);
+      b.T2 = pl.take(N * OV_NQ);
+      b.T3s = pl.take(N * OV_NQ);
+      b.T3 = pl.take(N * OV_NQ);
+      b.mu1 = pl.take(N * N);
+      b.mu2 = pl.take(N * N);
+      b.Q1 = pl.take(M * N);
+      b.Cocc = pl.take(M * N);
+      b.Z1 = pl.take(M * N);
+      b.Cvirt = pl.take(M * Nv);
+      b.T = pl.take(M * N);
+      b.d = pl.take(M);
+      b.e = pl.take(M);
+      b.Lov = pl.take(N * Nv);
+      b.R = pl.take(N * N);
+      b.Gam1 = pl.take(N * N);
+      b.Gam = pl.take(N * N);
+      b.Nm = pl.take(N * N);
+      b.Y1 = pl.take(N * N);
+      b.Y2 = pl.take(N * N);
+      b.HC0 = b.U;  // the preconditioner's H0 C0 shares the expm output workspace
+      b.n0 = pl.take(M);
+      b.eps = pl.take(M);
+    }
+  } else {
+    h->zb.resize(h->n_inst);
+    for (int i = 0; i < h->n_inst; ++i) {
+      const int64_t M = h->M[i], MM2 = 2 * M * M;
+      ZBuf& b = h->zb[i];
+      b.A = h->par_ws + h->par_off[i];
+      b.G = h->grad_ws + h->par_off[i];
+      b.C0 = pl.take(MM2);
+      b.H0 = pl.take(MM2);
+      b.f = pl.take(M);
+      b.Hk = pl.take(MM2);
+      b.V = pl.take(MM2);
+      b.w = pl.take(M);
+      b.Vp = pl.take(MM2);
+      b.Ue = pl.take(MM2);
+      b.C = pl.take(MM2);
+      b.T = pl.take(MM2);
+      b.d = pl.take(M);
+      b.e = pl.take(M);
+      b.L = pl.take(MM2);
+      b.LV = pl.take(MM2);
+      b.W1 = pl.take(MM2);
+      b.Y = pl.take(MM2);
+      b.n0 = pl.take(M);
+      b.eps = pl.take(M);
+    }
+  }
+  const int64_t np = h->n_param;
+  h->x = pl.take(np);
+  h->g = pl.take(np);
+  h->p = pl.take(np);
+  h->q = pl.take(np);
+  h->xt = pl.take(np);
+  h->gt = pl.take(np);
+  h->hd = pl.take(np);
+  h->wv = pl.take(np);
+  h->S = pl.take(np * LB_MMAX);
+  h->Yv = pl.take(np * LB_MMAX);
+  h->partial = pl.take(1024);
+  h->sc = pl.take(SC_COUNT);
+  return pl.off;
+}
+
+template <typename T>
+etdm_status upload(etdm_handle* h, T** dst, const std::vector<T>& v) {
+  *dst = nullptr;
+  if (v.empty()) return ETDM_OK;
+  void* p = nullptr;
+  HIPCHK(h, hipMalloc(&p, v.size() * sizeof(T)));
+  h->dev_allocs.push_back(p);
+  HIPCHK(h, hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  *dst = reinterpret_cast<T*>(p);
+  return ETDM_OK;
+}
+
+etdm_status upload_stage(etdm_handle* h, Stage& s) { return upload(h, &s.d, s.probs); }
+
+// ----- plan of the real occupied-virtual path ------------------------------
+etdm_status build_ov_plan(etdm_handle* h) {
+  const int bulk = h->prec;
+  h->s_PQ.init(OP_N, OP_T, bulk);
+  h->s_F3mu.init(OP_N, OP_T, GP_FP64);
+  h->s_CZ.init(OP_N, OP_N, bulk);
+  h->s_VT.init(OP_N, OP_N, bulk);
+  h->s_Lov.init(OP_T, OP_N, bulk);
+  h->s_R.init(OP_N, OP_T, bulk);
+  h->s_Gam1.init(OP_T, OP_N, GP_FP64);
+  h->s_Gam.init(OP_N, OP_N, GP_FP64);
+  h->s_Y1.init(OP_N, OP_N, GP_FP64);
+  h->s_Y2.init(OP_N, OP_T, GP_FP64);
+  h->s_G.init(OP_N, OP_N, bulk);
+  h->s_Uov.init(OP_N, OP_N, bulk);
+  h->s_Uvv.init(OP_T, OP_N, bulk);
+  h->s_HC0.init(OP_N, OP_N, bulk);
+  std::vector<OvSpec> spec;
+  std::vector<OvRows> rows;
+  std::vector<OvEnergy> en;
+  std::vector<OvPair> pair;
+  std::vector<int> bspec, brows, bpair;
+  std::vector<EighProb> el, eg;
+  for (int i = 0; i < h->n_inst; ++i) {
+    const int M = h->M[i], N = h->N[i], Nv = M - N;
+    const OvBuf& b = h->ov[i];
+    const double* Fc = b.F3;
+    const double* Fs = b.F3 + (size_t)N * N;
+    const double* Wm = b.F3 + 2 * (size_t)N * N;
+    // P = B B^T, Q1 = C0_v B^T
+    h->s_PQ.add(prob(N, N, Nv, b.B, Nv, b.B, Nv, b.P, N));
+    h->s_PQ.add(prob(M, N, Nv, b.C0 + N, M, b.B, Nv, b.Q1, N));
+    // P = X diag(s) X^T
+    EighProb ep{b.P, b.X, b.s, N, N <= EIGH_LDS_MAX ? 1 : 0};
+    (ep.lds ? el : eg).push_back(ep);
+    spec.push_back(OvSpec{b.s, b.X, b.Xcsw, b.T1s, b.T2, b.T3s, b.T3, N});
+    bspec.push_back(h->tot_spec);
+    h->tot_spec += N * N + N * OV_NQ;
+    // [cos; sinc; W](sqrt P) = Xcsw X^T and the two quadrature products
+    h->s_F3mu.add(prob(3 * N, N, N, b.Xcsw, N, b.X, N, b.F3, N));
+    h->s_F3mu.add(prob(N, N, OV_NQ, b.T1s, OV_NQ, b.T2, OV_NQ, b.mu1, N));
+    h->s_F3mu.add(prob(N, N, OV_NQ, b.T3s, OV_NQ, b.T3, OV_NQ, b.mu2, N));
+    // C_occ = C0_o cos - Q1 sinc, Z1 = C0_o sinc + Q1 W
+    h->s_CZ.add(with_second(prob(M, N, N, b.C0, M, Fc, N, b.Cocc, N), N, b.Q1, N, Fs, N, -1.0));
+    h->s_CZ.add(with_second(prob(M, N, N, b.C0, M, Fs, N, b.Z1, N), N, b.Q1, N, Wm, N, 1.0));
+    // C_virt = C0_v + Z1 B, T0 = H0 C_occ
+    h->s_VT.add(with_addend(prob(M, Nv, N, b.Z1, N, b.B, Nv, b.Cvirt, Nv), b.C0 + N, M, 1.0));
+    h->s_VT.add(prob(M, N, M, b.H0, M, b.Cocc, N, b.T, N));
+    rows.push_back(OvRows{b.Cocc, b.T, b.d, b.e, M, N, h->focc[i]});
+    brows.push_back(h->tot_rows);
+    h->tot_rows += M;
+    en.push_back(OvEnergy{b.d, b.e, M, h->focc[i], h->w[i]});
+    // L_ov = w f_occ T^T C_virt (the weight makes this the gradient of w E)
+    h->s_Lov.add(prob(N, Nv, M, b.T, N, b.Cvirt, Nv, b.Lov, Nv, h->w[i] * h->focc[i]));
+    // Gam = X^T (L_ov B^T) X
+    h->s_R.add(prob(N, N, Nv, b.Lov, Nv, b.B, Nv, b.R, N));
+    h->s_Gam1.add(prob(N, N, N, b.X, N, b.R, N, b.Gam1, N));
+    h->s_Gam.add(prob(N, N, N, b.Gam1, N, b.X, N, b.Gam, N));
+    pair.push_back(OvPair{b.Gam, b.mu1, b.mu2, b.Nm, N});
+    bpair.push_back(h->tot_pair);
+    h->tot_pair += N * N;
+    // Y2 = X Nm X^T ; G = -2 (sinc L_ov + Y2 B)
+    h->s_Y1.add(prob(N, N, N, b.X, N, b.Nm, N, b.Y1, N));
+    h->s_Y2.add(prob(N, N, N, b.Y1, N, b.X, N, b.Y2, N));
+    h->s_G.add(with_second(prob(N, Nv, N, Fs, N, b.Lov, Nv, b.G, Nv, -2.0), N, b.Y2, N, b.B, Nv, -2.0));
+    // exp(A) blocks: U_ov = sinc B, W B (into Lov), U_vo = -B^T sinc, U_vv = I + B^T (W B)
+    h->s_Uov.add(prob(N, Nv, N, Fs, N, b.B, Nv, b.U + N, M));
+    h->s_Uov.add(prob(N, Nv, N, Wm, N, b.B, Nv, b.Lov, Nv));
+    h->s_Uvv.add(prob(Nv, N, N, b.B, Nv, Fs, N, b.U + (size_t)N * M, M, -1.0));
+    h->s_Uvv.add(with_addend(prob(Nv, Nv, N, b.B, Nv, b.Lov, Nv, b.U + (size_t)N * M + N, M),
+                             b.U + (size_t)N * M + N, M, 1.0));
+    // preconditioner: H0 C0
+    h->s_HC0.add(prob(M, M, M, b.H0, M, b.C0, M, b.HC0, M));
+  }
+  h->n_eig_lds = (int)el.size();
+  h->n_eig_glb = (int)eg.size();
+  for (const EighProb& e : eg) h->eig_nmax = std::max(h->eig_nmax, e.n);
+  {
+    h->timers.assign(O_COUNT, StageTimer());
+    for (int i = 0; i < O_COUNT; ++i) h->timers[i].name = kOvNames[i];
+    const Stage* gs[O_COUNT] = {};
+    gs[O_PQ] = &h->s_PQ;
+    gs[O_F3MU] = &h->s_F3mu;
+    gs[O_CZ] = &h->s_CZ;
+    gs[O_VT] = &h->s_VT;
+    gs[O_LOV] = &h->s_Lov;
+    gs[O_R] = &h->s_R;
+    gs[O_GAM1] = &h->s_Gam1;
+    gs[O_GAM] = &h->s_Gam;
+    gs[O_Y1] = &h->s_Y1;
+    gs[O_Y2] = &h->s_Y2;
+    gs[O_G] = &h->s_G;
+    for (int i = 0; i < O_COUNT; ++i)
+      if (gs[i]) {
+        h->timers[i].flops = stage_flops(*gs[i]);
+        h->timers[i].bytes = stage_bytes(*gs[i]);
+      }
+    for (const EighProb& e : el) {
+      h->timers[O_EIGL].flops += 9.0 * e.n * (double)e.n * e.n;
+      h->timers[O_EIGL].bytes += 16.0 * e.n * (double)e.n + 8.0 * e.n;
+    }
+    for (const EighProb& e : eg) {
+      h->timers[O_EIGG].flops += 9.0 * e.n * (double)e.n * e.n;
+      h->timers[O_EIGG].bytes += 16.0 * e.n * (double)e.n + 8.0 * e.n;
+    }
+    for (int i = 0; i < h->n_inst; ++i) {
+      const double M = h->M[i], N = h->N[i];
+      h->timers[O_ROWS].flops += 6.0 * M * N;
+      h->timers[O_ROWS].bytes += 8.0 * (3.0 * M * N + 2.0 * M);
+      h->timers[O_SPEC].bytes += 8.0 * (4.0 * N * N + 4.0 * N * OV_NQ);
+      h->timers[O_PAIR].flops += 3.0 * N * N;
+      h->timers[O_PAIR].bytes += 8.0 * 5.0 * N * N;
+      h->timers[O_ENERGY].bytes += 16.0 * M;
+    }
+    h->timers[O_SCAN].bytes = 8.0 * h->n_param;
+  }
+  Stage* stages[] = {&h->s_PQ, &h->s_F3mu, &h->s_CZ, &h->s_VT, &h->s_Lov, &h->s_R,   &h->s_Gam1,
+                     &h->s_Gam, &h->s_Y1,  &h->s_Y2, &h->s_G,  &h->s_Uov, &h->s_Uvv, &h->s_HC0};
+  for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
+  CHECK(upload(h, &h->d_spec, spec));
+  CHECK(upload(h, &h->b_spec, bspec));
+  CHECK(upload(h, &h->d_rows, rows));
+  CHECK(upload(h, &h->b_rows, brows));
+  CHECK(upload(h, &h->d_energy, en));
+  CHECK(upload(h, &h->d_pair, pair));
+  CHECK(upload(h, &h->b_pair, bpair));
+  CHECK(upload(h, &h->d_eig_lds, el));
+  CHECK(upload(h, &h->d_eig_glb, eg));
+  return ETDM_OK;
+}
+
+// ----- plan of the complex full path -----------------------------------------
+etdm_status build_z_plan(etdm_handle* h) {
+  std::vector<ZInst> zi;
+  std::vector<int> bmat, brows;
+  std::vector<EighProb> eg;
+  std::vector<const double*> n0ptr;
+  h->z_Ue.init(OP_N, OP_C, GP_FP64, true);
+  h->z_C.init(OP_N, OP_N, GP_FP64, true);
+  h->z_T.init(OP_N, OP_N, GP_FP64, true);
+  h->z_HMO.init(OP_C, OP_N, GP_FP64, true);
+  h->z_LV.init(OP_N, OP_N, GP_FP64, true);
+  h->z_Lt.init(OP_C, OP_N, GP_FP64, true);
+  h->z_W1.init(OP_N, OP_C, GP_FP64, true);
+  h->z_Y.init(OP_N, OP_N, GP_FP64, true);
+  h->z_HC0.init(OP_N, OP_N, GP_FP64, true);
+  for (int i = 0; i < h->n_inst; ++i) {
+    const int M = h->M[i];
+    const ZBuf& b = h->zb[i];
+    ZInst z;
+    std::memset(&z, 0, sizeof(z));
+    z.A = b.A;
+    z.Hk = b.Hk;
+    z.V = b.V;
+    z.w = b.w;
+    z.Vp = b.Vp;
+    z.C = b.C;
+    z.T = b.T;
+    z.d = b.d;
+    z.e = b.e;
+    z.n = h->couple ? h->nvec : b.d;
+    z.L = b.L;
+    z.G = b.G;
+    z.Y = b.Y;
+    z.f = b.f;
+    z.M = M;
+    z.weight = h->w[i];
+    zi.push_back(z);
+    bmat.push_back(h->tot_mat);
+    h->tot_mat += M * M;
+    brows.push_back(h->tot_rows);
+    h->tot_rows += M;
+    eg.push_back(EighProb{b.Hk, b.V, b.w, M, 0});
+    n0ptr.push_back(b.n0);
+    h->z_Ue.add(prob(M, M, M, b.Vp, M, b.V, M, b.Ue, M));    // exp(A) = (V e^{-iw}) V^H
+    h->z_C.add(prob(M, M, M, b.C0, M, b.Ue, M, b.C, M));     // C = C0 exp(A)
+    h->z_T.add(prob(M, M, M, b.H0, M, b.C, M, b.T, M));      // H0 C
+    h->z_HMO.add(prob(M, M, M, b.C, M, b.T, M, b.L, M));     // H_MO = C^H H C
+    h->z_LV.add(prob(M, M, M, b.L, M, b.V, M, b.LV, M));     // L V
+    h->z_Lt.add(prob(M, M, M, b.V, M, b.LV, M, b.L, M));     // V^H L V
+    h->z_W1.add(prob(M, M, M, b.L, M, b.V, M, b.W1, M));     // (. o D) V^H
+    h->z_Y.add(prob(M, M, M, b.V, M, b.W1, M, b.Y, M));      // Y = V (.) V^H
+    h->z_HC0.add(prob(M, M, M, b.H0, M, b.C0, M, b.LV, M));  // preconditioner: H0 C0 (into LV)
+  }
+  h->n_eig_glb = (int)eg.size();
+  for (const EighProb& e : eg) h->eig_nmax = std::max(h->eig_nmax, e.n);
+  {
+    h->timers.assign(Z_COUNT, StageTimer());
+    for (int i = 0; i < Z_COUNT; ++i) h->timers[i].name = kZNames[i];
+    const Stage* gs[Z_COUNT] = {};
+    gs[Z_UE] = &h->z_Ue;
+    gs[Z_C] = &h->z_C;
+    gs[Z_T] = &h->z_T;
+    gs[Z_HMO] = &h->z_HMO;
+    gs[Z_LV] = &h->z_LV;
+    gs[Z_LT] = &h->z_Lt;
+    gs[Z_W1] = &h->z_W1;
+    gs[Z_Y] = &h->z_Y;
+    for (int i = 0; i < Z_COUNT; ++i)
+      if (gs[i]) {
+        h->timers[i].flops = stage_flops(*gs[i]);
+        h->timers[i].bytes = stage_bytes(*gs[i]);
+      }
+    for (int i = 0; i < h->n_inst; ++i) {
+      const double M = h->M[i];
+      h->timers[Z_EIG].flops += 36.0 * M * M * M;  // complex Hermitian eigensystem (4 x the real count)
+      h->timers[Z_EIG].bytes += 32.0 * M * M + 8.0 * M;
+      h->timers[Z_IA].bytes += 32.0 * M * M;
+      h->timers[Z_PHASE].bytes += 32.0 * M * M;
+      h->timers[Z_ROWS].bytes += 32.0 * M * M;
+      h->timers[Z_APPLY].bytes += 48.0 * M * M;
+      h->timers[Z_COMM].bytes += 32.0 * M * M;
+      h->timers[Z_DD].bytes += 32.0 * M * M;
+      h->timers[Z_GRAD].bytes += 32.0 * M * M;
+    }
+  }
+  Stage* stages[] = {&h->z_Ue, &h->z_C, &h->z_T, &h->z_HMO, &h->z_LV, &h->z_Lt, &h->z_W1, &h->z_Y, &h->z_HC0};
+  for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
+  CHECK(upload(h, &h->d_z, zi));
+  CHECK(upload(h, &h->b_mat, bmat));
+  CHECK(upload(h, &h->b_rows, brows));
+  CHECK(upload(h, &h->d_eig_glb, eg));
+  CHECK(upload(h, &h->d_n0ptr, n0ptr));
+  CHECK(upload(h, &h->d_wts, h->w));
+  return ETDM_OK;
+}
+
+void free_timers(etdm_handle* h) {
+  for (StageTimer& t : h->timers) {
+    for (hipEvent_t e : t.ev0) hipEventDestroy(e);
+    for (hipEvent_t e : t.ev1) hipEventDestroy(e);
+    t.ev0.clear();
+    t.ev1.clear();
+    t.pending.clear();
+  }
+}
+
+void free_handle(etdm_handle* h) {
+  if (!h) return;
+  free_timers(h);
+  if (h->base) hipFree(h->base);
+  for (void* p : h->dev_allocs) hipFree(p);
+  delete h;
+}
+
+// ----- launch sequences --------------------------------------------------------
+
+#define TIMED(id) Timed timed_scope_(h, id, s)
+
+void ov_exponential_part(etdm_handle* h, hipStream_t s) {
+  { TIMED(O_PQ); h->s_PQ.launch(s); }
+  { TIMED(O_EIGL); launch_eigh_real(h->d_eig_lds, h->n_eig_lds, true, EIGH_LDS_MAX, h->status, s); }
+  { TIMED(O_EIGG); launch_eigh_real(h->d_eig_glb, h->n_eig_glb, false, h->eig_nmax, h->status, s); }
+  { TIMED(O_SPEC); launch_ov_spectral(h->d_spec, h->b_spec, h->n_inst, h->tot_spec, h->gl_t, h->gl_w, s); }
+  { TIMED(O_F3MU); h->s_F3mu.launch(s); }
+}
+
+void ov_energy_grad(etdm_handle* h, hipStream_t s) {
+  ov_exponential_part(h, s);
+  { TIMED(O_CZ); h->s_CZ.launch(s); }
+  { TIMED(O_VT); h->s_VT.launch(s); }
+  { TIMED(O_ROWS); launch_ov_rows(h->d_rows, h->b_rows, h->n_inst, h->tot_rows, h->U, s); }
+  {
+    TIMED(O_ENERGY);
+    launch_ov_energy(h->d_energy, h->n_inst, h->U, h->E_ws, s);
+    launch_total_energy(h->E_ws, h->n_inst, 0.0, nullptr, 0, h->U, h->status, s);
+  }
+  { TIMED(O_LOV); h->s_Lov.launch(s); }
+  { TIMED(O_R); h->s_R.launch(s); }
+  { TIMED(O_GAM1); h->s_Gam1.launch(s); }
+  { TIMED(O_GAM); h->s_Gam.launch(s); }
+  { TIMED(O_PAIR); launch_ov_pair(h->d_pair, h->b_pair, h->n_inst, h->tot_pair, s); }
+  { TIMED(O_Y1); h->s_Y1.launch(s); }
+  { TIMED(O_Y2); h->s_Y2.launch(s); }
+  { TIMED(O_G); h->s_G.launch(s); }
+  { TIMED(O_SCAN); launch_nonfinite_scan(h->grad_ws, h->n_param, h->status, s); }
+}
+
+void ov_expm(etdm_handle* h, hipStream_t s) {
+  ov_exponential_part(h, s);
+  for (int i = 0; i < h->n_inst; ++i) {
+    const OvBuf& b = h->ov[i];
+    const int M = h->M[i], N = h->N[i];
+    launch_copy_block(b.U, M, b.F3, N, N, N, 1.0, s);                    // U_oo = cos sqrt(P)
+    launch_set_identity(b.U + (size_t)N * M + N, M, M - N, 1.0, s);     // U_vv = I (+ below)
+  }
+  h->s_Uov.launch(s);
+  h->s_Uvv.launch(s);
+}
+
+void ov_new_reference(etdm_handle* h, hipStream_t s) {
+  ov_exponential_part(h, s);
+  h->s_CZ.launch(s);
+  h->s_VT.launch(s);
+  for (int i = 0; i < h->n_inst; ++i) {
+    const OvBuf& b = h->ov[i];
+    const int M = h->M[i], N = h->N[i];
+    launch_copy_block(b.C0, M, b.Cocc, N, M, N, 1.0, s);
+    launch_copy_block(b.C0 + N, M, b.Cvirt, M - N, M, M - N, 1.0, s);
+  }
+}
+
+void z_exponential_part(etdm_handle* h, hipStream_t s) {
+  { TIMED(Z_IA); launch_z_build_iA(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s); }
+  { TIMED(Z_EIG); launch_eigh_complex(h->d_eig_glb, h->n_eig_glb, h->eig_nmax, h->status, s); }
+  { TIMED(Z_PHASE); launch_z_phase(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s); }
+  { TIMED(Z_UE); h->z_Ue.launch(s); }
+}
+
+void z_energy_grad(etdm_handle* h, hipStream_t s) {
+  z_exponential_part(h, s);
+  { TIMED(Z_C); h->z_C.launch(s); }
+  { TIMED(Z_T); h->z_T.launch(s); }
+  { TIMED(Z_ROWS); launch_z_rows(h->d_z, h->b_rows, h->n_inst, h->tot_rows, s); }
+  if (h->couple) {
+    TIMED(Z_HUBN);
+    launch_z_hubbard_density(h->d_z, h->n_inst, 1, h->nvec, h->M[0], s);
+  }
+  { TIMED(Z_APPLY); launch_z_apply_hubbard(h->d_z, h->b_rows, h->n_inst, h->tot_rows, h->U, s); }
+  {
+    TIMED(Z_ENERGY);
+    launch_z_energy(h->d_z, h->n_inst, h->couple, h->U, h->E_ws, s);
+    launch_total_energy(h->E_ws, h->n_inst, 0.0, h->couple ? h->nvec : nullptr, h->couple ? h->M[0] : 0, h->U,
+                        h->status, s);
+  }
+  { TIMED(Z_HMO); h->z_HMO.launch(s); }
+  { TIMED(Z_COMM); launch_z_commutator(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s); }
+  { TIMED(Z_LV); h->z_LV.launch(s); }
+  { TIMED(Z_LT); h->z_Lt.launch(s); }
+  { TIMED(Z_DD); launch_z_divdiff(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s); }
+  { TIMED(Z_W1); h->z_W1.launch(s); }
+  { TIMED(Z_Y); h->z_Y.launch(s); }
+  { TIMED(Z_GRAD); launch_z_grad(h->d_z, h->b_mat, h->n_inst, h->tot_mat, h->status, s); }
+}
+
+void run_energy_grad(etdm_handle* h, hipStream_t s) {
+  if (h->kind == ETDM_REAL_OV) ov_energy_grad(h, s);
+  else z_energy_grad(h, s);
+}
+
+// Read and clear the device status word.
+etdm_status check_status(etdm_handle* h, hipStream_t s) {
+  HIPCHK(h, hipStreamSynchronize(s));
+  int st = 0;
+  HIPCHK(h, hipMemcpy(&st, h->status, sizeof(int), hipMemcpyDeviceToHost));
+  if (st) {
+    HIPCHK(h, hipMemset(h->status, 0, sizeof(int)));
+    if (st & ST_EIGH) return fail(h, ETDM_E_EIGH, "Jacobi eigensolver hit its sweep limit");
+    if (st & ST_NONFINITE) return fail(h, ETDM_E_NONFINITE, "non-finite energy or gradient");
+  }
+  return ETDM_OK;
+}
+
+// Diagonal Hessian model of the preconditioner (Sec. 3.3) for the current
+// reference orbitals: eps_i = diag(C0^H H(rho0) C0),
+// h_ij = w * max(0, -2 (eps_i - eps_j)(f_i - f_j)).
+void build_hdiag(etdm_handle* h, hipStream_t s) {
+  if (h->kind == ETDM_REAL_OV) {
+    h->s_HC0.launch(s);
+    for (int i = 0; i < h->n_inst; ++i) {
+      const int M = h->M[i], N = h->N[i];
+      const OvBuf& b = h->ov[i];
+      launch_occ_density(b.C0, b.f, M, 0, b.n0, s);
+      launch_column_eps(b.C0, b.HC0, b.n0, h->U, M, 0, b.eps, s);
+      launch_hdiag_ov(h->hd + h->par_off[i], b.eps, b.f, M, N, h->w[i], s);
+      launch_fill(h->wv + h->par_off[i], (int64_t)N * (M - N), h->w[i], s);
+    }
+    return;
+  }
+  h->z_HC0.launch(s);
+  for (int i = 0; i < h->n_inst; ++i) launch_occ_density(h->zb[i].C0, h->zb[i].f, h->M[i], 1, h->zb[i].n0, s);
+  if (h->couple) launch_weighted_vsum(h->d_n0ptr, h->d_wts, h->n_inst, h->M[0], h->nvec, s);
+  for (int i = 0; i < h->n_inst; ++i) {
+    const ZBuf& b = h->zb[i];
+    const int M = h->M[i];
+    launch_column_eps(b.C0, b.LV, h->couple ? h->nvec : b.n0, h->U, M, 1, b.eps, s);
+    launch_hdiag_z(h->hd + h->par_off[i], h->wv + h->par_off[i], b.eps, b.f, M, h->w[i], s);
+  }
+}
+
+void new_reference(etdm_handle* h, hipStream_t s) {
+  if (h->kind == ETDM_REAL_OV) {
+    ov_new_reference(h, s);
+    return;
+  }
+  z_exponential_part(h, s);
+  h->z_C.launch(s);
+  for (int i = 0; i < h->n_inst; ++i)
+    hipMemcpyAsync(h->zb[i].C0, h->zb[i].C, 2 * sizeof(double) * h->M[i] * h->M[i], hipMemcpyDeviceToDevice, s);
+}
+
+// ----- L-BFGS driver ---------------------------------------------------------------
+
+struct Probe {
+  double a, f, d;
+};
+
+// E and g at x (device); returns E, the slope g.p, and optionally |g|^2.
+etdm_status lb_eval(etdm_handle* h, const double* xin, double* gout, double& E, double& slope, hipStream_t s,
+                    double* gg = nullptr) {
+  const size_t pb = (size_t)h->n_param * sizeof(double);
+  if (pb) HIPCHK(h, hipMemcpyAsync(h->par_ws, xin, pb, hipMemcpyDeviceToDevice, s));
+  run_energy_grad(h, s);
+  if (pb) HIPCHK(h, hipMemcpyAsync(gout, h->grad_ws, pb, hipMemcpyDeviceToDevice, s));
+  launch_dot(gout, h->p, h->n_param, h->partial, h->sc + SC_DPHI, s);
+  if (gg) launch_dot(gout, gout, h->n_param, h->partial, h->sc + SC_GG, s);
+  HIPCHK(h, hipMemcpyAsync(h->sc + SC_E, h->E_ws + h->n_inst, sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipGetLastError());
+  CHECK(check_status(h, s));
+  double v[8];
+  HIPCHK(h, hipMemcpy(v, h->sc, sizeof(v), hipMemcpyDeviceToHost));
+  E = v[SC_E];
+  slope = v[SC_DPHI];
+  if (gg) *gg = v[SC_GG];
+  ++h->lb_evals;
+  return ETDM_OK;
+}
+
+double* slot(double* base, int64_t n, int i) { return base + (int64_t)i * n; }
+
+// p = -H g by the two-loop recursion with H0 = diag(P) (Eq. prec_3); all scalars stay on the device.
+void lb_direction(etdm_handle* h, double gamma, hipStream_t s) {
+  const int64_t n = h->n_param;
+  const int m = h->lb_m;
+  hipMemcpyAsync(h->q, h->g, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+  for (int k = 0; k < h->lb_count; ++k) {  // newest to oldest
+    const int i = (h->lb_head - 1 - k + m) % m;
+    launch_dot(slot(h->S, n, i), h->q, n, h->partial, h->sc + SC_T, s);
+    launch_scalar_ratio(h->sc + SC_AL0 + i, h->sc + SC_T, h->sc + SC_YS0 + i, 1.0, s);
+    launch_axpby(h->q, slot(h->Yv, n, i), n, 1.0, nullptr, -1.0, h->sc + SC_AL0 + i, s);
+  }
+  launch_precond(h->p, h->q, h->hd, h->wv, n, gamma, h->lb_beta, s);
+  for (int k = h->lb_count - 1; k >= 0; --k) {  // oldest to newest
+    const int i = (h->lb_head - 1 - k + m) % m;
+    launch_dot(slot(h->Yv, n, i), h->p, n, h->partial, h->sc + SC_T, s);
+    launch_scalar_ratio(h->sc + SC_T2, h->sc + SC_T, h->sc + SC_YS0 + i, 1.0, s);
+    launch_scalar_sub(h->sc + SC_COEF, h->sc + SC_AL0 + i, h->sc + SC_T2, s);
+    launch_axpby(h->p, slot(h->S, n, i), n, 1.0, nullptr, 1.0, h->sc + SC_COEF, s);
+  }
+  launch_axpby(h->p, h->p, n, -1.0, nullptr, 0.0, nullptr, s);
+}
+
+void lb_steepest(etdm_handle* h, double gamma, hipStream_t s) {
+  launch_precond(h->p, h->g, h->hd, h->wv, h->n_param, gamma, h->lb_beta, s);
+  launch_axpby(h->p, h->p, h->n_param, -1.0, nullptr, 0.0, nullptr, s);
+}
+
+double cubic_min(double a, double fa, double ga, double b, double fb, double gb, bool& ok) {
+  ok = false;
+  if (a == b) return 0.0;
+  const double d1 = ga + gb - 3.0 * (fa - fb) / (a - b);
+  const double disc = d1 * d1 - ga * gb;
+  if (disc < 0.0) return 0.0;
+  const double d2 = std::copysign(std::sqrt(disc), b - a);
+  const double den = gb - ga + 2.0 * d2;
+  if (den == 0.0) return 0.0;
+  ok = true;
+  return b - (b - a) * (gb + d2 - d1) / den;
+}
+
+// Line search along p from (x, E0, g) (Sec. 3.2).  On success xt/gt hold the
+// accepted point, E_ws its energies.
+etdm_status lb_line_search(etdm_handle* h, const etdm_lbfgs_params& P, double f0, double dphi0, double& alpha,
+                           double& f_acc, bool& ok, hipStream_t s) {
+  const int64_t n = h->n_param;
+  int evals = 0;
+  double last_a = -1.0;
+  auto phi = [&](double a, Probe& pr) -> etdm_status {
+    HIPCHK(h, hipMemcpyAsync(h->xt, h->x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_axpby(h->xt, h->p, n, 1.0, nullptr, a, nullptr, s);
+    double E, d;
+    CHECK(lb_eval(h, h->xt, h->gt, E, d, s));
+    ++evals;
+    last_a = a;
+    pr = Probe{a, E, d};
+    return ETDM_OK;
+  };
+  auto strong_wolfe = [&](const Probe& r) {
+    return r.f <= f0 + P.c1 * r.a * dphi0 && std::fabs(r.d) <= P.c2 * std::fabs(dphi0);
+  };
+  auto approx_wolfe = [&](const Probe& r) {
+    return (2.0 * P.delta - 1.0) * dphi0 >= r.d && r.d >= P.sigma * dphi0 && r.f <= f0 + P.eps * std::fabs(f0);
+  };
+  Probe best{0.0, f0, dphi0};
+  auto note = [&](const Probe& r) {
+    if (r.f < best.f) best = r;
+  };
+  auto accept = [&](const Probe& r) {
+    alpha = r.a;
+    f_acc = r.f;
+    ok = true;
+    return ETDM_OK;
+  };
+  ok = false;
+  Probe prev{0.0, f0, dphi0}, cur;
+  CHECK(phi(1.0, cur));
+  note(cur);
+  if (strong_wolfe(cur)) return accept(cur);
+  bool first = true;
+  bool do_zoom = false;
+  Probe lo, hi;
+  while (true) {
+    if (cur.f > f0 + P.c1 * cur.a * dphi0 || (!first && cur.f >= prev.f)) {
+      lo = prev;
+      hi = cur;
+      do_zoom = true;
+      break;
+    }
+    if (cur.d >= 0.0) {
+      lo = cur;
+      hi = prev;
+      do_zoom = true;
+      break;
+    }
+    bool cok;
+    double a_new = cubic_min(prev.a, prev.f, prev.d, cur.a, cur.f, cur.d, cok);
+    if (!cok || !std::isfinite(a_new) || a_new < 1.1 * cur.a || a_new > 4.0 * cur.a)
+      a_new = (!cok || !std::isfinite(a_new) || a_new > 4.0 * cur.a) ? 4.0 * cur.a : 1.1 * cur.a;
+    prev = cur;
+    if (evals >= P.max_ls) break;
+    CHECK(phi(a_new, cur));
+    note(cur);
+    first = false;
+    if (strong_wolfe(cur) || approx_wolfe(cur)) return accept(cur);
+  }
+  if (do_zoom) {
+    while (evals < P.max_ls) {
+      bool cok;
+      double a = cubic_min(lo.a, lo.f, lo.d, hi.a, hi.f, hi.d, cok);
+      const double width = hi.a - lo.a;
+      const double left = std::min(lo.a, hi.a) + 0.1 * std::fabs(width);
+      const double right = std::max(lo.a, hi.a) - 0.1 * std::fabs(width);
+      if (!cok || !std::isfinite(a) || a < left || a > right) a = 0.5 * (lo.a + hi.a);
+      Probe r;
+      CHECK(phi(a, r));
+      note(r);
+      if (strong_wolfe(r) || approx_wolfe(r)) return accept(r);
+      if (r.f > f0 + P.c1 * r.a * dphi0 || r.f >= lo.f) {
+        hi = r;
+      } else {
+        if (r.d * (hi.a - lo.a) >= 0.0) hi = lo;
+        lo = r;
+      }
+    }
+  }
+  // no point met the conditions: take the lowest energy seen, if any
+  if (best.a > 0.0) {
+    if (best.a != last_a) {
+      Probe r;
+      CHECK(phi(best.a, r));
+    }
+    return accept(best);
+  }
+  return ETDM_OK;
+}
+
+etdm_status lb_initialise(etdm_handle* h, const etdm_lbfgs_params& P, hipStream_t s) {
+  double E, d, gg;
+  launch_fill(h->p, h->n_param, 0.0, s);
+  CHECK(lb_eval(h, h->x, h->g, E, d, s, &gg));
+  build_hdiag(h, s);
+  HIPCHK(h, hipGetLastError());
+  h->lb_E = E;
+  h->lb_count = 0;
+  h->lb_head = 0;
+  h->lb_m = std::min(std::max(P.m, 1), LB_MMAX);
+  return ETDM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* etdm_status_string(etdm_status s) {
+  switch (s) {
+    case ETDM_OK: return "ok";
+    case ETDM_E_ARG: return "invalid argument";
+    case ETDM_E_SHAPE: return "inconsistent shape";
+    case ETDM_E_HIP: return "HIP runtime error";
+    case ETDM_E_NOMEM: return "device allocation failed";
+    case ETDM_E_EIGH: return "eigensolver did not converge";
+    case ETDM_E_NONFINITE: return "non-finite energy or gradient";
+    case ETDM_E_LINESEARCH: return "line search failed";
+    case ETDM_E_STATE: return "invalid call sequence";
+  }
+  return "unknown status";
+}
+
+const char* etdm_last_error(const etdm_handle* h) { return h ? h->err.c_str() : ""; }
+
+int64_t etdm_param_count(const etdm_handle* h) { return h ? h->n_param : 0; }
+
+void etdm_lbfgs_defaults(etdm_lbfgs_params* p) {
+  if (!p) return;
+  p->m = 3;
+  p->c1 = 1e-4;
+  p->c2 = 0.9;
+  p->delta = 0.1;
+  p->sigma = 0.9;
+  p->eps = 1e-6;
+  p->gamma = 0.25;
+  p->beta0 = 1.0;
+  p->reset_every = 20;
+  p->max_ls = 20;
+}
+
+etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, const void* C0, const double* f,
+                        void* stream) {
+  if (!out) return ETDM_E_ARG;
+  *out = nullptr;
+  if (!d || !H0 || !C0 || !f) return ETDM_E_ARG;
+  if (d->n_inst < 1 || !d->M) return ETDM_E_ARG;
+  if (d->kind != ETDM_REAL_OV && d->kind != ETDM_COMPLEX_FULL) return ETDM_E_ARG;
+  if (d->precision < ETDM_FP64 || d->precision > ETDM_BF16X6) return ETDM_E_ARG;
+  if (d->kind == ETDM_COMPLEX_FULL && d->precision != ETDM_FP64) return ETDM_E_ARG;
+  if (d->kind == ETDM_REAL_OV && (!d->N || d->couple)) return ETDM_E_ARG;
+  if (d->h0_format != 0 && d->h0_format != 1) return ETDM_E_ARG;
+  if (d->h0_format == 1 && (d->kind != ETDM_REAL_OV || d->bsr_block < 1 || !d->bsr_row_ptr || !d->bsr_col_idx))
+    return ETDM_E_ARG;
+  if (!std::isfinite(d->hubbard_U)) return ETDM_E_ARG;
+  hipStream_t s = S(stream);
+  etdm_handle* h = new etdm_handle();
+  auto bail = [&](etdm_status st) {
+    free_handle(h);
+    return st;
+  };
+  h->n_inst = d->n_inst;
+  h->kind = d->kind;
+  h->prec = d->precision;
+  h->U = d->hubbard_U;
+  h->couple = d->couple ? 1 : 0;
+  h->h0_format = d->h0_format;
+  int64_t off = 0;
+  for (int i = 0; i < d->n_inst; ++i) {
+    const int M = d->M[i];
+    const int N = d->kind == ETDM_REAL_OV ? d->N[i] : M;
+    if (M < 1 || M > 32768 || N < 0 || N > M) return bail(ETDM_E_SHAPE);
+    if (d->kind == ETDM_REAL_OV && N > 4096) return bail(ETDM_E_SHAPE);
+    if (d->kind == ETDM_COMPLEX_FULL && M > 4000) return bail(ETDM_E_SHAPE);
+    if (d->h0_format == 1 && M % d->bsr_block != 0) return bail(ETDM_E_SHAPE);
+    const double wi = d->weights ? d->weights[i] : 1.0;
+    if (!(wi > 0.0) || !std::isfinite(wi)) return bail(ETDM_E_ARG);
+    h->M.push_back(M);
+    h->N.push_back(N);
+    h->w.push_back(wi);
+    h->par_off.push_back(off);
+    off += d->kind == ETDM_REAL_OV ? (int64_t)N * (M - N) : 2 * (int64_t)M * M;
+    h->n_U += (int64_t)M * M;
+  }
+  if (h->couple)
+    for (int i = 1; i < h->n_inst; ++i)
+      if (h->M[i] != h->M[0]) return bail(ETDM_E_SHAPE);
+  // occupations: REAL_OV needs f_occ > 0 on the first N columns and 0 on the rest
+  {
+    int64_t o = 0;
+    for (int i = 0; i < h->n_inst; ++i) {
+      const int M = h->M[i], N = h->N[i];
+      for (int j = 0; j < M; ++j)
+        if (!std::isfinite(f[o + j]) || f[o + j] < 0.0) return bail(ETDM_E_ARG);
+      double fo = 0.0;
+      if (d->kind == ETDM_REAL_OV) {
+        fo = N > 0 ? f[o] : 0.0;
+        if (N > 0 && !(fo > 0.0)) return bail(ETDM_E_ARG);
+        for (int j = 0; j < M; ++j)
+          if (f[o + j] != (j < N ? fo : 0.0)) return bail(ETDM_E_ARG);
+      }
+      h->focc.push_back(fo);
+      o += M;
+    }
+  }
+  h->n_param = off;
+  h->bytes = plan_buffers(h, nullptr);
+  if (hipMalloc(reinterpret_cast<void**>(&h->base), h->bytes) != hipSuccess) return bail(ETDM_E_NOMEM);
+  plan_buffers(h, h->base);
+  if (hipMemsetAsync(h->base, 0, h->bytes, s) != hipSuccess) return bail(ETDM_E_HIP);
+  {
+    double t[OV_NQ], wq[OV_NQ];
+    gauss_legendre01(OV_NQ, t, wq);
+    if (hipMemcpyAsync(h->gl_t, t, sizeof(t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->gl_w, wq, sizeof(wq), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return bail(ETDM_E_HIP);
+  }
+  // copies of C0, H0 and f
+  const bool real = d->kind == ETDM_REAL_OV;
+  const size_t esz = real ? sizeof(double) : 2 * sizeof(double);
+  const char* c0 = static_cast<const char*>(C0);
+  const char* h0 = static_cast<const char*>(H0);
+  int64_t fo = 0, row_off = 0, blk_off = 0;
+  for (int i = 0; i < h->n_inst; ++i) {
+    const int64_t M = h->M[i];
+    double* dC0 = real ? h->ov[i].C0 : h->zb[i].C0;
+    double* dH0 = real ? h->ov[i].H0 : h->zb[i].H0;
+    double* df = real ? h->ov[i].f : h->zb[i].f;
+    if (hipMemcpyAsync(dC0, c0, M * M * esz, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(df, f + fo, M * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+      return bail(ETDM_E_HIP);
+    c0 += M * M * esz;
+    fo += M;
+    if (d->h0_format == 0) {
+      if (hipMemcpyAsync(dH0, h0, M * M * esz, hipMemcpyDeviceToDevice, s) != hipSuccess) return bail(ETDM_E_HIP);
+      h0 += M * M * esz;
+      continue;
+    }
+    const int bs = d->bsr_block, nbr = (int)(M / bs);
+    const int32_t* rp = d->bsr_row_ptr + row_off;
+    const int nnzb = rp[nbr] - rp[0];
+    if (nnzb < 0) return bail(ETDM_E_ARG);
+    std::vector<int> brow(std::max(nnzb, 1)), bcol(std::max(nnzb, 1));
+    for (int r = 0; r < nbr; ++r) {
+      if (rp[r + 1] < rp[r]) return bail(ETDM_E_ARG);
+      for (int pidx = rp[r]; pidx < rp[r + 1]; ++pidx) {
+        const int c = d->bsr_col_idx[blk_off + pidx - rp[0]];
+        if (c < 0 || c >= nbr) return bail(ETDM_E_ARG);
+        brow[pidx - rp[0]] = r;
+        bcol[pidx - rp[0]] = c;
+      }
+    }
+    int *db = nullptr, *dc = nullptr;
+    if (hipMalloc(&db, brow.size() * sizeof(int)) != hipSuccess) return bail(ETDM_E_NOMEM);
+    h->dev_allocs.push_back(db);
+    if (hipMalloc(&dc, bcol.size() * sizeof(int)) != hipSuccess) return bail(ETDM_E_NOMEM);
+    h->dev_allocs.push_back(dc);
+    if (hipMemcpy(db, brow.data(), brow.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dc, bcol.data(), bcol.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(ETDM_E_HIP);
+    launch_bsr_to_dense(dH0, (int)M, reinterpret_cast<const double*>(h0), db, dc, nnzb, bs, s);
+    h0 += (size_t)nnzb * bs * bs * sizeof(double);
+    row_off += nbr + 1;
+    blk_off += nnzb;
+  }
+  etdm_status st = real ? build_ov_plan(h) : build_z_plan(h);
+  if (st != ETDM_OK) return bail(st);
+  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) return bail(ETDM_E_HIP);
+  *out = h;
+  return ETDM_OK;
+}
+
+etdm_status etdm_destroy(etdm_handle* h) {
+  if (!h) return ETDM_E_ARG;
+  hipDeviceSynchronize();
+  free_handle(h);
+  return ETDM_OK;
+}
+
+etdm_status etdm_energy_grad(etdm_handle* h, const void* A, double* E, void* G, void* stream) {
+  if (!h) return ETDM_E_ARG;
+  if ((!A || !G) && h->n_param > 0) return fail(h, ETDM_E_ARG, "null A or G");
+  if (!E) return fail(h, ETDM_E_ARG, "null E");
+  hipStream_t s = S(stream);
+  const size_t pb = (size_t)h->n_param * sizeof(double);
+  if (pb) HIPCHK(h, hipMemcpyAsync(h->par_ws, A, pb, hipMemcpyDeviceToDevice, s));
+  run_energy_grad(h, s);
+  if (pb) HIPCHK(h, hipMemcpyAsync(G, h->grad_ws, pb, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(E, h->E_ws, (h->n_inst + 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipGetLastError());
+  return ETDM_OK;
+}
+
+etdm_status etdm_expm(etdm_handle* h, const void* A, void* U, void* stream) {
+  if (!h) return ETDM_E_ARG;
+  if ((!A && h->n_param > 0) || !U) return fail(h, ETDM_E_ARG, "null A or U");
+  hipStream_t s = S(stream);
+  const size_t pb = (size_t)h->n_param * sizeof(double);
+  if (pb) HIPCHK(h, hipMemcpyAsync(h->par_ws, A, pb, hipMemcpyDeviceToDevice, s));
+  if (h->kind == ETDM_REAL_OV) {
+    ov_expm(h, s);
+    HIPCHK(h, hipMemcpyAsync(U, h->U_ws, h->n_U * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    z_exponential_part(h, s);
+    char* u = static_cast<char*>(U);
+    for (int i = 0; i < h->n_inst; ++i) {
+      const size_t b = 2 * sizeof(double) * h->M[i] * h->M[i];
+      HIPCHK(h, hipMemcpyAsync(u, h->zb[i].Ue, b, hipMemcpyDeviceToDevice, s));
+      u += b;
+    }
+  }
+  HIPCHK(h, hipGetLastError());
+  return ETDM_OK;
+}
+
+etdm_status etdm_set_reference(etdm_handle* h, const void* A, void* stream) {
+  if (!h) return ETDM_E_ARG;
+  if (!A && h->n_param > 0) return fail(h, ETDM_E_ARG, "null A");
+  hipStream_t s = S(stream);
+  const size_t pb = (size_t)h->n_param * sizeof(double);
+  if (pb) HIPCHK(h, hipMemcpyAsync(h->par_ws, A, pb, hipMemcpyDeviceToDevice, s));
+  new_reference(h, s);
+  HIPCHK(h, hipGetLastError());
+  h->lb_init = false;
+  return ETDM_OK;
+}
+
+etdm_status etdm_sync_status(etdm_handle* h, void* stream) {
+  if (!h) return ETDM_E_ARG;
+  return check_status(h, S(stream));
+}
+
+etdm_status etdm_set_timing(etdm_handle* h, int64_t mask) {
+  if (!h) return ETDM_E_ARG;
+  for (size_t i = 0; i < h->timers.size(); ++i) {
+    StageTimer& t = h->timers[i];
+    const bool want = (mask >> i) & 1;
+    if (want && t.ev0.empty()) {
+      t.ev0.resize(TIMER_RING);
+      t.ev1.resize(TIMER_RING);
+      t.pending.assign(TIMER_RING, 0);
+      for (int k = 0; k < TIMER_RING; ++k) {
+        HIPCHK(h, hipEventCreate(&t.ev0[k]));
+        HIPCHK(h, hipEventCreate(&t.ev1[k]));
+      }
+    }
+  }
+  h->tmask = mask;
+  return ETDM_OK;
+}
+
+etdm_status etdm_reset_timing(etdm_handle* h) {
+  if (!h) return ETDM_E_ARG;
+  for (StageTimer& t : h->timers) {
+    for (size_t k = 0; k < t.pending.size(); ++k) timer_collect(t, (int)k);
+    t.total_ms = 0.0;
+    t.launches = 0;
+  }
+  return ETDM_OK;
+}
+
+int32_t etdm_stage_count(const etdm_handle* h) { return h ? (int32_t)h->timers.size() : 0; }
+
+etdm_status etdm_stage_info(etdm_handle* h, int32_t i, const char** name, int64_t* launches, double* total_ms,
+                            double* flops, double* bytes) {
+  if (!h || i < 0 || i >= (int32_t)h->timers.size()) return ETDM_E_ARG;
+  StageTimer& t = h->timers[i];
+  for (size_t k = 0; k < t.pending.size(); ++k) timer_collect(t, (int)k);
+  if (name) *name = t.name;
+  if (launches) *launches = t.launches;
+  if (total_ms) *total_ms = t.total_ms;
+  if (flops) *flops = t.flops;
+  if (bytes) *bytes = t.bytes;
+  return ETDM_OK;
+}
+
+etdm_status etdm_lbfgs_step(etdm_handle* h, const etdm_lbfgs_params* params, void* A, double* E, void* G,
+                            etdm_lbfgs_info* info, void* stream) {
+  if (!h) return ETDM_E_ARG;
+  if ((!A || !G) && h->n_param > 0) return fail(h, ETDM_E_ARG, "null A or G");
+  if (!E || !info) return fail(h, ETDM_E_ARG, "null E or info");
+  etdm_lbfgs_params P;
+  if (params) P = *params;
+  else etdm_lbfgs_defaults(&P);
+  if (P.m < 1 || P.m > LB_MMAX || P.max_ls < 1 || !(P.c1 > 0.0) || !(P.c2 > P.c1) || !(P.c2 < 1.0) ||
+      !(P.gamma >= 0.0) || !(P.gamma <= 1.0) || !(P.beta0 > 0.0) || P.reset_every < 0)
+    return fail(h, ETDM_E_ARG, "invalid L-BFGS parameters");
+  hipStream_t s = S(stream);
+  const int64_t n = h->n_param;
+  const size_t pb = (size_t)n * sizeof(double);
+  std::memset(info, 0, sizeof(*info));
+  if (!h->lb_init) {
+    if (pb) HIPCHK(h, hipMemcpyAsync(h->x, A, pb, hipMemcpyDeviceToDevice, s));
+    h->lb_iter = 0;
+    h->lb_evals = 0;
+    h->lb_beta = P.beta0;
+    CHECK(lb_initialise(h, P, s));
+    h->lb_init = true;
+  } else if (P.reset_every > 0 && h->lb_iter > 0 && h->lb_iter % P.reset_every == 0) {
+    // reference reset (Sec. 3.4): C0 <- C0 exp(A), A <- 0, memory erased
+    HIPCHK(h, hipMemcpyAsync(h->par_ws, h->x, pb, hipMemcpyDeviceToDevice, s));
+    new_reference(h, s);
+    launch_fill(h->x, n, 0.0, s);
+    CHECK(lb_initialise(h, P, s));
+    info->flags |= 1;
+  }
+  h->lb_m = std::min(std::max(P.m, 1), LB_MMAX);
+  if (h->lb_count > h->lb_m) h->lb_count = h->lb_m;
+  double dphi0 = 0.0;
+  lb_direction(h, P.gamma, s);
+  launch_dot(h->g, h->p, n, h->partial, h->sc + SC_DPHI, s);
+  HIPCHK(h, hipMemcpy(&dphi0, h->sc + SC_DPHI, sizeof(double), hipMemcpyDeviceToHost));
+  if (!(dphi0 < 0.0)) {
+    h->lb_count = 0;
+    lb_steepest(h, P.gamma, s);
+    launch_dot(h->g, h->p, n, h->partial, h->sc + SC_DPHI, s);
+    HIPCHK(h, hipMemcpy(&dphi0, h->sc + SC_DPHI, sizeof(double), hipMemcpyDeviceToHost));
+    info->flags |= 2;
+  }
+  double alpha = 0.0, f_new = h->lb_E;
+  bool ok = false;
+  CHECK(lb_line_search(h, P, h->lb_E, dphi0, alpha, f_new, ok, s));
+  if (!ok) {
+    h->lb_count = 0;
+    lb_steepest(h, P.gamma, s);
+    launch_dot(h->g, h->p, n, h->partial, h->sc + SC_DPHI, s);
+    HIPCHK(h, hipMemcpy(&dphi0, h->sc + SC_DPHI, sizeof(double), hipMemcpyDeviceToHost));
+    info->flags |= 2;
+    CHECK(lb_line_search(h, P, h->lb_E, dphi0, alpha, f_new, ok, s));
+    if (!ok) {
+      info->flags |= 4;
+      info->iter = h->lb_iter;
+      info->n_evals = h->lb_evals;
+      info->E = h->lb_E;
+      return fail(h, ETDM_E_LINESEARCH, "no acceptable step along the search direction");
+    }
+  }
+  // memory update: s = xt - x, y = gt - g, beta = |y|^2 / (s.y) when s.y > 0
+  const int slot_i = h->lb_head;
+  double* Sn = slot(h->S, n, slot_i);
+  double* Yn = slot(h->Yv, n, slot_i);
+  HIPCHK(h, hipMemcpyAsync(Sn, h->xt, pb, hipMemcpyDeviceToDevice, s));
+  launch_axpby(Sn, h->x, n, 1.0, nullptr, -1.0, nullptr, s);
+  HIPCHK(h, hipMemcpyAsync(Yn, h->gt, pb, hipMemcpyDeviceToDevice, s));
+  launch_axpby(Yn, h->g, n, 1.0, nullptr, -1.0, nullptr, s);
+  launch_dot(Sn, Yn, n, h->partial, h->sc + SC_SY, s);
+  launch_dot(Yn, Yn, n, h->partial, h->sc + SC_YY, s);
+  launch_dot(h->gt, h->gt, n, h->partial, h->sc + SC_GG, s);
+  double v[8];
+  HIPCHK(h, hipMemcpy(v, h->sc, sizeof(v), hipMemcpyDeviceToHost));
+  if (v[SC_SY] > 0.0) {
+    HIPCHK(h, hipMemcpyAsync(h->sc + SC_YS0 + slot_i, h->sc + SC_SY, sizeof(double), hipMemcpyDeviceToDevice, s));
+    h->lb_head = (h->lb_head + 1) % h->lb_m;
+    h->lb_count = std::min(h->lb_count + 1, h->lb_m);
+    h->lb_beta = v[SC_YY] / v[SC_SY];
+  }
+  std::swap(h->x, h->xt);
+  std::swap(h->g, h->gt);
+  h->lb_E = f_new;
+  ++h->lb_iter;
+  if (pb) {
+    HIPCHK(h, hipMemcpyAsync(A, h->x, pb, hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(G, h->g, pb, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(h, hipMemcpyAsync(E, h->E_ws, (h->n_inst + 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  info->iter = h->lb_iter;
+  info->n_evals = h->lb_evals;
+  info->alpha = alpha;
+  info->E = f_new;
+  info->gnorm = std::sqrt(std::max(v[SC_GG], 0.0));
+  return ETDM_OK;
+}
+
+}  // extern "C"

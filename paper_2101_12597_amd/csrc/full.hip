@@ -1,0 +1,429 @@
+// Kernels of the complex full path: one skew-Hermitian A per k-point.
+//
+//   iA = V diag(w) V^H                      (FP64 Jacobi)          Sec. 3.4, Eq. ed
+//   exp(A) = V diag(exp(-i w)) V^H,  C = C0 exp(A)
+//   d_mu = sum_m f_m |C_mu_m|^2 = (rho)_mu_mu,  n = sum_k w_k d_k (coupled k-points)
+//   H = H0 + U diag(n),  H_MO = C^H H C,  L = w [F, H_MO]            Sec. 2
+//   Y = V ((V^H L V) o D) V^H,  D_pq = int_0^1 exp(-i t (w_p - w_q)) dt
+//   G_ij = dE/dRe a_ij + i dE/dIm a_ij = -(2 - delta_ij) Y_ij  (i <= j)   Eq. gradients
+#include "ov.h"
+
+namespace etdm {
+
+__device__ __forceinline__ int zfind(const int* __restrict__ begin, int n, int idx) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= idx) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ double sincz(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
+
+// H = iA from the upper triangle (incl. the diagonal) of A; Re of the diagonal is ignored.
+__global__ void z_build_iA_kernel(const ZInst* __restrict__ zi, const int* __restrict__ begin, int n_inst,
+                                  int total) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = zfind(begin, n_inst, idx);
+  const ZInst& z = zi[ii];
+  const int M = z.M, e = idx - begin[ii];
+  const int i = e / M, j = e - i * M;
+  const double2* A = reinterpret_cast<const double2*>(z.A);
+  double2* H = reinterpret_cast<double2*>(z.Hk);
+  double2 v;
+  if (i < j) {
+    double2 a = A[(size_t)i * M + j];
+    v = make_double2(-a.y, a.x);  // i * a
+  } else if (i > j) {
+    double2 a = A[(size_t)j * M + i];
+    v = make_double2(-a.y, -a.x);  // conj(i * a_ji)
+  } else {
+    v = make_double2(-A[(size_t)i * M + i].y, 0.0);
+  }
+  H[e] = v;
+}
+
+// Vp[i][p] = V[i][p] exp(-i w_p)
+__global__ void z_phase_kernel(const ZInst* __restrict__ zi, const int* __restrict__ begin, int n_inst,
+                               int total) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = zfind(begin, n_inst, idx);
+  const ZInst& z = zi[ii];
+  const int M = z.M, e = idx - begin[ii];
+  const int p = e % M;
+  double sn, cs;
+  sincos(z.w[p], &sn, &cs);
+  const double2 v = reinterpret_cast<const double2*>(z.V)[e];
+  reinterpret_cast<double2*>(z.Vp)[e] = make_double2(v.x * cs + v.y * sn, v.y * cs - v.x * sn);
+}
+
+// d_mu = sum_m f_m |C_mu_m|^2 and e_mu = sum_m f_m Re(conj(C_mu_m) (H0 C)_mu_m); one wavefront per row
+__global__ __launch_bounds__(256) void z_rows_kernel(const ZInst* __restrict__ zi, const int* __restrict__ begin,
+                                                     int n_inst, int total_rows) {
+  const int lane = threadIdx.x & 63;
+  const int row_g = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row_g >= total_rows) return;
+  const int ii = zfind(begin, n_inst, row_g);
+  const ZInst& z = zi[ii];
+  const int M = z.M, mu = row_g - begin[ii];
+  const double2* C = reinterpret_cast<const double2*>(z.C) + (size_t)mu * M;
+  const double2* T = reinterpret_cast<const double2*>(z.T) + (size_t)mu * M;
+  double sd = 0.0, se = 0.0;
+  for (int m = lane; m < M; m += 64) {
+    const double2 c = C[m], t = T[m];
+    const double fm = z.f[m];
+    sd += fm * (c.x * c.x + c.y * c.y);
+    se += fm * (c.x * t.x + c.y * t.y);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sd += __shfl_xor(sd, o);
+    se += __shfl_xor(se, o);
+  }
+  if (lane == 0) {
+    z.d[mu] = sd;
+    z.e[mu] = se;
+  }
+}
+
+// n_mu = sum_k w_k d_k,mu in a fixed order over k
+__global__ void z_hubbard_density_kernel(const ZInst* __restrict__ zi, int n_inst, double* n_out, int M) {
+  int mu = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mu >= M) return;
+  double s = 0.0;
+  for (int k = 0; k < n_inst; ++k) s += zi[k].weight * zi[k].d[mu];
+  n_out[mu] = s;
+}
+
+// T = H0 C + U diag(n) C, one wavefront per row
+__global__ __launch_bounds__(256) void z_apply_hubbard_kernel(const ZInst* __restrict__ zi,
+                                                              const int* __restrict__ begin, int n_inst,
+                                                              int total_rows, double U) {
+  const int lane = threadIdx.x & 63;
+  const int row_g = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row_g >= total_rows) return;
+  const int ii = zfind(begin, n_inst, row_g);
+  const ZInst& z = zi[ii];
+  const int M = z.M, mu = row_g - begin[ii];
+  const double un = U * z.n[mu];
+  const double2* C = reinterpret_cast<const double2*>(z.C) + (size_t)mu * M;
+  double2* T = reinterpret_cast<double2*>(z.T) + (size_t)mu * M;
+  for (int m = lane; m < M; m += 64) {
+    double2 t = T[m], c = C[m];
+    T[m] = make_double2(t.x + un * c.x, t.y + un * c.y);
+  }
+}
+
+__device__ __forceinline__ void zneumaier(double& s, double& c, double x) {
+  double t = s + x;
+  c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+  s = t;
+}
+
+__device__ double zblock_sum(double s, double c, double* red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    double s2 = __shfl_xor(s, o), c2 = __shfl_xor(c, o);
+    double t = s + s2;
+    c += c2 + ((fabs(s) >= fabs(s2)) ? (s - t) + s2 : (s2 - t) + s);
+    s = t;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) {
+    red[2 * wave] = s;
+    red[2 * wave + 1] = c;
+  }
+  __syncthreads();
+  double S = 0.0, Cc = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    double x = red[2 * w], t = S + x;
+    Cc += ((fabs(S) >= fabs(x)) ? (S - t) + x : (x - t) + S) + red[2 * w + 1];
+    S = t;
+  }
+  return S + Cc;
+}
+
+// E_k = w_k sum_mu e_mu (+ (U/2) sum d^2 for independent instances)
+__global__ __launch_bounds__(256) void z_energy_kernel(const ZInst* __restrict__ zi, int couple, double U,
+                                                       double* E) {
+  __shared__ double red[16];
+  const ZInst& z = zi[blockIdx.x];
+  double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+  for (int mu = threadIdx.x; mu < z.M; mu += blockDim.x) {
+    zneumaier(s1, c1, z.e[mu]);
+    if (!couple) zneumaier(s2, c2, z.d[mu] * z.d[mu]);
+  }
+  const double band = zblock_sum(s1, c1, red);
+  const double hub = zblock_sum(s2, c2, red);
+  if (threadIdx.x == 0) E[blockIdx.x] = z.weight * band + (couple ? 0.0 : 0.5 * U * hub);
+}
+
+// L[m][k] = w (f_m - f_k) H_MO[m][k], in place
+__global__ void z_commutator_kernel(const ZInst* __restrict__ zi, const int* __restrict__ begin, int n_inst,
+                                    int total) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = zfind(begin, n_inst, idx);
+  const ZInst& z = zi[ii];
+  const int M = z.M, e = idx - begin[ii];
+  const int m = e / M, k = e - m * M;
+  const double fac = z.weight * (z.f[m] - z.f[k]);
+  double2* L = reinterpret_cast<double2*>(z.L);
+  const double2 h = L[e];
+  L[e] = make_double2(fac * h.x, fac * h.y);
+}
+
+// Lt[p][q] *= exp(-i x/2) sinc(x/2), x = w_p - w_q (stored in z.L)
+__global__ void z_divdiff_kernel(const ZInst* __restrict__ zi, const int* __restrict__ begin, int n_inst,
+                                 int total) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = zfind(begin, n_inst, idx);
+  const ZInst& z = zi[ii];
+  const int M = z.M, e = idx - begin[ii];
+  const int p = e / M, q = e - p * M;
+  const double x = 0.5 * (z.w[p] - z.w[q]);
+  double sn, cs;
+  sincos(x, &sn, &cs);
+  const double sc = sincz(x);
+  const double dr = cs * sc, di = -sn * sc;
+  double2* L = reinterpret_cast<double2*>(z.L);
+  const double2 v = L[e];
+  L[e] = make_double2(v.x * dr - v.y * di, v.x * di + v.y * dr);
+}
+
+// G_ij = -(2 - delta_ij) Y_ij for i <= j (Re of the diagonal is not a variable), 0 below
+__global__ void z_grad_kernel(const ZInst* __restrict__ zi, const int* __restrict__ begin, int n_inst,
+                              int total, int* status) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = zfind(begin, n_inst, idx);
+  const ZInst& z = zi[ii];
+  const int M = z.M, e = idx - begin[ii];
+  const int i = e / M, j = e - i * M;
+  const double2 y = reinterpret_cast<const double2*>(z.Y)[e];
+  double2 g;
+  if (i < j) g = make_double2(-2.0 * y.x, -2.0 * y.y);
+  else if (i == j) g = make_double2(0.0, -y.y);
+  else g = make_double2(0.0, 0.0);
+  reinterpret_cast<double2*>(z.G)[e] = g;
+  if (!(isfinite(g.x) && isfinite(g.y))) atomicOr(status, ST_NONFINITE);
+}
+
+static inline int zb(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+void launch_z_build_iA(const ZInst* d, const int* b, int n, int total, hipStream_t s) {
+  if (total > 0) z_build_iA_kernel<<<zb(total, 256), 256, 0, s>>>(d, b, n, total);
+}
+void launch_z_phase(const ZInst* d, const int* b, int n, int total, hipStream_t s) {
+  if (total > 0) z_phase_kernel<<<zb(total, 256), 256, 0, s>>>(d, b, n, total);
+}
+void launch_z_rows(const ZInst* d, const int* b, int n, int rows, hipStream_t s) {
+  if (rows > 0) z_rows_kernel<<<zb(rows, 4), 256, 0, s>>>(d, b, n, rows);
+}
+void launch_z_hubbard_density(const ZInst* d, int n, int couple, double* n_out, int M, hipStream_t s) {
+  (void)couple;
+  if (M > 0) z_hubbard_density_kernel<<<zb(M, 256), 256, 0, s>>>(d, n, n_out, M);
+}
+void launch_z_apply_hubbard(const ZInst* d, const int* b, int n, int rows, double U, hipStream_t s) {
+  if (rows > 0) z_apply_hubbard_kernel<<<zb(rows, 4), 256, 0, s>>>(d, b, n, rows, U);
+}
+void launch_z_energy(const ZInst* d, int n, int couple, double U, double* E, hipStream_t s) {
+  if (n > 0) z_energy_kernel<<<n, 256, 0, s>>>(d, couple, U, E);
+}
+void launch_z_commutator(const ZInst* d, const int* b, int n, int total, hipStream_t s) {
+  if (total > 0) z_commutator_kernel<<<zb(total, 256), 256, 0, s>>>(d, b, n, total);
+}
+void launch_z_divdiff(const ZInst* d, const int* b, int n, int total, hipStream_t s) {
+  if (total > 0) z_divdiff_kernel<<<zb(total, 256), 256, 0, s>>>(d, b, n, total);
+}
+void launch_z_grad(const ZInst* d, const int* b, int n, int total, int* status, hipStream_t s) {
+  if (total > 0) z_grad_kernel<<<zb(total, 256), 256, 0, s>>>(d, b, n, total, status);
+}
+
+// ---------------------------------------------------------------------------
+// L-BFGS vector kernels (FP64)
+// ---------------------------------------------------------------------------
+constexpr int DOT_BLOCKS = 512;
+
+__global__ __launch_bounds__(256) void dot_partial_kernel(const double* __restrict__ x,
+                                                          const double* __restrict__ y, int64_t n,
+                                                          double* partial) {
+  __shared__ double red[16];
+  double s = 0.0, c = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    zneumaier(s, c, x[i] * y[i]);
+  double t = zblock_sum(s, c, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void dot_final_kernel(const double* partial, int nb, double* out) {
+  __shared__ double red[16];
+  double s = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) zneumaier(s, c, partial[i]);
+  double t = zblock_sum(s, c, red);
+  if (threadIdx.x == 0) *out = t;
+}
+
+__global__ void axpby_kernel(double* y, const double* x, int64_t n, double ca, const double* pa, double cb,
+                             const double* pb) {
+  const double a = ca * (pa ? *pa : 1.0), b = cb * (pb ? *pb : 1.0);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (a == 0.0 ? 0.0 : a * y[i]) + (b == 0.0 ? 0.0 : b * x[i]);
+}
+
+__global__ void scalar_ratio_kernel(double* out, const double* num, const double* den, double c) {
+  *out = c * (*num) / (*den);
+}
+__global__ void scalar_sub_kernel(double* out, const double* a, const double* b) { *out = *a - *b; }
+
+__global__ void precond_kernel(double* r, const double* q, const double* h, const double* w, int64_t n,
+                               double gamma, double beta) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = q[i] / ((1.0 - gamma) * h[i] + gamma * beta * w[i]);
+}
+
+__global__ void hdiag_ov_kernel(double* h, const double* eps, const double* f, int M, int N, double w) {
+  const int Nv = M - N;
+  int64_t total = (int64_t)N * Nv;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / Nv), j = N + (int)(idx - (int64_t)i * Nv);
+    h[idx] = w * fmax(0.0, -2.0 * (eps[i] - eps[j]) * (f[i] - f[j]));
+  }
+}
+
+__global__ void hdiag_z_kernel(double* h, double* wv, const double* eps, const double* f, int M, double w) {
+  int64_t total = (int64_t)M * M;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / M), j = (int)(idx - (int64_t)i * M);
+    const double v = w * fmax(0.0, -2.0 * (eps[i] - eps[j]) * (f[i] - f[j]));
+    h[2 * idx] = (i < j) ? v : 0.0;       // Re a_ij, i < j
+    h[2 * idx + 1] = (i <= j) ? v : 0.0;  // Im a_ij, i <= j
+    wv[2 * idx] = (i < j) ? w : 1.0;
+    wv[2 * idx + 1] = (i <= j) ? w : 1.0;
+  }
+}
+
+__global__ void fill_kernel(double* x, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// set-up kernels: block-sparse H0 -> dense, orbital energies of the preconditioner
+// ---------------------------------------------------------------------------
+// dense[(bi*bs + r) * M + bj*bs + c] = blocks[p][r][c] for block p at (bi, bj)
+__global__ void bsr_to_dense_kernel(double* dense, int M, const double* blocks, const int* brow,
+                                    const int* bcol, int nnzb, int bs) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = (int64_t)nnzb * bs * bs;
+  if (idx >= total) return;
+  const int p = (int)(idx / (bs * bs));
+  const int rc = (int)(idx - (int64_t)p * bs * bs);
+  const int r = rc / bs, c = rc - r * bs;
+  dense[(size_t)(brow[p] * bs + r) * M + bcol[p] * bs + c] = blocks[idx];
+}
+
+// n0_mu = sum_i f_i |C0_mu_i|^2 (row of a real or complex M x M matrix)
+__global__ __launch_bounds__(256) void occ_density_kernel(const double* C0, const double* f, int M, int cplx,
+                                                          double* out) {
+  const int lane = threadIdx.x & 63;
+  const int mu = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (mu >= M) return;
+  double s = 0.0;
+  for (int i = lane; i < M; i += 64) {
+    if (cplx) {
+      double2 c = reinterpret_cast<const double2*>(C0)[(size_t)mu * M + i];
+      s += f[i] * (c.x * c.x + c.y * c.y);
+    } else {
+      double c = C0[(size_t)mu * M + i];
+      s += f[i] * c * c;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) out[mu] = s;
+}
+
+// eps_i = Re sum_mu conj(C0_mu_i) ((H0 C0)_mu_i + U n0_mu C0_mu_i); one thread per column
+__global__ void column_eps_kernel(const double* C0, const double* HC0, const double* n0, double U, int M,
+                                  int cplx, double* eps) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  double s = 0.0;
+  for (int mu = 0; mu < M; ++mu) {
+    if (cplx) {
+      double2 c = reinterpret_cast<const double2*>(C0)[(size_t)mu * M + i];
+      double2 h = reinterpret_cast<const double2*>(HC0)[(size_t)mu * M + i];
+      s += c.x * h.x + c.y * h.y + U * n0[mu] * (c.x * c.x + c.y * c.y);
+    } else {
+      double c = C0[(size_t)mu * M + i];
+      s += c * (HC0[(size_t)mu * M + i] + U * n0[mu] * c);
+    }
+  }
+  eps[i] = s;
+}
+
+// out[mu] = sum_k w_k x_k[mu], fixed order over k
+__global__ void weighted_vsum_kernel(const double* const* xs, const double* ws, int n, int M, double* out) {
+  int mu = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mu >= M) return;
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) s += ws[k] * xs[k][mu];
+  out[mu] = s;
+}
+
+static inline int vgrid(int64_t n) { return (int)std::min<int64_t>(2048, std::max<int64_t>(1, (n + 255) / 256)); }
+
+void launch_dot(const double* x, const double* y, int64_t n, double* partial, double* out, hipStream_t s) {
+  dot_partial_kernel<<<DOT_BLOCKS, 256, 0, s>>>(x, y, n, partial);
+  dot_final_kernel<<<1, 256, 0, s>>>(partial, DOT_BLOCKS, out);
+}
+void launch_axpby(double* y, const double* x, int64_t n, double ca, const double* pa, double cb,
+                  const double* pb, hipStream_t s) {
+  if (n > 0) axpby_kernel<<<vgrid(n), 256, 0, s>>>(y, x, n, ca, pa, cb, pb);
+}
+void launch_scalar_ratio(double* out, const double* num, const double* den, double c, hipStream_t s) {
+  scalar_ratio_kernel<<<1, 1, 0, s>>>(out, num, den, c);
+}
+void launch_scalar_sub(double* out, const double* a, const double* b, hipStream_t s) {
+  scalar_sub_kernel<<<1, 1, 0, s>>>(out, a, b);
+}
+void launch_precond(double* r, const double* q, const double* h, const double* w, int64_t n, double gamma,
+                    double beta, hipStream_t s) {
+  if (n > 0) precond_kernel<<<vgrid(n), 256, 0, s>>>(r, q, h, w, n, gamma, beta);
+}
+void launch_hdiag_ov(double* h, const double* eps, const double* f, int M, int N, double w, hipStream_t s) {
+  int64_t n = (int64_t)N * (M - N);
+  if (n > 0) hdiag_ov_kernel<<<vgrid(n), 256, 0, s>>>(h, eps, f, M, N, w);
+}
+void launch_hdiag_z(double* h, double* wv, const double* eps, const double* f, int M, double w, hipStream_t s) {
+  int64_t n = (int64_t)M * M;
+  if (n > 0) hdiag_z_kernel<<<vgrid(n), 256, 0, s>>>(h, wv, eps, f, M, w);
+}
+void launch_fill(double* x, int64_t n, double v, hipStream_t s) {
+  if (n > 0) fill_kernel<<<vgrid(n), 256, 0, s>>>(x, n, v);
+}
+
+void launch_bsr_to_dense(double* dense, int M, const double* blocks, const int* brow, const int* bcol, int nnzb,
+                         int bs, hipStream_t s) {
+  int64_t total = (int64_t)nnzb * bs * bs;
+  if (total > 0) bsr_to_dense_kernel<<<zb(total, 256), 256, 0, s>>>(dense, M, blocks, brow, bcol, nnzb, bs);
+}
+void launch_occ_density(const double* C0, const double* f, int M, int cplx, double* out, hipStream_t s) {
+  if (M > 0) occ_density_kernel<<<zb(M, 4), 256, 0, s>>>(C0, f, M, cplx, out);
+}
+void launch_column_eps(const double* C0, const double* HC0, const double* n0, double U, int M, int cplx,
+                       double* eps, hipStream_t s) {
+  if (M > 0) column_eps_kernel<<<zb(M, 256), 256, 0, s>>>(C0, HC0, n0, U, M, cplx, eps);
+}
+
+void launch_weighted_vsum(const double* const* xs, const double* ws, int n, int M, double* out, hipStream_t s) {
+  if (M > 0) weighted_vsum_kernel<<<zb(M, 256), 256, 0, s>>>(xs, ws, n, M, out);
+}
+
+}  // namespace etdm

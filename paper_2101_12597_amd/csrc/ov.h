@@ -1,0 +1,120 @@
+// Descriptors and launchers of the elementwise / reduction kernels.
+#pragma once
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace etdm {
+
+constexpr int OV_NQ = 48;  // Gauss-Legendre nodes for the pair integrals (exact to rounding for sigma <= ~40)
+
+struct OvSpec {
+  const double* s;  // eigenvalues of P [N]
+  const double* X;  // eigenvectors [N x N]
+  double* Xcsw;     // [3N x N]
+  double* T1s;      // [N x NQ]
+  double* T2;
+  double* T3s;
+  double* T3;
+  int32_t N;
+};
+
+struct OvRows {
+  const double* Cocc;  // [M x N]
+  double* T;           // [M x N]: H0 Cocc in, H Cocc out
+  double* d;           // [M]
+  double* e;           // [M]
+  int32_t M, N;
+  double f_occ;
+};
+
+struct OvEnergy {
+  const double* d;
+  const double* e;
+  int32_t M;
+  double f_occ;
+  double weight;
+};
+
+struct OvPair {
+  const double* Gam;
+  const double* mu1;
+  const double* mu2;
+  double* Nm;
+  int32_t N;
+};
+
+void launch_ov_spectral(const OvSpec* d, const int* d_begin, int n_inst, int total, const double* gl_t,
+                        const double* gl_w, hipStream_t s);
+void launch_ov_rows(const OvRows* d, const int* d_begin, int n_inst, int total_rows, double U, hipStream_t s);
+void launch_ov_energy(const OvEnergy* d, int n_inst, double U, double* E, hipStream_t s);
+void launch_total_energy(double* E, int n_inst, double extra_hub, const double* hub_vec, int hub_n, double U,
+                         int* status, hipStream_t s);
+void launch_ov_pair(const OvPair* d, const int* d_begin, int n_inst, int total, hipStream_t s);
+void launch_nonfinite_scan(const double* g, int64_t n, int* status, hipStream_t s);
+void launch_set_identity(double* Y, int64_t ld, int n, double alpha, hipStream_t s);
+void launch_copy_block(double* dst, int64_t ldd, const double* src, int64_t lds, int m, int n, double alpha,
+                       hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// complex full path (interleaved complex float64; pointers address doubles)
+// ---------------------------------------------------------------------------
+struct ZInst {
+  const double* A;   // parameters [M x M] complex (upper triangle read)
+  double* Hk;        // iA workspace [M x M]
+  double* V;         // eigenvectors [M x M]
+  const double* w;   // eigenvalues [M]
+  double* Vp;        // V diag(exp(-i w)) [M x M]
+  const double* C;   // orbitals [M x M]
+  double* T;         // H0 C in, H C out [M x M]
+  double* d;         // diag(rho) [M] (real)
+  double* e;         // row energies [M] (real)
+  const double* n;   // Hubbard density used for this instance [M]
+  double* L;         // H_MO in, L out [M x M]
+  double* G;         // gradient out [M x M]
+  const double* Y;   // Y [M x M]
+  const double* f;   // occupations [M]
+  int32_t M;
+  double weight;
+};
+
+void launch_z_build_iA(const ZInst* d, const int* d_begin, int n_inst, int total, hipStream_t s);
+void launch_z_phase(const ZInst* d, const int* d_begin, int n_inst, int total, hipStream_t s);
+void launch_z_rows(const ZInst* d, const int* d_begin, int n_inst, int total_rows, hipStream_t s);
+void launch_z_hubbard_density(const ZInst* d, int n_inst, int couple, double* n_out, int M, hipStream_t s);
+void launch_z_apply_hubbard(const ZInst* d, const int* d_begin, int n_inst, int total_rows, double U,
+                            hipStream_t s);
+void launch_z_energy(const ZInst* d, int n_inst, int couple, double U, double* E, hipStream_t s);
+void launch_z_commutator(const ZInst* d, const int* d_begin, int n_inst, int total, hipStream_t s);
+void launch_z_divdiff(const ZInst* d, const int* d_begin, int n_inst, int total, hipStream_t s);
+void launch_z_grad(const ZInst* d, const int* d_begin, int n_inst, int total, int* status, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// FP64 vector kernels of the L-BFGS driver (device-resident scalars)
+// ---------------------------------------------------------------------------
+void launch_dot(const double* x, const double* y, int64_t n, double* partial, double* out, hipStream_t s);
+// y = a*y + b*x with a, b = ca * (*pa or 1) and cb * (*pb or 1)
+void launch_axpby(double* y, const double* x, int64_t n, double ca, const double* pa, double cb,
+                  const double* pb, hipStream_t s);
+// out = c * num / den  (device scalars)
+void launch_scalar_ratio(double* out, const double* num, const double* den, double c, hipStream_t s);
+// out = a - b
+void launch_scalar_sub(double* out, const double* a, const double* b, hipStream_t s);
+// r = q / ((1 - gamma) h + gamma beta w)   (Eq. prec_3 applied as a diagonal)
+void launch_precond(double* r, const double* q, const double* h, const double* w, int64_t n, double gamma,
+                    double beta, hipStream_t s);
+// h = w * max(0, -2 (eps_i - eps_j)(f_i - f_j)) over the free variables (REAL_OV layout)
+void launch_hdiag_ov(double* h, const double* eps, const double* f, int M, int N, double w, hipStream_t s);
+// same for the complex layout (interleaved: Re part for i < j, Im part for i <= j, 0 elsewhere)
+void launch_hdiag_z(double* h, double* wv, const double* eps, const double* f, int M, double w, hipStream_t s);
+void launch_fill(double* x, int64_t n, double v, hipStream_t s);
+
+void launch_bsr_to_dense(double* dense, int M, const double* blocks, const int* brow, const int* bcol, int nnzb,
+                         int bs, hipStream_t s);
+void launch_weighted_vsum(const double* const* xs, const double* ws, int n, int M, double* out, hipStream_t s);
+void launch_occ_density(const double* C0, const double* f, int M, int cplx, double* out, hipStream_t s);
+void launch_column_eps(const double* C0, const double* HC0, const double* n0, double U, int M, int cplx,
+                       double* eps, hipStream_t s);
+
+}  // namespace etdm

@@ -1,0 +1,232 @@
+// Kernels of the real occupied-virtual path (Hutter's parametrization
+// A = [[0, B], [-B^T, 0]], equal occupations f_occ on the first N orbitals).
+//
+// With P = B B^T = X diag(s) X^T and sigma = sqrt(s) (the rotation angles):
+//   exp(A) = [[cos sqrt(P), sinc sqrt(P) B], [-B^T sinc sqrt(P), I + B^T W B]],
+//   W = (cos sqrt(P) - I) P^{-1} = X diag(-1/2 sinc^2(sigma/2)) X^T      (Eq. uinv)
+// and the exact gradient (Eq. gradients) in the singular-value basis of B is
+//   dE/dB = -2 (sinc sqrt(P) L_ov + X Nm X^T B),  Gam = X^T (L_ov B^T) X,
+//   Nm[k][l] = Gam[k][l] mu1[k][l] + Gam[l][k] mu2[k][l],
+//   mu1[k][l] = -int_0^1 (t^2/2) cos(t sigma_k) sinc^2(t sigma_l / 2) dt,
+//   mu2[k][l] =  int_0^1 t^2 sinc(t sigma_k) sinc(t sigma_l) dt.
+// The two pair integrals are evaluated by Gauss-Legendre quadrature written as
+// two rank-NQ matrix products (tables built here, products on the GEMM kernel).
+#include "ov.h"
+
+namespace etdm {
+
+__device__ __forceinline__ double sincd(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
+
+__device__ __forceinline__ int find_range(const int* __restrict__ begin, int n, int idx) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= idx) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// per-angle spectral factors fn = [cos sigma | sinc sigma | -1/2 sinc^2(sigma/2)]
+// and the scaled eigenvector copies Xcsw = [X diag(fn0); X diag(fn1); X diag(fn2)],
+// plus the quadrature tables.  One thread per element of the N x N or N x NQ ranges.
+__global__ void ov_spectral_kernel(const OvSpec* __restrict__ specs, const int* __restrict__ begin,
+                                   int n_inst, int total, const double* __restrict__ gl_t,
+                                   const double* __restrict__ gl_w) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = find_range(begin, n_inst, idx);
+  const OvSpec& sp = specs[ii];
+  const int N = sp.N;
+  int e = idx - begin[ii];
+  if (e < N * N) {
+    const int i = e / N, k = e - i * N;
+    const double sig = sqrt(fmax(sp.s[k], 0.0));
+    const double x = sp.X[(size_t)i * N + k];
+    const double h = sincd(0.5 * sig);
+    sp.Xcsw[(size_t)i * N + k] = x * cos(sig);
+    sp.Xcsw[(size_t)(N + i) * N + k] = x * sincd(sig);
+    sp.Xcsw[(size_t)(2 * N + i) * N + k] = x * (-0.5 * h * h);
+    return;
+  }
+  e -= N * N;
+  const int k = e / OV_NQ, j = e - k * OV_NQ;
+  const double sig = sqrt(fmax(sp.s[k], 0.0));
+  const double t = gl_t[j], w = gl_w[j];
+  const double ts = t * sig;
+  const double h = sincd(0.5 * ts);
+  const double sc = sincd(ts);
+  const size_t o = (size_t)k * OV_NQ + j;
+  sp.T1s[o] = cos(ts) * (-0.5 * w * t * t);
+  sp.T2[o] = h * h;
+  sp.T3s[o] = sc * (w * t * t);
+  sp.T3[o] = sc;
+}
+
+// Row pass over the occupied orbitals: d_mu = f sum_i C_mu_i^2 (diagonal of rho),
+// e_mu = sum_i C_mu_i (H0 C)_mu_i, then T = H0 C + U diag(d) C in place.
+// One wavefront per row; lanes stride over columns, reduced in a fixed order.
+__global__ __launch_bounds__(256) void ov_rows_kernel(const OvRows* __restrict__ rows,
+                                                      const int* __restrict__ begin, int n_inst,
+                                                      int total_rows, double U) {
+  const int lane = threadIdx.x & 63;
+  const int row_g = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row_g >= total_rows) return;
+  const int ii = find_range(begin, n_inst, row_g);
+  const OvRows& r = rows[ii];
+  const int mu = row_g - begin[ii];
+  const int N = r.N;
+  const double* c = r.Cocc + (size_t)mu * N;
+  double* t = r.T + (size_t)mu * N;
+  double sd = 0.0, se = 0.0;
+  for (int i = lane; i < N; i += 64) {
+    const double ci = c[i];
+    sd += ci * ci;
+    se += ci * t[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sd += __shfl_xor(sd, o);
+    se += __shfl_xor(se, o);
+  }
+  const double d = r.f_occ * sd;
+  if (lane == 0) {
+    r.d[mu] = d;
+    r.e[mu] = se;
+  }
+  const double ud = U * d;
+  for (int i = lane; i < N; i += 64) t[i] += ud * c[i];
+}
+
+// Neumaier-compensated FP64 sum over a block, fixed order (deterministic).
+__device__ double block_sum_comp(double s, double c, double* red) {
+  // combine (s, c) pairs: first within the wavefront, then across wavefronts
+  for (int o = 32; o > 0; o >>= 1) {
+    double s2 = __shfl_xor(s, o), c2 = __shfl_xor(c, o);
+    double t = s + s2;
+    double err = (fabs(s) >= fabs(s2)) ? (s - t) + s2 : (s2 - t) + s;
+    s = t;
+    c += c2 + err;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) {
+    red[2 * wave] = s;
+    red[2 * wave + 1] = c;
+  }
+  __syncthreads();
+  double S = 0.0, Cc = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    double x = red[2 * w], t = S + x;
+    Cc += ((fabs(S) >= fabs(x)) ? (S - t) + x : (x - t) + S) + red[2 * w + 1];
+    S = t;
+  }
+  return S + Cc;
+}
+
+__device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
+  double t = s + x;
+  c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+  s = t;
+}
+
+// E_i = w_i (f sum_mu e_mu) + (U/2) sum_mu d_mu^2, one block per instance.
+__global__ __launch_bounds__(256) void ov_energy_kernel(const OvEnergy* __restrict__ en, double U,
+                                                        double* __restrict__ E) {
+  __shared__ double red[16];
+  const OvEnergy& q = en[blockIdx.x];
+  double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+  for (int mu = threadIdx.x; mu < q.M; mu += blockDim.x) {
+    neumaier_add(s1, c1, q.e[mu]);
+    neumaier_add(s2, c2, q.d[mu] * q.d[mu]);
+  }
+  const double band = block_sum_comp(s1, c1, red);
+  const double hub = block_sum_comp(s2, c2, red);
+  if (threadIdx.x == 0) E[blockIdx.x] = q.weight * q.f_occ * band + 0.5 * U * hub;
+}
+
+// E_total = sum_i E_i (fixed order), and the non-finite check.
+__global__ void total_energy_kernel(double* E, int n_inst, double extra_hub, const double* hub_vec,
+                                    int hub_n, double U, int* status) {
+  __shared__ double red[16];
+  double s = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) neumaier_add(s, c, E[i]);
+  const double tot = block_sum_comp(s, c, red);
+  double hs = 0.0, hc = 0.0;
+  for (int i = threadIdx.x; i < hub_n; i += blockDim.x) neumaier_add(hs, hc, hub_vec[i] * hub_vec[i]);
+  const double hub = hub_n > 0 ? block_sum_comp(hs, hc, red) : 0.0;
+  if (threadIdx.x == 0) {
+    const double v = tot + 0.5 * U * hub + extra_hub;
+    E[n_inst] = v;
+    if (!isfinite(v)) atomicOr(status, ST_NONFINITE);
+  }
+}
+
+// Nm[k][l] = Gam[k][l] mu1[k][l] + Gam[l][k] mu2[k][l]
+__global__ void ov_pair_kernel(const OvPair* __restrict__ pr, const int* __restrict__ begin, int n_inst,
+                               int total) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = find_range(begin, n_inst, idx);
+  const OvPair& q = pr[ii];
+  const int N = q.N;
+  const int e = idx - begin[ii];
+  const int k = e / N, l = e - k * N;
+  q.Nm[e] = q.Gam[e] * q.mu1[e] + q.Gam[(size_t)l * N + k] * q.mu2[e];
+}
+
+// Non-finite scan of a gradient range (sets ST_NONFINITE).
+__global__ void nonfinite_scan_kernel(const double* __restrict__ g, int64_t n, int* status) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) bad |= !isfinite(g[i]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(status, ST_NONFINITE);
+}
+
+// Y[i][j] = alpha * I (diagonal) for a strided square block
+__global__ void set_identity_kernel(double* Y, int64_t ld, int n, double alpha) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  int i = idx / n, j = idx - i * n;
+  Y[(size_t)i * ld + j] = (i == j) ? alpha : 0.0;
+}
+
+// copy an m x n block between strided row-major matrices, optionally scaled
+__global__ void copy_block_kernel(double* dst, int64_t ldd, const double* src, int64_t lds, int m, int n,
+                                  double alpha) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * n) return;
+  int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
+  dst[(size_t)i * ldd + j] = alpha * src[(size_t)i * lds + j];
+}
+
+static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+void launch_ov_spectral(const OvSpec* d, const int* d_begin, int n_inst, int total, const double* gl_t,
+                        const double* gl_w, hipStream_t s) {
+  if (total > 0) ov_spectral_kernel<<<nblk(total, 256), 256, 0, s>>>(d, d_begin, n_inst, total, gl_t, gl_w);
+}
+void launch_ov_rows(const OvRows* d, const int* d_begin, int n_inst, int total_rows, double U, hipStream_t s) {
+  if (total_rows > 0) ov_rows_kernel<<<nblk(total_rows, 4), 256, 0, s>>>(d, d_begin, n_inst, total_rows, U);
+}
+void launch_ov_energy(const OvEnergy* d, int n_inst, double U, double* E, hipStream_t s) {
+  if (n_inst > 0) ov_energy_kernel<<<n_inst, 256, 0, s>>>(d, U, E);
+}
+void launch_total_energy(double* E, int n_inst, double extra_hub, const double* hub_vec, int hub_n, double U,
+                         int* status, hipStream_t s) {
+  total_energy_kernel<<<1, 256, 0, s>>>(E, n_inst, extra_hub, hub_vec, hub_n, U, status);
+}
+void launch_ov_pair(const OvPair* d, const int* d_begin, int n_inst, int total, hipStream_t s) {
+  if (total > 0) ov_pair_kernel<<<nblk(total, 256), 256, 0, s>>>(d, d_begin, n_inst, total);
+}
+void launch_nonfinite_scan(const double* g, int64_t n, int* status, hipStream_t s) {
+  if (n > 0) nonfinite_scan_kernel<<<(int)std::min<int64_t>(1024, (n + 255) / 256), 256, 0, s>>>(g, n, status);
+}
+void launch_set_identity(double* Y, int64_t ld, int n, double alpha, hipStream_t s) {
+  if (n > 0) set_identity_kernel<<<nblk((int64_t)n * n, 256), 256, 0, s>>>(Y, ld, n, alpha);
+}
+void launch_copy_block(double* dst, int64_t ldd, const double* src, int64_t lds, int m, int n, double alpha,
+                       hipStream_t s) {
+  if (m > 0 && n > 0) copy_block_kernel<<<nblk((int64_t)m * n, 256), 256, 0, s>>>(dst, ldd, src, lds, m, n, alpha);
+}
+
+}  // namespace etdm

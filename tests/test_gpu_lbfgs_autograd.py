@@ -1,0 +1,101 @@
+"""GPU L-BFGS driver (etdm_lbfgs_step) and the autograd Function."""
+import numpy as np
+import pytest
+
+from oracle import etdm as O
+from oracle import lbfgs as LB
+from oracle import scf
+from workloads import make_config, tiny_complex, tiny_real
+from workloads.pack import pack_params, unpack_params
+
+from gpu_helpers import make_handle
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_lbfgs(h, wl, max_iter=333, gtol=1e-8):
+    import torch
+    dev = torch.device("cuda:0")
+    A = torch.zeros(h.n_param, dtype=torch.float64, device=dev)
+    E = torch.empty(h.n_inst + 1, dtype=torch.float64, device=dev)
+    G = torch.empty_like(A)
+    info = None
+    for _ in range(max_iter):
+        info = h.lbfgs_step(A, E, G)
+        if info["gnorm"] < gtol:
+            break
+    return info, A, E
+
+
+def test_config1_lbfgs_reaches_scf_minimum():
+    wl = make_config(1)
+    inst = wl.instances[0]
+    rho0 = inst.C0 @ np.diag(inst.f) @ inst.C0.T
+    E_scf, _, _ = scf.scf_minimum(inst.H0, inst.N, 2.0, wl.hubbard_U, rho0)
+    print("[case] config1 L-BFGS fp64", flush=True)
+    h, _ = make_handle(wl, "fp64")
+    info, A, E = _run_lbfgs(h, wl)
+    st, _ = LB.minimize(make_config(1))
+    print(f"[result] gpu iters={info['iter']} evals={info['n_evals']} E={info['E']!r}; "
+          f"oracle iters={st.n_iter} evals={st.n_evals} E={st.f!r}")
+    assert info["gnorm"] < 1e-8
+    assert abs(info["E"] - E_scf) < 1e-10
+    assert abs(E.cpu().numpy()[-1] - info["E"]) < 1e-12
+    assert abs(info["iter"] - st.n_iter) <= max(5, st.n_iter // 5)
+    h.close()
+
+
+def test_complex_lbfgs_ky_fan_minimum():
+    wl = tiny_complex(8, nk_side=2, kT=0.3, hubbard_U=0.0)
+    ref = sum(i.weight * np.sort(i.f)[::-1] @ np.linalg.eigvalsh(i.H0) for i in wl.instances)
+    print("[case] complex L-BFGS fp64", flush=True)
+    h, _ = make_handle(wl, "fp64")
+    info, _, _ = _run_lbfgs(h, wl)
+    assert info["gnorm"] < 1e-8
+    assert abs(info["E"] - ref) < 1e-10
+    h.close()
+
+
+@pytest.mark.parametrize("kind", ["real", "complex"])
+def test_autograd_function_matches_oracle_and_fd(kind):
+    import torch
+    from paper_2101_12597_amd import etdm_energy
+    wl = tiny_real(11, 3, seed=3, scale=0.4) if kind == "real" else tiny_complex(7, nk_side=1, kT=0.2)
+    params = O.parity_params(wl)
+    print(f"[case] autograd {kind}", flush=True)
+    h, _ = make_handle(wl, "fp64")
+    vec = pack_params(wl, params)
+    A = torch.from_numpy(vec).cuda()
+    if kind == "complex":
+        A = A.view(torch.complex128)
+    A.requires_grad_(True)
+    E = etdm_energy(A.view(torch.float64) if kind == "complex" else A, h) if False else None
+    # the Function works on the float64 parameter view; complex tensors go through view_as_real
+    Af = A.detach().view(torch.float64).clone().requires_grad_(True) if kind == "complex" else A
+    E = etdm_energy(Af, h)
+    E.backward()
+    g = Af.grad.detach().cpu().numpy()
+    E_ref, g_ref = O.energy_grad(wl, params)
+    assert abs(E.item() - E_ref) < 1e-12 * max(1.0, abs(E_ref))
+    g_ref_vec = pack_params(wl, g_ref)
+    assert np.abs(g - g_ref_vec).max() < 1e-10 * max(1.0, np.abs(g_ref_vec).max())
+    # central differences of the GPU energy along a random direction
+    rng = np.random.default_rng(0)
+    d = rng.standard_normal(vec.size)
+    if kind == "complex":
+        # only the free variables move: Re of the strict upper triangle, Im of the upper triangle
+        M = wl.instances[0].M
+        mask = np.zeros((M, M, 2))
+        iu = np.triu_indices(M, 1)
+        mask[iu[0], iu[1], 0] = 1.0
+        iu0 = np.triu_indices(M, 0)
+        mask[iu0[0], iu0[1], 1] = 1.0
+        d = d * mask.ravel()
+    hstep = 1e-4
+
+    def Eat(v):
+        with torch.no_grad():
+            return etdm_energy(torch.from_numpy(v).cuda(), h).item()
+    fd = (Eat(vec + hstep * d) - Eat(vec - hstep * d)) / (2 * hstep)
+    assert abs(fd - g @ d) < 1e-6 * max(1.0, abs(fd))
+    h.close()

@@ -1,0 +1,170 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances:
+  * FP64 mode: energies to 1e-12 relative, gradients to 1e-10 relative
+    (Frobenius norm over the batch), unitaries to 1e-13 absolute;
+  * mixed precision (the target of the bulk contractions): |dE| / N_e < 1e-8 Ha
+    per instance and ||dg|| / ||g|| < 1e-6 per instance.
+"""
+import copy
+
+import numpy as np
+import pytest
+
+from oracle import etdm as O
+from workloads import Instance, Workload, make_config, tiny_complex
+from workloads.gen import binary_occupations, chain_hamiltonian, haar_orthogonal, ov_parameters, rng_for
+
+from gpu_helpers import energy_grad, expm, make_handle, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def ragged_workload(scale=0.3):
+    """Ragged batch covering one-tile, multi-tile and ragged-tail shapes, the LDS and
+    global-memory eigensolvers, odd N, and the degenerate N = 0, N = M, M = 1 cases."""
+    shapes = [(5, 1), (9, 3), (2, 1), (17, 4), (33, 16), (64, 16), (70, 30), (130, 26), (120, 96),
+              (12, 12), (10, 0), (1, 1), (1, 0), (65, 13), (200, 7)]
+    wl = Workload(900, "ragged", "real_ov", 0.5, False)
+    for i, (M, N) in enumerate(shapes):
+        H0 = chain_hamiltonian(M, rng_for(900, i, 0))
+        C0 = haar_orthogonal(M, rng_for(900, i, 1))
+        B = ov_parameters(N, M - N, rng_for(900, i, 2), scale)
+        wl.instances.append(Instance(M=M, N=N, f=binary_occupations(M, N), C0=C0, A=B, H0=H0))
+    return wl
+
+
+def per_instance_errors(wl, E_gpu, g_gpu, E_ref, g_ref_list):
+    out = []
+    for k, inst in enumerate(wl.instances):
+        ne = max(inst.weight * inst.f.sum(), 1.0)
+        dE = abs(E_gpu[k] - E_ref[k]) / ne
+        gn = np.linalg.norm(g_ref_list[k])
+        dg = np.linalg.norm(g_gpu[k] - g_ref_list[k]) / gn if gn > 0 else np.linalg.norm(g_gpu[k])
+        out.append((dE, dg))
+    return out
+
+
+def oracle_per_instance(wl, params):
+    """Per-instance energies and gradients from the definition path."""
+    E_list, g_list = [], []
+    for k, inst in enumerate(wl.instances):
+        sub = copy.copy(wl)
+        sub.instances = [inst]
+        E, (g,) = O.energy_grad(sub, [params[k]])
+        E_list.append(E)
+        g_list.append(g)
+    return np.array(E_list), g_list
+
+
+@pytest.mark.parametrize("which", ["config1", "ragged"])
+def test_real_ov_fp64_matches_oracle(which):
+    wl = make_config(1) if which == "config1" else ragged_workload()
+    params = O.parity_params(wl)
+    print(f"[case] real_ov fp64 {which}", flush=True)
+    h, _ = make_handle(wl, "fp64")
+    E, g = energy_grad(h, wl, params)
+    E_ref, g_ref = oracle_per_instance(wl, params)
+    assert abs(E[-1] - E_ref.sum()) <= 1e-12 * max(1.0, abs(E_ref.sum()))
+    for k in range(len(wl.instances)):
+        assert abs(E[k] - E_ref[k]) <= 1e-12 * max(1.0, abs(E_ref[k])), k
+    assert rel_err(g, g_ref) < 1e-10
+    for k, (gk, gr) in enumerate(zip(g, g_ref)):
+        assert np.abs(gk - gr).max() <= 1e-10 * max(np.abs(gr).max(), 1.0), k
+    h.close()
+
+
+@pytest.mark.parametrize("which", ["config1", "ragged"])
+def test_real_ov_expm_matches_oracle(which):
+    wl = make_config(1) if which == "config1" else ragged_workload(scale=0.8)
+    params = O.parity_params(wl)
+    print(f"[case] real_ov expm {which}", flush=True)
+    h, _ = make_handle(wl, "fp64")
+    U = expm(h, wl, params)
+    U_ref = O.unitary(wl, params)
+    for k, (u, r) in enumerate(zip(U, U_ref)):
+        assert np.abs(u - r).max() < 1e-13, k
+        assert np.abs(u.T @ u - np.eye(u.shape[0])).max() < 1e-13
+    h.close()
+
+
+def test_real_ov_zero_rotation_and_repeatability():
+    """A = 0 gives E(0) and the commutator gradient; two calls agree bitwise."""
+    wl = ragged_workload()
+    params = O.zero_params(wl)
+    print("[case] real_ov fp64 A=0 twice", flush=True)
+    h, _ = make_handle(wl, "fp64")
+    E1, g1 = energy_grad(h, wl, params)
+    E2, g2 = energy_grad(h, wl, params)
+    assert np.array_equal(E1, E2)
+    assert all(np.array_equal(a, b) for a, b in zip(g1, g2))
+    E_ref, g_ref = oracle_per_instance(wl, params)
+    assert np.abs(E1[:-1] - E_ref).max() <= 1e-12 * np.abs(E_ref).max()
+    assert rel_err(g1, g_ref) < 1e-11
+    h.close()
+
+
+@pytest.mark.parametrize("precision,tol_e,tol_g", [("fp64", 1e-13, 1e-10), ("fp32", 1e-8, 1e-6),
+                                                   ("bf16x6", 1e-8, 1e-6), ("bf16x3", 1e-6, 1e-4)])
+def test_config2_batched(precision, tol_e, tol_g):
+    """All 148 ragged molecules of config 2 in one batch."""
+    wl = make_config(2)
+    params = O.parity_params(wl)
+    print(f"[case] config2 {precision}", flush=True)
+    h, _ = make_handle(wl, precision)
+    E, g = energy_grad(h, wl, params)
+    E_ref, g_ref = O.energy_grad_ov_workload(wl, params)
+    Ei = np.array([O.energy_grad_ov(inst, p, wl.hubbard_U)[0] for inst, p in zip(wl.instances, params)])
+    errs = per_instance_errors(wl, E, g, Ei, g_ref)
+    worst_e = max(e for e, _ in errs)
+    worst_g = max(x for _, x in errs)
+    print(f"[result] config2 {precision}: max |dE|/Ne = {worst_e:.3e}, max rel |dg| = {worst_g:.3e}")
+    assert worst_e < tol_e
+    assert worst_g < tol_g
+    h.close()
+
+
+@pytest.mark.parametrize("case", ["tiny_fd", "odd_size", "config4_8k"])
+def test_complex_full_matches_oracle(case):
+    if case == "tiny_fd":
+        wl = tiny_complex(12, nk_side=2, kT=0.3)
+        for inst in wl.instances:
+            inst.A = inst.A * 6.0
+    elif case == "odd_size":
+        wl = tiny_complex(13, nk_side=1, kT=0.1)
+    else:
+        wl = make_config(4, nk=8)
+        wl.instances = wl.instances[:8]
+    params = O.parity_params(wl)
+    print(f"[case] complex_full fp64 {case}", flush=True)
+    h, _ = make_handle(wl, "fp64")
+    E, G = energy_grad(h, wl, params)
+    E_ref, G_ref = O.energy_grad(wl, params)
+    assert abs(E[-1] - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
+    assert rel_err(G, G_ref) < 1e-10
+    U = expm(h, wl, params)
+    for u, r in zip(U, O.unitary(wl, params)):
+        assert np.abs(u - r).max() < 1e-13
+    h.close()
+
+
+def test_status_and_argument_errors():
+    import torch
+    from paper_2101_12597_amd import EtdmError
+    wl = make_config(1)
+    h, _ = make_handle(wl, "fp64")
+    A = torch.zeros(10, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(ValueError):
+        h.energy_grad(A, torch.empty(2, dtype=torch.float64, device="cuda:0"), A)
+    params = O.parity_params(wl)
+    params[0] = params[0].copy()
+    params[0][0, 0] = np.nan
+    print("[case] non-finite input", flush=True)
+    from gpu_helpers import pack_params
+    Ad = torch.from_numpy(pack_params(wl, params)).cuda()
+    E = torch.empty(2, dtype=torch.float64, device="cuda:0")
+    G = torch.empty_like(Ad)
+    h.energy_grad(Ad, E, G)
+    with pytest.raises(EtdmError):
+        h.sync_status()
+    h.close()
