@@ -15,7 +15,10 @@
 //
 // MFMA operand layout used below (16x16xK blocks, lane l of the wavefront):
 //   A operand: row l % 16, k slice l / 16;  B operand: column l % 16, same slice;
-//   accumulator element r of lane l: row 4 * (l / 16) + r, column l % 16.
+//   accumulator element r of lane l, FP32 results (f32 and bf16 inputs):
+//     row 4 * (l / 16) + r, column l % 16;
+//   accumulator element r of lane l, FP64 16x16x4:
+//     row l / 16 + 4 * r, column l % 16.
 #include "common.h"
 
 namespace etdm {
@@ -73,13 +76,20 @@ __device__ __forceinline__ void stage_b(const double* __restrict__ B, int64_t ld
   }
 }
 
+// row of accumulator element r of this lane inside a 16 x 16 block
+template <bool F64>
+__device__ __forceinline__ int acc_row(int lane, int r) {
+  return F64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+}
+
+template <bool F64>
 __device__ __forceinline__ void store_tile(const GemmProb& p, int row0, int col0, int wm, int wn,
                                            const double (&acc)[2][2][4]) {
   const int lane = threadIdx.x & 63;
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
       for (int r = 0; r < 4; ++r) {
-        int row = row0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        int row = row0 + wm + i * 16 + acc_row<F64>(lane, r);
         int col = col0 + wn + j * 16 + (lane & 15);
         if (row < p.m && col < p.n) {
           double v = acc[i][j][r];
@@ -172,7 +182,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_k4(const GemmProb* __restrict__
       flush();
     }
   }
-  store_tile(p, row0, col0, wm, wn, acc);
+  store_tile<sizeof(T) == 8>(p, row0, col0, wm, wn, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -267,7 +277,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf16split(const GemmProb* __res
     }
     flush();
   }
-  store_tile(p, row0, col0, wm, wn, acc);
+  store_tile<false>(p, row0, col0, wm, wn, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -352,7 +362,7 @@ __global__ __launch_bounds__(NTHREADS) void zgemm_k4(const GemmProb* __restrict_
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
       for (int r = 0; r < 4; ++r) {
-        int row = row0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        int row = row0 + wm + i * 16 + acc_row<true>(lane, r);
         int col = col0 + wn + j * 16 + (lane & 15);
         if (row < p.m && col < p.n) {
           double2 v = make_double2(cr[i][j][r], ci[i][j][r]);
