@@ -93,6 +93,16 @@ __global__ __launch_bounds__(NT) void jacobi_real(const EighProb* __restrict__ p
     A = pr.A;
     V = pr.V;
   }
+  __syncthreads();
+  // symmetric part (products formed in reduced precision need not be exactly symmetric)
+  for (int e = threadIdx.x; e < n * n; e += NT) {
+    const int i = e / n, k = e - i * n;
+    if (i < k) {
+      const double v = 0.5 * (A[(size_t)i * n + k] + A[(size_t)k * n + i]);
+      A[(size_t)i * n + k] = v;
+      A[(size_t)k * n + i] = v;
+    }
+  }
   for (int e = threadIdx.x; e < n * n; e += NT) V[e] = (e / n == e % n) ? 1.0 : 0.0;
   __syncthreads();
   double fro = 0.0;
@@ -158,6 +168,128 @@ __global__ __launch_bounds__(NT) void jacobi_real(const EighProb* __restrict__ p
   if (LDS)
     for (int e = threadIdx.x; e < n * n; e += NT) pr.V[e] = V[e];
   if ((!converged || !finite) && threadIdx.x == 0) atomicOr(status, finite ? ST_EIGH : ST_NONFINITE);
+}
+
+// ---------------------------------------------------------------------------
+// real symmetric, matrix and vectors in LDS (n <= EIGH_LDS_MAX), 1024 threads.
+// Same rounds as jacobi_real; the per-round index maps are advanced
+// incrementally (no integer division) and the pairing wraps without modulo.
+// ---------------------------------------------------------------------------
+constexpr int JL_NT = 1024;
+
+__device__ __forceinline__ void rr_pair_fast(int r, int j, int m, int nn, int& p, int& q) {
+  // m = nn - 1 players on the circle, player nn - 1 fixed
+  if (j == 0) {
+    p = r;
+    q = nn - 1;
+  } else {
+    p = r + j;
+    if (p >= m) p -= m;
+    q = r - j;
+    if (q < 0) q += m;
+  }
+}
+
+__global__ __launch_bounds__(JL_NT) void jacobi_real_lds(const EighProb* __restrict__ probs, int* status) {
+  extern __shared__ double smem[];
+  __shared__ double red[JL_NT / 64];
+  const EighProb pr = probs[blockIdx.x];
+  const int n = pr.n;
+  if (n <= 0) return;
+  const int nn = n + (n & 1), half = nn / 2, m = nn - 1;
+  double* pc = smem;
+  double* ps = pc + half;
+  int* pp = reinterpret_cast<int*>(ps + half);
+  int* pq = pp + half;
+  double* A = reinterpret_cast<double*>(pq + half);
+  double* V = A + n * n;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += JL_NT) {
+    const int i = e / n, k = e - i * n;
+    // symmetric part: products formed in reduced precision need not be exactly symmetric
+    A[e] = 0.5 * (pr.A[e] + pr.A[k * n + i]);
+    V[e] = (i == k) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double fro = 0.0;
+  for (int e = tid; e < n * n; e += JL_NT) fro += A[e] * A[e];
+  const double scale = sqrt(block_sum<JL_NT>(fro, red));
+  const bool finite = isfinite(scale);
+  bool converged = !finite || n == 1 || scale == 0.0;
+  // starting points and strides of this thread in the (ja, jb) block space and
+  // the (row, pair) space of V; one division each, done once
+  const int nblk = half * half, nvp = n * half;
+  const int bstep_a = JL_NT / half, bstep_b = JL_NT - bstep_a * half;
+  const int ja0 = tid / half, jb0 = tid - ja0 * half;
+  for (int sweep = 0; sweep < MAX_SWEEPS && !converged; ++sweep) {
+    double maxoff = 0.0;
+    for (int r = 0; r < m; ++r) {
+      if (tid < half) {
+        int p, q;
+        rr_pair_fast(r, tid, m, nn, p, q);
+        double c = 1.0, sn = 0.0;
+        if (q < n) {
+          const double apq = A[p * n + q];
+          maxoff = fmax(maxoff, fabs(apq));
+          if (apq != 0.0) {
+            jacobi_cs(A[p * n + p], A[q * n + q], fabs(apq), c, sn);
+            if (apq < 0.0) sn = -sn;
+          }
+        }
+        pp[tid] = p;
+        pq[tid] = q;
+        pc[tid] = c;
+        ps[tid] = sn;
+      }
+      __syncthreads();
+      // A <- J^T A J, one 2 x 2 block per (ja, jb)
+      for (int b = tid, ja = ja0, jb = jb0; b < nblk; b += JL_NT) {
+        const int pa = pp[ja], qa = pq[ja], pb = pp[jb], qb = pq[jb];
+        const double ca = pc[ja], sa = ps[ja], cb = pc[jb], sb = ps[jb];
+        const bool va = qa < n, vb = qb < n;
+        const double x00 = A[pa * n + pb];
+        const double x01 = vb ? A[pa * n + qb] : 0.0;
+        const double x10 = va ? A[qa * n + pb] : 0.0;
+        const double x11 = (va && vb) ? A[qa * n + qb] : 0.0;
+        const double y00 = x00 * cb - x01 * sb, y01 = x00 * sb + x01 * cb;
+        const double y10 = x10 * cb - x11 * sb, y11 = x10 * sb + x11 * cb;
+        double z00 = ca * y00 - sa * y10, z01 = ca * y01 - sa * y11;
+        double z10 = sa * y00 + ca * y10, z11 = sa * y01 + ca * y11;
+        if (ja == jb) z01 = z10 = 0.0;
+        A[pa * n + pb] = z00;
+        if (vb) A[pa * n + qb] = z01;
+        if (va) A[qa * n + pb] = z10;
+        if (va && vb) A[qa * n + qb] = z11;
+        ja += bstep_a;
+        jb += bstep_b;
+        if (jb >= half) {
+          jb -= half;
+          ++ja;
+        }
+      }
+      // V <- V J, one row pair per (row, pair)
+      for (int e = tid, i = ja0, j = jb0; e < nvp; e += JL_NT) {
+        const int p = pp[j], q = pq[j];
+        if (q < n) {
+          const double c = pc[j], sn = ps[j];
+          const double vp = V[i * n + p], vq = V[i * n + q];
+          V[i * n + p] = vp * c - vq * sn;
+          V[i * n + q] = vp * sn + vq * c;
+        }
+        i += bstep_a;
+        j += bstep_b;
+        if (j >= half) {
+          j -= half;
+          ++i;
+        }
+      }
+      __syncthreads();
+    }
+    converged = block_max<JL_NT>(maxoff, red) <= CONV_TOL * scale;
+  }
+  for (int i = tid; i < n; i += JL_NT) pr.w[i] = A[i * n + i];
+  for (int e = tid; e < n * n; e += JL_NT) pr.V[e] = V[e];
+  if ((!converged || !finite) && tid == 0) atomicOr(status, finite ? ST_EIGH : ST_NONFINITE);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,11 +419,11 @@ void launch_eigh_real(const EighProb* d_probs, int nprob, bool lds, int nmax, in
     size_t bytes = eigh_lds_bytes(EIGH_LDS_MAX);
     static bool attr = false;
     if (!attr) {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_real<512, true>),
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_real_lds),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
       attr = true;
     }
-    jacobi_real<512, true><<<nprob, 512, bytes, s>>>(d_probs, d_status);
+    jacobi_real_lds<<<nprob, JL_NT, bytes, s>>>(d_probs, d_status);
   } else {
     // rotation parameters for the largest matrix of the batch (n <= 4096: at most 48 KB)
     size_t bytes = real_params_bytes(nmax);

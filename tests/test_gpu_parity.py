@@ -173,3 +173,35 @@ def test_status_and_argument_errors():
     with pytest.raises(EtdmError):
         h.sync_status()
     h.close()
+
+
+@pytest.mark.parametrize("precision,tol_e,tol_g", [("fp64", 1e-12, 1e-10), ("bf16x6", 2e-7, 1e-6)])
+def test_config3_block_sparse_water_box(precision, tol_e, tol_g):
+    """Config 3 (M = 1472, N = 256, block-sparse H0 passed as BSR) at full size."""
+    wl = make_config(3)
+    params = O.parity_params(wl)
+    print(f"[case] config3 {precision}", flush=True)
+    h, _ = make_handle(wl, precision, use_bsr=True)
+    E, g = energy_grad(h, wl, params)
+    inst = wl.instances[0]
+    E_ref, g_ref = O.energy_grad_ov(inst, params[0], wl.hubbard_U)
+    dE = abs(E[0] - E_ref) / inst.f.sum()
+    dg = np.linalg.norm(g[0] - g_ref) / np.linalg.norm(g_ref)
+    print(f"[result] config3 {precision}: |dE|/Ne = {dE:.3e}, rel |dg| = {dg:.3e}")
+    assert dE < tol_e and dg < tol_g
+    h.close()
+
+
+def test_config4_all_kpoints():
+    """Config 4 at full size: 64 k-points, M = 208, complex, coupled Hubbard density."""
+    wl = make_config(4)
+    params = O.parity_params(wl)
+    print("[case] config4 64 k-points fp64", flush=True)
+    h, _ = make_handle(wl, "fp64")
+    E, G = energy_grad(h, wl, params)
+    E_ref, G_ref = O.energy_grad(wl, params)
+    dE = abs(E[-1] - E_ref) / wl.n_electrons
+    dg = rel_err(G, G_ref)
+    print(f"[result] config4: |dE|/Ne = {dE:.3e}, rel |dg| = {dg:.3e}")
+    assert dE < 1e-13 and dg < 1e-10
+    h.close()
