@@ -216,11 +216,11 @@ __global__ __launch_bounds__(JL_NT) void jacobi_real_lds(const EighProb* __restr
   const double scale = sqrt(block_sum<JL_NT>(fro, red));
   const bool finite = isfinite(scale);
   bool converged = !finite || n == 1 || scale == 0.0;
-  // starting points and strides of this thread in the (ja, jb) block space and
-  // the (row, pair) space of V; one division each, done once
-  const int nblk = half * half, nvp = n * half;
-  const int bstep_a = JL_NT / half, bstep_b = JL_NT - bstep_a * half;
-  const int ja0 = tid / half, jb0 = tid - ja0 * half;
+  // Thread t < nact keeps one column pair jb = t % half for the whole round (its
+  // rotation is read once) and walks the row pairs ja = t / half + k * stride;
+  // the same thread walks rows i of V for pair jb.  One division, done once.
+  const int stride = JL_NT / half, nact = stride * half;
+  const int jb = tid % half, ja0 = tid / half;
   for (int sweep = 0; sweep < MAX_SWEEPS && !converged; ++sweep) {
     double maxoff = 0.0;
     for (int r = 0; r < m; ++r) {
@@ -236,52 +236,42 @@ __global__ __launch_bounds__(JL_NT) void jacobi_real_lds(const EighProb* __restr
             if (apq < 0.0) sn = -sn;
           }
         }
-        pp[tid] = p;
-        pq[tid] = q;
         pc[tid] = c;
         ps[tid] = sn;
       }
       __syncthreads();
-      // A <- J^T A J, one 2 x 2 block per (ja, jb)
-      for (int b = tid, ja = ja0, jb = jb0; b < nblk; b += JL_NT) {
-        const int pa = pp[ja], qa = pq[ja], pb = pp[jb], qb = pq[jb];
-        const double ca = pc[ja], sa = ps[ja], cb = pc[jb], sb = ps[jb];
-        const bool va = qa < n, vb = qb < n;
-        const double x00 = A[pa * n + pb];
-        const double x01 = vb ? A[pa * n + qb] : 0.0;
-        const double x10 = va ? A[qa * n + pb] : 0.0;
-        const double x11 = (va && vb) ? A[qa * n + qb] : 0.0;
-        const double y00 = x00 * cb - x01 * sb, y01 = x00 * sb + x01 * cb;
-        const double y10 = x10 * cb - x11 * sb, y11 = x10 * sb + x11 * cb;
-        double z00 = ca * y00 - sa * y10, z01 = ca * y01 - sa * y11;
-        double z10 = sa * y00 + ca * y10, z11 = sa * y01 + ca * y11;
-        if (ja == jb) z01 = z10 = 0.0;
-        A[pa * n + pb] = z00;
-        if (vb) A[pa * n + qb] = z01;
-        if (va) A[qa * n + pb] = z10;
-        if (va && vb) A[qa * n + qb] = z11;
-        ja += bstep_a;
-        jb += bstep_b;
-        if (jb >= half) {
-          jb -= half;
-          ++ja;
+      if (tid < nact) {
+        int pb, qb;
+        rr_pair_fast(r, jb, m, nn, pb, qb);
+        const double cb = pc[jb], sb = ps[jb];
+        const bool vb = qb < n;
+        // A <- J^T A J, one 2 x 2 block per (ja, jb)
+        for (int ja = ja0; ja < half; ja += stride) {
+          int pa, qa;
+          rr_pair_fast(r, ja, m, nn, pa, qa);
+          const double ca = pc[ja], sa = ps[ja];
+          const bool va = qa < n;
+          const double x00 = A[pa * n + pb];
+          const double x01 = vb ? A[pa * n + qb] : 0.0;
+          const double x10 = va ? A[qa * n + pb] : 0.0;
+          const double x11 = (va && vb) ? A[qa * n + qb] : 0.0;
+          const double y00 = x00 * cb - x01 * sb, y01 = x00 * sb + x01 * cb;
+          const double y10 = x10 * cb - x11 * sb, y11 = x10 * sb + x11 * cb;
+          double z00 = ca * y00 - sa * y10, z01 = ca * y01 - sa * y11;
+          double z10 = sa * y00 + ca * y10, z11 = sa * y01 + ca * y11;
+          if (ja == jb) z01 = z10 = 0.0;
+          A[pa * n + pb] = z00;
+          if (vb) A[pa * n + qb] = z01;
+          if (va) A[qa * n + pb] = z10;
+          if (va && vb) A[qa * n + qb] = z11;
         }
-      }
-      // V <- V J, one row pair per (row, pair)
-      for (int e = tid, i = ja0, j = jb0; e < nvp; e += JL_NT) {
-        const int p = pp[j], q = pq[j];
-        if (q < n) {
-          const double c = pc[j], sn = ps[j];
-          const double vp = V[i * n + p], vq = V[i * n + q];
-          V[i * n + p] = vp * c - vq * sn;
-          V[i * n + q] = vp * sn + vq * c;
-        }
-        i += bstep_a;
-        j += bstep_b;
-        if (j >= half) {
-          j -= half;
-          ++i;
-        }
+        // V <- V J for rows i of this thread and pair jb
+        if (vb)
+          for (int i = ja0; i < n; i += stride) {
+            const double vp = V[i * n + pb], vq = V[i * n + qb];
+            V[i * n + pb] = vp * cb - vq * sb;
+            V[i * n + qb] = vp * sb + vq * cb;
+          }
       }
       __syncthreads();
     }

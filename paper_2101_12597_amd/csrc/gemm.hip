@@ -19,6 +19,8 @@
 //     row 4 * (l / 16) + r, column l % 16;
 //   accumulator element r of lane l, FP64 16x16x4:
 //     row l / 16 + 4 * r, column l % 16.
+#include <type_traits>
+
 #include "common.h"
 
 namespace etdm {
@@ -100,13 +102,39 @@ __device__ __forceinline__ void store_tile(const GemmProb& p, int row0, int col0
 }
 
 // ---------------------------------------------------------------------------
-// FP64 / FP32 kernel (16x16x4 MFMA, BK = 16)
+// FP64 / FP32 kernel (16x16x4 MFMA, BK = 32)
+//
+// The next k-tile is fetched into registers while the MFMAs consume the current
+// one from LDS.  LDS layouts follow the contiguous direction of each operand in
+// memory so that the staging stores are conflict free:
+//   op(A) = A   : A_s[m][k], row length BK + 1     op(A) = A^T : A_s[k][m], row length BM + 16
+//   op(B) = B   : B_s[k][n], row length BN + 16    op(B) = B^T : B_s[n][k], row length BK + 1
 // ---------------------------------------------------------------------------
+constexpr int K4_BK = 32;
+constexpr int K4_PER = GEMM_BM * K4_BK / NTHREADS;  // staged elements per thread and operand
+constexpr int K4_LDS = (K4_BK * (GEMM_BM + 16) > GEMM_BM * (K4_BK + 1)) ? K4_BK * (GEMM_BM + 16)
+                                                                          : GEMM_BM * (K4_BK + 1);
+
+template <bool TA>
+__device__ __forceinline__ int a_lds(int kk, int mm) {
+  return TA ? kk * (GEMM_BM + 16) + mm : mm * (K4_BK + 1) + kk;
+}
+template <bool TB>
+__device__ __forceinline__ int b_lds(int kk, int nn) {
+  return TB ? nn * (K4_BK + 1) + kk : kk * (GEMM_BN + 16) + nn;
+}
+// element e of a 64 x 32 staging pass -> (kk, mm), following the memory-contiguous direction
+template <bool T>
+__device__ __forceinline__ void stage_coord(int e, int& kk, int& mm) {
+  if (T) { kk = e / GEMM_BM; mm = e % GEMM_BM; }
+  else { mm = e / K4_BK; kk = e % K4_BK; }
+}
+
 template <typename T, bool TA, bool TB>
 __global__ __launch_bounds__(NTHREADS) void gemm_k4(const GemmProb* __restrict__ probs, int nprob) {
-  constexpr int BK = 16;
-  __shared__ T As[BK][BM + 1];
-  __shared__ T Bs[BK][BN + 1];
+  constexpr int BK = K4_BK;
+  __shared__ T As[K4_LDS];
+  __shared__ T Bs[K4_LDS];
   const GemmProb& p = probs[find_problem(probs, nprob, blockIdx.x)];
   const int t = blockIdx.x - p.tile_begin;
   const int row0 = (t / p.tiles_n) * BM, col0 = (t % p.tiles_n) * BN;
@@ -126,61 +154,70 @@ __global__ __launch_bounds__(NTHREADS) void gemm_k4(const GemmProb* __restrict__
     const int K = seg ? p.k2 : p.k;
     const double alpha = seg ? p.alpha2 : p.alpha;
     if (K <= 0) continue;
-    if constexpr (sizeof(T) == 8) {
-      d4 c[2][2];
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) c[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < K; k0 += BK) {
-        stage_a<TA, BK>(A, lda, row0, k0, p.m, K, [&](int kk, int mm, double v) { As[kk][mm] = alpha * v; });
-        stage_b<TB, BK>(B, ldb, k0, col0, K, p.n, [&](int kk, int nn, double v) { Bs[kk][nn] = v; });
-        __syncthreads();
+    double ra[K4_PER], rb[K4_PER];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int ks = 0; ks < BK; ks += 4) {
-          double a0 = As[ks + lk][wm + lr], a1 = As[ks + lk][wm + 16 + lr];
-          double b0 = Bs[ks + lk][wn + lr], b1 = Bs[ks + lk][wn + 16 + lr];
+      for (int i = 0; i < K4_PER; ++i) {
+        int kk, mm;
+        stage_coord<TA>(threadIdx.x + i * NTHREADS, kk, mm);
+        ra[i] = ld_op<TA>(A, lda, row0 + mm, k0 + kk, p.m, K);
+        int kb, nn;
+        stage_coord<TB>(threadIdx.x + i * NTHREADS, kb, nn);
+        rb[i] = ld_op<TB>(B, ldb, k0 + kb, col0 + nn, K, p.n);
+      }
+    };
+    auto commit = [&]() {
+#pragma unroll
+      for (int i = 0; i < K4_PER; ++i) {
+        int kk, mm;
+        stage_coord<TA>(threadIdx.x + i * NTHREADS, kk, mm);
+        As[a_lds<TA>(kk, mm)] = (T)(alpha * ra[i]);
+        int kb, nn;
+        stage_coord<TB>(threadIdx.x + i * NTHREADS, kb, nn);
+        Bs[b_lds<TB>(kb, nn)] = (T)rb[i];
+      }
+    };
+    using V4 = typename std::conditional<sizeof(T) == 8, d4, f4>::type;
+    V4 c[2][2];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) c[i][j] = V4{0, 0, 0, 0};
+    int since_flush = 0;
+    auto flush = [&]() {
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)c[i][j][r];
+          c[i][j] = V4{0, 0, 0, 0};
+        }
+      since_flush = 0;
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+      commit();
+      __syncthreads();
+      if (k0 + BK < K) fetch(k0 + BK);
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 4) {
+        const T a0 = As[a_lds<TA>(ks + lk, wm + lr)], a1 = As[a_lds<TA>(ks + lk, wm + 16 + lr)];
+        const T b0 = Bs[b_lds<TB>(ks + lk, wn + lr)], b1 = Bs[b_lds<TB>(ks + lk, wn + 16 + lr)];
+        if constexpr (sizeof(T) == 8) {
           c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c[0][0], 0, 0, 0);
           c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, c[0][1], 0, 0, 0);
           c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, c[1][0], 0, 0, 0);
           c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c[1][1], 0, 0, 0);
-        }
-        __syncthreads();
-      }
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
-          for (int r = 0; r < 4; ++r) acc[i][j][r] += c[i][j][r];
-    } else {
-      f4 c[2][2];
-      int since_flush = 0;
-      auto flush = [&]() {
-        for (int i = 0; i < 2; ++i)
-          for (int j = 0; j < 2; ++j) {
-            for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)c[i][j][r];
-            c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-          }
-        since_flush = 0;
-      };
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-      for (int k0 = 0; k0 < K; k0 += BK) {
-        stage_a<TA, BK>(A, lda, row0, k0, p.m, K,
-                        [&](int kk, int mm, double v) { As[kk][mm] = (float)(alpha * v); });
-        stage_b<TB, BK>(B, ldb, k0, col0, K, p.n, [&](int kk, int nn, double v) { Bs[kk][nn] = (float)v; });
-        __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < BK; ks += 4) {
-          float a0 = As[ks + lk][wm + lr], a1 = As[ks + lk][wm + 16 + lr];
-          float b0 = Bs[ks + lk][wn + lr], b1 = Bs[ks + lk][wn + 16 + lr];
+        } else {
           c[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, c[0][0], 0, 0, 0);
           c[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, c[0][1], 0, 0, 0);
           c[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, c[1][0], 0, 0, 0);
           c[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, c[1][1], 0, 0, 0);
         }
-        __syncthreads();
+      }
+      __syncthreads();
+      if constexpr (sizeof(T) == 4) {
         since_flush += BK;
         if (since_flush >= FLUSH_K) flush();
       }
-      flush();
     }
+    flush();
   }
   store_tile<sizeof(T) == 8>(p, row0, col0, wm, wn, acc);
 }
