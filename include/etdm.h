@@ -77,7 +77,10 @@ typedef enum {
   ETDM_FP64 = 0,   /* FP64 MFMA */
   ETDM_FP32 = 1,   /* operands rounded to FP32, FP32 MFMA, FP64 flush every K chunk */
   ETDM_BF16X3 = 2, /* 2-way BF16 split (hi+lo), 3 products, FP32 MFMA accumulation */
-  ETDM_BF16X6 = 3  /* 3-way BF16 split (hi+mid+lo), 6 products */
+  ETDM_BF16X6 = 3, /* 3-way BF16 split (hi+mid+lo), 6 products */
+  ETDM_MIXED = 4   /* by role: the contractions that E depends on (P, C0_v B^T, C_occ,
+                      H0 C_occ) in FP64, the gradient-only ones (Z1, C_virt, L_ov,
+                      L_ov B^T, G) as ETDM_BF16X6 */
 } etdm_precision;
 
 typedef struct {
@@ -161,6 +164,13 @@ etdm_status etdm_sync_status(etdm_handle *h, void *stream);
 const char *etdm_status_string(etdm_status s);
 /* Human-readable detail of the last error on this handle ("" if none). */
 const char *etdm_last_error(const etdm_handle *h);
+
+/* Replay the launch sequence of etdm_energy_grad from a HIP graph (enable = 1)
+ * or launch it kernel by kernel (0, the default).  The graph is captured on
+ * the first call after enabling (on an internal stream) and launched on the
+ * caller's stream; it holds only handle-owned buffers, so A, E and G may
+ * change between calls.  While stage timing is on, calls run eagerly. */
+etdm_status etdm_set_graph(etdm_handle *h, int32_t enable);
 
 /* Tracing: per-stage HIP-event timing of the launch sequences.  A "stage" is
  * one launch (or grouped launch) of the path: a GEMM group, the eigensolver,

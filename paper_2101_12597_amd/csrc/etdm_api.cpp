@@ -140,12 +140,12 @@ struct StageTimer {
 };
 
 // stage indices of the two paths
-enum OvStage { O_PQ, O_EIGL, O_EIGG, O_SPEC, O_F3MU, O_CZ, O_VT, O_ROWS, O_ENERGY, O_LOV, O_R, O_GAM1, O_GAM,
-               O_PAIR, O_Y1, O_Y2, O_G, O_SCAN, O_COUNT };
-const char* kOvNames[O_COUNT] = {"gemm_P_Q1",  "eigh_lds",    "eigh_global", "spectral_tables", "gemm_funcs_mu",
-                                 "gemm_Cocc_Z1", "gemm_Cvirt_H0C", "rows_density_hubbard", "energy_reduce",
-                                 "gemm_Lov",   "gemm_R",      "gemm_Gam1",   "gemm_Gam",        "pair_hadamard",
-                                 "gemm_Y1",    "gemm_Y2",     "gemm_grad",   "nonfinite_scan"};
+enum OvStage { O_PQ, O_EIGL, O_EIGG, O_SPEC, O_F3MU, O_C, O_Z, O_T, O_V, O_ROWS, O_ENERGY, O_LOV, O_R, O_GAM1,
+               O_GAM, O_PAIR, O_Y1, O_Y2, O_G, O_SCAN, O_COUNT };
+const char* kOvNames[O_COUNT] = {"gemm_P_Q1",  "eigh_lds",  "eigh_global", "spectral_tables", "gemm_funcs_mu",
+                                 "gemm_Cocc",  "gemm_Z1",   "gemm_H0C",    "gemm_Cvirt",      "rows_density_hubbard",
+                                 "energy_reduce", "gemm_Lov", "gemm_R",    "gemm_Gam1",       "gemm_Gam",
+                                 "pair_hadamard", "gemm_Y1", "gemm_Y2",    "gemm_grad",       "nonfinite_scan"};
 enum ZStage { Z_IA, Z_EIG, Z_PHASE, Z_UE, Z_C, Z_T, Z_ROWS, Z_HUBN, Z_APPLY, Z_ENERGY, Z_HMO, Z_COMM, Z_LV, Z_LT,
               Z_DD, Z_W1, Z_Y, Z_GRAD, Z_COUNT };
 const char* kZNames[Z_COUNT] = {"z_build_iA", "z_eigh",   "z_phase",  "zgemm_expA", "zgemm_C",   "zgemm_H0C",
@@ -182,7 +182,7 @@ struct etdm_handle {
   const double** d_n0ptr = nullptr;
   double* d_wts = nullptr;
   // grouped GEMM launches
-  Stage s_PQ, s_F3mu, s_CZ, s_VT, s_Lov, s_R, s_Gam1, s_Gam, s_Y1, s_Y2, s_G;  // real: energy+gradient
+  Stage s_PQ, s_F3mu, s_C, s_Z, s_T, s_V, s_Lov, s_R, s_Gam1, s_Gam, s_Y1, s_Y2, s_G;  // real: energy+gradient
   Stage s_Uov, s_Uvv, s_HC0;                                                   // real: expm, preconditioner
   Stage z_Ue, z_C, z_T, z_HMO, z_LV, z_Lt, z_W1, z_Y, z_HC0;                   // complex
   // L-BFGS state
@@ -191,6 +191,11 @@ struct etdm_handle {
   double lb_E = 0.0, lb_beta = 1.0;
   double *x = nullptr, *g = nullptr, *p = nullptr, *q = nullptr, *xt = nullptr, *gt = nullptr;
   double *hd = nullptr, *wv = nullptr, *S = nullptr, *Yv = nullptr, *partial = nullptr, *sc = nullptr;
+  // graph replay of the energy+gradient sequence
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   // tracing
   std::vector<StageTimer> timers;
   int64_t tmask = 0;
@@ -399,21 +404,25 @@ etdm_status upload_stage(etdm_handle* h, Stage& s) { return upload(h, &s.d, s.pr
 
 // ----- plan of the real occupied-virtual path ------------------------------
 etdm_status build_ov_plan(etdm_handle* h) {
-  const int bulk = h->prec;
-  h->s_PQ.init(OP_N, OP_T, bulk);
+  // precision by role: ep for the contractions E depends on, gp for the gradient-only ones
+  const int ep = h->prec == ETDM_MIXED ? GP_FP64 : h->prec;
+  const int gp = h->prec == ETDM_MIXED ? GP_BF16X6 : h->prec;
+  h->s_PQ.init(OP_N, OP_T, ep);
   h->s_F3mu.init(OP_N, OP_T, GP_FP64);
-  h->s_CZ.init(OP_N, OP_N, bulk);
-  h->s_VT.init(OP_N, OP_N, bulk);
-  h->s_Lov.init(OP_T, OP_N, bulk);
-  h->s_R.init(OP_N, OP_T, bulk);
+  h->s_C.init(OP_N, OP_N, ep);
+  h->s_Z.init(OP_N, OP_N, gp);
+  h->s_T.init(OP_N, OP_N, ep);
+  h->s_V.init(OP_N, OP_N, gp);
+  h->s_Lov.init(OP_T, OP_N, gp);
+  h->s_R.init(OP_N, OP_T, gp);
   h->s_Gam1.init(OP_T, OP_N, GP_FP64);
   h->s_Gam.init(OP_N, OP_N, GP_FP64);
   h->s_Y1.init(OP_N, OP_N, GP_FP64);
   h->s_Y2.init(OP_N, OP_T, GP_FP64);
-  h->s_G.init(OP_N, OP_N, bulk);
-  h->s_Uov.init(OP_N, OP_N, bulk);
-  h->s_Uvv.init(OP_T, OP_N, bulk);
-  h->s_HC0.init(OP_N, OP_N, bulk);
+  h->s_G.init(OP_N, OP_N, gp);
+  h->s_Uov.init(OP_N, OP_N, ep);
+  h->s_Uvv.init(OP_T, OP_N, ep);
+  h->s_HC0.init(OP_N, OP_N, ep);
   std::vector<OvSpec> spec;
   std::vector<OvRows> rows;
   std::vector<OvEnergy> en;
@@ -440,11 +449,11 @@ etdm_status build_ov_plan(etdm_handle* h) {
     h->s_F3mu.add(prob(N, N, OV_NQ, b.T1s, OV_NQ, b.T2, OV_NQ, b.mu1, N));
     h->s_F3mu.add(prob(N, N, OV_NQ, b.T3s, OV_NQ, b.T3, OV_NQ, b.mu2, N));
     // C_occ = C0_o cos - Q1 sinc, Z1 = C0_o sinc + Q1 W
-    h->s_CZ.add(with_second(prob(M, N, N, b.C0, M, Fc, N, b.Cocc, N), N, b.Q1, N, Fs, N, -1.0));
-    h->s_CZ.add(with_second(prob(M, N, N, b.C0, M, Fs, N, b.Z1, N), N, b.Q1, N, Wm, N, 1.0));
+    h->s_C.add(with_second(prob(M, N, N, b.C0, M, Fc, N, b.Cocc, N), N, b.Q1, N, Fs, N, -1.0));
+    h->s_Z.add(with_second(prob(M, N, N, b.C0, M, Fs, N, b.Z1, N), N, b.Q1, N, Wm, N, 1.0));
     // C_virt = C0_v + Z1 B, T0 = H0 C_occ
-    h->s_VT.add(with_addend(prob(M, Nv, N, b.Z1, N, b.B, Nv, b.Cvirt, Nv), b.C0 + N, M, 1.0));
-    h->s_VT.add(prob(M, N, M, b.H0, M, b.Cocc, N, b.T, N));
+    h->s_V.add(with_addend(prob(M, Nv, N, b.Z1, N, b.B, Nv, b.Cvirt, Nv), b.C0 + N, M, 1.0));
+    h->s_T.add(prob(M, N, M, b.H0, M, b.Cocc, N, b.T, N));
     rows.push_back(OvRows{b.Cocc, b.T, b.d, b.e, M, N, h->focc[i]});
     brows.push_back(h->tot_rows);
     h->tot_rows += M;
@@ -480,8 +489,10 @@ etdm_status build_ov_plan(etdm_handle* h) {
     const Stage* gs[O_COUNT] = {};
     gs[O_PQ] = &h->s_PQ;
     gs[O_F3MU] = &h->s_F3mu;
-    gs[O_CZ] = &h->s_CZ;
-    gs[O_VT] = &h->s_VT;
+    gs[O_C] = &h->s_C;
+    gs[O_Z] = &h->s_Z;
+    gs[O_T] = &h->s_T;
+    gs[O_V] = &h->s_V;
     gs[O_LOV] = &h->s_Lov;
     gs[O_R] = &h->s_R;
     gs[O_GAM1] = &h->s_Gam1;
@@ -513,8 +524,9 @@ etdm_status build_ov_plan(etdm_handle* h) {
     }
     h->timers[O_SCAN].bytes = 8.0 * h->n_param;
   }
-  Stage* stages[] = {&h->s_PQ, &h->s_F3mu, &h->s_CZ, &h->s_VT, &h->s_Lov, &h->s_R,   &h->s_Gam1,
-                     &h->s_Gam, &h->s_Y1,  &h->s_Y2, &h->s_G,  &h->s_Uov, &h->s_Uvv, &h->s_HC0};
+  Stage* stages[] = {&h->s_PQ,  &h->s_F3mu, &h->s_C,  &h->s_Z,   &h->s_T,   &h->s_V,   &h->s_Lov,
+                     &h->s_R,   &h->s_Gam1, &h->s_Gam, &h->s_Y1, &h->s_Y2, &h->s_G,  &h->s_Uov,
+                     &h->s_Uvv, &h->s_HC0};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
   CHECK(upload(h, &h->d_spec, spec));
   CHECK(upload(h, &h->b_spec, bspec));
@@ -634,8 +646,17 @@ void free_timers(etdm_handle* h) {
   }
 }
 
+void free_graph(etdm_handle* h) {
+  if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) hipGraphDestroy(h->graph);
+  h->graph_exec = nullptr;
+  h->graph = nullptr;
+}
+
 void free_handle(etdm_handle* h) {
   if (!h) return;
+  free_graph(h);
+  if (h->cap_stream) hipStreamDestroy(h->cap_stream);
   free_timers(h);
   if (h->base) hipFree(h->base);
   for (void* p : h->dev_allocs) hipFree(p);
@@ -656,8 +677,10 @@ void ov_exponential_part(etdm_handle* h, hipStream_t s) {
 
 void ov_energy_grad(etdm_handle* h, hipStream_t s) {
   ov_exponential_part(h, s);
-  { TIMED(O_CZ); h->s_CZ.launch(s); }
-  { TIMED(O_VT); h->s_VT.launch(s); }
+  { TIMED(O_C); h->s_C.launch(s); }
+  { TIMED(O_Z); h->s_Z.launch(s); }
+  { TIMED(O_T); h->s_T.launch(s); }
+  { TIMED(O_V); h->s_V.launch(s); }
   { TIMED(O_ROWS); launch_ov_rows(h->d_rows, h->b_rows, h->n_inst, h->tot_rows, h->U, s); }
   {
     TIMED(O_ENERGY);
@@ -689,8 +712,9 @@ void ov_expm(etdm_handle* h, hipStream_t s) {
 
 void ov_new_reference(etdm_handle* h, hipStream_t s) {
   ov_exponential_part(h, s);
-  h->s_CZ.launch(s);
-  h->s_VT.launch(s);
+  h->s_C.launch(s);
+  h->s_Z.launch(s);
+  h->s_V.launch(s);
   for (int i = 0; i < h->n_inst; ++i) {
     const OvBuf& b = h->ov[i];
     const int M = h->M[i], N = h->N[i];
@@ -732,9 +756,27 @@ void z_energy_grad(etdm_handle* h, hipStream_t s) {
   { TIMED(Z_GRAD); launch_z_grad(h->d_z, h->b_mat, h->n_inst, h->tot_mat, h->status, s); }
 }
 
-void run_energy_grad(etdm_handle* h, hipStream_t s) {
+void run_energy_grad_eager(etdm_handle* h, hipStream_t s) {
   if (h->kind == ETDM_REAL_OV) ov_energy_grad(h, s);
   else z_energy_grad(h, s);
+}
+
+// Energy+gradient launch sequence, from the captured graph when enabled.
+etdm_status run_energy_grad(etdm_handle* h, hipStream_t s) {
+  if (!h->use_graph || h->tmask != 0) {
+    run_energy_grad_eager(h, s);
+    return ETDM_OK;
+  }
+  if (!h->graph_exec) {
+    HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    run_energy_grad_eager(h, h->cap_stream);
+    hipGraph_t g = nullptr;
+    HIPCHK(h, hipStreamEndCapture(h->cap_stream, &g));
+    h->graph = g;
+    HIPCHK(h, hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+  }
+  HIPCHK(h, hipGraphLaunch(h->graph_exec, s));
+  return ETDM_OK;
 }
 
 // Read and clear the device status word.
@@ -799,7 +841,7 @@ etdm_status lb_eval(etdm_handle* h, const double* xin, double* gout, double& E, 
                     double* gg = nullptr) {
   const size_t pb = (size_t)h->n_param * sizeof(double);
   if (pb) HIPCHK(h, hipMemcpyAsync(h->par_ws, xin, pb, hipMemcpyDeviceToDevice, s));
-  run_energy_grad(h, s);
+  CHECK(run_energy_grad(h, s));
   if (pb) HIPCHK(h, hipMemcpyAsync(gout, h->grad_ws, pb, hipMemcpyDeviceToDevice, s));
   launch_dot(gout, h->p, h->n_param, h->partial, h->sc + SC_DPHI, s);
   if (gg) launch_dot(gout, gout, h->n_param, h->partial, h->sc + SC_GG, s);
@@ -1013,7 +1055,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (!d || !H0 || !C0 || !f) return ETDM_E_ARG;
   if (d->n_inst < 1 || !d->M) return ETDM_E_ARG;
   if (d->kind != ETDM_REAL_OV && d->kind != ETDM_COMPLEX_FULL) return ETDM_E_ARG;
-  if (d->precision < ETDM_FP64 || d->precision > ETDM_BF16X6) return ETDM_E_ARG;
+  if (d->precision < ETDM_FP64 || d->precision > ETDM_MIXED) return ETDM_E_ARG;
   if (d->kind == ETDM_COMPLEX_FULL && d->precision != ETDM_FP64) return ETDM_E_ARG;
   if (d->kind == ETDM_REAL_OV && (!d->N || d->couple)) return ETDM_E_ARG;
   if (d->h0_format != 0 && d->h0_format != 1) return ETDM_E_ARG;
@@ -1152,7 +1194,7 @@ etdm_status etdm_energy_grad(etdm_handle* h, const void* A, double* E, void* G, 
   hipStream_t s = S(stream);
   const size_t pb = (size_t)h->n_param * sizeof(double);
   if (pb) HIPCHK(h, hipMemcpyAsync(h->par_ws, A, pb, hipMemcpyDeviceToDevice, s));
-  run_energy_grad(h, s);
+  CHECK(run_energy_grad(h, s));
   if (pb) HIPCHK(h, hipMemcpyAsync(G, h->grad_ws, pb, hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipMemcpyAsync(E, h->E_ws, (h->n_inst + 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipGetLastError());
@@ -1196,6 +1238,14 @@ etdm_status etdm_set_reference(etdm_handle* h, const void* A, void* stream) {
 etdm_status etdm_sync_status(etdm_handle* h, void* stream) {
   if (!h) return ETDM_E_ARG;
   return check_status(h, S(stream));
+}
+
+etdm_status etdm_set_graph(etdm_handle* h, int32_t enable) {
+  if (!h) return ETDM_E_ARG;
+  if (enable && !h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  if (!enable) free_graph(h);
+  h->use_graph = enable != 0;
+  return ETDM_OK;
 }
 
 etdm_status etdm_set_timing(etdm_handle* h, int64_t mask) {

@@ -240,6 +240,16 @@ __device__ __forceinline__ void split_bf16(double v, __bf16 (&out)[NS]) {
   }
 }
 
+// Staging task of one thread for a 64 x 32 tile: one row (or column) and one
+// octet of 8 consecutive k.  The map follows the contiguous direction in memory:
+// consecutive threads take consecutive octets of one row when k is contiguous,
+// and consecutive rows of one octet when the row index is contiguous.
+template <bool KCONTIG>
+__device__ __forceinline__ void octet_task(int t, int& row, int& oct) {
+  if (KCONTIG) { row = t >> 2; oct = t & 3; }
+  else { row = t & 63; oct = t >> 6; }
+}
+
 template <int NS, bool TA, bool TB>
 __global__ __launch_bounds__(NTHREADS) void gemm_bf16split(const GemmProb* __restrict__ probs, int nprob) {
   constexpr int BK = 32;
@@ -253,6 +263,9 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf16split(const GemmProb* __res
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
+  int arow, aoct, bcol, boct;
+  octet_task<!TA>(threadIdx.x, arow, aoct);
+  octet_task<TB>(threadIdx.x, bcol, boct);
 
   double acc[2][2][4];
   for (int i = 0; i < 2; ++i)
@@ -266,6 +279,31 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf16split(const GemmProb* __res
     const int K = seg ? p.k2 : p.k;
     const double alpha = seg ? p.alpha2 : p.alpha;
     if (K <= 0) continue;
+    double ra[8], rb[8];
+    auto fetch = [&](int k0) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        ra[u] = ld_op<TA>(A, lda, row0 + arow, k0 + aoct * 8 + u, p.m, K);
+        rb[u] = ld_op<TB>(B, ldb, k0 + boct * 8 + u, col0 + bcol, K, p.n);
+      }
+    };
+    auto commit = [&]() {
+      bf8 sa[NS], sb[NS];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        __bf16 x[NS], y[NS];
+        split_bf16<NS>(alpha * ra[u], x);
+        split_bf16<NS>(rb[u], y);
+        for (int q = 0; q < NS; ++q) {
+          sa[q][u] = x[q];
+          sb[q][u] = y[q];
+        }
+      }
+      for (int q = 0; q < NS; ++q) {
+        *reinterpret_cast<bf8*>(&As[q][aoct][arow][0]) = sa[q];
+        *reinterpret_cast<bf8*>(&Bs[q][boct][bcol][0]) = sb[q];
+      }
+    };
     f4 c[2][2];
     int since_flush = 0;
     for (int i = 0; i < 2; ++i)
@@ -278,18 +316,11 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf16split(const GemmProb* __res
         }
       since_flush = 0;
     };
+    fetch(0);
     for (int k0 = 0; k0 < K; k0 += BK) {
-      stage_a<TA, BK>(A, lda, row0, k0, p.m, K, [&](int kk, int mm, double v) {
-        __bf16 s[NS];
-        split_bf16<NS>(alpha * v, s);
-        for (int q = 0; q < NS; ++q) As[q][kk >> 3][mm][kk & 7] = s[q];
-      });
-      stage_b<TB, BK>(B, ldb, k0, col0, K, p.n, [&](int kk, int nn, double v) {
-        __bf16 s[NS];
-        split_bf16<NS>(v, s);
-        for (int q = 0; q < NS; ++q) Bs[q][kk >> 3][nn][kk & 7] = s[q];
-      });
+      commit();
       __syncthreads();
+      if (k0 + BK < K) fetch(k0 + BK);
       bf8 a[NS][2], b[NS][2];
       for (int q = 0; q < NS; ++q) {
         a[q][0] = *reinterpret_cast<const bf8*>(&As[q][lk][wm + lr][0]);
@@ -302,7 +333,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf16split(const GemmProb* __res
       for (int sum = NS - 1; sum >= 0; --sum)
 #pragma unroll
         for (int qa = 0; qa < NS; ++qa) {
-          int qb = sum - qa;
+          const int qb = sum - qa;
           if (qb < 0 || qb >= NS) continue;
           for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j)

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libetdm.so")
 
 REAL_OV, COMPLEX_FULL = 0, 1
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "mixed": 4}
 
 STATUS = {
     0: "ok", -1: "invalid argument", -2: "inconsistent shape", -3: "HIP runtime error",
@@ -71,7 +71,7 @@ EXPORTS = [
     "etdm_create", "etdm_destroy", "etdm_expm", "etdm_energy_grad", "etdm_set_reference",
     "etdm_lbfgs_defaults", "etdm_lbfgs_step", "etdm_sync_status", "etdm_status_string",
     "etdm_last_error", "etdm_param_count", "etdm_set_timing", "etdm_reset_timing",
-    "etdm_stage_count", "etdm_stage_info",
+    "etdm_stage_count", "etdm_stage_info", "etdm_set_graph",
 ]
 
 _lib = None
@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.etdm_last_error.restype = ctypes.c_char_p
     L.etdm_param_count.argtypes = [vp]
     L.etdm_param_count.restype = i64
+    L.etdm_set_graph.argtypes = [vp, i32]
+    L.etdm_set_graph.restype = i32
     L.etdm_set_timing.argtypes = [vp, i64]
     L.etdm_set_timing.restype = i32
     L.etdm_reset_timing.argtypes = [vp]
@@ -151,7 +153,7 @@ class Handle:
     ----------
     M, N : per-instance basis sizes and occupied counts (N ignored for complex)
     kind : "real_ov" or "complex_full"
-    precision : "fp64" | "fp32" | "bf16x3" | "bf16x6"
+    precision : "fp64" | "fp32" | "bf16x3" | "bf16x6" | "mixed"
     H0 : device tensor, packed dense matrices (float64 / complex128), or the
          packed BSR blocks when ``bsr`` = (block, row_ptr, col_idx) is given
     C0 : device tensor, packed M x M reference orbitals
@@ -234,6 +236,10 @@ class Handle:
         self._check(st, "etdm_lbfgs_step")
         return dict(iter=info.iter, n_evals=info.n_evals, alpha=info.alpha, E=info.E,
                     gnorm=info.gnorm, flags=info.flags)
+
+    def set_graph(self, enable: bool = True):
+        """Replay the energy+gradient launch sequence from a captured HIP graph."""
+        self._check(self._L.etdm_set_graph(self._h, int(bool(enable))), "etdm_set_graph")
 
     def set_timing(self, mask: int = -1):
         """Record HIP events around the selected stages (bit i = stage i)."""

@@ -109,8 +109,9 @@ def test_real_ov_zero_rotation_and_repeatability():
 # (FP32 MFMA and the 3-way BF16 split) meet the gradient target but their
 # operand rounding (~6e-8 relative) enters E at first order, which on these
 # small molecules exceeds 1e-8 Ha per electron: their bounds record that.
-@pytest.mark.parametrize("precision,tol_e,tol_g", [("fp64", 1e-13, 1e-10), ("fp32", 2e-7, 1e-6),
-                                                   ("bf16x6", 2e-7, 1e-6), ("bf16x3", 1e-5, 1e-3)])
+@pytest.mark.parametrize("precision,tol_e,tol_g", [("fp64", 1e-13, 1e-10), ("mixed", 1e-8, 1e-6),
+                                                   ("fp32", 2e-7, 1e-6), ("bf16x6", 2e-7, 1e-6),
+                                                   ("bf16x3", 1e-5, 1e-3)])
 def test_config2_batched(precision, tol_e, tol_g):
     """All 148 ragged molecules of config 2 in one batch."""
     wl = make_config(2)
@@ -175,7 +176,8 @@ def test_status_and_argument_errors():
     h.close()
 
 
-@pytest.mark.parametrize("precision,tol_e,tol_g", [("fp64", 1e-12, 1e-10), ("bf16x6", 2e-7, 1e-6)])
+@pytest.mark.parametrize("precision,tol_e,tol_g", [("fp64", 1e-12, 1e-10), ("mixed", 1e-8, 1e-6),
+                                                   ("bf16x6", 1e-8, 1e-6)])
 def test_config3_block_sparse_water_box(precision, tol_e, tol_g):
     """Config 3 (M = 1472, N = 256, block-sparse H0 passed as BSR) at full size."""
     wl = make_config(3)
@@ -204,4 +206,31 @@ def test_config4_all_kpoints():
     dg = rel_err(G, G_ref)
     print(f"[result] config4: |dE|/Ne = {dE:.3e}, rel |dg| = {dg:.3e}")
     assert dE < 1e-13 and dg < 1e-10
+    h.close()
+
+
+@pytest.mark.parametrize("which,precision", [("config2", "mixed"), ("config4", "fp64")])
+def test_graph_replay_matches_eager(which, precision):
+    """The captured launch sequence reproduces the eager results bitwise on every
+    replay, with other GPU work and changing parameters between replays."""
+    import torch
+    wl = make_config(2) if which == "config2" else make_config(4, nk=8)
+    params = O.parity_params(wl)
+    params2 = [0.5 * p for p in params]
+    print(f"[case] graph replay {which} {precision}", flush=True)
+    h, _ = make_handle(wl, precision)
+    ref1 = energy_grad(h, wl, params)
+    ref2 = energy_grad(h, wl, params2)
+    h.set_graph(True)
+    for rep in range(4):
+        for prm, ref in ((params, ref1), (params2, ref2)):
+            E, g = energy_grad(h, wl, prm)
+            assert np.array_equal(E, ref[0]), rep
+            assert all(np.array_equal(a, b) for a, b in zip(g, ref[1])), rep
+        x = torch.randn(1 << 20, device="cuda:0", dtype=torch.float64)
+        assert torch.isfinite(x.sum()).item()
+        torch.cuda.synchronize()
+    h.set_graph(False)
+    E, g = energy_grad(h, wl, params)
+    assert np.array_equal(E, ref1[0])
     h.close()
