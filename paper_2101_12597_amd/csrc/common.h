@@ -49,12 +49,12 @@ struct EighProb {
   double* V;    // n x n eigenvectors (columns), same element type as A
   double* w;    // n eigenvalues (unsorted)
   int32_t n;
-  int32_t lds;  // 1: the kernel stages A and V in LDS (real, n <= EIGH_LDS_MAX)
+  int32_t lds;  // 1: small real problem solved in LDS (n <= EIGH_LDS_MAX)
 };
 constexpr int EIGH_LDS_MAX = 88;
 // dynamic LDS bytes of the staged real solver for size n
 size_t eigh_lds_bytes(int n);
-void launch_eigh_real(const EighProb* d_probs, int nprob, bool lds, int nmax, int* d_status, hipStream_t s);
+void launch_eigh_real_lds(const EighProb* d_probs, int nprob, int* d_status, hipStream_t s);
 void launch_eigh_complex(const EighProb* d_probs, int nprob, int nmax, int* d_status, hipStream_t s);
 
 // device status bits

@@ -69,108 +69,6 @@ __device__ double block_max(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------
-// real symmetric
-// ---------------------------------------------------------------------------
-template <int NT, bool LDS>
-__global__ __launch_bounds__(NT) void jacobi_real(const EighProb* __restrict__ probs, int* status) {
-  extern __shared__ double smem[];
-  __shared__ double red[NT / 64];
-  const EighProb pr = probs[blockIdx.x];
-  const int n = pr.n;
-  if (n <= 0) return;
-  const int nn = n + (n & 1), half = nn / 2;
-  double* pc = smem;                          // [half]
-  double* ps = pc + half;                     // [half]
-  int* pp = reinterpret_cast<int*>(ps + half);  // [half]
-  int* pq = pp + half;                        // [half]
-  double* A;
-  double* V;
-  if (LDS) {
-    A = reinterpret_cast<double*>(pq + half);  // 2*half ints keep 8-byte alignment
-    V = A + (size_t)n * n;
-    for (int e = threadIdx.x; e < n * n; e += NT) A[e] = pr.A[e];
-  } else {
-    A = pr.A;
-    V = pr.V;
-  }
-  __syncthreads();
-  // symmetric part (products formed in reduced precision need not be exactly symmetric)
-  for (int e = threadIdx.x; e < n * n; e += NT) {
-    const int i = e / n, k = e - i * n;
-    if (i < k) {
-      const double v = 0.5 * (A[(size_t)i * n + k] + A[(size_t)k * n + i]);
-      A[(size_t)i * n + k] = v;
-      A[(size_t)k * n + i] = v;
-    }
-  }
-  for (int e = threadIdx.x; e < n * n; e += NT) V[e] = (e / n == e % n) ? 1.0 : 0.0;
-  __syncthreads();
-  double fro = 0.0;
-  for (int e = threadIdx.x; e < n * n; e += NT) fro += A[e] * A[e];
-  const double scale = sqrt(block_sum<NT>(fro, red));
-
-  const bool finite = isfinite(scale);
-  bool converged = !finite || (n == 1) || scale == 0.0;
-  for (int sweep = 0; sweep < MAX_SWEEPS && !converged; ++sweep) {
-    double maxoff = 0.0;
-    for (int r = 0; r < nn - 1; ++r) {
-      for (int j = threadIdx.x; j < half; j += NT) {
-        int p, q;
-        rr_pair(r, j, nn, p, q);
-        double c = 1.0, s = 0.0;
-        if (p < n && q < n) {
-          double apq = A[(size_t)p * n + q];
-          maxoff = fmax(maxoff, fabs(apq));
-          if (apq != 0.0) {
-            jacobi_cs(A[(size_t)p * n + p], A[(size_t)q * n + q], fabs(apq), c, s);
-            if (apq < 0.0) s = -s;
-          }
-        }
-        pp[j] = p;
-        pq[j] = q;
-        pc[j] = c;
-        ps[j] = s;
-      }
-      __syncthreads();
-      for (int b = threadIdx.x; b < half * half; b += NT) {
-        const int ja = b / half, jb = b - ja * half;
-        const int pa = pp[ja], qa = pq[ja], pb = pp[jb], qb = pq[jb];
-        const double ca = pc[ja], sa = ps[ja], cb = pc[jb], sb = ps[jb];
-        const bool va = qa < n, vb = qb < n;  // p < n always (dummy index is nn-1)
-        double x00 = A[(size_t)pa * n + pb];
-        double x01 = vb ? A[(size_t)pa * n + qb] : 0.0;
-        double x10 = va ? A[(size_t)qa * n + pb] : 0.0;
-        double x11 = (va && vb) ? A[(size_t)qa * n + qb] : 0.0;
-        double y00 = x00 * cb - x01 * sb, y01 = x00 * sb + x01 * cb;
-        double y10 = x10 * cb - x11 * sb, y11 = x10 * sb + x11 * cb;
-        double z00 = ca * y00 - sa * y10, z01 = ca * y01 - sa * y11;
-        double z10 = sa * y00 + ca * y10, z11 = sa * y01 + ca * y11;
-        if (ja == jb) z01 = z10 = 0.0;
-        A[(size_t)pa * n + pb] = z00;
-        if (vb) A[(size_t)pa * n + qb] = z01;
-        if (va) A[(size_t)qa * n + pb] = z10;
-        if (va && vb) A[(size_t)qa * n + qb] = z11;
-      }
-      for (int e = threadIdx.x; e < n * half; e += NT) {
-        const int i = e / half, j = e - i * half;
-        const int p = pp[j], q = pq[j];
-        if (q >= n) continue;
-        const double c = pc[j], s = ps[j];
-        double vp = V[(size_t)i * n + p], vq = V[(size_t)i * n + q];
-        V[(size_t)i * n + p] = vp * c - vq * s;
-        V[(size_t)i * n + q] = vp * s + vq * c;
-      }
-      __syncthreads();
-    }
-    converged = block_max<NT>(maxoff, red) <= CONV_TOL * scale;
-  }
-  for (int i = threadIdx.x; i < n; i += NT) pr.w[i] = A[(size_t)i * n + i];
-  if (LDS)
-    for (int e = threadIdx.x; e < n * n; e += NT) pr.V[e] = V[e];
-  if ((!converged || !finite) && threadIdx.x == 0) atomicOr(status, finite ? ST_EIGH : ST_NONFINITE);
-}
-
-// ---------------------------------------------------------------------------
 // real symmetric, matrix and vectors in LDS (n <= EIGH_LDS_MAX), 1024 threads.
 // Same rounds as jacobi_real; the per-round index maps are advanced
 // incrementally (no integer division) and the pairing wraps without modulo.
@@ -403,22 +301,16 @@ static size_t real_params_bytes(int n) {
 
 size_t eigh_lds_bytes(int n) { return real_params_bytes(n) + 2 * (size_t)n * n * sizeof(double); }
 
-void launch_eigh_real(const EighProb* d_probs, int nprob, bool lds, int nmax, int* d_status, hipStream_t s) {
+void launch_eigh_real_lds(const EighProb* d_probs, int nprob, int* d_status, hipStream_t s) {
   if (nprob <= 0) return;
-  if (lds) {
-    size_t bytes = eigh_lds_bytes(EIGH_LDS_MAX);
-    static bool attr = false;
-    if (!attr) {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_real_lds),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-      attr = true;
-    }
-    jacobi_real_lds<<<nprob, JL_NT, bytes, s>>>(d_probs, d_status);
-  } else {
-    // rotation parameters for the largest matrix of the batch (n <= 4096: at most 48 KB)
-    size_t bytes = real_params_bytes(nmax);
-    jacobi_real<1024, false><<<nprob, 1024, bytes, s>>>(d_probs, d_status);
+  size_t bytes = eigh_lds_bytes(EIGH_LDS_MAX);
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_real_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)bytes);
+    attr = true;
   }
+  jacobi_real_lds<<<nprob, JL_NT, bytes, s>>>(d_probs, d_status);
 }
 
 void launch_eigh_complex(const EighProb* d_probs, int nprob, int nmax, int* d_status, hipStream_t s) {

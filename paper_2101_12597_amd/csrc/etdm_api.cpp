@@ -15,6 +15,7 @@
 #include "etdm.h"
 #include "common.h"
 #include "ov.h"
+#include "eigh_large.h"
 
 using namespace etdm;
 
@@ -22,6 +23,7 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int LB_MMAX = 8;
+constexpr int LARGE_EIGH_MAX_SWEEPS = 30;
 
 // Gauss-Legendre nodes and weights on [0, 1] by Newton iteration on the
 // Legendre polynomial P_n (three-term recurrence), mapped from [-1, 1].
@@ -117,6 +119,8 @@ GemmProb with_addend(GemmProb p, const double* D, int64_t ldd, double beta) {
 
 struct OvBuf {
   double *C0, *H0, *f, *B, *G, *U;
+  double* eig_ws;  // workspace of the large eigensolver (N > EIGH_LDS_MAX), else null
+  EighLargeState* eig_st;
   double *P, *X, *s, *Xcsw, *F3, *T1s, *T2, *T3s, *T3, *mu1, *mu2;
   double *Q1, *Cocc, *Z1, *Cvirt, *T, *d, *e, *Lov, *R, *Gam1, *Gam, *Nm, *Y1, *Y2;
   double *HC0, *n0, *eps;
@@ -179,6 +183,7 @@ struct etdm_handle {
   ZInst* d_z = nullptr;
   EighProb *d_eig_lds = nullptr, *d_eig_glb = nullptr;
   int n_eig_lds = 0, n_eig_glb = 0, eig_nmax = 1;
+  std::vector<EighLarge> eig_large;  // real problems above the LDS size
   const double** d_n0ptr = nullptr;
   double* d_wts = nullptr;
   // grouped GEMM launches
@@ -344,6 +349,12 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       b.HC0 = b.U;  // the preconditioner's H0 C0 shares the expm output workspace
       b.n0 = pl.take(M);
       b.eps = pl.take(M);
+      b.eig_ws = nullptr;
+      b.eig_st = nullptr;
+      if (N > EIGH_LDS_MAX) {
+        b.eig_ws = pl.take((int64_t)eigh_large_workspace((int)N, nullptr));
+        b.eig_st = reinterpret_cast<EighLargeState*>(pl.take(8));
+      }
     }
   } else {
     h->zb.resize(h->n_inst);
@@ -439,8 +450,25 @@ etdm_status build_ov_plan(etdm_handle* h) {
     h->s_PQ.add(prob(N, N, Nv, b.B, Nv, b.B, Nv, b.P, N));
     h->s_PQ.add(prob(M, N, Nv, b.C0 + N, M, b.B, Nv, b.Q1, N));
     // P = X diag(s) X^T
-    EighProb ep{b.P, b.X, b.s, N, N <= EIGH_LDS_MAX ? 1 : 0};
-    (ep.lds ? el : eg).push_back(ep);
+    if (N <= EIGH_LDS_MAX) {
+      el.push_back(EighProb{b.P, b.X, b.s, N, 1});
+    } else {
+      EighLarge e;
+      size_t npad = 0;
+      eigh_large_workspace(N, &npad);
+      e.P = b.P;
+      e.X = b.X;
+      e.w = b.s;
+      e.n = N;
+      e.npad = (int)npad;
+      e.nb = (int)npad / 32;
+      e.Aw = b.eig_ws;
+      e.Vw = e.Aw + npad * npad;
+      e.Qb = e.Vw + npad * npad;
+      e.partial = e.Qb + (size_t)(e.nb / 2) * 64 * 64;
+      e.st = b.eig_st;
+      h->eig_large.push_back(e);
+    }
     spec.push_back(OvSpec{b.s, b.X, b.Xcsw, b.T1s, b.T2, b.T3s, b.T3, N});
     bspec.push_back(h->tot_spec);
     h->tot_spec += N * N + N * OV_NQ;
@@ -509,7 +537,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
       h->timers[O_EIGL].flops += 9.0 * e.n * (double)e.n * e.n;
       h->timers[O_EIGL].bytes += 16.0 * e.n * (double)e.n + 8.0 * e.n;
     }
-    for (const EighProb& e : eg) {
+    for (const EighLarge& e : h->eig_large) {
       h->timers[O_EIGG].flops += 9.0 * e.n * (double)e.n * e.n;
       h->timers[O_EIGG].bytes += 16.0 * e.n * (double)e.n + 8.0 * e.n;
     }
@@ -669,8 +697,14 @@ void free_handle(etdm_handle* h) {
 
 void ov_exponential_part(etdm_handle* h, hipStream_t s) {
   { TIMED(O_PQ); h->s_PQ.launch(s); }
-  { TIMED(O_EIGL); launch_eigh_real(h->d_eig_lds, h->n_eig_lds, true, EIGH_LDS_MAX, h->status, s); }
-  { TIMED(O_EIGG); launch_eigh_real(h->d_eig_glb, h->n_eig_glb, false, h->eig_nmax, h->status, s); }
+  { TIMED(O_EIGL); launch_eigh_real_lds(h->d_eig_lds, h->n_eig_lds, h->status, s); }
+  if (!h->eig_large.empty()) {
+    TIMED(O_EIGG);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipStreamIsCapturing(s, &cs);
+    for (const EighLarge& e : h->eig_large)
+      launch_eigh_large(e, LARGE_EIGH_MAX_SWEEPS, h->status, s, cs == hipStreamCaptureStatusNone);
+  }
   { TIMED(O_SPEC); launch_ov_spectral(h->d_spec, h->b_spec, h->n_inst, h->tot_spec, h->gl_t, h->gl_w, s); }
   { TIMED(O_F3MU); h->s_F3mu.launch(s); }
 }
