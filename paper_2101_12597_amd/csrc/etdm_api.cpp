@@ -121,6 +121,8 @@ struct OvBuf {
   double *C0, *H0, *f, *B, *G, *U;
   double* eig_ws;  // workspace of the large eigensolver (N > EIGH_LDS_MAX), else null
   EighLargeState* eig_st;
+  BsrMat H0_bsr;   // block-sparse H0 (h0_format = 1; then H0 is null)
+  int64_t bsr_nnz; // stored entries of H0_bsr
   double *P, *X, *s, *Xcsw, *F3, *T1s, *T2, *T3s, *T3, *mu1, *mu2;
   double *Q1, *Cocc, *Z1, *Cvirt, *T, *d, *e, *Lov, *R, *Gam1, *Gam, *Nm, *Y1, *Y2;
   double *HC0, *n0, *eps;
@@ -319,7 +321,9 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       b.U = h->U_ws + uoff;
       uoff += M * M;
       b.C0 = pl.take(M * M);
-      b.H0 = pl.take(M * M);
+      b.H0 = h->h0_format == 0 ? pl.take(M * M) : nullptr;
+      b.H0_bsr = BsrMat{nullptr, nullptr, nullptr, 0, 0};
+      b.bsr_nnz = 0;
       b.f = pl.take(M);
       b.P = pl.take(N * N);
       b.X = pl.take(N * N);
@@ -481,7 +485,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
     h->s_Z.add(with_second(prob(M, N, N, b.C0, M, Fs, N, b.Z1, N), N, b.Q1, N, Wm, N, 1.0));
     // C_virt = C0_v + Z1 B, T0 = H0 C_occ
     h->s_V.add(with_addend(prob(M, Nv, N, b.Z1, N, b.B, Nv, b.Cvirt, Nv), b.C0 + N, M, 1.0));
-    h->s_T.add(prob(M, N, M, b.H0, M, b.Cocc, N, b.T, N));
+    if (b.H0) h->s_T.add(prob(M, N, M, b.H0, M, b.Cocc, N, b.T, N));
     rows.push_back(OvRows{b.Cocc, b.T, b.d, b.e, M, N, h->focc[i]});
     brows.push_back(h->tot_rows);
     h->tot_rows += M;
@@ -506,7 +510,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
     h->s_Uvv.add(with_addend(prob(Nv, Nv, N, b.B, Nv, b.Lov, Nv, b.U + (size_t)N * M + N, M),
                              b.U + (size_t)N * M + N, M, 1.0));
     // preconditioner: H0 C0
-    h->s_HC0.add(prob(M, M, M, b.H0, M, b.C0, M, b.HC0, M));
+    if (b.H0) h->s_HC0.add(prob(M, M, M, b.H0, M, b.C0, M, b.HC0, M));
   }
   h->n_eig_lds = (int)el.size();
   h->n_eig_glb = (int)eg.size();
@@ -544,6 +548,10 @@ etdm_status build_ov_plan(etdm_handle* h) {
     for (int i = 0; i < h->n_inst; ++i) {
       const double M = h->M[i], N = h->N[i];
       h->timers[O_ROWS].flops += 6.0 * M * N;
+      if (h->h0_format == 1) {
+        h->timers[O_T].flops += 2.0 * (double)h->ov[i].bsr_nnz * N;
+        h->timers[O_T].bytes += 8.0 * ((double)h->ov[i].bsr_nnz + 2.0 * M * N);
+      }
       h->timers[O_ROWS].bytes += 8.0 * (3.0 * M * N + 2.0 * M);
       h->timers[O_SPEC].bytes += 8.0 * (4.0 * N * N + 4.0 * N * OV_NQ);
       h->timers[O_PAIR].flops += 3.0 * N * N;
@@ -713,7 +721,15 @@ void ov_energy_grad(etdm_handle* h, hipStream_t s) {
   ov_exponential_part(h, s);
   { TIMED(O_C); h->s_C.launch(s); }
   { TIMED(O_Z); h->s_Z.launch(s); }
-  { TIMED(O_T); h->s_T.launch(s); }
+  {
+    TIMED(O_T);
+    h->s_T.launch(s);
+    if (h->h0_format == 1)
+      for (int i = 0; i < h->n_inst; ++i) {
+        const OvBuf& b = h->ov[i];
+        launch_bsr_spmm(b.H0_bsr, b.Cocc, h->N[i], h->N[i], b.T, h->N[i], s);
+      }
+  }
   { TIMED(O_V); h->s_V.launch(s); }
   { TIMED(O_ROWS); launch_ov_rows(h->d_rows, h->b_rows, h->n_inst, h->tot_rows, h->U, s); }
   {
@@ -832,6 +848,9 @@ etdm_status check_status(etdm_handle* h, hipStream_t s) {
 void build_hdiag(etdm_handle* h, hipStream_t s) {
   if (h->kind == ETDM_REAL_OV) {
     h->s_HC0.launch(s);
+    if (h->h0_format == 1)
+      for (int i = 0; i < h->n_inst; ++i)
+        launch_bsr_spmm(h->ov[i].H0_bsr, h->ov[i].C0, h->M[i], h->M[i], h->ov[i].HC0, h->M[i], s);
     for (int i = 0; i < h->n_inst; ++i) {
       const int M = h->M[i], N = h->N[i];
       const OvBuf& b = h->ov[i];
@@ -1093,7 +1112,8 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (d->kind == ETDM_COMPLEX_FULL && d->precision != ETDM_FP64) return ETDM_E_ARG;
   if (d->kind == ETDM_REAL_OV && (!d->N || d->couple)) return ETDM_E_ARG;
   if (d->h0_format != 0 && d->h0_format != 1) return ETDM_E_ARG;
-  if (d->h0_format == 1 && (d->kind != ETDM_REAL_OV || d->bsr_block < 1 || !d->bsr_row_ptr || !d->bsr_col_idx))
+  if (d->h0_format == 1 && (d->kind != ETDM_REAL_OV || d->bsr_block < 1 || d->bsr_block > BSR_MAX_BS ||
+                            !d->bsr_row_ptr || !d->bsr_col_idx))
     return ETDM_E_ARG;
   if (!std::isfinite(d->hubbard_U)) return ETDM_E_ARG;
   hipStream_t s = S(stream);
@@ -1180,29 +1200,38 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
       h0 += M * M * esz;
       continue;
     }
+    // block-sparse H0 stays block-sparse on the device: rebased row pointers,
+    // column indices (validated here) and a copy of the blocks
     const int bs = d->bsr_block, nbr = (int)(M / bs);
     const int32_t* rp = d->bsr_row_ptr + row_off;
     const int nnzb = rp[nbr] - rp[0];
     if (nnzb < 0) return bail(ETDM_E_ARG);
-    std::vector<int> brow(std::max(nnzb, 1)), bcol(std::max(nnzb, 1));
-    for (int r = 0; r < nbr; ++r) {
-      if (rp[r + 1] < rp[r]) return bail(ETDM_E_ARG);
-      for (int pidx = rp[r]; pidx < rp[r + 1]; ++pidx) {
-        const int c = d->bsr_col_idx[blk_off + pidx - rp[0]];
-        if (c < 0 || c >= nbr) return bail(ETDM_E_ARG);
-        brow[pidx - rp[0]] = r;
-        bcol[pidx - rp[0]] = c;
-      }
+    std::vector<int> rows(nbr + 1), cols(std::max(nnzb, 1));
+    for (int r = 0; r <= nbr; ++r) {
+      if (r < nbr && rp[r + 1] < rp[r]) return bail(ETDM_E_ARG);
+      rows[r] = rp[r] - rp[0];
     }
-    int *db = nullptr, *dc = nullptr;
-    if (hipMalloc(&db, brow.size() * sizeof(int)) != hipSuccess) return bail(ETDM_E_NOMEM);
-    h->dev_allocs.push_back(db);
-    if (hipMalloc(&dc, bcol.size() * sizeof(int)) != hipSuccess) return bail(ETDM_E_NOMEM);
-    h->dev_allocs.push_back(dc);
-    if (hipMemcpy(db, brow.data(), brow.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(dc, bcol.data(), bcol.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    for (int p = 0; p < nnzb; ++p) {
+      const int c = d->bsr_col_idx[blk_off + p];
+      if (c < 0 || c >= nbr) return bail(ETDM_E_ARG);
+      cols[p] = c;
+    }
+    int *drp = nullptr, *dci = nullptr;
+    double* dblk = nullptr;
+    const size_t blk_bytes = std::max<size_t>((size_t)nnzb * bs * bs, 1) * sizeof(double);
+    if (hipMalloc(&drp, rows.size() * sizeof(int)) != hipSuccess) return bail(ETDM_E_NOMEM);
+    h->dev_allocs.push_back(drp);
+    if (hipMalloc(&dci, cols.size() * sizeof(int)) != hipSuccess) return bail(ETDM_E_NOMEM);
+    h->dev_allocs.push_back(dci);
+    if (hipMalloc(&dblk, blk_bytes) != hipSuccess) return bail(ETDM_E_NOMEM);
+    h->dev_allocs.push_back(dblk);
+    if (hipMemcpy(drp, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dci, cols.data(), cols.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpyAsync(dblk, h0, (size_t)nnzb * bs * bs * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+            hipSuccess)
       return bail(ETDM_E_HIP);
-    launch_bsr_to_dense(dH0, (int)M, reinterpret_cast<const double*>(h0), db, dc, nnzb, bs, s);
+    h->ov[i].H0_bsr = BsrMat{dblk, drp, dci, nbr, bs};
+    h->ov[i].bsr_nnz = (int64_t)nnzb * bs * bs;
     h0 += (size_t)nnzb * bs * bs * sizeof(double);
     row_off += nbr + 1;
     blk_off += nnzb;

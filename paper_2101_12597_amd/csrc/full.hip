@@ -315,20 +315,8 @@ __global__ void fill_kernel(double* x, int64_t n, double v) {
 }
 
 // ---------------------------------------------------------------------------
-// set-up kernels: block-sparse H0 -> dense, orbital energies of the preconditioner
+// set-up kernels: orbital energies of the preconditioner
 // ---------------------------------------------------------------------------
-// dense[(bi*bs + r) * M + bj*bs + c] = blocks[p][r][c] for block p at (bi, bj)
-__global__ void bsr_to_dense_kernel(double* dense, int M, const double* blocks, const int* brow,
-                                    const int* bcol, int nnzb, int bs) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t total = (int64_t)nnzb * bs * bs;
-  if (idx >= total) return;
-  const int p = (int)(idx / (bs * bs));
-  const int rc = (int)(idx - (int64_t)p * bs * bs);
-  const int r = rc / bs, c = rc - r * bs;
-  dense[(size_t)(brow[p] * bs + r) * M + bcol[p] * bs + c] = blocks[idx];
-}
-
 // n0_mu = sum_i f_i |C0_mu_i|^2 (row of a real or complex M x M matrix)
 __global__ __launch_bounds__(256) void occ_density_kernel(const double* C0, const double* f, int M, int cplx,
                                                           double* out) {
@@ -409,11 +397,6 @@ void launch_fill(double* x, int64_t n, double v, hipStream_t s) {
   if (n > 0) fill_kernel<<<vgrid(n), 256, 0, s>>>(x, n, v);
 }
 
-void launch_bsr_to_dense(double* dense, int M, const double* blocks, const int* brow, const int* bcol, int nnzb,
-                         int bs, hipStream_t s) {
-  int64_t total = (int64_t)nnzb * bs * bs;
-  if (total > 0) bsr_to_dense_kernel<<<zb(total, 256), 256, 0, s>>>(dense, M, blocks, brow, bcol, nnzb, bs);
-}
 void launch_occ_density(const double* C0, const double* f, int M, int cplx, double* out, hipStream_t s) {
   if (M > 0) occ_density_kernel<<<zb(M, 4), 256, 0, s>>>(C0, f, M, cplx, out);
 }

@@ -7,7 +7,19 @@
 
 namespace etdm {
 
-constexpr int OV_NQ = 48;  // Gauss-Legendre nodes for the pair integrals (exact to rounding for sigma <= ~40)
+constexpr int OV_NQ = 48;
+constexpr int BSR_MAX_BS = 32;  // largest block size of a block-sparse H0
+
+// block-sparse rows, square blocks (device arrays)
+struct BsrMat {
+  const double* blocks;  // [nnzb][bs][bs]
+  const int* row_ptr;    // [nbr + 1]
+  const int* col_idx;    // [nnzb]
+  int nbr, bs;
+};
+// T = H C (C: M x ncols row-major, ld ldc; T: ld ldt)
+void launch_bsr_spmm(const BsrMat& H, const double* C, int64_t ldc, int ncols, double* T, int64_t ldt,
+                     hipStream_t s);  // Gauss-Legendre nodes for the pair integrals (exact to rounding for sigma <= ~40)
 
 struct OvSpec {
   const double* s;  // eigenvalues of P [N]
@@ -110,8 +122,6 @@ void launch_hdiag_ov(double* h, const double* eps, const double* f, int M, int N
 void launch_hdiag_z(double* h, double* wv, const double* eps, const double* f, int M, double w, hipStream_t s);
 void launch_fill(double* x, int64_t n, double v, hipStream_t s);
 
-void launch_bsr_to_dense(double* dense, int M, const double* blocks, const int* brow, const int* bcol, int nnzb,
-                         int bs, hipStream_t s);
 void launch_weighted_vsum(const double* const* xs, const double* ws, int n, int M, double* out, hipStream_t s);
 void launch_occ_density(const double* C0, const double* f, int M, int cplx, double* out, hipStream_t s);
 void launch_column_eps(const double* C0, const double* HC0, const double* n0, double U, int M, int cplx,

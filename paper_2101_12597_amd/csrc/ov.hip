@@ -199,6 +199,39 @@ __global__ void copy_block_kernel(double* dst, int64_t ldd, const double* src, i
   dst[(size_t)i * ldd + j] = alpha * src[(size_t)i * lds + j];
 }
 
+// T = H C for a block-sparse H (square bs x bs blocks, bs <= BSR_MAX_BS) and a
+// dense row-major C (ncols columns).  Grid: (column tiles of 256, block rows).
+// Every thread owns one column j of one block row and keeps the bs outputs in
+// registers; the blocks of the row are staged through LDS one at a time and
+// read as broadcasts.  FP64 FMA on the vector units (the blocks are too small
+// and too few per row to feed the matrix cores).
+__global__ __launch_bounds__(256) void bsr_spmm_kernel(BsrMat H, const double* __restrict__ C, int64_t ldc,
+                                                       int ncols, double* __restrict__ T, int64_t ldt) {
+  __shared__ double blk[BSR_MAX_BS * BSR_MAX_BS];
+  const int I = blockIdx.y, bs = H.bs;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const bool on = j < ncols;
+  double acc[BSR_MAX_BS];
+#pragma unroll
+  for (int r = 0; r < BSR_MAX_BS; ++r) acc[r] = 0.0;
+  for (int p = H.row_ptr[I]; p < H.row_ptr[I + 1]; ++p) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < bs * bs; e += 256) blk[e] = H.blocks[(size_t)p * bs * bs + e];
+    __syncthreads();
+    const double* Cc = C + (size_t)H.col_idx[p] * bs * ldc;
+    for (int c = 0; c < bs; ++c) {
+      const double x = on ? Cc[(size_t)c * ldc + j] : 0.0;
+#pragma unroll
+      for (int r = 0; r < BSR_MAX_BS; ++r)
+        if (r < bs) acc[r] += blk[r * bs + c] * x;
+    }
+  }
+  if (!on) return;
+#pragma unroll
+  for (int r = 0; r < BSR_MAX_BS; ++r)
+    if (r < bs) T[(size_t)(I * bs + r) * ldt + j] = acc[r];
+}
+
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 void launch_ov_spectral(const OvSpec* d, const int* d_begin, int n_inst, int total, const double* gl_t,
@@ -227,6 +260,13 @@ void launch_set_identity(double* Y, int64_t ld, int n, double alpha, hipStream_t
 void launch_copy_block(double* dst, int64_t ldd, const double* src, int64_t lds, int m, int n, double alpha,
                        hipStream_t s) {
   if (m > 0 && n > 0) copy_block_kernel<<<nblk((int64_t)m * n, 256), 256, 0, s>>>(dst, ldd, src, lds, m, n, alpha);
+}
+
+void launch_bsr_spmm(const BsrMat& H, const double* C, int64_t ldc, int ncols, double* T, int64_t ldt,
+                     hipStream_t s) {
+  if (ncols <= 0 || H.nbr <= 0) return;
+  dim3 grid((unsigned)nblk(ncols, 256), (unsigned)H.nbr);
+  bsr_spmm_kernel<<<grid, 256, 0, s>>>(H, C, ldc, ncols, T, ldt);
 }
 
 }  // namespace etdm
