@@ -42,6 +42,10 @@ WORKLOADS = {
 DEFAULT_PREC = {1: "fp64", 2: "mixed", 3: "mixed", 4: "fp64", 5: "mixed"}
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +55,7 @@ def parse():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--lbfgs-iters", type=int, default=0, help="also time this many L-BFGS iterations")
     return ap.parse_args()
 
 
@@ -107,7 +112,9 @@ def stage_profile(h, A, E, G, reps=5):
 
 
 def oracle_reference(wl, params):
-    """Per-instance E and g from the FP64 oracle (definition path), and its wall time."""
+    """Per-instance E and g from the FP64 oracle and its wall time: the definition path
+    (eigendecomposition of iA), or for M > 2000 the structured path (the M x M complex
+    eigendecomposition would take minutes per evaluation)."""
     import copy
     import numpy as np
     from oracle import etdm as O
@@ -118,7 +125,10 @@ def oracle_reference(wl, params):
         sub.instances = [inst]
         if wl.couple:
             break
-        e, (g,) = O.energy_grad(sub, [p])
+        if inst.M > 2000:
+            e, g = O.energy_grad_ov(inst, p, wl.hubbard_U)
+        else:
+            e, (g,) = O.energy_grad(sub, [p])
         Es.append(e)
         gs.append(g)
     if wl.couple:
@@ -150,9 +160,12 @@ def main():
 
     cfg = args.config
     prec = args.precision or DEFAULT_PREC[cfg]
+    log(f"generating config {cfg}")
     wl = make_config(cfg)
     params = O.parity_params(wl)
+    log("creating the handle")
     h, A, E, G = build_handle(wl, prec)
+    log("stage profile")
 
     # which stage dominates: time every stage over a few evaluations
     for _ in range(max(1, args.warmup)):
@@ -161,6 +174,7 @@ def main():
     prof = stage_profile(h, A, E, G)
     dom = max(prof, key=lambda r: r["total_ms"])
 
+    log(f"dominant stage {dom['name']}; timed runs")
     # throughput: the launch sequence replayed from a captured HIP graph
     h.set_graph(True)
     sec, _ = timed_run(h, A, E, G, args.steps, args.warmup)
@@ -177,6 +191,7 @@ def main():
     h.sync_status()
     E_gpu = E.cpu().numpy()
     g_gpu = unpack_params(wl, G.cpu().numpy())
+    log("oracle reference")
     Es, gs, t_oracle = oracle_reference(wl, params)
     if wl.couple:
         dE = abs(E_gpu[-1] - Es[0]) / wl.n_electrons
@@ -237,16 +252,33 @@ def main():
         sec64, _ = timed_run(h64, A64, E64, G64, max(5, args.steps // 2), 2)
         out["fp64_path"] = {"value": 1.0 / sec64, "ms_per_step": sec64 * 1e3, "speedup": sec64 / sec}
         h64.close()
+    if args.lbfgs_iters > 0:
+        log("L-BFGS iterations")
+        # full L-BFGS iterations from A = 0 (direction, line search, memory update)
+        h.set_graph(True)
+        A0 = torch.zeros_like(A)
+        info = h.lbfgs_step(A0, E, G)  # initialisation + first iteration
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [h.lbfgs_step(A0, E, G) for _ in range(args.lbfgs_iters)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.lbfgs_iters
+        out["lbfgs"] = {"ms_per_iteration": dt * 1e3, "iterations": args.lbfgs_iters,
+                        "evals_per_iteration": (infos[-1]["n_evals"] - info["n_evals"]) / args.lbfgs_iters,
+                        "E": infos[-1]["E"], "gnorm": infos[-1]["gnorm"]}
+        h.set_graph(False)
     if not args.no_cpu_baseline:
         reps, total = 1, t_oracle
         while total < 10.0 and reps < 8:
             _, _, t = oracle_reference(wl, params)
             total += t
             reps += 1
+        path = ("structured occupied-virtual path" if max(i.M for i in wl.instances) > 2000
+                else "definition path (eigendecomposition of iA)")
         out["cpu_baseline"] = {
             "value": reps / total, "unit": "evals/s", "cores": blas_threads(), "kind": "oracle",
             "sample": f"{reps} full evaluation(s) of all {len(wl.instances)} instances with the FP64 "
-                      "oracle's definition path (eigendecomposition of iA), NumPy/OpenBLAS",
+                      f"oracle's {path}, NumPy/OpenBLAS",
         }
     h.close()
     print(json.dumps(out))

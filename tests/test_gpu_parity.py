@@ -234,3 +234,20 @@ def test_graph_replay_matches_eager(which, precision):
     E, g = energy_grad(h, wl, params)
     assert np.array_equal(E, ref1[0])
     h.close()
+
+
+def test_config5_large_water_box_mixed():
+    """Config 5 at full size (M = 13248, N = 2304, block-sparse H0) in the mixed mode,
+    against the structured FP64 oracle (itself pinned to the definition path)."""
+    wl = make_config(5)
+    inst = wl.instances[0]
+    params = O.parity_params(wl)
+    print("[case] config5 mixed", flush=True)
+    h, _ = make_handle(wl, "mixed", use_bsr=True)
+    E, g = energy_grad(h, wl, params)
+    h.close()
+    E_ref, g_ref = O.energy_grad_ov(inst, params[0], wl.hubbard_U)
+    dE = abs(E[0] - E_ref) / inst.f.sum()
+    dg = np.linalg.norm(g[0] - g_ref) / np.linalg.norm(g_ref)
+    print(f"[result] config5 mixed: |dE|/Ne = {dE:.3e}, rel |dg| = {dg:.3e}")
+    assert dE < 1e-8 and dg < 1e-6
