@@ -1,4 +1,6 @@
-// FP64 Hermitian eigensolver: parallel cyclic Jacobi, one workgroup per matrix.
+// FP64 Hermitian eigensolvers, one workgroup per matrix: parallel cyclic Jacobi
+// (complex matrices, and the fallback of the small real solver) and, for small
+// real symmetric matrices, a tridiagonal solver in LDS (further below).
 //
 // Each sweep runs n' - 1 rounds (n' = n rounded up to even) of the round-robin
 // ("circle") pairing, so every index pair is rotated exactly once per sweep and
@@ -20,6 +22,8 @@
 // far smaller; a large multiple eigenvalue (the null space of B B^T when B has
 // more rows than columns) converges only about tenfold per sweep below 1e-8,
 // which is what sets the threshold.  More than MAX_SWEEPS sweeps sets ST_EIGH.
+#include <cfloat>
+
 #include "common.h"
 
 namespace etdm {
@@ -69,9 +73,10 @@ __device__ double block_max(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------
-// real symmetric, matrix and vectors in LDS (n <= EIGH_LDS_MAX), 1024 threads.
-// Same rounds as jacobi_real; the per-round index maps are advanced
+// real symmetric Jacobi sweeps on a matrix and vectors in LDS (n <= EIGH_LDS_MAX),
+// 1024 threads.  Same rounds as above; the per-round index maps are advanced
 // incrementally (no integer division) and the pairing wraps without modulo.
+// Returns whether the sweeps converged.
 // ---------------------------------------------------------------------------
 constexpr int JL_NT = 1024;
 
@@ -88,32 +93,11 @@ __device__ __forceinline__ void rr_pair_fast(int r, int j, int m, int nn, int& p
   }
 }
 
-__global__ __launch_bounds__(JL_NT) void jacobi_real_lds(const EighProb* __restrict__ probs, int* status) {
-  extern __shared__ double smem[];
-  __shared__ double red[JL_NT / 64];
-  const EighProb pr = probs[blockIdx.x];
-  const int n = pr.n;
-  if (n <= 0) return;
+__device__ bool jacobi_lds_sweeps(double* A, double* V, double* pc, double* ps, int n, double scale,
+                                  double* red) {
   const int nn = n + (n & 1), half = nn / 2, m = nn - 1;
-  double* pc = smem;
-  double* ps = pc + half;
-  int* pp = reinterpret_cast<int*>(ps + half);
-  int* pq = pp + half;
-  double* A = reinterpret_cast<double*>(pq + half);
-  double* V = A + n * n;
   const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += JL_NT) {
-    const int i = e / n, k = e - i * n;
-    // symmetric part: products formed in reduced precision need not be exactly symmetric
-    A[e] = 0.5 * (pr.A[e] + pr.A[k * n + i]);
-    V[e] = (i == k) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  double fro = 0.0;
-  for (int e = tid; e < n * n; e += JL_NT) fro += A[e] * A[e];
-  const double scale = sqrt(block_sum<JL_NT>(fro, red));
-  const bool finite = isfinite(scale);
-  bool converged = !finite || n == 1 || scale == 0.0;
+  bool converged = n == 1 || scale == 0.0;
   // Thread t < nact keeps one column pair jb = t % half for the whole round (its
   // rotation is read once) and walks the row pairs ja = t / half + k * stride;
   // the same thread walks rows i of V for pair jb.  One division, done once.
@@ -175,9 +159,517 @@ __global__ __launch_bounds__(JL_NT) void jacobi_real_lds(const EighProb* __restr
     }
     converged = block_max<JL_NT>(maxoff, red) <= CONV_TOL * scale;
   }
-  for (int i = tid; i < n; i += JL_NT) pr.w[i] = A[i * n + i];
-  for (int e = tid; e < n * n; e += JL_NT) pr.V[e] = V[e];
-  if ((!converged || !finite) && tid == 0) atomicOr(status, finite ? ST_EIGH : ST_NONFINITE);
+  return converged;
+}
+
+// ---------------------------------------------------------------------------
+// real symmetric, n <= EIGH_LDS_MAX, one workgroup of 1024 threads per matrix,
+// everything in LDS:
+//   1. Householder reduction A = Q T Q^T to tridiagonal T (d, e), Q^T accumulated;
+//   2. T is split where |e_k| <= eps ||T||; the eigenvalues of every unreduced
+//      block are bracketed by multisection (2 T points per eigenvalue and round)
+//      on Sturm counts of the LDL^T pivots, down to 1e-8 ||T||;
+//   3. per eigenvalue, twisted factorizations of T - lambda I (forward pivots D+,
+//      backward pivots D-, twist index r minimising |D+_r + D-_r - (d_r - lambda)|)
+//      give the eigenvector (z_r = 1 and the two one-sided recurrences outward) and
+//      the Rayleigh-quotient correction gamma_r / ||z||^2 of lambda, iterated while
+//      the correction is above rounding level (the bracket bounds every step);
+//   4. X = Q Z on the matrix cores;
+//   5. check: G = X^T X; one Newton-Schulz step X <- X (3 I - G) / 2 when
+//      max|G - I| > 1e-13, and the residual max|A X - X diag(lambda)|.
+// A matrix whose vectors are not orthogonal to 1e-6 (repeated or tightly
+// clustered eigenvalues, for which independent twisted vectors coincide) or
+// whose residual exceeds 1e-12 ||A||_F is solved again by the Jacobi sweeps.
+// ---------------------------------------------------------------------------
+constexpr int TL_NT = 1024;
+constexpr int TL_MAXT = 3;             // 16 x 16 tiles per wavefront: ceil(36 / 16)
+constexpr int TL_MAXIT = 64;           // multisection rounds (about 15 are needed)
+constexpr double TL_ORTH_NS = 1e-13;
+constexpr double TL_ORTH_MAX = 1e-6;
+constexpr double TL_RES_MAX = 1e-12;
+
+typedef double tl_d4 __attribute__((ext_vector_type(4)));
+
+// acc = op(X) Y for n x n row-major LDS matrices (ld n), op(X) = X or X^T.
+// Wavefront w owns tiles w, w + 16, w + 32 of the ceil(n/16)^2 grid.
+template <bool XT>
+__device__ void tl_mm(const double* X, const double* Y, int n, tl_d4 (&acc)[TL_MAXT]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nt = (n + 15) >> 4, lr = lane & 15, lk = lane >> 4;
+  for (int s = 0; s < TL_MAXT; ++s) {
+    acc[s] = tl_d4{0.0, 0.0, 0.0, 0.0};
+    const int t = wave + 16 * s;
+    if (t >= nt * nt) continue;  // uniform in the wavefront
+    const int row = (t / nt) * 16 + lr, col = (t % nt) * 16 + lr;
+    for (int k0 = 0; k0 < n; k0 += 4) {
+      const int k = k0 + lk;
+      double a = 0.0, b = 0.0;
+      if (k < n) {
+        if (row < n) a = XT ? X[k * n + row] : X[row * n + k];
+        if (col < n) b = Y[k * n + col];
+      }
+      acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
+    }
+  }
+}
+
+// (i, j) of accumulator element r of tile slot s of this lane; false outside n x n
+__device__ __forceinline__ bool tl_elem(int n, int s, int r, int& i, int& j) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nt = (n + 15) >> 4, t = wave + 16 * s;
+  if (t >= nt * nt) return false;
+  i = (t / nt) * 16 + (lane >> 4) + 4 * r;
+  j = (t % nt) * 16 + (lane & 15);
+  return i < n && j < n;
+}
+
+__device__ __forceinline__ void tl_store(double* C, int n, const tl_d4 (&acc)[TL_MAXT]) {
+  for (int s = 0; s < TL_MAXT; ++s)
+    for (int r = 0; r < 4; ++r) {
+      int i, j;
+      if (tl_elem(n, s, r, i, j)) C[i * n + j] = acc[s][r];
+    }
+}
+
+// NaN and overflow map to +inf so that a max-reduction cannot hide them
+__device__ __forceinline__ double tl_err(double x) { return (x <= 1e300) ? x : INFINITY; }
+
+// Cross-lane sums through DPP (no LDS round trip).  Every lane of a quad (and
+// of the wavefront, for tl_wave_sum) ends with bit-identical results.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double tl_dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double tl_quad_sum(double v) {
+  v += tl_dpp<0xB1>(v);  // quad_perm [1,0,3,2]
+  v += tl_dpp<0x4E>(v);  // quad_perm [2,3,0,1]
+  return v;
+}
+__device__ __forceinline__ double tl_wave_sum(double v) {
+  v = tl_quad_sum(v);
+  v += tl_dpp<0x141>(v);       // row_half_mirror: sums of 8 lanes
+  v += tl_dpp<0x140>(v);       // row_mirror: sums of 16 lanes
+  v += tl_dpp<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += tl_dpp<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3: lane 63 holds the total
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// 1 / q from the hardware reciprocal (about 28 correct bits) refined by one
+// Newton step (about 10 ulp): the pivot recurrences below are backward stable
+// with any relative error of a few ulps per operation.
+__device__ __forceinline__ double tl_rcp(double q) {
+  const double r = __builtin_amdgcn_rcp(q);
+  return fma(r, fma(-q, r, 1.0), r);
+}
+
+__device__ __forceinline__ double tl_readlane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// numbers of eigenvalues below x0 and below x1 of the unreduced block [b0, b1)
+// of T (two independent pivot chains; d and e^2 are read from LDS eight rows at
+// a time so that the loads overlap)
+__device__ void tl_sturm2(const double* d, const double* e2, int b0, int b1, double x0, double x1,
+                          double pivmin, int& c0, int& c1) {
+  double q0 = d[b0] - x0, q1 = d[b0] - x1;
+  if (fabs(q0) < pivmin) q0 = -pivmin;
+  if (fabs(q1) < pivmin) q1 = -pivmin;
+  c0 = q0 < 0.0;
+  c1 = q1 < 0.0;
+  int i = b0 + 1;
+  for (; i + 8 <= b1; i += 8) {
+    double dd[8], ee[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      dd[u] = d[i + u];
+      ee[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      q0 = (dd[u] - x0) - ee[u] * tl_rcp(q0);
+      q1 = (dd[u] - x1) - ee[u] * tl_rcp(q1);
+      if (fabs(q0) < pivmin) q0 = -pivmin;
+      if (fabs(q1) < pivmin) q1 = -pivmin;
+      c0 += q0 < 0.0;
+      c1 += q1 < 0.0;
+    }
+  }
+  for (; i < b1; ++i) {
+    const double dd = d[i], ee = e2[i - 1];
+    q0 = (dd - x0) - ee * tl_rcp(q0);
+    q1 = (dd - x1) - ee * tl_rcp(q1);
+    if (fabs(q0) < pivmin) q0 = -pivmin;
+    if (fabs(q1) < pivmin) q1 = -pivmin;
+    c0 += q0 < 0.0;
+    c1 += q1 < 0.0;
+  }
+}
+
+__device__ __forceinline__ double tl_piv(double x, double pivmin) { return fabs(x) < pivmin ? -pivmin : x; }
+
+constexpr int TL_NCH = 5;                     // row chunks of the matrix-vector products
+constexpr int TL_PMLD = 2 * EIGH_LDS_MAX;     // stride of their partial sums
+constexpr int TL_XS = 1024;                   // multisection points per round
+constexpr double TL_BISECT_TOL = 1e-8;        // bracket width / ||T|| handed to the RQI
+constexpr int TL_RQI_MAX = 4;                 // Rayleigh-quotient corrections per eigenvalue
+
+// LDS bytes of eigh_tridiag_lds for size n
+static size_t tl_lds_bytes(int n) {
+  return sizeof(double) * (2 * (size_t)n * n + 6 * (size_t)n + TL_NCH * TL_PMLD + TL_XS) +
+         sizeof(int) * (2 * (size_t)n + TL_XS);
+}
+
+// Householder reduction A = Q T Q^T of the symmetric n x n matrix A (LDS,
+// row-major, both triangles kept), with QT = Q^T accumulated (QT = I on entry).
+// Step k takes the reflector from row k right of the diagonal (row k equals
+// column k and is final); every wavefront computes the same reflector scalars
+// with a DPP sum.  Then, between two barriers:
+//   B: p = A_t v over the trailing columns and u = Q v over all rows, as column
+//      sums (coalesced row reads, v broadcast from registers with readlane), by
+//      3 x TL_NCH wavefronts over row chunks, partial sums to LDS;
+//   C: K = -tau p.v / 2, w = tau p + K v; A_t -= v w^T + w v^T (8 wavefronts),
+//      QT[k+1:, :] -= tau v u^T (8 wavefronts), one row per loop trip.
+// On return vd[0..n-1], ve[0..n-2] hold T.
+__device__ void tl_tridiag(double* A, double* QT, double* vd, double* ve, double* Pm, int n) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int k = 0; k < n - 2; ++k) {
+    const int L = n - k - 1;
+    const int i0 = k + 1 + lane, i1 = i0 + 64;
+    const double x0 = i0 < n ? A[k * n + i0] : 0.0;
+    const double x1 = i1 < n ? A[k * n + i1] : 0.0;
+    const double alpha = tl_readlane(x0, 0);
+    const double s2 = tl_wave_sum((lane > 0 ? x0 * x0 : 0.0) + x1 * x1);
+    double tau = 0.0, beta = alpha, inv = 0.0;
+    if (s2 != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+      tau = (beta - alpha) / beta;
+      inv = 1.0 / (alpha - beta);
+    }
+    if (threadIdx.x == 0) {
+      ve[k] = beta;
+      vd[k] = A[k * n + k];
+    }
+    if (tau == 0.0) continue;  // the column is already reduced; nothing changes
+    const double v0 = lane == 0 ? 1.0 : x0 * inv;  // v_{k+1+lane}
+    const double v1 = x1 * inv;                    // v_{k+65+lane}
+    if (wave < 3 * TL_NCH) {
+      const int ow = wave % 3, ch = wave / 3;
+      const int o = 64 * ow + lane;  // output: o < L -> p_{k+1+o}, else u_{o-L}
+      const int jb = ch * L / TL_NCH, je = (ch + 1) * L / TL_NCH;
+      const double* base = o < L ? A + (k + 1) * n + (k + 1 + o)
+                                 : (o < L + n ? QT + (k + 1) * n + (o - L) : A + (k + 1) * n + (k + 1));
+      double acc0 = 0.0, acc1 = 0.0;
+      int jj = jb;
+      for (; jj + 1 < je; jj += 2) {
+        const double va = jj < 64 ? tl_readlane(v0, jj) : tl_readlane(v1, jj - 64);
+        const double vb = jj + 1 < 64 ? tl_readlane(v0, jj + 1) : tl_readlane(v1, jj - 63);
+        acc0 += base[jj * n] * va;
+        acc1 += base[(jj + 1) * n] * vb;
+      }
+      if (jj < je) acc0 += base[jj * n] * (jj < 64 ? tl_readlane(v0, jj) : tl_readlane(v1, jj - 64));
+      if (o < L + n) Pm[ch * TL_PMLD + o] = acc0 + acc1;
+    }
+    __syncthreads();
+    double p0 = 0.0, p1 = 0.0;
+    for (int ch = 0; ch < TL_NCH; ++ch) {
+      if (lane < L) p0 += Pm[ch * TL_PMLD + lane];
+      if (lane + 64 < L) p1 += Pm[ch * TL_PMLD + lane + 64];
+    }
+    p0 *= tau;
+    p1 *= tau;
+    const double K = -0.5 * tau * tl_wave_sum(p0 * v0 + p1 * v1);
+    const double w0 = p0 + K * v0, w1 = p1 + K * v1;
+    const int grp = wave >> 3, cb = wave & 1, rc = (wave >> 1) & 3;
+    const int col = 64 * cb + lane;
+    const int rb = rc * L / 4, re = (rc + 1) * L / 4;
+    if (grp == 0) {
+      const int j = k + 1 + min(col, L - 1);
+      const double vj = cb ? v1 : v0, wj = cb ? w1 : w0;
+      for (int ii = rb; ii < re; ++ii) {
+        const double vi = ii < 64 ? tl_readlane(v0, ii) : tl_readlane(v1, ii - 64);
+        const double wi = ii < 64 ? tl_readlane(w0, ii) : tl_readlane(w1, ii - 64);
+        double* a = A + (k + 1 + ii) * n + j;
+        const double x = *a - (vi * wj + wi * vj);
+        if (col < L) *a = x;
+      }
+    } else {
+      double ur = 0.0;
+      const int r = min(col, n - 1);
+      for (int ch = 0; ch < TL_NCH; ++ch) ur += Pm[ch * TL_PMLD + L + r];
+      for (int jj = rb; jj < re; ++jj) {
+        const double tv = tau * (jj < 64 ? tl_readlane(v0, jj) : tl_readlane(v1, jj - 64));
+        double* q = QT + (k + 1 + jj) * n + r;
+        const double x = *q - tv * ur;
+        if (col < n) *q = x;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (n >= 2) {
+      vd[n - 2] = A[(n - 2) * n + n - 2];
+      ve[n - 2] = A[(n - 1) * n + n - 2];
+    }
+    vd[n - 1] = A[(n - 1) * n + n - 1];
+  }
+}
+
+// Twisted factorization of T - lam I on the unreduced block [b0, b1) (size >= 2):
+// forward pivots D+, backward pivots D-, twist r minimising
+// |gamma_i| = |D+_i + D-_i - (d_i - lam)|, then z_r = 1 and
+// z_i = -(e_i / D+_i) z_{i+1} (i < r), z_i = -(e_{i-1} / D-_i) z_{i-1} (i > r).
+// Writes z / ||z|| into column j of Z (ld n; D+ and D- are kept there meanwhile)
+// and returns the Rayleigh-quotient correction gamma_r / ||z||^2.
+__device__ double tl_twisted(const double* d, const double* e, const double* e2, int b0, int b1, double lam,
+                             double pivmin, double* Z, int n, int j) {
+  double D = tl_piv(d[b0] - lam, pivmin);
+  Z[b0 * n + j] = D;
+  for (int i = b0 + 1; i < b1; ++i) {
+    D = tl_piv((d[i] - lam) - e2[i - 1] * tl_rcp(D), pivmin);
+    Z[i * n + j] = D;
+  }
+  D = tl_piv(d[b1 - 1] - lam, pivmin);
+  int r = b1 - 1;
+  double gr = Z[(b1 - 1) * n + j] + D - (d[b1 - 1] - lam);
+  double best = fabs(gr);
+  for (int i = b1 - 2; i >= b0; --i) {
+    D = tl_piv((d[i] - lam) - e2[i] * tl_rcp(D), pivmin);
+    const double g = Z[i * n + j] + D - (d[i] - lam);
+    if (fabs(g) < best) {
+      best = fabs(g);
+      gr = g;
+      r = i;
+    }
+  }
+  if (r < b1 - 1) {  // backward pivots below the twist
+    D = tl_piv(d[b1 - 1] - lam, pivmin);
+    Z[(b1 - 1) * n + j] = D;
+    for (int i = b1 - 2; i > r; --i) {
+      D = tl_piv((d[i] - lam) - e2[i] * tl_rcp(D), pivmin);
+      Z[i * n + j] = D;
+    }
+  }
+  double nrm = 1.0, z = 1.0;
+  Z[r * n + j] = 1.0;
+  for (int i = r - 1; i >= b0; --i) {
+    z = -(e[i] * tl_rcp(Z[i * n + j])) * z;
+    Z[i * n + j] = z;
+    nrm += z * z;
+  }
+  z = 1.0;
+  for (int i = r + 1; i < b1; ++i) {
+    z = -(e[i - 1] * tl_rcp(Z[i * n + j])) * z;
+    Z[i * n + j] = z;
+    nrm += z * z;
+  }
+  const double sc = 1.0 / sqrt(nrm);
+  for (int i = b0; i < b1; ++i) Z[i * n + j] *= sc;
+  return gr / nrm;
+}
+
+__global__ __launch_bounds__(TL_NT) void eigh_tridiag_lds(const EighProb* __restrict__ probs, int* status) {
+  extern __shared__ double smem[];
+  __shared__ double red[TL_NT / 64];
+  const EighProb pr = probs[blockIdx.x];
+  const int n = pr.n;
+  if (n <= 0) return;
+  const int tid = threadIdx.x;
+  double* R1 = smem;         // A, then Z, then the Newton-Schulz factor, then A again
+  double* R2 = R1 + n * n;   // Q^T, then X
+  double* vd = R2 + n * n;   // diagonal of T
+  double* ve = vd + n;       // off-diagonal of T (n - 1)
+  double* ve2 = ve + n;      // its squares
+  double* vlo = ve2 + n;     // eigenvalue brackets
+  double* vhi = vlo + n;
+  double* vlam = vhi + n;    // eigenvalues
+  double* Pm = vlam + n;     // partial matrix-vector sums (TL_NCH x TL_PMLD)
+  double* xs = Pm + TL_NCH * TL_PMLD;  // multisection points (TL_XS)
+  int* ib0 = reinterpret_cast<int*>(xs + TL_XS);  // unreduced block of each eigenvalue
+  int* ib1 = ib0 + n;
+  int* cnt = ib1 + n;        // Sturm counts (TL_XS)
+
+  auto load_sym = [&]() {
+    for (int e = tid; e < n * n; e += TL_NT) {
+      const int i = e / n, k = e - i * n;
+      // symmetric part: products formed in reduced precision need not be exactly symmetric
+      R1[e] = 0.5 * (pr.A[e] + pr.A[k * n + i]);
+    }
+  };
+  auto set_identity = [&](double* M) {
+    for (int e = tid; e < n * n; e += TL_NT) {
+      const int i = e / n;
+      M[e] = (e == i * n + i) ? 1.0 : 0.0;
+    }
+  };
+  load_sym();
+  set_identity(R2);
+  __syncthreads();
+  double fro = 0.0;
+  for (int e = tid; e < n * n; e += TL_NT) fro += R1[e] * R1[e];
+  const double scale = sqrt(block_sum<TL_NT>(fro, red));
+  if (!isfinite(scale) || scale == 0.0 || n == 1) {
+    for (int i = tid; i < n; i += TL_NT) pr.w[i] = R1[i * n + i];
+    for (int e = tid; e < n * n; e += TL_NT) pr.V[e] = R2[e];
+    if (!isfinite(scale) && tid == 0) atomicOr(status, ST_NONFINITE);
+    return;
+  }
+
+  // 1. tridiagonal T and Q^T
+  tl_tridiag(R1, R2, vd, ve, Pm, n);
+  __syncthreads();
+
+  // 2. splitting, brackets, multisection down to TL_BISECT_TOL ||T||
+  double tn_loc = 0.0, e2_loc = 0.0;
+  for (int i = tid; i < n; i += TL_NT) {
+    const double el = i > 0 ? fabs(ve[i - 1]) : 0.0, er = i < n - 1 ? fabs(ve[i]) : 0.0;
+    tn_loc = fmax(tn_loc, fabs(vd[i]) + el + er);
+    if (i < n - 1) {
+      ve2[i] = ve[i] * ve[i];
+      e2_loc = fmax(e2_loc, ve2[i]);
+    }
+  }
+  const double tn = block_max<TL_NT>(tn_loc, red);
+  const double pivmin = DBL_MIN * fmax(1.0, block_max<TL_NT>(e2_loc, red));
+  const double eps = DBL_EPSILON, split = eps * tn;
+  if (tid < n) {
+    const int j = tid;
+    int b0 = j, b1 = j + 1;
+    while (b0 > 0 && fabs(ve[b0 - 1]) > split) --b0;
+    while (b1 < n && fabs(ve[b1 - 1]) > split) ++b1;
+    double gl = INFINITY, gu = -INFINITY;
+    for (int i = b0; i < b1; ++i) {
+      const double r = (i > b0 ? fabs(ve[i - 1]) : 0.0) + (i < b1 - 1 ? fabs(ve[i]) : 0.0);
+      gl = fmin(gl, vd[i] - r);
+      gu = fmax(gu, vd[i] + r);
+    }
+    const double margin = 8.0 * n * eps * tn + 4.0 * pivmin;
+    vlo[j] = gl - margin;
+    vhi[j] = gu + margin;
+    ib0[j] = b0;
+    ib1[j] = b1;
+  }
+  __syncthreads();
+  // T threads per eigenvalue, two points each
+  const int T = max(1, min(8, (TL_XS / 2) / n)), K = 2 * T;
+  for (int it = 0; it < TL_MAXIT; ++it) {
+    if (tid < n * T) {
+      const int j = tid / T, m = tid - j * T;
+      const double lo = vlo[j], hi = vhi[j], w = hi - lo;
+      const double x0 = lo + w * ((double)(2 * m + 1) / (double)(K + 1));
+      const double x1 = lo + w * ((double)(2 * m + 2) / (double)(K + 1));
+      int c0, c1;
+      tl_sturm2(vd, ve2, ib0[j], ib1[j], x0, x1, pivmin, c0, c1);
+      xs[2 * tid] = x0;
+      xs[2 * tid + 1] = x1;
+      cnt[2 * tid] = c0;
+      cnt[2 * tid + 1] = c1;
+    }
+    __syncthreads();
+    int more = 0;
+    if (tid < n) {
+      const int jl = tid - ib0[tid];
+      double lo = vlo[tid], hi = vhi[tid];
+      for (int m = 0; m < K; ++m) {
+        const double x = xs[tid * K + m];
+        if (cnt[tid * K + m] <= jl)
+          lo = fmax(lo, x);
+        else
+          hi = fmin(hi, x);
+      }
+      vlo[tid] = lo;
+      vhi[tid] = hi;
+      more = (hi - lo) > TL_BISECT_TOL * tn;
+    }
+    if (!__syncthreads_or(more)) break;
+  }
+
+  // 3. eigenvectors of T (column j of Z in R1, by thread j), with Rayleigh-quotient
+  //    corrections of the eigenvalue from each twisted factorization; a correction
+  //    that leaves the bracket is not taken
+  if (tid < n) {
+    const int j = tid, b0 = ib0[j], b1 = ib1[j];
+    for (int i = 0; i < b0; ++i) R1[i * n + j] = 0.0;
+    for (int i = b1; i < n; ++i) R1[i * n + j] = 0.0;
+    const double lo = vlo[j], hi = vhi[j];
+    double lam = 0.5 * (lo + hi);
+    if (b1 - b0 == 1) {
+      R1[b0 * n + j] = 1.0;
+      lam = vd[b0];
+    } else {
+      double dl = tl_twisted(vd, ve, ve2, b0, b1, lam, pivmin, R1, n, j);
+      for (int it = 0; it < TL_RQI_MAX && fabs(dl) > 2.0 * eps * tn; ++it) {
+        const double nl = lam + dl;
+        if (!(nl >= lo && nl <= hi)) break;
+        lam = nl;
+        dl = tl_twisted(vd, ve, ve2, b0, b1, lam, pivmin, R1, n, j);
+      }
+      const double nl = lam + dl;
+      if (nl >= lo && nl <= hi) lam = nl;
+    }
+    vlam[j] = lam;
+  }
+  __syncthreads();
+
+  // 4. X = Q Z = (Q^T)^T Z
+  tl_d4 acc[TL_MAXT];
+  tl_mm<true>(R2, R1, n, acc);
+  __syncthreads();
+  tl_store(R2, n, acc);
+  __syncthreads();
+
+  // 5. orthogonality, one Newton-Schulz step if needed, residual
+  tl_mm<true>(R2, R2, n, acc);
+  double orth_loc = 0.0;
+  for (int s = 0; s < TL_MAXT; ++s)
+    for (int r = 0; r < 4; ++r) {
+      int i, j;
+      if (tl_elem(n, s, r, i, j)) orth_loc = fmax(orth_loc, tl_err(fabs(acc[s][r] - (i == j ? 1.0 : 0.0))));
+    }
+  const double orth = block_max<TL_NT>(orth_loc, red);
+  bool accept = orth <= TL_ORTH_MAX;
+  if (accept && orth > TL_ORTH_NS) {
+    for (int s = 0; s < TL_MAXT; ++s)
+      for (int r = 0; r < 4; ++r) {
+        int i, j;
+        if (tl_elem(n, s, r, i, j)) R1[i * n + j] = (i == j ? 1.5 : 0.0) - 0.5 * acc[s][r];
+      }
+    __syncthreads();
+    tl_mm<false>(R2, R1, n, acc);
+    __syncthreads();
+    tl_store(R2, n, acc);
+  }
+  __syncthreads();
+  load_sym();
+  __syncthreads();
+  if (accept) {
+    tl_mm<false>(R1, R2, n, acc);
+    double res_loc = 0.0;
+    for (int s = 0; s < TL_MAXT; ++s)
+      for (int r = 0; r < 4; ++r) {
+        int i, j;
+        if (tl_elem(n, s, r, i, j)) res_loc = fmax(res_loc, tl_err(fabs(acc[s][r] - R2[i * n + j] * vlam[j])));
+      }
+    accept = block_max<TL_NT>(res_loc, red) <= TL_RES_MAX * scale;
+  }
+  if (accept) {
+    for (int i = tid; i < n; i += TL_NT) pr.w[i] = vlam[i];
+    for (int e = tid; e < n * n; e += TL_NT) pr.V[e] = R2[e];
+    return;
+  }
+  // fallback: Jacobi sweeps from the start (R1 holds A)
+  set_identity(R2);
+  __syncthreads();
+  const bool converged = jacobi_lds_sweeps(R1, R2, vlo, vhi, n, scale, red);
+  for (int i = tid; i < n; i += TL_NT) pr.w[i] = R1[i * n + i];
+  for (int e = tid; e < n * n; e += TL_NT) pr.V[e] = R2[e];
+  if (!converged && tid == 0) atomicOr(status, ST_EIGH);
 }
 
 // ---------------------------------------------------------------------------
@@ -294,23 +786,18 @@ __global__ __launch_bounds__(NT) void jacobi_complex(const EighProb* __restrict_
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static size_t real_params_bytes(int n) {
-  int half = (n + (n & 1)) / 2;
-  return (size_t)half * 2 * sizeof(double) + (size_t)half * 2 * sizeof(int);
-}
-
-size_t eigh_lds_bytes(int n) { return real_params_bytes(n) + 2 * (size_t)n * n * sizeof(double); }
+size_t eigh_lds_bytes(int n) { return tl_lds_bytes(n); }
 
 void launch_eigh_real_lds(const EighProb* d_probs, int nprob, int* d_status, hipStream_t s) {
   if (nprob <= 0) return;
-  size_t bytes = eigh_lds_bytes(EIGH_LDS_MAX);
+  const size_t bytes = tl_lds_bytes(EIGH_LDS_MAX);
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_real_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&eigh_tridiag_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)bytes);
     attr = true;
   }
-  jacobi_real_lds<<<nprob, JL_NT, bytes, s>>>(d_probs, d_status);
+  eigh_tridiag_lds<<<nprob, TL_NT, bytes, s>>>(d_probs, d_status);
 }
 
 void launch_eigh_complex(const EighProb* d_probs, int nprob, int nmax, int* d_status, hipStream_t s) {
