@@ -9,7 +9,7 @@ namespace etdm {
 
 struct EighLargeState {
   double scale;                  // ||A||_F
-  unsigned long long sweep_off;  // bit pattern of the largest pre-rotation |a_pq| of the sweep
+  unsigned long long sweep_off;  // bit pattern of the largest off-diagonal |a_ik| after the sweep
   int sweeps;
   int done;
   int finite;

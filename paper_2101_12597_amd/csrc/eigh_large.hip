@@ -13,9 +13,8 @@
 //      computing 64x64x64 FP64 MFMA products (4 wavefronts x 2 x 2 16x16x4 tiles).
 // Every index pair is rotated at least once per sweep (pairs inside a block once
 // per round), so the sweep converges at least as fast as a scalar cyclic sweep.
-// Convergence is decided on the device: the largest pre-rotation |a_pq| of a
-// sweep (atomic max on its bit pattern, which orders like the value for
-// non-negative doubles) is compared with 1e-14 ||A||_F after the sweep (a large
+// Convergence is decided on the device: after every sweep the largest
+// off-diagonal |a_ik| of the work matrix is compared with 1e-14 ||A||_F (a large
 // multiple eigenvalue, such as the null space of B B^T when B has more rows than
 // columns, converges only linearly in this ordering; well separated spectra
 // converge quadratically and do not pay for the tight threshold); later
@@ -106,7 +105,6 @@ __global__ __launch_bounds__(L_NT) void bjl_inner(EighLarge e, int r) {
   double* Q = S + SUB * SUB;    // 64 x 64
   double* pc = Q + SUB * SUB;   // 32
   double* ps = pc + SUB / 2;    // 32
-  __shared__ double red[L_NT / 64];
   const int j = blockIdx.x, npad = e.npad;
   int I, J;
   rrp(r, j, e.nb, I, J);
@@ -117,7 +115,6 @@ __global__ __launch_bounds__(L_NT) void bjl_inner(EighLarge e, int r) {
     Q[idx] = (a == b) ? 1.0 : 0.0;
   }
   __syncthreads();
-  double maxoff = 0.0;
   const int half = SUB / 2;
   const int jb = tid & (half - 1), ja0 = tid >> 5;  // 16 row-pair starts, stride 16
   for (int rr = 0; rr < SUB - 1; ++rr) {
@@ -125,7 +122,6 @@ __global__ __launch_bounds__(L_NT) void bjl_inner(EighLarge e, int r) {
       int p, q;
       rrp(rr, tid, SUB, p, q);
       const double apq = S[p * SUB + q];
-      maxoff = fmax(maxoff, fabs(apq));
       double c = 1.0, s = 0.0;
       if (apq != 0.0) rot_cs(S[p * SUB + p], S[q * SUB + q], apq, c, s);
       pc[tid] = c;
@@ -160,13 +156,28 @@ __global__ __launch_bounds__(L_NT) void bjl_inner(EighLarge e, int r) {
   }
   double* Qg = e.Qb + (size_t)j * SUB * SUB;
   for (int idx = tid; idx < SUB * SUB; idx += L_NT) Qg[idx] = Q[idx];
-  for (int o = 32; o > 0; o >>= 1) maxoff = fmax(maxoff, __shfl_xor(maxoff, o));
-  if ((tid & 63) == 0) red[tid >> 6] = maxoff;
+}
+
+// Largest |a_ik| (i != k) of the work matrix after a sweep: atomic max on the
+// bit pattern (which orders like the value for non-negative doubles).
+constexpr int OFF_BLOCKS = 512;
+__global__ __launch_bounds__(U_NT) void bjl_offmax(EighLarge e) {
+  if (e.st->done) return;
+  const int npad = e.npad, n = e.n;
+  double m = 0.0;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)npad * npad;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / npad), k = (int)(idx - (int64_t)i * npad);
+    if (i != k && i < n && k < n) m = fmax(m, fabs(e.Aw[idx]));
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  __shared__ double red[U_NT / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  if (tid == 0) {
-    double m = 0.0;
-    for (int w = 0; w < L_NT / 64; ++w) m = fmax(m, red[w]);
-    atomicMax(&e.st->sweep_off, (unsigned long long)__double_as_longlong(m));
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < U_NT / 64; ++w) t = fmax(t, red[w]);
+    atomicMax(&e.st->sweep_off, (unsigned long long)__double_as_longlong(t));
   }
 }
 
@@ -306,6 +317,7 @@ void launch_eigh_large(const EighLarge& e, int max_sweeps, int* status, hipStrea
       bjl_inner<<<half, L_NT, inner_lds, s>>>(e, r);
       bjl_update<<<tasks, U_NT, upd_lds, s>>>(e, r);
     }
+    bjl_offmax<<<OFF_BLOCKS, U_NT, 0, s>>>(e);
     bjl_sweep_end<<<1, 64, 0, s>>>(e, max_sweeps, status);
     if (check_host) {
       int done = 0;

@@ -83,9 +83,12 @@ def test_real_ov_expm_matches_oracle(which):
     h, _ = make_handle(wl, "fp64")
     U = expm(h, wl, params)
     U_ref = O.unitary(wl, params)
+    # U^T U = I to 5e-13: the instance with N = 96 > M - N has a 72-fold zero
+    # eigenvalue of P = B B^T, which the large eigensolver resolves only down to its
+    # stopping rule (largest off-diagonal after a sweep <= 1e-14 ||P||_F)
     for k, (u, r) in enumerate(zip(U, U_ref)):
         assert np.abs(u - r).max() < 1e-13, k
-        assert np.abs(u.T @ u - np.eye(u.shape[0])).max() < 1e-13
+        assert np.abs(u.T @ u - np.eye(u.shape[0])).max() < 5e-13, k
     h.close()
 
 
