@@ -137,6 +137,26 @@ def oracle_reference(wl, params):
     return np.array(Es), gs, time.perf_counter() - t0
 
 
+def measured_traffic(stage, cfg, prec):
+    """HBM bytes per launch of `stage` from a committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary (profiles/*_traffic_pmc.txt, copy-calibrated), or None when there is none
+    for this workload or the kernel source changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic_pmc.txt")):
+        for line in open(path):
+            if not line.startswith("# traffic:"):
+                continue
+            kv = dict(tok.split("=", 1) for tok in line[len("# traffic:"):].split())
+            if kv.get("stage") != stage or kv.get("config") != str(cfg) or kv.get("precision") != prec:
+                continue
+            src = os.path.join(ROOT, kv["source"])
+            if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv["sha256"]:
+                return None
+            return float(kv["bytes_per_launch"])
+    return None
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -219,7 +239,7 @@ def main():
         achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom["name"], cfg, prec)
     roof["kernel"] = dom["name"]
     roof["avg_launch_ms"] = avg_ms
     roof["launches_timed"] = dstage["launches"]

@@ -50,12 +50,35 @@ struct EighProb {
   double* w;    // n eigenvalues (unsorted)
   int32_t n;
   int32_t lds;  // 1: small real problem solved in LDS (n <= EIGH_LDS_MAX)
+  double* ws;   // complex tridiagonal path: Q^H (complex n x n)
+  int* ok;      // complex tridiagonal path: 1 when its result passed the checks (the
+                // Jacobi solver skips such problems), else 0
 };
 constexpr int EIGH_LDS_MAX = 88;
 // dynamic LDS bytes of the staged real solver for size n
 size_t eigh_lds_bytes(int n);
 void launch_eigh_real_lds(const EighProb* d_probs, int nprob, int* d_status, hipStream_t s);
 void launch_eigh_complex(const EighProb* d_probs, int nprob, int nmax, int* d_status, hipStream_t s);
+
+// Complex Hermitian eigensolver by reduction to real tridiagonal form (n <= HT_MAX),
+// one workgroup per matrix: writes the eigenvalues, the real eigenvectors Z of T
+// into the first n*n doubles of V, Q^H into ws and the acceptance flag *ok.
+constexpr int HT_MAX = 512;
+void launch_eigh_herm_tridiag(const EighProb* d_probs, int nprob, int nmax, int* d_status, hipStream_t s);
+// After G = Z^T Z: *ok &= max|G - I| <= 1e-6, and G <- (3 I - G) / 2 in place.
+struct HermCheck {
+  double* G;
+  int* ok;
+  int n;
+};
+void launch_herm_check(const HermCheck* d, int nprob, hipStream_t s);
+// Complex copy (imaginary part 0) of real n x n matrices.
+struct RealToComplex {
+  const double* src;
+  double* dst;
+  int n;
+};
+void launch_real_to_complex(const RealToComplex* d, int nprob, hipStream_t s);
 
 // device status bits
 enum : int { ST_EIGH = 1, ST_NONFINITE = 2 };

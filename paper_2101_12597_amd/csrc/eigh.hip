@@ -474,6 +474,102 @@ __device__ double tl_twisted(const double* d, const double* e, const double* e2,
   return gr / nrm;
 }
 
+// Splitting of T (d, e) where |e_k| <= eps ||T||, Gershgorin brackets per
+// unreduced block, and multisection on Sturm counts down to TL_BISECT_TOL ||T||.
+// On return lo/hi bracket eigenvalue j (ascending within its block [b0[j], b1[j])),
+// e2 holds e^2, tn = ||T||_inf-like bound, pivmin the pivot floor.  Called by all
+// threads of a workgroup of TL_NT threads; xs/cnt hold TL_XS entries.
+__device__ void tl_eigen_brackets(const double* vd, const double* ve, double* ve2, double* vlo, double* vhi,
+                                  double* xs, int* cnt, int* ib0, int* ib1, int n, double* red, double& tn,
+                                  double& pivmin) {
+  const int tid = threadIdx.x;
+  double tn_loc = 0.0, e2_loc = 0.0;
+  for (int i = tid; i < n; i += TL_NT) {
+    const double el = i > 0 ? fabs(ve[i - 1]) : 0.0, er = i < n - 1 ? fabs(ve[i]) : 0.0;
+    tn_loc = fmax(tn_loc, fabs(vd[i]) + el + er);
+    if (i < n - 1) {
+      ve2[i] = ve[i] * ve[i];
+      e2_loc = fmax(e2_loc, ve2[i]);
+    }
+  }
+  tn = block_max<TL_NT>(tn_loc, red);
+  pivmin = DBL_MIN * fmax(1.0, block_max<TL_NT>(e2_loc, red));
+  const double eps = DBL_EPSILON, split = eps * tn;
+  for (int j = tid; j < n; j += TL_NT) {
+    int b0 = j, b1 = j + 1;
+    while (b0 > 0 && fabs(ve[b0 - 1]) > split) --b0;
+    while (b1 < n && fabs(ve[b1 - 1]) > split) ++b1;
+    double gl = INFINITY, gu = -INFINITY;
+    for (int i = b0; i < b1; ++i) {
+      const double r = (i > b0 ? fabs(ve[i - 1]) : 0.0) + (i < b1 - 1 ? fabs(ve[i]) : 0.0);
+      gl = fmin(gl, vd[i] - r);
+      gu = fmax(gu, vd[i] + r);
+    }
+    const double margin = 8.0 * n * eps * tn + 4.0 * pivmin;
+    vlo[j] = gl - margin;
+    vhi[j] = gu + margin;
+    ib0[j] = b0;
+    ib1[j] = b1;
+  }
+  __syncthreads();
+  // T threads per eigenvalue, two points each
+  const int T = max(1, min(8, (TL_XS / 2) / n)), K = 2 * T;
+  for (int it = 0; it < TL_MAXIT; ++it) {
+    if (tid < n * T) {
+      const int j = tid / T, m = tid - j * T;
+      const double lo = vlo[j], hi = vhi[j], w = hi - lo;
+      const double x0 = lo + w * ((double)(2 * m + 1) / (double)(K + 1));
+      const double x1 = lo + w * ((double)(2 * m + 2) / (double)(K + 1));
+      int c0, c1;
+      tl_sturm2(vd, ve2, ib0[j], ib1[j], x0, x1, pivmin, c0, c1);
+      xs[2 * tid] = x0;
+      xs[2 * tid + 1] = x1;
+      cnt[2 * tid] = c0;
+      cnt[2 * tid + 1] = c1;
+    }
+    __syncthreads();
+    int more = 0;
+    if (tid < n) {
+      const int jl = tid - ib0[tid];
+      double lo = vlo[tid], hi = vhi[tid];
+      for (int m = 0; m < K; ++m) {
+        const double x = xs[tid * K + m];
+        if (cnt[tid * K + m] <= jl)
+          lo = fmax(lo, x);
+        else
+          hi = fmin(hi, x);
+      }
+      vlo[tid] = lo;
+      vhi[tid] = hi;
+      more = (hi - lo) > TL_BISECT_TOL * tn;
+    }
+    if (!__syncthreads_or(more)) break;
+  }
+}
+
+// Eigenvector of T for eigenvalue j (bracket lo..hi) into column j of Z (ld n),
+// with Rayleigh-quotient corrections; returns the eigenvalue.
+__device__ double tl_vector(const double* vd, const double* ve, const double* ve2, int b0, int b1, double lo,
+                            double hi, double tn, double pivmin, double* Z, int n, int j) {
+  const double eps = DBL_EPSILON;
+  for (int i = 0; i < b0; ++i) Z[i * n + j] = 0.0;
+  for (int i = b1; i < n; ++i) Z[i * n + j] = 0.0;
+  double lam = 0.5 * (lo + hi);
+  if (b1 - b0 == 1) {
+    Z[b0 * n + j] = 1.0;
+    return vd[b0];
+  }
+  double dl = tl_twisted(vd, ve, ve2, b0, b1, lam, pivmin, Z, n, j);
+  for (int it = 0; it < TL_RQI_MAX && fabs(dl) > 2.0 * eps * tn; ++it) {
+    const double nl = lam + dl;
+    if (!(nl >= lo && nl <= hi)) break;
+    lam = nl;
+    dl = tl_twisted(vd, ve, ve2, b0, b1, lam, pivmin, Z, n, j);
+  }
+  const double nl = lam + dl;
+  return (nl >= lo && nl <= hi) ? nl : lam;
+}
+
 __global__ __launch_bounds__(TL_NT) void eigh_tridiag_lds(const EighProb* __restrict__ probs, int* status) {
   extern __shared__ double smem[];
   __shared__ double red[TL_NT / 64];
@@ -526,95 +622,14 @@ __global__ __launch_bounds__(TL_NT) void eigh_tridiag_lds(const EighProb* __rest
   __syncthreads();
 
   // 2. splitting, brackets, multisection down to TL_BISECT_TOL ||T||
-  double tn_loc = 0.0, e2_loc = 0.0;
-  for (int i = tid; i < n; i += TL_NT) {
-    const double el = i > 0 ? fabs(ve[i - 1]) : 0.0, er = i < n - 1 ? fabs(ve[i]) : 0.0;
-    tn_loc = fmax(tn_loc, fabs(vd[i]) + el + er);
-    if (i < n - 1) {
-      ve2[i] = ve[i] * ve[i];
-      e2_loc = fmax(e2_loc, ve2[i]);
-    }
-  }
-  const double tn = block_max<TL_NT>(tn_loc, red);
-  const double pivmin = DBL_MIN * fmax(1.0, block_max<TL_NT>(e2_loc, red));
-  const double eps = DBL_EPSILON, split = eps * tn;
-  if (tid < n) {
-    const int j = tid;
-    int b0 = j, b1 = j + 1;
-    while (b0 > 0 && fabs(ve[b0 - 1]) > split) --b0;
-    while (b1 < n && fabs(ve[b1 - 1]) > split) ++b1;
-    double gl = INFINITY, gu = -INFINITY;
-    for (int i = b0; i < b1; ++i) {
-      const double r = (i > b0 ? fabs(ve[i - 1]) : 0.0) + (i < b1 - 1 ? fabs(ve[i]) : 0.0);
-      gl = fmin(gl, vd[i] - r);
-      gu = fmax(gu, vd[i] + r);
-    }
-    const double margin = 8.0 * n * eps * tn + 4.0 * pivmin;
-    vlo[j] = gl - margin;
-    vhi[j] = gu + margin;
-    ib0[j] = b0;
-    ib1[j] = b1;
-  }
-  __syncthreads();
-  // T threads per eigenvalue, two points each
-  const int T = max(1, min(8, (TL_XS / 2) / n)), K = 2 * T;
-  for (int it = 0; it < TL_MAXIT; ++it) {
-    if (tid < n * T) {
-      const int j = tid / T, m = tid - j * T;
-      const double lo = vlo[j], hi = vhi[j], w = hi - lo;
-      const double x0 = lo + w * ((double)(2 * m + 1) / (double)(K + 1));
-      const double x1 = lo + w * ((double)(2 * m + 2) / (double)(K + 1));
-      int c0, c1;
-      tl_sturm2(vd, ve2, ib0[j], ib1[j], x0, x1, pivmin, c0, c1);
-      xs[2 * tid] = x0;
-      xs[2 * tid + 1] = x1;
-      cnt[2 * tid] = c0;
-      cnt[2 * tid + 1] = c1;
-    }
-    __syncthreads();
-    int more = 0;
-    if (tid < n) {
-      const int jl = tid - ib0[tid];
-      double lo = vlo[tid], hi = vhi[tid];
-      for (int m = 0; m < K; ++m) {
-        const double x = xs[tid * K + m];
-        if (cnt[tid * K + m] <= jl)
-          lo = fmax(lo, x);
-        else
-          hi = fmin(hi, x);
-      }
-      vlo[tid] = lo;
-      vhi[tid] = hi;
-      more = (hi - lo) > TL_BISECT_TOL * tn;
-    }
-    if (!__syncthreads_or(more)) break;
-  }
+  double tn, pivmin;
+  tl_eigen_brackets(vd, ve, ve2, vlo, vhi, xs, cnt, ib0, ib1, n, red, tn, pivmin);
+  const double eps = DBL_EPSILON;
 
   // 3. eigenvectors of T (column j of Z in R1, by thread j), with Rayleigh-quotient
   //    corrections of the eigenvalue from each twisted factorization; a correction
   //    that leaves the bracket is not taken
-  if (tid < n) {
-    const int j = tid, b0 = ib0[j], b1 = ib1[j];
-    for (int i = 0; i < b0; ++i) R1[i * n + j] = 0.0;
-    for (int i = b1; i < n; ++i) R1[i * n + j] = 0.0;
-    const double lo = vlo[j], hi = vhi[j];
-    double lam = 0.5 * (lo + hi);
-    if (b1 - b0 == 1) {
-      R1[b0 * n + j] = 1.0;
-      lam = vd[b0];
-    } else {
-      double dl = tl_twisted(vd, ve, ve2, b0, b1, lam, pivmin, R1, n, j);
-      for (int it = 0; it < TL_RQI_MAX && fabs(dl) > 2.0 * eps * tn; ++it) {
-        const double nl = lam + dl;
-        if (!(nl >= lo && nl <= hi)) break;
-        lam = nl;
-        dl = tl_twisted(vd, ve, ve2, b0, b1, lam, pivmin, R1, n, j);
-      }
-      const double nl = lam + dl;
-      if (nl >= lo && nl <= hi) lam = nl;
-    }
-    vlam[j] = lam;
-  }
+  if (tid < n) vlam[tid] = tl_vector(vd, ve, ve2, ib0[tid], ib1[tid], vlo[tid], vhi[tid], tn, pivmin, R1, n, tid);
   __syncthreads();
 
   // 4. X = Q Z = (Q^T)^T Z
@@ -694,7 +709,7 @@ __global__ __launch_bounds__(NT) void jacobi_complex(const EighProb* __restrict_
   __shared__ double red[NT / 64];
   const EighProb pr = probs[blockIdx.x];
   const int n = pr.n;
-  if (n <= 0) return;
+  if (n <= 0 || (pr.ok && *pr.ok)) return;
   const int nn = n + (n & 1), half = nn / 2;
   double* pc = smem;                              // [half]
   double2* pz = reinterpret_cast<double2*>(pc + half + (half & 1));  // [half]
@@ -783,6 +798,240 @@ __global__ __launch_bounds__(NT) void jacobi_complex(const EighProb* __restrict_
   if ((!converged || !finite) && threadIdx.x == 0) atomicOr(status, finite ? ST_EIGH : ST_NONFINITE);
 }
 
+
+// ---------------------------------------------------------------------------
+// complex Hermitian, n <= HT_MAX, one workgroup of 1024 threads per matrix, the
+// matrix in global memory (it stays in the L2 / last-level caches):
+//   1. Householder reduction A = Q T Q^H to a REAL symmetric tridiagonal T:
+//      the reflector H_k = I - tau v v^H (v_{k+1} = 1, tau complex) satisfies
+//      H_k^H [alpha; x] = [beta; 0] with beta real, so every off-diagonal element
+//      of T is real (the last step, on a single element, only makes it real) and
+//      the diagonal of a Hermitian matrix is real; A <- H^H A H as
+//      A - v w^H - w v^H with p = tau A v, w = p - (tau/2)(p^H v) v;
+//      Q^H accumulated (Q <- Q H_k);
+//   2./3. eigenvalues and eigenvectors Z (real) of T as in the real solver, with
+//      the residual max|T z - lambda z| checked per vector (-> *ok).
+// The eigenvectors V = Q Z are formed outside this kernel, after the
+// orthogonality check of Z (launch_herm_check) and one Newton-Schulz step.
+// ---------------------------------------------------------------------------
+constexpr int HT_NCH = 5;  // row chunks of the matrix-vector products
+
+static size_t ht_lds_bytes(int n) {
+  return sizeof(double) * (6 * (size_t)n + 6 * (size_t)n + 2 * HT_NCH * 2 * (size_t)n + TL_XS) +
+         sizeof(int) * (2 * (size_t)n + TL_XS);
+}
+
+__global__ __launch_bounds__(TL_NT) void eigh_herm_tridiag(const EighProb* __restrict__ probs, int* status) {
+  extern __shared__ double smem[];
+  __shared__ double red[TL_NT / 64];
+  __shared__ double s_tau[2][2];
+  const EighProb pr = probs[blockIdx.x];
+  const int n = pr.n;
+  if (n <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double2* A = reinterpret_cast<double2*>(pr.A);
+  double2* QH = reinterpret_cast<double2*>(pr.ws);  // n x n
+  double* Z = pr.V;                                  // n x n real, in the first half of V
+  double* vd = smem;
+  double* ve = vd + n;
+  double* ve2 = ve + n;
+  double* vlo = ve2 + n;
+  double* vhi = vlo + n;
+  double* vlam = vhi + n;
+  double2* vv = reinterpret_cast<double2*>(vlam + n);  // reflector
+  double2* vw = vv + n;                                 // w
+  double2* vu = vw + n;                                 // Q v
+  double2* Pm = vu + n;                                 // HT_NCH x 2n partial sums
+  double* xs = reinterpret_cast<double*>(Pm + HT_NCH * 2 * n);
+  int* ib0 = reinterpret_cast<int*>(xs + TL_XS);
+  int* ib1 = ib0 + n;
+  int* cnt = ib1 + n;
+
+  for (int e = tid; e < n * n; e += TL_NT) {
+    const int i = e / n;
+    QH[e] = make_double2(e == i * n + i ? 1.0 : 0.0, 0.0);
+  }
+  double fro = 0.0;
+  for (int e = tid; e < n * n; e += TL_NT) fro += A[e].x * A[e].x + A[e].y * A[e].y;
+  const double scale = sqrt(block_sum<TL_NT>(fro, red));
+  if (!isfinite(scale) || scale == 0.0 || n == 1) {
+    for (int i = tid; i < n; i += TL_NT) pr.w[i] = A[(size_t)i * n + i].x;
+    for (int e = tid; e < n * n; e += TL_NT) {
+      const int i = e / n;
+      Z[e] = e == i * n + i ? 1.0 : 0.0;
+    }
+    if (tid == 0) {
+      *pr.ok = 1;
+      if (!isfinite(scale)) atomicOr(status, ST_NONFINITE);
+    }
+    return;
+  }
+
+  for (int k = 0; k < n - 1; ++k) {
+    const int L = n - k - 1;
+    double* tau2 = s_tau[k & 1];  // two buffers: a step without update has one barrier only
+    if (wave == 0) {
+      // x_i = A[i][k] = conj(A[k][i]) for i in [k+1, n)
+      double ar = 0.0, ai = 0.0, s2 = 0.0;
+      for (int i = k + 1 + lane; i < n; i += 64) {
+        const double2 a = A[(size_t)k * n + i];
+        if (i == k + 1) {
+          ar = a.x;
+          ai = -a.y;
+        } else {
+          s2 += a.x * a.x + a.y * a.y;
+        }
+      }
+      s2 = tl_wave_sum(s2);
+      ar = tl_readlane(ar, 0);
+      ai = tl_readlane(ai, 0);
+      double taur = 0.0, taui = 0.0, beta = ar;
+      double2 inv = make_double2(0.0, 0.0);
+      if (s2 != 0.0 || ai != 0.0) {
+        beta = -copysign(sqrt(ar * ar + ai * ai + s2), ar);
+        taur = (beta - ar) / beta;
+        taui = -ai / beta;
+        const double dr = ar - beta, den = dr * dr + ai * ai;
+        inv = make_double2(dr / den, -ai / den);  // 1 / (alpha - beta)
+      }
+      for (int i = k + 1 + lane; i < n; i += 64) {
+        const double2 a = A[(size_t)k * n + i];
+        vv[i] = i == k + 1 ? make_double2(1.0, 0.0) : cmul(make_double2(a.x, -a.y), inv);
+      }
+      if (lane == 0) {
+        tau2[0] = taur;
+        tau2[1] = taui;
+        ve[k] = beta;
+        vd[k] = A[(size_t)k * n + k].x;
+      }
+    }
+    __syncthreads();
+    const double2 tau = make_double2(tau2[0], tau2[1]);
+    if (tau.x == 0.0 && tau.y == 0.0) continue;
+    // p = A_t v (trailing columns) and u = Q v (all rows), as sums over the rows j of
+    // A_t and Q^H of conj(row entry) * v_j: lanes over the outputs, wavefronts over
+    // segments of 64 outputs and row chunks
+    const int nout = L + n, nseg = (nout + 63) >> 6;
+    const int nch = max(1, min(HT_NCH, (TL_NT / 64) / nseg));
+    if (wave < nseg * nch) {
+      const int seg = wave % nseg, ch = wave / nseg;
+      const int o = 64 * seg + lane;
+      const int jb = ch * L / nch, je = (ch + 1) * L / nch;
+      if (o < nout) {
+        const double2* base = o < L ? A + (size_t)(k + 1) * n + (k + 1 + o) : QH + (size_t)(k + 1) * n + (o - L);
+        double2 acc0 = make_double2(0.0, 0.0), acc1 = acc0;
+        int jj = jb;
+        for (; jj + 1 < je; jj += 2) {
+          const double2 m0 = base[(size_t)jj * n], m1 = base[(size_t)(jj + 1) * n];
+          acc0 = cadd(acc0, cconjmul(m0, vv[k + 1 + jj]));
+          acc1 = cadd(acc1, cconjmul(m1, vv[k + 2 + jj]));
+        }
+        if (jj < je) acc0 = cadd(acc0, cconjmul(base[(size_t)jj * n], vv[k + 1 + jj]));
+        Pm[ch * 2 * n + o] = cadd(acc0, acc1);
+      }
+    }
+    __syncthreads();
+    if (wave == 0) {  // p = tau * sum, K = -(tau/2) p^H v, w = p + K v
+      double dr = 0.0, di = 0.0;
+      for (int i = lane; i < L; i += 64) {
+        double2 p = make_double2(0.0, 0.0);
+        for (int ch = 0; ch < nch; ++ch) p = cadd(p, Pm[ch * 2 * n + i]);
+        p = cmul(tau, p);
+        vw[k + 1 + i] = p;
+        const double2 t = cconjmul(p, vv[k + 1 + i]);
+        dr += t.x;
+        di += t.y;
+      }
+      dr = tl_wave_sum(dr);
+      di = tl_wave_sum(di);
+      const double2 K = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), make_double2(dr, di));
+      for (int i = lane; i < L; i += 64) vw[k + 1 + i] = cadd(vw[k + 1 + i], cmul(K, vv[k + 1 + i]));
+    } else if (wave == 1) {  // u = Q v
+      for (int r = lane; r < n; r += 64) {
+        double2 u = make_double2(0.0, 0.0);
+        for (int ch = 0; ch < nch; ++ch) u = cadd(u, Pm[ch * 2 * n + L + r]);
+        vu[r] = u;
+      }
+    }
+    __syncthreads();
+    // A_t -= v w^H + w v^H (diagonal kept real);  Q^H rows j: -= conj(tau) v_j conj(u)
+    {
+      const int sa = (L + 63) >> 6, sq = (n + 63) >> 6;
+      const int na = L * sa, nq = L * sq;
+      const double2 ctau = make_double2(tau.x, -tau.y);
+      for (int t = wave; t < na + nq; t += TL_NT / 64) {
+        if (t < na) {
+          const int ii = t / sa, sg = t - ii * sa;
+          const int i = k + 1 + ii, c = 64 * sg + lane, j = k + 1 + c;
+          if (c < L) {
+            const double2 vi = vv[i], wi = vw[i], vj = vv[j], wj = vw[j];
+            double2 a = A[(size_t)i * n + j];
+            a = csub(a, cadd(cmulc(vi, wj), cmulc(wi, vj)));
+            if (i == j) a.y = 0.0;
+            A[(size_t)i * n + j] = a;
+          }
+        } else {
+          const int t2 = t - na, jj = t2 / sq, sg = t2 - jj * sq;
+          const int j = k + 1 + jj, r = 64 * sg + lane;
+          if (r < n) {
+            const double2 f = cmul(ctau, vv[j]);
+            QH[(size_t)j * n + r] = csub(QH[(size_t)j * n + r], cmulc(f, vu[r]));
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) vd[n - 1] = A[(size_t)(n - 1) * n + n - 1].x;
+  __syncthreads();
+
+  double tn, pivmin;
+  tl_eigen_brackets(vd, ve, ve2, vlo, vhi, xs, cnt, ib0, ib1, n, red, tn, pivmin);
+  double res = 0.0;
+  for (int j = tid; j < n; j += TL_NT) {
+    const int b0 = ib0[j], b1 = ib1[j];
+    const double lam = tl_vector(vd, ve, ve2, b0, b1, vlo[j], vhi[j], tn, pivmin, Z, n, j);
+    pr.w[j] = lam;
+    for (int i = b0; i < b1; ++i) {
+      double t = (vd[i] - lam) * Z[(size_t)i * n + j];
+      if (i > b0) t += ve[i - 1] * Z[(size_t)(i - 1) * n + j];
+      if (i < b1 - 1) t += ve[i] * Z[(size_t)(i + 1) * n + j];
+      res = fmax(res, tl_err(fabs(t)));
+    }
+  }
+  res = block_max<TL_NT>(res, red);
+  if (tid == 0) *pr.ok = res <= TL_RES_MAX * scale ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void herm_check_kernel(const HermCheck* __restrict__ chk) {
+  const HermCheck c = chk[blockIdx.x];
+  const int n = c.n;
+  double m = 0.0;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int i = e / n;
+    const double g = c.G[e], dlt = (e == i * n + i) ? 1.0 : 0.0;
+    m = fmax(m, tl_err(fabs(g - dlt)));
+    c.G[e] = 1.5 * dlt - 0.5 * g;
+  }
+  __shared__ double red[4];
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (!(t <= TL_ORTH_MAX)) *c.ok = 0;
+  }
+}
+
+__global__ void real_to_complex_kernel(const RealToComplex* __restrict__ rc) {
+  const RealToComplex r = rc[blockIdx.y];
+  double2* dst = reinterpret_cast<double2*>(r.dst);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)r.n * r.n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = make_double2(r.src[e], 0.0);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -806,6 +1055,26 @@ void launch_eigh_complex(const EighProb* d_probs, int nprob, int nmax, int* d_st
   size_t bytes = (size_t)(half + 1) * sizeof(double) + (size_t)half * sizeof(double2) +
                  (size_t)half * 2 * sizeof(int);
   jacobi_complex<1024><<<nprob, 1024, bytes, s>>>(d_probs, d_status);
+}
+
+void launch_eigh_herm_tridiag(const EighProb* d_probs, int nprob, int nmax, int* d_status, hipStream_t s) {
+  if (nprob <= 0) return;
+  const size_t bytes = ht_lds_bytes(nmax);
+  static size_t attr = 0;
+  if (bytes > attr) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&eigh_herm_tridiag), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)bytes);
+    attr = bytes;
+  }
+  eigh_herm_tridiag<<<nprob, TL_NT, bytes, s>>>(d_probs, d_status);
+}
+
+void launch_herm_check(const HermCheck* d, int nprob, hipStream_t s) {
+  if (nprob > 0) herm_check_kernel<<<nprob, 256, 0, s>>>(d);
+}
+
+void launch_real_to_complex(const RealToComplex* d, int nprob, hipStream_t s) {
+  if (nprob > 0) real_to_complex_kernel<<<dim3(64, nprob), 256, 0, s>>>(d);
 }
 
 }  // namespace etdm

@@ -185,6 +185,13 @@ struct etdm_handle {
   ZInst* d_z = nullptr;
   EighProb *d_eig_lds = nullptr, *d_eig_glb = nullptr;
   int n_eig_lds = 0, n_eig_glb = 0, eig_nmax = 1;
+  // complex path: tridiagonal solver (M <= HT_MAX), its checks and back-transform
+  EighProb* d_eig_herm = nullptr;
+  HermCheck* d_hchk = nullptr;
+  RealToComplex* d_r2c = nullptr;
+  int n_eig_herm = 0, herm_nmax = 1;
+  int* herm_ok = nullptr;
+  Stage z_HG, z_HNS, z_HV;
   std::vector<EighLarge> eig_large;  // real problems above the LDS size
   const double** d_n0ptr = nullptr;
   double* d_wts = nullptr;
@@ -361,6 +368,7 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       }
     }
   } else {
+    h->herm_ok = reinterpret_cast<int*>(pl.take(h->n_inst / 2 + 1));
     h->zb.resize(h->n_inst);
     for (int i = 0; i < h->n_inst; ++i) {
       const int64_t M = h->M[i], MM2 = 2 * M * M;
@@ -580,8 +588,13 @@ etdm_status build_ov_plan(etdm_handle* h) {
 etdm_status build_z_plan(etdm_handle* h) {
   std::vector<ZInst> zi;
   std::vector<int> bmat, brows;
-  std::vector<EighProb> eg;
+  std::vector<EighProb> eg, eh;
+  std::vector<HermCheck> hchk;
+  std::vector<RealToComplex> r2c;
   std::vector<const double*> n0ptr;
+  h->z_HG.init(OP_T, OP_N, GP_FP64, false);
+  h->z_HNS.init(OP_N, OP_N, GP_FP64, false);
+  h->z_HV.init(OP_C, OP_N, GP_FP64, true);
   h->z_Ue.init(OP_N, OP_C, GP_FP64, true);
   h->z_C.init(OP_N, OP_N, GP_FP64, true);
   h->z_T.init(OP_N, OP_N, GP_FP64, true);
@@ -617,7 +630,19 @@ etdm_status build_z_plan(etdm_handle* h) {
     h->tot_mat += M * M;
     brows.push_back(h->tot_rows);
     h->tot_rows += M;
-    eg.push_back(EighProb{b.Hk, b.V, b.w, M, 0});
+    if (M <= HT_MAX) {
+      // tridiagonal solver; Z (real) in V, G and the Newton-Schulz factor in C,
+      // Z (3 I - G) / 2 in the second half of C, its complex copy in T, Q^H in Ue
+      eh.push_back(EighProb{b.Hk, b.V, b.w, M, 0, b.Ue, h->herm_ok + i});
+      hchk.push_back(HermCheck{b.C, h->herm_ok + i, M});
+      r2c.push_back(RealToComplex{b.C + (size_t)M * M, b.T, M});
+      h->z_HG.add(prob(M, M, M, b.V, M, b.V, M, b.C, M));
+      h->z_HNS.add(prob(M, M, M, b.V, M, b.C, M, b.C + (size_t)M * M, M));
+      h->z_HV.add(prob(M, M, M, b.Ue, M, b.T, M, b.V, M));
+      h->herm_nmax = std::max(h->herm_nmax, M);
+    }
+    // the Jacobi sweeps take the matrices the tridiagonal solver did not accept
+    eg.push_back(EighProb{b.Hk, b.V, b.w, M, 0, nullptr, M <= HT_MAX ? h->herm_ok + i : nullptr});
     n0ptr.push_back(b.n0);
     h->z_Ue.add(prob(M, M, M, b.Vp, M, b.V, M, b.Ue, M));    // exp(A) = (V e^{-iw}) V^H
     h->z_C.add(prob(M, M, M, b.C0, M, b.Ue, M, b.C, M));     // C = C0 exp(A)
@@ -631,6 +656,7 @@ etdm_status build_z_plan(etdm_handle* h) {
   }
   h->n_eig_glb = (int)eg.size();
   for (const EighProb& e : eg) h->eig_nmax = std::max(h->eig_nmax, e.n);
+  h->n_eig_herm = (int)eh.size();
   {
     h->timers.assign(Z_COUNT, StageTimer());
     for (int i = 0; i < Z_COUNT; ++i) h->timers[i].name = kZNames[i];
@@ -661,12 +687,18 @@ etdm_status build_z_plan(etdm_handle* h) {
       h->timers[Z_GRAD].bytes += 32.0 * M * M;
     }
   }
-  Stage* stages[] = {&h->z_Ue, &h->z_C, &h->z_T, &h->z_HMO, &h->z_LV, &h->z_Lt, &h->z_W1, &h->z_Y, &h->z_HC0};
+  Stage* stages[] = {&h->z_Ue, &h->z_C,   &h->z_T,  &h->z_HMO, &h->z_LV, &h->z_Lt,
+                     &h->z_W1, &h->z_Y,   &h->z_HC0, &h->z_HG, &h->z_HNS, &h->z_HV};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
   CHECK(upload(h, &h->d_z, zi));
   CHECK(upload(h, &h->b_mat, bmat));
   CHECK(upload(h, &h->b_rows, brows));
   CHECK(upload(h, &h->d_eig_glb, eg));
+  if (!eh.empty()) {
+    CHECK(upload(h, &h->d_eig_herm, eh));
+    CHECK(upload(h, &h->d_hchk, hchk));
+    CHECK(upload(h, &h->d_r2c, r2c));
+  }
   CHECK(upload(h, &h->d_n0ptr, n0ptr));
   CHECK(upload(h, &h->d_wts, h->w));
   return ETDM_OK;
@@ -775,7 +807,22 @@ void ov_new_reference(etdm_handle* h, hipStream_t s) {
 
 void z_exponential_part(etdm_handle* h, hipStream_t s) {
   { TIMED(Z_IA); launch_z_build_iA(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s); }
-  { TIMED(Z_EIG); launch_eigh_complex(h->d_eig_glb, h->n_eig_glb, h->eig_nmax, h->status, s); }
+  {
+    TIMED(Z_EIG);
+    if (h->n_eig_herm > 0) {
+      // tridiagonal solver, orthogonality check of Z, one Newton-Schulz step,
+      // V = (Q^H)^H Z; then iA is rebuilt (the reduction consumed it) for the Jacobi
+      // sweeps, which return at once on the accepted matrices
+      launch_eigh_herm_tridiag(h->d_eig_herm, h->n_eig_herm, h->herm_nmax, h->status, s);
+      h->z_HG.launch(s);
+      launch_herm_check(h->d_hchk, h->n_eig_herm, s);
+      h->z_HNS.launch(s);
+      launch_real_to_complex(h->d_r2c, h->n_eig_herm, s);
+      h->z_HV.launch(s);
+      launch_z_build_iA(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s);
+    }
+    launch_eigh_complex(h->d_eig_glb, h->n_eig_glb, h->eig_nmax, h->status, s);
+  }
   { TIMED(Z_PHASE); launch_z_phase(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s); }
   { TIMED(Z_UE); h->z_Ue.launch(s); }
 }

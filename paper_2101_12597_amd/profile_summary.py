@@ -1,17 +1,47 @@
-"""Summarize a rocprofv3 kernel-trace database (``*_results.db``) as text:
-kernel name, calls, total and average duration, share of GPU time."""
+"""Text summaries of rocprofv3 output for the profiles/ folder.
+
+  python -m paper_2101_12597_amd.profile_summary trace <dir>/kt_kernel_stats.csv [top]
+      kernel name, calls, total and average duration (microseconds), share of GPU time
+  python -m paper_2101_12597_amd.profile_summary pmc <dir>/p_counter_collection.csv [top]
+      per kernel: dispatches and the mean counter value per dispatch (KiB for
+      FETCH_SIZE / WRITE_SIZE)
+  python -m paper_2101_12597_amd.profile_summary db <dir>/<name>_results.db [top]
+      the same as "trace" for a rocpd SQLite database
+"""
+import collections
+import csv
 import sqlite3
 import sys
 
 
-def main(db, top=30):
-    cur = sqlite3.connect(db).cursor()
+def trace_csv(path, top=30):
+    rows = list(csv.DictReader(open(path)))
+    print(f"{'kernel':<100} {'calls':>6} {'total_us':>12} {'avg_us':>11} {'pct':>6}")
+    for r in rows[:top]:
+        print(f"{r['Name'][:100]:<100} {int(r['Calls']):>6} {float(r['TotalDurationNs']) / 1e3:>12.1f} "
+              f"{float(r['AverageNs']) / 1e3:>11.2f} {float(r['Percentage']):>6.2f}")
+
+
+def pmc_csv(path, top=30):
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        agg[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+    items = sorted(agg.items(), key=lambda kv: -sum(kv[1]))
+    print(f"{'kernel':<100} {'counter':<12} {'dispatches':>10} {'mean_per_dispatch':>18}")
+    for (name, counter), vals in items[:top]:
+        print(f"{name[:100]:<100} {counter:<12} {len(vals):>10} {sum(vals) / len(vals):>18.1f}")
+
+
+def trace_db(path, top=30):
+    cur = sqlite3.connect(path).cursor()
     rows = list(cur.execute("select name, total_calls, total_duration, average, percentage "
                             "from top_kernels order by total_duration desc"))
-    print(f"{'kernel':<100} {'calls':>6} {'total_us':>11} {'avg_us':>10} {'pct':>6}")
+    print(f"{'kernel':<100} {'calls':>6} {'total_us':>12} {'avg_us':>11} {'pct':>6}")
     for name, calls, tot, avg, pct in rows[:top]:
-        print(f"{name[:100]:<100} {calls:>6} {tot:>11.1f} {avg:>10.2f} {pct:>6.2f}")
+        print(f"{name[:100]:<100} {calls:>6} {tot:>12.1f} {avg:>11.2f} {pct:>6.2f}")
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 30)
+    mode, path = sys.argv[1], sys.argv[2]
+    top = int(sys.argv[3]) if len(sys.argv) > 3 else 30
+    {"trace": trace_csv, "pmc": pmc_csv, "db": trace_db}[mode](path, top)
