@@ -62,8 +62,17 @@ void launch_eigh_complex(const EighProb* d_probs, int nprob, int nmax, int* d_st
 
 // Complex Hermitian eigensolver by reduction to real tridiagonal form (n <= HT_MAX),
 // one workgroup per matrix: writes the eigenvalues, the real eigenvectors Z of T
-// into the first n*n doubles of V, Q^H into ws and the acceptance flag *ok.
+// into the first n*n doubles of V, the reflectors into ws (n x n complex: v_k in
+// column k, tau_k at [k][n-1]) and the acceptance flag *ok.
 constexpr int HT_MAX = 512;
+constexpr int HT_NB = 32;  // reflectors per compact-WY block of the back-transform
+struct HermWY {
+  const double* Y;  // reflectors (as written by the solver)
+  double* T;        // ceil((n-1)/HT_NB) blocks of HT_NB x HT_NB complex
+  int n;
+};
+// T factors of all blocks (grid: instances x blocks).
+void launch_herm_wy_t(const HermWY* d, int nprob, int nblk, hipStream_t s);
 void launch_eigh_herm_tridiag(const EighProb* d_probs, int nprob, int nmax, int* d_status, hipStream_t s);
 // After G = Z^T Z: *ok &= max|G - I| <= 1e-6, and G <- (3 I - G) / 2 in place.
 struct HermCheck {

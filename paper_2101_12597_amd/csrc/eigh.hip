@@ -807,17 +807,19 @@ __global__ __launch_bounds__(NT) void jacobi_complex(const EighProb* __restrict_
 //      H_k^H [alpha; x] = [beta; 0] with beta real, so every off-diagonal element
 //      of T is real (the last step, on a single element, only makes it real) and
 //      the diagonal of a Hermitian matrix is real; A <- H^H A H as
-//      A - v w^H - w v^H with p = tau A v, w = p - (tau/2)(p^H v) v;
-//      Q^H accumulated (Q <- Q H_k);
+//      A - v w^H - w v^H with p = tau A v, w = p - (tau/2)(p^H v) v.  The
+//      reflectors are kept: v_k in column k of Y (rows k+1..n-1, zero above), tau_k
+//      in Y[k][n-1] (column n-1 holds no reflector);
 //   2./3. eigenvalues and eigenvectors Z (real) of T as in the real solver, with
 //      the residual max|T z - lambda z| checked per vector (-> *ok).
-// The eigenvectors V = Q Z are formed outside this kernel, after the
-// orthogonality check of Z (launch_herm_check) and one Newton-Schulz step.
+// Outside this kernel: the orthogonality check of Z and one Newton-Schulz step,
+// then V = Q Z with Q applied in blocks of HT_NB reflectors in compact WY form
+// (Q_b = I - Y_b T_b Y_b^H; herm_wy_t_kernel forms T_b) on the matrix cores.
 // ---------------------------------------------------------------------------
-constexpr int HT_NCH = 5;  // row chunks of the matrix-vector products
+constexpr int HT_NCH = 5;  // row chunks of the matrix-vector product
 
 static size_t ht_lds_bytes(int n) {
-  return sizeof(double) * (6 * (size_t)n + 6 * (size_t)n + 2 * HT_NCH * 2 * (size_t)n + TL_XS) +
+  return sizeof(double) * (6 * (size_t)n + 4 * (size_t)n + 2 * HT_NCH * (size_t)n + TL_XS) +
          sizeof(int) * (2 * (size_t)n + TL_XS);
 }
 
@@ -831,8 +833,8 @@ __global__ __launch_bounds__(TL_NT) void eigh_herm_tridiag(const EighProb* __res
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   double2* A = reinterpret_cast<double2*>(pr.A);
-  double2* QH = reinterpret_cast<double2*>(pr.ws);  // n x n
-  double* Z = pr.V;                                  // n x n real, in the first half of V
+  double2* Y = reinterpret_cast<double2*>(pr.ws);  // n x n reflectors
+  double* Z = pr.V;                                 // n x n real, in the first half of V
   double* vd = smem;
   double* ve = vd + n;
   double* ve2 = ve + n;
@@ -841,21 +843,17 @@ __global__ __launch_bounds__(TL_NT) void eigh_herm_tridiag(const EighProb* __res
   double* vlam = vhi + n;
   double2* vv = reinterpret_cast<double2*>(vlam + n);  // reflector
   double2* vw = vv + n;                                 // w
-  double2* vu = vw + n;                                 // Q v
-  double2* Pm = vu + n;                                 // HT_NCH x 2n partial sums
-  double* xs = reinterpret_cast<double*>(Pm + HT_NCH * 2 * n);
+  double2* Pm = vw + n;                                 // HT_NCH x n partial sums
+  double* xs = reinterpret_cast<double*>(Pm + HT_NCH * n);
   int* ib0 = reinterpret_cast<int*>(xs + TL_XS);
   int* ib1 = ib0 + n;
   int* cnt = ib1 + n;
 
-  for (int e = tid; e < n * n; e += TL_NT) {
-    const int i = e / n;
-    QH[e] = make_double2(e == i * n + i ? 1.0 : 0.0, 0.0);
-  }
+  for (int e = tid; e < n * n; e += TL_NT) Y[e] = make_double2(0.0, 0.0);
   double fro = 0.0;
   for (int e = tid; e < n * n; e += TL_NT) fro += A[e].x * A[e].x + A[e].y * A[e].y;
   const double scale = sqrt(block_sum<TL_NT>(fro, red));
-  if (!isfinite(scale) || scale == 0.0 || n == 1) {
+  if (!isfinite(scale) || scale == 0.0 || n == 1) {  // T = diag(A), Q = I (all tau = 0)
     for (int i = tid; i < n; i += TL_NT) pr.w[i] = A[(size_t)i * n + i].x;
     for (int e = tid; e < n * n; e += TL_NT) {
       const int i = e / n;
@@ -897,11 +895,14 @@ __global__ __launch_bounds__(TL_NT) void eigh_herm_tridiag(const EighProb* __res
       }
       for (int i = k + 1 + lane; i < n; i += 64) {
         const double2 a = A[(size_t)k * n + i];
-        vv[i] = i == k + 1 ? make_double2(1.0, 0.0) : cmul(make_double2(a.x, -a.y), inv);
+        const double2 v = i == k + 1 ? make_double2(1.0, 0.0) : cmul(make_double2(a.x, -a.y), inv);
+        vv[i] = v;
+        Y[(size_t)i * n + k] = v;
       }
       if (lane == 0) {
         tau2[0] = taur;
         tau2[1] = taui;
+        Y[(size_t)k * n + (n - 1)] = make_double2(taur, taui);
         ve[k] = beta;
         vd[k] = A[(size_t)k * n + k].x;
       }
@@ -909,17 +910,16 @@ __global__ __launch_bounds__(TL_NT) void eigh_herm_tridiag(const EighProb* __res
     __syncthreads();
     const double2 tau = make_double2(tau2[0], tau2[1]);
     if (tau.x == 0.0 && tau.y == 0.0) continue;
-    // p = A_t v (trailing columns) and u = Q v (all rows), as sums over the rows j of
-    // A_t and Q^H of conj(row entry) * v_j: lanes over the outputs, wavefronts over
-    // segments of 64 outputs and row chunks
-    const int nout = L + n, nseg = (nout + 63) >> 6;
+    // p = A_t v as sums over the rows j of A_t of conj(A[j][o]) v_j: lanes over the
+    // columns o, wavefronts over segments of 64 columns and row chunks
+    const int nseg = (L + 63) >> 6;
     const int nch = max(1, min(HT_NCH, (TL_NT / 64) / nseg));
     if (wave < nseg * nch) {
       const int seg = wave % nseg, ch = wave / nseg;
       const int o = 64 * seg + lane;
       const int jb = ch * L / nch, je = (ch + 1) * L / nch;
-      if (o < nout) {
-        const double2* base = o < L ? A + (size_t)(k + 1) * n + (k + 1 + o) : QH + (size_t)(k + 1) * n + (o - L);
+      if (o < L) {
+        const double2* base = A + (size_t)(k + 1) * n + (k + 1 + o);
         double2 acc0 = make_double2(0.0, 0.0), acc1 = acc0;
         int jj = jb;
         for (; jj + 1 < je; jj += 2) {
@@ -928,7 +928,7 @@ __global__ __launch_bounds__(TL_NT) void eigh_herm_tridiag(const EighProb* __res
           acc1 = cadd(acc1, cconjmul(m1, vv[k + 2 + jj]));
         }
         if (jj < je) acc0 = cadd(acc0, cconjmul(base[(size_t)jj * n], vv[k + 1 + jj]));
-        Pm[ch * 2 * n + o] = cadd(acc0, acc1);
+        Pm[ch * n + o] = cadd(acc0, acc1);
       }
     }
     __syncthreads();
@@ -936,7 +936,7 @@ __global__ __launch_bounds__(TL_NT) void eigh_herm_tridiag(const EighProb* __res
       double dr = 0.0, di = 0.0;
       for (int i = lane; i < L; i += 64) {
         double2 p = make_double2(0.0, 0.0);
-        for (int ch = 0; ch < nch; ++ch) p = cadd(p, Pm[ch * 2 * n + i]);
+        for (int ch = 0; ch < nch; ++ch) p = cadd(p, Pm[ch * n + i]);
         p = cmul(tau, p);
         vw[k + 1 + i] = p;
         const double2 t = cconjmul(p, vv[k + 1 + i]);
@@ -947,37 +947,20 @@ __global__ __launch_bounds__(TL_NT) void eigh_herm_tridiag(const EighProb* __res
       di = tl_wave_sum(di);
       const double2 K = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), make_double2(dr, di));
       for (int i = lane; i < L; i += 64) vw[k + 1 + i] = cadd(vw[k + 1 + i], cmul(K, vv[k + 1 + i]));
-    } else if (wave == 1) {  // u = Q v
-      for (int r = lane; r < n; r += 64) {
-        double2 u = make_double2(0.0, 0.0);
-        for (int ch = 0; ch < nch; ++ch) u = cadd(u, Pm[ch * 2 * n + L + r]);
-        vu[r] = u;
-      }
     }
     __syncthreads();
-    // A_t -= v w^H + w v^H (diagonal kept real);  Q^H rows j: -= conj(tau) v_j conj(u)
+    // A_t -= v w^H + w v^H (diagonal kept real); one row segment of 64 columns per item
     {
-      const int sa = (L + 63) >> 6, sq = (n + 63) >> 6;
-      const int na = L * sa, nq = L * sq;
-      const double2 ctau = make_double2(tau.x, -tau.y);
-      for (int t = wave; t < na + nq; t += TL_NT / 64) {
-        if (t < na) {
-          const int ii = t / sa, sg = t - ii * sa;
-          const int i = k + 1 + ii, c = 64 * sg + lane, j = k + 1 + c;
-          if (c < L) {
-            const double2 vi = vv[i], wi = vw[i], vj = vv[j], wj = vw[j];
-            double2 a = A[(size_t)i * n + j];
-            a = csub(a, cadd(cmulc(vi, wj), cmulc(wi, vj)));
-            if (i == j) a.y = 0.0;
-            A[(size_t)i * n + j] = a;
-          }
-        } else {
-          const int t2 = t - na, jj = t2 / sq, sg = t2 - jj * sq;
-          const int j = k + 1 + jj, r = 64 * sg + lane;
-          if (r < n) {
-            const double2 f = cmul(ctau, vv[j]);
-            QH[(size_t)j * n + r] = csub(QH[(size_t)j * n + r], cmulc(f, vu[r]));
-          }
+      const int sa = (L + 63) >> 6, na = L * sa;
+      for (int t = wave; t < na; t += TL_NT / 64) {
+        const int ii = t / sa, sg = t - ii * sa;
+        const int i = k + 1 + ii, c = 64 * sg + lane, j = k + 1 + c;
+        if (c < L) {
+          const double2 vi = vv[i], wi = vw[i], vj = vv[j], wj = vw[j];
+          double2 a = A[(size_t)i * n + j];
+          a = csub(a, cadd(cmulc(vi, wj), cmulc(wi, vj)));
+          if (i == j) a.y = 0.0;
+          A[(size_t)i * n + j] = a;
         }
       }
     }
@@ -1002,6 +985,45 @@ __global__ __launch_bounds__(TL_NT) void eigh_herm_tridiag(const EighProb* __res
   }
   res = block_max<TL_NT>(res, red);
   if (tid == 0) *pr.ok = res <= TL_RES_MAX * scale ? 1 : 0;
+}
+
+// T_b of the compact WY form Q_b = H_k0 ... H_(k0+m-1) = I - Y_b T_b Y_b^H (upper
+// triangular, columnwise forward recurrence T[:c, c] = T[:c, :c] (-tau_c Y_b^H y_c))
+// for block blockIdx.y of instance blockIdx.x; workgroup of 256 threads.
+__global__ __launch_bounds__(256) void herm_wy_t_kernel(const HermWY* __restrict__ wy) {
+  const HermWY w = wy[blockIdx.x];
+  const int n = w.n, k0 = blockIdx.y * HT_NB;
+  if (k0 >= n - 1) return;
+  const int m = min(HT_NB, n - 1 - k0);
+  const double2* Y = reinterpret_cast<const double2*>(w.Y);
+  double2* Tb = reinterpret_cast<double2*>(w.T) + (size_t)blockIdx.y * HT_NB * HT_NB;
+  __shared__ double2 g[HT_NB][HT_NB + 1];
+  __shared__ double2 T[HT_NB][HT_NB + 1];
+  __shared__ double2 col[HT_NB];
+  for (int q = threadIdx.x; q < HT_NB * HT_NB; q += 256) {
+    const int r = q / HT_NB, c = q - r * HT_NB;
+    double2 acc = make_double2(0.0, 0.0);
+    if (r < c && c < m)  // rows above k0 + r + 1 of column k0 + r are zero
+      for (int i = k0 + 1 + r; i < n; ++i)
+        acc = cadd(acc, cconjmul(Y[(size_t)i * n + k0 + r], Y[(size_t)i * n + k0 + c]));
+    g[r][c] = acc;
+    T[r][c] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int c = 0; c < m; ++c) {
+    const double2 tau = Y[(size_t)(k0 + c) * n + (n - 1)];
+    const int r = threadIdx.x;
+    if (r < c) col[r] = cmul(make_double2(-tau.x, -tau.y), g[r][c]);
+    __syncthreads();
+    if (r < c) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int q = r; q < c; ++q) acc = cadd(acc, cmul(T[r][q], col[q]));
+      T[r][c] = acc;
+    }
+    if (r == c) T[c][c] = tau;
+    __syncthreads();
+  }
+  for (int q = threadIdx.x; q < HT_NB * HT_NB; q += 256) Tb[q] = T[q / HT_NB][q % HT_NB];
 }
 
 __global__ __launch_bounds__(256) void herm_check_kernel(const HermCheck* __restrict__ chk) {
@@ -1071,6 +1093,10 @@ void launch_eigh_herm_tridiag(const EighProb* d_probs, int nprob, int nmax, int*
 
 void launch_herm_check(const HermCheck* d, int nprob, hipStream_t s) {
   if (nprob > 0) herm_check_kernel<<<nprob, 256, 0, s>>>(d);
+}
+
+void launch_herm_wy_t(const HermWY* d, int nprob, int nblk, hipStream_t s) {
+  if (nprob > 0 && nblk > 0) herm_wy_t_kernel<<<dim3(nprob, nblk), 256, 0, s>>>(d);
 }
 
 void launch_real_to_complex(const RealToComplex* d, int nprob, hipStream_t s) {

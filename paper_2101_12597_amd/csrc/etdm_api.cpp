@@ -129,6 +129,7 @@ struct OvBuf {
 };
 
 struct ZBuf {
+  double *wyT, *wyW;  // compact-WY factors and scratch of the tridiagonal eigensolver
   double *C0, *H0, *f, *A, *G;
   double *Hk, *V, *w, *Vp, *Ue, *C, *T, *d, *e, *L, *LV, *W1, *Y;
   double *n0, *eps;
@@ -189,9 +190,11 @@ struct etdm_handle {
   EighProb* d_eig_herm = nullptr;
   HermCheck* d_hchk = nullptr;
   RealToComplex* d_r2c = nullptr;
-  int n_eig_herm = 0, herm_nmax = 1;
+  HermWY* d_hwy = nullptr;
+  int n_eig_herm = 0, herm_nmax = 1, herm_nblk = 0;
   int* herm_ok = nullptr;
-  Stage z_HG, z_HNS, z_HV;
+  Stage z_HG, z_HNS;
+  std::vector<Stage> z_WY1, z_WY2, z_WY3;  // per block of reflectors: W1 = Y^H V, W2 = T W1, V -= Y W2
   std::vector<EighLarge> eig_large;  // real problems above the LDS size
   const double** d_n0ptr = nullptr;
   double* d_wts = nullptr;
@@ -393,6 +396,9 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       b.Y = pl.take(MM2);
       b.n0 = pl.take(M);
       b.eps = pl.take(M);
+      const int64_t nblk = M <= HT_MAX ? (M - 1 + HT_NB - 1) / HT_NB : 0;
+      b.wyT = pl.take(2 * nblk * HT_NB * HT_NB);
+      b.wyW = pl.take(M <= HT_MAX ? 2 * 2 * HT_NB * M : 0);
     }
   }
   const int64_t np = h->n_param;
@@ -591,10 +597,10 @@ etdm_status build_z_plan(etdm_handle* h) {
   std::vector<EighProb> eg, eh;
   std::vector<HermCheck> hchk;
   std::vector<RealToComplex> r2c;
+  std::vector<HermWY> hwy;
   std::vector<const double*> n0ptr;
   h->z_HG.init(OP_T, OP_N, GP_FP64, false);
   h->z_HNS.init(OP_N, OP_N, GP_FP64, false);
-  h->z_HV.init(OP_C, OP_N, GP_FP64, true);
   h->z_Ue.init(OP_N, OP_C, GP_FP64, true);
   h->z_C.init(OP_N, OP_N, GP_FP64, true);
   h->z_T.init(OP_N, OP_N, GP_FP64, true);
@@ -631,15 +637,37 @@ etdm_status build_z_plan(etdm_handle* h) {
     brows.push_back(h->tot_rows);
     h->tot_rows += M;
     if (M <= HT_MAX) {
-      // tridiagonal solver; Z (real) in V, G and the Newton-Schulz factor in C,
-      // Z (3 I - G) / 2 in the second half of C, its complex copy in T, Q^H in Ue
+      // tridiagonal solver: reflectors in Ue, Z (real) in V, G and the Newton-Schulz
+      // factor in C, Z (3 I - G) / 2 in the second half of C, its complex copy in V,
+      // then V <- Q_b V for the blocks of reflectors, last block first
       eh.push_back(EighProb{b.Hk, b.V, b.w, M, 0, b.Ue, h->herm_ok + i});
       hchk.push_back(HermCheck{b.C, h->herm_ok + i, M});
-      r2c.push_back(RealToComplex{b.C + (size_t)M * M, b.T, M});
+      r2c.push_back(RealToComplex{b.C + (size_t)M * M, b.V, M});
+      hwy.push_back(HermWY{b.Ue, b.wyT, M});
       h->z_HG.add(prob(M, M, M, b.V, M, b.V, M, b.C, M));
       h->z_HNS.add(prob(M, M, M, b.V, M, b.C, M, b.C + (size_t)M * M, M));
-      h->z_HV.add(prob(M, M, M, b.Ue, M, b.T, M, b.V, M));
       h->herm_nmax = std::max(h->herm_nmax, M);
+      const int nblk = (M - 1 + HT_NB - 1) / HT_NB;
+      h->herm_nblk = std::max(h->herm_nblk, nblk);
+      if ((int)h->z_WY1.size() < nblk) {
+        h->z_WY1.resize(nblk);
+        h->z_WY2.resize(nblk);
+        h->z_WY3.resize(nblk);
+      }
+      double* W1 = b.wyW;
+      double* W2 = b.wyW + 2 * (size_t)HT_NB * M;
+      for (int bk = 0; bk < nblk; ++bk) {
+        const int k0 = bk * HT_NB, mb = std::min(HT_NB, M - 1 - k0), R = M - 1 - k0;
+        const double* Yb = b.Ue + 2 * ((size_t)(k0 + 1) * M + k0);  // rows k0+1.., columns k0..
+        double* Vr = b.V + 2 * (size_t)(k0 + 1) * M;                 // rows k0+1..
+        h->z_WY1[bk].add(prob(mb, M, R, Yb, M, Vr, M, W1, M));
+        h->z_WY2[bk].add(prob(mb, M, mb, b.wyT + 2 * (size_t)bk * HT_NB * HT_NB, HT_NB, W1, M, W2, M));
+        GemmProb up = prob(R, M, mb, Yb, M, W2, M, Vr, M, -1.0);
+        up.beta = 1.0;
+        up.D = Vr;
+        up.ldd = M;
+        h->z_WY3[bk].add(up);
+      }
     }
     // the Jacobi sweeps take the matrices the tridiagonal solver did not accept
     eg.push_back(EighProb{b.Hk, b.V, b.w, M, 0, nullptr, M <= HT_MAX ? h->herm_ok + i : nullptr});
@@ -687,9 +715,17 @@ etdm_status build_z_plan(etdm_handle* h) {
       h->timers[Z_GRAD].bytes += 32.0 * M * M;
     }
   }
-  Stage* stages[] = {&h->z_Ue, &h->z_C,   &h->z_T,  &h->z_HMO, &h->z_LV, &h->z_Lt,
-                     &h->z_W1, &h->z_Y,   &h->z_HC0, &h->z_HG, &h->z_HNS, &h->z_HV};
+  Stage* stages[] = {&h->z_Ue, &h->z_C, &h->z_T,   &h->z_HMO, &h->z_LV,
+                     &h->z_Lt, &h->z_W1, &h->z_Y, &h->z_HC0, &h->z_HG, &h->z_HNS};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
+  for (int bk = 0; bk < h->herm_nblk; ++bk) {
+    h->z_WY1[bk].init(OP_C, OP_N, GP_FP64, true);
+    h->z_WY2[bk].init(OP_N, OP_N, GP_FP64, true);
+    h->z_WY3[bk].init(OP_N, OP_N, GP_FP64, true);
+    CHECK(upload_stage(h, h->z_WY1[bk]));
+    CHECK(upload_stage(h, h->z_WY2[bk]));
+    CHECK(upload_stage(h, h->z_WY3[bk]));
+  }
   CHECK(upload(h, &h->d_z, zi));
   CHECK(upload(h, &h->b_mat, bmat));
   CHECK(upload(h, &h->b_rows, brows));
@@ -698,6 +734,7 @@ etdm_status build_z_plan(etdm_handle* h) {
     CHECK(upload(h, &h->d_eig_herm, eh));
     CHECK(upload(h, &h->d_hchk, hchk));
     CHECK(upload(h, &h->d_r2c, r2c));
+    CHECK(upload(h, &h->d_hwy, hwy));
   }
   CHECK(upload(h, &h->d_n0ptr, n0ptr));
   CHECK(upload(h, &h->d_wts, h->w));
@@ -811,14 +848,19 @@ void z_exponential_part(etdm_handle* h, hipStream_t s) {
     TIMED(Z_EIG);
     if (h->n_eig_herm > 0) {
       // tridiagonal solver, orthogonality check of Z, one Newton-Schulz step,
-      // V = (Q^H)^H Z; then iA is rebuilt (the reduction consumed it) for the Jacobi
+      // V = Q Z in compact-WY blocks; then iA is rebuilt (the reduction consumed it) for the Jacobi
       // sweeps, which return at once on the accepted matrices
       launch_eigh_herm_tridiag(h->d_eig_herm, h->n_eig_herm, h->herm_nmax, h->status, s);
       h->z_HG.launch(s);
       launch_herm_check(h->d_hchk, h->n_eig_herm, s);
       h->z_HNS.launch(s);
       launch_real_to_complex(h->d_r2c, h->n_eig_herm, s);
-      h->z_HV.launch(s);
+      launch_herm_wy_t(h->d_hwy, h->n_eig_herm, h->herm_nblk, s);
+      for (int bk = h->herm_nblk - 1; bk >= 0; --bk) {
+        h->z_WY1[bk].launch(s);
+        h->z_WY2[bk].launch(s);
+        h->z_WY3[bk].launch(s);
+      }
       launch_z_build_iA(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s);
     }
     launch_eigh_complex(h->d_eig_glb, h->n_eig_glb, h->eig_nmax, h->status, s);
