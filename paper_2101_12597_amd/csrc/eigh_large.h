@@ -25,10 +25,37 @@ struct EighLarge {
   double* partial;  // reduction scratch (256 doubles)
   EighLargeState* st;
   int n, npad, nb;
+  // reduction to tridiagonal form, tried first (the Jacobi sweeps are its fallback);
+  // it reuses Aw (work matrix, ld n; later Z^T Z) and Vw (reflectors, ld n: v_k in
+  // column k below row k, tau_k at [k][n-1])
+  double* Zw;       // n x n eigenvectors of T
+  double* Ps;       // n x n symmetric part of P (for the final residual check)
+  double* d;        // n: diagonal of T
+  double* e;        // n: off-diagonal of T
+  double* pv;       // 2 x n: tau A v of a step (two buffers by step parity)
+  double* rowbuf;   // 2 x n: look-ahead rows (two buffers by parity)
+  double* W1;       // TB_NBW x n compact-WY scratch
+  double* W2;       // TB_NBW x n
+  double* Tw;       // ceil((n-1)/TB_NBW) blocks of TB_NBW x TB_NBW compact-WY factors
+  unsigned* bar;    // grid barrier words: [0] top arrivals, [1] generation, [2] abort, group counters
+  int* ok;          // 1 when the tridiagonal result passed its checks
+  int grid;         // workgroups of the reduction (one per CU, all resident)
 };
 
-// float64 elements of workspace for size n (Aw, Vw, Qb, partial); npad returned.
+constexpr int TB_NBW = 64;  // reflectors per compact-WY block of the back-transform
+
+// float64 elements of workspace for size n; npad returned.
 size_t eigh_large_workspace(int n, size_t* npad_out);
+// Point the members of e at the workspace ws (n set; grid from the CU count).
+void eigh_large_layout(EighLarge& e, double* ws, EighLargeState* st, int cu_count);
+// Tridiagonal path, part 1: reduction (cooperative), eigenpairs of T (Zw, w) and
+// their residual check.  Part 2 (orthogonality check, one Newton-Schulz step into
+// X, compact-WY back-transform of X) is launched by the caller with grouped GEMMs;
+// launch_tb_wy_t forms the T factors.
+void launch_tb_solve(const EighLarge& e, int* status, hipStream_t s);
+void launch_tb_wy_t(const EighLarge& e, hipStream_t s);
+// After R = sym(P) X has been formed in Aw: *ok = 0 unless max|R - X diag(w)| <= 1e-11 ||sym(P)||_F.
+void launch_tb_final_check(const EighLarge& e, hipStream_t s);
 // Launch the whole solve on stream s.  With check_host the host reads the
 // convergence flag after every sweep and stops launching early (not usable
 // under graph capture); otherwise all max_sweeps sweeps are launched and the

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include "eigh_large.h"
+#include "tridiag.h"
 
 namespace etdm {
 
@@ -87,6 +88,11 @@ constexpr int PREP_BLOCKS = 256;
 
 __global__ void bjl_start(EighLarge e, const double* partial) {
   if (threadIdx.x != 0) return;
+  if (e.ok && *e.ok) {  // the tridiagonal path already produced X and w
+    e.st->done = 1;
+    e.st->finite = 1;
+    return;
+  }
   double t = 0.0;
   for (int b = 0; b < PREP_BLOCKS; ++b) t += partial[b];
   const double scale = sqrt(t);
@@ -278,6 +284,7 @@ __global__ void bjl_sweep_end(EighLarge e, int max_sweeps, int* status) {
 }
 
 __global__ void bjl_finish(EighLarge e, int* status) {
+  if (e.ok && *e.ok) return;
   const int n = e.n, npad = e.npad;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)n * n;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -288,11 +295,477 @@ __global__ void bjl_finish(EighLarge e, int* status) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && !e.st->finite) atomicOr(status, ST_NONFINITE);
 }
 
+// ---------------------------------------------------------------------------
+// Reduction to tridiagonal form by all CUs together (tried before the Jacobi
+// sweeps).  Workgroup g owns rows g, g + G, ... of the work matrix A (G
+// workgroups, one per CU, all resident).  Step k applies reflector k
+// (H = I - tau v v^T, v_{k+1} = 1) as A_t <- A_t - v w^T - w v^T with p = tau A_t v
+// and w = p - (tau/2)(p.v) v, and at the same time forms p for step k + 1:
+//   after the grid barrier every workgroup has p_k (global), forms w_k, and
+//   updates its copy of row k + 1 (kept by the row's owner in a look-ahead buffer
+//   before the owner changes it) -> reflector k + 1, computed identically by every
+//   workgroup; then each owner updates its rows i >= k + 2 (columns >= k + 2) and
+//   in the same pass accumulates p_{k+1,i} = tau_{k+1} sum_j a_ij v_{k+1,j}.
+// One grid barrier per step; A is read and written once per step.  The barrier
+// waits are bounded: a wait longer than TB_SPIN sets the abort word, every
+// workgroup leaves, *ok stays 0 and the Jacobi sweeps take over.
+// ---------------------------------------------------------------------------
+constexpr int TB_NT = 256;      // threads of the reduction
+constexpr int TB_RMAX = 2;      // own rows per pass (all their loads issued before any store)
+constexpr int TB_CMAX = 10;     // columns per thread and row and chunk (TB_NT * TB_CMAX columns per chunk)
+constexpr int TB_GRP = 16;      // workgroups per first-level barrier counter
+constexpr int TB_BAR_WORDS = 64 + 32 * 64;  // barrier words (group counters 128 bytes apart)
+constexpr unsigned long long TB_SPIN = 20000000ull;  // 0.2 s of the 100 MHz wall clock
+constexpr int TE_CH = 16;       // eigenvalues per workgroup in the eigenpair kernel
+constexpr int TE_NT = 1024;
+
 size_t eigh_large_workspace(int n, size_t* npad_out) {
   const size_t npad = (size_t)((n + SUB - 1) / SUB) * SUB;
   if (npad_out) *npad_out = npad;
   const size_t half = npad / BLK / 2;
-  return 2 * npad * npad + half * SUB * SUB + PREP_BLOCKS;
+  const size_t nblk = (size_t)(n - 1 + TB_NBW - 1) / TB_NBW;
+  return 2 * npad * npad + half * SUB * SUB + PREP_BLOCKS + 2 * (size_t)n * n + 6 * (size_t)n +
+         2 * (size_t)TB_NBW * n + nblk * TB_NBW * TB_NBW + TB_BAR_WORDS / 2 + 2;
+}
+
+void eigh_large_layout(EighLarge& e, double* ws, EighLargeState* st, int cu_count) {
+  size_t npad = 0;
+  eigh_large_workspace(e.n, &npad);
+  const int n = e.n;
+  e.npad = (int)npad;
+  e.nb = (int)npad / BLK;
+  e.Aw = ws;
+  e.Vw = e.Aw + npad * npad;
+  e.Qb = e.Vw + npad * npad;
+  e.partial = e.Qb + (size_t)(e.nb / 2) * SUB * SUB;
+  e.Zw = e.partial + PREP_BLOCKS;
+  e.Ps = e.Zw + (size_t)n * n;
+  e.d = e.Ps + (size_t)n * n;
+  e.e = e.d + n;
+  e.pv = e.e + n;
+  e.rowbuf = e.pv + 2 * n;
+  e.W1 = e.rowbuf + 2 * n;
+  e.W2 = e.W1 + (size_t)TB_NBW * n;
+  e.Tw = e.W2 + (size_t)TB_NBW * n;
+  const size_t nblk = (size_t)(n - 1 + TB_NBW - 1) / TB_NBW;
+  e.bar = reinterpret_cast<unsigned*>(e.Tw + nblk * TB_NBW * TB_NBW);
+  e.ok = reinterpret_cast<int*>(e.bar + TB_BAR_WORDS);
+  e.st = st;
+  e.grid = std::max(1, std::min(std::min(cu_count, n / 8), 64 * TB_GRP));
+}
+
+// workgroup sum of TB_NT threads, returned to every thread
+__device__ __forceinline__ double tb_sum(double v, double* red) {
+  v = tl_wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int q = 0; q < TB_NT / 64; ++q) t += red[q];
+  return t;
+}
+
+// Grid barrier in two levels: workgroups arrive on the counter of their group of
+// TB_GRP (bar[64 + 32 grp], on separate 128-byte lines), the last of a group on
+// the top counter bar[0], the last of all bumps the generation word bar[1], which
+// the others poll with device-coherent loads; false when the grid is aborting
+// (bar[2]).  Only p and the look-ahead rows cross workgroups, and they are stored
+// and loaded with device-scope atomics; every thread waits for its stores to
+// complete before its workgroup arrives, so no cache writeback or invalidation is
+// needed (the rows of A never leave their workgroup).
+__device__ bool tb_grid_sync(unsigned* bar, unsigned& gen) {
+  __shared__ int s_go;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int go = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+    if (go) {
+      const int G = gridDim.x, grp = blockIdx.x / TB_GRP, ngrp = (G + TB_GRP - 1) / TB_GRP;
+      const unsigned gsize = (unsigned)min(TB_GRP, G - grp * TB_GRP);
+      bool last = false;
+      unsigned* gc = &bar[64 + 32 * grp];
+      if (atomicAdd(gc, 1u) == gsize - 1) {
+        atomicExch(gc, 0u);
+        if (atomicAdd(&bar[0], 1u) == (unsigned)ngrp - 1) {
+          atomicExch(&bar[0], 0u);
+          atomicAdd(&bar[1], 1u);
+          last = true;
+        }
+      }
+      if (!last) {
+        const unsigned long long t0 = wall_clock64();
+        while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+          if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+            go = 0;
+            break;
+          }
+          if (wall_clock64() - t0 > TB_SPIN) {
+            atomicExch(&bar[2], 1u);
+            go = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+    }
+    s_go = go;
+  }
+  __syncthreads();
+  ++gen;
+  return s_go != 0;
+}
+
+__device__ __forceinline__ void tb_put(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double tb_get(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Reflector from row r (= column k below the diagonal): alpha = r[k+1],
+// sigma^2 = sum_{j>=k+2} r_j^2; v[k+1] = 1, v[j] = r_j / (alpha - beta).
+__device__ double tb_reflector(const double* r, int k, int n, double* v, double* red, double& beta) {
+  double s2 = 0.0;
+  for (int j = k + 2 + (int)threadIdx.x; j < n; j += TB_NT) s2 += r[j] * r[j];
+  s2 = tb_sum(s2, red);
+  const double alpha = r[k + 1];
+  double tau = 0.0, inv = 0.0;
+  beta = alpha;
+  if (s2 != 0.0) {
+    beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+    tau = (beta - alpha) / beta;
+    inv = 1.0 / (alpha - beta);
+  }
+  for (int j = k + 1 + (int)threadIdx.x; j < n; j += TB_NT) v[j] = (j == k + 1) ? 1.0 : r[j] * inv;
+  __syncthreads();
+  return tau;
+}
+
+// Own rows i >= ilo over columns j >= jlo: with upd, a_ij -= v_i w_j + w_i v_j;
+// then p[i] = tau1 sum_j a_ij v1_j.  Row rowcopy (if owned) is also written to rb.
+// TB_RMAX rows at a time, all their loads issued before any store.
+__device__ void tb_rows(double* A, int n, int ilo, int jlo, bool upd, const double* v, const double* w,
+                        double tau1, const double* v1, double* p, int rowcopy, double* rb, double (*red2)[TB_RMAX]) {
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int first = ilo + ((g - ilo) % G + G) % G;
+  for (int base = first; base < n; base += G * TB_RMAX) {
+    double acc[TB_RMAX];
+#pragma unroll
+    for (int q = 0; q < TB_RMAX; ++q) acc[q] = 0.0;
+    for (int c0 = jlo; c0 < n; c0 += TB_NT * TB_CMAX) {
+      double x[TB_RMAX][TB_CMAX];
+#pragma unroll
+      for (int q = 0; q < TB_RMAX; ++q) {
+        const int i = min(base + q * G, n - 1);
+        const double* row = A + (size_t)i * n;
+#pragma unroll
+        for (int c = 0; c < TB_CMAX; ++c) {
+          const int j = c0 + tid + c * TB_NT;
+          x[q][c] = row[min(j, n - 1)];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < TB_RMAX; ++q) {
+        const int i = base + q * G;
+        if (i < n) {
+          double* row = A + (size_t)i * n;
+          const double vi = upd ? v[i] : 0.0, wi = upd ? w[i] : 0.0;
+#pragma unroll
+          for (int c = 0; c < TB_CMAX; ++c) {
+            const int j = c0 + tid + c * TB_NT;
+            if (j < n) {
+              if (upd) {
+                x[q][c] -= vi * w[j] + wi * v[j];
+                row[j] = x[q][c];
+              }
+              if (i == rowcopy) tb_put(&rb[j], x[q][c]);
+              acc[q] += x[q][c] * v1[j];
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < TB_RMAX; ++q) acc[q] = tl_wave_sum(acc[q]);
+    if (lane == 0)
+      for (int q = 0; q < TB_RMAX; ++q) red2[wave][q] = acc[q];
+    __syncthreads();
+    if (tid < TB_RMAX) {
+      const int i = base + tid * G;
+      if (i < n) {
+        double t = 0.0;
+        for (int q = 0; q < TB_NT / 64; ++q) t += red2[q][tid];
+        tb_put(&p[i], tau1 * t);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void tb_init(EighLarge e) {
+  for (int q = threadIdx.x; q < TB_BAR_WORDS; q += blockDim.x) e.bar[q] = 0u;
+  if (threadIdx.x == 0) *e.ok = 0;
+}
+
+__global__ __launch_bounds__(TB_NT) void tb_reduce(EighLarge e) {
+  extern __shared__ double sm[];
+  __shared__ double red[TB_NT / 64];
+  __shared__ double red2[TB_NT / 64][TB_RMAX];
+  const int n = e.n, G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  double* A = e.Aw;  // ld n
+  double* Y = e.Vw;  // ld n
+  double* vc = sm;   // reflector of the current step
+  double* vn = vc + n;
+  double* w = vn + n;
+  double* r = w + n;
+  unsigned gen = 0;
+  // own rows of A = sym(P).  Y is written by workgroup 0 only: each reflector
+  // column with the zeros above it that its compact-WY block reads (rows k0+1..c of
+  // column c, k0 the first column of the block), so no other workgroup's stores to
+  // Y can race with them.
+  for (int i = g; i < n; i += G)
+    for (int j = tid; j < n; j += TB_NT) {
+      const double a = 0.5 * (e.P[(size_t)i * n + j] + e.P[(size_t)j * n + i]);
+      A[(size_t)i * n + j] = a;
+      e.Ps[(size_t)i * n + j] = a;
+    }
+  // reflector 0 from row 0 (formed from P by every workgroup); p_0 and the look-ahead copy of row 1
+  for (int j = tid; j < n; j += TB_NT) r[j] = 0.5 * (e.P[j] + e.P[(size_t)j * n]);
+  __syncthreads();
+  double beta;
+  double tau = tb_reflector(r, 0, n, vc, red, beta);
+  if (g == 0) {
+    for (int j = 1 + tid; j < n; j += TB_NT) Y[(size_t)j * n] = vc[j];
+    if (tid == 0) {
+      Y[n - 1] = tau;
+      e.d[0] = r[0];
+      e.e[0] = beta;
+    }
+  }
+  tb_rows(A, n, 1, 1, false, vc, w, tau, vc, e.pv, 1, e.rowbuf + n, red2);
+  if (!tb_grid_sync(e.bar, gen)) return;
+  for (int k = 0; k < n - 2; ++k) {
+    const double* p = e.pv + (size_t)(k & 1) * n;
+    double part = 0.0;
+    for (int i = k + 1 + tid; i < n; i += TB_NT) {
+      const double pi = tb_get(&p[i]);
+      w[i] = pi;
+      part += pi * vc[i];
+    }
+    const double K = -0.5 * tau * tb_sum(part, red);
+    for (int i = k + 1 + tid; i < n; i += TB_NT) w[i] += K * vc[i];
+    __syncthreads();
+    const double* rb = e.rowbuf + (size_t)((k + 1) & 1) * n;
+    const double vk1 = vc[k + 1], wk1 = w[k + 1];
+    for (int j = k + 1 + tid; j < n; j += TB_NT) r[j] = tb_get(&rb[j]) - (vk1 * w[j] + wk1 * vc[j]);
+    __syncthreads();
+    double taun = 0.0;
+    if (k + 1 <= n - 3) {
+      taun = tb_reflector(r, k + 1, n, vn, red, beta);
+      if (g == 0) {
+        const int c = k + 1, k0 = (c / TB_NBW) * TB_NBW;
+        for (int j = k0 + 1 + tid; j < n; j += TB_NT) Y[(size_t)j * n + c] = j >= c + 1 ? vn[j] : 0.0;
+        if (tid == 0) {
+          Y[(size_t)(k + 1) * n + (n - 1)] = taun;
+          e.d[k + 1] = r[k + 1];
+          e.e[k + 1] = beta;
+        }
+      }
+    } else if (g == 0 && tid == 0) {  // the last 2 x 2 block
+      e.d[n - 2] = r[n - 2];
+      e.e[n - 2] = r[n - 1];
+    }
+    tb_rows(A, n, k + 2, k + 2, true, vc, w, taun, vn, e.pv + (size_t)((k + 1) & 1) * n, k + 2,
+            e.rowbuf + (size_t)((k + 2) & 1) * n, red2);
+    if (k == n - 3 && g == (n - 1) % G && tid == 0) e.d[n - 1] = A[(size_t)(n - 1) * n + (n - 1)];
+    double* t = vc;
+    vc = vn;
+    vn = t;
+    tau = taun;
+    if (!tb_grid_sync(e.bar, gen)) return;
+  }
+  if (g == 0 && tid == 0) *e.ok = 1;  // reached only when no barrier aborted
+}
+
+// Eigenpairs of T: workgroup b takes eigenvalues [b TE_CH, (b+1) TE_CH): brackets on
+// the unreduced blocks, multisection, twisted-factorization vectors (column j of
+// Zw) with Rayleigh-quotient corrections, and the residual max|T z - lambda z|.
+__global__ __launch_bounds__(TE_NT) void tb_eig(EighLarge e, int* status) {
+  extern __shared__ double sm[];
+  __shared__ double red[TE_NT / 64];
+  __shared__ double lo_s[TE_CH], hi_s[TE_CH];
+  __shared__ int b0_s[TE_CH], b1_s[TE_CH];
+  __shared__ double xs[TE_NT];
+  __shared__ int cnt[TE_NT];
+  if (!*e.ok) return;  // the reduction aborted
+  const int n = e.n, tid = threadIdx.x;
+  double* d = sm;
+  double* ee = d + n;
+  double* e2 = ee + n;
+  for (int i = tid; i < n; i += TE_NT) {
+    d[i] = e.d[i];
+    ee[i] = i < n - 1 ? e.e[i] : 0.0;
+  }
+  __syncthreads();
+  double tn_loc = 0.0, e2_loc = 0.0, fro = 0.0;
+  for (int i = tid; i < n; i += TE_NT) {
+    const double el = i > 0 ? fabs(ee[i - 1]) : 0.0, er = i < n - 1 ? fabs(ee[i]) : 0.0;
+    tn_loc = fmax(tn_loc, fabs(d[i]) + el + er);
+    e2[i] = ee[i] * ee[i];
+    e2_loc = fmax(e2_loc, e2[i]);
+    fro += d[i] * d[i] + 2.0 * e2[i];
+  }
+  const double tn = block_max<TE_NT>(tn_loc, red);
+  const double pivmin = DBL_MIN * fmax(1.0, block_max<TE_NT>(e2_loc, red));
+  const double scale = sqrt(block_sum<TE_NT>(fro, red));
+  const double eps = DBL_EPSILON, split = eps * tn;
+  const int j0 = blockIdx.x * TE_CH, m = min(TE_CH, n - j0);
+  if (tid < m) {
+    const int j = j0 + tid;
+    int b0 = j, b1 = j + 1;
+    while (b0 > 0 && fabs(ee[b0 - 1]) > split) --b0;
+    while (b1 < n && fabs(ee[b1 - 1]) > split) ++b1;
+    double gl = INFINITY, gu = -INFINITY;
+    for (int i = b0; i < b1; ++i) {
+      const double rr = (i > b0 ? fabs(ee[i - 1]) : 0.0) + (i < b1 - 1 ? fabs(ee[i]) : 0.0);
+      gl = fmin(gl, d[i] - rr);
+      gu = fmax(gu, d[i] + rr);
+    }
+    const double margin = 8.0 * n * eps * tn + 4.0 * pivmin;
+    lo_s[tid] = gl - margin;
+    hi_s[tid] = gu + margin;
+    b0_s[tid] = b0;
+    b1_s[tid] = b1;
+  }
+  __syncthreads();
+  const int T = max(1, (TE_NT / 2) / TE_CH), K = 2 * T;
+  for (int it = 0; it < TL_MAXIT; ++it) {
+    if (tid < m * T) {
+      const int jj = tid / T, q = tid - jj * T;
+      const double lo = lo_s[jj], hi = hi_s[jj], wd = hi - lo;
+      const double x0 = lo + wd * ((double)(2 * q + 1) / (double)(K + 1));
+      const double x1 = lo + wd * ((double)(2 * q + 2) / (double)(K + 1));
+      int c0, c1;
+      tl_sturm2(d, e2, b0_s[jj], b1_s[jj], x0, x1, pivmin, c0, c1);
+      xs[2 * tid] = x0;
+      xs[2 * tid + 1] = x1;
+      cnt[2 * tid] = c0;
+      cnt[2 * tid + 1] = c1;
+    }
+    __syncthreads();
+    int more = 0;
+    if (tid < m) {
+      const int jl = j0 + tid - b0_s[tid];
+      double lo = lo_s[tid], hi = hi_s[tid];
+      for (int q = 0; q < K; ++q) {
+        const double x = xs[tid * K + q];
+        if (cnt[tid * K + q] <= jl)
+          lo = fmax(lo, x);
+        else
+          hi = fmin(hi, x);
+      }
+      lo_s[tid] = lo;
+      hi_s[tid] = hi;
+      more = (hi - lo) > TL_BISECT_TOL * tn;
+    }
+    if (!__syncthreads_or(more)) break;
+  }
+  double res = 0.0;
+  if (tid < m) {
+    const int j = j0 + tid, b0 = b0_s[tid], b1 = b1_s[tid];
+    const double lam = tl_vector(d, ee, e2, b0, b1, lo_s[tid], hi_s[tid], tn, pivmin, e.Zw, n, j);
+    e.w[j] = lam;
+    for (int i = b0; i < b1; ++i) {
+      double t = (d[i] - lam) * e.Zw[(size_t)i * n + j];
+      if (i > b0) t += ee[i - 1] * e.Zw[(size_t)(i - 1) * n + j];
+      if (i < b1 - 1) t += ee[i] * e.Zw[(size_t)(i + 1) * n + j];
+      res = fmax(res, tl_err(fabs(t)));
+    }
+  }
+  res = block_max<TE_NT>(res, red);
+  if (tid == 0 && !(res <= 1e-12 * scale)) atomicExch(e.ok, 0);
+}
+
+// T factors of the compact WY form of blocks of TB_NBW reflectors (one workgroup
+// per block): T[:c, c] = T[:c, :c] (-tau_c Y_b^T y_c), T[c][c] = tau_c.
+__global__ __launch_bounds__(256) void tb_wy_t(EighLarge e) {
+  if (!*e.ok) return;
+  const int n = e.n, k0 = blockIdx.x * TB_NBW;
+  const int m = min(TB_NBW, n - 1 - k0);
+  const double* Y = e.Vw;
+  double* Tb = e.Tw + (size_t)blockIdx.x * TB_NBW * TB_NBW;
+  __shared__ double g[TB_NBW][TB_NBW + 1];
+  __shared__ double T[TB_NBW][TB_NBW + 1];
+  __shared__ double col[TB_NBW];
+  for (int q = threadIdx.x; q < TB_NBW * TB_NBW; q += 256) {
+    const int r = q / TB_NBW, c = q - r * TB_NBW;
+    double acc = 0.0;
+    if (r < c && c < m)
+      for (int i = k0 + 1 + c; i < n; ++i) acc += Y[(size_t)i * n + k0 + r] * Y[(size_t)i * n + k0 + c];
+    g[r][c] = acc;
+    T[r][c] = 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < m; ++c) {
+    const double tau = Y[(size_t)(k0 + c) * n + (n - 1)];
+    const int r = threadIdx.x;
+    if (r < c) col[r] = -tau * g[r][c];
+    __syncthreads();
+    if (r < c) {
+      double acc = 0.0;
+      for (int q = r; q < c; ++q) acc += T[r][q] * col[q];
+      T[r][c] = acc;
+    }
+    if (r == c) T[c][c] = tau;
+    __syncthreads();
+  }
+  for (int q = threadIdx.x; q < TB_NBW * TB_NBW; q += 256) Tb[q] = T[q / TB_NBW][q % TB_NBW];
+}
+
+// Final check of the tridiagonal path against the input: with R = sym(P) X (in
+// Aw), *ok = 0 unless max |R_ij - X_ij w_j| <= 1e-11 ||sym(P)||_F.
+__global__ __launch_bounds__(1024) void tb_final_check(EighLarge e) {
+  __shared__ double red[16];
+  if (!*e.ok) return;
+  const int n = e.n;
+  double res = 0.0, fro = 0.0;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += 1024) {
+    const int j = (int)(idx % n);
+    res = fmax(res, tl_err(fabs(e.Aw[idx] - e.X[idx] * e.w[j])));
+    fro += e.Ps[idx] * e.Ps[idx];
+  }
+  res = block_max<1024>(res, red);
+  fro = block_sum<1024>(fro, red);
+  if (threadIdx.x == 0 && !(res <= 1e-11 * sqrt(fro))) *e.ok = 0;
+}
+
+void launch_tb_final_check(const EighLarge& e, hipStream_t s) { tb_final_check<<<1, 1024, 0, s>>>(e); }
+
+void launch_tb_solve(const EighLarge& e, int* status, hipStream_t s) {
+  const int n = e.n;
+  const size_t red_lds = sizeof(double) * 4 * (size_t)n;
+  // more than half of a CU's LDS, so that no two workgroups share a CU
+  const size_t lds = std::max<size_t>(red_lds, 96 * 1024);
+  const size_t eig_lds = sizeof(double) * 3 * (size_t)n;
+  static size_t attr_r = 0, attr_e = 0;
+  if (lds > attr_r) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_reduce), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    attr_r = lds;
+  }
+  if (eig_lds > attr_e) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_eig), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)eig_lds);
+    attr_e = eig_lds;
+  }
+  tb_init<<<1, 256, 0, s>>>(e);
+  tb_reduce<<<e.grid, TB_NT, lds, s>>>(e);
+  tb_eig<<<(n + TE_CH - 1) / TE_CH, TE_NT, eig_lds, s>>>(e, status);
+}
+
+void launch_tb_wy_t(const EighLarge& e, hipStream_t s) {
+  const int nblk = (e.n - 1 + TB_NBW - 1) / TB_NBW;
+  if (nblk > 0) tb_wy_t<<<nblk, 256, 0, s>>>(e);
 }
 
 static bool g_attr = false;

@@ -194,6 +194,11 @@ struct etdm_handle {
   int n_eig_herm = 0, herm_nmax = 1, herm_nblk = 0;
   int* herm_ok = nullptr;
   Stage z_HG, z_HNS;
+  // real large path: tridiagonal solver part 2
+  Stage s_LG, s_LNS, s_LR;
+  std::vector<Stage> s_LWY1, s_LWY2, s_LWY3;
+  HermCheck* d_lchk = nullptr;
+  int cu_count = 1;
   std::vector<Stage> z_WY1, z_WY2, z_WY3;  // per block of reflectors: W1 = Y^H V, W2 = T W1, V -= Y W2
   std::vector<EighLarge> eig_large;  // real problems above the LDS size
   const double** d_n0ptr = nullptr;
@@ -458,6 +463,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
   std::vector<OvPair> pair;
   std::vector<int> bspec, brows, bpair;
   std::vector<EighProb> el, eg;
+  std::vector<HermCheck> lchk;
   for (int i = 0; i < h->n_inst; ++i) {
     const int M = h->M[i], N = h->N[i], Nv = M - N;
     const OvBuf& b = h->ov[i];
@@ -472,20 +478,37 @@ etdm_status build_ov_plan(etdm_handle* h) {
       el.push_back(EighProb{b.P, b.X, b.s, N, 1});
     } else {
       EighLarge e;
-      size_t npad = 0;
-      eigh_large_workspace(N, &npad);
+      std::memset(&e, 0, sizeof(e));
       e.P = b.P;
       e.X = b.X;
       e.w = b.s;
       e.n = N;
-      e.npad = (int)npad;
-      e.nb = (int)npad / 32;
-      e.Aw = b.eig_ws;
-      e.Vw = e.Aw + npad * npad;
-      e.Qb = e.Vw + npad * npad;
-      e.partial = e.Qb + (size_t)(e.nb / 2) * 64 * 64;
-      e.st = b.eig_st;
+      eigh_large_layout(e, b.eig_ws, b.eig_st, h->cu_count);
       h->eig_large.push_back(e);
+      // tridiagonal path, part 2: Z^T Z (into the free work matrix), its check and
+      // one Newton-Schulz step into X, then X <- Q X in compact-WY blocks
+      h->s_LG.add(prob(N, N, N, e.Zw, N, e.Zw, N, e.Aw, N));
+      h->s_LNS.add(prob(N, N, N, e.Zw, N, e.Aw, N, e.X, N));
+      h->s_LR.add(prob(N, N, N, e.Ps, N, e.X, N, e.Aw, N));  // R = sym(P) X for the final check
+      lchk.push_back(HermCheck{e.Aw, e.ok, N});
+      const int nblk = (N - 1 + TB_NBW - 1) / TB_NBW;
+      if ((int)h->s_LWY1.size() < nblk) {
+        h->s_LWY1.resize(nblk);
+        h->s_LWY2.resize(nblk);
+        h->s_LWY3.resize(nblk);
+      }
+      for (int bk = 0; bk < nblk; ++bk) {
+        const int k0 = bk * TB_NBW, mb = std::min(TB_NBW, N - 1 - k0), R = N - 1 - k0;
+        const double* Yb = e.Vw + (size_t)(k0 + 1) * N + k0;
+        double* Xr = e.X + (size_t)(k0 + 1) * N;
+        h->s_LWY1[bk].add(prob(mb, N, R, Yb, N, Xr, N, e.W1, N));
+        h->s_LWY2[bk].add(prob(mb, N, mb, e.Tw + (size_t)bk * TB_NBW * TB_NBW, TB_NBW, e.W1, N, e.W2, N));
+        GemmProb up = prob(R, N, mb, Yb, N, e.W2, N, Xr, N, -1.0);
+        up.beta = 1.0;
+        up.D = Xr;
+        up.ldd = N;
+        h->s_LWY3[bk].add(up);
+      }
     }
     spec.push_back(OvSpec{b.s, b.X, b.Xcsw, b.T1s, b.T2, b.T3s, b.T3, N});
     bspec.push_back(h->tot_spec);
@@ -578,6 +601,23 @@ etdm_status build_ov_plan(etdm_handle* h) {
                      &h->s_R,   &h->s_Gam1, &h->s_Gam, &h->s_Y1, &h->s_Y2, &h->s_G,  &h->s_Uov,
                      &h->s_Uvv, &h->s_HC0};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
+  if (!h->eig_large.empty()) {
+    h->s_LG.init(OP_T, OP_N, GP_FP64);
+    h->s_LNS.init(OP_N, OP_N, GP_FP64);
+    h->s_LR.init(OP_N, OP_N, GP_FP64);
+    CHECK(upload_stage(h, h->s_LG));
+    CHECK(upload_stage(h, h->s_LNS));
+    CHECK(upload_stage(h, h->s_LR));
+    for (size_t bk = 0; bk < h->s_LWY1.size(); ++bk) {
+      h->s_LWY1[bk].init(OP_T, OP_N, GP_FP64);
+      h->s_LWY2[bk].init(OP_N, OP_N, GP_FP64);
+      h->s_LWY3[bk].init(OP_N, OP_N, GP_FP64);
+      CHECK(upload_stage(h, h->s_LWY1[bk]));
+      CHECK(upload_stage(h, h->s_LWY2[bk]));
+      CHECK(upload_stage(h, h->s_LWY3[bk]));
+    }
+    CHECK(upload(h, &h->d_lchk, lchk));
+  }
   CHECK(upload(h, &h->d_spec, spec));
   CHECK(upload(h, &h->b_spec, bspec));
   CHECK(upload(h, &h->d_rows, rows));
@@ -779,6 +819,22 @@ void ov_exponential_part(etdm_handle* h, hipStream_t s) {
     TIMED(O_EIGG);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     hipStreamIsCapturing(s, &cs);
+    // reduction to tridiagonal form and its eigenpairs, the orthogonality check and
+    // one Newton-Schulz step, the compact-WY back-transform, the residual against P;
+    // then the Jacobi sweeps,
+    // which return at once when the tridiagonal result was accepted
+    for (const EighLarge& e : h->eig_large) launch_tb_solve(e, h->status, s);
+    h->s_LG.launch(s);
+    launch_herm_check(h->d_lchk, (int)h->eig_large.size(), s);
+    h->s_LNS.launch(s);
+    for (const EighLarge& e : h->eig_large) launch_tb_wy_t(e, s);
+    for (int bk = (int)h->s_LWY1.size() - 1; bk >= 0; --bk) {
+      h->s_LWY1[bk].launch(s);
+      h->s_LWY2[bk].launch(s);
+      h->s_LWY3[bk].launch(s);
+    }
+    h->s_LR.launch(s);
+    for (const EighLarge& e : h->eig_large) launch_tb_final_check(e, s);
     for (const EighLarge& e : h->eig_large)
       launch_eigh_large(e, LARGE_EIGH_MAX_SWEEPS, h->status, s, cs == hipStreamCaptureStatusNone);
   }
@@ -1213,6 +1269,11 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   };
   h->n_inst = d->n_inst;
   h->kind = d->kind;
+  {
+    int dev = 0, cus = 1;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      h->cu_count = std::max(1, cus);
+  }
   h->prec = d->precision;
   h->U = d->hubbard_U;
   h->couple = d->couple ? 1 : 0;
