@@ -37,8 +37,13 @@ struct EighLarge {
   double* W1;       // TB_NBW x n compact-WY scratch
   double* W2;       // TB_NBW x n
   double* Tw;       // ceil((n-1)/TB_NBW) blocks of TB_NBW x TB_NBW compact-WY factors
+  double* Gw;       // the same number of Gram matrices Y_b^T Y_b (m_b x m_b, ld m_b)
   unsigned* bar;    // grid barrier words: [0] top arrivals, [1] generation, [2] abort, group counters
   int* ok;          // 1 when the tridiagonal result passed its checks
+  double* scan;     // 4: maxima / sums of the grid-wide checks
+  double* blo;      // n: eigenvalue brackets of T
+  double* bhi;      // n
+  int* bb;          // 2 n: unreduced block [b0, b1) of each eigenvalue
   int grid;         // workgroups of the reduction (one per CU, all resident)
 };
 
@@ -51,9 +56,11 @@ void eigh_large_layout(EighLarge& e, double* ws, EighLargeState* st, int cu_coun
 // Tridiagonal path, part 1: reduction (cooperative), eigenpairs of T (Zw, w) and
 // their residual check.  Part 2 (orthogonality check, one Newton-Schulz step into
 // X, compact-WY back-transform of X) is launched by the caller with grouped GEMMs;
-// launch_tb_wy_t forms the T factors.
+// launch_tb_wy_t forms the T factors from the Gram matrices in Gw.
 void launch_tb_solve(const EighLarge& e, int* status, hipStream_t s);
 void launch_tb_wy_t(const EighLarge& e, hipStream_t s);
+// After G = Z^T Z has been formed in Aw: *ok = 0 unless max|G - I| <= 1e-6; Aw <- (3 I - G) / 2.
+void launch_tb_orth_check(const EighLarge& e, hipStream_t s);
 // After R = sym(P) X has been formed in Aw: *ok = 0 unless max|R - X diag(w)| <= 1e-11 ||sym(P)||_F.
 void launch_tb_final_check(const EighLarge& e, hipStream_t s);
 // Launch the whole solve on stream s.  With check_host the host reads the

@@ -325,7 +325,7 @@ size_t eigh_large_workspace(int n, size_t* npad_out) {
   const size_t half = npad / BLK / 2;
   const size_t nblk = (size_t)(n - 1 + TB_NBW - 1) / TB_NBW;
   return 2 * npad * npad + half * SUB * SUB + PREP_BLOCKS + 2 * (size_t)n * n + 6 * (size_t)n +
-         2 * (size_t)TB_NBW * n + nblk * TB_NBW * TB_NBW + TB_BAR_WORDS / 2 + 2;
+         2 * (size_t)TB_NBW * n + 2 * nblk * TB_NBW * TB_NBW + TB_BAR_WORDS / 2 + 2 + 4 + 3 * (size_t)n;
 }
 
 void eigh_large_layout(EighLarge& e, double* ws, EighLargeState* st, int cu_count) {
@@ -348,8 +348,13 @@ void eigh_large_layout(EighLarge& e, double* ws, EighLargeState* st, int cu_coun
   e.W2 = e.W1 + (size_t)TB_NBW * n;
   e.Tw = e.W2 + (size_t)TB_NBW * n;
   const size_t nblk = (size_t)(n - 1 + TB_NBW - 1) / TB_NBW;
-  e.bar = reinterpret_cast<unsigned*>(e.Tw + nblk * TB_NBW * TB_NBW);
+  e.Gw = e.Tw + nblk * TB_NBW * TB_NBW;
+  e.bar = reinterpret_cast<unsigned*>(e.Gw + nblk * TB_NBW * TB_NBW);
   e.ok = reinterpret_cast<int*>(e.bar + TB_BAR_WORDS);
+  e.scan = reinterpret_cast<double*>(e.bar + TB_BAR_WORDS + 4);
+  e.blo = e.scan + 4;
+  e.bhi = e.blo + n;
+  e.bb = reinterpret_cast<int*>(e.bhi + n);
   e.st = st;
   e.grid = std::max(1, std::min(std::min(cu_count, n / 8), 64 * TB_GRP));
 }
@@ -504,6 +509,7 @@ __device__ void tb_rows(double* A, int n, int ilo, int jlo, bool upd, const doub
 
 __global__ void tb_init(EighLarge e) {
   for (int q = threadIdx.x; q < TB_BAR_WORDS; q += blockDim.x) e.bar[q] = 0u;
+  if (threadIdx.x < 4) e.scan[threadIdx.x] = 0.0;
   if (threadIdx.x == 0) *e.ok = 0;
 }
 
@@ -587,10 +593,12 @@ __global__ __launch_bounds__(TB_NT) void tb_reduce(EighLarge e) {
   if (g == 0 && tid == 0) *e.ok = 1;  // reached only when no barrier aborted
 }
 
-// Eigenpairs of T: workgroup b takes eigenvalues [b TE_CH, (b+1) TE_CH): brackets on
-// the unreduced blocks, multisection, twisted-factorization vectors (column j of
-// Zw) with Rayleigh-quotient corrections, and the residual max|T z - lambda z|.
-__global__ __launch_bounds__(TE_NT) void tb_eig(EighLarge e, int* status) {
+// Eigenvalue brackets of T: workgroup b takes eigenvalues [b m, (b+1) m) (m = TE_CH):
+// brackets on the unreduced blocks and multisection down to TB_BISECT_TOL ||T||,
+// written to lo / hi (and the block bounds) for the vector kernel.
+constexpr double TB_BISECT_TOL = 1e-13;
+
+__global__ __launch_bounds__(TE_NT) void tb_bisect(EighLarge e) {
   extern __shared__ double sm[];
   __shared__ double red[TE_NT / 64];
   __shared__ double lo_s[TE_CH], hi_s[TE_CH];
@@ -607,17 +615,15 @@ __global__ __launch_bounds__(TE_NT) void tb_eig(EighLarge e, int* status) {
     ee[i] = i < n - 1 ? e.e[i] : 0.0;
   }
   __syncthreads();
-  double tn_loc = 0.0, e2_loc = 0.0, fro = 0.0;
+  double tn_loc = 0.0, e2_loc = 0.0;
   for (int i = tid; i < n; i += TE_NT) {
     const double el = i > 0 ? fabs(ee[i - 1]) : 0.0, er = i < n - 1 ? fabs(ee[i]) : 0.0;
     tn_loc = fmax(tn_loc, fabs(d[i]) + el + er);
     e2[i] = ee[i] * ee[i];
     e2_loc = fmax(e2_loc, e2[i]);
-    fro += d[i] * d[i] + 2.0 * e2[i];
   }
   const double tn = block_max<TE_NT>(tn_loc, red);
   const double pivmin = DBL_MIN * fmax(1.0, block_max<TE_NT>(e2_loc, red));
-  const double scale = sqrt(block_sum<TE_NT>(fro, red));
   const double eps = DBL_EPSILON, split = eps * tn;
   const int j0 = blockIdx.x * TE_CH, m = min(TE_CH, n - j0);
   if (tid < m) {
@@ -638,7 +644,7 @@ __global__ __launch_bounds__(TE_NT) void tb_eig(EighLarge e, int* status) {
     b1_s[tid] = b1;
   }
   __syncthreads();
-  const int T = max(1, (TE_NT / 2) / TE_CH), K = 2 * T;
+  const int T = max(1, (TE_NT / 2) / max(m, 1)), K = 2 * T;
   for (int it = 0; it < TL_MAXIT; ++it) {
     if (tid < m * T) {
       const int jj = tid / T, q = tid - jj * T;
@@ -666,14 +672,50 @@ __global__ __launch_bounds__(TE_NT) void tb_eig(EighLarge e, int* status) {
       }
       lo_s[tid] = lo;
       hi_s[tid] = hi;
-      more = (hi - lo) > TL_BISECT_TOL * tn;
+      more = (hi - lo) > TB_BISECT_TOL * tn;
     }
     if (!__syncthreads_or(more)) break;
   }
-  double res = 0.0;
   if (tid < m) {
-    const int j = j0 + tid, b0 = b0_s[tid], b1 = b1_s[tid];
-    const double lam = tl_vector(d, ee, e2, b0, b1, lo_s[tid], hi_s[tid], tn, pivmin, e.Zw, n, j);
+    e.blo[j0 + tid] = lo_s[tid];
+    e.bhi[j0 + tid] = hi_s[tid];
+    e.bb[2 * (j0 + tid)] = b0_s[tid];
+    e.bb[2 * (j0 + tid) + 1] = b1_s[tid];
+  }
+}
+
+// Eigenvectors of T: one lane per eigenvalue (64 per workgroup), twisted
+// factorizations with Rayleigh-quotient corrections; the pivots and the vector
+// are kept in column j of Zw (lanes read and write consecutive addresses), and the
+// residual max|T z - lambda z| is checked.
+constexpr int TV_NT = 64;
+
+__global__ __launch_bounds__(TV_NT) void tb_vectors(EighLarge e) {
+  extern __shared__ double sm[];
+  if (!*e.ok) return;
+  const int n = e.n, tid = threadIdx.x;
+  double* d = sm;
+  double* ee = d + n;
+  double* e2 = ee + n;
+  double tn_loc = 0.0, e2_loc = 0.0, fro = 0.0;
+  for (int i = tid; i < n; i += TV_NT) {
+    d[i] = e.d[i];
+    ee[i] = i < n - 1 ? e.e[i] : 0.0;
+    e2[i] = ee[i] * ee[i];
+    const double el = i > 0 ? fabs(e.e[i - 1]) : 0.0;
+    tn_loc = fmax(tn_loc, fabs(d[i]) + el + fabs(ee[i]));
+    e2_loc = fmax(e2_loc, e2[i]);
+    fro += d[i] * d[i] + 2.0 * e2[i];
+  }
+  const double tn = tl_wave_max(tn_loc);
+  const double pivmin = DBL_MIN * fmax(1.0, tl_wave_max(e2_loc));
+  const double scale = sqrt(tl_wave_sum(fro));
+  __syncthreads();
+  const int j = blockIdx.x * TV_NT + tid;
+  double res = 0.0;
+  if (j < n) {
+    const int b0 = e.bb[2 * j], b1 = e.bb[2 * j + 1];
+    const double lam = tl_vector(d, ee, e2, b0, b1, e.blo[j], e.bhi[j], tn, pivmin, e.Zw, n, j, n);
     e.w[j] = lam;
     for (int i = b0; i < b1; ++i) {
       double t = (d[i] - lam) * e.Zw[(size_t)i * n + j];
@@ -682,27 +724,75 @@ __global__ __launch_bounds__(TE_NT) void tb_eig(EighLarge e, int* status) {
       res = fmax(res, tl_err(fabs(t)));
     }
   }
-  res = block_max<TE_NT>(res, red);
+  res = tl_wave_max(res);
   if (tid == 0 && !(res <= 1e-12 * scale)) atomicExch(e.ok, 0);
 }
 
+// Orthogonality of Z over many workgroups: max |G - I| (G = Z^T Z in Aw) into
+// scan[0] (atomic max on the bit pattern), and G <- (3 I - G) / 2.
+__global__ __launch_bounds__(256) void tb_orth_scan(EighLarge e) {
+  __shared__ double red[4];
+  if (!*e.ok) return;
+  const int n = e.n;
+  double m = 0.0;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < (int64_t)n * n; idx += (int64_t)gridDim.x * 256) {
+    const int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
+    const double g = e.Aw[idx], dlt = i == j ? 1.0 : 0.0;
+    m = fmax(m, tl_err(fabs(g - dlt)));
+    e.Aw[idx] = 1.5 * dlt - 0.5 * g;
+  }
+  m = block_max<256>(m, red);
+  if (threadIdx.x == 0) atomicMax(reinterpret_cast<unsigned long long*>(e.scan), (unsigned long long)__double_as_longlong(m));
+}
+
+// Residual of the accepted result against sym(P): max |R - X diag(w)| (R = sym(P) X
+// in Aw) into scan[1], ||sym(P)||_F^2 partial sums into scan[2].
+__global__ __launch_bounds__(256) void tb_res_scan(EighLarge e) {
+  __shared__ double red[4];
+  if (!*e.ok) return;
+  const int n = e.n;
+  double r = 0.0, f = 0.0;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < (int64_t)n * n; idx += (int64_t)gridDim.x * 256) {
+    const int j = (int)(idx % n);
+    r = fmax(r, tl_err(fabs(e.Aw[idx] - e.X[idx] * e.w[j])));
+    f += e.Ps[idx] * e.Ps[idx];
+  }
+  r = block_max<256>(r, red);
+  f = block_sum<256>(f, red);
+  if (threadIdx.x == 0) {
+    atomicMax(reinterpret_cast<unsigned long long*>(e.scan) + 1, (unsigned long long)__double_as_longlong(r));
+    atomicAdd(e.scan + 2, f);
+  }
+}
+
+// which = 0: *ok = 0 unless max|G - I| <= 1e-6;  which = 1: unless the residual
+// max <= 1e-11 ||sym(P)||_F.
+__global__ void tb_verdict(EighLarge e, int which) {
+  if (threadIdx.x != 0 || !*e.ok) return;
+  const unsigned long long* b = reinterpret_cast<const unsigned long long*>(e.scan);
+  if (which == 0) {
+    if (!(__longlong_as_double((long long)b[0]) <= 1e-6)) *e.ok = 0;
+  } else {
+    if (!(__longlong_as_double((long long)b[1]) <= 1e-11 * sqrt(e.scan[2]))) *e.ok = 0;
+  }
+}
+
 // T factors of the compact WY form of blocks of TB_NBW reflectors (one workgroup
-// per block): T[:c, c] = T[:c, :c] (-tau_c Y_b^T y_c), T[c][c] = tau_c.
+// per block): T[:c, c] = T[:c, :c] (-tau_c g[:c, c]), T[c][c] = tau_c, with the Gram
+// matrix g = Y_b^T Y_b of the block already in Gw.
 __global__ __launch_bounds__(256) void tb_wy_t(EighLarge e) {
   if (!*e.ok) return;
   const int n = e.n, k0 = blockIdx.x * TB_NBW;
   const int m = min(TB_NBW, n - 1 - k0);
   const double* Y = e.Vw;
+  const double* Gb = e.Gw + (size_t)blockIdx.x * TB_NBW * TB_NBW;
   double* Tb = e.Tw + (size_t)blockIdx.x * TB_NBW * TB_NBW;
   __shared__ double g[TB_NBW][TB_NBW + 1];
   __shared__ double T[TB_NBW][TB_NBW + 1];
   __shared__ double col[TB_NBW];
   for (int q = threadIdx.x; q < TB_NBW * TB_NBW; q += 256) {
     const int r = q / TB_NBW, c = q - r * TB_NBW;
-    double acc = 0.0;
-    if (r < c && c < m)
-      for (int i = k0 + 1 + c; i < n; ++i) acc += Y[(size_t)i * n + k0 + r] * Y[(size_t)i * n + k0 + c];
-    g[r][c] = acc;
+    g[r][c] = (r < m && c < m) ? Gb[r * m + c] : 0.0;
     T[r][c] = 0.0;
   }
   __syncthreads();
@@ -722,24 +812,15 @@ __global__ __launch_bounds__(256) void tb_wy_t(EighLarge e) {
   for (int q = threadIdx.x; q < TB_NBW * TB_NBW; q += 256) Tb[q] = T[q / TB_NBW][q % TB_NBW];
 }
 
-// Final check of the tridiagonal path against the input: with R = sym(P) X (in
-// Aw), *ok = 0 unless max |R_ij - X_ij w_j| <= 1e-11 ||sym(P)||_F.
-__global__ __launch_bounds__(1024) void tb_final_check(EighLarge e) {
-  __shared__ double red[16];
-  if (!*e.ok) return;
-  const int n = e.n;
-  double res = 0.0, fro = 0.0;
-  for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += 1024) {
-    const int j = (int)(idx % n);
-    res = fmax(res, tl_err(fabs(e.Aw[idx] - e.X[idx] * e.w[j])));
-    fro += e.Ps[idx] * e.Ps[idx];
-  }
-  res = block_max<1024>(res, red);
-  fro = block_sum<1024>(fro, red);
-  if (threadIdx.x == 0 && !(res <= 1e-11 * sqrt(fro))) *e.ok = 0;
+void launch_tb_orth_check(const EighLarge& e, hipStream_t s) {
+  tb_orth_scan<<<256, 256, 0, s>>>(e);
+  tb_verdict<<<1, 64, 0, s>>>(e, 0);
 }
 
-void launch_tb_final_check(const EighLarge& e, hipStream_t s) { tb_final_check<<<1, 1024, 0, s>>>(e); }
+void launch_tb_final_check(const EighLarge& e, hipStream_t s) {
+  tb_res_scan<<<256, 256, 0, s>>>(e);
+  tb_verdict<<<1, 64, 0, s>>>(e, 1);
+}
 
 void launch_tb_solve(const EighLarge& e, int* status, hipStream_t s) {
   const int n = e.n;
@@ -754,13 +835,16 @@ void launch_tb_solve(const EighLarge& e, int* status, hipStream_t s) {
     attr_r = lds;
   }
   if (eig_lds > attr_e) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_eig), hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_bisect), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)eig_lds);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_vectors), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)eig_lds);
     attr_e = eig_lds;
   }
   tb_init<<<1, 256, 0, s>>>(e);
   tb_reduce<<<e.grid, TB_NT, lds, s>>>(e);
-  tb_eig<<<(n + TE_CH - 1) / TE_CH, TE_NT, eig_lds, s>>>(e, status);
+  tb_bisect<<<(n + TE_CH - 1) / TE_CH, TE_NT, eig_lds, s>>>(e);
+  tb_vectors<<<(n + TV_NT - 1) / TV_NT, TV_NT, eig_lds, s>>>(e);
 }
 
 void launch_tb_wy_t(const EighLarge& e, hipStream_t s) {

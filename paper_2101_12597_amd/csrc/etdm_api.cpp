@@ -195,7 +195,7 @@ struct etdm_handle {
   int* herm_ok = nullptr;
   Stage z_HG, z_HNS;
   // real large path: tridiagonal solver part 2
-  Stage s_LG, s_LNS, s_LR;
+  Stage s_LG, s_LNS, s_LR, s_LGram;
   std::vector<Stage> s_LWY1, s_LWY2, s_LWY3;
   HermCheck* d_lchk = nullptr;
   int cu_count = 1;
@@ -500,6 +500,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
       for (int bk = 0; bk < nblk; ++bk) {
         const int k0 = bk * TB_NBW, mb = std::min(TB_NBW, N - 1 - k0), R = N - 1 - k0;
         const double* Yb = e.Vw + (size_t)(k0 + 1) * N + k0;
+        h->s_LGram.add(prob(mb, mb, R, Yb, N, Yb, N, e.Gw + (size_t)bk * TB_NBW * TB_NBW, mb));
         double* Xr = e.X + (size_t)(k0 + 1) * N;
         h->s_LWY1[bk].add(prob(mb, N, R, Yb, N, Xr, N, e.W1, N));
         h->s_LWY2[bk].add(prob(mb, N, mb, e.Tw + (size_t)bk * TB_NBW * TB_NBW, TB_NBW, e.W1, N, e.W2, N));
@@ -605,6 +606,8 @@ etdm_status build_ov_plan(etdm_handle* h) {
     h->s_LG.init(OP_T, OP_N, GP_FP64);
     h->s_LNS.init(OP_N, OP_N, GP_FP64);
     h->s_LR.init(OP_N, OP_N, GP_FP64);
+    h->s_LGram.init(OP_T, OP_N, GP_FP64);
+    CHECK(upload_stage(h, h->s_LGram));
     CHECK(upload_stage(h, h->s_LG));
     CHECK(upload_stage(h, h->s_LNS));
     CHECK(upload_stage(h, h->s_LR));
@@ -825,8 +828,9 @@ void ov_exponential_part(etdm_handle* h, hipStream_t s) {
     // which return at once when the tridiagonal result was accepted
     for (const EighLarge& e : h->eig_large) launch_tb_solve(e, h->status, s);
     h->s_LG.launch(s);
-    launch_herm_check(h->d_lchk, (int)h->eig_large.size(), s);
+    for (const EighLarge& e : h->eig_large) launch_tb_orth_check(e, s);
     h->s_LNS.launch(s);
+    h->s_LGram.launch(s);
     for (const EighLarge& e : h->eig_large) launch_tb_wy_t(e, s);
     for (int bk = (int)h->s_LWY1.size() - 1; bk >= 0; --bk) {
       h->s_LWY1[bk].launch(s);

@@ -62,6 +62,11 @@ __device__ __forceinline__ double tl_wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ double tl_wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
 // 1 / q from the hardware reciprocal (about 28 correct bits) refined by one
 // Newton step (about 10 ulp): the pivot recurrences below are backward stable
 // with any relative error of a few ulps per operation.
@@ -128,20 +133,20 @@ constexpr int TL_RQI_MAX = 4;                 // Rayleigh-quotient corrections p
 // Writes z / ||z|| into column j of Z (ld n; D+ and D- are kept there meanwhile)
 // and returns the Rayleigh-quotient correction gamma_r / ||z||^2.
 __device__ inline double tl_twisted(const double* d, const double* e, const double* e2, int b0, int b1, double lam,
-                             double pivmin, double* Z, int n, int j) {
+                             double pivmin, double* Z, int ld, int j) {
   double D = tl_piv(d[b0] - lam, pivmin);
-  Z[b0 * n + j] = D;
+  Z[b0 * ld + j] = D;
   for (int i = b0 + 1; i < b1; ++i) {
     D = tl_piv((d[i] - lam) - e2[i - 1] * tl_rcp(D), pivmin);
-    Z[i * n + j] = D;
+    Z[i * ld + j] = D;
   }
   D = tl_piv(d[b1 - 1] - lam, pivmin);
   int r = b1 - 1;
-  double gr = Z[(b1 - 1) * n + j] + D - (d[b1 - 1] - lam);
+  double gr = Z[(b1 - 1) * ld + j] + D - (d[b1 - 1] - lam);
   double best = fabs(gr);
   for (int i = b1 - 2; i >= b0; --i) {
     D = tl_piv((d[i] - lam) - e2[i] * tl_rcp(D), pivmin);
-    const double g = Z[i * n + j] + D - (d[i] - lam);
+    const double g = Z[i * ld + j] + D - (d[i] - lam);
     if (fabs(g) < best) {
       best = fabs(g);
       gr = g;
@@ -150,48 +155,48 @@ __device__ inline double tl_twisted(const double* d, const double* e, const doub
   }
   if (r < b1 - 1) {  // backward pivots below the twist
     D = tl_piv(d[b1 - 1] - lam, pivmin);
-    Z[(b1 - 1) * n + j] = D;
+    Z[(b1 - 1) * ld + j] = D;
     for (int i = b1 - 2; i > r; --i) {
       D = tl_piv((d[i] - lam) - e2[i] * tl_rcp(D), pivmin);
-      Z[i * n + j] = D;
+      Z[i * ld + j] = D;
     }
   }
   double nrm = 1.0, z = 1.0;
-  Z[r * n + j] = 1.0;
+  Z[r * ld + j] = 1.0;
   for (int i = r - 1; i >= b0; --i) {
-    z = -(e[i] * tl_rcp(Z[i * n + j])) * z;
-    Z[i * n + j] = z;
+    z = -(e[i] * tl_rcp(Z[i * ld + j])) * z;
+    Z[i * ld + j] = z;
     nrm += z * z;
   }
   z = 1.0;
   for (int i = r + 1; i < b1; ++i) {
-    z = -(e[i - 1] * tl_rcp(Z[i * n + j])) * z;
-    Z[i * n + j] = z;
+    z = -(e[i - 1] * tl_rcp(Z[i * ld + j])) * z;
+    Z[i * ld + j] = z;
     nrm += z * z;
   }
   const double sc = 1.0 / sqrt(nrm);
-  for (int i = b0; i < b1; ++i) Z[i * n + j] *= sc;
+  for (int i = b0; i < b1; ++i) Z[i * ld + j] *= sc;
   return gr / nrm;
 }
 
-// Eigenvector of T for eigenvalue j (bracket lo..hi) into column j of Z (ld n),
-// with Rayleigh-quotient corrections; returns the eigenvalue.
+// Eigenvector of T (size n) for eigenvalue j (bracket lo..hi) into column j of Z
+// (leading dimension ld), with Rayleigh-quotient corrections; returns the eigenvalue.
 __device__ inline double tl_vector(const double* vd, const double* ve, const double* ve2, int b0, int b1, double lo,
-                            double hi, double tn, double pivmin, double* Z, int n, int j) {
+                            double hi, double tn, double pivmin, double* Z, int n, int j, int ld) {
   const double eps = DBL_EPSILON;
-  for (int i = 0; i < b0; ++i) Z[i * n + j] = 0.0;
-  for (int i = b1; i < n; ++i) Z[i * n + j] = 0.0;
+  for (int i = 0; i < b0; ++i) Z[i * ld + j] = 0.0;
+  for (int i = b1; i < n; ++i) Z[i * ld + j] = 0.0;
   double lam = 0.5 * (lo + hi);
   if (b1 - b0 == 1) {
-    Z[b0 * n + j] = 1.0;
+    Z[b0 * ld + j] = 1.0;
     return vd[b0];
   }
-  double dl = tl_twisted(vd, ve, ve2, b0, b1, lam, pivmin, Z, n, j);
+  double dl = tl_twisted(vd, ve, ve2, b0, b1, lam, pivmin, Z, ld, j);
   for (int it = 0; it < TL_RQI_MAX && fabs(dl) > 2.0 * eps * tn; ++it) {
     const double nl = lam + dl;
     if (!(nl >= lo && nl <= hi)) break;
     lam = nl;
-    dl = tl_twisted(vd, ve, ve2, b0, b1, lam, pivmin, Z, n, j);
+    dl = tl_twisted(vd, ve, ve2, b0, b1, lam, pivmin, Z, ld, j);
   }
   const double nl = lam + dl;
   return (nl >= lo && nl <= hi) ? nl : lam;
