@@ -1,8 +1,21 @@
-// FP64 symmetric eigensolver for large n: block-cyclic Jacobi with matrix-core updates.
+// FP64 symmetric eigensolver for large n (the ov matrix P = B B^T, n > 88).
 //
-// The matrix (padded with zero rows/columns to npad = 64 * ceil(n / 64), which
-// never rotate) is split into nb = npad / 32 blocks of 32 indices.  A sweep runs
-// nb - 1 rounds of the round-robin pairing of the blocks.  In a round:
+// Main path (Sec. 3.4 asks only for the eigenpairs of iA; the method here is the
+// classical one for dense symmetric matrices):
+//   1. tb_reduce: Householder reduction A = Q T Q^T by all CUs together, one grid
+//      barrier per step (below);
+//   2. tb_bisect: eigenvalue brackets of T by multisection on Sturm counts;
+//   3. tb_vectors: eigenvectors of T by twisted factorizations, one lane each;
+//   4. on the host stream: Z^T Z and one Newton-Schulz step (grouped GEMMs), the
+//      back-transform X = Q Z in compact-WY blocks of TB_NBW reflectors, and a
+//      final residual check of sym(P) X = X diag(w).
+// Every check that fails leaves *ok = 0.
+//
+// Fallback: block-cyclic Jacobi with matrix-core updates.  It returns at once
+// when *ok is set.  The matrix (padded with zero rows/columns to
+// npad = 64 * ceil(n / 64), which never rotate) is split into nb = npad / 32
+// blocks of 32 indices, and a sweep runs nb - 1 rounds of the round-robin
+// pairing of the blocks.  In a round:
 //   1. bjl_inner: every block pair (I, J) is one workgroup: it loads the 64 x 64
 //      subproblem S = A[{I,J},{I,J}] into LDS and applies ONE sweep of the
 //      parallel cyclic Jacobi of eigh.hip to it, accumulating the orthogonal
