@@ -111,6 +111,21 @@ def stage_profile(h, A, E, G, reps=5):
     return info
 
 
+def gemm_kernel_table(h, prof):
+    """Kernel of every GEMM stage; for the split-precision stages also the two launch
+    times the tuning at handle creation measured (tile64 / packed128, ms)."""
+    names = {r["index"]: r["name"] for r in prof}
+    out = {}
+    for k in h.stage_kernels():
+        if not k["kernel"]:
+            continue
+        entry = {"kernel": k["kernel"]}
+        if k["tuned_ms_tile64"] > 0 or k["tuned_ms_packed128"] > 0:
+            entry["tuned_ms"] = [round(k["tuned_ms_tile64"], 4), round(k["tuned_ms_packed128"], 4)]
+        out[names.get(k["index"], str(k["index"]))] = entry
+    return out
+
+
 def oracle_reference(wl, params):
     """Per-instance E and g from the FP64 oracle and its wall time: the definition path
     (eigendecomposition of iA), or for M > 2000 the structured path (the M x M complex
@@ -265,6 +280,7 @@ def main():
         "parity": {"max_dE_per_electron": dE, "max_rel_dg": dg,
                    "target_dE_per_electron": 1e-8, "target_rel_dg": 1e-6},
         "stages_ms": {r["name"]: round(r["total_ms"] / max(r["launches"], 1), 5) for r in prof if r["launches"]},
+        "gemm_kernels": gemm_kernel_table(h, prof),
     }
     if not args.no_fp64_compare and prec != "fp64":
         h64, A64, E64, G64 = build_handle(wl, "fp64")

@@ -42,6 +42,38 @@ void launch_zgemm(const GemmProb* d_probs, int nprob, int total_tiles, int opA, 
                   hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// split-precision GEMM on pre-split operands (large problems, gemm_split.hip)
+// ---------------------------------------------------------------------------
+constexpr int PK_R = 64;  // rows per panel of a packed operand
+constexpr int PK_K = 32;  // k per k-tile
+constexpr int PK_S = 3;   // BF16 slices per value
+// Pack op(X) = alpha * (trans ? X^T : X) (rows x K, FP64 row-major X with leading
+// dimension ld) into k-tiles [kt0, kt0 + ceil(K / 32)) of a packed operand with
+// ktiles k-tiles per panel.  The job covers 2 ceil(rows / 128) panels (zero rows
+// past the end); begin is the prefix sum of chunks (panels x kt_n) over the jobs.
+struct PackJob {
+  const double* src;
+  __bf16* dst;
+  int64_t ld;
+  double alpha;
+  int32_t trans, rows, K, kt0, ktiles, kt_n, begin;
+};
+// C (m x n, FP64) = sum over k of A[i][k] B[j][k] + beta D for packed A (m rows) and
+// B (n rows) with ktiles k-tiles; 128 x 128 tiles, begin = prefix sum of tiles.
+struct SplitProb {
+  const __bf16* A;
+  const __bf16* B;
+  const double* D;
+  double* C;
+  int64_t ldc, ldd;
+  double beta;
+  int32_t m, n, ktiles, tiles_m, tiles_n, begin;
+};
+constexpr int SPLIT_TILE = 128;
+void launch_split_pack(const PackJob* d_jobs, int njobs, int chunks, hipStream_t s);
+void launch_gemm_x6_packed(const SplitProb* d_probs, int nprob, int tiles, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Jacobi eigensolver (FP64), one workgroup per matrix
 // ---------------------------------------------------------------------------
 struct EighProb {

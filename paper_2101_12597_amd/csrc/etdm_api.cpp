@@ -55,12 +55,23 @@ void gauss_legendre01(int n, double* t, double* w) {
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // One grouped GEMM launch.  Problems are added at plan time and uploaded once.
+// A BF16x6 stage has two kernels: the grouped 64 x 64 kernel that splits the
+// operands inside every tile ("tile64"), and split_pack + gemm_x6_packed, which
+// split each operand once into a packed buffer shared by all stages ("packed128").
+// Which one runs is chosen at plan time (tune_stage).
 struct Stage {
   std::vector<GemmProb> probs;
   GemmProb* d = nullptr;
   int tiles = 0;
   int opA = OP_N, opB = OP_N, prec = GP_FP64;
   bool cplx = false;
+  bool packed = false;
+  std::vector<PackJob> pjobs;
+  std::vector<SplitProb> sprobs;
+  PackJob* d_pjobs = nullptr;
+  SplitProb* d_sprobs = nullptr;
+  int pchunks = 0, stiles = 0;
+  float tuned_ms[2] = {0.f, 0.f};  // plan-time launch times of tile64 / packed128 (0: not timed)
   void init(int a, int b, int p, bool c = false) {
     opA = a;
     opB = b;
@@ -74,10 +85,95 @@ struct Stage {
     tiles += p.tiles_n * ceil_div(p.m, GEMM_BM);
     probs.push_back(p);
   }
+  bool can_pack() const { return !cplx && prec == GP_BF16X6 && !probs.empty(); }
+  static int ktiles(const GemmProb& p) {
+    return ceil_div(std::max(p.k, 0), PK_K) + ceil_div(std::max(p.k2, 0), PK_K);
+  }
+  static int panels(int rows) { return 2 * ceil_div(rows, SPLIT_TILE); }
+  // BF16 values of the packed operands of all problems
+  size_t pack_elems() const {
+    size_t n = 0;
+    for (const GemmProb& p : probs)
+      n += (size_t)(panels(p.m) + panels(p.n)) * ktiles(p) * PK_S * PK_R * PK_K;
+    return n;
+  }
+  // pack jobs and packed problems with the operands at arena (pack_elems() values)
+  void plan_pack(__bf16* arena) {
+    pjobs.clear();
+    sprobs.clear();
+    pchunks = stiles = 0;
+    const size_t chunk = (size_t)PK_S * PK_R * PK_K;
+    size_t off = 0;
+    auto job = [&](const double* src, __bf16* dst, int64_t ld, double alpha, bool trans, int rows, int K,
+                   int kt0, int kt, int np) {
+      if (K <= 0) return;
+      PackJob j;
+      j.src = src;
+      j.dst = dst;
+      j.ld = ld;
+      j.alpha = alpha;
+      j.trans = trans ? 1 : 0;
+      j.rows = rows;
+      j.K = K;
+      j.kt0 = kt0;
+      j.ktiles = kt;
+      j.kt_n = ceil_div(K, PK_K);
+      j.begin = pchunks;
+      pchunks += np * j.kt_n;
+      pjobs.push_back(j);
+    };
+    for (const GemmProb& p : probs) {
+      const int kt = ktiles(p), kt1 = ceil_div(std::max(p.k, 0), PK_K);
+      const int pa = panels(p.m), pb = panels(p.n);
+      __bf16* a = arena + off;
+      off += (size_t)pa * kt * chunk;
+      __bf16* b = arena + off;
+      off += (size_t)pb * kt * chunk;
+      // op(A)[i][k] = TA ? A[k][i] : A[i][k];  op(B)^T[j][k] = TB ? B[j][k] : B[k][j]
+      job(p.A, a, p.lda, p.alpha, opA == OP_T, p.m, p.k, 0, kt, pa);
+      job(p.B, b, p.ldb, 1.0, opB != OP_T, p.n, p.k, 0, kt, pb);
+      job(p.A2, a, p.lda2, p.alpha2, opA == OP_T, p.m, p.k2, kt1, kt, pa);
+      job(p.B2, b, p.ldb2, 1.0, opB != OP_T, p.n, p.k2, kt1, kt, pb);
+      SplitProb sp;
+      sp.A = a;
+      sp.B = b;
+      sp.D = p.D;
+      sp.C = p.C;
+      sp.ldc = p.ldc;
+      sp.ldd = p.ldd;
+      sp.beta = p.beta;
+      sp.m = p.m;
+      sp.n = p.n;
+      sp.ktiles = kt;
+      sp.tiles_m = ceil_div(p.m, SPLIT_TILE);
+      sp.tiles_n = ceil_div(p.n, SPLIT_TILE);
+      sp.begin = stiles;
+      stiles += sp.tiles_m * sp.tiles_n;
+      sprobs.push_back(sp);
+    }
+  }
+  // the fixed rule when no timing is wanted: packed when every problem fills
+  // 128 x 128 tiles and its K is long enough to amortize the split
+  bool pack_by_size() const {
+    for (const GemmProb& p : probs)
+      if (p.m < SPLIT_TILE || p.n < SPLIT_TILE || p.k + std::max(p.k2, 0) < 256) return false;
+    return true;
+  }
+  const char* variant() const {
+    if (cplx) return "zgemm64";
+    if (prec != GP_BF16X6) return prec == GP_FP64 ? "fp64_tile64" : "tile64";
+    return packed ? "packed128" : "tile64";
+  }
   void launch(hipStream_t s) const {
     if (probs.empty()) return;
-    if (cplx) launch_zgemm(d, (int)probs.size(), tiles, opA, opB, s);
-    else launch_gemm(d, (int)probs.size(), tiles, opA, opB, prec, s);
+    if (packed) {
+      launch_split_pack(d_pjobs, (int)pjobs.size(), pchunks, s);
+      launch_gemm_x6_packed(d_sprobs, (int)sprobs.size(), stiles, s);
+    } else if (cplx) {
+      launch_zgemm(d, (int)probs.size(), tiles, opA, opB, s);
+    } else {
+      launch_gemm(d, (int)probs.size(), tiles, opA, opB, prec, s);
+    }
   }
 };
 
@@ -218,6 +314,10 @@ struct etdm_handle {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // packed operands of the split-precision stages (shared: stages run in order)
+  __bf16* pack_arena = nullptr;
+  int gemm_tuning = 0;
+  std::vector<Stage*> timer_stage;  // per timed stage: its GEMM launch, or null
   // tracing
   std::vector<StageTimer> timers;
   int64_t tmask = 0;
@@ -436,6 +536,60 @@ etdm_status upload(etdm_handle* h, T** dst, const std::vector<T>& v) {
 
 etdm_status upload_stage(etdm_handle* h, Stage& s) { return upload(h, &s.d, s.probs); }
 
+// Packed operands for every split-precision stage: one arena of the largest
+// stage's size (the stages of a launch sequence run one after another).
+etdm_status plan_packed_stages(etdm_handle* h, Stage* const* stages, size_t n) {
+  size_t elems = 0;
+  for (size_t i = 0; i < n; ++i)
+    if (stages[i]->can_pack()) elems = std::max(elems, stages[i]->pack_elems());
+  if (elems == 0) return ETDM_OK;
+  void* p = nullptr;
+  HIPCHK(h, hipMalloc(&p, elems * sizeof(__bf16)));
+  h->dev_allocs.push_back(p);
+  h->pack_arena = reinterpret_cast<__bf16*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    Stage& sg = *stages[i];
+    if (!sg.can_pack()) continue;
+    sg.plan_pack(h->pack_arena);
+    CHECK(upload(h, &sg.d_pjobs, sg.pjobs));
+    CHECK(upload(h, &sg.d_sprobs, sg.sprobs));
+    sg.packed = sg.pack_by_size();
+  }
+  return ETDM_OK;
+}
+
+// Plan-time choice between the two kernels of a split-precision stage: both run
+// on the handle's own buffers (every evaluation overwrites what they write), one
+// warm-up and three timed launches each, and the faster is kept.
+etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
+  if (h->gemm_tuning != 0) return ETDM_OK;
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  etdm_status st = ETDM_OK;
+  for (Stage* sg : h->timer_stage) {
+    if (!sg || !sg->can_pack()) continue;
+    for (int v = 0; v < 2 && st == ETDM_OK; ++v) {
+      sg->packed = v == 1;
+      sg->launch(s);
+      float ms = 0.f;
+      if (hipEventRecord(e0, s) != hipSuccess) st = ETDM_E_HIP;
+      for (int r = 0; r < 3; ++r) sg->launch(s);
+      if (st == ETDM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = ETDM_E_HIP;
+      sg->tuned_ms[v] = ms / 3.f;
+    }
+    if (st != ETDM_OK) break;
+    sg->packed = sg->tuned_ms[1] < sg->tuned_ms[0];
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != ETDM_OK) return fail(h, st, "GEMM kernel tuning failed");
+  HIPCHK(h, hipGetLastError());
+  return ETDM_OK;
+}
+
 // ----- plan of the real occupied-virtual path ------------------------------
 etdm_status build_ov_plan(etdm_handle* h) {
   // precision by role: ep for the contractions E depends on, gp for the gradient-only ones
@@ -556,7 +710,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
   {
     h->timers.assign(O_COUNT, StageTimer());
     for (int i = 0; i < O_COUNT; ++i) h->timers[i].name = kOvNames[i];
-    const Stage* gs[O_COUNT] = {};
+    Stage* gs[O_COUNT] = {};
     gs[O_PQ] = &h->s_PQ;
     gs[O_F3MU] = &h->s_F3mu;
     gs[O_C] = &h->s_C;
@@ -570,6 +724,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
     gs[O_Y1] = &h->s_Y1;
     gs[O_Y2] = &h->s_Y2;
     gs[O_G] = &h->s_G;
+    h->timer_stage.assign(gs, gs + O_COUNT);
     for (int i = 0; i < O_COUNT; ++i)
       if (gs[i]) {
         h->timers[i].flops = stage_flops(*gs[i]);
@@ -602,6 +757,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
                      &h->s_R,   &h->s_Gam1, &h->s_Gam, &h->s_Y1, &h->s_Y2, &h->s_G,  &h->s_Uov,
                      &h->s_Uvv, &h->s_HC0};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
+  CHECK(plan_packed_stages(h, stages, sizeof(stages) / sizeof(stages[0])));
   if (!h->eig_large.empty()) {
     h->s_LG.init(OP_T, OP_N, GP_FP64);
     h->s_LNS.init(OP_N, OP_N, GP_FP64);
@@ -731,7 +887,7 @@ etdm_status build_z_plan(etdm_handle* h) {
   {
     h->timers.assign(Z_COUNT, StageTimer());
     for (int i = 0; i < Z_COUNT; ++i) h->timers[i].name = kZNames[i];
-    const Stage* gs[Z_COUNT] = {};
+    Stage* gs[Z_COUNT] = {};
     gs[Z_UE] = &h->z_Ue;
     gs[Z_C] = &h->z_C;
     gs[Z_T] = &h->z_T;
@@ -740,6 +896,7 @@ etdm_status build_z_plan(etdm_handle* h) {
     gs[Z_LT] = &h->z_Lt;
     gs[Z_W1] = &h->z_W1;
     gs[Z_Y] = &h->z_Y;
+    h->timer_stage.assign(gs, gs + Z_COUNT);
     for (int i = 0; i < Z_COUNT; ++i)
       if (gs[i]) {
         h->timers[i].flops = stage_flops(*gs[i]);
@@ -1259,6 +1416,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (d->kind != ETDM_REAL_OV && d->kind != ETDM_COMPLEX_FULL) return ETDM_E_ARG;
   if (d->precision < ETDM_FP64 || d->precision > ETDM_MIXED) return ETDM_E_ARG;
   if (d->kind == ETDM_COMPLEX_FULL && d->precision != ETDM_FP64) return ETDM_E_ARG;
+  if (d->gemm_tuning < 0 || d->gemm_tuning > 1) return ETDM_E_ARG;
   if (d->kind == ETDM_REAL_OV && (!d->N || d->couple)) return ETDM_E_ARG;
   if (d->h0_format != 0 && d->h0_format != 1) return ETDM_E_ARG;
   if (d->h0_format == 1 && (d->kind != ETDM_REAL_OV || d->bsr_block < 1 || d->bsr_block > BSR_MAX_BS ||
@@ -1279,6 +1437,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
       h->cu_count = std::max(1, cus);
   }
   h->prec = d->precision;
+  h->gemm_tuning = d->gemm_tuning;
   h->U = d->hubbard_U;
   h->couple = d->couple ? 1 : 0;
   h->h0_format = d->h0_format;
@@ -1391,6 +1550,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
     blk_off += nnzb;
   }
   etdm_status st = real ? build_ov_plan(h) : build_z_plan(h);
+  if (st == ETDM_OK) st = tune_stages(h, s);
   if (st != ETDM_OK) return bail(st);
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) return bail(ETDM_E_HIP);
   *out = h;
@@ -1506,6 +1666,16 @@ etdm_status etdm_stage_info(etdm_handle* h, int32_t i, const char** name, int64_
   if (total_ms) *total_ms = t.total_ms;
   if (flops) *flops = t.flops;
   if (bytes) *bytes = t.bytes;
+  return ETDM_OK;
+}
+
+etdm_status etdm_stage_kernel(const etdm_handle* h, int32_t i, const char** variant, double* ms_tile,
+                              double* ms_packed) {
+  if (!h || i < 0 || i >= (int32_t)h->timers.size()) return ETDM_E_ARG;
+  const Stage* sg = i < (int32_t)h->timer_stage.size() ? h->timer_stage[i] : nullptr;
+  if (variant) *variant = sg && !sg->probs.empty() ? sg->variant() : "";
+  if (ms_tile) *ms_tile = sg ? sg->tuned_ms[0] : 0.0;
+  if (ms_packed) *ms_packed = sg ? sg->tuned_ms[1] : 0.0;
   return ETDM_OK;
 }
 

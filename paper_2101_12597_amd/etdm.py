@@ -46,6 +46,7 @@ class _Desc(ctypes.Structure):
         ("bsr_block", ctypes.c_int32),
         ("bsr_row_ptr", ctypes.POINTER(ctypes.c_int32)),
         ("bsr_col_idx", ctypes.POINTER(ctypes.c_int32)),
+        ("gemm_tuning", ctypes.c_int32),
     ]
 
 
@@ -71,7 +72,7 @@ EXPORTS = [
     "etdm_create", "etdm_destroy", "etdm_expm", "etdm_energy_grad", "etdm_set_reference",
     "etdm_lbfgs_defaults", "etdm_lbfgs_step", "etdm_sync_status", "etdm_status_string",
     "etdm_last_error", "etdm_param_count", "etdm_set_timing", "etdm_reset_timing",
-    "etdm_stage_count", "etdm_stage_info", "etdm_set_graph",
+    "etdm_stage_count", "etdm_stage_info", "etdm_stage_kernel", "etdm_set_graph",
 ]
 
 _lib = None
@@ -121,6 +122,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.etdm_stage_info.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(i64),
                                   ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     L.etdm_stage_info.restype = i32
+    L.etdm_stage_kernel.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(dbl),
+                                    ctypes.POINTER(dbl)]
+    L.etdm_stage_kernel.restype = i32
     _lib = L
     return L
 
@@ -158,11 +162,14 @@ class Handle:
          packed BSR blocks when ``bsr`` = (block, row_ptr, col_idx) is given
     C0 : device tensor, packed M x M reference orbitals
     f : host array of occupations, packed [sum M]
+    gemm_tuning : 0 = time the candidate kernels of each BF16x6 stage at creation
+                  and keep the faster, 1 = fixed size rule
     """
 
     def __init__(self, M: Sequence[int], N: Optional[Sequence[int]], kind: str, precision: str,
                  hubbard_U: float, H0, C0, f: np.ndarray, couple: bool = False,
-                 weights: Optional[Sequence[float]] = None, bsr=None, stream=None):
+                 weights: Optional[Sequence[float]] = None, bsr=None, stream=None,
+                 gemm_tuning: int = 0):
         L = load_library()
         self._L = L
         n = len(M)
@@ -180,6 +187,7 @@ class Handle:
         d.hubbard_U = float(hubbard_U)
         d.couple = int(bool(couple))
         d.weights = self._w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.gemm_tuning = int(gemm_tuning)
         if bsr is not None:
             blk, rp, ci = bsr
             self._rp = np.ascontiguousarray(rp, dtype=np.int32)
@@ -260,6 +268,19 @@ class Handle:
                         "etdm_stage_info")
             out.append(dict(index=i, name=name.value.decode(), launches=n.value, total_ms=ms.value,
                             flops=fl.value, bytes=by.value))
+        return out
+
+    def stage_kernels(self) -> list:
+        """Per stage: its GEMM kernel ("" if not a GEMM) and the launch times of the two
+        split-precision kernels measured by the tuning at creation (0 if not timed)."""
+        out = []
+        for i in range(int(self._L.etdm_stage_count(self._h))):
+            v = ctypes.c_char_p()
+            t0, t1 = ctypes.c_double(), ctypes.c_double()
+            self._check(self._L.etdm_stage_kernel(self._h, i, ctypes.byref(v), ctypes.byref(t0),
+                                                  ctypes.byref(t1)), "etdm_stage_kernel")
+            out.append(dict(index=i, kernel=v.value.decode(), tuned_ms_tile64=t0.value,
+                            tuned_ms_packed128=t1.value))
         return out
 
     def sync_status(self, stream=None):

@@ -46,3 +46,27 @@ def test_host_only_calls(repo_root):
     assert lib.etdm_energy_grad(None, None, None, None, None) == -1
     assert lib.etdm_destroy(None) == -1
     assert lib.etdm_param_count(None) == 0
+
+
+def test_create_rejects_bad_gemm_tuning(repo_root):
+    """gemm_tuning outside {0, 1} is an argument error, found before any device call."""
+    from paper_2101_12597_amd import LIB_PATH, load_library
+    from paper_2101_12597_amd.etdm import _Desc
+    if not os.path.exists(LIB_PATH):
+        pytest.skip("libetdm.so not built")
+    lib = load_library()
+    M = (ctypes.c_int32 * 1)(64)
+    N = (ctypes.c_int32 * 1)(16)
+    f = (ctypes.c_double * 64)(*([2.0] * 16 + [0.0] * 48))
+    for bad in (-1, 2):
+        d = _Desc()
+        d.n_inst = 1
+        d.M = M
+        d.N = N
+        d.kind = 0
+        d.precision = 4
+        d.gemm_tuning = bad
+        h = ctypes.c_void_p()
+        dummy = ctypes.c_void_p(8)  # never dereferenced: validation fails first
+        assert lib.etdm_create(ctypes.byref(h), ctypes.byref(d), dummy, dummy, f, None) == -1
+        assert h.value is None
