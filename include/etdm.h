@@ -98,11 +98,12 @@ typedef struct {
   int32_t bsr_block;      /* block size when h0_format = 1 (M divisible by it) */
   const int32_t *bsr_row_ptr; /* host, per instance (M/bs + 1) entries, concatenated */
   const int32_t *bsr_col_idx; /* host, per instance row_ptr[last] entries, concatenated */
-  int32_t gemm_tuning;    /* kernel choice of the BF16x6 stages (ETDM_BF16X6, ETDM_MIXED):
+  int32_t gemm_tuning;    /* kernel choice of the real FP64 and BF16x6 GEMM stages:
                              0 = time both kernels on the handle's buffers in etdm_create
-                             and keep the faster; 1 = fixed rule (pre-split 128 x 128
-                             tiles when every problem of the stage is at least 128 x 128
-                             with K >= 256).  Other values: ETDM_E_ARG */
+                             and keep the faster; 1 = fixed rule (packed 128 x 128 tiles
+                             when every problem of the stage is at least 128 x 128 with
+                             K >= 256); 2 = always packed; 3 = always 64 x 64 tiles.
+                             Other values: ETDM_E_ARG */
 } etdm_desc;
 
 /* Create a handle.  H0: device, dense float64 (REAL_OV) or complex float64
@@ -194,9 +195,10 @@ int32_t etdm_stage_count(const etdm_handle *h);
 etdm_status etdm_stage_info(etdm_handle *h, int32_t i, const char **name, int64_t *launches,
                             double *total_ms, double *flops, double *bytes);
 
-/* GEMM kernel of stage i: *variant = "tile64" (grouped 64 x 64 tiles, operands
- * split in every tile), "packed128" (operands split once per launch into a
- * packed buffer, 128 x 128 tiles), "fp64_tile64", "zgemm64", or "" for a stage
+/* GEMM kernel of stage i: *variant = "tile64" / "fp64_tile64" (grouped 64 x 64
+ * tiles reading, and for BF16x6 splitting, the operands in every tile),
+ * "packed128" / "fp64_packed128" (operands packed, and split, once per launch
+ * into a panel buffer, 128 x 128 tiles), "zgemm64" (complex), or "" for a stage
  * that is not a GEMM; ms_tile / ms_packed = the launch times measured by the
  * tuning in etdm_create (0 when not timed).  Any output pointer may be NULL. */
 etdm_status etdm_stage_kernel(const etdm_handle *h, int32_t i, const char **variant, double *ms_tile,

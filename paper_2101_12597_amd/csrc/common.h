@@ -11,7 +11,8 @@ namespace etdm {
 //   C = alpha * op(A) op(B) + alpha2 * op(A2) op(B2) + beta * D
 // op(A) is m x k, op(B) is k x n (second segment: k2).  All problems of one
 // launch share the transposition flags.  Every workgroup computes one 64 x 64
-// tile; tile_begin is the prefix sum of tiles over the problem list.
+// tile; tile_begin is the prefix sum of tiles over the problem list, and the
+// launch's tile table maps each workgroup to its problem.
 // ---------------------------------------------------------------------------
 struct GemmProb {
   const double* A;
@@ -33,12 +34,12 @@ constexpr int GEMM_BM = 64;
 constexpr int GEMM_BN = 64;
 
 // Real grouped GEMM; opA/opB in {OP_N, OP_T}.
-void launch_gemm(const GemmProb* d_probs, int nprob, int total_tiles, int opA, int opB, int prec,
+void launch_gemm(const GemmProb* d_probs, const int* d_tile_prob, int total_tiles, int opA, int opB, int prec,
                  hipStream_t s);
 // Complex (interleaved re,im float64) grouped GEMM; the double pointers in the
 // problems address complex elements, leading dimensions count complex elements,
 // alpha/alpha2/beta are real.  opA/opB in {OP_N, OP_T, OP_C}.
-void launch_zgemm(const GemmProb* d_probs, int nprob, int total_tiles, int opA, int opB,
+void launch_zgemm(const GemmProb* d_probs, const int* d_tile_prob, int total_tiles, int opA, int opB,
                   hipStream_t s);
 
 // ---------------------------------------------------------------------------
@@ -51,9 +52,10 @@ constexpr int PK_S = 3;   // BF16 slices per value
 // dimension ld) into k-tiles [kt0, kt0 + ceil(K / 32)) of a packed operand with
 // ktiles k-tiles per panel.  The job covers 2 ceil(rows / 128) panels (zero rows
 // past the end); begin is the prefix sum of chunks (panels x kt_n) over the jobs.
+// dst: BF16 slices (split_pack) or FP64 values (copy_pack64).
 struct PackJob {
   const double* src;
-  __bf16* dst;
+  void* dst;
   int64_t ld;
   double alpha;
   int32_t trans, rows, K, kt0, ktiles, kt_n, begin;
@@ -61,8 +63,8 @@ struct PackJob {
 // C (m x n, FP64) = sum over k of A[i][k] B[j][k] + beta D for packed A (m rows) and
 // B (n rows) with ktiles k-tiles; 128 x 128 tiles, begin = prefix sum of tiles.
 struct SplitProb {
-  const __bf16* A;
-  const __bf16* B;
+  const void* A;
+  const void* B;
   const double* D;
   double* C;
   int64_t ldc, ldd;
@@ -70,7 +72,11 @@ struct SplitProb {
   int32_t m, n, ktiles, tiles_m, tiles_n, begin;
 };
 constexpr int SPLIT_TILE = 128;
+constexpr int PK_CHUNK_X6 = PK_S * PK_R * PK_K;  // BF16 values of a split chunk
+constexpr int PK_CHUNK_64 = PK_R * PK_K;         // FP64 values of an FP64 chunk
 void launch_split_pack(const PackJob* d_jobs, int njobs, int chunks, hipStream_t s);
+void launch_copy_pack64(const PackJob* d_jobs, int njobs, int chunks, hipStream_t s);
+void launch_gemm_f64_packed(const SplitProb* d_probs, int nprob, int tiles, hipStream_t s);
 void launch_gemm_x6_packed(const SplitProb* d_probs, int nprob, int tiles, hipStream_t s);
 
 // ---------------------------------------------------------------------------

@@ -55,13 +55,16 @@ void gauss_legendre01(int n, double* t, double* w) {
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // One grouped GEMM launch.  Problems are added at plan time and uploaded once.
-// A BF16x6 stage has two kernels: the grouped 64 x 64 kernel that splits the
-// operands inside every tile ("tile64"), and split_pack + gemm_x6_packed, which
-// split each operand once into a packed buffer shared by all stages ("packed128").
-// Which one runs is chosen at plan time (tune_stage).
+// A real FP64 or BF16x6 stage has two kernels: the grouped 64 x 64 kernel that
+// reads (and splits) the operands inside every tile ("tile64"), and a pack pass
+// into a panel layout shared by all stages followed by the 128 x 128 kernel
+// ("packed128": copy_pack64 + gemm_f64_packed, or split_pack + gemm_x6_packed).
+// Which one runs is chosen at plan time (tune_stages).
 struct Stage {
   std::vector<GemmProb> probs;
+  std::vector<int32_t> tile_prob;  // workgroup -> problem
   GemmProb* d = nullptr;
+  int32_t* d_tile_prob = nullptr;
   int tiles = 0;
   int opA = OP_N, opB = OP_N, prec = GP_FP64;
   bool cplx = false;
@@ -83,28 +86,31 @@ struct Stage {
     p.tiles_n = ceil_div(p.n, GEMM_BN);
     p.tile_begin = tiles;
     tiles += p.tiles_n * ceil_div(p.m, GEMM_BM);
+    tile_prob.resize(tiles, (int32_t)probs.size());
     probs.push_back(p);
   }
-  bool can_pack() const { return !cplx && prec == GP_BF16X6 && !probs.empty(); }
+  bool can_pack() const { return !cplx && (prec == GP_BF16X6 || prec == GP_FP64) && !probs.empty(); }
+  size_t chunk_bytes() const {
+    return prec == GP_FP64 ? (size_t)PK_CHUNK_64 * sizeof(double) : (size_t)PK_CHUNK_X6 * sizeof(__bf16);
+  }
   static int ktiles(const GemmProb& p) {
     return ceil_div(std::max(p.k, 0), PK_K) + ceil_div(std::max(p.k2, 0), PK_K);
   }
   static int panels(int rows) { return 2 * ceil_div(rows, SPLIT_TILE); }
-  // BF16 values of the packed operands of all problems
-  size_t pack_elems() const {
+  // bytes of the packed operands of all problems
+  size_t pack_bytes() const {
     size_t n = 0;
-    for (const GemmProb& p : probs)
-      n += (size_t)(panels(p.m) + panels(p.n)) * ktiles(p) * PK_S * PK_R * PK_K;
+    for (const GemmProb& p : probs) n += (size_t)(panels(p.m) + panels(p.n)) * ktiles(p) * chunk_bytes();
     return n;
   }
-  // pack jobs and packed problems with the operands at arena (pack_elems() values)
-  void plan_pack(__bf16* arena) {
+  // pack jobs and packed problems with the operands at arena (pack_bytes() bytes)
+  void plan_pack(char* arena) {
     pjobs.clear();
     sprobs.clear();
     pchunks = stiles = 0;
-    const size_t chunk = (size_t)PK_S * PK_R * PK_K;
+    const size_t chunk = chunk_bytes();
     size_t off = 0;
-    auto job = [&](const double* src, __bf16* dst, int64_t ld, double alpha, bool trans, int rows, int K,
+    auto job = [&](const double* src, char* dst, int64_t ld, double alpha, bool trans, int rows, int K,
                    int kt0, int kt, int np) {
       if (K <= 0) return;
       PackJob j;
@@ -125,9 +131,9 @@ struct Stage {
     for (const GemmProb& p : probs) {
       const int kt = ktiles(p), kt1 = ceil_div(std::max(p.k, 0), PK_K);
       const int pa = panels(p.m), pb = panels(p.n);
-      __bf16* a = arena + off;
+      char* a = arena + off;
       off += (size_t)pa * kt * chunk;
-      __bf16* b = arena + off;
+      char* b = arena + off;
       off += (size_t)pb * kt * chunk;
       // op(A)[i][k] = TA ? A[k][i] : A[i][k];  op(B)^T[j][k] = TB ? B[j][k] : B[k][j]
       job(p.A, a, p.lda, p.alpha, opA == OP_T, p.m, p.k, 0, kt, pa);
@@ -161,18 +167,21 @@ struct Stage {
   }
   const char* variant() const {
     if (cplx) return "zgemm64";
-    if (prec != GP_BF16X6) return prec == GP_FP64 ? "fp64_tile64" : "tile64";
+    if (prec == GP_FP64) return packed ? "fp64_packed128" : "fp64_tile64";
     return packed ? "packed128" : "tile64";
   }
   void launch(hipStream_t s) const {
     if (probs.empty()) return;
-    if (packed) {
+    if (packed && prec == GP_FP64) {
+      launch_copy_pack64(d_pjobs, (int)pjobs.size(), pchunks, s);
+      launch_gemm_f64_packed(d_sprobs, (int)sprobs.size(), stiles, s);
+    } else if (packed) {
       launch_split_pack(d_pjobs, (int)pjobs.size(), pchunks, s);
       launch_gemm_x6_packed(d_sprobs, (int)sprobs.size(), stiles, s);
     } else if (cplx) {
-      launch_zgemm(d, (int)probs.size(), tiles, opA, opB, s);
+      launch_zgemm(d, d_tile_prob, tiles, opA, opB, s);
     } else {
-      launch_gemm(d, (int)probs.size(), tiles, opA, opB, prec, s);
+      launch_gemm(d, d_tile_prob, tiles, opA, opB, prec, s);
     }
   }
 };
@@ -314,8 +323,8 @@ struct etdm_handle {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  // packed operands of the split-precision stages (shared: stages run in order)
-  __bf16* pack_arena = nullptr;
+  // packed operands of the FP64 / BF16x6 stages (shared: stages run in order)
+  char* pack_arena = nullptr;
   int gemm_tuning = 0;
   std::vector<Stage*> timer_stage;  // per timed stage: its GEMM launch, or null
   // tracing
@@ -534,31 +543,34 @@ etdm_status upload(etdm_handle* h, T** dst, const std::vector<T>& v) {
   return ETDM_OK;
 }
 
-etdm_status upload_stage(etdm_handle* h, Stage& s) { return upload(h, &s.d, s.probs); }
+etdm_status upload_stage(etdm_handle* h, Stage& s) {
+  CHECK(upload(h, &s.d, s.probs));
+  return upload(h, &s.d_tile_prob, s.tile_prob);
+}
 
-// Packed operands for every split-precision stage: one arena of the largest
+// Packed operands for every FP64 / BF16x6 stage: one arena of the largest
 // stage's size (the stages of a launch sequence run one after another).
 etdm_status plan_packed_stages(etdm_handle* h, Stage* const* stages, size_t n) {
-  size_t elems = 0;
+  size_t bytes = 0;
   for (size_t i = 0; i < n; ++i)
-    if (stages[i]->can_pack()) elems = std::max(elems, stages[i]->pack_elems());
-  if (elems == 0) return ETDM_OK;
+    if (stages[i]->can_pack()) bytes = std::max(bytes, stages[i]->pack_bytes());
+  if (bytes == 0) return ETDM_OK;
   void* p = nullptr;
-  HIPCHK(h, hipMalloc(&p, elems * sizeof(__bf16)));
+  HIPCHK(h, hipMalloc(&p, bytes));
   h->dev_allocs.push_back(p);
-  h->pack_arena = reinterpret_cast<__bf16*>(p);
+  h->pack_arena = reinterpret_cast<char*>(p);
   for (size_t i = 0; i < n; ++i) {
     Stage& sg = *stages[i];
     if (!sg.can_pack()) continue;
     sg.plan_pack(h->pack_arena);
     CHECK(upload(h, &sg.d_pjobs, sg.pjobs));
     CHECK(upload(h, &sg.d_sprobs, sg.sprobs));
-    sg.packed = sg.pack_by_size();
+    sg.packed = h->gemm_tuning == 2 ? true : h->gemm_tuning == 3 ? false : sg.pack_by_size();
   }
   return ETDM_OK;
 }
 
-// Plan-time choice between the two kernels of a split-precision stage: both run
+// Plan-time choice between the two kernels of an FP64 / BF16x6 stage: both run
 // on the handle's own buffers (every evaluation overwrites what they write), one
 // warm-up and three timed launches each, and the faster is kept.
 etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
@@ -1416,7 +1428,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (d->kind != ETDM_REAL_OV && d->kind != ETDM_COMPLEX_FULL) return ETDM_E_ARG;
   if (d->precision < ETDM_FP64 || d->precision > ETDM_MIXED) return ETDM_E_ARG;
   if (d->kind == ETDM_COMPLEX_FULL && d->precision != ETDM_FP64) return ETDM_E_ARG;
-  if (d->gemm_tuning < 0 || d->gemm_tuning > 1) return ETDM_E_ARG;
+  if (d->gemm_tuning < 0 || d->gemm_tuning > 3) return ETDM_E_ARG;
   if (d->kind == ETDM_REAL_OV && (!d->N || d->couple)) return ETDM_E_ARG;
   if (d->h0_format != 0 && d->h0_format != 1) return ETDM_E_ARG;
   if (d->h0_format == 1 && (d->kind != ETDM_REAL_OV || d->bsr_block < 1 || d->bsr_block > BSR_MAX_BS ||

@@ -33,16 +33,6 @@ constexpr int BM = GEMM_BM, BN = GEMM_BN;
 constexpr int NTHREADS = 256;
 constexpr int FLUSH_K = 128;
 
-__device__ __forceinline__ int find_problem(const GemmProb* __restrict__ probs, int nprob, int bid) {
-  int lo = 0, hi = nprob - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (probs[mid].tile_begin <= bid) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 // ---------------------------------------------------------------------------
 // operand staging: element (r, c) of op(X) for a row-major X
 // ---------------------------------------------------------------------------
@@ -131,11 +121,11 @@ __device__ __forceinline__ void stage_coord(int e, int& kk, int& mm) {
 }
 
 template <typename T, bool TA, bool TB>
-__global__ __launch_bounds__(NTHREADS) void gemm_k4(const GemmProb* __restrict__ probs, int nprob) {
+__global__ __launch_bounds__(NTHREADS) void gemm_k4(const GemmProb* __restrict__ probs, const int* __restrict__ tile_prob) {
   constexpr int BK = K4_BK;
   __shared__ T As[K4_LDS];
   __shared__ T Bs[K4_LDS];
-  const GemmProb& p = probs[find_problem(probs, nprob, blockIdx.x)];
+  const GemmProb& p = probs[tile_prob[blockIdx.x]];
   const int t = blockIdx.x - p.tile_begin;
   const int row0 = (t / p.tiles_n) * BM, col0 = (t % p.tiles_n) * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -251,13 +241,13 @@ __device__ __forceinline__ void octet_task(int t, int& row, int& oct) {
 }
 
 template <int NS, bool TA, bool TB>
-__global__ __launch_bounds__(NTHREADS) void gemm_bf16split(const GemmProb* __restrict__ probs, int nprob) {
+__global__ __launch_bounds__(NTHREADS) void gemm_bf16split(const GemmProb* __restrict__ probs, const int* __restrict__ tile_prob) {
   constexpr int BK = 32;
   // slice-major k-blocked layout: S[slice][kk / 8][row][kk % 8] so that one lane
   // reads its 8 consecutive k values of one row as a single 16-byte vector
   __shared__ __attribute__((aligned(16))) __bf16 As[NS][BK / 8][BM][8];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[NS][BK / 8][BN][8];
-  const GemmProb& p = probs[find_problem(probs, nprob, blockIdx.x)];
+  const GemmProb& p = probs[tile_prob[blockIdx.x]];
   const int t = blockIdx.x - p.tile_begin;
   const int row0 = (t / p.tiles_n) * BM, col0 = (t % p.tiles_n) * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -362,11 +352,11 @@ __device__ __forceinline__ double2 ld_zop(const double2* __restrict__ X, int64_t
 }
 
 template <int OPA, int OPB>
-__global__ __launch_bounds__(NTHREADS) void zgemm_k4(const GemmProb* __restrict__ probs, int nprob) {
+__global__ __launch_bounds__(NTHREADS) void zgemm_k4(const GemmProb* __restrict__ probs, const int* __restrict__ tile_prob) {
   constexpr int BK = 16;
   __shared__ double Ar[BK][BM + 1], Ai[BK][BM + 1];
   __shared__ double Br[BK][BN + 1], Bi[BK][BN + 1];
-  const GemmProb& p = probs[find_problem(probs, nprob, blockIdx.x)];
+  const GemmProb& p = probs[tile_prob[blockIdx.x]];
   const int t = blockIdx.x - p.tile_begin;
   const int row0 = (t / p.tiles_n) * BM, col0 = (t % p.tiles_n) * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -448,40 +438,40 @@ __global__ __launch_bounds__(NTHREADS) void zgemm_k4(const GemmProb* __restrict_
 // launchers
 // ---------------------------------------------------------------------------
 template <bool TA, bool TB>
-static void launch_real(const GemmProb* d, int nprob, int tiles, int prec, hipStream_t s) {
+static void launch_real(const GemmProb* d, const int* tp, int tiles, int prec, hipStream_t s) {
   switch (prec) {
-    case GP_FP64: gemm_k4<double, TA, TB><<<tiles, NTHREADS, 0, s>>>(d, nprob); break;
-    case GP_FP32: gemm_k4<float, TA, TB><<<tiles, NTHREADS, 0, s>>>(d, nprob); break;
-    case GP_BF16X3: gemm_bf16split<2, TA, TB><<<tiles, NTHREADS, 0, s>>>(d, nprob); break;
-    default: gemm_bf16split<3, TA, TB><<<tiles, NTHREADS, 0, s>>>(d, nprob); break;
+    case GP_FP64: gemm_k4<double, TA, TB><<<tiles, NTHREADS, 0, s>>>(d, tp); break;
+    case GP_FP32: gemm_k4<float, TA, TB><<<tiles, NTHREADS, 0, s>>>(d, tp); break;
+    case GP_BF16X3: gemm_bf16split<2, TA, TB><<<tiles, NTHREADS, 0, s>>>(d, tp); break;
+    default: gemm_bf16split<3, TA, TB><<<tiles, NTHREADS, 0, s>>>(d, tp); break;
   }
 }
 
-void launch_gemm(const GemmProb* d_probs, int nprob, int total_tiles, int opA, int opB, int prec,
+void launch_gemm(const GemmProb* d_probs, const int* d_tile_prob, int total_tiles, int opA, int opB, int prec,
                  hipStream_t s) {
-  if (total_tiles <= 0 || nprob <= 0) return;
-  if (opA == OP_N && opB == OP_N) launch_real<false, false>(d_probs, nprob, total_tiles, prec, s);
-  else if (opA == OP_N) launch_real<false, true>(d_probs, nprob, total_tiles, prec, s);
-  else if (opB == OP_N) launch_real<true, false>(d_probs, nprob, total_tiles, prec, s);
-  else launch_real<true, true>(d_probs, nprob, total_tiles, prec, s);
+  if (total_tiles <= 0) return;
+  if (opA == OP_N && opB == OP_N) launch_real<false, false>(d_probs, d_tile_prob, total_tiles, prec, s);
+  else if (opA == OP_N) launch_real<false, true>(d_probs, d_tile_prob, total_tiles, prec, s);
+  else if (opB == OP_N) launch_real<true, false>(d_probs, d_tile_prob, total_tiles, prec, s);
+  else launch_real<true, true>(d_probs, d_tile_prob, total_tiles, prec, s);
 }
 
 template <int OPA>
-static void launch_z_b(const GemmProb* d, int nprob, int tiles, int opB, hipStream_t s) {
+static void launch_z_b(const GemmProb* d, const int* tp, int tiles, int opB, hipStream_t s) {
   switch (opB) {
-    case OP_N: zgemm_k4<OPA, OP_N><<<tiles, NTHREADS, 0, s>>>(d, nprob); break;
-    case OP_T: zgemm_k4<OPA, OP_T><<<tiles, NTHREADS, 0, s>>>(d, nprob); break;
-    default: zgemm_k4<OPA, OP_C><<<tiles, NTHREADS, 0, s>>>(d, nprob); break;
+    case OP_N: zgemm_k4<OPA, OP_N><<<tiles, NTHREADS, 0, s>>>(d, tp); break;
+    case OP_T: zgemm_k4<OPA, OP_T><<<tiles, NTHREADS, 0, s>>>(d, tp); break;
+    default: zgemm_k4<OPA, OP_C><<<tiles, NTHREADS, 0, s>>>(d, tp); break;
   }
 }
 
-void launch_zgemm(const GemmProb* d_probs, int nprob, int total_tiles, int opA, int opB,
+void launch_zgemm(const GemmProb* d_probs, const int* d_tile_prob, int total_tiles, int opA, int opB,
                   hipStream_t s) {
-  if (total_tiles <= 0 || nprob <= 0) return;
+  if (total_tiles <= 0) return;
   switch (opA) {
-    case OP_N: launch_z_b<OP_N>(d_probs, nprob, total_tiles, opB, s); break;
-    case OP_T: launch_z_b<OP_T>(d_probs, nprob, total_tiles, opB, s); break;
-    default: launch_z_b<OP_C>(d_probs, nprob, total_tiles, opB, s); break;
+    case OP_N: launch_z_b<OP_N>(d_probs, d_tile_prob, total_tiles, opB, s); break;
+    case OP_T: launch_z_b<OP_T>(d_probs, d_tile_prob, total_tiles, opB, s); break;
+    default: launch_z_b<OP_C>(d_probs, d_tile_prob, total_tiles, opB, s); break;
   }
 }
 

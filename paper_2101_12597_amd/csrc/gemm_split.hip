@@ -22,6 +22,11 @@
 // accumulates the six slice products with i + j <= 2 in FP32, added into FP64
 // registers every FLUSH k.  k-tiles of 32 are double-buffered in LDS (96 KB)
 // with the next one fetched into registers during the MFMAs.
+//
+// The FP64 pair (copy_pack64, gemm_f64_packed) uses the same panels and tile
+// order without the split: a chunk is [k][row] FP64 (64 x 32 x 8 bytes = 16 KB),
+// so the 16 lanes that share a k of a v_mfma_f64_16x16x4f64 fragment read 128
+// consecutive bytes; 128 KB of LDS double-buffer the k-tiles.
 #include "common.h"
 
 namespace etdm {
@@ -31,8 +36,9 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef int i4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int PK_CHUNK = PK_S * PK_R * PK_K;  // BF16 values of one (panel, k-tile) chunk
+constexpr int PK_CHUNK = PK_CHUNK_X6;
 constexpr int XT = 128;                        // workgroup tile (rows and columns)
 constexpr int XNT = 256;
 constexpr int X_FLUSH = 4;                     // k-tiles between FP64 flushes (128 k)
@@ -94,7 +100,7 @@ __global__ __launch_bounds__(256) void split_pack(const PackJob* __restrict__ jo
       x -= (double)(float)h;
     }
   }
-  __bf16* base = j.dst + ((int64_t)panel * j.ktiles + j.kt0 + q) * PK_CHUNK;
+  __bf16* base = static_cast<__bf16*>(j.dst) + ((int64_t)panel * j.ktiles + j.kt0 + q) * PK_CHUNK;
 #pragma unroll
   for (int s = 0; s < PK_S; ++s)
     *reinterpret_cast<bf8*>(base + (s * PK_R + r) * PK_K + pk_phys(oct, r) * 8) = out[s];
@@ -132,8 +138,8 @@ __global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restric
   // LDS: [buffer][operand][panel][slice][row][k]
   constexpr int OPER = 2 * PK_CHUNK;
   constexpr int BUF = 2 * OPER;
-  const __bf16* Ag = p.A + (int64_t)(2 * tm) * p.ktiles * PK_CHUNK;
-  const __bf16* Bg = p.B + (int64_t)(2 * tn) * p.ktiles * PK_CHUNK;
+  const __bf16* Ag = static_cast<const __bf16*>(p.A) + (int64_t)(2 * tm) * p.ktiles * PK_CHUNK;
+  const __bf16* Bg = static_cast<const __bf16*>(p.B) + (int64_t)(2 * tn) * p.ktiles * PK_CHUNK;
   const int64_t pstride = (int64_t)p.ktiles * PK_CHUNK;  // panel stride in the packed operand
 
   // staging: 2 operands x 2 panels x 768 pieces of 16 bytes; thread t takes
@@ -237,11 +243,147 @@ __global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restric
       }
 }
 
+// ---------------------------------------------------------------------------
+// copy_pack64 / gemm_f64_packed
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void copy_pack64(const PackJob* __restrict__ jobs, int njobs) {
+  __shared__ double t[PK_R][PK_K + 1];
+  const PackJob& j = jobs[find_item(jobs, njobs, blockIdx.x)];
+  const int c = blockIdx.x - j.begin;
+  const int panel = c / j.kt_n, q = c % j.kt_n;
+  const int r0 = panel * PK_R, k0 = q * PK_K;
+  if (!j.trans) {
+    for (int e = threadIdx.x; e < PK_R * PK_K; e += 256) {
+      const int r = e / PK_K, k = e % PK_K;
+      const int gr = r0 + r, gk = k0 + k;
+      t[r][k] = (gr < j.rows && gk < j.K) ? j.alpha * j.src[(int64_t)gr * j.ld + gk] : 0.0;
+    }
+  } else {
+    for (int e = threadIdx.x; e < PK_R * PK_K; e += 256) {
+      const int k = e / PK_R, r = e % PK_R;
+      const int gr = r0 + r, gk = k0 + k;
+      t[r][k] = (gr < j.rows && gk < j.K) ? j.alpha * j.src[(int64_t)gk * j.ld + gr] : 0.0;
+    }
+  }
+  __syncthreads();
+  double* base = static_cast<double*>(j.dst) + ((int64_t)panel * j.ktiles + j.kt0 + q) * PK_CHUNK_64;
+  for (int e = threadIdx.x; e < PK_R * PK_K; e += 256) base[e] = t[e % PK_R][e / PK_R];
+}
+
+__global__ __launch_bounds__(XNT) void gemm_f64_packed(const SplitProb* __restrict__ probs, int nprob,
+                                                       int total) {
+  extern __shared__ __attribute__((aligned(16))) double f64_lds[];
+  const int b = blockIdx.x, t8 = total & ~7;
+  const int tile = b < t8 ? (b & 7) * (t8 >> 3) + (b >> 3) : b;
+  const SplitProb& p = probs[find_item(probs, nprob, tile)];
+  int tm, tn;
+  x6_tile(p, tile - p.begin, tm, tn);
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int pa = wave >> 1, pb = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  // LDS: [buffer][operand][panel][k][row]
+  constexpr int OPER = 2 * PK_CHUNK_64;
+  constexpr int BUF = 2 * OPER;
+  const double* Ag = static_cast<const double*>(p.A) + (int64_t)(2 * tm) * p.ktiles * PK_CHUNK_64;
+  const double* Bg = static_cast<const double*>(p.B) + (int64_t)(2 * tn) * p.ktiles * PK_CHUNK_64;
+  const int64_t pstride = (int64_t)p.ktiles * PK_CHUNK_64;
+
+  // staging: per operand 2 panels x 1024 pieces of 16 bytes; thread t takes
+  // pieces t + 256 u (u < 8)
+  i4 ra[8], rb[8];
+  auto fetch = [&](int kt) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + u * XNT;
+      const int pan = e >> 10, w = e & 1023;
+      ra[u] = *reinterpret_cast<const i4*>(Ag + pan * pstride + (int64_t)kt * PK_CHUNK_64 + w * 2);
+      rb[u] = *reinterpret_cast<const i4*>(Bg + pan * pstride + (int64_t)kt * PK_CHUNK_64 + w * 2);
+    }
+  };
+  auto commit = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = threadIdx.x + u * XNT;
+      const int pan = e >> 10, w = e & 1023;
+      *reinterpret_cast<i4*>(f64_lds + buf * BUF + pan * PK_CHUNK_64 + w * 2) = ra[u];
+      *reinterpret_cast<i4*>(f64_lds + buf * BUF + OPER + pan * PK_CHUNK_64 + w * 2) = rb[u];
+    }
+  };
+
+  d4 c[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  if (p.ktiles > 0) {
+    fetch(0);
+    commit(0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < p.ktiles; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < p.ktiles) fetch(kt + 1);
+    const double* As = f64_lds + buf * BUF + pa * PK_CHUNK_64;
+    const double* Bs = f64_lds + buf * BUF + OPER + pb * PK_CHUNK_64;
+#pragma unroll
+    for (int ks = 0; ks < PK_K; ks += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        av[i] = As[(ks + lk) * PK_R + i * 16 + lr];
+        bv[i] = Bs[(ks + lk) * PK_R + i * 16 + lr];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < p.ktiles) commit(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: element r of lane l of block (i, j) is row l / 16 + 4 r, column l % 16
+  const int row0 = tm * XT + pa * 64, col0 = tn * XT + pb * 64;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + i * 16 + lk + 4 * r, col = col0 + j * 16 + lr;
+        if (row < p.m && col < p.n) {
+          double v = c[i][j][r];
+          if (p.beta != 0.0) v += p.beta * p.D[(int64_t)row * p.ldd + col];
+          p.C[(int64_t)row * p.ldc + col] = v;
+        }
+      }
+}
+
 size_t split_gemm_lds_bytes() { return (size_t)2 * 2 * 2 * PK_CHUNK * sizeof(__bf16); }
 
 void launch_split_pack(const PackJob* d_jobs, int njobs, int chunks, hipStream_t s) {
   if (njobs <= 0 || chunks <= 0) return;
   split_pack<<<chunks, 256, 0, s>>>(d_jobs, njobs);
+}
+
+void launch_copy_pack64(const PackJob* d_jobs, int njobs, int chunks, hipStream_t s) {
+  if (njobs <= 0 || chunks <= 0) return;
+  copy_pack64<<<chunks, 256, 0, s>>>(d_jobs, njobs);
+}
+
+void launch_gemm_f64_packed(const SplitProb* d_probs, int nprob, int tiles, hipStream_t s) {
+  if (nprob <= 0 || tiles <= 0) return;
+  const size_t lds = (size_t)2 * 2 * 2 * PK_CHUNK_64 * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_f64_packed),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr = true;
+  }
+  gemm_f64_packed<<<tiles, XNT, lds, s>>>(d_probs, nprob, tiles);
 }
 
 void launch_gemm_x6_packed(const SplitProb* d_probs, int nprob, int tiles, hipStream_t s) {

@@ -162,8 +162,9 @@ class Handle:
          packed BSR blocks when ``bsr`` = (block, row_ptr, col_idx) is given
     C0 : device tensor, packed M x M reference orbitals
     f : host array of occupations, packed [sum M]
-    gemm_tuning : 0 = time the candidate kernels of each BF16x6 stage at creation
-                  and keep the faster, 1 = fixed size rule
+    gemm_tuning : kernel choice of the FP64 / BF16x6 GEMM stages: 0 = time both
+                  kernels at creation and keep the faster, 1 = fixed size rule,
+                  2 = always the packed 128 x 128 kernels, 3 = always the 64 x 64 ones
     """
 
     def __init__(self, M: Sequence[int], N: Optional[Sequence[int]], kind: str, precision: str,

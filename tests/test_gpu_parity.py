@@ -75,6 +75,37 @@ def test_real_ov_fp64_matches_oracle(which):
     h.close()
 
 
+# Both kernels of the FP64 and BF16x6 GEMM stages, forced (2 = packed 128 x 128
+# panels, 3 = grouped 64 x 64 tiles), so each is checked whichever one the tuning
+# picks: ragged shapes (K = 0, one-row and partial tiles, two K segments) and the
+# 148 molecules of config 2.
+@pytest.mark.parametrize("tuning", [2, 3])
+@pytest.mark.parametrize("which,precision", [("ragged", "fp64"), ("ragged", "mixed"), ("config2", "mixed"),
+                                             ("config2", "bf16x6")])
+def test_forced_gemm_kernels(which, precision, tuning):
+    wl = make_config(2) if which == "config2" else ragged_workload()
+    params = O.parity_params(wl)
+    print(f"[case] forced GEMM kernels {which} {precision} tuning={tuning}", flush=True)
+    h, _ = make_handle(wl, precision, gemm_tuning=tuning)
+    want = "packed128" if tuning == 2 else "tile64"
+    kernels = [k["kernel"] for k in h.stage_kernels() if k["kernel"]]
+    assert kernels and all(k.endswith(want) for k in kernels), kernels
+    E, g = energy_grad(h, wl, params)
+    if which == "ragged":
+        E_ref, g_ref = oracle_per_instance(wl, params)
+    else:
+        E_ref = np.array([O.energy_grad_ov(inst, p, wl.hubbard_U)[0] for inst, p in zip(wl.instances, params)])
+        g_ref = O.energy_grad_ov_workload(wl, params)[1]
+    errs = per_instance_errors(wl, E, g, E_ref, g_ref)
+    worst_e = max(e for e, _ in errs)
+    worst_g = max(x for _, x in errs)
+    print(f"[result] {which} {precision} tuning={tuning}: max |dE|/Ne = {worst_e:.3e}, "
+          f"max rel |dg| = {worst_g:.3e}")
+    tol_e, tol_g = {"fp64": (1e-13, 1e-10), "mixed": (1e-8, 1e-6), "bf16x6": (2e-7, 1e-6)}[precision]
+    assert worst_e < tol_e and worst_g < tol_g
+    h.close()
+
+
 @pytest.mark.parametrize("which", ["config1", "ragged"])
 def test_real_ov_expm_matches_oracle(which):
     wl = make_config(1) if which == "config1" else ragged_workload(scale=0.8)
