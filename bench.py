@@ -56,10 +56,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--lbfgs-iters", type=int, default=0, help="also time this many L-BFGS iterations")
+    ap.add_argument("--gemm-tuning", type=int, default=0, choices=[0, 1, 2, 3, 4],
+                    help="GEMM kernel choice: 0 tuned at creation, 1 size rule, 2 packed 128x128, "
+                         "3 grouped 64x64, 4 packed 64x64")
     return ap.parse_args()
 
 
-def build_handle(wl, precision):
+def build_handle(wl, precision, gemm_tuning=0):
     import torch
     from paper_2101_12597_amd import Handle
     from workloads.pack import pack
@@ -68,7 +71,7 @@ def build_handle(wl, precision):
     H0 = torch.from_numpy(pk["H0"]).to(dev)
     C0 = torch.from_numpy(pk["C0"]).to(dev)
     h = Handle(pk["M"], pk["N"], wl.kind, precision, wl.hubbard_U, H0, C0, pk["f"],
-               couple=wl.couple, weights=pk["weights"], bsr=pk["bsr"])
+               couple=wl.couple, weights=pk["weights"], bsr=pk["bsr"], gemm_tuning=gemm_tuning)
     A = torch.from_numpy(pk["A"]).to(dev)
     E = torch.empty(h.n_inst + 1, dtype=torch.float64, device=dev)
     G = torch.empty_like(A)
@@ -112,16 +115,16 @@ def stage_profile(h, A, E, G, reps=5):
 
 
 def gemm_kernel_table(h, prof):
-    """Kernel of every GEMM stage; for the split-precision stages also the two launch
-    times the tuning at handle creation measured (tile64 / packed128, ms)."""
+    """Kernel of every GEMM stage; for the FP64 / BF16x6 stages also the launch times
+    (ms) of the three kernels measured by the tuning at handle creation."""
     names = {r["index"]: r["name"] for r in prof}
     out = {}
     for k in h.stage_kernels():
         if not k["kernel"]:
             continue
         entry = {"kernel": k["kernel"]}
-        if k["tuned_ms_tile64"] > 0 or k["tuned_ms_packed128"] > 0:
-            entry["tuned_ms"] = [round(k["tuned_ms_tile64"], 4), round(k["tuned_ms_packed128"], 4)]
+        if any(v > 0 for v in k["tuned_ms"].values()):
+            entry["tuned_ms"] = {n: round(v, 4) for n, v in k["tuned_ms"].items()}
         out[names.get(k["index"], str(k["index"]))] = entry
     return out
 
@@ -199,7 +202,7 @@ def main():
     wl = make_config(cfg)
     params = O.parity_params(wl)
     log("creating the handle")
-    h, A, E, G = build_handle(wl, prec)
+    h, A, E, G = build_handle(wl, prec, args.gemm_tuning)
     log("stage profile")
 
     # which stage dominates: time every stage over a few evaluations
@@ -283,7 +286,7 @@ def main():
         "gemm_kernels": gemm_kernel_table(h, prof),
     }
     if not args.no_fp64_compare and prec != "fp64":
-        h64, A64, E64, G64 = build_handle(wl, "fp64")
+        h64, A64, E64, G64 = build_handle(wl, "fp64", args.gemm_tuning)
         h64.set_graph(True)
         sec64, _ = timed_run(h64, A64, E64, G64, max(5, args.steps // 2), 2)
         out["fp64_path"] = {"value": 1.0 / sec64, "ms_per_step": sec64 * 1e3, "speedup": sec64 / sec}

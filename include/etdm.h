@@ -99,11 +99,12 @@ typedef struct {
   const int32_t *bsr_row_ptr; /* host, per instance (M/bs + 1) entries, concatenated */
   const int32_t *bsr_col_idx; /* host, per instance row_ptr[last] entries, concatenated */
   int32_t gemm_tuning;    /* kernel choice of the real FP64 and BF16x6 GEMM stages:
-                             0 = time both kernels on the handle's buffers in etdm_create
-                             and keep the faster; 1 = fixed rule (packed 128 x 128 tiles
-                             when every problem of the stage is at least 128 x 128 with
-                             K >= 256); 2 = always packed; 3 = always 64 x 64 tiles.
-                             Other values: ETDM_E_ARG */
+                             0 = time the three kernels on the handle's buffers in
+                             etdm_create and keep the fastest; 1 = fixed rule (packed
+                             128 x 128 tiles when every problem of the stage is at least
+                             128 x 128 with K >= 256, else 64 x 64 tiles); 2 = always
+                             packed 128 x 128; 3 = always grouped 64 x 64; 4 = always
+                             packed 64 x 64.  Other values: ETDM_E_ARG */
 } etdm_desc;
 
 /* Create a handle.  H0: device, dense float64 (REAL_OV) or complex float64
@@ -196,13 +197,14 @@ etdm_status etdm_stage_info(etdm_handle *h, int32_t i, const char **name, int64_
                             double *total_ms, double *flops, double *bytes);
 
 /* GEMM kernel of stage i: *variant = "tile64" / "fp64_tile64" (grouped 64 x 64
- * tiles reading, and for BF16x6 splitting, the operands in every tile),
- * "packed128" / "fp64_packed128" (operands packed, and split, once per launch
- * into a panel buffer, 128 x 128 tiles), "zgemm64" (complex), or "" for a stage
- * that is not a GEMM; ms_tile / ms_packed = the launch times measured by the
- * tuning in etdm_create (0 when not timed).  Any output pointer may be NULL. */
+ * tiles that read, and for BF16x6 split, the operands in every tile),
+ * "packed64" / "fp64_packed64" and "packed128" / "fp64_packed128" (operands
+ * packed, and split, once per launch into a panel buffer; 64 x 64 or 128 x 128
+ * tiles), "zgemm64" (complex), or "" for a stage that is not a GEMM.  ms_* = the
+ * launch times of the three kernels measured by the tuning in etdm_create (0 when
+ * not timed).  Any output pointer may be NULL. */
 etdm_status etdm_stage_kernel(const etdm_handle *h, int32_t i, const char **variant, double *ms_tile,
-                              double *ms_packed);
+                              double *ms_packed64, double *ms_packed128);
 
 /* Number of parameters of one A (or G) array in float64 units:
  * REAL_OV sum N(M-N); COMPLEX_FULL 2 sum M^2. */

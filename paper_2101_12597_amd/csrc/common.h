@@ -50,8 +50,9 @@ constexpr int PK_K = 32;  // k per k-tile
 constexpr int PK_S = 3;   // BF16 slices per value
 // Pack op(X) = alpha * (trans ? X^T : X) (rows x K, FP64 row-major X with leading
 // dimension ld) into k-tiles [kt0, kt0 + ceil(K / 32)) of a packed operand with
-// ktiles k-tiles per panel.  The job covers 2 ceil(rows / 128) panels (zero rows
-// past the end); begin is the prefix sum of chunks (panels x kt_n) over the jobs.
+// ktiles k-tiles per panel.  The job covers whole tiles of panels (zero rows past
+// the end); begin is the prefix sum of chunks (panels x kt_n) over the jobs, and
+// the launch's chunk table maps each workgroup to its job.
 // dst: BF16 slices (split_pack) or FP64 values (copy_pack64).
 struct PackJob {
   const double* src;
@@ -61,7 +62,8 @@ struct PackJob {
   int32_t trans, rows, K, kt0, ktiles, kt_n, begin;
 };
 // C (m x n, FP64) = sum over k of A[i][k] B[j][k] + beta D for packed A (m rows) and
-// B (n rows) with ktiles k-tiles; 128 x 128 tiles, begin = prefix sum of tiles.
+// B (n rows) with ktiles k-tiles, in tiles of tp x tp panels (64 tp rows and
+// columns); begin = prefix sum of tiles, the tile table maps workgroups to problems.
 struct SplitProb {
   const void* A;
   const void* B;
@@ -71,13 +73,13 @@ struct SplitProb {
   double beta;
   int32_t m, n, ktiles, tiles_m, tiles_n, begin;
 };
-constexpr int SPLIT_TILE = 128;
 constexpr int PK_CHUNK_X6 = PK_S * PK_R * PK_K;  // BF16 values of a split chunk
 constexpr int PK_CHUNK_64 = PK_R * PK_K;         // FP64 values of an FP64 chunk
-void launch_split_pack(const PackJob* d_jobs, int njobs, int chunks, hipStream_t s);
-void launch_copy_pack64(const PackJob* d_jobs, int njobs, int chunks, hipStream_t s);
-void launch_gemm_f64_packed(const SplitProb* d_probs, int nprob, int tiles, hipStream_t s);
-void launch_gemm_x6_packed(const SplitProb* d_probs, int nprob, int tiles, hipStream_t s);
+void launch_split_pack(const PackJob* d_jobs, const int* d_chunk_job, int chunks, hipStream_t s);
+void launch_copy_pack64(const PackJob* d_jobs, const int* d_chunk_job, int chunks, hipStream_t s);
+// tp = 1 (64 x 64 tiles) or 2 (128 x 128 tiles)
+void launch_gemm_f64_packed(int tp, const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s);
+void launch_gemm_x6_packed(int tp, const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Jacobi eigensolver (FP64), one workgroup per matrix

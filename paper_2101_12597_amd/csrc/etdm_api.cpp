@@ -55,11 +55,28 @@ void gauss_legendre01(int n, double* t, double* w) {
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // One grouped GEMM launch.  Problems are added at plan time and uploaded once.
-// A real FP64 or BF16x6 stage has two kernels: the grouped 64 x 64 kernel that
-// reads (and splits) the operands inside every tile ("tile64"), and a pack pass
-// into a panel layout shared by all stages followed by the 128 x 128 kernel
-// ("packed128": copy_pack64 + gemm_f64_packed, or split_pack + gemm_x6_packed).
+// A real FP64 or BF16x6 stage has three kernels:
+//   V_TILE64   the grouped 64 x 64 kernel that reads (and splits) the operands
+//              inside every tile (gemm.hip);
+//   V_PACK64   a pack pass into a panel layout shared by all stages, then
+//              64 x 64 tiles on the packed operands (gemm_split.hip);
+//   V_PACK128  the same with 128 x 128 tiles.
 // Which one runs is chosen at plan time (tune_stages).
+enum GemmVariant { V_TILE64 = 0, V_PACK64 = 1, V_PACK128 = 2, V_COUNT = 3 };
+
+// The launches of one packed variant (tp panels of 64 rows per tile side).
+struct PackPlan {
+  std::vector<PackJob> jobs;
+  std::vector<int32_t> chunk_job;  // pack workgroup -> job
+  std::vector<SplitProb> probs;
+  std::vector<int32_t> tile_prob;  // GEMM workgroup -> problem
+  PackJob* d_jobs = nullptr;
+  int32_t* d_chunk_job = nullptr;
+  SplitProb* d_probs = nullptr;
+  int32_t* d_tile_prob = nullptr;
+  int chunks = 0, tiles = 0;
+};
+
 struct Stage {
   std::vector<GemmProb> probs;
   std::vector<int32_t> tile_prob;  // workgroup -> problem
@@ -68,13 +85,9 @@ struct Stage {
   int tiles = 0;
   int opA = OP_N, opB = OP_N, prec = GP_FP64;
   bool cplx = false;
-  bool packed = false;
-  std::vector<PackJob> pjobs;
-  std::vector<SplitProb> sprobs;
-  PackJob* d_pjobs = nullptr;
-  SplitProb* d_sprobs = nullptr;
-  int pchunks = 0, stiles = 0;
-  float tuned_ms[2] = {0.f, 0.f};  // plan-time launch times of tile64 / packed128 (0: not timed)
+  int variant = V_TILE64;
+  PackPlan pk[2];                      // tp = 1, 2
+  float tuned_ms[V_COUNT] = {0.f, 0.f, 0.f};  // plan-time launch times per variant (0: not timed)
   void init(int a, int b, int p, bool c = false) {
     opA = a;
     opB = b;
@@ -96,18 +109,17 @@ struct Stage {
   static int ktiles(const GemmProb& p) {
     return ceil_div(std::max(p.k, 0), PK_K) + ceil_div(std::max(p.k2, 0), PK_K);
   }
-  static int panels(int rows) { return 2 * ceil_div(rows, SPLIT_TILE); }
-  // bytes of the packed operands of all problems
-  size_t pack_bytes() const {
+  static int panels(int rows, int tp) { return tp * ceil_div(rows, PK_R * tp); }
+  // bytes of the packed operands of all problems for tiles of tp panels
+  size_t pack_bytes(int tp) const {
     size_t n = 0;
-    for (const GemmProb& p : probs) n += (size_t)(panels(p.m) + panels(p.n)) * ktiles(p) * chunk_bytes();
+    for (const GemmProb& p : probs) n += (size_t)(panels(p.m, tp) + panels(p.n, tp)) * ktiles(p) * chunk_bytes();
     return n;
   }
-  // pack jobs and packed problems with the operands at arena (pack_bytes() bytes)
-  void plan_pack(char* arena) {
-    pjobs.clear();
-    sprobs.clear();
-    pchunks = stiles = 0;
+  // pack jobs and packed problems of variant tp with the operands at arena
+  void plan_pack(int tp, char* arena) {
+    PackPlan& q = pk[tp - 1];
+    q = PackPlan();
     const size_t chunk = chunk_bytes();
     size_t off = 0;
     auto job = [&](const double* src, char* dst, int64_t ld, double alpha, bool trans, int rows, int K,
@@ -124,13 +136,14 @@ struct Stage {
       j.kt0 = kt0;
       j.ktiles = kt;
       j.kt_n = ceil_div(K, PK_K);
-      j.begin = pchunks;
-      pchunks += np * j.kt_n;
-      pjobs.push_back(j);
+      j.begin = q.chunks;
+      q.chunks += np * j.kt_n;
+      q.chunk_job.resize(q.chunks, (int32_t)q.jobs.size());
+      q.jobs.push_back(j);
     };
     for (const GemmProb& p : probs) {
       const int kt = ktiles(p), kt1 = ceil_div(std::max(p.k, 0), PK_K);
-      const int pa = panels(p.m), pb = panels(p.n);
+      const int pa = panels(p.m, tp), pb = panels(p.n, tp);
       char* a = arena + off;
       off += (size_t)pa * kt * chunk;
       char* b = arena + off;
@@ -151,33 +164,39 @@ struct Stage {
       sp.m = p.m;
       sp.n = p.n;
       sp.ktiles = kt;
-      sp.tiles_m = ceil_div(p.m, SPLIT_TILE);
-      sp.tiles_n = ceil_div(p.n, SPLIT_TILE);
-      sp.begin = stiles;
-      stiles += sp.tiles_m * sp.tiles_n;
-      sprobs.push_back(sp);
+      sp.tiles_m = ceil_div(p.m, PK_R * tp);
+      sp.tiles_n = ceil_div(p.n, PK_R * tp);
+      sp.begin = q.tiles;
+      q.tiles += sp.tiles_m * sp.tiles_n;
+      q.tile_prob.resize(q.tiles, (int32_t)q.probs.size());
+      q.probs.push_back(sp);
     }
   }
-  // the fixed rule when no timing is wanted: packed when every problem fills
-  // 128 x 128 tiles and its K is long enough to amortize the split
-  bool pack_by_size() const {
+  // the fixed rule when no timing is wanted: 128 x 128 packed tiles when every
+  // problem fills them and its K is long enough to amortize the pack
+  int variant_by_size() const {
     for (const GemmProb& p : probs)
-      if (p.m < SPLIT_TILE || p.n < SPLIT_TILE || p.k + std::max(p.k2, 0) < 256) return false;
-    return true;
+      if (p.m < 128 || p.n < 128 || p.k + std::max(p.k2, 0) < 256) return V_TILE64;
+    return V_PACK128;
   }
-  const char* variant() const {
+  const char* variant_name() const {
+    static const char* real[V_COUNT] = {"tile64", "packed64", "packed128"};
+    static const char* f64[V_COUNT] = {"fp64_tile64", "fp64_packed64", "fp64_packed128"};
     if (cplx) return "zgemm64";
-    if (prec == GP_FP64) return packed ? "fp64_packed128" : "fp64_tile64";
-    return packed ? "packed128" : "tile64";
+    return prec == GP_FP64 ? f64[variant] : real[variant];
   }
   void launch(hipStream_t s) const {
     if (probs.empty()) return;
-    if (packed && prec == GP_FP64) {
-      launch_copy_pack64(d_pjobs, (int)pjobs.size(), pchunks, s);
-      launch_gemm_f64_packed(d_sprobs, (int)sprobs.size(), stiles, s);
-    } else if (packed) {
-      launch_split_pack(d_pjobs, (int)pjobs.size(), pchunks, s);
-      launch_gemm_x6_packed(d_sprobs, (int)sprobs.size(), stiles, s);
+    if (variant != V_TILE64) {
+      const int tp = variant == V_PACK128 ? 2 : 1;
+      const PackPlan& q = pk[tp - 1];
+      if (prec == GP_FP64) {
+        launch_copy_pack64(q.d_jobs, q.d_chunk_job, q.chunks, s);
+        launch_gemm_f64_packed(tp, q.d_probs, q.d_tile_prob, q.tiles, s);
+      } else {
+        launch_split_pack(q.d_jobs, q.d_chunk_job, q.chunks, s);
+        launch_gemm_x6_packed(tp, q.d_probs, q.d_tile_prob, q.tiles, s);
+      }
     } else if (cplx) {
       launch_zgemm(d, d_tile_prob, tiles, opA, opB, s);
     } else {
@@ -549,11 +568,12 @@ etdm_status upload_stage(etdm_handle* h, Stage& s) {
 }
 
 // Packed operands for every FP64 / BF16x6 stage: one arena of the largest
-// stage's size (the stages of a launch sequence run one after another).
+// stage's size (the stages of a launch sequence run one after another, and a
+// stage runs one variant at a time).
 etdm_status plan_packed_stages(etdm_handle* h, Stage* const* stages, size_t n) {
   size_t bytes = 0;
   for (size_t i = 0; i < n; ++i)
-    if (stages[i]->can_pack()) bytes = std::max(bytes, stages[i]->pack_bytes());
+    if (stages[i]->can_pack()) bytes = std::max({bytes, stages[i]->pack_bytes(1), stages[i]->pack_bytes(2)});
   if (bytes == 0) return ETDM_OK;
   void* p = nullptr;
   HIPCHK(h, hipMalloc(&p, bytes));
@@ -562,17 +582,27 @@ etdm_status plan_packed_stages(etdm_handle* h, Stage* const* stages, size_t n) {
   for (size_t i = 0; i < n; ++i) {
     Stage& sg = *stages[i];
     if (!sg.can_pack()) continue;
-    sg.plan_pack(h->pack_arena);
-    CHECK(upload(h, &sg.d_pjobs, sg.pjobs));
-    CHECK(upload(h, &sg.d_sprobs, sg.sprobs));
-    sg.packed = h->gemm_tuning == 2 ? true : h->gemm_tuning == 3 ? false : sg.pack_by_size();
+    for (int tp = 1; tp <= 2; ++tp) {
+      sg.plan_pack(tp, h->pack_arena);
+      PackPlan& q = sg.pk[tp - 1];
+      CHECK(upload(h, &q.d_jobs, q.jobs));
+      CHECK(upload(h, &q.d_chunk_job, q.chunk_job));
+      CHECK(upload(h, &q.d_probs, q.probs));
+      CHECK(upload(h, &q.d_tile_prob, q.tile_prob));
+    }
+    switch (h->gemm_tuning) {
+      case 2: sg.variant = V_PACK128; break;
+      case 3: sg.variant = V_TILE64; break;
+      case 4: sg.variant = V_PACK64; break;
+      default: sg.variant = sg.variant_by_size();
+    }
   }
   return ETDM_OK;
 }
 
-// Plan-time choice between the two kernels of an FP64 / BF16x6 stage: both run
-// on the handle's own buffers (every evaluation overwrites what they write), one
-// warm-up and three timed launches each, and the faster is kept.
+// Plan-time choice among the kernels of an FP64 / BF16x6 stage: each runs on the
+// handle's own buffers (every evaluation overwrites what they write), one warm-up
+// and three timed launches, and the fastest is kept.
 etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
   if (h->gemm_tuning != 0) return ETDM_OK;
   hipEvent_t e0, e1;
@@ -581,8 +611,9 @@ etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
   etdm_status st = ETDM_OK;
   for (Stage* sg : h->timer_stage) {
     if (!sg || !sg->can_pack()) continue;
-    for (int v = 0; v < 2 && st == ETDM_OK; ++v) {
-      sg->packed = v == 1;
+    int best = V_TILE64;
+    for (int v = 0; v < V_COUNT && st == ETDM_OK; ++v) {
+      sg->variant = v;
       sg->launch(s);
       float ms = 0.f;
       if (hipEventRecord(e0, s) != hipSuccess) st = ETDM_E_HIP;
@@ -591,9 +622,10 @@ etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
         st = ETDM_E_HIP;
       sg->tuned_ms[v] = ms / 3.f;
+      if (sg->tuned_ms[v] < sg->tuned_ms[best]) best = v;
     }
     if (st != ETDM_OK) break;
-    sg->packed = sg->tuned_ms[1] < sg->tuned_ms[0];
+    sg->variant = best;
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -1428,7 +1460,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (d->kind != ETDM_REAL_OV && d->kind != ETDM_COMPLEX_FULL) return ETDM_E_ARG;
   if (d->precision < ETDM_FP64 || d->precision > ETDM_MIXED) return ETDM_E_ARG;
   if (d->kind == ETDM_COMPLEX_FULL && d->precision != ETDM_FP64) return ETDM_E_ARG;
-  if (d->gemm_tuning < 0 || d->gemm_tuning > 3) return ETDM_E_ARG;
+  if (d->gemm_tuning < 0 || d->gemm_tuning > 4) return ETDM_E_ARG;
   if (d->kind == ETDM_REAL_OV && (!d->N || d->couple)) return ETDM_E_ARG;
   if (d->h0_format != 0 && d->h0_format != 1) return ETDM_E_ARG;
   if (d->h0_format == 1 && (d->kind != ETDM_REAL_OV || d->bsr_block < 1 || d->bsr_block > BSR_MAX_BS ||
@@ -1682,12 +1714,13 @@ etdm_status etdm_stage_info(etdm_handle* h, int32_t i, const char** name, int64_
 }
 
 etdm_status etdm_stage_kernel(const etdm_handle* h, int32_t i, const char** variant, double* ms_tile,
-                              double* ms_packed) {
+                              double* ms_packed64, double* ms_packed128) {
   if (!h || i < 0 || i >= (int32_t)h->timers.size()) return ETDM_E_ARG;
   const Stage* sg = i < (int32_t)h->timer_stage.size() ? h->timer_stage[i] : nullptr;
-  if (variant) *variant = sg && !sg->probs.empty() ? sg->variant() : "";
-  if (ms_tile) *ms_tile = sg ? sg->tuned_ms[0] : 0.0;
-  if (ms_packed) *ms_packed = sg ? sg->tuned_ms[1] : 0.0;
+  if (variant) *variant = sg && !sg->probs.empty() ? sg->variant_name() : "";
+  if (ms_tile) *ms_tile = sg ? sg->tuned_ms[V_TILE64] : 0.0;
+  if (ms_packed64) *ms_packed64 = sg ? sg->tuned_ms[V_PACK64] : 0.0;
+  if (ms_packed128) *ms_packed128 = sg ? sg->tuned_ms[V_PACK128] : 0.0;
   return ETDM_OK;
 }
 

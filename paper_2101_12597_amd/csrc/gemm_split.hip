@@ -1,32 +1,34 @@
-// Split-precision GEMM for large problems on pre-split operands (gfx950).
+// GEMMs on packed operands (gfx950): FP64, and the split-precision BF16x6
+// product for large problems.
 //
 // The BF16x6 product of the grouped GEMM in gemm.hip splits every FP64 operand
 // element into three BF16 slices x = hi + md + lo inside each workgroup, so an
-// element is split once per tile that reads it.  For large problems the split
-// is done once instead, by split_pack, into a packed layout that the GEMM reads
-// with plain 16-byte loads:
+// element is split once per tile that reads it, and every tile computes its own
+// bounds-checked addresses.  Here the operands are packed once per launch
+// (split_pack, copy_pack64) into a layout that the GEMMs read with plain
+// contiguous 16-byte loads:
 //
 //   op(X) (rows x K) -> panels of PK_R = 64 rows, each a run of k-tiles of
-//   PK_K = 32; one (panel, k-tile) chunk holds [slice][row][k] BF16 values,
-//   3 x 64 x 32 x 2 bytes = 12 KB, contiguous.  Inside a row the four 8-value
-//   octets are permuted by an XOR of the row index (pk_phys), so the MFMA
-//   fragment reads of 16 consecutive rows hit distinct LDS banks.
+//   PK_K = 32.  A BF16x6 chunk (one panel, one k-tile) holds [slice][row][k]
+//   values, 3 x 64 x 32 x 2 bytes = 12 KB, contiguous; inside a row the four
+//   8-value octets are permuted by an XOR of the row index (pk_phys), so the
+//   MFMA fragment reads of 16 consecutive rows hit distinct LDS banks.  An FP64
+//   chunk is [k][row], 64 x 32 x 8 bytes = 16 KB, so the 16 lanes that share a
+//   k of a v_mfma_f64_16x16x4f64 fragment read 128 consecutive bytes.
 //
-// Rows are padded to a multiple of 128 and k to a multiple of 32 with zeros.  A
-// problem with two K segments (C = a1 A1 B1 + a2 A2 B2) packs [a1 A1 | a2 A2] and
+// Rows are padded with zeros to whole tiles and k to a multiple of 32.  A problem
+// with two K segments (C = a1 A1 B1 + a2 A2 B2) packs [a1 A1 | a2 A2] and
 // [B1; B2] along k, so the GEMM sees one K.
 //
-// gemm_x6_packed: C = op(A) op(B) + beta D for packed op(A) and op(B)^T (both
-// rows x K).  One workgroup of 4 wavefronts computes a 128 x 128 tile; each
-// wavefront owns 64 x 64 as 4 x 4 blocks of v_mfma_f32_16x16x32_bf16 and
-// accumulates the six slice products with i + j <= 2 in FP32, added into FP64
-// registers every FLUSH k.  k-tiles of 32 are double-buffered in LDS (96 KB)
-// with the next one fetched into registers during the MFMAs.
-//
-// The FP64 pair (copy_pack64, gemm_f64_packed) uses the same panels and tile
-// order without the split: a chunk is [k][row] FP64 (64 x 32 x 8 bytes = 16 KB),
-// so the 16 lanes that share a k of a v_mfma_f64_16x16x4f64 fragment read 128
-// consecutive bytes; 128 KB of LDS double-buffer the k-tiles.
+// gemm_x6_packed<TP> / gemm_f64_packed<TP>: C = op(A) op(B) + beta D for packed
+// op(A) and op(B)^T (both rows x K).  A workgroup of 4 wavefronts computes a
+// tile of TP x TP panels (TP = 1: 64 x 64, TP = 2: 128 x 128); each wavefront
+// owns a 32 TP x 32 TP quarter as (2 TP)^2 blocks of 16 x 16.  BF16x6 sums the
+// six slice products with i + j <= 2 (v_mfma_f32_16x16x32_bf16) in FP32 and adds
+// them into FP64 registers every X_FLUSH k-tiles.  The k-tiles are
+// double-buffered in LDS with the next one fetched into registers during the
+// MFMAs; tiles are ordered in groups of X_GROUP tile rows and dealt out so that
+// each XCD works on a contiguous range.
 #include "common.h"
 
 namespace etdm {
@@ -39,7 +41,6 @@ typedef int i4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int PK_CHUNK = PK_CHUNK_X6;
-constexpr int XT = 128;                        // workgroup tile (rows and columns)
 constexpr int XNT = 256;
 constexpr int X_FLUSH = 4;                     // k-tiles between FP64 flushes (128 k)
 constexpr int X_GROUP = 4;                     // tile rows per group of the tile order
@@ -50,25 +51,15 @@ __device__ __forceinline__ int pk_phys(int oct, int row) {
   return oct ^ (((row >> 1) ^ (row >> 3)) & 3);
 }
 
-template <typename J>
-__device__ __forceinline__ int find_item(const J* __restrict__ v, int n, int bid) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (v[mid].begin <= bid) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // split_pack: one workgroup per (panel, k-tile) chunk of one job
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void split_pack(const PackJob* __restrict__ jobs, int njobs) {
+__global__ __launch_bounds__(256) void split_pack(const PackJob* __restrict__ jobs,
+                                                  const int* __restrict__ chunk_job) {
   __shared__ double t[PK_R][PK_K + 1];
-  const PackJob& j = jobs[find_item(jobs, njobs, blockIdx.x)];
+  const PackJob& j = jobs[chunk_job[blockIdx.x]];
   const int c = blockIdx.x - j.begin;
   const int panel = c / j.kt_n, q = c % j.kt_n;
   const int r0 = panel * PK_R, k0 = q * PK_K;
@@ -107,7 +98,9 @@ __global__ __launch_bounds__(256) void split_pack(const PackJob* __restrict__ jo
 }
 
 // ---------------------------------------------------------------------------
-// gemm_x6_packed
+// gemm_x6_packed<TP>: tiles of TP x TP panels (64 TP rows and columns); the four
+// wavefronts form a 2 x 2 grid of 32 TP x 32 TP sub-tiles, NB = 2 TP blocks of
+// 16 x 16 per side
 // ---------------------------------------------------------------------------
 // tile index inside one problem, grouped X_GROUP tile rows at a time so that the
 // workgroups resident together share A and B panels
@@ -120,34 +113,40 @@ __device__ __forceinline__ void x6_tile(const SplitProb& p, int lt, int& tm, int
   tn = idx / gr;
 }
 
-__global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restrict__ probs, int nprob,
-                                                      int total) {
+// logical tile of workgroup b: workgroups are dealt to the 8 XCDs in turn, so
+// consecutive logical tiles are given to the workgroups of one XCD (shared L2)
+__device__ __forceinline__ int xcd_tile(int b, int total) {
+  const int t8 = total & ~7;
+  return b < t8 ? (b & 7) * (t8 >> 3) + (b >> 3) : b;
+}
+
+template <int TP>
+__global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restrict__ probs,
+                                                      const int* __restrict__ tile_prob, int total) {
+  constexpr int NB = 2 * TP;
   extern __shared__ __attribute__((aligned(16))) __bf16 x6_lds[];
-  // logical tile: workgroups are dealt to the 8 XCDs in turn, so consecutive
-  // logical tiles are given to the workgroups of one XCD (shared L2)
-  const int b = blockIdx.x, t8 = total & ~7;
-  const int tile = b < t8 ? (b & 7) * (t8 >> 3) + (b >> 3) : b;
-  const SplitProb& p = probs[find_item(probs, nprob, tile)];
+  const int tile = xcd_tile(blockIdx.x, total);
+  const SplitProb& p = probs[tile_prob[tile]];
   int tm, tn;
   x6_tile(p, tile - p.begin, tm, tn);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int pa = wave >> 1, pb = wave & 1;  // this wavefront's A and B panel inside the tile
+  const int wrow = (wave >> 1) * 32 * TP, wcol = (wave & 1) * 32 * TP;  // sub-tile offsets
   const int lr = lane & 15, lo = lane >> 4;
 
   // LDS: [buffer][operand][panel][slice][row][k]
-  constexpr int OPER = 2 * PK_CHUNK;
+  constexpr int OPER = TP * PK_CHUNK;
   constexpr int BUF = 2 * OPER;
-  const __bf16* Ag = static_cast<const __bf16*>(p.A) + (int64_t)(2 * tm) * p.ktiles * PK_CHUNK;
-  const __bf16* Bg = static_cast<const __bf16*>(p.B) + (int64_t)(2 * tn) * p.ktiles * PK_CHUNK;
   const int64_t pstride = (int64_t)p.ktiles * PK_CHUNK;  // panel stride in the packed operand
+  const __bf16* Ag = static_cast<const __bf16*>(p.A) + (int64_t)(TP * tm) * pstride;
+  const __bf16* Bg = static_cast<const __bf16*>(p.B) + (int64_t)(TP * tn) * pstride;
 
-  // staging: 2 operands x 2 panels x 768 pieces of 16 bytes; thread t takes
-  // pieces t + 256 u (u < 6) of each operand
-  i4 ra[6], rb[6];
+  // staging: per operand TP panels x 768 pieces of 16 bytes; thread t takes
+  // pieces t + 256 u (u < 3 TP)
+  i4 ra[3 * TP], rb[3 * TP];
   auto fetch = [&](int kt) {
 #pragma unroll
-    for (int u = 0; u < 6; ++u) {
+    for (int u = 0; u < 3 * TP; ++u) {
       const int e = threadIdx.x + u * XNT;
       const int pan = e / 768, w = e % 768;
       ra[u] = *reinterpret_cast<const i4*>(Ag + pan * pstride + (int64_t)kt * PK_CHUNK + w * 8);
@@ -156,31 +155,32 @@ __global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restric
   };
   auto commit = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 6; ++u) {
+    for (int u = 0; u < 3 * TP; ++u) {
       const int e = threadIdx.x + u * XNT;
-      const int pan = e / 768, w = e % 768;
-      *reinterpret_cast<i4*>(x6_lds + buf * BUF + pan * PK_CHUNK + w * 8) = ra[u];
-      *reinterpret_cast<i4*>(x6_lds + buf * BUF + OPER + pan * PK_CHUNK + w * 8) = rb[u];
+      *reinterpret_cast<i4*>(x6_lds + buf * BUF + e * 8) = ra[u];
+      *reinterpret_cast<i4*>(x6_lds + buf * BUF + OPER + e * 8) = rb[u];
     }
   };
 
-  double acc[4][4][4];
+  double acc[NB][NB][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NB; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
-  f4 c[4][4];
+  f4 c[NB][NB];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NB; ++j) c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  // fragment offset (BF16 elements) of 16-row block blk, slice s, inside a panel
-  auto frag = [&](int s, int blk) {
-    const int row = blk * 16 + lr;
-    return (s * PK_R + row) * PK_K + pk_phys(lo, row) * 8;
+  // fragment offset (BF16 elements) of the 16-row block starting at tile row
+  // off + 16 blk, slice s
+  auto frag = [&](int off, int s, int blk) {
+    const int trow = off + blk * 16;
+    const int row = (trow & 63) + lr;
+    return (trow >> 6) * PK_CHUNK + (s * PK_R + row) * PK_K + pk_phys(lo, row) * 8;
   };
 
   if (p.ktiles > 0) {
@@ -191,33 +191,33 @@ __global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restric
   for (int kt = 0; kt < p.ktiles; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < p.ktiles) fetch(kt + 1);
-    const __bf16* As = x6_lds + buf * BUF + pa * PK_CHUNK;
-    const __bf16* Bs = x6_lds + buf * BUF + OPER + pb * PK_CHUNK;
-    bf8 bv[PK_S][4];
+    const __bf16* As = x6_lds + buf * BUF;
+    const __bf16* Bs = x6_lds + buf * BUF + OPER;
+    bf8 bv[PK_S][NB];
 #pragma unroll
     for (int s = 0; s < PK_S; ++s)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[s][j] = *reinterpret_cast<const bf8*>(Bs + frag(s, j));
+      for (int j = 0; j < NB; ++j) bv[s][j] = *reinterpret_cast<const bf8*>(Bs + frag(wcol, s, j));
     // A slice sa meets the B slices sb <= 2 - sa; lowest-order products first
 #pragma unroll
     for (int sa = PK_S - 1; sa >= 0; --sa) {
-      bf8 av[4];
+      bf8 av[NB];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = *reinterpret_cast<const bf8*>(As + frag(sa, i));
+      for (int i = 0; i < NB; ++i) av[i] = *reinterpret_cast<const bf8*>(As + frag(wrow, sa, i));
 #pragma unroll
       for (int sb = PK_S - 1 - sa; sb >= 0; --sb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NB; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < NB; ++j)
             c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[sb][j], c[i][j], 0, 0, 0);
     }
     if (kt + 1 < p.ktiles) commit(buf ^ 1);
     if ((kt + 1) % X_FLUSH == 0 || kt + 1 == p.ktiles) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NB; ++j) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)c[i][j][r];
           c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
@@ -227,11 +227,11 @@ __global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restric
   }
 
   // epilogue: element r of lane l of block (i, j) is row 4 (l / 16) + r, column l % 16
-  const int row0 = tm * XT + pa * 64, col0 = tn * XT + pb * 64;
+  const int row0 = tm * 64 * TP + wrow, col0 = tn * 64 * TP + wcol;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NB; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + i * 16 + 4 * lo + r, col = col0 + j * 16 + lr;
@@ -246,9 +246,10 @@ __global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restric
 // ---------------------------------------------------------------------------
 // copy_pack64 / gemm_f64_packed
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void copy_pack64(const PackJob* __restrict__ jobs, int njobs) {
+__global__ __launch_bounds__(256) void copy_pack64(const PackJob* __restrict__ jobs,
+                                                   const int* __restrict__ chunk_job) {
   __shared__ double t[PK_R][PK_K + 1];
-  const PackJob& j = jobs[find_item(jobs, njobs, blockIdx.x)];
+  const PackJob& j = jobs[chunk_job[blockIdx.x]];
   const int c = blockIdx.x - j.begin;
   const int panel = c / j.kt_n, q = c % j.kt_n;
   const int r0 = panel * PK_R, k0 = q * PK_K;
@@ -270,32 +271,33 @@ __global__ __launch_bounds__(256) void copy_pack64(const PackJob* __restrict__ j
   for (int e = threadIdx.x; e < PK_R * PK_K; e += 256) base[e] = t[e % PK_R][e / PK_R];
 }
 
-__global__ __launch_bounds__(XNT) void gemm_f64_packed(const SplitProb* __restrict__ probs, int nprob,
-                                                       int total) {
+template <int TP>
+__global__ __launch_bounds__(XNT) void gemm_f64_packed(const SplitProb* __restrict__ probs,
+                                                       const int* __restrict__ tile_prob, int total) {
+  constexpr int NB = 2 * TP;
   extern __shared__ __attribute__((aligned(16))) double f64_lds[];
-  const int b = blockIdx.x, t8 = total & ~7;
-  const int tile = b < t8 ? (b & 7) * (t8 >> 3) + (b >> 3) : b;
-  const SplitProb& p = probs[find_item(probs, nprob, tile)];
+  const int tile = xcd_tile(blockIdx.x, total);
+  const SplitProb& p = probs[tile_prob[tile]];
   int tm, tn;
   x6_tile(p, tile - p.begin, tm, tn);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int pa = wave >> 1, pb = wave & 1;
+  const int wrow = (wave >> 1) * 32 * TP, wcol = (wave & 1) * 32 * TP;
   const int lr = lane & 15, lk = lane >> 4;
 
   // LDS: [buffer][operand][panel][k][row]
-  constexpr int OPER = 2 * PK_CHUNK_64;
+  constexpr int OPER = TP * PK_CHUNK_64;
   constexpr int BUF = 2 * OPER;
-  const double* Ag = static_cast<const double*>(p.A) + (int64_t)(2 * tm) * p.ktiles * PK_CHUNK_64;
-  const double* Bg = static_cast<const double*>(p.B) + (int64_t)(2 * tn) * p.ktiles * PK_CHUNK_64;
   const int64_t pstride = (int64_t)p.ktiles * PK_CHUNK_64;
+  const double* Ag = static_cast<const double*>(p.A) + (int64_t)(TP * tm) * pstride;
+  const double* Bg = static_cast<const double*>(p.B) + (int64_t)(TP * tn) * pstride;
 
-  // staging: per operand 2 panels x 1024 pieces of 16 bytes; thread t takes
-  // pieces t + 256 u (u < 8)
-  i4 ra[8], rb[8];
+  // staging: per operand TP panels x 1024 pieces of 16 bytes; thread t takes
+  // pieces t + 256 u (u < 4 TP)
+  i4 ra[4 * TP], rb[4 * TP];
   auto fetch = [&](int kt) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 4 * TP; ++u) {
       const int e = threadIdx.x + u * XNT;
       const int pan = e >> 10, w = e & 1023;
       ra[u] = *reinterpret_cast<const i4*>(Ag + pan * pstride + (int64_t)kt * PK_CHUNK_64 + w * 2);
@@ -304,19 +306,23 @@ __global__ __launch_bounds__(XNT) void gemm_f64_packed(const SplitProb* __restri
   };
   auto commit = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 4 * TP; ++u) {
       const int e = threadIdx.x + u * XNT;
-      const int pan = e >> 10, w = e & 1023;
-      *reinterpret_cast<i4*>(f64_lds + buf * BUF + pan * PK_CHUNK_64 + w * 2) = ra[u];
-      *reinterpret_cast<i4*>(f64_lds + buf * BUF + OPER + pan * PK_CHUNK_64 + w * 2) = rb[u];
+      *reinterpret_cast<i4*>(f64_lds + buf * BUF + e * 2) = ra[u];
+      *reinterpret_cast<i4*>(f64_lds + buf * BUF + OPER + e * 2) = rb[u];
     }
   };
+  // element offset of (k, tile row off + 16 blk + lane row) inside an operand's panels
+  auto at = [&](int k, int off, int blk) {
+    const int trow = off + blk * 16;
+    return (trow >> 6) * PK_CHUNK_64 + k * PK_R + (trow & 63) + lr;
+  };
 
-  d4 c[4][4];
+  d4 c[NB][NB];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) c[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NB; ++j) c[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   if (p.ktiles > 0) {
     fetch(0);
@@ -326,31 +332,31 @@ __global__ __launch_bounds__(XNT) void gemm_f64_packed(const SplitProb* __restri
   for (int kt = 0; kt < p.ktiles; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < p.ktiles) fetch(kt + 1);
-    const double* As = f64_lds + buf * BUF + pa * PK_CHUNK_64;
-    const double* Bs = f64_lds + buf * BUF + OPER + pb * PK_CHUNK_64;
+    const double* As = f64_lds + buf * BUF;
+    const double* Bs = f64_lds + buf * BUF + OPER;
 #pragma unroll
     for (int ks = 0; ks < PK_K; ks += 4) {
-      double av[4], bv[4];
+      double av[NB], bv[NB];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        av[i] = As[(ks + lk) * PK_R + i * 16 + lr];
-        bv[i] = Bs[(ks + lk) * PK_R + i * 16 + lr];
+      for (int i = 0; i < NB; ++i) {
+        av[i] = As[at(ks + lk, wrow, i)];
+        bv[i] = Bs[at(ks + lk, wcol, i)];
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c[i][j], 0, 0, 0);
+        for (int j = 0; j < NB; ++j) c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c[i][j], 0, 0, 0);
     }
     if (kt + 1 < p.ktiles) commit(buf ^ 1);
     __syncthreads();
   }
 
   // epilogue: element r of lane l of block (i, j) is row l / 16 + 4 r, column l % 16
-  const int row0 = tm * XT + pa * 64, col0 = tn * XT + pb * 64;
+  const int row0 = tm * 64 * TP + wrow, col0 = tn * 64 * TP + wcol;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NB; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + i * 16 + lk + 4 * r, col = col0 + j * 16 + lr;
@@ -362,39 +368,46 @@ __global__ __launch_bounds__(XNT) void gemm_f64_packed(const SplitProb* __restri
       }
 }
 
-size_t split_gemm_lds_bytes() { return (size_t)2 * 2 * 2 * PK_CHUNK * sizeof(__bf16); }
-
-void launch_split_pack(const PackJob* d_jobs, int njobs, int chunks, hipStream_t s) {
-  if (njobs <= 0 || chunks <= 0) return;
-  split_pack<<<chunks, 256, 0, s>>>(d_jobs, njobs);
+void launch_split_pack(const PackJob* d_jobs, const int* d_chunk_job, int chunks, hipStream_t s) {
+  if (chunks <= 0) return;
+  split_pack<<<chunks, 256, 0, s>>>(d_jobs, d_chunk_job);
 }
 
-void launch_copy_pack64(const PackJob* d_jobs, int njobs, int chunks, hipStream_t s) {
-  if (njobs <= 0 || chunks <= 0) return;
-  copy_pack64<<<chunks, 256, 0, s>>>(d_jobs, njobs);
+void launch_copy_pack64(const PackJob* d_jobs, const int* d_chunk_job, int chunks, hipStream_t s) {
+  if (chunks <= 0) return;
+  copy_pack64<<<chunks, 256, 0, s>>>(d_jobs, d_chunk_job);
 }
 
-void launch_gemm_f64_packed(const SplitProb* d_probs, int nprob, int tiles, hipStream_t s) {
-  if (nprob <= 0 || tiles <= 0) return;
-  const size_t lds = (size_t)2 * 2 * 2 * PK_CHUNK_64 * sizeof(double);
+template <typename K>
+static void set_lds_limit(K kernel, size_t bytes) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes);
+}
+
+void launch_gemm_f64_packed(int tp, const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
+  if (tiles <= 0) return;
   static bool attr = false;
+  const size_t lds = (size_t)2 * 2 * tp * PK_CHUNK_64 * sizeof(double);
   if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_f64_packed),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    set_lds_limit(gemm_f64_packed<1>, (size_t)2 * 2 * 1 * PK_CHUNK_64 * sizeof(double));
+    set_lds_limit(gemm_f64_packed<2>, (size_t)2 * 2 * 2 * PK_CHUNK_64 * sizeof(double));
     attr = true;
   }
-  gemm_f64_packed<<<tiles, XNT, lds, s>>>(d_probs, nprob, tiles);
+  if (tp == 2) gemm_f64_packed<2><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
+  else gemm_f64_packed<1><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
 }
 
-void launch_gemm_x6_packed(const SplitProb* d_probs, int nprob, int tiles, hipStream_t s) {
-  if (nprob <= 0 || tiles <= 0) return;
+void launch_gemm_x6_packed(int tp, const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
+  if (tiles <= 0) return;
   static bool attr = false;
+  const size_t lds = (size_t)2 * 2 * tp * PK_CHUNK * sizeof(__bf16);
   if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_x6_packed),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)split_gemm_lds_bytes());
+    set_lds_limit(gemm_x6_packed<1>, (size_t)2 * 2 * 1 * PK_CHUNK * sizeof(__bf16));
+    set_lds_limit(gemm_x6_packed<2>, (size_t)2 * 2 * 2 * PK_CHUNK * sizeof(__bf16));
     attr = true;
   }
-  gemm_x6_packed<<<tiles, XNT, split_gemm_lds_bytes(), s>>>(d_probs, nprob, tiles);
+  if (tp == 2) gemm_x6_packed<2><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
+  else gemm_x6_packed<1><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
 }
 
 }  // namespace etdm
