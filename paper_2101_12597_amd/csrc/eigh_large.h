@@ -34,9 +34,11 @@ struct EighLarge {
   double* e;        // n: off-diagonal of T
   double* pv;       // 2 x n: tau A v of a step (two buffers by step parity)
   double* rowbuf;   // 2 x n: look-ahead rows (two buffers by parity)
-  double* W1;       // TB_NBW x n compact-WY scratch
+  double* W1;       // nkc x TB_NBW x n compact-WY scratch: the partial products Y_b^T X of
+                    // the TB_KC-row chunks of a block, stacked (chunk c at row c m_b)
   double* W2;       // TB_NBW x n
-  double* Tw;       // ceil((n-1)/TB_NBW) blocks of TB_NBW x TB_NBW compact-WY factors
+  double* Tw;       // ceil((n-1)/TB_NBW) blocks of TB_NBW x (nkc TB_NBW) compact-WY factors:
+                    // T_b (m_b x m_b) repeated nkc times side by side (at columns c m_b)
   double* Gw;       // the same number of Gram matrices Y_b^T Y_b (m_b x m_b, ld m_b)
   unsigned* bar;    // grid barrier words: [0] top arrivals, [1] generation, [2] abort, group counters
   int* ok;          // 1 when the tridiagonal result passed its checks
@@ -45,9 +47,11 @@ struct EighLarge {
   double* bhi;      // n
   int* bb;          // 2 n: unreduced block [b0, b1) of each eigenvalue
   int grid;         // workgroups of the reduction (one per CU, all resident)
+  int nkc;          // ceil((n - 1) / TB_KC): most K chunks of a block's Y_b^T X
 };
 
-constexpr int TB_NBW = 64;  // reflectors per compact-WY block of the back-transform
+constexpr int TB_NBW = 64;   // reflectors per compact-WY block of the back-transform
+constexpr int TB_KC = 256;   // K chunk of Y_b^T X (split K, so that the product fills the GPU)
 
 // float64 elements of workspace for size n; npad returned.
 size_t eigh_large_workspace(int n, size_t* npad_out);

@@ -337,8 +337,10 @@ size_t eigh_large_workspace(int n, size_t* npad_out) {
   if (npad_out) *npad_out = npad;
   const size_t half = npad / BLK / 2;
   const size_t nblk = (size_t)(n - 1 + TB_NBW - 1) / TB_NBW;
+  const size_t nkc = (size_t)std::max(1, (n - 1 + TB_KC - 1) / TB_KC);
   return 2 * npad * npad + half * SUB * SUB + PREP_BLOCKS + 2 * (size_t)n * n + 6 * (size_t)n +
-         2 * (size_t)TB_NBW * n + 2 * nblk * TB_NBW * TB_NBW + TB_BAR_WORDS / 2 + 2 + 4 + 3 * (size_t)n;
+         (nkc + 1) * TB_NBW * n + nblk * TB_NBW * TB_NBW * (nkc + 1) + TB_BAR_WORDS / 2 + 2 + 4 +
+         3 * (size_t)n;
 }
 
 void eigh_large_layout(EighLarge& e, double* ws, EighLargeState* st, int cu_count) {
@@ -357,11 +359,12 @@ void eigh_large_layout(EighLarge& e, double* ws, EighLargeState* st, int cu_coun
   e.e = e.d + n;
   e.pv = e.e + n;
   e.rowbuf = e.pv + 2 * n;
+  e.nkc = std::max(1, (n - 1 + TB_KC - 1) / TB_KC);
   e.W1 = e.rowbuf + 2 * n;
-  e.W2 = e.W1 + (size_t)TB_NBW * n;
+  e.W2 = e.W1 + (size_t)e.nkc * TB_NBW * n;
   e.Tw = e.W2 + (size_t)TB_NBW * n;
   const size_t nblk = (size_t)(n - 1 + TB_NBW - 1) / TB_NBW;
-  e.Gw = e.Tw + nblk * TB_NBW * TB_NBW;
+  e.Gw = e.Tw + nblk * TB_NBW * TB_NBW * e.nkc;
   e.bar = reinterpret_cast<unsigned*>(e.Gw + nblk * TB_NBW * TB_NBW);
   e.ok = reinterpret_cast<int*>(e.bar + TB_BAR_WORDS);
   e.scan = reinterpret_cast<double*>(e.bar + TB_BAR_WORDS + 4);
@@ -792,14 +795,16 @@ __global__ void tb_verdict(EighLarge e, int which) {
 
 // T factors of the compact WY form of blocks of TB_NBW reflectors (one workgroup
 // per block): T[:c, c] = T[:c, :c] (-tau_c g[:c, c]), T[c][c] = tau_c, with the Gram
-// matrix g = Y_b^T Y_b of the block already in Gw.
+// matrix g = Y_b^T Y_b of the block already in Gw.  T_b is written nkc times side by
+// side, so that T_b (sum over chunks of the partial Y_b^T X) is one product.
 __global__ __launch_bounds__(256) void tb_wy_t(EighLarge e) {
   if (!*e.ok) return;
   const int n = e.n, k0 = blockIdx.x * TB_NBW;
   const int m = min(TB_NBW, n - 1 - k0);
   const double* Y = e.Vw;
   const double* Gb = e.Gw + (size_t)blockIdx.x * TB_NBW * TB_NBW;
-  double* Tb = e.Tw + (size_t)blockIdx.x * TB_NBW * TB_NBW;
+  const int ldT = e.nkc * TB_NBW;
+  double* Tb = e.Tw + (size_t)blockIdx.x * TB_NBW * ldT;
   __shared__ double g[TB_NBW][TB_NBW + 1];
   __shared__ double T[TB_NBW][TB_NBW + 1];
   __shared__ double col[TB_NBW];
@@ -822,7 +827,10 @@ __global__ __launch_bounds__(256) void tb_wy_t(EighLarge e) {
     if (r == c) T[c][c] = tau;
     __syncthreads();
   }
-  for (int q = threadIdx.x; q < TB_NBW * TB_NBW; q += 256) Tb[q] = T[q / TB_NBW][q % TB_NBW];
+  for (int q = threadIdx.x; q < e.nkc * m * m; q += 256) {
+    const int c = q / (m * m), rem = q - c * m * m, r = rem / m, j = rem - r * m;
+    Tb[(size_t)r * ldT + c * m + j] = T[r][j];
+  }
 }
 
 void launch_tb_orth_check(const EighLarge& e, hipStream_t s) {

@@ -346,6 +346,7 @@ struct etdm_handle {
   char* pack_arena = nullptr;
   int gemm_tuning = 0;
   std::vector<Stage*> timer_stage;  // per timed stage: its GEMM launch, or null
+  std::vector<Stage*> tune_extra;   // further stages with a kernel choice (inside a timed stage)
   // tracing
   std::vector<StageTimer> timers;
   int64_t tmask = 0;
@@ -609,7 +610,9 @@ etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
   etdm_status st = ETDM_OK;
-  for (Stage* sg : h->timer_stage) {
+  std::vector<Stage*> all(h->timer_stage);
+  all.insert(all.end(), h->tune_extra.begin(), h->tune_extra.end());
+  for (Stage* sg : all) {
     if (!sg || !sg->can_pack()) continue;
     int best = V_TILE64;
     for (int v = 0; v < V_COUNT && st == ETDM_OK; ++v) {
@@ -695,13 +698,19 @@ etdm_status build_ov_plan(etdm_handle* h) {
         h->s_LWY2.resize(nblk);
         h->s_LWY3.resize(nblk);
       }
+      const int ldT = e.nkc * TB_NBW;
       for (int bk = 0; bk < nblk; ++bk) {
         const int k0 = bk * TB_NBW, mb = std::min(TB_NBW, N - 1 - k0), R = N - 1 - k0;
         const double* Yb = e.Vw + (size_t)(k0 + 1) * N + k0;
         h->s_LGram.add(prob(mb, mb, R, Yb, N, Yb, N, e.Gw + (size_t)bk * TB_NBW * TB_NBW, mb));
         double* Xr = e.X + (size_t)(k0 + 1) * N;
-        h->s_LWY1[bk].add(prob(mb, N, R, Yb, N, Xr, N, e.W1, N));
-        h->s_LWY2[bk].add(prob(mb, N, mb, e.Tw + (size_t)bk * TB_NBW * TB_NBW, TB_NBW, e.W1, N, e.W2, N));
+        // W1 = Y_b^T X in K chunks of TB_KC rows (partial c at rows c mb), then
+        // W2 = [T_b ... T_b] [W1_0; W1_1; ...] = T_b W1
+        int nc = 0;
+        for (int r0 = 0; r0 < R; r0 += TB_KC, ++nc)
+          h->s_LWY1[bk].add(prob(mb, N, std::min(TB_KC, R - r0), Yb + (size_t)r0 * N, N, Xr + (size_t)r0 * N, N,
+                                 e.W1 + (size_t)nc * mb * N, N));
+        h->s_LWY2[bk].add(prob(mb, N, nc * mb, e.Tw + (size_t)bk * TB_NBW * ldT, ldT, e.W1, N, e.W2, N));
         GemmProb up = prob(R, N, mb, Yb, N, e.W2, N, Xr, N, -1.0);
         up.beta = 1.0;
         up.D = Xr;
@@ -801,7 +810,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
                      &h->s_R,   &h->s_Gam1, &h->s_Gam, &h->s_Y1, &h->s_Y2, &h->s_G,  &h->s_Uov,
                      &h->s_Uvv, &h->s_HC0};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
-  CHECK(plan_packed_stages(h, stages, sizeof(stages) / sizeof(stages[0])));
+  std::vector<Stage*> packable(stages, stages + sizeof(stages) / sizeof(stages[0]));
   if (!h->eig_large.empty()) {
     h->s_LG.init(OP_T, OP_N, GP_FP64);
     h->s_LNS.init(OP_N, OP_N, GP_FP64);
@@ -811,6 +820,10 @@ etdm_status build_ov_plan(etdm_handle* h) {
     CHECK(upload_stage(h, h->s_LG));
     CHECK(upload_stage(h, h->s_LNS));
     CHECK(upload_stage(h, h->s_LR));
+    // the three N^3 products of the checks and the Gram matrices also get the
+    // kernel choice (the compact-WY blocks keep the grouped kernel: small m)
+    h->tune_extra = {&h->s_LG, &h->s_LNS, &h->s_LR, &h->s_LGram};
+    packable.insert(packable.end(), h->tune_extra.begin(), h->tune_extra.end());
     for (size_t bk = 0; bk < h->s_LWY1.size(); ++bk) {
       h->s_LWY1[bk].init(OP_T, OP_N, GP_FP64);
       h->s_LWY2[bk].init(OP_N, OP_N, GP_FP64);
@@ -821,6 +834,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
     }
     CHECK(upload(h, &h->d_lchk, lchk));
   }
+  CHECK(plan_packed_stages(h, packable.data(), packable.size()));
   CHECK(upload(h, &h->d_spec, spec));
   CHECK(upload(h, &h->b_spec, bspec));
   CHECK(upload(h, &h->d_rows, rows));
