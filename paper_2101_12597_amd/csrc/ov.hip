@@ -199,37 +199,81 @@ __global__ void copy_block_kernel(double* dst, int64_t ldd, const double* src, i
   dst[(size_t)i * ldd + j] = alpha * src[(size_t)i * lds + j];
 }
 
-// T = H C for a block-sparse H (square bs x bs blocks, bs <= BSR_MAX_BS) and a
-// dense row-major C (ncols columns).  Grid: (column tiles of 256, block rows).
-// Every thread owns one column j of one block row and keeps the bs outputs in
-// registers; the blocks of the row are staged through LDS one at a time and
-// read as broadcasts.  FP64 FMA on the vector units (the blocks are too small
-// and too few per row to feed the matrix cores).
+// T = H C for a block-sparse H (square bs x bs blocks, bs <= BSR_MAX_BS = 32) and a
+// dense row-major C (ncols columns), on the FP64 matrix cores.  Grid: (column
+// tiles of BSR_TC, block rows).  A workgroup computes one block row x BSR_TC
+// columns: every block of the row is staged in LDS zero-padded to 32 x kp (kp =
+// bs rounded up to 4) together with its bs x BSR_TC slab of C, and wavefront w
+// accumulates the 32 x 16 columns [16 w, 16 w + 16) as two v_mfma_f64_16x16x4f64
+// blocks.  The next block and slab are fetched into registers while the current
+// ones are multiplied.
+typedef double bsr_d4 __attribute__((ext_vector_type(4)));
+constexpr int BSR_TC = 64;                                         // columns per workgroup
+constexpr int BSR_HPER = (BSR_MAX_BS * BSR_MAX_BS + 255) / 256;    // block values per thread
+constexpr int BSR_CPER = (BSR_MAX_BS * BSR_TC + 255) / 256;        // slab values per thread
 __global__ __launch_bounds__(256) void bsr_spmm_kernel(BsrMat H, const double* __restrict__ C, int64_t ldc,
                                                        int ncols, double* __restrict__ T, int64_t ldt) {
-  __shared__ double blk[BSR_MAX_BS * BSR_MAX_BS];
-  const int I = blockIdx.y, bs = H.bs;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  const bool on = j < ncols;
-  double acc[BSR_MAX_BS];
+  __shared__ double hs[BSR_MAX_BS][BSR_MAX_BS + 1];
+  __shared__ double cs[BSR_MAX_BS][BSR_TC + 1];
+  const int I = blockIdx.y, bs = H.bs, kp = (bs + 3) & ~3;
+  const int j0 = blockIdx.x * BSR_TC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  // the padding (rows and columns >= bs) is zeroed once and never written
+  for (int e = tid; e < BSR_MAX_BS * (BSR_MAX_BS + 1); e += 256) (&hs[0][0])[e] = 0.0;
+  for (int e = tid; e < BSR_MAX_BS * (BSR_TC + 1); e += 256) (&cs[0][0])[e] = 0.0;
+  const int p0 = H.row_ptr[I], p1 = H.row_ptr[I + 1];
+  double rh[BSR_HPER], rc[BSR_CPER];
+  auto fetch = [&](int p) {
+    const double* hb = H.blocks + (size_t)p * bs * bs;
+    const double* cb = C + (size_t)H.col_idx[p] * bs * ldc + j0;
 #pragma unroll
-  for (int r = 0; r < BSR_MAX_BS; ++r) acc[r] = 0.0;
-  for (int p = H.row_ptr[I]; p < H.row_ptr[I + 1]; ++p) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < bs * bs; e += 256) blk[e] = H.blocks[(size_t)p * bs * bs + e];
-    __syncthreads();
-    const double* Cc = C + (size_t)H.col_idx[p] * bs * ldc;
-    for (int c = 0; c < bs; ++c) {
-      const double x = on ? Cc[(size_t)c * ldc + j] : 0.0;
-#pragma unroll
-      for (int r = 0; r < BSR_MAX_BS; ++r)
-        if (r < bs) acc[r] += blk[r * bs + c] * x;
+    for (int u = 0; u < BSR_HPER; ++u) {
+      const int e = tid + 256 * u;
+      rh[u] = e < bs * bs ? hb[e] : 0.0;
     }
-  }
-  if (!on) return;
 #pragma unroll
-  for (int r = 0; r < BSR_MAX_BS; ++r)
-    if (r < bs) T[(size_t)(I * bs + r) * ldt + j] = acc[r];
+    for (int u = 0; u < BSR_CPER; ++u) {
+      const int e = tid + 256 * u, k = e / BSR_TC, jj = e - k * BSR_TC;
+      rc[u] = (k < bs && j0 + jj < ncols) ? cb[(size_t)k * ldc + jj] : 0.0;
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int u = 0; u < BSR_HPER; ++u) {
+      const int e = tid + 256 * u;
+      if (e < bs * bs) hs[e / bs][e % bs] = rh[u];
+    }
+#pragma unroll
+    for (int u = 0; u < BSR_CPER; ++u) {
+      const int e = tid + 256 * u, k = e / BSR_TC, jj = e - k * BSR_TC;
+      if (k < bs) cs[k][jj] = rc[u];
+    }
+  };
+  bsr_d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  if (p0 < p1) fetch(p0);
+  __syncthreads();
+  for (int p = p0; p < p1; ++p) {
+    commit();
+    __syncthreads();
+    if (p + 1 < p1) fetch(p + 1);
+    for (int ks = 0; ks < kp; ks += 4) {
+      const double a0 = hs[lr][ks + lk], a1 = hs[16 + lr][ks + lk];
+      const double b = cs[ks + lk][wave * 16 + lr];
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc1, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // element r of lane l: row l / 16 + 4 r of the 16-row block, column l % 16
+  const int col = j0 + wave * 16 + lr;
+  if (col >= ncols) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int r0 = lk + 4 * r, r1 = 16 + lk + 4 * r;
+    if (r0 < bs) T[(size_t)(I * bs + r0) * ldt + col] = acc0[r];
+    if (r1 < bs) T[(size_t)(I * bs + r1) * ldt + col] = acc1[r];
+  }
 }
 
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
@@ -265,7 +309,7 @@ void launch_copy_block(double* dst, int64_t ldd, const double* src, int64_t lds,
 void launch_bsr_spmm(const BsrMat& H, const double* C, int64_t ldc, int ncols, double* T, int64_t ldt,
                      hipStream_t s) {
   if (ncols <= 0 || H.nbr <= 0) return;
-  dim3 grid((unsigned)nblk(ncols, 256), (unsigned)H.nbr);
+  dim3 grid((unsigned)nblk(ncols, BSR_TC), (unsigned)H.nbr);
   bsr_spmm_kernel<<<grid, 256, 0, s>>>(H, C, ldc, ncols, T, ldt);
 }
 
