@@ -609,6 +609,251 @@ __global__ __launch_bounds__(TB_NT) void tb_reduce(EighLarge e) {
   if (g == 0 && tid == 0) *e.ok = 1;  // reached only when no barrier aborted
 }
 
+// ---------------------------------------------------------------------------
+// The same reduction with the owned rows held in registers (n <= TR_NT TR_Q and
+// at most TR_R rows per workgroup): thread t of workgroup g keeps a_ij for the
+// rows i = g + G r and the columns j = t + TR_NT q.  The rank-2 update and the
+// fused product for p then never touch memory; per step only p, the look-ahead
+// row and the reflector column of Y cross the chip.  One grid barrier per step,
+// three workgroup barriers (the dot p.v, the reflector norm, the row dots).
+// ---------------------------------------------------------------------------
+constexpr int TR_NT = 512;
+constexpr int TR_Q = 5;    // columns per thread
+constexpr int TR_R = 10;   // own rows per workgroup
+constexpr int TR_W = TR_NT / 64;
+
+// Reflector c from register row c (entries j >= c + 1 valid): alpha = row[c+1],
+// sigma^2 = sum_{j >= c+2} row_j^2; v_{c+1} = 1, v_j = row_j / (alpha - beta).
+__device__ __forceinline__ double tr_reflector(const double (&row)[TR_Q], int c, int n, double (&v)[TR_Q],
+                                               double* red, double* s_alpha, double& beta) {
+  const int tid = threadIdx.x;
+  double s2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < TR_Q; ++q) {
+    const int j = tid + TR_NT * q;
+    if (j == c + 1) *s_alpha = row[q];
+    if (j >= c + 2 && j < n) s2 += row[q] * row[q];
+  }
+  s2 = tl_wave_sum(s2);
+  if ((tid & 63) == 0) red[tid >> 6] = s2;
+  __syncthreads();
+  s2 = 0.0;
+#pragma unroll
+  for (int w = 0; w < TR_W; ++w) s2 += red[w];
+  const double alpha = *s_alpha;
+  double tau = 0.0, inv = 0.0;
+  beta = alpha;
+  if (s2 != 0.0) {
+    beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+    tau = (beta - alpha) / beta;
+    inv = 1.0 / (alpha - beta);
+  }
+#pragma unroll
+  for (int q = 0; q < TR_Q; ++q) {
+    const int j = tid + TR_NT * q;
+    v[q] = j == c + 1 ? 1.0 : (j >= c + 2 && j < n ? row[q] * inv : 0.0);
+  }
+  return tau;
+}
+
+// Reflector column c of Y (workgroup 0): v_c below row c, zeros above it within
+// its compact-WY block, tau_c in the last column; d_c and e_c of T.
+__device__ __forceinline__ void tr_store_reflector(EighLarge& e, const double (&v)[TR_Q], double tau, double beta,
+                                                   int c, const double (&row)[TR_Q]) {
+  const int n = e.n, k0 = (c / TB_NBW) * TB_NBW;
+#pragma unroll
+  for (int q = 0; q < TR_Q; ++q) {
+    const int j = threadIdx.x + TR_NT * q;
+    if (j >= k0 + 1 && j < n) e.Vw[(size_t)j * n + c] = j >= c + 1 ? v[q] : 0.0;
+    if (j == c) e.d[c] = row[q];
+  }
+  if (threadIdx.x == 0) {
+    e.Vw[(size_t)c * n + (n - 1)] = tau;
+    e.e[c] = beta;
+  }
+}
+
+__global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
+  extern __shared__ double sm[];
+  __shared__ double red1[TR_W], red2[TR_W], red3[TR_W][TR_R];
+  __shared__ double s_pk1, s_alpha;
+  __shared__ double pown[TR_R];
+  const int n = e.n, G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* vfull = sm;  // the reflector of the step (n), read for the own rows
+  unsigned gen = 0;
+  double a[TR_R][TR_Q];
+  // own rows of A = sym(P), also kept in Ps for the final residual check
+#pragma unroll
+  for (int r = 0; r < TR_R; ++r) {
+    const int i = g + G * r;
+#pragma unroll
+    for (int q = 0; q < TR_Q; ++q) {
+      const int j = tid + TR_NT * q;
+      double x = 0.0;
+      if (i < n && j < n) {
+        x = 0.5 * (e.P[(size_t)i * n + j] + e.P[(size_t)j * n + i]);
+        e.Ps[(size_t)i * n + j] = x;
+      }
+      a[r][q] = x;
+    }
+  }
+  // reflector 0 from row 0 of sym(P), formed by every workgroup
+  double row[TR_Q], vc[TR_Q], vn[TR_Q];
+#pragma unroll
+  for (int q = 0; q < TR_Q; ++q) {
+    const int j = tid + TR_NT * q;
+    row[q] = j < n ? 0.5 * (e.P[j] + e.P[(size_t)j * n]) : 0.0;
+  }
+  double beta;
+  double tau = tr_reflector(row, 0, n, vc, red2, &s_alpha, beta);
+  if (g == 0) tr_store_reflector(e, vc, tau, beta, 0, row);
+#pragma unroll
+  for (int q = 0; q < TR_Q; ++q) {
+    const int j = tid + TR_NT * q;
+    if (j < n) vfull[j] = vc[q];
+  }
+  // p_0 = tau_0 A v_0 for the own rows i >= 1, and the look-ahead copy of row 1
+  {
+    double acc[TR_R];
+#pragma unroll
+    for (int r = 0; r < TR_R; ++r) {
+      const int i = g + G * r;
+      acc[r] = 0.0;
+      if (i >= 1 && i < n) {
+#pragma unroll
+        for (int q = 0; q < TR_Q; ++q) {
+          const int j = tid + TR_NT * q;
+          if (j >= 1 && j < n) {
+            acc[r] += a[r][q] * vc[q];
+            if (i == 1) tb_put(&e.rowbuf[n + j], a[r][q]);
+          }
+        }
+      }
+      acc[r] = tl_wave_sum(acc[r]);
+    }
+    if (lane == 0)
+#pragma unroll
+      for (int r = 0; r < TR_R; ++r) red3[wave][r] = acc[r];
+    __syncthreads();
+    if (tid < TR_R) {
+      const int i = g + G * tid;
+      double t = 0.0;
+      for (int w = 0; w < TR_W; ++w) t += red3[w][tid];
+      pown[tid] = tau * t;
+      if (i >= 1 && i < n) tb_put(&e.pv[i], tau * t);
+    }
+  }
+  if (!tb_grid_sync(e.bar, gen)) return;
+  double vown[TR_R];
+#pragma unroll
+  for (int r = 0; r < TR_R; ++r) {
+    const int i = g + G * r;
+    vown[r] = i < n ? vfull[i] : 0.0;
+  }
+
+  for (int k = 0; k < n - 2; ++k) {
+    // p_k and the look-ahead row k + 1 (as after step k - 1)
+    const double* p = e.pv + (size_t)(k & 1) * n;
+    const double* rb = e.rowbuf + (size_t)((k + 1) & 1) * n;
+    double pj[TR_Q], rj[TR_Q];
+#pragma unroll
+    for (int q = 0; q < TR_Q; ++q) {
+      const int j = tid + TR_NT * q;
+      const bool on = j >= k + 1 && j < n;
+      pj[q] = on ? tb_get(&p[j]) : 0.0;
+      rj[q] = on ? tb_get(&rb[j]) : 0.0;
+    }
+    // w = p - (tau / 2) (p . v) v
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < TR_Q; ++q) {
+      part += pj[q] * vc[q];
+      if (tid + TR_NT * q == k + 1) s_pk1 = pj[q];
+    }
+    part = tl_wave_sum(part);
+    if (lane == 0) red1[wave] = part;
+    __syncthreads();
+    double dot = 0.0;
+#pragma unroll
+    for (int w = 0; w < TR_W; ++w) dot += red1[w];
+    const double K = -0.5 * tau * dot;
+    const double wk1 = s_pk1 + K;  // w_{k+1} (v_{k+1} = 1)
+    double wv[TR_Q];
+#pragma unroll
+    for (int q = 0; q < TR_Q; ++q) {
+      wv[q] = pj[q] + K * vc[q];
+      row[q] = rj[q] - (wv[q] + wk1 * vc[q]);  // row k + 1 after this step
+    }
+    double wown[TR_R];
+#pragma unroll
+    for (int r = 0; r < TR_R; ++r) wown[r] = pown[r] + K * vown[r];
+    // reflector k + 1 from row k + 1
+    double taun = 0.0;
+    if (k + 1 <= n - 3) {
+      taun = tr_reflector(row, k + 1, n, vn, red2, &s_alpha, beta);
+      if (g == 0) tr_store_reflector(e, vn, taun, beta, k + 1, row);
+#pragma unroll
+      for (int q = 0; q < TR_Q; ++q) {
+        const int j = tid + TR_NT * q;
+        if (j >= k + 2 && j < n) vfull[j] = vn[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < TR_Q; ++q) {
+        vn[q] = 0.0;
+        const int j = tid + TR_NT * q;
+        if (g == 0 && j == n - 2) e.d[n - 2] = row[q];  // the last 2 x 2 block
+        if (g == 0 && j == n - 1) e.e[n - 2] = row[q];
+      }
+    }
+    // own rows i >= k + 2, columns j >= k + 2: a_ij -= v_i w_j + w_i v_j, and the
+    // partial sums of p_{k+1} = tau_{k+1} A v_{k+1}
+    const int rnext = k + 2;
+    double* pn = e.pv + (size_t)((k + 1) & 1) * n;
+    double* rbn = e.rowbuf + (size_t)((k + 2) & 1) * n;
+    double acc[TR_R];
+#pragma unroll
+    for (int r = 0; r < TR_R; ++r) {
+      const int i = g + G * r;
+      acc[r] = 0.0;
+      if (i >= rnext && i < n) {
+#pragma unroll
+        for (int q = 0; q < TR_Q; ++q) {
+          const int j = tid + TR_NT * q;
+          if (j >= rnext && j < n) {
+            a[r][q] -= vown[r] * wv[q] + wown[r] * vc[q];
+            acc[r] += a[r][q] * vn[q];
+            if (i == rnext) tb_put(&rbn[j], a[r][q]);
+            if (k == n - 3 && i == n - 1 && j == n - 1) e.d[n - 1] = a[r][q];
+          }
+        }
+      }
+      acc[r] = tl_wave_sum(acc[r]);
+    }
+    if (lane == 0)
+#pragma unroll
+      for (int r = 0; r < TR_R; ++r) red3[wave][r] = acc[r];
+    __syncthreads();
+    if (tid < TR_R) {
+      const int i = g + G * tid;
+      double t = 0.0;
+      for (int w = 0; w < TR_W; ++w) t += red3[w][tid];
+      pown[tid] = taun * t;
+      if (i >= rnext && i < n) tb_put(&pn[i], taun * t);
+    }
+#pragma unroll
+    for (int q = 0; q < TR_Q; ++q) vc[q] = vn[q];
+    tau = taun;
+    if (!tb_grid_sync(e.bar, gen)) return;
+#pragma unroll
+    for (int r = 0; r < TR_R; ++r) {
+      const int i = g + G * r;
+      vown[r] = i < n ? vfull[i] : 0.0;
+    }
+  }
+  if (g == 0 && tid == 0) *e.ok = 1;  // reached only when no barrier aborted
+}
+
 // Eigenvalue brackets of T: workgroup b takes eigenvalues [b m, (b+1) m) (m = TE_CH):
 // brackets on the unreduced blocks and multisection down to TB_BISECT_TOL ||T||,
 // written to lo / hi (and the block bounds) for the vector kernel.
@@ -862,8 +1107,18 @@ void launch_tb_solve(const EighLarge& e, int* status, hipStream_t s) {
                         (int)eig_lds);
     attr_e = eig_lds;
   }
+  static size_t attr_g = 0;
+  if (lds > attr_g) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_reduce_reg), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    attr_g = lds;
+  }
   tb_init<<<1, 256, 0, s>>>(e);
-  tb_reduce<<<e.grid, TB_NT, lds, s>>>(e);
+  // rows in registers when they fit: n <= TR_NT TR_Q columns, <= TR_R rows per workgroup
+  if (n <= TR_NT * TR_Q && (n + e.grid - 1) / e.grid <= TR_R)
+    tb_reduce_reg<<<e.grid, TR_NT, lds, s>>>(e);
+  else
+    tb_reduce<<<e.grid, TB_NT, lds, s>>>(e);
   tb_bisect<<<(n + TE_CH - 1) / TE_CH, TE_NT, eig_lds, s>>>(e);
   tb_vectors<<<(n + TV_NT - 1) / TV_NT, TV_NT, eig_lds, s>>>(e);
 }
