@@ -56,9 +56,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--lbfgs-iters", type=int, default=0, help="also time this many L-BFGS iterations")
-    ap.add_argument("--gemm-tuning", type=int, default=0, choices=[0, 1, 2, 3, 4],
+    ap.add_argument("--gemm-tuning", type=int, default=0, choices=range(7),
                     help="GEMM kernel choice: 0 tuned at creation, 1 size rule, 2 packed 128x128, "
-                         "3 grouped 64x64, 4 packed 64x64")
+                         "3 grouped 64x64, 4 packed 64x64, 5 packed 128x64, 6 packed 64x128")
     return ap.parse_args()
 
 

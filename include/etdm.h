@@ -99,12 +99,13 @@ typedef struct {
   const int32_t *bsr_row_ptr; /* host, per instance (M/bs + 1) entries, concatenated */
   const int32_t *bsr_col_idx; /* host, per instance row_ptr[last] entries, concatenated */
   int32_t gemm_tuning;    /* kernel choice of the real FP64 and BF16x6 GEMM stages:
-                             0 = time the three kernels on the handle's buffers in
-                             etdm_create and keep the fastest; 1 = fixed rule (packed
-                             128 x 128 tiles when every problem of the stage is at least
-                             128 x 128 with K >= 256, else 64 x 64 tiles); 2 = always
-                             packed 128 x 128; 3 = always grouped 64 x 64; 4 = always
-                             packed 64 x 64.  Other values: ETDM_E_ARG */
+                             0 = time the ETDM_GEMM_VARIANTS kernels on the handle's
+                             buffers in etdm_create and keep the fastest; 1 = fixed rule
+                             (packed 128 x 128 tiles when every problem of the stage is at
+                             least 128 x 128 with K >= 256, else grouped 64 x 64); forced:
+                             2 = packed 128 x 128, 3 = grouped 64 x 64, 4 = packed 64 x 64,
+                             5 = packed 128 x 64, 6 = packed 64 x 128.
+                             Other values: ETDM_E_ARG */
 } etdm_desc;
 
 /* Create a handle.  H0: device, dense float64 (REAL_OV) or complex float64
@@ -196,15 +197,18 @@ int32_t etdm_stage_count(const etdm_handle *h);
 etdm_status etdm_stage_info(etdm_handle *h, int32_t i, const char **name, int64_t *launches,
                             double *total_ms, double *flops, double *bytes);
 
-/* GEMM kernel of stage i: *variant = "tile64" / "fp64_tile64" (grouped 64 x 64
- * tiles that read, and for BF16x6 split, the operands in every tile),
- * "packed64" / "fp64_packed64" and "packed128" / "fp64_packed128" (operands
- * packed, and split, once per launch into a panel buffer; 64 x 64 or 128 x 128
- * tiles), "zgemm64" (complex), or "" for a stage that is not a GEMM.  ms_* = the
- * launch times of the three kernels measured by the tuning in etdm_create (0 when
- * not timed).  Any output pointer may be NULL. */
-etdm_status etdm_stage_kernel(const etdm_handle *h, int32_t i, const char **variant, double *ms_tile,
-                              double *ms_packed64, double *ms_packed128);
+/* GEMM kernels of a real FP64 / BF16x6 stage, in the order of etdm_stage_kernel's
+ * tuned_ms: grouped 64 x 64 tiles that read (and split) the operands in every tile;
+ * then the operands packed (and split) once per launch into a panel buffer and
+ * tiles of 64 x 64, 128 x 64, 64 x 128 and 128 x 128. */
+#define ETDM_GEMM_VARIANTS 5
+
+/* GEMM kernel of stage i: *variant = "tile64", "packed64", "packed128x64",
+ * "packed64x128" or "packed128" (prefixed "fp64_" for FP64 stages), "zgemm64"
+ * (complex), or "" for a stage that is not a GEMM.  tuned_ms (ETDM_GEMM_VARIANTS
+ * doubles, or NULL) = the launch times of the kernels measured by the tuning in
+ * etdm_create (0 when not timed). */
+etdm_status etdm_stage_kernel(const etdm_handle *h, int32_t i, const char **variant, double *tuned_ms);
 
 /* Number of parameters of one A (or G) array in float64 units:
  * REAL_OV sum N(M-N); COMPLEX_FULL 2 sum M^2. */

@@ -62,7 +62,7 @@ struct PackJob {
   int32_t trans, rows, K, kt0, ktiles, kt_n, begin;
 };
 // C (m x n, FP64) = sum over k of A[i][k] B[j][k] + beta D for packed A (m rows) and
-// B (n rows) with ktiles k-tiles, in tiles of tp x tp panels (64 tp rows and
+// B (n rows) with ktiles k-tiles, in tiles of tpm x tpn panels (64 tpm rows, 64 tpn
 // columns); begin = prefix sum of tiles, the tile table maps workgroups to problems.
 struct SplitProb {
   const void* A;
@@ -77,9 +77,11 @@ constexpr int PK_CHUNK_X6 = PK_S * PK_R * PK_K;  // BF16 values of a split chunk
 constexpr int PK_CHUNK_64 = PK_R * PK_K;         // FP64 values of an FP64 chunk
 void launch_split_pack(const PackJob* d_jobs, const int* d_chunk_job, int chunks, hipStream_t s);
 void launch_copy_pack64(const PackJob* d_jobs, const int* d_chunk_job, int chunks, hipStream_t s);
-// tp = 1 (64 x 64 tiles) or 2 (128 x 128 tiles)
-void launch_gemm_f64_packed(int tp, const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s);
-void launch_gemm_x6_packed(int tp, const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s);
+// tiles of tpm x tpn panels of 64 (tpm, tpn in {1, 2})
+void launch_gemm_f64_packed(int tpm, int tpn, const SplitProb* d_probs, const int* d_tile_prob, int tiles,
+                            hipStream_t s);
+void launch_gemm_x6_packed(int tpm, int tpn, const SplitProb* d_probs, const int* d_tile_prob, int tiles,
+                           hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Jacobi eigensolver (FP64), one workgroup per matrix

@@ -55,16 +55,18 @@ void gauss_legendre01(int n, double* t, double* w) {
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // One grouped GEMM launch.  Problems are added at plan time and uploaded once.
-// A real FP64 or BF16x6 stage has three kernels:
+// A real FP64 or BF16x6 stage has five kernels:
 //   V_TILE64   the grouped 64 x 64 kernel that reads (and splits) the operands
 //              inside every tile (gemm.hip);
-//   V_PACK64   a pack pass into a panel layout shared by all stages, then
-//              64 x 64 tiles on the packed operands (gemm_split.hip);
-//   V_PACK128  the same with 128 x 128 tiles.
+//   V_P11 .. V_P22  a pack pass into a panel layout shared by all stages, then
+//              tiles of tpm x tpn panels of 64 on the packed operands
+//              (gemm_split.hip): 64 x 64, 128 x 64, 64 x 128, 128 x 128.
 // Which one runs is chosen at plan time (tune_stages).
-enum GemmVariant { V_TILE64 = 0, V_PACK64 = 1, V_PACK128 = 2, V_COUNT = 3 };
+enum GemmVariant { V_TILE64 = 0, V_P11 = 1, V_P21 = 2, V_P12 = 3, V_P22 = 4, V_COUNT = 5 };
+constexpr int kVarTpm[V_COUNT] = {0, 1, 2, 1, 2};
+constexpr int kVarTpn[V_COUNT] = {0, 1, 1, 2, 2};
 
-// The launches of one packed variant (tp panels of 64 rows per tile side).
+// The launches of one packed variant.
 struct PackPlan {
   std::vector<PackJob> jobs;
   std::vector<int32_t> chunk_job;  // pack workgroup -> job
@@ -86,8 +88,8 @@ struct Stage {
   int opA = OP_N, opB = OP_N, prec = GP_FP64;
   bool cplx = false;
   int variant = V_TILE64;
-  PackPlan pk[2];                      // tp = 1, 2
-  float tuned_ms[V_COUNT] = {0.f, 0.f, 0.f};  // plan-time launch times per variant (0: not timed)
+  PackPlan pk[V_COUNT - 1];                  // the packed variants V_P11 .. V_P22
+  float tuned_ms[V_COUNT] = {};              // plan-time launch times per variant (0: not timed)
   void init(int a, int b, int p, bool c = false) {
     opA = a;
     opB = b;
@@ -110,15 +112,17 @@ struct Stage {
     return ceil_div(std::max(p.k, 0), PK_K) + ceil_div(std::max(p.k2, 0), PK_K);
   }
   static int panels(int rows, int tp) { return tp * ceil_div(rows, PK_R * tp); }
-  // bytes of the packed operands of all problems for tiles of tp panels
-  size_t pack_bytes(int tp) const {
+  // bytes of the packed operands of all problems for packed variant v
+  size_t pack_bytes(int v) const {
     size_t n = 0;
-    for (const GemmProb& p : probs) n += (size_t)(panels(p.m, tp) + panels(p.n, tp)) * ktiles(p) * chunk_bytes();
+    for (const GemmProb& p : probs)
+      n += (size_t)(panels(p.m, kVarTpm[v]) + panels(p.n, kVarTpn[v])) * ktiles(p) * chunk_bytes();
     return n;
   }
-  // pack jobs and packed problems of variant tp with the operands at arena
-  void plan_pack(int tp, char* arena) {
-    PackPlan& q = pk[tp - 1];
+  // pack jobs and packed problems of packed variant v with the operands at arena
+  void plan_pack(int v, char* arena) {
+    const int tpm = kVarTpm[v], tpn = kVarTpn[v];
+    PackPlan& q = pk[v - 1];
     q = PackPlan();
     const size_t chunk = chunk_bytes();
     size_t off = 0;
@@ -143,7 +147,7 @@ struct Stage {
     };
     for (const GemmProb& p : probs) {
       const int kt = ktiles(p), kt1 = ceil_div(std::max(p.k, 0), PK_K);
-      const int pa = panels(p.m, tp), pb = panels(p.n, tp);
+      const int pa = panels(p.m, tpm), pb = panels(p.n, tpn);
       char* a = arena + off;
       off += (size_t)pa * kt * chunk;
       char* b = arena + off;
@@ -164,8 +168,8 @@ struct Stage {
       sp.m = p.m;
       sp.n = p.n;
       sp.ktiles = kt;
-      sp.tiles_m = ceil_div(p.m, PK_R * tp);
-      sp.tiles_n = ceil_div(p.n, PK_R * tp);
+      sp.tiles_m = ceil_div(p.m, PK_R * tpm);
+      sp.tiles_n = ceil_div(p.n, PK_R * tpn);
       sp.begin = q.tiles;
       q.tiles += sp.tiles_m * sp.tiles_n;
       q.tile_prob.resize(q.tiles, (int32_t)q.probs.size());
@@ -177,25 +181,25 @@ struct Stage {
   int variant_by_size() const {
     for (const GemmProb& p : probs)
       if (p.m < 128 || p.n < 128 || p.k + std::max(p.k2, 0) < 256) return V_TILE64;
-    return V_PACK128;
+    return V_P22;
   }
   const char* variant_name() const {
-    static const char* real[V_COUNT] = {"tile64", "packed64", "packed128"};
-    static const char* f64[V_COUNT] = {"fp64_tile64", "fp64_packed64", "fp64_packed128"};
+    static const char* real[V_COUNT] = {"tile64", "packed64", "packed128x64", "packed64x128", "packed128"};
+    static const char* f64[V_COUNT] = {"fp64_tile64", "fp64_packed64", "fp64_packed128x64", "fp64_packed64x128",
+                                       "fp64_packed128"};
     if (cplx) return "zgemm64";
     return prec == GP_FP64 ? f64[variant] : real[variant];
   }
   void launch(hipStream_t s) const {
     if (probs.empty()) return;
     if (variant != V_TILE64) {
-      const int tp = variant == V_PACK128 ? 2 : 1;
-      const PackPlan& q = pk[tp - 1];
+      const PackPlan& q = pk[variant - 1];
       if (prec == GP_FP64) {
         launch_copy_pack64(q.d_jobs, q.d_chunk_job, q.chunks, s);
-        launch_gemm_f64_packed(tp, q.d_probs, q.d_tile_prob, q.tiles, s);
+        launch_gemm_f64_packed(kVarTpm[variant], kVarTpn[variant], q.d_probs, q.d_tile_prob, q.tiles, s);
       } else {
         launch_split_pack(q.d_jobs, q.d_chunk_job, q.chunks, s);
-        launch_gemm_x6_packed(tp, q.d_probs, q.d_tile_prob, q.tiles, s);
+        launch_gemm_x6_packed(kVarTpm[variant], kVarTpn[variant], q.d_probs, q.d_tile_prob, q.tiles, s);
       }
     } else if (cplx) {
       launch_zgemm(d, d_tile_prob, tiles, opA, opB, s);
@@ -574,7 +578,8 @@ etdm_status upload_stage(etdm_handle* h, Stage& s) {
 etdm_status plan_packed_stages(etdm_handle* h, Stage* const* stages, size_t n) {
   size_t bytes = 0;
   for (size_t i = 0; i < n; ++i)
-    if (stages[i]->can_pack()) bytes = std::max({bytes, stages[i]->pack_bytes(1), stages[i]->pack_bytes(2)});
+    if (stages[i]->can_pack())
+      for (int v = V_P11; v < V_COUNT; ++v) bytes = std::max(bytes, stages[i]->pack_bytes(v));
   if (bytes == 0) return ETDM_OK;
   void* p = nullptr;
   HIPCHK(h, hipMalloc(&p, bytes));
@@ -583,18 +588,20 @@ etdm_status plan_packed_stages(etdm_handle* h, Stage* const* stages, size_t n) {
   for (size_t i = 0; i < n; ++i) {
     Stage& sg = *stages[i];
     if (!sg.can_pack()) continue;
-    for (int tp = 1; tp <= 2; ++tp) {
-      sg.plan_pack(tp, h->pack_arena);
-      PackPlan& q = sg.pk[tp - 1];
+    for (int v = V_P11; v < V_COUNT; ++v) {
+      sg.plan_pack(v, h->pack_arena);
+      PackPlan& q = sg.pk[v - 1];
       CHECK(upload(h, &q.d_jobs, q.jobs));
       CHECK(upload(h, &q.d_chunk_job, q.chunk_job));
       CHECK(upload(h, &q.d_probs, q.probs));
       CHECK(upload(h, &q.d_tile_prob, q.tile_prob));
     }
     switch (h->gemm_tuning) {
-      case 2: sg.variant = V_PACK128; break;
+      case 2: sg.variant = V_P22; break;
       case 3: sg.variant = V_TILE64; break;
-      case 4: sg.variant = V_PACK64; break;
+      case 4: sg.variant = V_P11; break;
+      case 5: sg.variant = V_P21; break;
+      case 6: sg.variant = V_P12; break;
       default: sg.variant = sg.variant_by_size();
     }
   }
@@ -1474,7 +1481,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (d->kind != ETDM_REAL_OV && d->kind != ETDM_COMPLEX_FULL) return ETDM_E_ARG;
   if (d->precision < ETDM_FP64 || d->precision > ETDM_MIXED) return ETDM_E_ARG;
   if (d->kind == ETDM_COMPLEX_FULL && d->precision != ETDM_FP64) return ETDM_E_ARG;
-  if (d->gemm_tuning < 0 || d->gemm_tuning > 4) return ETDM_E_ARG;
+  if (d->gemm_tuning < 0 || d->gemm_tuning > 6) return ETDM_E_ARG;
   if (d->kind == ETDM_REAL_OV && (!d->N || d->couple)) return ETDM_E_ARG;
   if (d->h0_format != 0 && d->h0_format != 1) return ETDM_E_ARG;
   if (d->h0_format == 1 && (d->kind != ETDM_REAL_OV || d->bsr_block < 1 || d->bsr_block > BSR_MAX_BS ||
@@ -1727,14 +1734,12 @@ etdm_status etdm_stage_info(etdm_handle* h, int32_t i, const char** name, int64_
   return ETDM_OK;
 }
 
-etdm_status etdm_stage_kernel(const etdm_handle* h, int32_t i, const char** variant, double* ms_tile,
-                              double* ms_packed64, double* ms_packed128) {
+etdm_status etdm_stage_kernel(const etdm_handle* h, int32_t i, const char** variant, double* tuned_ms) {
   if (!h || i < 0 || i >= (int32_t)h->timers.size()) return ETDM_E_ARG;
   const Stage* sg = i < (int32_t)h->timer_stage.size() ? h->timer_stage[i] : nullptr;
   if (variant) *variant = sg && !sg->probs.empty() ? sg->variant_name() : "";
-  if (ms_tile) *ms_tile = sg ? sg->tuned_ms[V_TILE64] : 0.0;
-  if (ms_packed64) *ms_packed64 = sg ? sg->tuned_ms[V_PACK64] : 0.0;
-  if (ms_packed128) *ms_packed128 = sg ? sg->tuned_ms[V_PACK128] : 0.0;
+  if (tuned_ms)
+    for (int v = 0; v < V_COUNT; ++v) tuned_ms[v] = sg ? sg->tuned_ms[v] : 0.0;
   return ETDM_OK;
 }
 

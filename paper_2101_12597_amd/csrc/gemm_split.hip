@@ -20,10 +20,12 @@
 // with two K segments (C = a1 A1 B1 + a2 A2 B2) packs [a1 A1 | a2 A2] and
 // [B1; B2] along k, so the GEMM sees one K.
 //
-// gemm_x6_packed<TP> / gemm_f64_packed<TP>: C = op(A) op(B) + beta D for packed
-// op(A) and op(B)^T (both rows x K).  A workgroup of 4 wavefronts computes a
-// tile of TP x TP panels (TP = 1: 64 x 64, TP = 2: 128 x 128); each wavefront
-// owns a 32 TP x 32 TP quarter as (2 TP)^2 blocks of 16 x 16.  BF16x6 sums the
+// gemm_x6_packed<TPM, TPN> / gemm_f64_packed<TPM, TPN>: C = op(A) op(B) + beta D
+// for packed op(A) and op(B)^T (both rows x K).  A workgroup of 4 wavefronts
+// computes a tile of TPM x TPN panels (64 TPM x 64 TPN, TPM and TPN in {1, 2});
+// each wavefront owns a 32 TPM x 32 TPN quarter as 2 TPM x 2 TPN blocks of
+// 16 x 16.  Larger wavefront tiles read fewer LDS fragments per MFMA; smaller
+// ones leave room for more wavefronts per SIMD.  BF16x6 sums the
 // six slice products with i + j <= 2 (v_mfma_f32_16x16x32_bf16) in FP32 and adds
 // them into FP64 registers every X_FLUSH k-tiles.  The k-tiles are
 // double-buffered in LDS with the next one fetched into registers during the
@@ -98,9 +100,9 @@ __global__ __launch_bounds__(256) void split_pack(const PackJob* __restrict__ jo
 }
 
 // ---------------------------------------------------------------------------
-// gemm_x6_packed<TP>: tiles of TP x TP panels (64 TP rows and columns); the four
-// wavefronts form a 2 x 2 grid of 32 TP x 32 TP sub-tiles, NB = 2 TP blocks of
-// 16 x 16 per side
+// gemm_x6_packed<TPM, TPN>: tiles of TPM x TPN panels (64 TPM rows, 64 TPN
+// columns); the four wavefronts form a 2 x 2 grid of 32 TPM x 32 TPN sub-tiles,
+// NBM = 2 TPM by NBN = 2 TPN blocks of 16 x 16
 // ---------------------------------------------------------------------------
 // tile index inside one problem, grouped X_GROUP tile rows at a time so that the
 // workgroups resident together share A and B panels
@@ -120,10 +122,10 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
   return b < t8 ? (b & 7) * (t8 >> 3) + (b >> 3) : b;
 }
 
-template <int TP>
+template <int TPM, int TPN>
 __global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restrict__ probs,
                                                       const int* __restrict__ tile_prob, int total) {
-  constexpr int NB = 2 * TP;
+  constexpr int NBM = 2 * TPM, NBN = 2 * TPN;
   extern __shared__ __attribute__((aligned(16))) __bf16 x6_lds[];
   const int tile = xcd_tile(blockIdx.x, total);
   const SplitProb& p = probs[tile_prob[tile]];
@@ -131,49 +133,54 @@ __global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restric
   x6_tile(p, tile - p.begin, tm, tn);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wrow = (wave >> 1) * 32 * TP, wcol = (wave & 1) * 32 * TP;  // sub-tile offsets
+  const int wrow = (wave >> 1) * 32 * TPM, wcol = (wave & 1) * 32 * TPN;  // sub-tile offsets
   const int lr = lane & 15, lo = lane >> 4;
 
-  // LDS: [buffer][operand][panel][slice][row][k]
-  constexpr int OPER = TP * PK_CHUNK;
-  constexpr int BUF = 2 * OPER;
+  // LDS: [buffer][A panels | B panels][slice][row][k]
+  constexpr int OPERA = TPM * PK_CHUNK, OPERB = TPN * PK_CHUNK;
+  constexpr int BUF = OPERA + OPERB;
   const int64_t pstride = (int64_t)p.ktiles * PK_CHUNK;  // panel stride in the packed operand
-  const __bf16* Ag = static_cast<const __bf16*>(p.A) + (int64_t)(TP * tm) * pstride;
-  const __bf16* Bg = static_cast<const __bf16*>(p.B) + (int64_t)(TP * tn) * pstride;
+  const __bf16* Ag = static_cast<const __bf16*>(p.A) + (int64_t)(TPM * tm) * pstride;
+  const __bf16* Bg = static_cast<const __bf16*>(p.B) + (int64_t)(TPN * tn) * pstride;
 
-  // staging: per operand TP panels x 768 pieces of 16 bytes; thread t takes
-  // pieces t + 256 u (u < 3 TP)
-  i4 ra[3 * TP], rb[3 * TP];
+  // staging: TPM (TPN) panels x 768 pieces of 16 bytes of A (B); thread t takes
+  // pieces t + 256 u
+  i4 ra[3 * TPM], rb[3 * TPN];
   auto fetch = [&](int kt) {
 #pragma unroll
-    for (int u = 0; u < 3 * TP; ++u) {
+    for (int u = 0; u < 3 * TPM; ++u) {
       const int e = threadIdx.x + u * XNT;
       const int pan = e / 768, w = e % 768;
       ra[u] = *reinterpret_cast<const i4*>(Ag + pan * pstride + (int64_t)kt * PK_CHUNK + w * 8);
+    }
+#pragma unroll
+    for (int u = 0; u < 3 * TPN; ++u) {
+      const int e = threadIdx.x + u * XNT;
+      const int pan = e / 768, w = e % 768;
       rb[u] = *reinterpret_cast<const i4*>(Bg + pan * pstride + (int64_t)kt * PK_CHUNK + w * 8);
     }
   };
   auto commit = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 3 * TP; ++u) {
-      const int e = threadIdx.x + u * XNT;
-      *reinterpret_cast<i4*>(x6_lds + buf * BUF + e * 8) = ra[u];
-      *reinterpret_cast<i4*>(x6_lds + buf * BUF + OPER + e * 8) = rb[u];
-    }
+    for (int u = 0; u < 3 * TPM; ++u)
+      *reinterpret_cast<i4*>(x6_lds + buf * BUF + (threadIdx.x + u * XNT) * 8) = ra[u];
+#pragma unroll
+    for (int u = 0; u < 3 * TPN; ++u)
+      *reinterpret_cast<i4*>(x6_lds + buf * BUF + OPERA + (threadIdx.x + u * XNT) * 8) = rb[u];
   };
 
-  double acc[NB][NB][4];
+  double acc[NBM][NBN][4];
 #pragma unroll
-  for (int i = 0; i < NB; ++i)
+  for (int i = 0; i < NBM; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
+    for (int j = 0; j < NBN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
-  f4 c[NB][NB];
+  f4 c[NBM][NBN];
 #pragma unroll
-  for (int i = 0; i < NB; ++i)
+  for (int i = 0; i < NBM; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NBN; ++j) c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   // fragment offset (BF16 elements) of the 16-row block starting at tile row
   // off + 16 blk, slice s
@@ -192,32 +199,32 @@ __global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restric
     const int buf = kt & 1;
     if (kt + 1 < p.ktiles) fetch(kt + 1);
     const __bf16* As = x6_lds + buf * BUF;
-    const __bf16* Bs = x6_lds + buf * BUF + OPER;
-    bf8 bv[PK_S][NB];
+    const __bf16* Bs = x6_lds + buf * BUF + OPERA;
+    bf8 bv[PK_S][NBN];
 #pragma unroll
     for (int s = 0; s < PK_S; ++s)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) bv[s][j] = *reinterpret_cast<const bf8*>(Bs + frag(wcol, s, j));
+      for (int j = 0; j < NBN; ++j) bv[s][j] = *reinterpret_cast<const bf8*>(Bs + frag(wcol, s, j));
     // A slice sa meets the B slices sb <= 2 - sa; lowest-order products first
 #pragma unroll
     for (int sa = PK_S - 1; sa >= 0; --sa) {
-      bf8 av[NB];
+      bf8 av[NBM];
 #pragma unroll
-      for (int i = 0; i < NB; ++i) av[i] = *reinterpret_cast<const bf8*>(As + frag(wrow, sa, i));
+      for (int i = 0; i < NBM; ++i) av[i] = *reinterpret_cast<const bf8*>(As + frag(wrow, sa, i));
 #pragma unroll
       for (int sb = PK_S - 1 - sa; sb >= 0; --sb)
 #pragma unroll
-        for (int i = 0; i < NB; ++i)
+        for (int i = 0; i < NBM; ++i)
 #pragma unroll
-          for (int j = 0; j < NB; ++j)
+          for (int j = 0; j < NBN; ++j)
             c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[sb][j], c[i][j], 0, 0, 0);
     }
     if (kt + 1 < p.ktiles) commit(buf ^ 1);
     if ((kt + 1) % X_FLUSH == 0 || kt + 1 == p.ktiles) {
 #pragma unroll
-      for (int i = 0; i < NB; ++i)
+      for (int i = 0; i < NBM; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
+        for (int j = 0; j < NBN; ++j) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)c[i][j][r];
           c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
@@ -227,11 +234,11 @@ __global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restric
   }
 
   // epilogue: element r of lane l of block (i, j) is row 4 (l / 16) + r, column l % 16
-  const int row0 = tm * 64 * TP + wrow, col0 = tn * 64 * TP + wcol;
+  const int row0 = tm * 64 * TPM + wrow, col0 = tn * 64 * TPN + wcol;
 #pragma unroll
-  for (int i = 0; i < NB; ++i)
+  for (int i = 0; i < NBM; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
+    for (int j = 0; j < NBN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + i * 16 + 4 * lo + r, col = col0 + j * 16 + lr;
@@ -271,10 +278,10 @@ __global__ __launch_bounds__(256) void copy_pack64(const PackJob* __restrict__ j
   for (int e = threadIdx.x; e < PK_R * PK_K; e += 256) base[e] = t[e % PK_R][e / PK_R];
 }
 
-template <int TP>
+template <int TPM, int TPN>
 __global__ __launch_bounds__(XNT) void gemm_f64_packed(const SplitProb* __restrict__ probs,
                                                        const int* __restrict__ tile_prob, int total) {
-  constexpr int NB = 2 * TP;
+  constexpr int NBM = 2 * TPM, NBN = 2 * TPN;
   extern __shared__ __attribute__((aligned(16))) double f64_lds[];
   const int tile = xcd_tile(blockIdx.x, total);
   const SplitProb& p = probs[tile_prob[tile]];
@@ -282,35 +289,40 @@ __global__ __launch_bounds__(XNT) void gemm_f64_packed(const SplitProb* __restri
   x6_tile(p, tile - p.begin, tm, tn);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wrow = (wave >> 1) * 32 * TP, wcol = (wave & 1) * 32 * TP;
+  const int wrow = (wave >> 1) * 32 * TPM, wcol = (wave & 1) * 32 * TPN;
   const int lr = lane & 15, lk = lane >> 4;
 
-  // LDS: [buffer][operand][panel][k][row]
-  constexpr int OPER = TP * PK_CHUNK_64;
-  constexpr int BUF = 2 * OPER;
+  // LDS: [buffer][A panels | B panels][k][row]
+  constexpr int OPERA = TPM * PK_CHUNK_64, OPERB = TPN * PK_CHUNK_64;
+  constexpr int BUF = OPERA + OPERB;
   const int64_t pstride = (int64_t)p.ktiles * PK_CHUNK_64;
-  const double* Ag = static_cast<const double*>(p.A) + (int64_t)(TP * tm) * pstride;
-  const double* Bg = static_cast<const double*>(p.B) + (int64_t)(TP * tn) * pstride;
+  const double* Ag = static_cast<const double*>(p.A) + (int64_t)(TPM * tm) * pstride;
+  const double* Bg = static_cast<const double*>(p.B) + (int64_t)(TPN * tn) * pstride;
 
-  // staging: per operand TP panels x 1024 pieces of 16 bytes; thread t takes
-  // pieces t + 256 u (u < 4 TP)
-  i4 ra[4 * TP], rb[4 * TP];
+  // staging: TPM (TPN) panels x 1024 pieces of 16 bytes of A (B); thread t takes
+  // pieces t + 256 u
+  i4 ra[4 * TPM], rb[4 * TPN];
   auto fetch = [&](int kt) {
 #pragma unroll
-    for (int u = 0; u < 4 * TP; ++u) {
+    for (int u = 0; u < 4 * TPM; ++u) {
       const int e = threadIdx.x + u * XNT;
       const int pan = e >> 10, w = e & 1023;
       ra[u] = *reinterpret_cast<const i4*>(Ag + pan * pstride + (int64_t)kt * PK_CHUNK_64 + w * 2);
+    }
+#pragma unroll
+    for (int u = 0; u < 4 * TPN; ++u) {
+      const int e = threadIdx.x + u * XNT;
+      const int pan = e >> 10, w = e & 1023;
       rb[u] = *reinterpret_cast<const i4*>(Bg + pan * pstride + (int64_t)kt * PK_CHUNK_64 + w * 2);
     }
   };
   auto commit = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 4 * TP; ++u) {
-      const int e = threadIdx.x + u * XNT;
-      *reinterpret_cast<i4*>(f64_lds + buf * BUF + e * 2) = ra[u];
-      *reinterpret_cast<i4*>(f64_lds + buf * BUF + OPER + e * 2) = rb[u];
-    }
+    for (int u = 0; u < 4 * TPM; ++u)
+      *reinterpret_cast<i4*>(f64_lds + buf * BUF + (threadIdx.x + u * XNT) * 2) = ra[u];
+#pragma unroll
+    for (int u = 0; u < 4 * TPN; ++u)
+      *reinterpret_cast<i4*>(f64_lds + buf * BUF + OPERA + (threadIdx.x + u * XNT) * 2) = rb[u];
   };
   // element offset of (k, tile row off + 16 blk + lane row) inside an operand's panels
   auto at = [&](int k, int off, int blk) {
@@ -318,11 +330,11 @@ __global__ __launch_bounds__(XNT) void gemm_f64_packed(const SplitProb* __restri
     return (trow >> 6) * PK_CHUNK_64 + k * PK_R + (trow & 63) + lr;
   };
 
-  d4 c[NB][NB];
+  d4 c[NBM][NBN];
 #pragma unroll
-  for (int i = 0; i < NB; ++i)
+  for (int i = 0; i < NBM; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) c[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NBN; ++j) c[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   if (p.ktiles > 0) {
     fetch(0);
@@ -333,30 +345,29 @@ __global__ __launch_bounds__(XNT) void gemm_f64_packed(const SplitProb* __restri
     const int buf = kt & 1;
     if (kt + 1 < p.ktiles) fetch(kt + 1);
     const double* As = f64_lds + buf * BUF;
-    const double* Bs = f64_lds + buf * BUF + OPER;
+    const double* Bs = f64_lds + buf * BUF + OPERA;
 #pragma unroll
     for (int ks = 0; ks < PK_K; ks += 4) {
-      double av[NB], bv[NB];
+      double av[NBM], bv[NBN];
 #pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        av[i] = As[at(ks + lk, wrow, i)];
-        bv[i] = Bs[at(ks + lk, wcol, i)];
-      }
+      for (int i = 0; i < NBM; ++i) av[i] = As[at(ks + lk, wrow, i)];
 #pragma unroll
-      for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NBN; ++j) bv[j] = Bs[at(ks + lk, wcol, j)];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c[i][j], 0, 0, 0);
+      for (int i = 0; i < NBM; ++i)
+#pragma unroll
+        for (int j = 0; j < NBN; ++j) c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c[i][j], 0, 0, 0);
     }
     if (kt + 1 < p.ktiles) commit(buf ^ 1);
     __syncthreads();
   }
 
   // epilogue: element r of lane l of block (i, j) is row l / 16 + 4 r, column l % 16
-  const int row0 = tm * 64 * TP + wrow, col0 = tn * 64 * TP + wcol;
+  const int row0 = tm * 64 * TPM + wrow, col0 = tn * 64 * TPN + wcol;
 #pragma unroll
-  for (int i = 0; i < NB; ++i)
+  for (int i = 0; i < NBM; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
+    for (int j = 0; j < NBN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + i * 16 + lk + 4 * r, col = col0 + j * 16 + lr;
@@ -384,30 +395,44 @@ static void set_lds_limit(K kernel, size_t bytes) {
                             (int)bytes);
 }
 
-void launch_gemm_f64_packed(int tp, const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
-  if (tiles <= 0) return;
+// tile shapes (tpm, tpn) in {(1,1), (2,1), (1,2), (2,2)}
+template <int TPM, int TPN>
+static void f64_packed(const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
+  const size_t lds = (size_t)2 * (TPM + TPN) * PK_CHUNK_64 * sizeof(double);
   static bool attr = false;
-  const size_t lds = (size_t)2 * 2 * tp * PK_CHUNK_64 * sizeof(double);
   if (!attr) {
-    set_lds_limit(gemm_f64_packed<1>, (size_t)2 * 2 * 1 * PK_CHUNK_64 * sizeof(double));
-    set_lds_limit(gemm_f64_packed<2>, (size_t)2 * 2 * 2 * PK_CHUNK_64 * sizeof(double));
+    set_lds_limit(gemm_f64_packed<TPM, TPN>, lds);
     attr = true;
   }
-  if (tp == 2) gemm_f64_packed<2><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
-  else gemm_f64_packed<1><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
+  gemm_f64_packed<TPM, TPN><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
+}
+template <int TPM, int TPN>
+static void x6_packed(const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
+  const size_t lds = (size_t)2 * (TPM + TPN) * PK_CHUNK * sizeof(__bf16);
+  static bool attr = false;
+  if (!attr) {
+    set_lds_limit(gemm_x6_packed<TPM, TPN>, lds);
+    attr = true;
+  }
+  gemm_x6_packed<TPM, TPN><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
 }
 
-void launch_gemm_x6_packed(int tp, const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
+void launch_gemm_f64_packed(int tpm, int tpn, const SplitProb* d_probs, const int* d_tile_prob, int tiles,
+                            hipStream_t s) {
   if (tiles <= 0) return;
-  static bool attr = false;
-  const size_t lds = (size_t)2 * 2 * tp * PK_CHUNK * sizeof(__bf16);
-  if (!attr) {
-    set_lds_limit(gemm_x6_packed<1>, (size_t)2 * 2 * 1 * PK_CHUNK * sizeof(__bf16));
-    set_lds_limit(gemm_x6_packed<2>, (size_t)2 * 2 * 2 * PK_CHUNK * sizeof(__bf16));
-    attr = true;
-  }
-  if (tp == 2) gemm_x6_packed<2><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
-  else gemm_x6_packed<1><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
+  if (tpm == 2 && tpn == 2) f64_packed<2, 2>(d_probs, d_tile_prob, tiles, s);
+  else if (tpm == 2) f64_packed<2, 1>(d_probs, d_tile_prob, tiles, s);
+  else if (tpn == 2) f64_packed<1, 2>(d_probs, d_tile_prob, tiles, s);
+  else f64_packed<1, 1>(d_probs, d_tile_prob, tiles, s);
+}
+
+void launch_gemm_x6_packed(int tpm, int tpn, const SplitProb* d_probs, const int* d_tile_prob, int tiles,
+                           hipStream_t s) {
+  if (tiles <= 0) return;
+  if (tpm == 2 && tpn == 2) x6_packed<2, 2>(d_probs, d_tile_prob, tiles, s);
+  else if (tpm == 2) x6_packed<2, 1>(d_probs, d_tile_prob, tiles, s);
+  else if (tpn == 2) x6_packed<1, 2>(d_probs, d_tile_prob, tiles, s);
+  else x6_packed<1, 1>(d_probs, d_tile_prob, tiles, s);
 }
 
 }  // namespace etdm

@@ -26,6 +26,10 @@ STATUS = {
 }
 
 
+# the GEMM kernels of a real FP64 / BF16x6 stage, in the order of etdm_stage_kernel's times
+GEMM_VARIANTS = ("tile64", "packed64", "packed128x64", "packed64x128", "packed128")
+
+
 class EtdmError(RuntimeError):
     def __init__(self, code: int, detail: str = ""):
         self.code = code
@@ -122,8 +126,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.etdm_stage_info.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(i64),
                                   ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     L.etdm_stage_info.restype = i32
-    L.etdm_stage_kernel.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(dbl),
-                                    ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    L.etdm_stage_kernel.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(dbl)]
     L.etdm_stage_kernel.restype = i32
     _lib = L
     return L
@@ -162,9 +165,10 @@ class Handle:
          packed BSR blocks when ``bsr`` = (block, row_ptr, col_idx) is given
     C0 : device tensor, packed M x M reference orbitals
     f : host array of occupations, packed [sum M]
-    gemm_tuning : kernel choice of the FP64 / BF16x6 GEMM stages: 0 = time the three
+    gemm_tuning : kernel choice of the FP64 / BF16x6 GEMM stages: 0 = time the five
                   kernels at creation and keep the fastest, 1 = fixed size rule,
-                  2 = packed 128 x 128, 3 = grouped 64 x 64, 4 = packed 64 x 64
+                  2 = packed 128 x 128, 3 = grouped 64 x 64, 4 = packed 64 x 64,
+                  5 = packed 128 x 64, 6 = packed 64 x 128
     """
 
     def __init__(self, M: Sequence[int], N: Optional[Sequence[int]], kind: str, precision: str,
@@ -272,16 +276,15 @@ class Handle:
         return out
 
     def stage_kernels(self) -> list:
-        """Per stage: its GEMM kernel ("" if not a GEMM) and the launch times of the three
-        real FP64 / BF16x6 kernels measured by the tuning at creation (0 if not timed)."""
+        """Per stage: its GEMM kernel ("" if not a GEMM) and the launch times of the real
+        FP64 / BF16x6 kernels measured by the tuning at creation (0 if not timed)."""
         out = []
         for i in range(int(self._L.etdm_stage_count(self._h))):
             v = ctypes.c_char_p()
-            t = [ctypes.c_double() for _ in range(3)]
-            self._check(self._L.etdm_stage_kernel(self._h, i, ctypes.byref(v), ctypes.byref(t[0]),
-                                                  ctypes.byref(t[1]), ctypes.byref(t[2])), "etdm_stage_kernel")
+            t = (ctypes.c_double * len(GEMM_VARIANTS))()
+            self._check(self._L.etdm_stage_kernel(self._h, i, ctypes.byref(v), t), "etdm_stage_kernel")
             out.append(dict(index=i, kernel=v.value.decode(),
-                            tuned_ms={"tile64": t[0].value, "packed64": t[1].value, "packed128": t[2].value}))
+                            tuned_ms={name: t[k] for k, name in enumerate(GEMM_VARIANTS)}))
         return out
 
     def sync_status(self, stream=None):

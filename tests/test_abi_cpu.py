@@ -49,7 +49,7 @@ def test_host_only_calls(repo_root):
 
 
 def test_create_rejects_bad_gemm_tuning(repo_root):
-    """gemm_tuning outside 0..4 is an argument error, found before any device call."""
+    """gemm_tuning outside 0..6 is an argument error, found before any device call."""
     from paper_2101_12597_amd import LIB_PATH, load_library
     from paper_2101_12597_amd.etdm import _Desc
     if not os.path.exists(LIB_PATH):
@@ -58,7 +58,7 @@ def test_create_rejects_bad_gemm_tuning(repo_root):
     M = (ctypes.c_int32 * 1)(64)
     N = (ctypes.c_int32 * 1)(16)
     f = (ctypes.c_double * 64)(*([2.0] * 16 + [0.0] * 48))
-    for bad in (-1, 5):
+    for bad in (-1, 7):
         d = _Desc()
         d.n_inst = 1
         d.M = M

@@ -75,11 +75,12 @@ def test_real_ov_fp64_matches_oracle(which):
     h.close()
 
 
-# The three kernels of the FP64 and BF16x6 GEMM stages, forced (2 = packed
-# 128 x 128, 3 = grouped 64 x 64, 4 = packed 64 x 64), so each is checked whichever
-# one the tuning picks: ragged shapes (K = 0, one-row and partial tiles, two K
-# segments) and the 148 molecules of config 2.
-@pytest.mark.parametrize("tuning", [2, 3, 4])
+# The five kernels of the FP64 and BF16x6 GEMM stages, forced (2 = packed
+# 128 x 128, 3 = grouped 64 x 64, 4 = packed 64 x 64, 5 = packed 128 x 64,
+# 6 = packed 64 x 128), so each is checked whichever one the tuning picks: ragged
+# shapes (K = 0, one-row and partial tiles, two K segments) and the 148 molecules
+# of config 2.
+@pytest.mark.parametrize("tuning", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("which,precision", [("ragged", "fp64"), ("ragged", "mixed"), ("config2", "mixed"),
                                              ("config2", "bf16x6")])
 def test_forced_gemm_kernels(which, precision, tuning):
@@ -87,7 +88,7 @@ def test_forced_gemm_kernels(which, precision, tuning):
     params = O.parity_params(wl)
     print(f"[case] forced GEMM kernels {which} {precision} tuning={tuning}", flush=True)
     h, _ = make_handle(wl, precision, gemm_tuning=tuning)
-    want = {2: "packed128", 3: "tile64", 4: "packed64"}[tuning]
+    want = {2: "packed128", 3: "tile64", 4: "packed64", 5: "packed128x64", 6: "packed64x128"}[tuning]
     kernels = [k["kernel"] for k in h.stage_kernels() if k["kernel"]]
     assert kernels and all(k.endswith(want) for k in kernels), kernels
     E, g = energy_grad(h, wl, params)
