@@ -29,7 +29,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ETDM energy+gradient evals/sec, MFMA TFLOP/s vs peak, at stated |dE|"
 PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
-ENERGY_CHAIN = ("gemm_P_Q1", "gemm_Cocc", "gemm_H0C")
+# GEMM stages that run in FP64 also in the mixed mode
+FP64_STAGES = ("gemm_P", "gemm_Q1", "gemm_Cocc", "gemm_H0C", "gemm_funcs_mu", "gemm_Gam1", "gemm_Gam",
+               "gemm_Y1", "gemm_Y2")
 HBM_PEAK_GBS = 8000.0
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x6": "bf16", "mixed": "f64+bf16x6"}
 WORKLOADS = {
@@ -245,7 +247,7 @@ def main():
         gemm_prec = "fp64" if dom["name"] in ("gemm_funcs_mu", "gemm_Gam1", "gemm_Gam", "gemm_Y1",
                                               "gemm_Y2") else prec
         if gemm_prec == "mixed":
-            gemm_prec = "fp64" if dom["name"] in ENERGY_CHAIN else "bf16x6"
+            gemm_prec = "fp64" if dom["name"] in FP64_STAGES else "bf16x6"
         peak = PEAKS_TFLOPS[gemm_prec]
         achieved = dom["flops"] / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}

@@ -443,7 +443,7 @@ __global__ __launch_bounds__(TL_NT) void eigh_tridiag_lds(const EighProb* __rest
   // 3. eigenvectors of T (column j of Z in R1, by thread j), with Rayleigh-quotient
   //    corrections of the eigenvalue from each twisted factorization; a correction
   //    that leaves the bracket is not taken
-  if (tid < n) vlam[tid] = tl_vector(vd, ve, ve2, ib0[tid], ib1[tid], vlo[tid], vhi[tid], tn, pivmin, R1, n, tid, n);
+  if (tid < n) vlam[tid] = tl_vector<0>(vd, ve, ve2, ib0[tid], ib1[tid], vlo[tid], vhi[tid], tn, pivmin, R1, n, tid, n);
   __syncthreads();
 
   // 4. X = Q Z = (Q^T)^T Z
@@ -788,7 +788,7 @@ __global__ __launch_bounds__(TL_NT) void eigh_herm_tridiag(const EighProb* __res
   double res = 0.0;
   for (int j = tid; j < n; j += TL_NT) {
     const int b0 = ib0[j], b1 = ib1[j];
-    const double lam = tl_vector(vd, ve, ve2, b0, b1, vlo[j], vhi[j], tn, pivmin, Z, n, j, n);
+    const double lam = tl_vector<0>(vd, ve, ve2, b0, b1, vlo[j], vhi[j], tn, pivmin, Z, n, j, n);
     pr.w[j] = lam;
     for (int i = b0; i < b1; ++i) {
       double t = (vd[i] - lam) * Z[(size_t)i * n + j];

@@ -57,11 +57,13 @@ constexpr int TB_KC = 256;   // K chunk of Y_b^T X (split K, so that the product
 size_t eigh_large_workspace(int n, size_t* npad_out);
 // Point the members of e at the workspace ws (n set; grid from the CU count).
 void eigh_large_layout(EighLarge& e, double* ws, EighLargeState* st, int cu_count);
-// Tridiagonal path, part 1: reduction (cooperative), eigenpairs of T (Zw, w) and
-// their residual check.  Part 2 (orthogonality check, one Newton-Schulz step into
-// X, compact-WY back-transform of X) is launched by the caller with grouped GEMMs;
-// launch_tb_wy_t forms the T factors from the Gram matrices in Gw.
-void launch_tb_solve(const EighLarge& e, int* status, hipStream_t s);
+// Tridiagonal path, part 1: the reduction (cooperative: every workgroup must be
+// resident, so nothing else should be queued beside it), then the eigenpairs of T
+// (Zw, w) and their residual check.  Part 2 (orthogonality check, one Newton-Schulz
+// step into X, compact-WY back-transform of X) is launched by the caller with
+// grouped GEMMs; launch_tb_wy_t forms the T factors from the Gram matrices in Gw.
+void launch_tb_reduce(const EighLarge& e, hipStream_t s);
+void launch_tb_eigenpairs(const EighLarge& e, hipStream_t s);
 void launch_tb_wy_t(const EighLarge& e, hipStream_t s);
 // After G = Z^T Z has been formed in Aw: *ok = 0 unless max|G - I| <= 1e-6; Aw <- (3 I - G) / 2.
 void launch_tb_orth_check(const EighLarge& e, hipStream_t s);

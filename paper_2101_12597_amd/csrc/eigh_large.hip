@@ -976,7 +976,7 @@ __global__ __launch_bounds__(TV_NT) void tb_vectors(EighLarge e) {
   double res = 0.0;
   if (j < n) {
     const int b0 = e.bb[2 * j], b1 = e.bb[2 * j + 1];
-    const double lam = tl_vector(d, ee, e2, b0, b1, e.blo[j], e.bhi[j], tn, pivmin, e.Zw, n, j, n);
+    const double lam = tl_vector<8>(d, ee, e2, b0, b1, e.blo[j], e.bhi[j], tn, pivmin, e.Zw, n, j, n);
     e.w[j] = lam;
     for (int i = b0; i < b1; ++i) {
       double t = (d[i] - lam) * e.Zw[(size_t)i * n + j];
@@ -1088,7 +1088,7 @@ void launch_tb_final_check(const EighLarge& e, hipStream_t s) {
   tb_verdict<<<1, 64, 0, s>>>(e, 1);
 }
 
-void launch_tb_solve(const EighLarge& e, int* status, hipStream_t s) {
+void launch_tb_reduce(const EighLarge& e, hipStream_t s) {
   const int n = e.n;
   const size_t red_lds = sizeof(double) * 4 * (size_t)n;
   // more than half of a CU's LDS, so that no two workgroups share a CU
@@ -1119,6 +1119,11 @@ void launch_tb_solve(const EighLarge& e, int* status, hipStream_t s) {
     tb_reduce_reg<<<e.grid, TR_NT, lds, s>>>(e);
   else
     tb_reduce<<<e.grid, TB_NT, lds, s>>>(e);
+}
+
+void launch_tb_eigenpairs(const EighLarge& e, hipStream_t s) {
+  const int n = e.n;
+  const size_t eig_lds = sizeof(double) * 3 * (size_t)n;
   tb_bisect<<<(n + TE_CH - 1) / TE_CH, TE_NT, eig_lds, s>>>(e);
   tb_vectors<<<(n + TV_NT - 1) / TV_NT, TV_NT, eig_lds, s>>>(e);
 }
@@ -1145,6 +1150,12 @@ void launch_eigh_large(const EighLarge& e, int max_sweeps, int* status, hipStrea
   const int tasks = half * half + (e.npad / SUB) * half;
   bjl_prepare<<<PREP_BLOCKS, U_NT, 0, s>>>(e, e.partial);
   bjl_start<<<1, 64, 0, s>>>(e, e.partial);
+  if (check_host) {  // accepted tridiagonal result (or a zero matrix): no sweep at all
+    int done = 0;
+    if (hipMemcpyAsync(&done, &e.st->done, sizeof(int), hipMemcpyDeviceToHost, s) == hipSuccess &&
+        hipStreamSynchronize(s) == hipSuccess && done)
+      max_sweeps = 0;
+  }
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     for (int r = 0; r < e.nb - 1; ++r) {
       bjl_inner<<<half, L_NT, inner_lds, s>>>(e, r);

@@ -276,11 +276,12 @@ struct StageTimer {
 
 // stage indices of the two paths
 enum OvStage { O_PQ, O_EIGL, O_EIGG, O_SPEC, O_F3MU, O_C, O_Z, O_T, O_V, O_ROWS, O_ENERGY, O_LOV, O_R, O_GAM1,
-               O_GAM, O_PAIR, O_Y1, O_Y2, O_G, O_SCAN, O_COUNT };
-const char* kOvNames[O_COUNT] = {"gemm_P_Q1",  "eigh_lds",  "eigh_global", "spectral_tables", "gemm_funcs_mu",
+               O_GAM, O_PAIR, O_Y1, O_Y2, O_G, O_SCAN, O_Q1, O_COUNT };
+const char* kOvNames[O_COUNT] = {"gemm_P",  "eigh_lds",  "eigh_global", "spectral_tables", "gemm_funcs_mu",
                                  "gemm_Cocc",  "gemm_Z1",   "gemm_H0C",    "gemm_Cvirt",      "rows_density_hubbard",
                                  "energy_reduce", "gemm_Lov", "gemm_R",    "gemm_Gam1",       "gemm_Gam",
-                                 "pair_hadamard", "gemm_Y1", "gemm_Y2",    "gemm_grad",       "nonfinite_scan"};
+                                 "pair_hadamard", "gemm_Y1", "gemm_Y2",    "gemm_grad",       "nonfinite_scan",
+                                 "gemm_Q1"};
 enum ZStage { Z_IA, Z_EIG, Z_PHASE, Z_UE, Z_C, Z_T, Z_ROWS, Z_HUBN, Z_APPLY, Z_ENERGY, Z_HMO, Z_COMM, Z_LV, Z_LT,
               Z_DD, Z_W1, Z_Y, Z_GRAD, Z_COUNT };
 const char* kZNames[Z_COUNT] = {"z_build_iA", "z_eigh",   "z_phase",  "zgemm_expA", "zgemm_C",   "zgemm_H0C",
@@ -332,7 +333,11 @@ struct etdm_handle {
   const double** d_n0ptr = nullptr;
   double* d_wts = nullptr;
   // grouped GEMM launches
-  Stage s_PQ, s_F3mu, s_C, s_Z, s_T, s_V, s_Lov, s_R, s_Gam1, s_Gam, s_Y1, s_Y2, s_G;  // real: energy+gradient
+  Stage s_PQ, s_Q1, s_F3mu, s_C, s_Z, s_T, s_V, s_Lov, s_R, s_Gam1, s_Gam, s_Y1, s_Y2, s_G;  // real: energy+gradient
+  // Q1 = C0_v B^T does not depend on the eigendecomposition: it runs on a side
+  // stream beside the eigensolver (forked and joined by events)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   Stage s_Uov, s_Uvv, s_HC0;                                                   // real: expm, preconditioner
   Stage z_Ue, z_C, z_T, z_HMO, z_LV, z_Lt, z_W1, z_Y, z_HC0;                   // complex
   // L-BFGS state
@@ -346,6 +351,9 @@ struct etdm_handle {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph2 = nullptr;          // second part when the large solver splits the sequence
+  hipGraphExec_t graph2_exec = nullptr;
+  int* ok_host = nullptr;               // pinned: acceptance flags of the large instances
   // packed operands of the FP64 / BF16x6 stages (shared: stages run in order)
   char* pack_arena = nullptr;
   int gemm_tuning = 0;
@@ -650,6 +658,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
   const int ep = h->prec == ETDM_MIXED ? GP_FP64 : h->prec;
   const int gp = h->prec == ETDM_MIXED ? GP_BF16X6 : h->prec;
   h->s_PQ.init(OP_N, OP_T, ep);
+  h->s_Q1.init(OP_N, OP_T, ep);
   h->s_F3mu.init(OP_N, OP_T, GP_FP64);
   h->s_C.init(OP_N, OP_N, ep);
   h->s_Z.init(OP_N, OP_N, gp);
@@ -680,7 +689,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
     const double* Wm = b.F3 + 2 * (size_t)N * N;
     // P = B B^T, Q1 = C0_v B^T
     h->s_PQ.add(prob(N, N, Nv, b.B, Nv, b.B, Nv, b.P, N));
-    h->s_PQ.add(prob(M, N, Nv, b.C0 + N, M, b.B, Nv, b.Q1, N));
+    h->s_Q1.add(prob(M, N, Nv, b.C0 + N, M, b.B, Nv, b.Q1, N));
     // P = X diag(s) X^T
     if (N <= EIGH_LDS_MAX) {
       el.push_back(EighProb{b.P, b.X, b.s, N, 1});
@@ -772,6 +781,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
     for (int i = 0; i < O_COUNT; ++i) h->timers[i].name = kOvNames[i];
     Stage* gs[O_COUNT] = {};
     gs[O_PQ] = &h->s_PQ;
+    gs[O_Q1] = &h->s_Q1;
     gs[O_F3MU] = &h->s_F3mu;
     gs[O_C] = &h->s_C;
     gs[O_Z] = &h->s_Z;
@@ -813,7 +823,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
     }
     h->timers[O_SCAN].bytes = 8.0 * h->n_param;
   }
-  Stage* stages[] = {&h->s_PQ,  &h->s_F3mu, &h->s_C,  &h->s_Z,   &h->s_T,   &h->s_V,   &h->s_Lov,
+  Stage* stages[] = {&h->s_PQ,  &h->s_Q1,   &h->s_F3mu, &h->s_C,  &h->s_Z,   &h->s_T,   &h->s_V,   &h->s_Lov,
                      &h->s_R,   &h->s_Gam1, &h->s_Gam, &h->s_Y1, &h->s_Y2, &h->s_G,  &h->s_Uov,
                      &h->s_Uvv, &h->s_HC0};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
@@ -1019,14 +1029,20 @@ void free_timers(etdm_handle* h) {
 void free_graph(etdm_handle* h) {
   if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
   if (h->graph) hipGraphDestroy(h->graph);
-  h->graph_exec = nullptr;
-  h->graph = nullptr;
+  if (h->graph2_exec) hipGraphExecDestroy(h->graph2_exec);
+  if (h->graph2) hipGraphDestroy(h->graph2);
+  h->graph_exec = h->graph2_exec = nullptr;
+  h->graph = h->graph2 = nullptr;
 }
 
 void free_handle(etdm_handle* h) {
   if (!h) return;
   free_graph(h);
   if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+  if (h->ok_host) hipHostFree(h->ok_host);
+  if (h->side) hipStreamDestroy(h->side);
+  if (h->ev_fork) hipEventDestroy(h->ev_fork);
+  if (h->ev_join) hipEventDestroy(h->ev_join);
   free_timers(h);
   if (h->base) hipFree(h->base);
   for (void* p : h->dev_allocs) hipFree(p);
@@ -1037,18 +1053,37 @@ void free_handle(etdm_handle* h) {
 
 #define TIMED(id) Timed timed_scope_(h, id, s)
 
-void ov_exponential_part(etdm_handle* h, hipStream_t s) {
+// Exponential part, front: P, Q1, the small eigensolver and the tridiagonal path
+// of the large instances up to their acceptance checks.  fallback selects what
+// follows for the large instances: 0 nothing (the caller decides), 1 the Jacobi
+// sweeps launched until the host sees them converge, 2 all sweeps launched (each
+// returns at once when the tridiagonal result was accepted; for graph capture).
+void ov_front(etdm_handle* h, hipStream_t s, int fallback) {
   { TIMED(O_PQ); h->s_PQ.launch(s); }
+  // Q1 on the side stream, beside the eigensolver (in order while stages are timed).
+  // With large instances it starts after the cooperative reductions, whose
+  // workgroups must all be resident at once.
+  const bool fork = h->side && h->tmask == 0 && !h->s_Q1.probs.empty();
+  if (!fork) {
+    TIMED(O_Q1);
+    h->s_Q1.launch(s);
+  }
+  auto launch_q1 = [&]() {
+    if (!fork) return;
+    hipEventRecord(h->ev_fork, s);
+    hipStreamWaitEvent(h->side, h->ev_fork, 0);
+    h->s_Q1.launch(h->side);
+    hipEventRecord(h->ev_join, h->side);
+  };
+  if (h->eig_large.empty()) launch_q1();
   { TIMED(O_EIGL); launch_eigh_real_lds(h->d_eig_lds, h->n_eig_lds, h->status, s); }
   if (!h->eig_large.empty()) {
     TIMED(O_EIGG);
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    hipStreamIsCapturing(s, &cs);
     // reduction to tridiagonal form and its eigenpairs, the orthogonality check and
-    // one Newton-Schulz step, the compact-WY back-transform, the residual against P;
-    // then the Jacobi sweeps,
-    // which return at once when the tridiagonal result was accepted
-    for (const EighLarge& e : h->eig_large) launch_tb_solve(e, h->status, s);
+    // one Newton-Schulz step, the compact-WY back-transform, the residual against P
+    for (const EighLarge& e : h->eig_large) launch_tb_reduce(e, s);
+    launch_q1();
+    for (const EighLarge& e : h->eig_large) launch_tb_eigenpairs(e, s);
     h->s_LG.launch(s);
     for (const EighLarge& e : h->eig_large) launch_tb_orth_check(e, s);
     h->s_LNS.launch(s);
@@ -1061,15 +1096,35 @@ void ov_exponential_part(etdm_handle* h, hipStream_t s) {
     }
     h->s_LR.launch(s);
     for (const EighLarge& e : h->eig_large) launch_tb_final_check(e, s);
-    for (const EighLarge& e : h->eig_large)
-      launch_eigh_large(e, LARGE_EIGH_MAX_SWEEPS, h->status, s, cs == hipStreamCaptureStatusNone);
+    // the block Jacobi fallback, which returns at once when the tridiagonal result
+    // was accepted
+    if (fallback)
+      for (const EighLarge& e : h->eig_large) launch_eigh_large(e, LARGE_EIGH_MAX_SWEEPS, h->status, s, fallback == 1);
   }
+  if (fork) hipStreamWaitEvent(s, h->ev_join, 0);
+}
+
+void ov_back_exp(etdm_handle* h, hipStream_t s) {
   { TIMED(O_SPEC); launch_ov_spectral(h->d_spec, h->b_spec, h->n_inst, h->tot_spec, h->gl_t, h->gl_w, s); }
   { TIMED(O_F3MU); h->s_F3mu.launch(s); }
 }
 
+void ov_exponential_part(etdm_handle* h, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipStreamIsCapturing(s, &cs);
+  ov_front(h, s, cs == hipStreamCaptureStatusNone ? 1 : 2);
+  ov_back_exp(h, s);
+}
+
+void ov_energy_grad_rest(etdm_handle* h, hipStream_t s);
+
 void ov_energy_grad(etdm_handle* h, hipStream_t s) {
   ov_exponential_part(h, s);
+  ov_energy_grad_rest(h, s);
+}
+
+// After the exponential part: C, H0 C_occ, the energy, L and the gradient.
+void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
   { TIMED(O_C); h->s_C.launch(s); }
   { TIMED(O_Z); h->s_Z.launch(s); }
   {
@@ -1182,21 +1237,46 @@ void run_energy_grad_eager(etdm_handle* h, hipStream_t s) {
   else z_energy_grad(h, s);
 }
 
-// Energy+gradient launch sequence, from the captured graph when enabled.
+// Energy+gradient launch sequence, from the captured graphs when enabled.  With
+// large real instances the sequence is captured in two graphs around the block
+// Jacobi fallback: after the first, the host reads the acceptance flags of the
+// tridiagonal path (one stream synchronization) and launches the fallback only
+// for an instance that failed; a graph would replay all its sweeps.
+etdm_status capture(etdm_handle* h, hipGraph_t* g, hipGraphExec_t* x, void (*seq)(etdm_handle*, hipStream_t)) {
+  HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  seq(h, h->cap_stream);
+  HIPCHK(h, hipStreamEndCapture(h->cap_stream, g));
+  HIPCHK(h, hipGraphInstantiate(x, *g, nullptr, nullptr, 0));
+  return ETDM_OK;
+}
+
 etdm_status run_energy_grad(etdm_handle* h, hipStream_t s) {
   if (!h->use_graph || h->tmask != 0) {
     run_energy_grad_eager(h, s);
     return ETDM_OK;
   }
+  const bool split = h->kind == ETDM_REAL_OV && !h->eig_large.empty();
   if (!h->graph_exec) {
-    HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    run_energy_grad_eager(h, h->cap_stream);
-    hipGraph_t g = nullptr;
-    HIPCHK(h, hipStreamEndCapture(h->cap_stream, &g));
-    h->graph = g;
-    HIPCHK(h, hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+    if (split) {
+      CHECK(capture(h, &h->graph, &h->graph_exec, [](etdm_handle* hh, hipStream_t ss) { ov_front(hh, ss, 0); }));
+      CHECK(capture(h, &h->graph2, &h->graph2_exec, [](etdm_handle* hh, hipStream_t ss) {
+        ov_back_exp(hh, ss);
+        ov_energy_grad_rest(hh, ss);
+      }));
+      if (!h->ok_host) HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&h->ok_host), h->eig_large.size() * sizeof(int)));
+    } else {
+      CHECK(capture(h, &h->graph, &h->graph_exec, run_energy_grad_eager));
+    }
   }
   HIPCHK(h, hipGraphLaunch(h->graph_exec, s));
+  if (split) {
+    for (size_t i = 0; i < h->eig_large.size(); ++i)
+      HIPCHK(h, hipMemcpyAsync(&h->ok_host[i], h->eig_large[i].ok, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    for (size_t i = 0; i < h->eig_large.size(); ++i)
+      if (!h->ok_host[i]) launch_eigh_large(h->eig_large[i], LARGE_EIGH_MAX_SWEEPS, h->status, s, true);
+    HIPCHK(h, hipGraphLaunch(h->graph2_exec, s));
+  }
   return ETDM_OK;
 }
 
@@ -1616,6 +1696,11 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   }
   etdm_status st = real ? build_ov_plan(h) : build_z_plan(h);
   if (st == ETDM_OK) st = tune_stages(h, s);
+  if (st == ETDM_OK && real && !h->s_Q1.probs.empty() &&
+      (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess))
+    st = ETDM_E_HIP;
   if (st != ETDM_OK) return bail(st);
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) return bail(ETDM_E_HIP);
   *out = h;

@@ -132,6 +132,9 @@ constexpr int TL_RQI_MAX = 4;                 // Rayleigh-quotient corrections p
 // z_i = -(e_i / D+_i) z_{i+1} (i < r), z_i = -(e_{i-1} / D-_i) z_{i-1} (i > r).
 // Writes z / ||z|| into column j of Z (ld n; D+ and D- are kept there meanwhile)
 // and returns the Rayleigh-quotient correction gamma_r / ||z||^2.
+// Twisted factorization at lam (pivots in Z), the twist index r minimising
+// |gamma_r|, the vector z (z_r = 1) normalized into column j of Z; returns the
+// Rayleigh-quotient correction gamma_r / ||z||^2.  Plain loops, for Z in LDS.
 __device__ inline double tl_twisted(const double* d, const double* e, const double* e2, int b0, int b1, double lam,
                              double pivmin, double* Z, int ld, int j) {
   double D = tl_piv(d[b0] - lam, pivmin);
@@ -179,8 +182,155 @@ __device__ inline double tl_twisted(const double* d, const double* e, const doub
   return gr / nrm;
 }
 
+// The same with the loads issued TL_PF indices ahead (the next chunk while the
+// current one is used), for Z in global memory: their addresses do not depend on
+// the recurrences, but without this each step would wait for its own load, since
+// the compiler keeps the loads behind the stores to the same array.
+template <int TL_PF>
+__device__ inline double tl_twisted_pf(const double* d, const double* e, const double* e2, int b0, int b1, double lam,
+                             double pivmin, double* Z, int ld, int j) {
+  // forward pivots D+ (stored in Z)
+  double D = tl_piv(d[b0] - lam, pivmin);
+  Z[b0 * ld + j] = D;
+  for (int i = b0 + 1; i < b1; ++i) {
+    D = tl_piv((d[i] - lam) - e2[i - 1] * tl_rcp(D), pivmin);
+    Z[i * ld + j] = D;
+  }
+  // backward pivots D- and the twist index r minimising |gamma_r| = |D+_r + D-_r - (d_r - lam)|
+  D = tl_piv(d[b1 - 1] - lam, pivmin);
+  int r = b1 - 1;
+  double gr = Z[(b1 - 1) * ld + j] + D - (d[b1 - 1] - lam);
+  double best = fabs(gr);
+  {
+    double cur[TL_PF];
+#pragma unroll
+    for (int u = 0; u < TL_PF; ++u) {
+      const int i = b1 - 2 - u;
+      cur[u] = i >= b0 ? Z[i * ld + j] : 0.0;
+    }
+    for (int i0 = b1 - 2; i0 >= b0; i0 -= TL_PF) {
+      double nxt[TL_PF];
+#pragma unroll
+      for (int u = 0; u < TL_PF; ++u) {
+        const int i = i0 - TL_PF - u;
+        nxt[u] = i >= b0 ? Z[i * ld + j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < TL_PF; ++u) {
+        const int i = i0 - u;
+        if (i >= b0) {
+          D = tl_piv((d[i] - lam) - e2[i] * tl_rcp(D), pivmin);
+          const double g = cur[u] + D - (d[i] - lam);
+          if (fabs(g) < best) {
+            best = fabs(g);
+            gr = g;
+            r = i;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TL_PF; ++u) cur[u] = nxt[u];
+    }
+  }
+  if (r < b1 - 1) {  // backward pivots below the twist
+    D = tl_piv(d[b1 - 1] - lam, pivmin);
+    Z[(b1 - 1) * ld + j] = D;
+    for (int i = b1 - 2; i > r; --i) {
+      D = tl_piv((d[i] - lam) - e2[i] * tl_rcp(D), pivmin);
+      Z[i * ld + j] = D;
+    }
+  }
+  // z_r = 1 and the two one-sided recurrences: z_i = -(e_i / D+_i) z_{i+1} above the
+  // twist, z_i = -(e_{i-1} / D-_i) z_{i-1} below it
+  double nrm = 1.0, z = 1.0;
+  Z[r * ld + j] = 1.0;
+  {
+    double cur[TL_PF];
+#pragma unroll
+    for (int u = 0; u < TL_PF; ++u) {
+      const int i = r - 1 - u;
+      cur[u] = i >= b0 ? Z[i * ld + j] : 1.0;
+    }
+    for (int i0 = r - 1; i0 >= b0; i0 -= TL_PF) {
+      double nxt[TL_PF];
+#pragma unroll
+      for (int u = 0; u < TL_PF; ++u) {
+        const int i = i0 - TL_PF - u;
+        nxt[u] = i >= b0 ? Z[i * ld + j] : 1.0;
+      }
+#pragma unroll
+      for (int u = 0; u < TL_PF; ++u) {
+        const int i = i0 - u;
+        if (i >= b0) {
+          z = -(e[i] * tl_rcp(cur[u])) * z;
+          Z[i * ld + j] = z;
+          nrm += z * z;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TL_PF; ++u) cur[u] = nxt[u];
+    }
+  }
+  z = 1.0;
+  {
+    double cur[TL_PF];
+#pragma unroll
+    for (int u = 0; u < TL_PF; ++u) {
+      const int i = r + 1 + u;
+      cur[u] = i < b1 ? Z[i * ld + j] : 1.0;
+    }
+    for (int i0 = r + 1; i0 < b1; i0 += TL_PF) {
+      double nxt[TL_PF];
+#pragma unroll
+      for (int u = 0; u < TL_PF; ++u) {
+        const int i = i0 + TL_PF + u;
+        nxt[u] = i < b1 ? Z[i * ld + j] : 1.0;
+      }
+#pragma unroll
+      for (int u = 0; u < TL_PF; ++u) {
+        const int i = i0 + u;
+        if (i < b1) {
+          z = -(e[i - 1] * tl_rcp(cur[u])) * z;
+          Z[i * ld + j] = z;
+          nrm += z * z;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TL_PF; ++u) cur[u] = nxt[u];
+    }
+  }
+  // normalization
+  const double sc = 1.0 / sqrt(nrm);
+  {
+    double cur[TL_PF];
+#pragma unroll
+    for (int u = 0; u < TL_PF; ++u) {
+      const int i = b0 + u;
+      cur[u] = i < b1 ? Z[i * ld + j] : 0.0;
+    }
+    for (int i0 = b0; i0 < b1; i0 += TL_PF) {
+      double nxt[TL_PF];
+#pragma unroll
+      for (int u = 0; u < TL_PF; ++u) {
+        const int i = i0 + TL_PF + u;
+        nxt[u] = i < b1 ? Z[i * ld + j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < TL_PF; ++u) {
+        const int i = i0 + u;
+        if (i < b1) Z[i * ld + j] = cur[u] * sc;
+      }
+#pragma unroll
+      for (int u = 0; u < TL_PF; ++u) cur[u] = nxt[u];
+    }
+  }
+  return gr / nrm;
+}
+
 // Eigenvector of T (size n) for eigenvalue j (bracket lo..hi) into column j of Z
 // (leading dimension ld), with Rayleigh-quotient corrections; returns the eigenvalue.
+// PF = 0: plain loops (Z in LDS), else loads PF indices ahead (Z in global memory).
+template <int PF>
 __device__ inline double tl_vector(const double* vd, const double* ve, const double* ve2, int b0, int b1, double lo,
                             double hi, double tn, double pivmin, double* Z, int n, int j, int ld) {
   const double eps = DBL_EPSILON;
@@ -191,12 +341,16 @@ __device__ inline double tl_vector(const double* vd, const double* ve, const dou
     Z[b0 * ld + j] = 1.0;
     return vd[b0];
   }
-  double dl = tl_twisted(vd, ve, ve2, b0, b1, lam, pivmin, Z, ld, j);
+  auto twisted = [&](double at) {
+    if constexpr (PF > 0) return tl_twisted_pf<PF>(vd, ve, ve2, b0, b1, at, pivmin, Z, ld, j);
+    else return tl_twisted(vd, ve, ve2, b0, b1, at, pivmin, Z, ld, j);
+  };
+  double dl = twisted(lam);
   for (int it = 0; it < TL_RQI_MAX && fabs(dl) > 2.0 * eps * tn; ++it) {
     const double nl = lam + dl;
     if (!(nl >= lo && nl <= hi)) break;
     lam = nl;
-    dl = tl_twisted(vd, ve, ve2, b0, b1, lam, pivmin, Z, ld, j);
+    dl = twisted(lam);
   }
   const double nl = lam + dl;
   return (nl >= lo && nl <= hi) ? nl : lam;

@@ -244,16 +244,21 @@ def test_config4_all_kpoints():
     h.close()
 
 
-@pytest.mark.parametrize("which,precision", [("config2", "mixed"), ("config4", "fp64")])
+# config3 and ragged take the large eigensolver, whose graphs are split around the
+# block Jacobi fallback: config 3's instance is accepted by the tridiagonal path,
+# the ragged batch's rank-deficient N = 96 instance goes through the fallback.
+@pytest.mark.parametrize("which,precision", [("config2", "mixed"), ("config4", "fp64"), ("config3", "mixed"),
+                                             ("ragged", "fp64")])
 def test_graph_replay_matches_eager(which, precision):
     """The captured launch sequence reproduces the eager results bitwise on every
     replay, with other GPU work and changing parameters between replays."""
     import torch
-    wl = make_config(2) if which == "config2" else make_config(4, nk=8)
+    wl = {"config2": lambda: make_config(2), "config4": lambda: make_config(4, nk=8),
+          "config3": lambda: make_config(3), "ragged": lambda: ragged_workload()}[which]()
     params = O.parity_params(wl)
     params2 = [0.5 * p for p in params]
     print(f"[case] graph replay {which} {precision}", flush=True)
-    h, _ = make_handle(wl, precision)
+    h, _ = make_handle(wl, precision, use_bsr=which == "config3")
     ref1 = energy_grad(h, wl, params)
     ref2 = energy_grad(h, wl, params2)
     h.set_graph(True)
