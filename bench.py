@@ -170,8 +170,14 @@ def measured_traffic(stage, cfg, prec):
             kv = dict(tok.split("=", 1) for tok in line[len("# traffic:"):].split())
             if kv.get("stage") != stage or kv.get("config") != str(cfg) or kv.get("precision") != prec:
                 continue
-            src = os.path.join(ROOT, kv["source"])
-            if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv["sha256"]:
+            # source: the kernel's files, comma-separated, hashed in that order
+            h = hashlib.sha256()
+            for rel in kv["source"].split(","):
+                src = os.path.join(ROOT, rel)
+                if not os.path.exists(src):
+                    return None
+                h.update(open(src, "rb").read())
+            if h.hexdigest()[:16] != kv["sha256"]:
                 return None
             return float(kv["bytes_per_launch"])
     return None
