@@ -208,6 +208,7 @@ __device__ __forceinline__ void tl_store(double* C, int n, const tl_d4 (&acc)[TL
 }
 
 constexpr int TL_NCH = 5;                     // row chunks of the matrix-vector products
+constexpr int TL_RB = 4;                      // rows per group of the rank-2 / rank-1 updates
 constexpr int TL_PMLD = 2 * EIGH_LDS_MAX;     // stride of their partial sums
 // LDS bytes of eigh_tridiag_lds for size n
 static size_t tl_lds_bytes(int n) {
@@ -279,10 +280,27 @@ __device__ void tl_tridiag(double* A, double* QT, double* vd, double* ve, double
     const int grp = wave >> 3, cb = wave & 1, rc = (wave >> 1) & 3;
     const int col = 64 * cb + lane;
     const int rb = rc * L / 4, re = (rc + 1) * L / 4;
+    // rows in groups of TL_RB: their loads are issued before any of their stores
     if (grp == 0) {
       const int j = k + 1 + min(col, L - 1);
       const double vj = cb ? v1 : v0, wj = cb ? w1 : w0;
-      for (int ii = rb; ii < re; ++ii) {
+      int ii = rb;
+      for (; ii + TL_RB <= re; ii += TL_RB) {
+        double x[TL_RB];
+#pragma unroll
+        for (int u = 0; u < TL_RB; ++u) x[u] = A[(k + 1 + ii + u) * n + j];
+#pragma unroll
+        for (int u = 0; u < TL_RB; ++u) {
+          const int r = ii + u;
+          const double vi = r < 64 ? tl_readlane(v0, r) : tl_readlane(v1, r - 64);
+          const double wi = r < 64 ? tl_readlane(w0, r) : tl_readlane(w1, r - 64);
+          x[u] -= vi * wj + wi * vj;
+        }
+        if (col < L)
+#pragma unroll
+          for (int u = 0; u < TL_RB; ++u) A[(k + 1 + ii + u) * n + j] = x[u];
+      }
+      for (; ii < re; ++ii) {
         const double vi = ii < 64 ? tl_readlane(v0, ii) : tl_readlane(v1, ii - 64);
         const double wi = ii < 64 ? tl_readlane(w0, ii) : tl_readlane(w1, ii - 64);
         double* a = A + (k + 1 + ii) * n + j;
@@ -293,7 +311,21 @@ __device__ void tl_tridiag(double* A, double* QT, double* vd, double* ve, double
       double ur = 0.0;
       const int r = min(col, n - 1);
       for (int ch = 0; ch < TL_NCH; ++ch) ur += Pm[ch * TL_PMLD + L + r];
-      for (int jj = rb; jj < re; ++jj) {
+      int jj = rb;
+      for (; jj + TL_RB <= re; jj += TL_RB) {
+        double x[TL_RB];
+#pragma unroll
+        for (int u = 0; u < TL_RB; ++u) x[u] = QT[(k + 1 + jj + u) * n + r];
+#pragma unroll
+        for (int u = 0; u < TL_RB; ++u) {
+          const int c = jj + u;
+          x[u] -= tau * (c < 64 ? tl_readlane(v0, c) : tl_readlane(v1, c - 64)) * ur;
+        }
+        if (col < n)
+#pragma unroll
+          for (int u = 0; u < TL_RB; ++u) QT[(k + 1 + jj + u) * n + r] = x[u];
+      }
+      for (; jj < re; ++jj) {
         const double tv = tau * (jj < 64 ? tl_readlane(v0, jj) : tl_readlane(v1, jj - 64));
         double* q = QT + (k + 1 + jj) * n + r;
         const double x = *q - tv * ur;

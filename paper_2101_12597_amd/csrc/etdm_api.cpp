@@ -254,6 +254,7 @@ struct OvBuf {
   double *P, *X, *s, *Xcsw, *F3, *T1s, *T2, *T3s, *T3, *mu1, *mu2;
   double *Q1, *Cocc, *Z1, *Cvirt, *T, *d, *e, *Lov, *R, *Gam1, *Gam, *Nm, *Y1, *Y2;
   double *HC0, *n0, *eps;
+  double* HQ1;  // dense H0: H0 Q1 = (H0 C0)_v B^T (HC0 is then kept for the current C0)
 };
 
 struct ZBuf {
@@ -333,7 +334,7 @@ struct etdm_handle {
   const double** d_n0ptr = nullptr;
   double* d_wts = nullptr;
   // grouped GEMM launches
-  Stage s_PQ, s_Q1, s_F3mu, s_C, s_Z, s_T, s_V, s_Lov, s_R, s_Gam1, s_Gam, s_Y1, s_Y2, s_G;  // real: energy+gradient
+  Stage s_PQ, s_Q1, s_F3mu, s_C, s_Z, s_V, s_Lov, s_R, s_Gam1, s_Gam, s_Y1, s_Y2, s_G;  // real: energy+gradient
   // Q1 = C0_v B^T does not depend on the eigendecomposition: it runs on a side
   // stream beside the eigensolver (forked and joined by events)
   hipStream_t side = nullptr;
@@ -506,7 +507,10 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       b.Nm = pl.take(N * N);
       b.Y1 = pl.take(N * N);
       b.Y2 = pl.take(N * N);
-      b.HC0 = b.U;  // the preconditioner's H0 C0 shares the expm output workspace
+      // Dense H0: HC0 = H0 C0 is kept for the current reference (T = H0 C_occ is formed
+      // from it); block-sparse H0: the preconditioner's H0 C0 shares the expm output
+      b.HC0 = h->h0_format == 0 ? pl.take(M * M) : b.U;
+      b.HQ1 = h->h0_format == 0 ? pl.take(M * N) : nullptr;
       b.n0 = pl.take(M);
       b.eps = pl.take(M);
       b.eig_ws = nullptr;
@@ -662,7 +666,6 @@ etdm_status build_ov_plan(etdm_handle* h) {
   h->s_F3mu.init(OP_N, OP_T, GP_FP64);
   h->s_C.init(OP_N, OP_N, ep);
   h->s_Z.init(OP_N, OP_N, gp);
-  h->s_T.init(OP_N, OP_N, ep);
   h->s_V.init(OP_N, OP_N, gp);
   h->s_Lov.init(OP_T, OP_N, gp);
   h->s_R.init(OP_N, OP_T, gp);
@@ -690,6 +693,8 @@ etdm_status build_ov_plan(etdm_handle* h) {
     // P = B B^T, Q1 = C0_v B^T
     h->s_PQ.add(prob(N, N, Nv, b.B, Nv, b.B, Nv, b.P, N));
     h->s_Q1.add(prob(M, N, Nv, b.C0 + N, M, b.B, Nv, b.Q1, N));
+    // dense H0: H0 Q1 = (H0 C0)_v B^T, also independent of the eigendecomposition
+    if (b.H0) h->s_Q1.add(prob(M, N, Nv, b.HC0 + N, M, b.B, Nv, b.HQ1, N));
     // P = X diag(s) X^T
     if (N <= EIGH_LDS_MAX) {
       el.push_back(EighProb{b.P, b.X, b.s, N, 1});
@@ -743,10 +748,12 @@ etdm_status build_ov_plan(etdm_handle* h) {
     h->s_F3mu.add(prob(N, N, OV_NQ, b.T3s, OV_NQ, b.T3, OV_NQ, b.mu2, N));
     // C_occ = C0_o cos - Q1 sinc, Z1 = C0_o sinc + Q1 W
     h->s_C.add(with_second(prob(M, N, N, b.C0, M, Fc, N, b.Cocc, N), N, b.Q1, N, Fs, N, -1.0));
+    // dense H0: T = H0 C_occ = (H0 C0)_o cos - (H0 Q1) sinc, in the same launch
+    if (b.H0) h->s_C.add(with_second(prob(M, N, N, b.HC0, M, Fc, N, b.T, N), N, b.HQ1, N, Fs, N, -1.0));
     h->s_Z.add(with_second(prob(M, N, N, b.C0, M, Fs, N, b.Z1, N), N, b.Q1, N, Wm, N, 1.0));
     // C_virt = C0_v + Z1 B, T0 = H0 C_occ
     h->s_V.add(with_addend(prob(M, Nv, N, b.Z1, N, b.B, Nv, b.Cvirt, Nv), b.C0 + N, M, 1.0));
-    if (b.H0) h->s_T.add(prob(M, N, M, b.H0, M, b.Cocc, N, b.T, N));
+
     rows.push_back(OvRows{b.Cocc, b.T, b.d, b.e, M, N, h->focc[i]});
     brows.push_back(h->tot_rows);
     h->tot_rows += M;
@@ -785,7 +792,6 @@ etdm_status build_ov_plan(etdm_handle* h) {
     gs[O_F3MU] = &h->s_F3mu;
     gs[O_C] = &h->s_C;
     gs[O_Z] = &h->s_Z;
-    gs[O_T] = &h->s_T;
     gs[O_V] = &h->s_V;
     gs[O_LOV] = &h->s_Lov;
     gs[O_R] = &h->s_R;
@@ -823,7 +829,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
     }
     h->timers[O_SCAN].bytes = 8.0 * h->n_param;
   }
-  Stage* stages[] = {&h->s_PQ,  &h->s_Q1,   &h->s_F3mu, &h->s_C,  &h->s_Z,   &h->s_T,   &h->s_V,   &h->s_Lov,
+  Stage* stages[] = {&h->s_PQ,  &h->s_Q1,   &h->s_F3mu, &h->s_C,  &h->s_Z,   &h->s_V,   &h->s_Lov,
                      &h->s_R,   &h->s_Gam1, &h->s_Gam, &h->s_Y1, &h->s_Y2, &h->s_G,  &h->s_Uov,
                      &h->s_Uvv, &h->s_HC0};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
@@ -1063,7 +1069,7 @@ void ov_front(etdm_handle* h, hipStream_t s, int fallback) {
   // Q1 on the side stream, beside the eigensolver (in order while stages are timed).
   // With large instances it starts after the cooperative reductions, whose
   // workgroups must all be resident at once.
-  const bool fork = h->side && h->tmask == 0 && !h->s_Q1.probs.empty();
+  const bool fork = h->side && h->tmask == 0 && !h->s_Q1.probs.empty();  // (side: only when it pays)
   if (!fork) {
     TIMED(O_Q1);
     h->s_Q1.launch(s);
@@ -1128,13 +1134,14 @@ void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
   { TIMED(O_C); h->s_C.launch(s); }
   { TIMED(O_Z); h->s_Z.launch(s); }
   {
-    TIMED(O_T);
-    h->s_T.launch(s);
-    if (h->h0_format == 1)
+    // block-sparse H0: T = H0 C_occ here (dense H0: T was formed with C_occ)
+    if (h->h0_format == 1) {
+      TIMED(O_T);
       for (int i = 0; i < h->n_inst; ++i) {
         const OvBuf& b = h->ov[i];
         launch_bsr_spmm(b.H0_bsr, b.Cocc, h->N[i], h->N[i], b.T, h->N[i], s);
       }
+    }
   }
   { TIMED(O_V); h->s_V.launch(s); }
   { TIMED(O_ROWS); launch_ov_rows(h->d_rows, h->b_rows, h->n_inst, h->tot_rows, h->U, s); }
@@ -1177,6 +1184,7 @@ void ov_new_reference(etdm_handle* h, hipStream_t s) {
     launch_copy_block(b.C0, M, b.Cocc, N, M, N, 1.0, s);
     launch_copy_block(b.C0 + N, M, b.Cvirt, M - N, M, M - N, 1.0, s);
   }
+  if (h->h0_format == 0) h->s_HC0.launch(s);  // H0 C0 for the new reference
 }
 
 void z_exponential_part(etdm_handle* h, hipStream_t s) {
@@ -1696,7 +1704,10 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   }
   etdm_status st = real ? build_ov_plan(h) : build_z_plan(h);
   if (st == ETDM_OK) st = tune_stages(h, s);
-  if (st == ETDM_OK && real && !h->s_Q1.probs.empty() &&
+  if (st == ETDM_OK && real && h->h0_format == 0) h->s_HC0.launch(s);  // H0 C0 of the reference
+  // the side stream only where Q1 is worth a fork and join (on one small molecule
+  // they cost more than they hide)
+  if (st == ETDM_OK && real && stage_flops(h->s_Q1) >= 1e8 &&
       (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
        hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
        hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess))
