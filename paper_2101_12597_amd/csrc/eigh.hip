@@ -364,21 +364,52 @@ __device__ void tl_eigen_brackets(const double* vd, const double* ve, double* ve
   tn = block_max<TL_NT>(tn_loc, red);
   pivmin = DBL_MIN * fmax(1.0, block_max<TL_NT>(e2_loc, red));
   const double eps = DBL_EPSILON, split = eps * tn;
+  // split points of T (|e_i| <= split) as a bit mask (one ballot per wavefront,
+  // n <= 64 TL_SPLIT_WORDS), so that every eigenvalue finds the unreduced block of
+  // its index with bit scans
+  constexpr int TL_SPLIT_WORDS = (HT_MAX + 63) / 64;
+  static_assert(TL_SPLIT_WORDS * 64 <= TL_NT && EIGH_LDS_MAX <= HT_MAX, "one wavefront per mask word");
+  __shared__ unsigned long long s_split[TL_SPLIT_WORDS];
+  if ((tid >> 6) < TL_SPLIT_WORDS) {
+    const int i = tid;
+    const unsigned long long m = __ballot(i < n - 1 && fabs(ve[i]) <= split);
+    if ((tid & 63) == 0) s_split[tid >> 6] = m;
+  }
+  // one Gershgorin interval for all blocks (the off-diagonals at the split points
+  // left out); it contains the spectrum of every block
+  double gl = INFINITY, gu = -INFINITY;
+  for (int i = tid; i < n; i += TL_NT) {
+    const double r = (i > 0 && fabs(ve[i - 1]) > split ? fabs(ve[i - 1]) : 0.0) +
+                     (i < n - 1 && fabs(ve[i]) > split ? fabs(ve[i]) : 0.0);
+    gl = fmin(gl, vd[i] - r);
+    gu = fmax(gu, vd[i] + r);
+  }
+  gl = -block_max<TL_NT>(-gl, red);
+  gu = block_max<TL_NT>(gu, red);
+  const double margin = 8.0 * n * eps * tn + 4.0 * pivmin;
   for (int j = tid; j < n; j += TL_NT) {
-    int b0 = j, b1 = j + 1;
-    while (b0 > 0 && fabs(ve[b0 - 1]) > split) --b0;
-    while (b1 < n && fabs(ve[b1 - 1]) > split) ++b1;
-    double gl = INFINITY, gu = -INFINITY;
-    for (int i = b0; i < b1; ++i) {
-      const double r = (i > b0 ? fabs(ve[i - 1]) : 0.0) + (i < b1 - 1 ? fabs(ve[i]) : 0.0);
-      gl = fmin(gl, vd[i] - r);
-      gu = fmax(gu, vd[i] + r);
+    // b0 = 1 + (last split point below j), b1 = 1 + (first split point at or above j)
+    int lo_split = -1, hi_split = n - 1;
+    for (int w = (j - 1) >> 6; j > 0 && w >= 0; --w) {
+      const int top = j - 1 - 64 * w;  // highest bit of word w to consider
+      const unsigned long long m = s_split[w] & (top >= 63 ? ~0ull : ((2ull << top) - 1));
+      if (m) {
+        lo_split = 64 * w + 63 - __clzll(m);
+        break;
+      }
     }
-    const double margin = 8.0 * n * eps * tn + 4.0 * pivmin;
+    for (int w = j >> 6; w < TL_SPLIT_WORDS; ++w) {
+      const int bot = j - 64 * w;  // lowest bit of word w to consider
+      const unsigned long long m = s_split[w] & (bot <= 0 ? ~0ull : (~0ull << bot));
+      if (m) {
+        hi_split = min(64 * w + __ffsll(m) - 1, n - 1);
+        break;
+      }
+    }
     vlo[j] = gl - margin;
     vhi[j] = gu + margin;
-    ib0[j] = b0;
-    ib1[j] = b1;
+    ib0[j] = lo_split + 1;
+    ib1[j] = hi_split + 1;
   }
   __syncthreads();
   // T threads per eigenvalue, two points each
