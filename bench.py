@@ -61,10 +61,12 @@ def parse():
     ap.add_argument("--gemm-tuning", type=int, default=0, choices=range(7),
                     help="GEMM kernel choice: 0 tuned at creation, 1 size rule, 2 packed 128x128, "
                          "3 grouped 64x64, 4 packed 64x64, 5 packed 128x64, 6 packed 64x128")
+    ap.add_argument("--gradient", default="exact", choices=("exact", "approx"),
+                    help="exact dE/dA (Eq. gradients) or the approximation G ~ L^T (Eq. app_grad)")
     return ap.parse_args()
 
 
-def build_handle(wl, precision, gemm_tuning=0):
+def build_handle(wl, precision, gemm_tuning=0, gradient="exact"):
     import torch
     from paper_2101_12597_amd import Handle
     from workloads.pack import pack
@@ -73,7 +75,8 @@ def build_handle(wl, precision, gemm_tuning=0):
     H0 = torch.from_numpy(pk["H0"]).to(dev)
     C0 = torch.from_numpy(pk["C0"]).to(dev)
     h = Handle(pk["M"], pk["N"], wl.kind, precision, wl.hubbard_U, H0, C0, pk["f"],
-               couple=wl.couple, weights=pk["weights"], bsr=pk["bsr"], gemm_tuning=gemm_tuning)
+               couple=wl.couple, weights=pk["weights"], bsr=pk["bsr"], gemm_tuning=gemm_tuning,
+               gradient=gradient)
     A = torch.from_numpy(pk["A"]).to(dev)
     E = torch.empty(h.n_inst + 1, dtype=torch.float64, device=dev)
     G = torch.empty_like(A)
@@ -131,7 +134,7 @@ def gemm_kernel_table(h, prof):
     return out
 
 
-def oracle_reference(wl, params):
+def oracle_reference(wl, params, gradient="exact"):
     """Per-instance E and g from the FP64 oracle and its wall time: the definition path
     (eigendecomposition of iA), or for M > 2000 the structured path (the M x M complex
     eigendecomposition would take minutes per evaluation)."""
@@ -146,13 +149,14 @@ def oracle_reference(wl, params):
         if wl.couple:
             break
         if inst.M > 2000:
-            e, g = O.energy_grad_ov(inst, p, wl.hubbard_U)
+            ov = O.energy_grad_ov if gradient == "exact" else O.energy_grad_ov_approx
+            e, g = ov(inst, p, wl.hubbard_U)[:2]
         else:
-            e, (g,) = O.energy_grad(sub, [p])
+            e, (g,) = (O.energy_grad if gradient == "exact" else O.energy_grad_approx)(sub, [p])
         Es.append(e)
         gs.append(g)
     if wl.couple:
-        e, gs = O.energy_grad(wl, params)
+        e, gs = (O.energy_grad if gradient == "exact" else O.energy_grad_approx)(wl, params)
         Es = [e]
     return np.array(Es), gs, time.perf_counter() - t0
 
@@ -210,7 +214,7 @@ def main():
     wl = make_config(cfg)
     params = O.parity_params(wl)
     log("creating the handle")
-    h, A, E, G = build_handle(wl, prec, args.gemm_tuning)
+    h, A, E, G = build_handle(wl, prec, args.gemm_tuning, args.gradient)
     log("stage profile")
 
     # which stage dominates: time every stage over a few evaluations
@@ -238,7 +242,7 @@ def main():
     E_gpu = E.cpu().numpy()
     g_gpu = unpack_params(wl, G.cpu().numpy())
     log("oracle reference")
-    Es, gs, t_oracle = oracle_reference(wl, params)
+    Es, gs, t_oracle = oracle_reference(wl, params, args.gradient)
     if wl.couple:
         dE = abs(E_gpu[-1] - Es[0]) / wl.n_electrons
         g_all, r_all = np.concatenate([x.ravel() for x in g_gpu]), np.concatenate([x.ravel() for x in gs])
@@ -284,7 +288,7 @@ def main():
         "dtype": DTYPE[prec],
         "data": "synthetic",
         "config": {"workload": WORKLOADS[cfg], "precision": prec, "instances": len(wl.instances),
-                   "electrons": wl.n_electrons},
+                   "electrons": wl.n_electrons, "gradient": args.gradient},
         "tflops": total_flops / sec / 1e12,
         "ms_per_step_eager": sec_eager * 1e3,
         "roofline": roof,
@@ -294,7 +298,7 @@ def main():
         "gemm_kernels": gemm_kernel_table(h, prof),
     }
     if not args.no_fp64_compare and prec != "fp64":
-        h64, A64, E64, G64 = build_handle(wl, "fp64", args.gemm_tuning)
+        h64, A64, E64, G64 = build_handle(wl, "fp64", args.gemm_tuning, args.gradient)
         h64.set_graph(True)
         sec64, _ = timed_run(h64, A64, E64, G64, max(5, args.steps // 2), 2)
         out["fp64_path"] = {"value": 1.0 / sec64, "ms_per_step": sec64 * 1e3, "speedup": sec64 / sec}
@@ -317,7 +321,7 @@ def main():
     if not args.no_cpu_baseline:
         reps, total = 1, t_oracle
         while total < 10.0 and reps < 8:
-            _, _, t = oracle_reference(wl, params)
+            _, _, t = oracle_reference(wl, params, args.gradient)
             total += t
             reps += 1
         path = ("structured occupied-virtual path" if max(i.M for i in wl.instances) > 2000
@@ -325,7 +329,7 @@ def main():
         out["cpu_baseline"] = {
             "value": reps / total, "unit": "evals/s", "cores": blas_threads(), "kind": "oracle",
             "sample": f"{reps} full evaluation(s) of all {len(wl.instances)} instances with the FP64 "
-                      f"oracle's {path}, NumPy/OpenBLAS",
+                      f"oracle's {path} ({args.gradient} gradient), NumPy/OpenBLAS",
         }
     h.close()
     print(json.dumps(out))

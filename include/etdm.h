@@ -106,6 +106,10 @@ typedef struct {
                              2 = packed 128 x 128, 3 = grouped 64 x 64, 4 = packed 64 x 64,
                              5 = packed 128 x 64, 6 = packed 64 x 128.
                              Other values: ETDM_E_ARG */
+  int32_t gradient;       /* 0 = exact dE/dA (Eq. gradients, Sec. 3.4); 1 = the approximate
+                             gradient G ~ L^T of Eq. app_grad (first term of the expansion,
+                             exact at A = 0; keep A small, e.g. by reference updates).
+                             Other values: ETDM_E_ARG */
 } etdm_desc;
 
 /* Create a handle.  H0: device, dense float64 (REAL_OV) or complex float64
@@ -123,7 +127,8 @@ etdm_status etdm_destroy(etdm_handle *h);
  * instance (float64 for REAL_OV, complex for COMPLEX_FULL). */
 etdm_status etdm_expm(etdm_handle *h, const void *A, void *U, void *stream);
 
-/* E and dE/dA (Eq. gradients).  A, G: device, parameter layout.  E: device
+/* E and dE/dA (Eq. gradients), or with desc.gradient = 1 the approximation
+ * G ~ L^T of Eq. app_grad in the same layout.  A, G: device, parameter layout.  E: device
  * float64 [n_inst + 1] = per-instance energies (weighted, Hubbard included per
  * instance; with `couple` the Hubbard energy is in the total only) followed
  * by the batch total. */

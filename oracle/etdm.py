@@ -198,6 +198,34 @@ def energy_grad(wl, params) -> Tuple[float, List[np.ndarray]]:
     return E, grads
 
 
+def energy_grad_approx(wl, params) -> Tuple[float, List[np.ndarray]]:
+    """E(A) and the approximate gradient G ~ L^T of Sec. 3.4, Eq. app_grad: the first
+    term of the gradient expansion, with L = w [F, H_MO] at the current orbitals
+    C = C0 exp(A).  It replaces Y by L in energy_grad (exact at A = 0, where the
+    divided-difference factors are all 1); same layout of the returned gradients.
+    """
+    Cs, ds = _densities(wl, params)
+    ns = _hubbard_density(wl, ds)
+    E = energy(wl, params)
+    grads = []
+    for inst, C, n in zip(wl.instances, Cs, ns):
+        H = inst.h0_dense() + wl.hubbard_U * np.diag(n)
+        H_MO = C.conj().T @ H @ C
+        F = np.diag(inst.f)
+        L = inst.weight * (F @ H_MO - H_MO @ F)
+        M = L.shape[0]
+        delta = np.eye(M)
+        dEda = 0.5 * (2.0 - delta) * L.T  # G = 2 / (2 - delta) dE/da ~ L^T
+        dRe = 2.0 * np.real(dEda)
+        dIm = -2.0 * np.imag(dEda)
+        if wl.kind == "real_ov":
+            N = inst.N
+            grads.append(dRe[:N, N:].copy())
+        else:
+            grads.append(np.triu(dRe, 1) + 1j * np.triu(dIm))
+    return E, grads
+
+
 def unitary(wl, params) -> List[np.ndarray]:
     """exp(A) per instance (the etdm_expm output)."""
     return [expm_eig(generator(wl.kind, a)) for a in params]
@@ -302,6 +330,15 @@ def energy_grad_ov(inst, B: np.ndarray, hubbard_U: float, want_parts: bool = Fal
     if want_parts:
         return E, g, dict(Cocc=Cocc, Cvirt=Cvirt, d=d, Lov=Lov, sig=sig, X=X)
     return E, g
+
+
+def energy_grad_ov_approx(inst, B: np.ndarray, hubbard_U: float):
+    """E and the approximate gradient of Eq. app_grad for one real occupied-virtual
+    instance: with G ~ L^T, the ov parameters get g = -2 L_ov, L_ov = f_occ C_occ^T H C_virt
+    (the structured form of energy_grad_approx, for sizes where the M x M definition
+    path is out of reach)."""
+    E, _, parts = energy_grad_ov(inst, B, hubbard_U, want_parts=True)
+    return E, -2.0 * parts["Lov"]
 
 
 def _h0_times(inst, Cm: np.ndarray) -> np.ndarray:

@@ -358,6 +358,7 @@ struct etdm_handle {
   // packed operands of the FP64 / BF16x6 stages (shared: stages run in order)
   char* pack_arena = nullptr;
   int gemm_tuning = 0;
+  int grad_approx = 0;  // 1: G ~ L^T (Eq. app_grad) instead of the exact gradient
   std::vector<Stage*> timer_stage;  // per timed stage: its GEMM launch, or null
   std::vector<Stage*> tune_extra;   // further stages with a kernel choice (inside a timed stage)
   // tracing
@@ -744,8 +745,10 @@ etdm_status build_ov_plan(etdm_handle* h) {
     h->tot_spec += N * N + N * OV_NQ;
     // [cos; sinc; W](sqrt P) = Xcsw X^T and the two quadrature products
     h->s_F3mu.add(prob(3 * N, N, N, b.Xcsw, N, b.X, N, b.F3, N));
-    h->s_F3mu.add(prob(N, N, OV_NQ, b.T1s, OV_NQ, b.T2, OV_NQ, b.mu1, N));
-    h->s_F3mu.add(prob(N, N, OV_NQ, b.T3s, OV_NQ, b.T3, OV_NQ, b.mu2, N));
+    if (!h->grad_approx) {  // the pair integrals enter only the exact gradient
+      h->s_F3mu.add(prob(N, N, OV_NQ, b.T1s, OV_NQ, b.T2, OV_NQ, b.mu1, N));
+      h->s_F3mu.add(prob(N, N, OV_NQ, b.T3s, OV_NQ, b.T3, OV_NQ, b.mu2, N));
+    }
     // C_occ = C0_o cos - Q1 sinc, Z1 = C0_o sinc + Q1 W
     h->s_C.add(with_second(prob(M, N, N, b.C0, M, Fc, N, b.Cocc, N), N, b.Q1, N, Fs, N, -1.0));
     // dense H0: T = H0 C_occ = (H0 C0)_o cos - (H0 Q1) sinc, in the same launch
@@ -758,6 +761,10 @@ etdm_status build_ov_plan(etdm_handle* h) {
     brows.push_back(h->tot_rows);
     h->tot_rows += M;
     en.push_back(OvEnergy{b.d, b.e, M, h->focc[i], h->w[i]});
+    if (h->grad_approx) {
+      // G ~ L^T (Eq. app_grad): g = -2 L_ov, straight from the L_ov product
+      h->s_Lov.add(prob(N, Nv, M, b.T, N, b.Cvirt, Nv, b.G, Nv, -2.0 * h->w[i] * h->focc[i]));
+    } else {
     // L_ov = w f_occ T^T C_virt (the weight makes this the gradient of w E)
     h->s_Lov.add(prob(N, Nv, M, b.T, N, b.Cvirt, Nv, b.Lov, Nv, h->w[i] * h->focc[i]));
     // Gam = X^T (L_ov B^T) X
@@ -771,6 +778,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
     h->s_Y1.add(prob(N, N, N, b.X, N, b.Nm, N, b.Y1, N));
     h->s_Y2.add(prob(N, N, N, b.Y1, N, b.X, N, b.Y2, N));
     h->s_G.add(with_second(prob(N, Nv, N, Fs, N, b.Lov, Nv, b.G, Nv, -2.0), N, b.Y2, N, b.B, Nv, -2.0));
+    }
     // exp(A) blocks: U_ov = sinc B, W B (into Lov), U_vo = -B^T sinc, U_vv = I + B^T (W B)
     h->s_Uov.add(prob(N, Nv, N, Fs, N, b.B, Nv, b.U + N, M));
     h->s_Uov.add(prob(N, Nv, N, Wm, N, b.B, Nv, b.Lov, Nv));
@@ -907,7 +915,7 @@ etdm_status build_z_plan(etdm_handle* h) {
     z.n = h->couple ? h->nvec : b.d;
     z.L = b.L;
     z.G = b.G;
-    z.Y = b.Y;
+    z.Y = h->grad_approx ? b.L : b.Y;  // G ~ L^T: the gradient kernel reads L itself
     z.f = b.f;
     z.M = M;
     z.weight = h->w[i];
@@ -956,10 +964,12 @@ etdm_status build_z_plan(etdm_handle* h) {
     h->z_C.add(prob(M, M, M, b.C0, M, b.Ue, M, b.C, M));     // C = C0 exp(A)
     h->z_T.add(prob(M, M, M, b.H0, M, b.C, M, b.T, M));      // H0 C
     h->z_HMO.add(prob(M, M, M, b.C, M, b.T, M, b.L, M));     // H_MO = C^H H C
-    h->z_LV.add(prob(M, M, M, b.L, M, b.V, M, b.LV, M));     // L V
-    h->z_Lt.add(prob(M, M, M, b.V, M, b.LV, M, b.L, M));     // V^H L V
-    h->z_W1.add(prob(M, M, M, b.L, M, b.V, M, b.W1, M));     // (. o D) V^H
-    h->z_Y.add(prob(M, M, M, b.V, M, b.W1, M, b.Y, M));      // Y = V (.) V^H
+    if (!h->grad_approx) {  // Y through the eigenbasis (the exact gradient only)
+      h->z_LV.add(prob(M, M, M, b.L, M, b.V, M, b.LV, M));     // L V
+      h->z_Lt.add(prob(M, M, M, b.V, M, b.LV, M, b.L, M));     // V^H L V
+      h->z_W1.add(prob(M, M, M, b.L, M, b.V, M, b.W1, M));     // (. o D) V^H
+      h->z_Y.add(prob(M, M, M, b.V, M, b.W1, M, b.Y, M));      // Y = V (.) V^H
+    }
     h->z_HC0.add(prob(M, M, M, b.H0, M, b.C0, M, b.LV, M));  // preconditioner: H0 C0 (into LV)
   }
   h->n_eig_glb = (int)eg.size();
@@ -1151,13 +1161,34 @@ void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
     launch_total_energy(h->E_ws, h->n_inst, 0.0, nullptr, 0, h->U, h->status, s);
   }
   { TIMED(O_LOV); h->s_Lov.launch(s); }
-  { TIMED(O_R); h->s_R.launch(s); }
-  { TIMED(O_GAM1); h->s_Gam1.launch(s); }
-  { TIMED(O_GAM); h->s_Gam.launch(s); }
-  { TIMED(O_PAIR); launch_ov_pair(h->d_pair, h->b_pair, h->n_inst, h->tot_pair, s); }
-  { TIMED(O_Y1); h->s_Y1.launch(s); }
-  { TIMED(O_Y2); h->s_Y2.launch(s); }
-  { TIMED(O_G); h->s_G.launch(s); }
+  if (!h->s_R.probs.empty()) {
+    TIMED(O_R);
+    h->s_R.launch(s);
+  }
+  if (!h->s_Gam1.probs.empty()) {
+    TIMED(O_GAM1);
+    h->s_Gam1.launch(s);
+  }
+  if (!h->s_Gam.probs.empty()) {
+    TIMED(O_GAM);
+    h->s_Gam.launch(s);
+  }
+  if (h->tot_pair > 0) {
+    TIMED(O_PAIR);
+    launch_ov_pair(h->d_pair, h->b_pair, h->n_inst, h->tot_pair, s);
+  }
+  if (!h->s_Y1.probs.empty()) {
+    TIMED(O_Y1);
+    h->s_Y1.launch(s);
+  }
+  if (!h->s_Y2.probs.empty()) {
+    TIMED(O_Y2);
+    h->s_Y2.launch(s);
+  }
+  if (!h->s_G.probs.empty()) {
+    TIMED(O_G);
+    h->s_G.launch(s);
+  }
   { TIMED(O_SCAN); launch_nonfinite_scan(h->grad_ws, h->n_param, h->status, s); }
 }
 
@@ -1232,11 +1263,26 @@ void z_energy_grad(etdm_handle* h, hipStream_t s) {
   }
   { TIMED(Z_HMO); h->z_HMO.launch(s); }
   { TIMED(Z_COMM); launch_z_commutator(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s); }
-  { TIMED(Z_LV); h->z_LV.launch(s); }
-  { TIMED(Z_LT); h->z_Lt.launch(s); }
-  { TIMED(Z_DD); launch_z_divdiff(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s); }
-  { TIMED(Z_W1); h->z_W1.launch(s); }
-  { TIMED(Z_Y); h->z_Y.launch(s); }
+  if (!h->z_LV.probs.empty()) {
+    TIMED(Z_LV);
+    h->z_LV.launch(s);
+  }
+  if (!h->z_Lt.probs.empty()) {
+    TIMED(Z_LT);
+    h->z_Lt.launch(s);
+  }
+  if (!h->grad_approx) {
+    TIMED(Z_DD);
+    launch_z_divdiff(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s);
+  }
+  if (!h->z_W1.probs.empty()) {
+    TIMED(Z_W1);
+    h->z_W1.launch(s);
+  }
+  if (!h->z_Y.probs.empty()) {
+    TIMED(Z_Y);
+    h->z_Y.launch(s);
+  }
   { TIMED(Z_GRAD); launch_z_grad(h->d_z, h->b_mat, h->n_inst, h->tot_mat, h->status, s); }
 }
 
@@ -1570,6 +1616,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (d->precision < ETDM_FP64 || d->precision > ETDM_MIXED) return ETDM_E_ARG;
   if (d->kind == ETDM_COMPLEX_FULL && d->precision != ETDM_FP64) return ETDM_E_ARG;
   if (d->gemm_tuning < 0 || d->gemm_tuning > 6) return ETDM_E_ARG;
+  if (d->gradient != 0 && d->gradient != 1) return ETDM_E_ARG;
   if (d->kind == ETDM_REAL_OV && (!d->N || d->couple)) return ETDM_E_ARG;
   if (d->h0_format != 0 && d->h0_format != 1) return ETDM_E_ARG;
   if (d->h0_format == 1 && (d->kind != ETDM_REAL_OV || d->bsr_block < 1 || d->bsr_block > BSR_MAX_BS ||
@@ -1591,6 +1638,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   }
   h->prec = d->precision;
   h->gemm_tuning = d->gemm_tuning;
+  h->grad_approx = d->gradient;
   h->U = d->hubbard_U;
   h->couple = d->couple ? 1 : 0;
   h->h0_format = d->h0_format;

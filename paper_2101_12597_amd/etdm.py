@@ -51,6 +51,7 @@ class _Desc(ctypes.Structure):
         ("bsr_row_ptr", ctypes.POINTER(ctypes.c_int32)),
         ("bsr_col_idx", ctypes.POINTER(ctypes.c_int32)),
         ("gemm_tuning", ctypes.c_int32),
+        ("gradient", ctypes.c_int32),
     ]
 
 
@@ -169,12 +170,13 @@ class Handle:
                   kernels at creation and keep the fastest, 1 = fixed size rule,
                   2 = packed 128 x 128, 3 = grouped 64 x 64, 4 = packed 64 x 64,
                   5 = packed 128 x 64, 6 = packed 64 x 128
+    gradient : "exact" (Eq. gradients) or "approx" (G ~ L^T, Eq. app_grad)
     """
 
     def __init__(self, M: Sequence[int], N: Optional[Sequence[int]], kind: str, precision: str,
                  hubbard_U: float, H0, C0, f: np.ndarray, couple: bool = False,
                  weights: Optional[Sequence[float]] = None, bsr=None, stream=None,
-                 gemm_tuning: int = 0):
+                 gemm_tuning: int = 0, gradient: str = "exact"):
         L = load_library()
         self._L = L
         n = len(M)
@@ -193,6 +195,9 @@ class Handle:
         d.couple = int(bool(couple))
         d.weights = self._w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         d.gemm_tuning = int(gemm_tuning)
+        if gradient not in ("exact", "approx"):
+            raise ValueError("gradient must be 'exact' or 'approx'")
+        d.gradient = 1 if gradient == "approx" else 0
         if bsr is not None:
             blk, rp, ci = bsr
             self._rp = np.ascontiguousarray(rp, dtype=np.int32)

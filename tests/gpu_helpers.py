@@ -12,14 +12,15 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
-def make_handle(wl, precision="fp64", use_bsr=False, gemm_tuning=0):
+def make_handle(wl, precision="fp64", use_bsr=False, gemm_tuning=0, gradient="exact"):
     torch, dev = torch_dev()
     from paper_2101_12597_amd import Handle
     pk = pack(wl, use_bsr=use_bsr)
     H0 = torch.from_numpy(pk["H0"]).to(dev)
     C0 = torch.from_numpy(pk["C0"]).to(dev)
     h = Handle(pk["M"], pk["N"], wl.kind, precision, wl.hubbard_U, H0, C0, pk["f"],
-               couple=wl.couple, weights=pk["weights"], bsr=pk["bsr"], gemm_tuning=gemm_tuning)
+               couple=wl.couple, weights=pk["weights"], bsr=pk["bsr"], gemm_tuning=gemm_tuning,
+               gradient=gradient)
     torch.cuda.synchronize()
     return h, pk
 

@@ -48,8 +48,11 @@ def test_host_only_calls(repo_root):
     assert lib.etdm_param_count(None) == 0
 
 
-def test_create_rejects_bad_gemm_tuning(repo_root):
-    """gemm_tuning outside 0..6 is an argument error, found before any device call."""
+@pytest.mark.parametrize("field,bad", [("gemm_tuning", -1), ("gemm_tuning", 7), ("gradient", -1),
+                                       ("gradient", 2)])
+def test_create_rejects_bad_mode_fields(repo_root, field, bad):
+    """gemm_tuning outside 0..6 and gradient outside {0, 1} are argument errors,
+    found before any device call."""
     from paper_2101_12597_amd import LIB_PATH, load_library
     from paper_2101_12597_amd.etdm import _Desc
     if not os.path.exists(LIB_PATH):
@@ -58,15 +61,14 @@ def test_create_rejects_bad_gemm_tuning(repo_root):
     M = (ctypes.c_int32 * 1)(64)
     N = (ctypes.c_int32 * 1)(16)
     f = (ctypes.c_double * 64)(*([2.0] * 16 + [0.0] * 48))
-    for bad in (-1, 7):
-        d = _Desc()
-        d.n_inst = 1
-        d.M = M
-        d.N = N
-        d.kind = 0
-        d.precision = 4
-        d.gemm_tuning = bad
-        h = ctypes.c_void_p()
-        dummy = ctypes.c_void_p(8)  # never dereferenced: validation fails first
-        assert lib.etdm_create(ctypes.byref(h), ctypes.byref(d), dummy, dummy, f, None) == -1
-        assert h.value is None
+    d = _Desc()
+    d.n_inst = 1
+    d.M = M
+    d.N = N
+    d.kind = 0
+    d.precision = 4
+    setattr(d, field, bad)
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(8)  # never dereferenced: validation fails first
+    assert lib.etdm_create(ctypes.byref(h), ctypes.byref(d), dummy, dummy, f, None) == -1
+    assert h.value is None

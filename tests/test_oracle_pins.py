@@ -153,6 +153,78 @@ def test_gradient_at_zero_is_commutator():
     assert np.abs(g - (-2.0 * 2.0 * H_MO[:5, 5:])).max() < 1e-14
 
 
+# ---------------------------------------------------------------------------
+# approximate gradient G ~ L^T (Eq. app_grad)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["real_ov", "complex"])
+def test_approx_gradient_at_zero_matches_finite_differences(kind):
+    """At A = 0 the first term of the expansion is the whole gradient: G ~ L^T agrees
+    with central differences of E (not only with the exact-gradient code)."""
+    wl = tiny_real(11, 4, seed=21) if kind == "real_ov" else tiny_complex(6, nk_side=1, kT=0.05)
+    zero = O.zero_params(wl)
+    _, grads = O.energy_grad_approx(wl, zero)
+    gv = O.flatten(wl.kind, grads)
+    _, gex = O.energy_grad(wl, zero)
+    assert np.abs(gv - O.flatten(wl.kind, gex)).max() < 1e-13 * (np.abs(gv).max() + 1.0)
+    rng = np.random.default_rng(22)
+    for _ in range(3):
+        d = rng.standard_normal(gv.size)
+        assert abs(_fd_directional(wl, zero, d, 1e-3) - gv @ d) < 2e-9 * (np.abs(gv).sum() + 1.0)
+
+
+@pytest.mark.parametrize("kind,order", [("real_ov", 2), ("complex", 1)])
+def test_approx_gradient_error_order(kind, order):
+    """G ~ L^T drops the terms of the expansion beyond the first; the next one is
+    [A, L]/2.  With fractional occupations (complex case) it is O(A), so the error
+    halves with A.  In the ov parametrization with integer occupations A and L are
+    both block off-diagonal, [A, L] has no ov block, and the error is O(A^2)."""
+    wl = tiny_real(12, 5, seed=23, scale=1.0) if kind == "real_ov" else tiny_complex(6, nk_side=1, kT=0.05)
+    base = O.parity_params(wl)
+    errs = []
+    for t in (0.04, 0.02, 0.01):
+        p = [t * b / max(np.abs(b).max(), 1e-300) for b in base]
+        _, ga = O.energy_grad_approx(wl, p)
+        _, ge = O.energy_grad(wl, p)
+        errs.append(np.linalg.norm(O.flatten(wl.kind, ga) - O.flatten(wl.kind, ge)))
+    want = 2.0 ** order
+    assert all(0.9 * want < errs[i] / errs[i + 1] < 1.1 * want for i in range(2)), errs
+    assert errs[2] > 0.0
+
+
+def test_approx_gradient_exact_for_one_rotation_plane():
+    """One occupied and one virtual orbital: rotations in the single plane commute,
+    so the derivative at the current orbitals, L^T, is the exact dE/dtheta for
+    every angle (closed form E(theta) differentiated numerically)."""
+    M, N = 2, 1
+    rng = np.random.default_rng(24)
+    H0 = rng.standard_normal((M, M))
+    H0 = 0.5 * (H0 + H0.T)
+    C0 = haar_orthogonal(M, rng)
+    wl = Workload(0, "two-level", "real_ov", 0.7, False)
+    f = np.array([2.0, 0.0])
+    for th in (0.3, -1.1, 2.0):
+        wl.instances = [Instance(M=M, N=N, f=f, C0=C0, A=np.array([[th]]), H0=H0)]
+        _, (ga,) = O.energy_grad_approx(wl, [np.array([[th]])])
+        _, (ge,) = O.energy_grad(wl, [np.array([[th]])])
+        h = 1e-4
+        fd = (O.energy(wl, [np.array([[th + h]])]) - O.energy(wl, [np.array([[th - h]])])) / (2 * h)
+        assert abs(ga[0, 0] - ge[0, 0]) < 1e-12 * max(1.0, abs(ge[0, 0]))
+        assert abs(ga[0, 0] - fd) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_structured_approx_gradient_matches_definition_path():
+    """The structured ov form (g = -2 L_ov from C_occ, C_virt) agrees with the M x M
+    definition path of G ~ L^T at a rotation far from zero."""
+    wl = tiny_real(14, 5, seed=25, scale=0.8)
+    p = O.parity_params(wl)
+    E, (g,) = O.energy_grad_approx(wl, p)
+    Es, gs = O.energy_grad_ov_approx(wl.instances[0], p[0], wl.hubbard_U)
+    assert abs(E - Es) < 1e-12 * max(1.0, abs(E))
+    assert np.abs(g - gs).max() < 1e-12 * max(1.0, np.abs(g).max())
+    _, (ge,) = O.energy_grad(wl, p)
+    assert np.abs(g - ge).max() > 1e-6  # far enough from zero that the two gradients differ
+
+
 def _fd_directional(wl, params, d, h):
     kind = wl.kind
     v = O.flatten(kind, params)
