@@ -167,9 +167,30 @@ void etdm_lbfgs_defaults(etdm_lbfgs_params *p);
  * etdm_set_reference) the state is initialised from A.  When a reference reset
  * happens (every reset_every iterations) C0 <- C0 exp(A) and A is set to 0
  * before the step.  params may be NULL (defaults).  info: host, out.
- * Synchronizes `stream` once per line-search probe to read three numbers. */
+ * The direction, the Wolfe tests and cubic steps of the line search, and the
+ * memory and beta updates are decided on the device; the host synchronizes
+ * `stream` once per line-search probe to read the outcome.  With etdm_set_graph
+ * on, each probe (with the direction for the first) replays one captured graph.
+ * ETDM_E_LINESEARCH when neither the L-BFGS direction nor steepest descent
+ * yields an acceptable step (state unchanged). */
 etdm_status etdm_lbfgs_step(etdm_handle *h, const etdm_lbfgs_params *params, void *A, double *E,
                             void *G, etdm_lbfgs_info *info, void *stream);
+
+/* L-BFGS checkpoint (Sec. 3.4: the state of the minimization is the reference
+ * orbitals, A and the L-BFGS memory).  The image lives in caller-owned DEVICE
+ * memory of etdm_lbfgs_state_bytes(h) bytes (0 before the first
+ * etdm_lbfgs_step): a header, the device-side L-BFGS scalars, A, g, the m
+ * stored pairs and every instance's reference orbitals C0.  It is opaque and
+ * valid only for a handle created from the same shapes, kind, precision and
+ * gradient mode (etdm_lbfgs_set_state returns ETDM_E_SHAPE otherwise).
+ * set_state also rebuilds the preconditioner from the restored C0.  On a handle
+ * whose kernels are the same (the same gemm_tuning choice), the etdm_lbfgs_step
+ * calls after set_state repeat bit for bit those that followed get_state.
+ * get_state before the first etdm_lbfgs_step: ETDM_E_ARG.  Both synchronize
+ * `stream`. */
+size_t etdm_lbfgs_state_bytes(const etdm_handle *h);
+etdm_status etdm_lbfgs_get_state(etdm_handle *h, void *state, void *stream);
+etdm_status etdm_lbfgs_set_state(etdm_handle *h, const void *state, void *stream);
 
 /* Wait for `stream` and report a device-side failure recorded since the last call. */
 etdm_status etdm_sync_status(etdm_handle *h, void *stream);

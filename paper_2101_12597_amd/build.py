@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libetdm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["gemm.hip", "gemm_split.hip", "eigh.hip", "eigh_large.hip", "ov.hip", "full.hip", "etdm_api.cpp"]
+SOURCES = ["gemm.hip", "gemm_split.hip", "eigh.hip", "eigh_large.hip", "ov.hip", "full.hip", "lbfgs.hip",
+           "etdm_api.cpp"]
 
 COMMON_FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"-I{INCLUDE}", f"-I{CSRC}",

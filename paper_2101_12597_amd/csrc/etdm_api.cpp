@@ -16,13 +16,13 @@
 #include "common.h"
 #include "ov.h"
 #include "eigh_large.h"
+#include "lbfgs.h"
 
 using namespace etdm;
 
 namespace {
 
 constexpr size_t ALIGN = 256;
-constexpr int LB_MMAX = 8;
 constexpr int LARGE_EIGH_MAX_SWEEPS = 30;
 
 // Gauss-Legendre nodes and weights on [0, 1] by Newton iteration on the
@@ -341,12 +341,22 @@ struct etdm_handle {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   Stage s_Uov, s_Uvv, s_HC0;                                                   // real: expm, preconditioner
   Stage z_Ue, z_C, z_T, z_HMO, z_LV, z_Lt, z_W1, z_Y, z_HC0;                   // complex
-  // L-BFGS state
+  // L-BFGS: scalars and decisions in lb_st (device); the host keeps the iteration
+  // and evaluation counts and reads lb_sum (pinned) once per line-search probe
   bool lb_init = false;
-  int lb_iter = 0, lb_evals = 0, lb_count = 0, lb_head = 0, lb_m = 3;
-  double lb_E = 0.0, lb_beta = 1.0;
-  double *x = nullptr, *g = nullptr, *p = nullptr, *q = nullptr, *xt = nullptr, *gt = nullptr;
-  double *hd = nullptr, *wv = nullptr, *S = nullptr, *Yv = nullptr, *partial = nullptr, *sc = nullptr;
+  int lb_iter = 0, lb_evals = 0;
+  LbParams lbp{};
+  bool lbp_set = false;
+  LbState* lb_st = nullptr;
+  LbState* lb_sum = nullptr;
+  double *x = nullptr, *g = nullptr, *p = nullptr, *q = nullptr;
+  double *hd = nullptr, *wv = nullptr, *S = nullptr, *Yv = nullptr, *partial = nullptr;
+  // captured L-BFGS probes: [0] direction + probe, [1] probe, [2] steepest restart + probe;
+  // with the large solver each ends at its acceptance checks and lbg_back finishes the probe
+  hipGraph_t lbg[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t lbg_exec[3] = {nullptr, nullptr, nullptr};
+  hipGraph_t lbg_back = nullptr;
+  hipGraphExec_t lbg_back_exec = nullptr;
   // graph replay of the energy+gradient sequence
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
@@ -368,10 +378,6 @@ struct etdm_handle {
 };
 
 namespace {
-
-// device scalar slots of the L-BFGS driver
-enum { SC_T = 0, SC_T2 = 1, SC_DPHI = 2, SC_E = 3, SC_SY = 4, SC_YY = 5, SC_GG = 6, SC_YS0 = 8,
-       SC_AL0 = 16, SC_COEF = 24, SC_COUNT = 32 };
 
 etdm_status fail(etdm_handle* h, etdm_status s, const std::string& msg) {
   if (h) h->err = msg;
@@ -557,14 +563,12 @@ size_t plan_buffers(etdm_handle* h, char* base) {
   h->g = pl.take(np);
   h->p = pl.take(np);
   h->q = pl.take(np);
-  h->xt = pl.take(np);
-  h->gt = pl.take(np);
   h->hd = pl.take(np);
   h->wv = pl.take(np);
   h->S = pl.take(np * LB_MMAX);
   h->Yv = pl.take(np * LB_MMAX);
-  h->partial = pl.take(1024);
-  h->sc = pl.take(SC_COUNT);
+  h->partial = pl.take(3 * LB_DOT_BLOCKS);
+  h->lb_st = reinterpret_cast<LbState*>(pl.take((sizeof(LbState) + 7) / 8));
   return pl.off;
 }
 
@@ -1042,6 +1046,19 @@ void free_timers(etdm_handle* h) {
   }
 }
 
+void free_lb_graphs(etdm_handle* h) {
+  for (int i = 0; i < 3; ++i) {
+    if (h->lbg_exec[i]) hipGraphExecDestroy(h->lbg_exec[i]);
+    if (h->lbg[i]) hipGraphDestroy(h->lbg[i]);
+    h->lbg_exec[i] = nullptr;
+    h->lbg[i] = nullptr;
+  }
+  if (h->lbg_back_exec) hipGraphExecDestroy(h->lbg_back_exec);
+  if (h->lbg_back) hipGraphDestroy(h->lbg_back);
+  h->lbg_back_exec = nullptr;
+  h->lbg_back = nullptr;
+}
+
 void free_graph(etdm_handle* h) {
   if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
   if (h->graph) hipGraphDestroy(h->graph);
@@ -1049,6 +1066,7 @@ void free_graph(etdm_handle* h) {
   if (h->graph2) hipGraphDestroy(h->graph2);
   h->graph_exec = h->graph2_exec = nullptr;
   h->graph = h->graph2 = nullptr;
+  free_lb_graphs(h);
 }
 
 void free_handle(etdm_handle* h) {
@@ -1056,6 +1074,7 @@ void free_handle(etdm_handle* h) {
   free_graph(h);
   if (h->cap_stream) hipStreamDestroy(h->cap_stream);
   if (h->ok_host) hipHostFree(h->ok_host);
+  if (h->lb_sum) hipHostFree(h->lb_sum);
   if (h->side) hipStreamDestroy(h->side);
   if (h->ev_fork) hipEventDestroy(h->ev_fork);
   if (h->ev_join) hipEventDestroy(h->ev_join);
@@ -1304,12 +1323,26 @@ etdm_status capture(etdm_handle* h, hipGraph_t* g, hipGraphExec_t* x, void (*seq
   return ETDM_OK;
 }
 
+// Between the two graphs of a split sequence: read the acceptance flags of the
+// large instances and run the block Jacobi fallback for those that failed.
+etdm_status large_fallback(etdm_handle* h, hipStream_t s) {
+  if (!h->ok_host) HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&h->ok_host), h->eig_large.size() * sizeof(int)));
+  for (size_t i = 0; i < h->eig_large.size(); ++i)
+    HIPCHK(h, hipMemcpyAsync(&h->ok_host[i], h->eig_large[i].ok, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  for (size_t i = 0; i < h->eig_large.size(); ++i)
+    if (!h->ok_host[i]) launch_eigh_large(h->eig_large[i], LARGE_EIGH_MAX_SWEEPS, h->status, s, true);
+  return ETDM_OK;
+}
+
+bool split_sequence(const etdm_handle* h) { return h->kind == ETDM_REAL_OV && !h->eig_large.empty(); }
+
 etdm_status run_energy_grad(etdm_handle* h, hipStream_t s) {
   if (!h->use_graph || h->tmask != 0) {
     run_energy_grad_eager(h, s);
     return ETDM_OK;
   }
-  const bool split = h->kind == ETDM_REAL_OV && !h->eig_large.empty();
+  const bool split = split_sequence(h);
   if (!h->graph_exec) {
     if (split) {
       CHECK(capture(h, &h->graph, &h->graph_exec, [](etdm_handle* hh, hipStream_t ss) { ov_front(hh, ss, 0); }));
@@ -1317,18 +1350,13 @@ etdm_status run_energy_grad(etdm_handle* h, hipStream_t s) {
         ov_back_exp(hh, ss);
         ov_energy_grad_rest(hh, ss);
       }));
-      if (!h->ok_host) HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&h->ok_host), h->eig_large.size() * sizeof(int)));
     } else {
       CHECK(capture(h, &h->graph, &h->graph_exec, run_energy_grad_eager));
     }
   }
   HIPCHK(h, hipGraphLaunch(h->graph_exec, s));
   if (split) {
-    for (size_t i = 0; i < h->eig_large.size(); ++i)
-      HIPCHK(h, hipMemcpyAsync(&h->ok_host[i], h->eig_large[i].ok, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    for (size_t i = 0; i < h->eig_large.size(); ++i)
-      if (!h->ok_host[i]) launch_eigh_large(h->eig_large[i], LARGE_EIGH_MAX_SWEEPS, h->status, s, true);
+    CHECK(large_fallback(h, s));
     HIPCHK(h, hipGraphLaunch(h->graph2_exec, s));
   }
   return ETDM_OK;
@@ -1389,180 +1417,102 @@ void new_reference(etdm_handle* h, hipStream_t s) {
 }
 
 // ----- L-BFGS driver ---------------------------------------------------------------
+//
+// One probe of the line search is: [pre] evaluation at xtrial (= par_ws) [post].
+// pre is the direction and the line-search start (which 0), nothing (which 1), or
+// the steepest-descent restart (which 2); post is launch_lb_after_probe, which
+// ends with the state copied to lb_sum.  With graphs on, each probe is one graph
+// replay (two around the block Jacobi fallback of the large solver) and one
+// stream synchronization.
 
-struct Probe {
-  double a, f, d;
-};
+void lb_pre(etdm_handle* h, int which, hipStream_t s) {
+  const int64_t n = h->n_param;
+  if (which == 0)
+    launch_lb_direction(h->lb_st, h->lbp, h->x, h->g, h->p, h->q, h->S, h->Yv, h->hd, h->wv, n, h->partial,
+                        h->par_ws, s);
+  else if (which == 2)
+    launch_lb_restart(h->lb_st, h->lbp, h->x, h->g, h->p, h->hd, h->wv, n, h->partial, h->par_ws, s);
+}
 
-// E and g at x (device); returns E, the slope g.p, and optionally |g|^2.
-etdm_status lb_eval(etdm_handle* h, const double* xin, double* gout, double& E, double& slope, hipStream_t s,
-                    double* gg = nullptr) {
-  const size_t pb = (size_t)h->n_param * sizeof(double);
-  if (pb) HIPCHK(h, hipMemcpyAsync(h->par_ws, xin, pb, hipMemcpyDeviceToDevice, s));
-  CHECK(run_energy_grad(h, s));
-  if (pb) HIPCHK(h, hipMemcpyAsync(gout, h->grad_ws, pb, hipMemcpyDeviceToDevice, s));
-  launch_dot(gout, h->p, h->n_param, h->partial, h->sc + SC_DPHI, s);
-  if (gg) launch_dot(gout, gout, h->n_param, h->partial, h->sc + SC_GG, s);
-  HIPCHK(h, hipMemcpyAsync(h->sc + SC_E, h->E_ws + h->n_inst, sizeof(double), hipMemcpyDeviceToDevice, s));
+void lb_post(etdm_handle* h, hipStream_t s) {
+  launch_lb_after_probe(h->lb_st, h->lbp, h->x, h->g, h->p, h->grad_ws, h->E_ws + h->n_inst, h->status, h->S,
+                        h->Yv, h->n_param, h->partial, h->par_ws, h->lb_sum, s);
+}
+
+template <int W>
+void lb_seq_whole(etdm_handle* h, hipStream_t s) {
+  lb_pre(h, W, s);
+  run_energy_grad_eager(h, s);
+  lb_post(h, s);
+}
+
+template <int W>
+void lb_seq_front(etdm_handle* h, hipStream_t s) {
+  lb_pre(h, W, s);
+  ov_front(h, s, 0);
+}
+
+void lb_seq_back(etdm_handle* h, hipStream_t s) {
+  ov_back_exp(h, s);
+  ov_energy_grad_rest(h, s);
+  lb_post(h, s);
+}
+
+// one probe: launch, wait, and read the device decision from lb_sum
+etdm_status lb_probe(etdm_handle* h, int which, hipStream_t s) {
+  if (!h->use_graph || h->tmask != 0) {
+    lb_pre(h, which, s);
+    run_energy_grad_eager(h, s);
+    lb_post(h, s);
+  } else if (split_sequence(h)) {
+    if (!h->lbg_exec[which]) {
+      void (*seq)(etdm_handle*, hipStream_t) =
+          which == 0 ? lb_seq_front<0> : which == 1 ? lb_seq_front<1> : lb_seq_front<2>;
+      CHECK(capture(h, &h->lbg[which], &h->lbg_exec[which], seq));
+    }
+    if (!h->lbg_back_exec) CHECK(capture(h, &h->lbg_back, &h->lbg_back_exec, lb_seq_back));
+    HIPCHK(h, hipGraphLaunch(h->lbg_exec[which], s));
+    CHECK(large_fallback(h, s));
+    HIPCHK(h, hipGraphLaunch(h->lbg_back_exec, s));
+  } else {
+    if (!h->lbg_exec[which]) {
+      void (*seq)(etdm_handle*, hipStream_t) =
+          which == 0 ? lb_seq_whole<0> : which == 1 ? lb_seq_whole<1> : lb_seq_whole<2>;
+      CHECK(capture(h, &h->lbg[which], &h->lbg_exec[which], seq));
+    }
+    HIPCHK(h, hipGraphLaunch(h->lbg_exec[which], s));
+  }
   HIPCHK(h, hipGetLastError());
-  CHECK(check_status(h, s));
-  double v[8];
-  HIPCHK(h, hipMemcpy(v, h->sc, sizeof(v), hipMemcpyDeviceToHost));
-  E = v[SC_E];
-  slope = v[SC_DPHI];
-  if (gg) *gg = v[SC_GG];
+  HIPCHK(h, hipStreamSynchronize(s));
   ++h->lb_evals;
   return ETDM_OK;
 }
 
-double* slot(double* base, int64_t n, int i) { return base + (int64_t)i * n; }
-
-// p = -H g by the two-loop recursion with H0 = diag(P) (Eq. prec_3); all scalars stay on the device.
-void lb_direction(etdm_handle* h, double gamma, hipStream_t s) {
-  const int64_t n = h->n_param;
-  const int m = h->lb_m;
-  hipMemcpyAsync(h->q, h->g, n * sizeof(double), hipMemcpyDeviceToDevice, s);
-  for (int k = 0; k < h->lb_count; ++k) {  // newest to oldest
-    const int i = (h->lb_head - 1 - k + m) % m;
-    launch_dot(slot(h->S, n, i), h->q, n, h->partial, h->sc + SC_T, s);
-    launch_scalar_ratio(h->sc + SC_AL0 + i, h->sc + SC_T, h->sc + SC_YS0 + i, 1.0, s);
-    launch_axpby(h->q, slot(h->Yv, n, i), n, 1.0, nullptr, -1.0, h->sc + SC_AL0 + i, s);
-  }
-  launch_precond(h->p, h->q, h->hd, h->wv, n, gamma, h->lb_beta, s);
-  for (int k = h->lb_count - 1; k >= 0; --k) {  // oldest to newest
-    const int i = (h->lb_head - 1 - k + m) % m;
-    launch_dot(slot(h->Yv, n, i), h->p, n, h->partial, h->sc + SC_T, s);
-    launch_scalar_ratio(h->sc + SC_T2, h->sc + SC_T, h->sc + SC_YS0 + i, 1.0, s);
-    launch_scalar_sub(h->sc + SC_COEF, h->sc + SC_AL0 + i, h->sc + SC_T2, s);
-    launch_axpby(h->p, slot(h->S, n, i), n, 1.0, nullptr, 1.0, h->sc + SC_COEF, s);
-  }
-  launch_axpby(h->p, h->p, n, -1.0, nullptr, 0.0, nullptr, s);
-}
-
-void lb_steepest(etdm_handle* h, double gamma, hipStream_t s) {
-  launch_precond(h->p, h->g, h->hd, h->wv, h->n_param, gamma, h->lb_beta, s);
-  launch_axpby(h->p, h->p, h->n_param, -1.0, nullptr, 0.0, nullptr, s);
-}
-
-double cubic_min(double a, double fa, double ga, double b, double fb, double gb, bool& ok) {
-  ok = false;
-  if (a == b) return 0.0;
-  const double d1 = ga + gb - 3.0 * (fa - fb) / (a - b);
-  const double disc = d1 * d1 - ga * gb;
-  if (disc < 0.0) return 0.0;
-  const double d2 = std::copysign(std::sqrt(disc), b - a);
-  const double den = gb - ga + 2.0 * d2;
-  if (den == 0.0) return 0.0;
-  ok = true;
-  return b - (b - a) * (gb + d2 - d1) / den;
-}
-
-// Line search along p from (x, E0, g) (Sec. 3.2).  On success xt/gt hold the
-// accepted point, E_ws its energies.
-etdm_status lb_line_search(etdm_handle* h, const etdm_lbfgs_params& P, double f0, double dphi0, double& alpha,
-                           double& f_acc, bool& ok, hipStream_t s) {
-  const int64_t n = h->n_param;
-  int evals = 0;
-  double last_a = -1.0;
-  auto phi = [&](double a, Probe& pr) -> etdm_status {
-    HIPCHK(h, hipMemcpyAsync(h->xt, h->x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    launch_axpby(h->xt, h->p, n, 1.0, nullptr, a, nullptr, s);
-    double E, d;
-    CHECK(lb_eval(h, h->xt, h->gt, E, d, s));
-    ++evals;
-    last_a = a;
-    pr = Probe{a, E, d};
-    return ETDM_OK;
-  };
-  auto strong_wolfe = [&](const Probe& r) {
-    return r.f <= f0 + P.c1 * r.a * dphi0 && std::fabs(r.d) <= P.c2 * std::fabs(dphi0);
-  };
-  auto approx_wolfe = [&](const Probe& r) {
-    return (2.0 * P.delta - 1.0) * dphi0 >= r.d && r.d >= P.sigma * dphi0 && r.f <= f0 + P.eps * std::fabs(f0);
-  };
-  Probe best{0.0, f0, dphi0};
-  auto note = [&](const Probe& r) {
-    if (r.f < best.f) best = r;
-  };
-  auto accept = [&](const Probe& r) {
-    alpha = r.a;
-    f_acc = r.f;
-    ok = true;
-    return ETDM_OK;
-  };
-  ok = false;
-  Probe prev{0.0, f0, dphi0}, cur;
-  CHECK(phi(1.0, cur));
-  note(cur);
-  if (strong_wolfe(cur)) return accept(cur);
-  bool first = true;
-  bool do_zoom = false;
-  Probe lo, hi;
-  while (true) {
-    if (cur.f > f0 + P.c1 * cur.a * dphi0 || (!first && cur.f >= prev.f)) {
-      lo = prev;
-      hi = cur;
-      do_zoom = true;
-      break;
-    }
-    if (cur.d >= 0.0) {
-      lo = cur;
-      hi = prev;
-      do_zoom = true;
-      break;
-    }
-    bool cok;
-    double a_new = cubic_min(prev.a, prev.f, prev.d, cur.a, cur.f, cur.d, cok);
-    if (!cok || !std::isfinite(a_new) || a_new < 1.1 * cur.a || a_new > 4.0 * cur.a)
-      a_new = (!cok || !std::isfinite(a_new) || a_new > 4.0 * cur.a) ? 4.0 * cur.a : 1.1 * cur.a;
-    prev = cur;
-    if (evals >= P.max_ls) break;
-    CHECK(phi(a_new, cur));
-    note(cur);
-    first = false;
-    if (strong_wolfe(cur) || approx_wolfe(cur)) return accept(cur);
-  }
-  if (do_zoom) {
-    while (evals < P.max_ls) {
-      bool cok;
-      double a = cubic_min(lo.a, lo.f, lo.d, hi.a, hi.f, hi.d, cok);
-      const double width = hi.a - lo.a;
-      const double left = std::min(lo.a, hi.a) + 0.1 * std::fabs(width);
-      const double right = std::max(lo.a, hi.a) - 0.1 * std::fabs(width);
-      if (!cok || !std::isfinite(a) || a < left || a > right) a = 0.5 * (lo.a + hi.a);
-      Probe r;
-      CHECK(phi(a, r));
-      note(r);
-      if (strong_wolfe(r) || approx_wolfe(r)) return accept(r);
-      if (r.f > f0 + P.c1 * r.a * dphi0 || r.f >= lo.f) {
-        hi = r;
-      } else {
-        if (r.d * (hi.a - lo.a) >= 0.0) hi = lo;
-        lo = r;
-      }
-    }
-  }
-  // no point met the conditions: take the lowest energy seen, if any
-  if (best.a > 0.0) {
-    if (best.a != last_a) {
-      Probe r;
-      CHECK(phi(best.a, r));
-    }
-    return accept(best);
+// Line search started by `which` (0 or 2): probes until the device accepts or
+// gives up; lb_sum then holds the final state.
+etdm_status lb_search(etdm_handle* h, int which, hipStream_t s) {
+  CHECK(lb_probe(h, which, s));
+  while (h->lb_sum->result == LR_CONT) CHECK(lb_probe(h, 1, s));
+  if (h->lb_sum->result == LR_STATUS) {
+    CHECK(check_status(h, s));
+    return fail(h, ETDM_E_HIP, "device status word set during the line search");
   }
   return ETDM_OK;
 }
 
-etdm_status lb_initialise(etdm_handle* h, const etdm_lbfgs_params& P, hipStream_t s) {
-  double E, d, gg;
-  launch_fill(h->p, h->n_param, 0.0, s);
-  CHECK(lb_eval(h, h->x, h->g, E, d, s, &gg));
+// Evaluation at x, then a fresh memory (beta reset to beta0 when set_beta) and the
+// preconditioner of the current reference orbitals.
+etdm_status lb_start(etdm_handle* h, double beta0, int set_beta, hipStream_t s) {
+  const size_t pb = (size_t)h->n_param * sizeof(double);
+  if (pb) HIPCHK(h, hipMemcpyAsync(h->par_ws, h->x, pb, hipMemcpyDeviceToDevice, s));
+  CHECK(run_energy_grad(h, s));
+  if (pb) HIPCHK(h, hipMemcpyAsync(h->g, h->grad_ws, pb, hipMemcpyDeviceToDevice, s));
+  launch_lb_start(h->lb_st, h->g, h->n_param, h->E_ws + h->n_inst, beta0, set_beta, h->lbp.m, h->partial, s);
   build_hdiag(h, s);
+  HIPCHK(h, hipMemcpyAsync(h->lb_sum, h->lb_st, sizeof(LbState), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipGetLastError());
-  h->lb_E = E;
-  h->lb_count = 0;
-  h->lb_head = 0;
-  h->lb_m = std::min(std::max(P.m, 1), LB_MMAX);
+  CHECK(check_status(h, s));
+  ++h->lb_evals;
   return ETDM_OK;
 }
 
@@ -1887,6 +1837,143 @@ etdm_status etdm_stage_kernel(const etdm_handle* h, int32_t i, const char** vari
   return ETDM_OK;
 }
 
+}  // extern "C"
+
+// ----- L-BFGS checkpoint -----------------------------------------------------------
+
+namespace {
+
+constexpr size_t LB_CKPT_HEADER = 256;
+
+struct LbCheckpoint {
+  char magic[8];
+  uint64_t layout;      // FNV-1a of kind, precision, gradient mode and every (M, N)
+  int64_t n_param, c0_doubles;
+  int32_t iter, evals, m, pad;
+  LbParams lbp;
+};
+static_assert(sizeof(LbCheckpoint) <= LB_CKPT_HEADER, "checkpoint header too large");
+const char kCkptMagic[8] = {'E', 'T', 'D', 'M', 'L', 'B', 'S', '1'};
+
+uint64_t ckpt_layout(const etdm_handle* h) {
+  uint64_t v = 1469598103934665603ull;
+  auto mix = [&](int64_t x) {
+    for (int b = 0; b < 8; ++b) {
+      v ^= (uint64_t)((x >> (8 * b)) & 0xff);
+      v *= 1099511628211ull;
+    }
+  };
+  mix(h->kind);
+  mix(h->prec);
+  mix(h->grad_approx);
+  mix(h->n_inst);
+  for (int i = 0; i < h->n_inst; ++i) {
+    mix(h->M[i]);
+    mix(h->N[i]);
+  }
+  return v;
+}
+
+int64_t c0_doubles(const etdm_handle* h, int i) {
+  const int64_t MM = (int64_t)h->M[i] * h->M[i];
+  return h->kind == ETDM_REAL_OV ? MM : 2 * MM;
+}
+
+double* c0_ptr(etdm_handle* h, int i) { return h->kind == ETDM_REAL_OV ? h->ov[i].C0 : h->zb[i].C0; }
+
+size_t state_scalars_bytes() { return (sizeof(LbState) + 7) / 8 * 8; }
+
+}  // namespace
+
+extern "C" {
+
+size_t etdm_lbfgs_state_bytes(const etdm_handle* h) {
+  if (!h || !h->lb_init) return 0;
+  int64_t c0 = 0;
+  for (int i = 0; i < h->n_inst; ++i) c0 += c0_doubles(h, i);
+  const int64_t n = h->n_param;
+  return LB_CKPT_HEADER + state_scalars_bytes() + sizeof(double) * (size_t)(2 * n + 2 * h->lbp.m * n + c0);
+}
+
+etdm_status etdm_lbfgs_get_state(etdm_handle* h, void* state, void* stream) {
+  if (!h) return ETDM_E_ARG;
+  if (!h->lb_init) return fail(h, ETDM_E_ARG, "no L-BFGS state before the first etdm_lbfgs_step");
+  if (!state) return fail(h, ETDM_E_ARG, "null state buffer");
+  hipStream_t s = S(stream);
+  LbCheckpoint hd{};
+  std::memcpy(hd.magic, kCkptMagic, 8);
+  hd.layout = ckpt_layout(h);
+  hd.n_param = h->n_param;
+  for (int i = 0; i < h->n_inst; ++i) hd.c0_doubles += c0_doubles(h, i);
+  hd.iter = h->lb_iter;
+  hd.evals = h->lb_evals;
+  hd.m = h->lbp.m;
+  hd.lbp = h->lbp;
+  char* out = static_cast<char*>(state);
+  const int64_t n = h->n_param;
+  const size_t vb = (size_t)n * sizeof(double);
+  HIPCHK(h, hipMemcpyAsync(out, &hd, sizeof(hd), hipMemcpyHostToDevice, s));
+  out += LB_CKPT_HEADER;
+  HIPCHK(h, hipMemcpyAsync(out, h->lb_st, sizeof(LbState), hipMemcpyDeviceToDevice, s));
+  out += state_scalars_bytes();
+  const std::pair<const double*, size_t> parts[] = {
+      {h->x, vb}, {h->g, vb}, {h->S, vb * hd.m}, {h->Yv, vb * hd.m}};
+  for (const auto& pr : parts) {
+    if (pr.second) HIPCHK(h, hipMemcpyAsync(out, pr.first, pr.second, hipMemcpyDeviceToDevice, s));
+    out += pr.second;
+  }
+  for (int i = 0; i < h->n_inst; ++i) {
+    const size_t b = (size_t)c0_doubles(h, i) * sizeof(double);
+    if (b) HIPCHK(h, hipMemcpyAsync(out, c0_ptr(h, i), b, hipMemcpyDeviceToDevice, s));
+    out += b;
+  }
+  HIPCHK(h, hipStreamSynchronize(s));  // the header is copied from this stack frame
+  return ETDM_OK;
+}
+
+etdm_status etdm_lbfgs_set_state(etdm_handle* h, const void* state, void* stream) {
+  if (!h) return ETDM_E_ARG;
+  if (!state) return fail(h, ETDM_E_ARG, "null state buffer");
+  hipStream_t s = S(stream);
+  LbCheckpoint hd{};
+  const char* in = static_cast<const char*>(state);
+  HIPCHK(h, hipMemcpyAsync(&hd, in, sizeof(hd), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  int64_t c0 = 0;
+  for (int i = 0; i < h->n_inst; ++i) c0 += c0_doubles(h, i);
+  if (std::memcmp(hd.magic, kCkptMagic, 8) != 0) return fail(h, ETDM_E_ARG, "not an L-BFGS checkpoint");
+  if (hd.layout != ckpt_layout(h) || hd.n_param != h->n_param || hd.c0_doubles != c0)
+    return fail(h, ETDM_E_SHAPE, "checkpoint from a handle with other shapes or modes");
+  if (hd.m < 1 || hd.m > LB_MMAX || hd.lbp.m != hd.m) return fail(h, ETDM_E_ARG, "corrupt checkpoint header");
+  if (!h->lb_sum) HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&h->lb_sum), sizeof(LbState)));
+  const int64_t n = h->n_param;
+  const size_t vb = (size_t)n * sizeof(double);
+  in += LB_CKPT_HEADER;
+  HIPCHK(h, hipMemcpyAsync(h->lb_st, in, sizeof(LbState), hipMemcpyDeviceToDevice, s));
+  in += state_scalars_bytes();
+  const std::pair<double*, size_t> parts[] = {{h->x, vb}, {h->g, vb}, {h->S, vb * hd.m}, {h->Yv, vb * hd.m}};
+  for (const auto& pr : parts) {
+    if (pr.second) HIPCHK(h, hipMemcpyAsync(pr.first, in, pr.second, hipMemcpyDeviceToDevice, s));
+    in += pr.second;
+  }
+  for (int i = 0; i < h->n_inst; ++i) {
+    const size_t b = (size_t)c0_doubles(h, i) * sizeof(double);
+    if (b) HIPCHK(h, hipMemcpyAsync(c0_ptr(h, i), in, b, hipMemcpyDeviceToDevice, s));
+    in += b;
+  }
+  build_hdiag(h, s);  // preconditioner (and H0 C0) of the restored reference orbitals
+  HIPCHK(h, hipMemcpyAsync(h->lb_sum, h->lb_st, sizeof(LbState), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(s));
+  free_lb_graphs(h);
+  h->lbp = hd.lbp;
+  h->lbp_set = true;
+  h->lb_iter = hd.iter;
+  h->lb_evals = hd.evals;
+  h->lb_init = true;
+  return ETDM_OK;
+}
+
 etdm_status etdm_lbfgs_step(etdm_handle* h, const etdm_lbfgs_params* params, void* A, double* E, void* G,
                             etdm_lbfgs_info* info, void* stream) {
   if (!h) return ETDM_E_ARG;
@@ -1902,74 +1989,43 @@ etdm_status etdm_lbfgs_step(etdm_handle* h, const etdm_lbfgs_params* params, voi
   const int64_t n = h->n_param;
   const size_t pb = (size_t)n * sizeof(double);
   std::memset(info, 0, sizeof(*info));
+  if (!h->lb_sum) HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&h->lb_sum), sizeof(LbState)));
+  const LbParams lp{P.c1, P.c2, P.delta, P.sigma, P.eps, P.gamma, P.max_ls, P.m};
+  const bool m_changed = h->lbp_set && h->lbp.m != lp.m;
+  if (!h->lbp_set || std::memcmp(&lp, &h->lbp, sizeof(lp)) != 0) {
+    free_lb_graphs(h);  // the constants are part of the captured launches
+    h->lbp = lp;
+    h->lbp_set = true;
+  }
   if (!h->lb_init) {
     if (pb) HIPCHK(h, hipMemcpyAsync(h->x, A, pb, hipMemcpyDeviceToDevice, s));
     h->lb_iter = 0;
     h->lb_evals = 0;
-    h->lb_beta = P.beta0;
-    CHECK(lb_initialise(h, P, s));
+    CHECK(lb_start(h, P.beta0, 1, s));
     h->lb_init = true;
   } else if (P.reset_every > 0 && h->lb_iter > 0 && h->lb_iter % P.reset_every == 0) {
-    // reference reset (Sec. 3.4): C0 <- C0 exp(A), A <- 0, memory erased
+    // reference reset (Sec. 3.4): C0 <- C0 exp(A), A <- 0, memory erased, beta kept
     HIPCHK(h, hipMemcpyAsync(h->par_ws, h->x, pb, hipMemcpyDeviceToDevice, s));
     new_reference(h, s);
     launch_fill(h->x, n, 0.0, s);
-    CHECK(lb_initialise(h, P, s));
+    CHECK(lb_start(h, P.beta0, 0, s));
     info->flags |= 1;
+  } else if (m_changed) {
+    CHECK(lb_start(h, P.beta0, 0, s));  // a new memory length starts an empty memory
   }
-  h->lb_m = std::min(std::max(P.m, 1), LB_MMAX);
-  if (h->lb_count > h->lb_m) h->lb_count = h->lb_m;
-  double dphi0 = 0.0;
-  lb_direction(h, P.gamma, s);
-  launch_dot(h->g, h->p, n, h->partial, h->sc + SC_DPHI, s);
-  HIPCHK(h, hipMemcpy(&dphi0, h->sc + SC_DPHI, sizeof(double), hipMemcpyDeviceToHost));
-  if (!(dphi0 < 0.0)) {
-    h->lb_count = 0;
-    lb_steepest(h, P.gamma, s);
-    launch_dot(h->g, h->p, n, h->partial, h->sc + SC_DPHI, s);
-    HIPCHK(h, hipMemcpy(&dphi0, h->sc + SC_DPHI, sizeof(double), hipMemcpyDeviceToHost));
+  CHECK(lb_search(h, 0, s));
+  if (h->lb_sum->steepest) info->flags |= 2;
+  if (h->lb_sum->result == LR_FAIL) {
     info->flags |= 2;
-  }
-  double alpha = 0.0, f_new = h->lb_E;
-  bool ok = false;
-  CHECK(lb_line_search(h, P, h->lb_E, dphi0, alpha, f_new, ok, s));
-  if (!ok) {
-    h->lb_count = 0;
-    lb_steepest(h, P.gamma, s);
-    launch_dot(h->g, h->p, n, h->partial, h->sc + SC_DPHI, s);
-    HIPCHK(h, hipMemcpy(&dphi0, h->sc + SC_DPHI, sizeof(double), hipMemcpyDeviceToHost));
-    info->flags |= 2;
-    CHECK(lb_line_search(h, P, h->lb_E, dphi0, alpha, f_new, ok, s));
-    if (!ok) {
+    CHECK(lb_search(h, 2, s));
+    if (h->lb_sum->result != LR_ACCEPT) {
       info->flags |= 4;
       info->iter = h->lb_iter;
       info->n_evals = h->lb_evals;
-      info->E = h->lb_E;
+      info->E = h->lb_sum->E;
       return fail(h, ETDM_E_LINESEARCH, "no acceptable step along the search direction");
     }
   }
-  // memory update: s = xt - x, y = gt - g, beta = |y|^2 / (s.y) when s.y > 0
-  const int slot_i = h->lb_head;
-  double* Sn = slot(h->S, n, slot_i);
-  double* Yn = slot(h->Yv, n, slot_i);
-  HIPCHK(h, hipMemcpyAsync(Sn, h->xt, pb, hipMemcpyDeviceToDevice, s));
-  launch_axpby(Sn, h->x, n, 1.0, nullptr, -1.0, nullptr, s);
-  HIPCHK(h, hipMemcpyAsync(Yn, h->gt, pb, hipMemcpyDeviceToDevice, s));
-  launch_axpby(Yn, h->g, n, 1.0, nullptr, -1.0, nullptr, s);
-  launch_dot(Sn, Yn, n, h->partial, h->sc + SC_SY, s);
-  launch_dot(Yn, Yn, n, h->partial, h->sc + SC_YY, s);
-  launch_dot(h->gt, h->gt, n, h->partial, h->sc + SC_GG, s);
-  double v[8];
-  HIPCHK(h, hipMemcpy(v, h->sc, sizeof(v), hipMemcpyDeviceToHost));
-  if (v[SC_SY] > 0.0) {
-    HIPCHK(h, hipMemcpyAsync(h->sc + SC_YS0 + slot_i, h->sc + SC_SY, sizeof(double), hipMemcpyDeviceToDevice, s));
-    h->lb_head = (h->lb_head + 1) % h->lb_m;
-    h->lb_count = std::min(h->lb_count + 1, h->lb_m);
-    h->lb_beta = v[SC_YY] / v[SC_SY];
-  }
-  std::swap(h->x, h->xt);
-  std::swap(h->g, h->gt);
-  h->lb_E = f_new;
   ++h->lb_iter;
   if (pb) {
     HIPCHK(h, hipMemcpyAsync(A, h->x, pb, hipMemcpyDeviceToDevice, s));
@@ -1977,11 +2033,12 @@ etdm_status etdm_lbfgs_step(etdm_handle* h, const etdm_lbfgs_params* params, voi
   }
   HIPCHK(h, hipMemcpyAsync(E, h->E_ws, (h->n_inst + 1) * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipStreamSynchronize(s));
+  const LbState& r = *h->lb_sum;
   info->iter = h->lb_iter;
   info->n_evals = h->lb_evals;
-  info->alpha = alpha;
-  info->E = f_new;
-  info->gnorm = std::sqrt(std::max(v[SC_GG], 0.0));
+  info->alpha = r.acc_a;
+  info->E = r.acc_f;
+  info->gnorm = std::sqrt(std::max(r.gg, 0.0));
   return ETDM_OK;
 }
 

@@ -7,6 +7,7 @@
 //   Y = V ((V^H L V) o D) V^H,  D_pq = int_0^1 exp(-i t (w_p - w_q)) dt
 //   G_ij = dE/dRe a_ij + i dE/dIm a_ij = -(2 - delta_ij) Y_ij  (i <= j)   Eq. gradients
 #include "ov.h"
+#include "reduce.h"
 
 namespace etdm {
 
@@ -117,35 +118,6 @@ __global__ __launch_bounds__(256) void z_apply_hubbard_kernel(const ZInst* __res
   }
 }
 
-__device__ __forceinline__ void zneumaier(double& s, double& c, double x) {
-  double t = s + x;
-  c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
-  s = t;
-}
-
-__device__ double zblock_sum(double s, double c, double* red) {
-  for (int o = 32; o > 0; o >>= 1) {
-    double s2 = __shfl_xor(s, o), c2 = __shfl_xor(c, o);
-    double t = s + s2;
-    c += c2 + ((fabs(s) >= fabs(s2)) ? (s - t) + s2 : (s2 - t) + s);
-    s = t;
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) {
-    red[2 * wave] = s;
-    red[2 * wave + 1] = c;
-  }
-  __syncthreads();
-  double S = 0.0, Cc = 0.0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-    double x = red[2 * w], t = S + x;
-    Cc += ((fabs(S) >= fabs(x)) ? (S - t) + x : (x - t) + S) + red[2 * w + 1];
-    S = t;
-  }
-  return S + Cc;
-}
-
 // E_k = w_k sum_mu e_mu (+ (U/2) sum d^2 for independent instances)
 __global__ __launch_bounds__(256) void z_energy_kernel(const ZInst* __restrict__ zi, int couple, double U,
                                                        double* E) {
@@ -153,11 +125,11 @@ __global__ __launch_bounds__(256) void z_energy_kernel(const ZInst* __restrict__
   const ZInst& z = zi[blockIdx.x];
   double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
   for (int mu = threadIdx.x; mu < z.M; mu += blockDim.x) {
-    zneumaier(s1, c1, z.e[mu]);
-    if (!couple) zneumaier(s2, c2, z.d[mu] * z.d[mu]);
+    neumaier_add(s1, c1, z.e[mu]);
+    if (!couple) neumaier_add(s2, c2, z.d[mu] * z.d[mu]);
   }
-  const double band = zblock_sum(s1, c1, red);
-  const double hub = zblock_sum(s2, c2, red);
+  const double band = block_sum_neumaier(s1, c1, red);
+  const double hub = block_sum_neumaier(s2, c2, red);
   if (threadIdx.x == 0) E[blockIdx.x] = z.weight * band + (couple ? 0.0 : 0.5 * U * hub);
 }
 
@@ -245,47 +217,8 @@ void launch_z_grad(const ZInst* d, const int* b, int n, int total, int* status, 
 }
 
 // ---------------------------------------------------------------------------
-// L-BFGS vector kernels (FP64)
+// Preconditioner set-up of the L-BFGS driver (FP64)
 // ---------------------------------------------------------------------------
-constexpr int DOT_BLOCKS = 512;
-
-__global__ __launch_bounds__(256) void dot_partial_kernel(const double* __restrict__ x,
-                                                          const double* __restrict__ y, int64_t n,
-                                                          double* partial) {
-  __shared__ double red[16];
-  double s = 0.0, c = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    zneumaier(s, c, x[i] * y[i]);
-  double t = zblock_sum(s, c, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
-}
-
-__global__ __launch_bounds__(256) void dot_final_kernel(const double* partial, int nb, double* out) {
-  __shared__ double red[16];
-  double s = 0.0, c = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) zneumaier(s, c, partial[i]);
-  double t = zblock_sum(s, c, red);
-  if (threadIdx.x == 0) *out = t;
-}
-
-__global__ void axpby_kernel(double* y, const double* x, int64_t n, double ca, const double* pa, double cb,
-                             const double* pb) {
-  const double a = ca * (pa ? *pa : 1.0), b = cb * (pb ? *pb : 1.0);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = (a == 0.0 ? 0.0 : a * y[i]) + (b == 0.0 ? 0.0 : b * x[i]);
-}
-
-__global__ void scalar_ratio_kernel(double* out, const double* num, const double* den, double c) {
-  *out = c * (*num) / (*den);
-}
-__global__ void scalar_sub_kernel(double* out, const double* a, const double* b) { *out = *a - *b; }
-
-__global__ void precond_kernel(double* r, const double* q, const double* h, const double* w, int64_t n,
-                               double gamma, double beta) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    r[i] = q[i] / ((1.0 - gamma) * h[i] + gamma * beta * w[i]);
-}
-
 __global__ void hdiag_ov_kernel(double* h, const double* eps, const double* f, int M, int N, double w) {
   const int Nv = M - N;
   int64_t total = (int64_t)N * Nv;
@@ -367,24 +300,6 @@ __global__ void weighted_vsum_kernel(const double* const* xs, const double* ws, 
 
 static inline int vgrid(int64_t n) { return (int)std::min<int64_t>(2048, std::max<int64_t>(1, (n + 255) / 256)); }
 
-void launch_dot(const double* x, const double* y, int64_t n, double* partial, double* out, hipStream_t s) {
-  dot_partial_kernel<<<DOT_BLOCKS, 256, 0, s>>>(x, y, n, partial);
-  dot_final_kernel<<<1, 256, 0, s>>>(partial, DOT_BLOCKS, out);
-}
-void launch_axpby(double* y, const double* x, int64_t n, double ca, const double* pa, double cb,
-                  const double* pb, hipStream_t s) {
-  if (n > 0) axpby_kernel<<<vgrid(n), 256, 0, s>>>(y, x, n, ca, pa, cb, pb);
-}
-void launch_scalar_ratio(double* out, const double* num, const double* den, double c, hipStream_t s) {
-  scalar_ratio_kernel<<<1, 1, 0, s>>>(out, num, den, c);
-}
-void launch_scalar_sub(double* out, const double* a, const double* b, hipStream_t s) {
-  scalar_sub_kernel<<<1, 1, 0, s>>>(out, a, b);
-}
-void launch_precond(double* r, const double* q, const double* h, const double* w, int64_t n, double gamma,
-                    double beta, hipStream_t s) {
-  if (n > 0) precond_kernel<<<vgrid(n), 256, 0, s>>>(r, q, h, w, n, gamma, beta);
-}
 void launch_hdiag_ov(double* h, const double* eps, const double* f, int M, int N, double w, hipStream_t s) {
   int64_t n = (int64_t)N * (M - N);
   if (n > 0) hdiag_ov_kernel<<<vgrid(n), 256, 0, s>>>(h, eps, f, M, N, w);

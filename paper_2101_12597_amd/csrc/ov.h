@@ -103,19 +103,8 @@ void launch_z_divdiff(const ZInst* d, const int* d_begin, int n_inst, int total,
 void launch_z_grad(const ZInst* d, const int* d_begin, int n_inst, int total, int* status, hipStream_t s);
 
 // ---------------------------------------------------------------------------
-// FP64 vector kernels of the L-BFGS driver (device-resident scalars)
+// Preconditioner set-up of the L-BFGS driver (FP64)
 // ---------------------------------------------------------------------------
-void launch_dot(const double* x, const double* y, int64_t n, double* partial, double* out, hipStream_t s);
-// y = a*y + b*x with a, b = ca * (*pa or 1) and cb * (*pb or 1)
-void launch_axpby(double* y, const double* x, int64_t n, double ca, const double* pa, double cb,
-                  const double* pb, hipStream_t s);
-// out = c * num / den  (device scalars)
-void launch_scalar_ratio(double* out, const double* num, const double* den, double c, hipStream_t s);
-// out = a - b
-void launch_scalar_sub(double* out, const double* a, const double* b, hipStream_t s);
-// r = q / ((1 - gamma) h + gamma beta w)   (Eq. prec_3 applied as a diagonal)
-void launch_precond(double* r, const double* q, const double* h, const double* w, int64_t n, double gamma,
-                    double beta, hipStream_t s);
 // h = w * max(0, -2 (eps_i - eps_j)(f_i - f_j)) over the free variables (REAL_OV layout)
 void launch_hdiag_ov(double* h, const double* eps, const double* f, int M, int N, double w, hipStream_t s);
 // same for the complex layout (interleaved: Re part for i < j, Im part for i <= j, 0 elsewhere)

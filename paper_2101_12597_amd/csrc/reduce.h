@@ -1,0 +1,40 @@
+// Compensated (Neumaier) summation for the FP64 reductions: a running sum and
+// its correction term, combined across a wavefront by butterfly shuffles and
+// across the waves of a workgroup in a fixed order, so a reduction gives the same
+// bits on every run.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace etdm {
+
+__device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
+  double t = s + x;
+  c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+  s = t;
+}
+
+__device__ inline double block_sum_neumaier(double s, double c, double* red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    double s2 = __shfl_xor(s, o), c2 = __shfl_xor(c, o);
+    double t = s + s2;
+    c += c2 + ((fabs(s) >= fabs(s2)) ? (s - t) + s2 : (s2 - t) + s);
+    s = t;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) {
+    red[2 * wave] = s;
+    red[2 * wave + 1] = c;
+  }
+  __syncthreads();
+  double S = 0.0, Cc = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    double x = red[2 * w], t = S + x;
+    Cc += ((fabs(S) >= fabs(x)) ? (S - t) + x : (x - t) + S) + red[2 * w + 1];
+    S = t;
+  }
+  return S + Cc;
+}
+
+}  // namespace etdm

@@ -108,6 +108,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.etdm_lbfgs_step.argtypes = [vp, ctypes.POINTER(LbfgsParams), vp, vp, vp,
                                   ctypes.POINTER(LbfgsInfo), vp]
     L.etdm_lbfgs_step.restype = i32
+    L.etdm_lbfgs_state_bytes.argtypes = [vp]
+    L.etdm_lbfgs_state_bytes.restype = ctypes.c_size_t
+    L.etdm_lbfgs_get_state.argtypes = [vp, vp, vp]
+    L.etdm_lbfgs_get_state.restype = i32
+    L.etdm_lbfgs_set_state.argtypes = [vp, vp, vp]
+    L.etdm_lbfgs_set_state.restype = i32
     L.etdm_sync_status.argtypes = [vp, vp]
     L.etdm_sync_status.restype = i32
     L.etdm_status_string.argtypes = [i32]
@@ -254,6 +260,32 @@ class Handle:
         self._check(st, "etdm_lbfgs_step")
         return dict(iter=info.iter, n_evals=info.n_evals, alpha=info.alpha, E=info.E,
                     gnorm=info.gnorm, flags=info.flags)
+
+    def lbfgs_state_bytes(self) -> int:
+        """Size of the L-BFGS checkpoint image (0 before the first lbfgs_step)."""
+        return int(self._L.etdm_lbfgs_state_bytes(self._h))
+
+    def lbfgs_get_state(self, buf, stream=None):
+        """Write the L-BFGS checkpoint into `buf`, a device uint8 tensor of
+        lbfgs_state_bytes() bytes."""
+        self._check_state_buffer(buf)
+        self._check(self._L.etdm_lbfgs_get_state(self._h, _dptr(buf), _stream_ptr(stream)),
+                    "etdm_lbfgs_get_state")
+
+    def lbfgs_set_state(self, buf, stream=None):
+        """Restore the L-BFGS run saved by lbfgs_get_state (same shapes and modes)."""
+        self._check_state_buffer(buf)
+        self._check(self._L.etdm_lbfgs_set_state(self._h, _dptr(buf), _stream_ptr(stream)),
+                    "etdm_lbfgs_set_state")
+
+    def _check_state_buffer(self, buf):
+        import torch
+        if not (isinstance(buf, torch.Tensor) and buf.is_cuda and buf.dtype == torch.uint8
+                and buf.is_contiguous()):
+            raise TypeError("the state buffer must be a contiguous uint8 tensor on the GPU")
+        need = self.lbfgs_state_bytes()
+        if need and buf.numel() < need:
+            raise ValueError(f"state buffer holds {buf.numel()} bytes, {need} needed")
 
     def set_graph(self, enable: bool = True):
         """Replay the energy+gradient launch sequence from a captured HIP graph."""

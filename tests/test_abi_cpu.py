@@ -11,14 +11,15 @@ import pytest
 def declared_symbols(root):
     text = open(os.path.join(root, "include", "etdm.h")).read()
     # function declarations: a return type at the start of a line, then the name
-    pat = r"^(?:const\s+)?(?:void|int64_t|char|etdm_status)\s*\*?\s*(etdm_[a-z_]+)\s*\("
+    pat = r"^(?:const\s+)?(?:void|int64_t|size_t|char|etdm_status)\s*\*?\s*(etdm_[a-z_]+)\s*\("
     return sorted(set(re.findall(pat, text, flags=re.M)))
 
 
 def test_header_declares_expected_entry_points(repo_root):
     syms = declared_symbols(repo_root)
     for s in ["etdm_create", "etdm_destroy", "etdm_expm", "etdm_energy_grad", "etdm_lbfgs_step",
-              "etdm_set_reference", "etdm_sync_status", "etdm_status_string", "etdm_last_error"]:
+              "etdm_set_reference", "etdm_sync_status", "etdm_status_string", "etdm_last_error",
+              "etdm_lbfgs_state_bytes", "etdm_lbfgs_get_state", "etdm_lbfgs_set_state"]:
         assert s in syms
 
 
@@ -46,6 +47,9 @@ def test_host_only_calls(repo_root):
     assert lib.etdm_energy_grad(None, None, None, None, None) == -1
     assert lib.etdm_destroy(None) == -1
     assert lib.etdm_param_count(None) == 0
+    assert lib.etdm_lbfgs_state_bytes(None) == 0
+    assert lib.etdm_lbfgs_get_state(None, None, None) == -1
+    assert lib.etdm_lbfgs_set_state(None, None, None) == -1
 
 
 @pytest.mark.parametrize("field,bad", [("gemm_tuning", -1), ("gemm_tuning", 7), ("gradient", -1),

@@ -1,0 +1,238 @@
+"""The device-resident L-BFGS iteration (etdm_lbfgs_step): its trajectory against
+the oracle's minimizer, graph replay against eager launches, checkpoint and
+resume, and the line-search failure path forced from the host.
+
+The oracle and the device take the same decisions (Wolfe tests, cubic steps,
+memory updates) in FP64; each GPU iteration is compared with the oracle's step
+from the same state.
+"""
+import numpy as np
+import pytest
+
+from oracle import etdm as O
+from oracle import lbfgs as LB
+from workloads import make_config, tiny_complex, tiny_real
+from workloads.pack import unpack_params
+
+from gpu_helpers import make_handle
+
+pytestmark = pytest.mark.gpu
+
+
+def _tensors(h):
+    import torch
+    dev = torch.device("cuda:0")
+    A = torch.zeros(h.n_param, dtype=torch.float64, device=dev)
+    E = torch.empty(h.n_inst + 1, dtype=torch.float64, device=dev)
+    G = torch.empty_like(A)
+    return A, E, G
+
+
+def _params(**kw):
+    from paper_2101_12597_amd import lbfgs_defaults
+    p = lbfgs_defaults()
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _run(h, A, E, G, iters, params=None):
+    """Per iteration: (info, A copy, E copy) as host arrays."""
+    out = []
+    for _ in range(iters):
+        info = h.lbfgs_step(A, E, G, params)
+        out.append((info, A.cpu().numpy().copy(), E.cpu().numpy().copy()))
+    return out
+
+
+def _workload(which):
+    if which == "config1":
+        return make_config(1)
+    if which == "tiny_real":
+        return tiny_real(24, 7, seed=5, scale=0.0)
+    return tiny_complex(8, nk_side=2, kT=0.3)
+
+
+def _flat(wl, vec):
+    """GPU parameter vector -> the oracle's flat layout (free variables only)."""
+    return O.flatten(wl.kind, unpack_params(wl, vec))
+
+
+def _oracle_step(fun, x, f, g, beta, S, Y, hdiag, wvec, cfg):
+    st = LB.LbfgsState(x=x.copy(), f=f, g=g.copy(), beta=beta, S=list(S), Y=list(Y))
+    st, info = LB.lbfgs_step(fun, st, hdiag, wvec, cfg)
+    return st, info
+
+
+@pytest.mark.parametrize("which", ["config1", "tiny_real", "tiny_complex"])
+def test_each_step_matches_oracle_from_the_same_state(which):
+    """Every GPU iteration against the oracle's lbfgs_step from the state the GPU
+    reached (x, g, E, the stored pairs and beta, rebuilt from the GPU's outputs).
+
+    * The accepted point satisfies strong Wolfe, or approximate Wolfe with the
+      energy condition, along the GPU's own direction (x_new - x) / alpha.
+    * Same fallbacks; same evaluation count and step within 1e-6 relative, widened
+      by the oracle's own spread when its inputs move by 1e-12 relative: a cubic
+      step through nearly equal energies amplifies rounding, so in ill-conditioned
+      searches (tiny steps) rounding alone changes the result, and whole
+      trajectories drift apart and are not compared.
+    * The returned (A, E, G) matches the oracle's E and gradient at that A."""
+    iters = 15
+    wl = _workload(which)
+    print(f"[case] device L-BFGS steps vs oracle {which}", flush=True)
+    h, _ = make_handle(wl, "fp64", gemm_tuning=1)
+    A, E, G = _tensors(h)
+    gpu = []
+    for _ in range(iters):
+        info = h.lbfgs_step(A, E, G)
+        gpu.append((info, A.cpu().numpy().copy(), E.cpu().numpy().copy(), G.cpu().numpy().copy()))
+    h.close()
+    assert not any(i["flags"] & 1 for i, *_ in gpu)  # no reference reset inside the window
+    kind = wl.kind
+    rng = np.random.default_rng(7)
+
+    def fun(v, noise=0.0):
+        e, gs = O.energy_grad(wl, O.unflatten(kind, wl, v))
+        gv = O.flatten(kind, gs)
+        if noise:
+            e *= 1.0 + noise * rng.standard_normal()
+            gv = gv * (1.0 + noise * rng.standard_normal(gv.size))
+        return e, gv
+
+    cfg = LB.LbfgsConfig()
+    hdiag = LB.hessian_diagonal(wl, O.orbital_energies(wl))
+    wvec = LB.weight_vector(wl)
+    x = O.flatten(kind, O.zero_params(wl))
+    f, g = fun(x)
+    beta, S, Y = cfg.beta0, [], []
+    evals_before = 1
+    for k, (info, a_k, e_k, g_k) in enumerate(gpu):
+        x_new, g_new = _flat(wl, a_k), _flat(wl, g_k)
+        f_new, alpha = float(e_k[-1]), info["alpha"]
+        n_ev = info["n_evals"] - evals_before
+        # acceptance conditions of the step the GPU took
+        p = (x_new - x) / alpha
+        d0, d1 = float(np.dot(g, p)), float(np.dot(g_new, p))
+        strong = f_new <= f + cfg.c1 * alpha * d0 + 1e-12 * abs(f) and abs(d1) <= cfg.c2 * abs(d0) * (1 + 1e-9)
+        approx = ((2 * cfg.delta - 1) * d0 >= d1 - 1e-9 * abs(d0) and d1 >= cfg.sigma * d0 - 1e-9 * abs(d0)
+                  and f_new <= f + cfg.eps * abs(f) + 1e-12 * abs(f))
+        assert d0 < 0.0, k
+        assert strong or approx or n_ev >= cfg.max_ls, (k, info)
+        # the oracle from the same state, plain and with perturbed inputs
+        st, ref = _oracle_step(fun, x, f, g, beta, S, Y, hdiag, wvec, cfg)
+        _, pert = _oracle_step(lambda v: fun(v, 1e-12), x, f, g, beta, S, Y, hdiag, wvec, cfg)
+        assert not ref["failed"]
+        assert bool(info["flags"] & 2) == ref["fallback"], (k, info, ref)
+        spread = abs(pert["alpha"] - ref["alpha"]) / abs(ref["alpha"])
+        if pert["evals"] == ref["evals"]:
+            assert n_ev == ref["evals"], (k, info, ref)
+        assert abs(alpha - ref["alpha"]) <= (1e-6 + 1e3 * spread) * abs(ref["alpha"]), (k, info, ref, spread)
+        # the returned point: E and gradient of the oracle at the GPU's A
+        e_ref, g_ref = fun(x_new)
+        assert abs(f_new - e_ref) <= 1e-12 * max(1.0, abs(e_ref)), k
+        assert np.linalg.norm(g_new - g_ref) <= 1e-10 * max(1.0, np.linalg.norm(g_ref)), k
+        # the state the GPU continues from
+        if ref["fallback"]:
+            S, Y = [], []
+        s_k, y_k = x_new - x, g_new - g
+        if np.dot(s_k, y_k) > 0.0:
+            S, Y = (S + [s_k])[-cfg.m:], (Y + [y_k])[-cfg.m:]
+            beta = float(np.dot(y_k, y_k)) / float(np.dot(s_k, y_k))
+        x, f, g = x_new, f_new, g_new
+        evals_before = info["n_evals"]
+
+
+@pytest.mark.parametrize("which,precision", [("config1", "fp64"), ("config3", "mixed"), ("tiny_complex", "fp64")])
+def test_graph_replay_matches_eager(which, precision):
+    """The captured probes (one graph each; two around the large solver's fallback
+    for config 3) give the eager trajectory bit for bit."""
+    wl = make_config(3) if which == "config3" else _workload(which)
+    print(f"[case] device L-BFGS graph vs eager {which} {precision}", flush=True)
+    runs = []
+    for graph in (False, True):
+        h, _ = make_handle(wl, precision, use_bsr=which == "config3", gemm_tuning=1)
+        h.set_graph(graph)
+        A, E, G = _tensors(h)
+        runs.append(_run(h, A, E, G, 6, _params(reset_every=4)))
+        h.close()
+    for (i0, a0, e0), (i1, a1, e1) in zip(*runs):
+        assert i0 == i1
+        assert np.array_equal(a0, a1) and np.array_equal(e0, e1)
+
+
+@pytest.mark.parametrize("which,precision", [("config1", "fp64"), ("config2", "mixed"), ("tiny_complex", "fp64")])
+def test_checkpoint_resume_is_bitwise(which, precision):
+    """get_state after 4 iterations; the next 5 (crossing reference resets every 3
+    iterations) are repeated bit for bit after set_state, on the same handle and on
+    a fresh one."""
+    import torch
+    wl = make_config(2) if which == "config2" else _workload(which)
+    prm = _params(reset_every=3)
+    print(f"[case] L-BFGS checkpoint {which} {precision}", flush=True)
+    h, _ = make_handle(wl, precision, gemm_tuning=1)
+    h.set_graph(True)
+    A, E, G = _tensors(h)
+    _run(h, A, E, G, 4, prm)
+    nbytes = h.lbfgs_state_bytes()
+    assert nbytes > 0
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    h.lbfgs_get_state(buf)
+    ref = _run(h, A, E, G, 5, prm)
+    assert any(r[0]["flags"] & 1 for r in ref)  # a reference reset happens after the checkpoint
+    h.lbfgs_set_state(buf)
+    again = _run(h, A, E, G, 5, prm)
+    h.close()
+    h2, _ = make_handle(wl, precision, gemm_tuning=1)
+    h2.lbfgs_set_state(buf)
+    A2, E2, G2 = _tensors(h2)
+    fresh = _run(h2, A2, E2, G2, 5, prm)
+    h2.close()
+    for run in (again, fresh):
+        for (i0, a0, e0), (i1, a1, e1) in zip(ref, run):
+            assert i0 == i1
+            assert np.array_equal(a0, a1) and np.array_equal(e0, e1)
+
+
+def test_checkpoint_rejects_other_shapes():
+    import torch
+    from paper_2101_12597_amd import EtdmError
+    print("[case] L-BFGS checkpoint shape check", flush=True)
+    h, _ = make_handle(_workload("tiny_real"), "fp64", gemm_tuning=1)
+    A, E, G = _tensors(h)
+    with pytest.raises(EtdmError):
+        h.lbfgs_get_state(torch.empty(16, dtype=torch.uint8, device="cuda:0"))
+    _run(h, A, E, G, 2)
+    buf = torch.empty(h.lbfgs_state_bytes(), dtype=torch.uint8, device="cuda:0")
+    h.lbfgs_get_state(buf)
+    h.close()
+    other, _ = make_handle(tiny_real(25, 7, seed=5, scale=0.0), "fp64", gemm_tuning=1)
+    with pytest.raises(EtdmError) as e:
+        other.lbfgs_set_state(buf)
+    assert e.value.code == -2  # ETDM_E_SHAPE
+    other.close()
+
+
+def test_line_search_failure_forced_from_the_host():
+    """With an empty memory the direction is preconditioned steepest descent, and
+    with gamma = 1, beta0 = 1e-3 its unit step (checked with the oracle) raises the
+    energy of config 1.  One probe allowed: both the L-BFGS and the restarted
+    steepest-descent searches fail and the state is left unchanged; with the
+    usual probe budget the same iteration then succeeds."""
+    from paper_2101_12597_amd import EtdmError
+    wl = _workload("config1")
+    zero = O.zero_params(wl)
+    E0, g0 = O.energy_grad(wl, zero)
+    P = LB.preconditioner(LB.hessian_diagonal(wl, O.orbital_energies(wl)), LB.weight_vector(wl), 1e-3, 1.0)
+    step = -P * O.flatten(wl.kind, g0)
+    assert O.energy(wl, O.unflatten(wl.kind, wl, step)) > E0 + 1.0
+    print("[case] L-BFGS forced line-search failure", flush=True)
+    h, _ = make_handle(wl, "fp64", gemm_tuning=1)
+    A, E, G = _tensors(h)
+    with pytest.raises(EtdmError) as e:
+        h.lbfgs_step(A, E, G, _params(max_ls=1, gamma=1.0, beta0=1e-3))
+    assert e.value.code == -7  # ETDM_E_LINESEARCH
+    assert not A.any().item()
+    info = h.lbfgs_step(A, E, G, _params(gamma=1.0, beta0=1e-3))
+    assert info["iter"] == 1 and info["n_evals"] > 3
+    assert info["E"] < E0
+    h.close()
