@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--lbfgs-iters", type=int, default=0, help="also time this many L-BFGS iterations")
+    ap.add_argument("--lbfgs-reset-norm", type=float, default=0.0,
+                    help="L-BFGS: also reset the reference orbitals when an instance's |A| exceeds this")
     ap.add_argument("--gemm-tuning", type=int, default=0, choices=range(7),
                     help="GEMM kernel choice: 0 tuned at creation, 1 size rule, 2 packed 128x128, "
                          "3 grouped 64x64, 4 packed 64x64, 5 packed 128x64, 6 packed 64x128")
@@ -306,17 +308,22 @@ def main():
     if args.lbfgs_iters > 0:
         log("L-BFGS iterations")
         # full L-BFGS iterations from A = 0 (direction, line search, memory update)
+        from paper_2101_12597_amd import lbfgs_defaults
+        lp = lbfgs_defaults()
+        lp.reset_norm = args.lbfgs_reset_norm
         h.set_graph(True)
         A0 = torch.zeros_like(A)
-        info = h.lbfgs_step(A0, E, G)  # initialisation + first iteration
+        info = h.lbfgs_step(A0, E, G, lp)  # initialisation + first iteration
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        infos = [h.lbfgs_step(A0, E, G) for _ in range(args.lbfgs_iters)]
+        infos = [h.lbfgs_step(A0, E, G, lp) for _ in range(args.lbfgs_iters)]
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.lbfgs_iters
         out["lbfgs"] = {"ms_per_iteration": dt * 1e3, "iterations": args.lbfgs_iters,
                         "evals_per_iteration": (infos[-1]["n_evals"] - info["n_evals"]) / args.lbfgs_iters,
-                        "E": infos[-1]["E"], "gnorm": infos[-1]["gnorm"]}
+                        "E": infos[-1]["E"], "gnorm": infos[-1]["gnorm"],
+                        "reset_norm": args.lbfgs_reset_norm,
+                        "resets": sum(1 for i in infos if i["flags"] & 1)}
         h.set_graph(False)
     if not args.no_cpu_baseline:
         reps, total = 1, t_oracle

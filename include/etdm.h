@@ -140,12 +140,15 @@ etdm_status etdm_set_reference(etdm_handle *h, const void *A, void *stream);
 
 /* L-BFGS settings (Sec. 3.1-3.3).  etdm_lbfgs_defaults fills the paper's values:
  * m = 3, c1 = 1e-4, c2 = 0.9, delta = 0.1, sigma = 0.9, eps = 1e-6,
- * gamma = 0.25, beta0 = 1, reset_every = 20, max_ls = 20. */
+ * gamma = 0.25, beta0 = 1, reset_every = 20, max_ls = 20, and reset_norm = 0. */
 typedef struct {
   int32_t m;
   double c1, c2, delta, sigma, eps, gamma, beta0;
   int32_t reset_every; /* reference reset period in iterations, 0 = never */
   int32_t max_ls;      /* energy+gradient evaluations per line search */
+  double reset_norm;   /* also reset the reference when, after a step, some instance's
+                          parameters have a 2-norm above this (Sec. 3.4 suggests resets
+                          once the norm of A exceeds 1); 0 = never */
 } etdm_lbfgs_params;
 
 typedef struct {

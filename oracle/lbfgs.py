@@ -244,12 +244,15 @@ def lbfgs_step(fun, st: LbfgsState, hdiag, wvec, cfg: LbfgsConfig) -> Tuple[Lbfg
     return st, dict(alpha=ls.alpha, failed=False, fallback=fallback, evals=ls.n_evals)
 
 
-def minimize(wl, cfg: Optional[LbfgsConfig] = None, reset_every: int = 20, callback=None):
+def minimize(wl, cfg: Optional[LbfgsConfig] = None, reset_every: int = 20, callback=None,
+             reset_norm: float = 0.0):
     """Minimize E from A = 0 with periodic reference-orbital resets (Sec. 3.4).
 
     Every ``reset_every`` iterations the reference orbitals are replaced by the
     current ones, C0 <- C0 exp(A), A <- 0, and the L-BFGS memory is erased (the
-    paper's choice).  Reading: the orbital energies of the preconditioner are
+    paper's choice).  With ``reset_norm`` > 0 a reset also happens before an
+    iteration whenever some instance's parameters have a 2-norm above it (the
+    paper's suggestion to reset once the norm of A exceeds 1).  Reading: the orbital energies of the preconditioner are
     recomputed from the new reference orbitals ("at the beginning" of each
     cycle) and beta carries over.  ``wl`` is modified in place (its C0).
     Returns (final state, history); the final state's x refers to the last
@@ -270,8 +273,12 @@ def minimize(wl, cfg: Optional[LbfgsConfig] = None, reset_every: int = 20, callb
     history = [dict(E=f, gnorm=float(np.linalg.norm(g)), alpha=0.0, evals=1)]
     total_evals = 1
     total_iter = 0
+    resets = 0
     while np.linalg.norm(st.g) >= cfg.gtol and total_iter < cfg.max_iter:
-        if reset_every and total_iter > 0 and total_iter % reset_every == 0:
+        periodic = reset_every and total_iter > 0 and total_iter % reset_every == 0
+        large = reset_norm > 0.0 and max(np.linalg.norm(a) for a in etdm.unflatten(kind, wl, st.x)) > reset_norm
+        if periodic or large:
+            resets += 1
             reset_reference(wl, etdm.unflatten(kind, wl, st.x))
             x = etdm.flatten(kind, etdm.zero_params(wl))
             f, g = fun(x)
@@ -283,7 +290,7 @@ def minimize(wl, cfg: Optional[LbfgsConfig] = None, reset_every: int = 20, callb
         total_evals += st.n_evals - n_before
         total_iter += 1
         history.append(dict(E=st.f, gnorm=float(np.linalg.norm(st.g)), alpha=info["alpha"],
-                            evals=total_evals))
+                            evals=total_evals, resets=resets))
         if callback:
             callback(st, info)
         if info["failed"]:

@@ -349,6 +349,7 @@ struct etdm_handle {
   bool lbp_set = false;
   LbState* lb_st = nullptr;
   LbState* lb_sum = nullptr;
+  int64_t* d_par_off = nullptr;  // n_inst + 1 parameter offsets (device)
   double *x = nullptr, *g = nullptr, *p = nullptr, *q = nullptr;
   double *hd = nullptr, *wv = nullptr, *S = nullptr, *Yv = nullptr, *partial = nullptr;
   // captured L-BFGS probes: [0] direction + probe, [1] probe, [2] steepest restart + probe;
@@ -567,7 +568,7 @@ size_t plan_buffers(etdm_handle* h, char* base) {
   h->wv = pl.take(np);
   h->S = pl.take(np * LB_MMAX);
   h->Yv = pl.take(np * LB_MMAX);
-  h->partial = pl.take(3 * LB_DOT_BLOCKS);
+  h->partial = pl.take(std::max<int64_t>(3 * LB_DOT_BLOCKS, h->n_inst));
   h->lb_st = reinterpret_cast<LbState*>(pl.take((sizeof(LbState) + 7) / 8));
   return pl.off;
 }
@@ -1436,7 +1437,7 @@ void lb_pre(etdm_handle* h, int which, hipStream_t s) {
 
 void lb_post(etdm_handle* h, hipStream_t s) {
   launch_lb_after_probe(h->lb_st, h->lbp, h->x, h->g, h->p, h->grad_ws, h->E_ws + h->n_inst, h->status, h->S,
-                        h->Yv, h->n_param, h->partial, h->par_ws, h->lb_sum, s);
+                        h->Yv, h->n_param, h->d_par_off, h->n_inst, h->partial, h->par_ws, h->lb_sum, s);
 }
 
 template <int W>
@@ -1554,6 +1555,7 @@ void etdm_lbfgs_defaults(etdm_lbfgs_params* p) {
   p->beta0 = 1.0;
   p->reset_every = 20;
   p->max_ls = 20;
+  p->reset_norm = 0.0;
 }
 
 etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, const void* C0, const double* f,
@@ -1701,6 +1703,11 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
     blk_off += nnzb;
   }
   etdm_status st = real ? build_ov_plan(h) : build_z_plan(h);
+  if (st == ETDM_OK) {
+    std::vector<int64_t> offs(h->par_off);
+    offs.push_back(h->n_param);
+    st = upload(h, &h->d_par_off, offs);
+  }
   if (st == ETDM_OK) st = tune_stages(h, s);
   if (st == ETDM_OK && real && h->h0_format == 0) h->s_HC0.launch(s);  // H0 C0 of the reference
   // the side stream only where Q1 is worth a fork and join (on one small molecule
@@ -1983,14 +1990,15 @@ etdm_status etdm_lbfgs_step(etdm_handle* h, const etdm_lbfgs_params* params, voi
   if (params) P = *params;
   else etdm_lbfgs_defaults(&P);
   if (P.m < 1 || P.m > LB_MMAX || P.max_ls < 1 || !(P.c1 > 0.0) || !(P.c2 > P.c1) || !(P.c2 < 1.0) ||
-      !(P.gamma >= 0.0) || !(P.gamma <= 1.0) || !(P.beta0 > 0.0) || P.reset_every < 0)
+      !(P.gamma >= 0.0) || !(P.gamma <= 1.0) || !(P.beta0 > 0.0) || P.reset_every < 0 ||
+      !(P.reset_norm >= 0.0))
     return fail(h, ETDM_E_ARG, "invalid L-BFGS parameters");
   hipStream_t s = S(stream);
   const int64_t n = h->n_param;
   const size_t pb = (size_t)n * sizeof(double);
   std::memset(info, 0, sizeof(*info));
   if (!h->lb_sum) HIPCHK(h, hipHostMalloc(reinterpret_cast<void**>(&h->lb_sum), sizeof(LbState)));
-  const LbParams lp{P.c1, P.c2, P.delta, P.sigma, P.eps, P.gamma, P.max_ls, P.m};
+  const LbParams lp{P.c1, P.c2, P.delta, P.sigma, P.eps, P.gamma, P.max_ls, P.m, P.reset_norm};
   const bool m_changed = h->lbp_set && h->lbp.m != lp.m;
   if (!h->lbp_set || std::memcmp(&lp, &h->lbp, sizeof(lp)) != 0) {
     free_lb_graphs(h);  // the constants are part of the captured launches
@@ -2003,7 +2011,8 @@ etdm_status etdm_lbfgs_step(etdm_handle* h, const etdm_lbfgs_params* params, voi
     h->lb_evals = 0;
     CHECK(lb_start(h, P.beta0, 1, s));
     h->lb_init = true;
-  } else if (P.reset_every > 0 && h->lb_iter > 0 && h->lb_iter % P.reset_every == 0) {
+  } else if ((P.reset_every > 0 && h->lb_iter > 0 && h->lb_iter % P.reset_every == 0) ||
+             (P.reset_norm > 0.0 && h->lb_sum->xmax2 > P.reset_norm * P.reset_norm)) {
     // reference reset (Sec. 3.4): C0 <- C0 exp(A), A <- 0, memory erased, beta kept
     HIPCHK(h, hipMemcpyAsync(h->par_ws, h->x, pb, hipMemcpyDeviceToDevice, s));
     new_reference(h, s);

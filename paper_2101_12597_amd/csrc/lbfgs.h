@@ -23,6 +23,7 @@ enum LbPhase : int32_t { LS_TRIAL = 0, LS_BRACKET = 1, LS_ZOOM = 2, LS_BEST = 3 
 struct LbParams {
   double c1, c2, delta, sigma, eps, gamma;
   int32_t max_ls, m;
+  double reset_norm;  // > 0: the largest per-instance parameter norm is tracked
 };
 
 // All state of one L-BFGS run that lives on the device.  A probe is (step a,
@@ -39,6 +40,7 @@ struct LbState {
   double gg;              // |g|^2 at x
   double sy, yy;          // of the latest pair
   double coef;            // two-loop scalar of the current step
+  double xmax2;           // largest per-instance |x_k|^2 after the last accepted step
   double ys[LB_MMAX];     // s_i . y_i of the stored pairs
   double al[LB_MMAX];     // two-loop alpha_i
   int32_t evals;          // evaluations in this line search
@@ -70,9 +72,12 @@ void launch_lb_restart(LbState* st, const LbParams& P, const double* x, const do
 // After an evaluation at x + alpha p (gradient gw, total energy E_total, status
 // word): one line-search step; on CONT the next trial point goes to xtrial, on
 // ACCEPT the pair (alpha p, gw - g) is stored when s.y > 0 (beta updated) and
-// x, g advance to the accepted point.  The state is then copied to `summary`.
+// x, g advance to the accepted point; with P.reset_norm > 0 the largest squared
+// norm of the instances' segments of x (offsets off[0..n_inst]) goes to xmax2.
+// The state is then copied to `summary`.
 void launch_lb_after_probe(LbState* st, const LbParams& P, double* x, double* g, const double* p,
                            const double* gw, const double* E_total, const int* status, double* S, double* Y,
-                           int64_t n, double* partial, double* xtrial, LbState* summary, hipStream_t s);
+                           int64_t n, const int64_t* off, int n_inst, double* partial, double* xtrial,
+                           LbState* summary, hipStream_t s);
 
 }  // namespace etdm

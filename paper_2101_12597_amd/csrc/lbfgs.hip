@@ -125,6 +125,7 @@ __global__ __launch_bounds__(TPB) void start_state(LbState* st, const double* E_
   st->status = 0;
   st->steepest = 0;
   st->evals = 0;
+  st->xmax2 = 0.0;
 }
 
 // slope of the two-loop direction; a direction that does not descend is replaced
@@ -380,6 +381,32 @@ __global__ void advance(const LbState* st, double* __restrict__ x, double* __res
   }
 }
 
+// |x_k|^2 of each instance's segment, one workgroup per instance
+__global__ __launch_bounds__(TPB) void segment_norms(const LbState* st, const double* __restrict__ x,
+                                                     const int64_t* __restrict__ off, double* partial) {
+  if (st->result != LR_ACCEPT) return;
+  __shared__ double red[16];
+  double s = 0.0, c = 0.0;
+  for (int64_t j = off[blockIdx.x] + threadIdx.x; j < off[blockIdx.x + 1]; j += blockDim.x)
+    neumaier_add(s, c, x[j] * x[j]);
+  const double t = block_sum_neumaier(s, c, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(TPB) void segment_norm_max(LbState* st, const double* partial, int n_inst) {
+  if (st->result != LR_ACCEPT) return;
+  __shared__ double red[TPB];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) m = fmax(m, partial[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) st->xmax2 = red[0];
+}
+
 }  // namespace
 
 void launch_lb_start(LbState* st, const double* g, int64_t n, const double* E_total, double beta0, int set_beta,
@@ -426,7 +453,8 @@ void launch_lb_restart(LbState* st, const LbParams& P, const double* x, const do
 
 void launch_lb_after_probe(LbState* st, const LbParams& P, double* x, double* g, const double* p,
                            const double* gw, const double* E_total, const int* status, double* S, double* Y,
-                           int64_t n, double* partial, double* xtrial, LbState* summary, hipStream_t s) {
+                           int64_t n, const int64_t* off, int n_inst, double* partial, double* xtrial,
+                           LbState* summary, hipStream_t s) {
   const int vg = vgrid(n);
   dot_partial<<<LB_DOT_BLOCKS, TPB, 0, s>>>(gw, p, n, nullptr, partial);
   search_step<<<1, TPB, 0, s>>>(st, P, partial, E_total, status);
@@ -434,6 +462,10 @@ void launch_lb_after_probe(LbState* st, const LbParams& P, double* x, double* g,
   pair_partial<<<LB_DOT_BLOCKS, TPB, 0, s>>>(st, p, gw, g, n, partial);
   pair_final<<<1, TPB, 0, s>>>(st, partial);
   advance<<<vg, TPB, 0, s>>>(st, x, g, p, gw, S, Y, n);
+  if (P.reset_norm > 0.0 && n_inst > 0) {
+    segment_norms<<<n_inst, TPB, 0, s>>>(st, x, off, partial);
+    segment_norm_max<<<1, TPB, 0, s>>>(st, partial, n_inst);
+  }
   (void)hipMemcpyAsync(summary, st, sizeof(LbState), hipMemcpyDeviceToHost, s);
 }
 

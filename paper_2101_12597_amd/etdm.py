@@ -63,6 +63,7 @@ class LbfgsParams(ctypes.Structure):
         ("beta0", ctypes.c_double),
         ("reset_every", ctypes.c_int32),
         ("max_ls", ctypes.c_int32),
+        ("reset_norm", ctypes.c_double),
     ]
 
 

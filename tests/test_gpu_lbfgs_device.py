@@ -193,6 +193,30 @@ def test_checkpoint_resume_is_bitwise(which, precision):
             assert np.array_equal(a0, a1) and np.array_equal(e0, e1)
 
 
+@pytest.mark.parametrize("which", ["config1", "tiny_complex"])
+def test_norm_reset_rule(which):
+    """With reset_norm = 1 a reference reset starts every iteration that follows an
+    A with some instance's parameter norm above 1 (and every 20th iteration)."""
+    wl = _workload(which)
+    print(f"[case] L-BFGS norm-triggered resets {which}", flush=True)
+    h, _ = make_handle(wl, "fp64", gemm_tuning=1)
+    A, E, G = _tensors(h)
+    run = _run(h, A, E, G, 30, _params(reset_norm=1.0))
+    h.close()
+    n_norm = 0
+    for k in range(1, len(run)):
+        prev_info, prev_a, _ = run[k - 1]
+        big = max(np.linalg.norm(a) for a in unpack_params(wl, prev_a))
+        if abs(big - 1.0) < 1e-9:
+            continue
+        periodic = prev_info["iter"] % 20 == 0
+        assert bool(run[k][0]["flags"] & 1) == (periodic or big > 1.0), (k, big, run[k][0])
+        n_norm += big > 1.0
+    assert n_norm >= 2
+    Es = [r[0]["E"] for r in run]
+    assert Es[-1] < Es[0]
+
+
 def test_checkpoint_rejects_other_shapes():
     import torch
     from paper_2101_12597_amd import EtdmError

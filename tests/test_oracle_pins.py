@@ -404,6 +404,26 @@ def test_config1_lbfgs_reaches_scf_fixed_point():
     assert all(b <= a + 1e-12 for a, b in zip(Es, Es[1:]))
 
 
+def test_config1_lbfgs_with_norm_resets_reaches_scf_fixed_point():
+    """Resets whenever |A| > 1 (the paper's norm rule, on top of every 20 iterations)
+    keep |A| small and still reach the Roothaan SCF fixed point."""
+    wl = make_config(1)
+    inst = wl.instances[0]
+    rho0 = inst.C0 @ np.diag(inst.f) @ inst.C0.T
+    E_scf, _, _ = scf.scf_minimum(inst.H0, inst.N, 2.0, wl.hubbard_U, rho0)
+    norms = []
+    st, hist = LB.minimize(wl, reset_norm=1.0,
+                           callback=lambda s, info: norms.append(np.linalg.norm(s.x)))
+    assert np.linalg.norm(st.g) < 1e-8
+    assert abs(st.f - E_scf) < 1e-10
+    n_periodic = (len(hist) - 2) // 20
+    assert hist[-1]["resets"] > n_periodic + 3
+    # a reset follows every iterate above the threshold
+    for k in range(len(norms) - 1):
+        if norms[k] > 1.0:
+            assert hist[k + 2]["resets"] == hist[k + 1]["resets"] + 1, k
+
+
 def test_planted_mistakes_are_caught():
     """A dropped Hubbard term or a transposed gradient fails the finite-difference pin."""
     wl = tiny_real(9, 3, seed=16, scale=0.3)
