@@ -77,8 +77,56 @@ def expm_eig(A: np.ndarray) -> np.ndarray:
 
 def expm_pade(A: np.ndarray) -> np.ndarray:
     """Scaling and squaring with Pade approximant (Eq. ss; SciPy's Al-Mohy-Higham),
-    an independent algorithm used to cross-check expm_eig."""
+    an independent algorithm used to cross-check expm_eig and expm_ss."""
     return scipy.linalg.expm(A)
+
+
+# Eq. ss: exp(A) = exp(A / 2^s)^(2^s) with the [m/m] Pade approximant of exp(A / 2^s).
+# theta_m: the largest 1-norm of the scaled matrix for which the [m/m] approximant has
+# backward error below the FP64 unit roundoff (the table of Higham's scaling and
+# squaring method, which the Al-Mohy-Higham algorithm refines).
+PADE_THETA = ((3, 1.495585217958292e-2), (5, 2.539398330063230e-1), (7, 9.504178996162932e-1),
+              (9, 2.097847961257068e0), (13, 5.371920351148152e0))
+
+
+def pade_coefficients(m: int) -> List[float]:
+    """Numerator coefficients b_j of the [m/m] Pade approximant of exp: p(x) = sum_j b_j x^j,
+    b_j = (2m - j)! m! / ((2m)! j! (m - j)!), and the denominator is q(x) = p(-x)."""
+    from math import factorial
+    return [factorial(2 * m - j) * factorial(m) / (factorial(2 * m) * factorial(j) * factorial(m - j))
+            for j in range(m + 1)]
+
+
+def pade_degree_and_scaling(norm1: float) -> Tuple[int, int]:
+    """(m, s): the smallest tabulated m whose theta_m covers the 1-norm; beyond theta_13,
+    m = 13 and the fewest halvings s that bring the norm under theta_13."""
+    for m, theta in PADE_THETA[:-1]:
+        if norm1 <= theta:
+            return m, 0
+    theta13 = PADE_THETA[-1][1]
+    s = 0
+    while norm1 / 2.0 ** s > theta13:
+        s += 1
+    return 13, s
+
+
+def expm_ss(A: np.ndarray) -> np.ndarray:
+    """exp(A) by scaling and squaring with a diagonal Pade approximant (Eq. ss): scale by
+    2^-s, evaluate q(X)^-1 p(X) from plain powers of X, square s times."""
+    m, s = pade_degree_and_scaling(float(np.abs(A).sum(axis=0).max()))
+    X = A / 2.0 ** s
+    b = pade_coefficients(m)
+    P = np.zeros_like(X)
+    Q = np.zeros_like(X)
+    Xj = np.eye(A.shape[0], dtype=X.dtype)
+    for j in range(m + 1):
+        P = P + b[j] * Xj
+        Q = Q + (-1.0) ** j * b[j] * Xj
+        Xj = Xj @ X
+    R = np.linalg.solve(Q, P)
+    for _ in range(s):
+        R = R @ R
+    return R
 
 
 def _sinc(x):
@@ -126,12 +174,14 @@ def divided_difference_factor(w: np.ndarray) -> np.ndarray:
     return np.exp(-0.5j * x) * _sinc(0.5 * x)
 
 
-def _densities(wl, params):
-    """Current orbitals C = C0 exp(A) and the diagonals of rho = C F C^dagger."""
+def _densities(wl, params, expm=None):
+    """Current orbitals C = C0 exp(A) and the diagonals of rho = C F C^dagger; exp(A) by
+    the eigendecomposition of iA unless another exponential is given."""
+    expm = expm or expm_eig
     Cs, ds = [], []
     for inst, a in zip(wl.instances, params):
         A = generator(wl.kind, a)
-        C = inst.C0 @ expm_eig(A)
+        C = inst.C0 @ expm(A)
         Cs.append(C)
         ds.append((np.abs(C) ** 2 * inst.f[None, :]).sum(axis=1))
     return Cs, ds
@@ -144,9 +194,9 @@ def _hubbard_density(wl, ds):
     return list(ds)
 
 
-def energy(wl, params) -> float:
+def energy(wl, params, expm=None) -> float:
     """Total energy E(A) of the workload (all instances)."""
-    Cs, ds = _densities(wl, params)
+    Cs, ds = _densities(wl, params, expm)
     ns = _hubbard_density(wl, ds)
     E = 0.0
     for inst, C in zip(wl.instances, Cs):
@@ -198,15 +248,16 @@ def energy_grad(wl, params) -> Tuple[float, List[np.ndarray]]:
     return E, grads
 
 
-def energy_grad_approx(wl, params) -> Tuple[float, List[np.ndarray]]:
+def energy_grad_approx(wl, params, expm=None) -> Tuple[float, List[np.ndarray]]:
     """E(A) and the approximate gradient G ~ L^T of Sec. 3.4, Eq. app_grad: the first
     term of the gradient expansion, with L = w [F, H_MO] at the current orbitals
     C = C0 exp(A).  It replaces Y by L in energy_grad (exact at A = 0, where the
     divided-difference factors are all 1); same layout of the returned gradients.
+    expm selects the exponential (expm_ss: the scaling-and-squaring configuration).
     """
-    Cs, ds = _densities(wl, params)
+    Cs, ds = _densities(wl, params, expm)
     ns = _hubbard_density(wl, ds)
-    E = energy(wl, params)
+    E = energy(wl, params, expm)
     grads = []
     for inst, C, n in zip(wl.instances, Cs, ns):
         H = inst.h0_dense() + wl.hubbard_U * np.diag(n)

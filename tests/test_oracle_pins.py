@@ -225,6 +225,95 @@ def test_structured_approx_gradient_matches_definition_path():
     assert np.abs(g - ge).max() > 1e-6  # far enough from zero that the two gradients differ
 
 
+def _pade_from_conditions(m):
+    """[m/m] Pade approximant of exp from its definition, in exact rationals:
+    q(x) e^x - p(x) = O(x^(2m+1)) with q_0 = 1 (m linear equations for q_1..q_m from the
+    coefficients of x^(m+1)..x^(2m), then p_k = sum_j q_j / (k - j)!)."""
+    from fractions import Fraction
+    from math import factorial
+
+    def inv_fact(n):
+        return Fraction(1, factorial(n)) if n >= 0 else Fraction(0)
+    # rows k = m+1..2m: sum_{j=1..m} q_j / (k-j)! = -1 / k!
+    rows = [[inv_fact(k - j) for j in range(1, m + 1)] + [-inv_fact(k)] for k in range(m + 1, 2 * m + 1)]
+    for c in range(m):  # Gauss-Jordan in exact arithmetic
+        piv = next(r for r in range(c, m) if rows[r][c] != 0)
+        rows[c], rows[piv] = rows[piv], rows[c]
+        rows[c] = [v / rows[c][c] for v in rows[c]]
+        for r in range(m):
+            if r != c and rows[r][c] != 0:
+                f = rows[r][c]
+                rows[r] = [v - f * w for v, w in zip(rows[r], rows[c])]
+    q = [Fraction(1)] + [rows[j][m] for j in range(m)]
+    p = [sum(q[j] * inv_fact(k - j) for j in range(0, k + 1)) for k in range(m + 1)]
+    return p, q
+
+
+def test_pade_coefficients_match_the_defining_conditions():
+    """The closed-form b_j of every tabulated degree equal the approximant solved from its
+    defining conditions, and the denominator is p(-x); [3/3] is 1 + x/2 + x^2/10 + x^3/120."""
+    assert np.allclose(O.pade_coefficients(3), [1.0, 0.5, 0.1, 1.0 / 120.0], rtol=0, atol=1e-16)
+    for m, _ in O.PADE_THETA:
+        p, q = _pade_from_conditions(m)
+        b = O.pade_coefficients(m)
+        for j in range(m + 1):
+            assert abs(b[j] - float(p[j])) <= 1e-15 * float(p[j]), (m, j)
+            assert q[j] == (-1) ** j * p[j], (m, j)
+
+
+@pytest.mark.parametrize("theta,m,s", [(0.01, 3, 0), (0.2, 5, 0), (0.9, 7, 0), (2.0, 9, 0), (5.0, 13, 0),
+                                       (40.0, 13, 3), (1000.0, 13, 8)])
+def test_expm_ss_plane_rotation(theta, m, s):
+    """exp([[0, t], [-t, 0]]) is the rotation by t; the 1-norm t picks degree m and s halvings."""
+    A = np.array([[0.0, theta], [-theta, 0.0]])
+    assert O.pade_degree_and_scaling(theta) == (m, s)
+    R = O.expm_ss(A)
+    ref = np.array([[np.cos(theta), np.sin(theta)], [-np.sin(theta), np.cos(theta)]])
+    assert np.abs(R - ref).max() < 1e-13 * max(1.0, 2.0 ** s)
+
+
+def test_expm_ss_closed_forms():
+    """Nilpotent N (N^5 = 0): exp(N) = sum_k<5 N^k / k!; diagonal i w: exp is diag(e^{i w})."""
+    rng = np.random.default_rng(31)
+    N = np.triu(rng.standard_normal((5, 5)), 1) * 3.0
+    ref = np.eye(5)
+    term = np.eye(5)
+    for k in range(1, 5):
+        term = term @ N / k
+        ref = ref + term
+    assert np.abs(O.expm_ss(N) - ref).max() < 1e-12 * np.abs(ref).max()
+    w = rng.uniform(-9.0, 9.0, 7)
+    D = O.expm_ss(np.diag(1j * w))
+    assert np.abs(D - np.diag(np.exp(1j * w))).max() < 1e-13
+
+
+@pytest.mark.parametrize("scale", [1e-3, 0.3, 3.0, 60.0])
+def test_expm_ss_matches_eigendecomposition_and_scipy(scale):
+    """Random skew-Hermitian A: expm_ss agrees with exp through eigh(iA) and with SciPy's
+    expm, and is unitary."""
+    rng = np.random.default_rng(32)
+    M = 40
+    X = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+    A = scale * (X - X.conj().T) / np.sqrt(M)
+    R = O.expm_ss(A)
+    tol = 1e-13 * max(1.0, scale)
+    assert np.abs(R - O.expm_eig(A)).max() < tol
+    assert np.abs(R - O.expm_pade(A)).max() < tol
+    assert np.abs(R.conj().T @ R - np.eye(M)).max() < tol
+
+
+def test_scaling_and_squaring_configuration_matches_eigendecomposition():
+    """E and G ~ L^T with exp(A) by scaling and squaring equal those with exp(A) through
+    eigh(iA), also for rotations large enough to need squarings."""
+    wl = tiny_complex(9, nk_side=2, kT=0.2)
+    for scale in (1.0, 40.0):
+        p = [scale * a for a in O.parity_params(wl)]
+        E1, G1 = O.energy_grad_approx(wl, p)
+        E2, G2 = O.energy_grad_approx(wl, p, expm=O.expm_ss)
+        assert abs(E1 - E2) < 1e-12 * max(1.0, abs(E1))
+        assert max(np.abs(a - b).max() for a, b in zip(G1, G2)) < 1e-11 * max(1.0, scale)
+
+
 def _fd_directional(wl, params, d, h):
     kind = wl.kind
     v = O.flatten(kind, params)
