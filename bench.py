@@ -63,12 +63,15 @@ def parse():
     ap.add_argument("--gemm-tuning", type=int, default=0, choices=range(7),
                     help="GEMM kernel choice: 0 tuned at creation, 1 size rule, 2 packed 128x128, "
                          "3 grouped 64x64, 4 packed 64x64, 5 packed 128x64, 6 packed 64x128")
+    ap.add_argument("--expm", default="eig", choices=("eig", "ss"),
+                    help="exp(A) through eigh(iA) (Eq. ed) or scaling and squaring with a Pade "
+                         "approximant (Eq. ss; complex workloads with --gradient approx)")
     ap.add_argument("--gradient", default="exact", choices=("exact", "approx"),
                     help="exact dE/dA (Eq. gradients) or the approximation G ~ L^T (Eq. app_grad)")
     return ap.parse_args()
 
 
-def build_handle(wl, precision, gemm_tuning=0, gradient="exact"):
+def build_handle(wl, precision, gemm_tuning=0, gradient="exact", expm="eig"):
     import torch
     from paper_2101_12597_amd import Handle
     from workloads.pack import pack
@@ -78,7 +81,7 @@ def build_handle(wl, precision, gemm_tuning=0, gradient="exact"):
     C0 = torch.from_numpy(pk["C0"]).to(dev)
     h = Handle(pk["M"], pk["N"], wl.kind, precision, wl.hubbard_U, H0, C0, pk["f"],
                couple=wl.couple, weights=pk["weights"], bsr=pk["bsr"], gemm_tuning=gemm_tuning,
-               gradient=gradient)
+               gradient=gradient, expm=expm)
     A = torch.from_numpy(pk["A"]).to(dev)
     E = torch.empty(h.n_inst + 1, dtype=torch.float64, device=dev)
     G = torch.empty_like(A)
@@ -136,7 +139,7 @@ def gemm_kernel_table(h, prof):
     return out
 
 
-def oracle_reference(wl, params, gradient="exact"):
+def oracle_reference(wl, params, gradient="exact", expm="eig"):
     """Per-instance E and g from the FP64 oracle and its wall time: the definition path
     (eigendecomposition of iA), or for M > 2000 the structured path (the M x M complex
     eigendecomposition would take minutes per evaluation)."""
@@ -154,11 +157,17 @@ def oracle_reference(wl, params, gradient="exact"):
             ov = O.energy_grad_ov if gradient == "exact" else O.energy_grad_ov_approx
             e, g = ov(inst, p, wl.hubbard_U)[:2]
         else:
-            e, (g,) = (O.energy_grad if gradient == "exact" else O.energy_grad_approx)(sub, [p])
+            if gradient == "exact":
+                e, (g,) = O.energy_grad(sub, [p])
+            else:
+                e, (g,) = O.energy_grad_approx(sub, [p], expm=O.expm_ss if expm == "ss" else None)
         Es.append(e)
         gs.append(g)
     if wl.couple:
-        e, gs = (O.energy_grad if gradient == "exact" else O.energy_grad_approx)(wl, params)
+        if gradient == "exact":
+            e, gs = O.energy_grad(wl, params)
+        else:
+            e, gs = O.energy_grad_approx(wl, params, expm=O.expm_ss if expm == "ss" else None)
         Es = [e]
     return np.array(Es), gs, time.perf_counter() - t0
 
@@ -216,7 +225,7 @@ def main():
     wl = make_config(cfg)
     params = O.parity_params(wl)
     log("creating the handle")
-    h, A, E, G = build_handle(wl, prec, args.gemm_tuning, args.gradient)
+    h, A, E, G = build_handle(wl, prec, args.gemm_tuning, args.gradient, args.expm)
     log("stage profile")
 
     # which stage dominates: time every stage over a few evaluations
@@ -244,7 +253,7 @@ def main():
     E_gpu = E.cpu().numpy()
     g_gpu = unpack_params(wl, G.cpu().numpy())
     log("oracle reference")
-    Es, gs, t_oracle = oracle_reference(wl, params, args.gradient)
+    Es, gs, t_oracle = oracle_reference(wl, params, args.gradient, args.expm)
     if wl.couple:
         dE = abs(E_gpu[-1] - Es[0]) / wl.n_electrons
         g_all, r_all = np.concatenate([x.ravel() for x in g_gpu]), np.concatenate([x.ravel() for x in gs])
@@ -254,7 +263,8 @@ def main():
         dg = max(float(np.linalg.norm(g_gpu[k] - gs[k]) / max(np.linalg.norm(gs[k]), 1e-300))
                  for k in range(len(wl.instances)))
 
-    is_gemm = dom["name"].startswith("gemm") or dom["name"].startswith("zgemm")
+    # the Pade products and the squarings are FP64 complex GEMMs; the Gauss-Jordan solve is FP64 ALU work
+    is_gemm = dom["name"].startswith(("gemm", "zgemm", "ss_pade", "ss_square"))
     if is_gemm:
         gemm_prec = "fp64" if dom["name"] in ("gemm_funcs_mu", "gemm_Gam1", "gemm_Gam", "gemm_Y1",
                                               "gemm_Y2") else prec
@@ -263,7 +273,7 @@ def main():
         peak = PEAKS_TFLOPS[gemm_prec]
         achieved = dom["flops"] / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
-    elif dom["name"].startswith("eigh") or dom["name"] == "z_eigh":
+    elif dom["name"].startswith("eigh") or dom["name"] in ("z_eigh", "ss_solve"):
         peak = 78.6  # FP64 vector ALU peak: 256 CUs x 2.4 GHz x 128 FP64 flops/clk
         achieved = dom["flops"] / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
@@ -290,7 +300,7 @@ def main():
         "dtype": DTYPE[prec],
         "data": "synthetic",
         "config": {"workload": WORKLOADS[cfg], "precision": prec, "instances": len(wl.instances),
-                   "electrons": wl.n_electrons, "gradient": args.gradient},
+                   "electrons": wl.n_electrons, "gradient": args.gradient, "expm": args.expm},
         "tflops": total_flops / sec / 1e12,
         "ms_per_step_eager": sec_eager * 1e3,
         "roofline": roof,
@@ -300,7 +310,7 @@ def main():
         "gemm_kernels": gemm_kernel_table(h, prof),
     }
     if not args.no_fp64_compare and prec != "fp64":
-        h64, A64, E64, G64 = build_handle(wl, "fp64", args.gemm_tuning, args.gradient)
+        h64, A64, E64, G64 = build_handle(wl, "fp64", args.gemm_tuning, args.gradient, args.expm)
         h64.set_graph(True)
         sec64, _ = timed_run(h64, A64, E64, G64, max(5, args.steps // 2), 2)
         out["fp64_path"] = {"value": 1.0 / sec64, "ms_per_step": sec64 * 1e3, "speedup": sec64 / sec}
@@ -328,7 +338,7 @@ def main():
     if not args.no_cpu_baseline:
         reps, total = 1, t_oracle
         while total < 10.0 and reps < 8:
-            _, _, t = oracle_reference(wl, params, args.gradient)
+            _, _, t = oracle_reference(wl, params, args.gradient, args.expm)
             total += t
             reps += 1
         path = ("structured occupied-virtual path" if max(i.M for i in wl.instances) > 2000

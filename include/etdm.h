@@ -110,6 +110,12 @@ typedef struct {
                              gradient G ~ L^T of Eq. app_grad (first term of the expansion,
                              exact at A = 0; keep A small, e.g. by reference updates).
                              Other values: ETDM_E_ARG */
+  int32_t expm_method;    /* 0 = exp(A) through the eigendecomposition of iA (Eq. ed, Eq. uinv);
+                             1 = scaling and squaring with the [13/13] Pade approximant
+                             (Eq. ss): COMPLEX_FULL with gradient = 1 and M <= 1024 only
+                             (ETDM_E_ARG / ETDM_E_SHAPE otherwise); one stream
+                             synchronization per evaluation reads the number of squarings,
+                             so its evaluations are not replayed from graphs */
 } etdm_desc;
 
 /* Create a handle.  H0: device, dense float64 (REAL_OV) or complex float64

@@ -17,6 +17,7 @@
 #include "ov.h"
 #include "eigh_large.h"
 #include "lbfgs.h"
+#include "expm_ss.h"
 
 using namespace etdm;
 
@@ -262,6 +263,7 @@ struct ZBuf {
   double *C0, *H0, *f, *A, *G;
   double *Hk, *V, *w, *Vp, *Ue, *C, *T, *d, *e, *L, *LV, *W1, *Y;
   double *n0, *eps;
+  double *sX, *sX2, *sX4, *sX6, *sW, *sZ, *sT, *sV;  // scaling and squaring (Eq. ss) workspace
 };
 
 // Accumulated HIP-event timing of one stage of the launch sequence.
@@ -284,10 +286,11 @@ const char* kOvNames[O_COUNT] = {"gemm_P",  "eigh_lds",  "eigh_global", "spectra
                                  "pair_hadamard", "gemm_Y1", "gemm_Y2",    "gemm_grad",       "nonfinite_scan",
                                  "gemm_Q1"};
 enum ZStage { Z_IA, Z_EIG, Z_PHASE, Z_UE, Z_C, Z_T, Z_ROWS, Z_HUBN, Z_APPLY, Z_ENERGY, Z_HMO, Z_COMM, Z_LV, Z_LT,
-              Z_DD, Z_W1, Z_Y, Z_GRAD, Z_COUNT };
+              Z_DD, Z_W1, Z_Y, Z_GRAD, Z_SS_SCALE, Z_SS_PADE, Z_SS_SOLVE, Z_SS_SQUARE, Z_COUNT };
 const char* kZNames[Z_COUNT] = {"z_build_iA", "z_eigh",   "z_phase",  "zgemm_expA", "zgemm_C",   "zgemm_H0C",
                                 "z_rows",     "z_hub_n",  "z_hub_apply", "z_energy", "zgemm_HMO", "z_commutator",
-                                "zgemm_LV",   "zgemm_VhLV", "z_divdiff", "zgemm_W1",  "zgemm_Y",   "z_grad"};
+                                "zgemm_LV",   "zgemm_VhLV", "z_divdiff", "zgemm_W1",  "zgemm_Y",   "z_grad",
+                                "ss_scaling", "ss_pade",  "ss_solve", "ss_square"};
 
 }  // namespace
 
@@ -370,6 +373,15 @@ struct etdm_handle {
   char* pack_arena = nullptr;
   int gemm_tuning = 0;
   int grad_approx = 0;  // 1: G ~ L^T (Eq. app_grad) instead of the exact gradient
+  // exp(A) by scaling and squaring (Eq. ss) instead of the eigendecomposition
+  int expm_ss = 0;
+  SsInst* d_ss = nullptr;
+  double* ss_norms = nullptr;
+  int* ss_s_dev = nullptr;
+  int* ss_s_host = nullptr;  // pinned: the batch's number of squarings
+  int ss_max_m = 0;
+  PadeB13 ss_b{};
+  Stage ss_X2, ss_X4, ss_X6, ss_T, ss_V, ss_U, ss_sq0, ss_sq1;
   std::vector<Stage*> timer_stage;  // per timed stage: its GEMM launch, or null
   std::vector<Stage*> tune_extra;   // further stages with a kernel choice (inside a timed stage)
   // tracing
@@ -557,7 +569,18 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       const int64_t nblk = M <= HT_MAX ? (M - 1 + HT_NB - 1) / HT_NB : 0;
       b.wyT = pl.take(2 * nblk * HT_NB * HT_NB);
       b.wyW = pl.take(M <= HT_MAX ? 2 * 2 * HT_NB * M : 0);
+      const int64_t ssz = h->expm_ss ? MM2 : 0;
+      b.sX = pl.take(ssz);
+      b.sX2 = pl.take(ssz);
+      b.sX4 = pl.take(ssz);
+      b.sX6 = pl.take(ssz);
+      b.sW = pl.take(ssz);
+      b.sZ = pl.take(ssz);
+      b.sT = pl.take(ssz);
+      b.sV = pl.take(ssz);
     }
+    h->ss_norms = pl.take(h->expm_ss ? h->n_inst : 0);
+    h->ss_s_dev = reinterpret_cast<int*>(pl.take(h->expm_ss ? 1 : 0));
   }
   const int64_t np = h->n_param;
   h->x = pl.take(np);
@@ -903,6 +926,9 @@ etdm_status build_z_plan(etdm_handle* h) {
   h->z_W1.init(OP_N, OP_C, GP_FP64, true);
   h->z_Y.init(OP_N, OP_N, GP_FP64, true);
   h->z_HC0.init(OP_N, OP_N, GP_FP64, true);
+  for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_T, &h->ss_V, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
+    st->init(OP_N, OP_N, GP_FP64, true);
+  std::vector<SsInst> ss;
   for (int i = 0; i < h->n_inst; ++i) {
     const int M = h->M[i];
     const ZBuf& b = h->zb[i];
@@ -976,6 +1002,27 @@ etdm_status build_z_plan(etdm_handle* h) {
       h->z_Y.add(prob(M, M, M, b.V, M, b.W1, M, b.Y, M));      // Y = V (.) V^H
     }
     h->z_HC0.add(prob(M, M, M, b.H0, M, b.C0, M, b.LV, M));  // preconditioner: H0 C0 (into LV)
+    if (h->expm_ss) {
+      // Eq. ss: powers, the numerator's three products, the squarings (ping-pong Ue <-> X)
+      ss.push_back(SsInst{b.A, b.sX, b.sX2, b.sX4, b.sX6, b.sW, b.sZ, b.sT, b.sV, b.Ue, M});
+      h->ss_X2.add(prob(M, M, M, b.sX, M, b.sX, M, b.sX2, M));
+      h->ss_X4.add(prob(M, M, M, b.sX2, M, b.sX2, M, b.sX4, M));
+      h->ss_X6.add(prob(M, M, M, b.sX4, M, b.sX2, M, b.sX6, M));
+      h->ss_T.add(prob(M, M, M, b.sX6, M, b.sW, M, b.sT, M));   // X6 (b13 X6 + b11 X4 + b9 X2)
+      h->ss_V.add(prob(M, M, M, b.sX6, M, b.sZ, M, b.sV, M));   // X6 (b12 X6 + b10 X4 + b8 X2)
+      h->ss_U.add(prob(M, M, M, b.sX, M, b.sT, M, b.sW, M));    // U = X (...), into W
+      h->ss_sq0.add(prob(M, M, M, b.Ue, M, b.Ue, M, b.sX, M));
+      h->ss_sq1.add(prob(M, M, M, b.sX, M, b.sX, M, b.Ue, M));
+      h->ss_max_m = std::max(h->ss_max_m, M);
+    }
+  }
+  if (h->expm_ss) {
+    CHECK(upload(h, &h->d_ss, ss));
+    // numerator coefficients of the [13/13] approximant: b_0 = 1, b_{j+1} = b_j (m - j) / ((2m - j)(j + 1))
+    h->ss_b.b[0] = 1.0;
+    for (int j = 0; j < 13; ++j) h->ss_b.b[j + 1] = h->ss_b.b[j] * (13 - j) / ((26.0 - j) * (j + 1));
+    for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_T, &h->ss_V, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
+      CHECK(upload_stage(h, *st));
   }
   h->n_eig_glb = (int)eg.size();
   for (const EighProb& e : eg) h->eig_nmax = std::max(h->eig_nmax, e.n);
@@ -1009,7 +1056,18 @@ etdm_status build_z_plan(etdm_handle* h) {
       h->timers[Z_COMM].bytes += 32.0 * M * M;
       h->timers[Z_DD].bytes += 32.0 * M * M;
       h->timers[Z_GRAD].bytes += 32.0 * M * M;
+      if (h->expm_ss) {
+        h->timers[Z_SS_SCALE].bytes += 16.0 * M * M;
+        h->timers[Z_SS_SOLVE].flops += 12.0 * M * M * M;  // Gauss-Jordan on [q(X) | p(X)]
+        h->timers[Z_SS_SOLVE].bytes += 32.0 * M * M;
+      }
     }
+    for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_T, &h->ss_V, &h->ss_U}) {
+      h->timers[Z_SS_PADE].flops += stage_flops(*st);
+      h->timers[Z_SS_PADE].bytes += stage_bytes(*st);
+    }
+    h->timers[Z_SS_SQUARE].flops = stage_flops(h->ss_sq0);  // per squaring
+    h->timers[Z_SS_SQUARE].bytes = stage_bytes(h->ss_sq0);
   }
   Stage* stages[] = {&h->z_Ue, &h->z_C, &h->z_T,   &h->z_HMO, &h->z_LV,
                      &h->z_Lt, &h->z_W1, &h->z_Y, &h->z_HC0, &h->z_HG, &h->z_HNS};
@@ -1075,6 +1133,7 @@ void free_handle(etdm_handle* h) {
   free_graph(h);
   if (h->cap_stream) hipStreamDestroy(h->cap_stream);
   if (h->ok_host) hipHostFree(h->ok_host);
+  if (h->ss_s_host) hipHostFree(h->ss_s_host);
   if (h->lb_sum) hipHostFree(h->lb_sum);
   if (h->side) hipStreamDestroy(h->side);
   if (h->ev_fork) hipEventDestroy(h->ev_fork);
@@ -1238,7 +1297,42 @@ void ov_new_reference(etdm_handle* h, hipStream_t s) {
   if (h->h0_format == 0) h->s_HC0.launch(s);  // H0 C0 for the new reference
 }
 
+// exp(A) by scaling and squaring (Eq. ss) into Ue.  The number of squarings is the
+// batch's, read by the host (one synchronization).
+void ss_exponential(etdm_handle* h, hipStream_t s) {
+  {
+    TIMED(Z_SS_SCALE);
+    launch_ss_scaling(h->d_ss, h->n_inst, h->ss_norms, h->ss_s_dev, s);
+    (void)hipMemcpyAsync(h->ss_s_host, h->ss_s_dev, sizeof(int), hipMemcpyDeviceToHost, s);
+  }
+  (void)hipStreamSynchronize(s);
+  const int sq = *h->ss_s_host;
+  {
+    TIMED(Z_SS_PADE);
+    launch_ss_build(h->d_ss, h->b_mat, h->n_inst, h->tot_mat, h->ss_s_dev, s);
+    h->ss_X2.launch(s);
+    h->ss_X4.launch(s);
+    h->ss_X6.launch(s);
+    launch_ss_combine_high(h->d_ss, h->b_mat, h->n_inst, h->tot_mat, h->ss_b, s);
+    h->ss_T.launch(s);
+    h->ss_V.launch(s);
+    launch_ss_combine_odd(h->d_ss, h->b_mat, h->n_inst, h->tot_mat, h->ss_b, s);
+    h->ss_U.launch(s);
+    launch_ss_combine_even(h->d_ss, h->b_mat, h->n_inst, h->tot_mat, h->ss_b, s);
+  }
+  { TIMED(Z_SS_SOLVE); launch_ss_solve(h->d_ss, h->n_inst, h->ss_max_m, s); }
+  {
+    TIMED(Z_SS_SQUARE);
+    for (int k = 0; k < sq; ++k) (k % 2 == 0 ? h->ss_sq0 : h->ss_sq1).launch(s);
+    if (sq % 2) launch_ss_copy_back(h->d_ss, h->b_mat, h->n_inst, h->tot_mat, s);
+  }
+}
+
 void z_exponential_part(etdm_handle* h, hipStream_t s) {
+  if (h->expm_ss) {
+    ss_exponential(h, s);
+    return;
+  }
   { TIMED(Z_IA); launch_z_build_iA(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s); }
   {
     TIMED(Z_EIG);
@@ -1339,7 +1433,7 @@ etdm_status large_fallback(etdm_handle* h, hipStream_t s) {
 bool split_sequence(const etdm_handle* h) { return h->kind == ETDM_REAL_OV && !h->eig_large.empty(); }
 
 etdm_status run_energy_grad(etdm_handle* h, hipStream_t s) {
-  if (!h->use_graph || h->tmask != 0) {
+  if (!h->use_graph || h->tmask != 0 || h->expm_ss) {
     run_energy_grad_eager(h, s);
     return ETDM_OK;
   }
@@ -1461,7 +1555,7 @@ void lb_seq_back(etdm_handle* h, hipStream_t s) {
 
 // one probe: launch, wait, and read the device decision from lb_sum
 etdm_status lb_probe(etdm_handle* h, int which, hipStream_t s) {
-  if (!h->use_graph || h->tmask != 0) {
+  if (!h->use_graph || h->tmask != 0 || h->expm_ss) {
     lb_pre(h, which, s);
     run_energy_grad_eager(h, s);
     lb_post(h, s);
@@ -1569,6 +1663,8 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (d->kind == ETDM_COMPLEX_FULL && d->precision != ETDM_FP64) return ETDM_E_ARG;
   if (d->gemm_tuning < 0 || d->gemm_tuning > 6) return ETDM_E_ARG;
   if (d->gradient != 0 && d->gradient != 1) return ETDM_E_ARG;
+  if (d->expm_method != 0 && d->expm_method != 1) return ETDM_E_ARG;
+  if (d->expm_method == 1 && (d->kind != ETDM_COMPLEX_FULL || d->gradient != 1)) return ETDM_E_ARG;
   if (d->kind == ETDM_REAL_OV && (!d->N || d->couple)) return ETDM_E_ARG;
   if (d->h0_format != 0 && d->h0_format != 1) return ETDM_E_ARG;
   if (d->h0_format == 1 && (d->kind != ETDM_REAL_OV || d->bsr_block < 1 || d->bsr_block > BSR_MAX_BS ||
@@ -1591,6 +1687,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   h->prec = d->precision;
   h->gemm_tuning = d->gemm_tuning;
   h->grad_approx = d->gradient;
+  h->expm_ss = d->expm_method;
   h->U = d->hubbard_U;
   h->couple = d->couple ? 1 : 0;
   h->h0_format = d->h0_format;
@@ -1601,6 +1698,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
     if (M < 1 || M > 32768 || N < 0 || N > M) return bail(ETDM_E_SHAPE);
     if (d->kind == ETDM_REAL_OV && N > 4096) return bail(ETDM_E_SHAPE);
     if (d->kind == ETDM_COMPLEX_FULL && M > 4000) return bail(ETDM_E_SHAPE);
+    if (d->expm_method == 1 && M > SS_MAX_M) return bail(ETDM_E_SHAPE);
     if (d->h0_format == 1 && M % d->bsr_block != 0) return bail(ETDM_E_SHAPE);
     const double wi = d->weights ? d->weights[i] : 1.0;
     if (!(wi > 0.0) || !std::isfinite(wi)) return bail(ETDM_E_ARG);
@@ -1709,6 +1807,9 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
     st = upload(h, &h->d_par_off, offs);
   }
   if (st == ETDM_OK) st = tune_stages(h, s);
+  if (st == ETDM_OK && h->expm_ss &&
+      hipHostMalloc(reinterpret_cast<void**>(&h->ss_s_host), sizeof(int)) != hipSuccess)
+    st = ETDM_E_NOMEM;
   if (st == ETDM_OK && real && h->h0_format == 0) h->s_HC0.launch(s);  // H0 C0 of the reference
   // the side stream only where Q1 is worth a fork and join (on one small molecule
   // they cost more than they hide)
@@ -1873,6 +1974,7 @@ uint64_t ckpt_layout(const etdm_handle* h) {
   mix(h->kind);
   mix(h->prec);
   mix(h->grad_approx);
+  mix(h->expm_ss);
   mix(h->n_inst);
   for (int i = 0; i < h->n_inst; ++i) {
     mix(h->M[i]);

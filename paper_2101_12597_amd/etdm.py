@@ -52,6 +52,7 @@ class _Desc(ctypes.Structure):
         ("bsr_col_idx", ctypes.POINTER(ctypes.c_int32)),
         ("gemm_tuning", ctypes.c_int32),
         ("gradient", ctypes.c_int32),
+        ("expm_method", ctypes.c_int32),
     ]
 
 
@@ -178,12 +179,14 @@ class Handle:
                   2 = packed 128 x 128, 3 = grouped 64 x 64, 4 = packed 64 x 64,
                   5 = packed 128 x 64, 6 = packed 64 x 128
     gradient : "exact" (Eq. gradients) or "approx" (G ~ L^T, Eq. app_grad)
+    expm : "eig" (eigendecomposition of iA, Eq. ed) or "ss" (scaling and squaring with a
+           Pade approximant, Eq. ss; complex kind with the approximate gradient)
     """
 
     def __init__(self, M: Sequence[int], N: Optional[Sequence[int]], kind: str, precision: str,
                  hubbard_U: float, H0, C0, f: np.ndarray, couple: bool = False,
                  weights: Optional[Sequence[float]] = None, bsr=None, stream=None,
-                 gemm_tuning: int = 0, gradient: str = "exact"):
+                 gemm_tuning: int = 0, gradient: str = "exact", expm: str = "eig"):
         L = load_library()
         self._L = L
         n = len(M)
@@ -205,6 +208,9 @@ class Handle:
         if gradient not in ("exact", "approx"):
             raise ValueError("gradient must be 'exact' or 'approx'")
         d.gradient = 1 if gradient == "approx" else 0
+        if expm not in ("eig", "ss"):
+            raise ValueError("expm must be 'eig' or 'ss'")
+        d.expm_method = 1 if expm == "ss" else 0
         if bsr is not None:
             blk, rp, ci = bsr
             self._rp = np.ascontiguousarray(rp, dtype=np.int32)

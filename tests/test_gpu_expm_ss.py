@@ -1,0 +1,76 @@
+"""exp(A) by scaling and squaring with the [13/13] Pade approximant (Sec. 3.4, Eq. ss)
+on the complex path, with the approximate gradient G ~ L^T of the paper's "ss"
+configuration: against the oracle's expm_ss and energy_grad_approx(expm=expm_ss), and
+against the eigendecomposition path.  FP64 tolerances: energies 1e-12 relative,
+gradients 1e-10 relative, unitaries 1e-13 absolute (times 2^s for s squarings)."""
+import numpy as np
+import pytest
+
+from oracle import etdm as O
+from workloads import make_config, tiny_complex
+
+from gpu_helpers import energy_grad, expm, make_handle, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _workload(which):
+    if which == "tiny":
+        return tiny_complex(12, nk_side=2, kT=0.3), 1.0
+    if which == "odd":
+        return tiny_complex(13, nk_side=1, kT=0.1), 1.0
+    wl = make_config(4, nk=8)
+    wl.instances = wl.instances[:8]
+    return wl, (30.0 if which == "config4_8k_large" else 1.0)
+
+
+@pytest.mark.parametrize("which", ["tiny", "odd", "config4_8k", "config4_8k_large"])
+def test_ss_matches_oracle(which):
+    wl, scale = _workload(which)
+    params = [scale * p for p in O.parity_params(wl)]
+    s_max = max(O.pade_degree_and_scaling(float(np.abs(O.generator(wl.kind, p)).sum(axis=0).max()))[1]
+                for p in params)
+    print(f"[case] ss {which} (oracle halvings up to {s_max})", flush=True)
+    h, _ = make_handle(wl, "fp64", gradient="approx", expm="ss")
+    E, G = energy_grad(h, wl, params)
+    U = expm(h, wl, params)
+    h.close()
+    E_ref, G_ref = O.energy_grad_approx(wl, params, expm=O.expm_ss)
+    assert abs(E[-1] - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
+    assert rel_err(G, G_ref) < 1e-10
+    for u, p in zip(U, params):
+        assert np.abs(u - O.expm_ss(O.generator(wl.kind, p))).max() < 1e-13 * 2.0 ** s_max
+
+
+def test_ss_equals_eigendecomposition_path():
+    wl, _ = _workload("config4_8k")
+    params = O.parity_params(wl)
+    print("[case] ss vs eig, approximate gradient", flush=True)
+    he, _ = make_handle(wl, "fp64", gradient="approx")
+    hs, _ = make_handle(wl, "fp64", gradient="approx", expm="ss")
+    Ee, Ge = energy_grad(he, wl, params)
+    Es, Gs = energy_grad(hs, wl, params)
+    he.close()
+    hs.close()
+    assert abs(Ee[-1] - Es[-1]) <= 1e-12 * abs(Ee[-1])
+    assert rel_err(Gs, Ge) < 1e-10
+
+
+def test_ss_zero_rotation_and_lbfgs():
+    """A = 0: exp(A) = I exactly (no squarings, q(0) = p(0) = I).  Then L-BFGS
+    iterations on the ss path (graphs requested, evaluations launched eagerly) lower E."""
+    import torch
+    wl = tiny_complex(8, nk_side=2, kT=0.3)
+    print("[case] ss zero rotation and L-BFGS", flush=True)
+    h, _ = make_handle(wl, "fp64", gradient="approx", expm="ss")
+    U = expm(h, wl, O.zero_params(wl))
+    for u in U:
+        assert np.array_equal(u, np.eye(u.shape[0]))
+    h.set_graph(True)
+    A = torch.zeros(h.n_param, dtype=torch.float64, device="cuda:0")
+    E = torch.empty(h.n_inst + 1, dtype=torch.float64, device="cuda:0")
+    G = torch.empty_like(A)
+    infos = [h.lbfgs_step(A, E, G) for _ in range(10)]
+    h.close()
+    assert infos[-1]["E"] < infos[0]["E"]
+    assert all(b["E"] <= a["E"] + 1e-6 * abs(a["E"]) for a, b in zip(infos, infos[1:]))
