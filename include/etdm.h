@@ -111,7 +111,7 @@ typedef struct {
                              exact at A = 0; keep A small, e.g. by reference updates).
                              Other values: ETDM_E_ARG */
   int32_t expm_method;    /* 0 = exp(A) through the eigendecomposition of iA (Eq. ed, Eq. uinv);
-                             1 = scaling and squaring with the [13/13] Pade approximant
+                             1 = scaling and squaring with the [9/9] Pade approximant
                              (Eq. ss): COMPLEX_FULL with gradient = 1 and M <= 1024 only
                              (ETDM_E_ARG / ETDM_E_SHAPE otherwise); one stream
                              synchronization per evaluation reads the number of squarings,

@@ -263,7 +263,7 @@ struct ZBuf {
   double *C0, *H0, *f, *A, *G;
   double *Hk, *V, *w, *Vp, *Ue, *C, *T, *d, *e, *L, *LV, *W1, *Y;
   double *n0, *eps;
-  double *sX, *sX2, *sX4, *sX6, *sW, *sZ, *sT, *sV;  // scaling and squaring (Eq. ss) workspace
+  double *sX, *sX2, *sX4, *sX6, *sX8, *sT, *sU, *sZ;  // scaling and squaring (Eq. ss) workspace
 };
 
 // Accumulated HIP-event timing of one stage of the launch sequence.
@@ -380,8 +380,8 @@ struct etdm_handle {
   int* ss_s_dev = nullptr;
   int* ss_s_host = nullptr;  // pinned: the batch's number of squarings
   int ss_max_m = 0;
-  PadeB13 ss_b{};
-  Stage ss_X2, ss_X4, ss_X6, ss_T, ss_V, ss_U, ss_sq0, ss_sq1;
+  PadeB9 ss_b{};
+  Stage ss_X2, ss_X4, ss_X6, ss_X8, ss_U, ss_sq0, ss_sq1;
   std::vector<Stage*> timer_stage;  // per timed stage: its GEMM launch, or null
   std::vector<Stage*> tune_extra;   // further stages with a kernel choice (inside a timed stage)
   // tracing
@@ -574,10 +574,10 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       b.sX2 = pl.take(ssz);
       b.sX4 = pl.take(ssz);
       b.sX6 = pl.take(ssz);
-      b.sW = pl.take(ssz);
-      b.sZ = pl.take(ssz);
+      b.sX8 = pl.take(ssz);
       b.sT = pl.take(ssz);
-      b.sV = pl.take(ssz);
+      b.sU = pl.take(ssz);
+      b.sZ = pl.take(ssz);
     }
     h->ss_norms = pl.take(h->expm_ss ? h->n_inst : 0);
     h->ss_s_dev = reinterpret_cast<int*>(pl.take(h->expm_ss ? 1 : 0));
@@ -926,7 +926,7 @@ etdm_status build_z_plan(etdm_handle* h) {
   h->z_W1.init(OP_N, OP_C, GP_FP64, true);
   h->z_Y.init(OP_N, OP_N, GP_FP64, true);
   h->z_HC0.init(OP_N, OP_N, GP_FP64, true);
-  for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_T, &h->ss_V, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
+  for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_X8, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
     st->init(OP_N, OP_N, GP_FP64, true);
   std::vector<SsInst> ss;
   for (int i = 0; i < h->n_inst; ++i) {
@@ -1003,14 +1003,13 @@ etdm_status build_z_plan(etdm_handle* h) {
     }
     h->z_HC0.add(prob(M, M, M, b.H0, M, b.C0, M, b.LV, M));  // preconditioner: H0 C0 (into LV)
     if (h->expm_ss) {
-      // Eq. ss: powers, the numerator's three products, the squarings (ping-pong Ue <-> X)
-      ss.push_back(SsInst{b.A, b.sX, b.sX2, b.sX4, b.sX6, b.sW, b.sZ, b.sT, b.sV, b.Ue, M});
+      // Eq. ss: the even powers, U = X T, the squarings (ping-pong Ue <-> X)
+      ss.push_back(SsInst{b.A, b.sX, b.sX2, b.sX4, b.sX6, b.sX8, b.sT, b.sU, b.sZ, b.Ue, M});
       h->ss_X2.add(prob(M, M, M, b.sX, M, b.sX, M, b.sX2, M));
       h->ss_X4.add(prob(M, M, M, b.sX2, M, b.sX2, M, b.sX4, M));
       h->ss_X6.add(prob(M, M, M, b.sX4, M, b.sX2, M, b.sX6, M));
-      h->ss_T.add(prob(M, M, M, b.sX6, M, b.sW, M, b.sT, M));   // X6 (b13 X6 + b11 X4 + b9 X2)
-      h->ss_V.add(prob(M, M, M, b.sX6, M, b.sZ, M, b.sV, M));   // X6 (b12 X6 + b10 X4 + b8 X2)
-      h->ss_U.add(prob(M, M, M, b.sX, M, b.sT, M, b.sW, M));    // U = X (...), into W
+      h->ss_X8.add(prob(M, M, M, b.sX4, M, b.sX4, M, b.sX8, M));
+      h->ss_U.add(prob(M, M, M, b.sX, M, b.sT, M, b.sU, M));  // U = X (b9 X8 + ... + b1 I)
       h->ss_sq0.add(prob(M, M, M, b.Ue, M, b.Ue, M, b.sX, M));
       h->ss_sq1.add(prob(M, M, M, b.sX, M, b.sX, M, b.Ue, M));
       h->ss_max_m = std::max(h->ss_max_m, M);
@@ -1018,10 +1017,10 @@ etdm_status build_z_plan(etdm_handle* h) {
   }
   if (h->expm_ss) {
     CHECK(upload(h, &h->d_ss, ss));
-    // numerator coefficients of the [13/13] approximant: b_0 = 1, b_{j+1} = b_j (m - j) / ((2m - j)(j + 1))
+    // numerator coefficients of the [9/9] approximant: b_0 = 1, b_{j+1} = b_j (m - j) / ((2m - j)(j + 1))
     h->ss_b.b[0] = 1.0;
-    for (int j = 0; j < 13; ++j) h->ss_b.b[j + 1] = h->ss_b.b[j] * (13 - j) / ((26.0 - j) * (j + 1));
-    for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_T, &h->ss_V, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
+    for (int j = 0; j < 9; ++j) h->ss_b.b[j + 1] = h->ss_b.b[j] * (9 - j) / ((18.0 - j) * (j + 1));
+    for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_X8, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
       CHECK(upload_stage(h, *st));
   }
   h->n_eig_glb = (int)eg.size();
@@ -1058,11 +1057,11 @@ etdm_status build_z_plan(etdm_handle* h) {
       h->timers[Z_GRAD].bytes += 32.0 * M * M;
       if (h->expm_ss) {
         h->timers[Z_SS_SCALE].bytes += 16.0 * M * M;
-        h->timers[Z_SS_SOLVE].flops += 12.0 * M * M * M;  // Gauss-Jordan on [q(X) | p(X)]
+        h->timers[Z_SS_SOLVE].flops += 12.0 * M * M * M;  // Gauss-Jordan on [q(X) | p(X)], complex
         h->timers[Z_SS_SOLVE].bytes += 32.0 * M * M;
       }
     }
-    for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_T, &h->ss_V, &h->ss_U}) {
+    for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_X8, &h->ss_U}) {
       h->timers[Z_SS_PADE].flops += stage_flops(*st);
       h->timers[Z_SS_PADE].bytes += stage_bytes(*st);
     }
@@ -1313,9 +1312,7 @@ void ss_exponential(etdm_handle* h, hipStream_t s) {
     h->ss_X2.launch(s);
     h->ss_X4.launch(s);
     h->ss_X6.launch(s);
-    launch_ss_combine_high(h->d_ss, h->b_mat, h->n_inst, h->tot_mat, h->ss_b, s);
-    h->ss_T.launch(s);
-    h->ss_V.launch(s);
+    h->ss_X8.launch(s);
     launch_ss_combine_odd(h->d_ss, h->b_mat, h->n_inst, h->tot_mat, h->ss_b, s);
     h->ss_U.launch(s);
     launch_ss_combine_even(h->d_ss, h->b_mat, h->n_inst, h->tot_mat, h->ss_b, s);

@@ -1,12 +1,18 @@
-// exp(A) of the complex skew-Hermitian generators by scaling and squaring with the
-// [13/13] Pade approximant (Sec. 3.4, Eq. ss).
+// exp(A) of the complex skew-Hermitian generators by scaling and squaring with a
+// diagonal Pade approximant (Sec. 3.4, Eq. ss).
 //
-//   s      halvings that bring the largest 1-norm of the batch under theta_13
-//   X      = A / 2^s
-//   p(X)   = U + V with U the odd and V the even part (powers X^2, X^4, X^6 and
-//            three more products, the usual evaluation of the degree-13 numerator)
-//   R      = q(X)^-1 p(X), q(X) = p(-X) = V - U  (Gauss-Jordan, partial pivoting)
+//   s      halvings that bring the largest 1-norm of the batch under theta_9
+//   X      = A / 2^s; the [9/9] approximant is accurate to the unit roundoff there
+//   p(X)   = U + V, U = X (b9 X^8 + b7 X^6 + b5 X^4 + b3 X^2 + b1 I) the odd part,
+//            V = b8 X^8 + ... + b0 I the even part (powers X^2, X^4, X^6, X^8 and one
+//            more product)
+//   R      = q(X)^-1 p(X), q(X) = p(-X) = V - U
 //   exp(A) = R^(2^s)  (s squarings, grouped GEMMs launched by the caller)
+//
+// X is skew-Hermitian, so V is Hermitian, U skew-Hermitian, and q(X) has Hermitian
+// part V with eigenvalues Re p(i w) for the eigenvalues i w of X.  With |w| <=
+// theta_9 < pi these are positive (Re p(i w) > 0 up to |w| = pi for this degree), so
+// elimination without pivoting is stable and the solve is blocked by panels.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,39 +21,38 @@
 
 namespace etdm {
 
-constexpr double SS_THETA13 = 5.371920351148152;  // 1-norm bound of the degree-13 approximant
+constexpr double SS_THETA9 = 2.097847961257068;  // 1-norm bound of the degree-9 approximant
 constexpr int SS_MAX_HALVINGS = 64;
 constexpr int SS_MAX_M = 1024;  // LDS of the solve: 3 rows of M complex
 
 // Per instance: M x M complex matrices (interleaved re, im), row-major.
 struct SsInst {
   const double* A;  // parameters (upper triangle read; the generator is skew-Hermitian)
-  double *X, *X2, *X4, *X6;
-  double *W, *Z, *T, *V;  // W becomes U = X T, Z becomes the denominator q(X)
-  double* R;              // p(X) in, q(X)^-1 p(X) out (the exp(A) buffer)
+  double *X, *X2, *X4, *X6, *X8;
+  double *T, *U, *Z;  // T = odd polynomial in X^2, U = X T, Z = q(X)
+  double* R;          // p(X) in, q(X)^-1 p(X) out (the exp(A) buffer)
   int32_t M;
 };
 
-// numerator coefficients b_0..b_13 of the [13/13] approximant
-struct PadeB13 {
-  double b[14];
+// numerator coefficients b_0..b_9 of the [9/9] approximant
+struct PadeB9 {
+  double b[10];
 };
 
-// 1-norm of every generator, then the batch's halvings s (device int) and a copy for the host.
+// 1-norm of every generator, then the batch's halvings s (device int).
 void launch_ss_scaling(const SsInst* d, int n_inst, double* norms, int* s_dev, hipStream_t s);
 // X = A / 2^s as a full matrix
 void launch_ss_build(const SsInst* d, const int* d_begin, int n_inst, int total, const int* s_dev, hipStream_t s);
-// W = b13 X6 + b11 X4 + b9 X2,  Z = b12 X6 + b10 X4 + b8 X2
-void launch_ss_combine_high(const SsInst* d, const int* d_begin, int n_inst, int total, const PadeB13& b,
-                            hipStream_t s);
-// T += b7 X6 + b5 X4 + b3 X2 + b1 I
-void launch_ss_combine_odd(const SsInst* d, const int* d_begin, int n_inst, int total, const PadeB13& b,
+// T = b9 X8 + b7 X6 + b5 X4 + b3 X2 + b1 I
+void launch_ss_combine_odd(const SsInst* d, const int* d_begin, int n_inst, int total, const PadeB9& b,
                            hipStream_t s);
-// with V_full = V + b6 X6 + b4 X4 + b2 X2 + b0 I and U (in W):  Z = V_full - U,  R = V_full + U
-void launch_ss_combine_even(const SsInst* d, const int* d_begin, int n_inst, int total, const PadeB13& b,
+// V = b8 X8 + b6 X6 + b4 X4 + b2 X2 + b0 I and U:  Z = V - U,  R = V + U
+void launch_ss_combine_even(const SsInst* d, const int* d_begin, int n_inst, int total, const PadeB9& b,
                             hipStream_t s);
-// R <- Z^-1 R by Gauss-Jordan elimination with partial pivoting (one workgroup per
-// instance, 3 max_m complex of LDS); Z is overwritten.
+// Panel width of the solve for matrices up to max_m (its LDS stays within 64 KiB).
+int ss_solve_panel(int max_m);
+// R <- Z^-1 R by block Gauss-Jordan elimination without pivoting, panels of
+// ss_solve_panel(max_m) rows (one workgroup per instance); Z is overwritten.
 void launch_ss_solve(const SsInst* d, int n_inst, int max_m, hipStream_t s);
 // R <- X (after an odd number of squarings the result sits in X)
 void launch_ss_copy_back(const SsInst* d, const int* d_begin, int n_inst, int total, hipStream_t s);

@@ -1,8 +1,7 @@
-// Scaling and squaring with the [13/13] Pade approximant for the complex generators
-// (Sec. 3.4, Eq. ss).  The products (powers of X, the three products of the
-// numerator's evaluation, the squarings) are grouped complex GEMMs launched by the
-// caller; this file holds the norm and scaling choice, the elementwise
-// combinations of the powers and the denominator solve.
+// Scaling and squaring with the [9/9] Pade approximant for the complex generators
+// (Sec. 3.4, Eq. ss).  The products (powers of X, U = X T, the squarings) are grouped
+// complex GEMMs launched by the caller; this file holds the norm and scaling
+// choice, the elementwise combinations of the powers and the denominator solve.
 #include <algorithm>
 
 #include "expm_ss.h"
@@ -12,6 +11,7 @@ namespace {
 
 constexpr int TPB = 256;
 constexpr int SOLVE_TPB = 1024;
+constexpr int SOLVE_NB_MAX = 16;
 
 inline int blocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
@@ -60,13 +60,13 @@ __global__ __launch_bounds__(TPB) void norm1_kernel(const SsInst* __restrict__ s
   if (threadIdx.x == 0) norms[blockIdx.x] = red[0];
 }
 
-// the fewest halvings that bring every instance's 1-norm under theta_13
+// the fewest halvings that bring every instance's 1-norm under theta_9
 __global__ void scaling_kernel(const double* norms, int n_inst, int* s_dev) {
   int s = 0;
   for (int i = 0; i < n_inst; ++i) {
     const double v = norms[i];
     if (!isfinite(v)) continue;  // non-finite input: caught by the energy and gradient scans
-    while (s < SS_MAX_HALVINGS && ldexp(v, -s) > SS_THETA13) ++s;
+    while (s < SS_MAX_HALVINGS && ldexp(v, -s) > SS_THETA9) ++s;
   }
   *s_dev = s;
 }
@@ -83,24 +83,8 @@ __global__ void build_kernel(const SsInst* __restrict__ si, const int* __restric
   reinterpret_cast<double2*>(z.X)[e] = make_double2(sc * a.x, sc * a.y);
 }
 
-__global__ void combine_high_kernel(const SsInst* __restrict__ si, const int* __restrict__ begin, int n, int total,
-                                    PadeB13 b) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int ii = instance_of(begin, n, idx);
-  const SsInst& z = si[ii];
-  const int e = idx - begin[ii];
-  const double2 x2 = reinterpret_cast<const double2*>(z.X2)[e];
-  const double2 x4 = reinterpret_cast<const double2*>(z.X4)[e];
-  const double2 x6 = reinterpret_cast<const double2*>(z.X6)[e];
-  reinterpret_cast<double2*>(z.W)[e] = make_double2(b.b[13] * x6.x + b.b[11] * x4.x + b.b[9] * x2.x,
-                                                    b.b[13] * x6.y + b.b[11] * x4.y + b.b[9] * x2.y);
-  reinterpret_cast<double2*>(z.Z)[e] = make_double2(b.b[12] * x6.x + b.b[10] * x4.x + b.b[8] * x2.x,
-                                                    b.b[12] * x6.y + b.b[10] * x4.y + b.b[8] * x2.y);
-}
-
 __global__ void combine_odd_kernel(const SsInst* __restrict__ si, const int* __restrict__ begin, int n, int total,
-                                   PadeB13 b) {
+                                   PadeB9 b) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   const int ii = instance_of(begin, n, idx);
@@ -109,13 +93,14 @@ __global__ void combine_odd_kernel(const SsInst* __restrict__ si, const int* __r
   const double2 x2 = reinterpret_cast<const double2*>(z.X2)[e];
   const double2 x4 = reinterpret_cast<const double2*>(z.X4)[e];
   const double2 x6 = reinterpret_cast<const double2*>(z.X6)[e];
-  double2& t = reinterpret_cast<double2*>(z.T)[e];
-  t.x += b.b[7] * x6.x + b.b[5] * x4.x + b.b[3] * x2.x + (i == j ? b.b[1] : 0.0);
-  t.y += b.b[7] * x6.y + b.b[5] * x4.y + b.b[3] * x2.y;
+  const double2 x8 = reinterpret_cast<const double2*>(z.X8)[e];
+  reinterpret_cast<double2*>(z.T)[e] =
+      make_double2(b.b[9] * x8.x + b.b[7] * x6.x + b.b[5] * x4.x + b.b[3] * x2.x + (i == j ? b.b[1] : 0.0),
+                   b.b[9] * x8.y + b.b[7] * x6.y + b.b[5] * x4.y + b.b[3] * x2.y);
 }
 
 __global__ void combine_even_kernel(const SsInst* __restrict__ si, const int* __restrict__ begin, int n, int total,
-                                    PadeB13 b) {
+                                    PadeB9 b) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   const int ii = instance_of(begin, n, idx);
@@ -124,113 +109,87 @@ __global__ void combine_even_kernel(const SsInst* __restrict__ si, const int* __
   const double2 x2 = reinterpret_cast<const double2*>(z.X2)[e];
   const double2 x4 = reinterpret_cast<const double2*>(z.X4)[e];
   const double2 x6 = reinterpret_cast<const double2*>(z.X6)[e];
-  const double2 v = reinterpret_cast<const double2*>(z.V)[e];
-  const double2 u = reinterpret_cast<const double2*>(z.W)[e];
-  const double vx = v.x + b.b[6] * x6.x + b.b[4] * x4.x + b.b[2] * x2.x + (i == j ? b.b[0] : 0.0);
-  const double vy = v.y + b.b[6] * x6.y + b.b[4] * x4.y + b.b[2] * x2.y;
+  const double2 x8 = reinterpret_cast<const double2*>(z.X8)[e];
+  const double2 u = reinterpret_cast<const double2*>(z.U)[e];
+  const double vx = b.b[8] * x8.x + b.b[6] * x6.x + b.b[4] * x4.x + b.b[2] * x2.x + (i == j ? b.b[0] : 0.0);
+  const double vy = b.b[8] * x8.y + b.b[6] * x6.y + b.b[4] * x4.y + b.b[2] * x2.y;
   reinterpret_cast<double2*>(z.Z)[e] = make_double2(vx - u.x, vy - u.y);
   reinterpret_cast<double2*>(z.R)[e] = make_double2(vx + u.x, vy + u.y);
 }
 
-// Gauss-Jordan elimination on [Z | R] with row pivoting on the largest |Z_ik|
-// (ties: the lowest row).  Rows stay in global memory (L2-resident for the sizes
-// of one workgroup's matrix); the pivot rows and the multipliers of a step are
-// staged in LDS.
-__global__ __launch_bounds__(SOLVE_TPB) void solve_kernel(const SsInst* __restrict__ si) {
+__device__ __forceinline__ double2 cinv(double2 d) {
+  const double dd = d.x * d.x + d.y * d.y;
+  return make_double2(d.x / dd, -d.y / dd);
+}
+
+// Block Gauss-Jordan elimination on [Z | R] without pivoting (Z has a positive
+// definite Hermitian part).  Per panel of nb rows k0..k1: the panel rows (columns
+// k0.. of Z and all of R) and the multipliers Z[:, k0:k1] go to LDS; the panel is
+// reduced to D^-1 (panel rows) in LDS; every other row i gets
+// row_i -= Z[i, k0:k1] (D^-1 panel rows), so [Z | R] is read and written once per
+// panel rather than once per column.
+__global__ __launch_bounds__(SOLVE_TPB) void solve_kernel(const SsInst* __restrict__ si, int NB) {
   const SsInst& z = si[blockIdx.x];
   const int M = z.M;
   double2* __restrict__ Q = reinterpret_cast<double2*>(z.Z);
   double2* __restrict__ R = reinterpret_cast<double2*>(z.R);
   extern __shared__ double2 sh[];
-  double2* prQ = sh;          // scaled pivot row of Q
-  double2* prR = sh + M;      // scaled pivot row of R
-  double2* mult = sh + 2 * M; // column k of Q (the multipliers)
-  __shared__ double red_v[SOLVE_TPB / 64];
-  __shared__ int red_i[SOLVE_TPB / 64];
-  __shared__ int piv_sh;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int k = 0; k < M; ++k) {
-    double best = -1.0;
-    int bi = M;
-    for (int i = k + threadIdx.x; i < M; i += blockDim.x) {
-      const double2 v = Q[(size_t)i * M + k];
-      const double a = v.x * v.x + v.y * v.y;
-      if (a > best) {
-        best = a;
-        bi = i;
-      }
+  double2* P = sh;                        // panel rows, NB x W (W <= 2M)
+  double2* F = sh + (size_t)NB * 2 * M;   // multipliers, M x NB
+  double2* fc = F + (size_t)M * NB;       // one column of the panel, NB
+  for (int k0 = 0; k0 < M; k0 += NB) {
+    const int nb = min(NB, M - k0);
+    const int wq = M - k0, W = wq + M;
+    for (int t = threadIdx.x; t < nb * W; t += blockDim.x) {
+      const int r = t / W, c = t - r * W;
+      P[t] = c < wq ? Q[(size_t)(k0 + r) * M + k0 + c] : R[(size_t)(k0 + r) * M + (c - wq)];
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o);
-      const int oi = __shfl_xor(bi, o);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      red_v[wave] = best;
-      red_i[wave] = bi;
+    for (int t = threadIdx.x; t < M * nb; t += blockDim.x) {
+      const int i = t / nb, c = t - i * nb;
+      F[t] = Q[(size_t)i * M + k0 + c];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      double bb = red_v[0];
-      int ib = red_i[0];
-      for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-        if (red_v[w] > bb || (red_v[w] == bb && red_i[w] < ib)) {
-          bb = red_v[w];
-          ib = red_i[w];
-        }
-      piv_sh = ib < M ? ib : k;
-    }
-    __syncthreads();
-    const int piv = piv_sh;
-    if (piv != k) {
-      for (int j = k + threadIdx.x; j < M; j += blockDim.x) {
-        const double2 t = Q[(size_t)k * M + j];
-        Q[(size_t)k * M + j] = Q[(size_t)piv * M + j];
-        Q[(size_t)piv * M + j] = t;
+    // the panel: D^-1 (panel rows) by Gauss-Jordan on its nb x nb block
+    for (int c = 0; c < nb; ++c) {
+      if ((int)threadIdx.x < nb) fc[threadIdx.x] = P[threadIdx.x * W + c];
+      __syncthreads();
+      const double2 inv = cinv(fc[c]);
+      for (int t = threadIdx.x; t < W; t += blockDim.x) P[c * W + t] = cmul(P[c * W + t], inv);
+      __syncthreads();
+      for (int t = threadIdx.x; t < (nb - 1) * W; t += blockDim.x) {
+        int r = t / W;
+        const int col = t - r * W;
+        r += r >= c;
+        const double2 f = fc[r], p = P[c * W + col];
+        P[r * W + col].x -= f.x * p.x - f.y * p.y;
+        P[r * W + col].y -= f.x * p.y + f.y * p.x;
       }
-      for (int j = threadIdx.x; j < M; j += blockDim.x) {
-        const double2 t = R[(size_t)k * M + j];
-        R[(size_t)k * M + j] = R[(size_t)piv * M + j];
-        R[(size_t)piv * M + j] = t;
-      }
+      __syncthreads();
     }
-    __syncthreads();
-    const double2 d = Q[(size_t)k * M + k];
-    const double dd = d.x * d.x + d.y * d.y;
-    const double2 inv = make_double2(d.x / dd, -d.y / dd);
-    for (int j = k + 1 + threadIdx.x; j < M; j += blockDim.x) prQ[j] = cmul(Q[(size_t)k * M + j], inv);
-    for (int j = threadIdx.x; j < M; j += blockDim.x) prR[j] = cmul(R[(size_t)k * M + j], inv);
-    for (int i = threadIdx.x; i < M; i += blockDim.x) mult[i] = Q[(size_t)i * M + k];
-    __syncthreads();
-    for (int j = k + 1 + threadIdx.x; j < M; j += blockDim.x) Q[(size_t)k * M + j] = prQ[j];
-    for (int j = threadIdx.x; j < M; j += blockDim.x) R[(size_t)k * M + j] = prR[j];
-    if (threadIdx.x == 0) Q[(size_t)k * M + k] = make_double2(1.0, 0.0);
-    // rows i != k: row_i -= Q_ik * (pivot row), over Q's columns k+1.. and all of R's
-    const int wq = M - k - 1, width = wq + M;
-    const int64_t work = (int64_t)M * width;
-    for (int64_t t = threadIdx.x; t < work; t += blockDim.x) {
-      const int i = (int)(t / width), c = (int)(t - (int64_t)i * width);
-      if (i == k) continue;
-      const double2 f = mult[i];
-      if (c < wq) {
-        const int j = k + 1 + c;
-        const double2 p = prQ[j];
-        double2& q = Q[(size_t)i * M + j];
-        q.x -= f.x * p.x - f.y * p.y;
-        q.y -= f.x * p.y + f.y * p.x;
-      } else {
-        const int j = c - wq;
-        const double2 p = prR[j];
-        double2& r = R[(size_t)i * M + j];
-        r.x -= f.x * p.x - f.y * p.y;
-        r.y -= f.x * p.y + f.y * p.x;
+    // the other rows, one pass
+    for (int64_t t = threadIdx.x; t < (int64_t)(M - nb) * W; t += blockDim.x) {
+      int r = (int)(t / W);
+      const int col = (int)(t - (int64_t)r * W);
+      const int i = r < k0 ? r : r + nb;
+      double2* dst = col < wq ? &Q[(size_t)i * M + k0 + col] : &R[(size_t)i * M + (col - wq)];
+      if (col < nb) {
+        *dst = make_double2(0.0, 0.0);
+        continue;
       }
+      double2 acc = *dst;
+      const double2* f = F + (size_t)i * nb;
+      for (int u = 0; u < nb; ++u) {
+        const double2 p = P[u * W + col];
+        acc.x -= f[u].x * p.x - f[u].y * p.y;
+        acc.y -= f[u].x * p.y + f[u].y * p.x;
+      }
+      *dst = acc;
     }
-    for (int i = threadIdx.x; i < M; i += blockDim.x)
-      if (i != k) Q[(size_t)i * M + k] = make_double2(0.0, 0.0);
+    for (int t = threadIdx.x; t < nb * W; t += blockDim.x) {
+      const int r = t / W, c = t - r * W;
+      if (c < wq) Q[(size_t)(k0 + r) * M + k0 + c] = P[t];
+      else R[(size_t)(k0 + r) * M + (c - wq)] = P[t];
+    }
     __syncthreads();
   }
 }
@@ -256,23 +215,43 @@ void launch_ss_build(const SsInst* d, const int* d_begin, int n_inst, int total,
   if (total > 0) build_kernel<<<blocks(total, TPB), TPB, 0, s>>>(d, d_begin, n_inst, total, s_dev);
 }
 
-void launch_ss_combine_high(const SsInst* d, const int* d_begin, int n_inst, int total, const PadeB13& b,
-                            hipStream_t s) {
-  if (total > 0) combine_high_kernel<<<blocks(total, TPB), TPB, 0, s>>>(d, d_begin, n_inst, total, b);
-}
-
-void launch_ss_combine_odd(const SsInst* d, const int* d_begin, int n_inst, int total, const PadeB13& b,
+void launch_ss_combine_odd(const SsInst* d, const int* d_begin, int n_inst, int total, const PadeB9& b,
                            hipStream_t s) {
   if (total > 0) combine_odd_kernel<<<blocks(total, TPB), TPB, 0, s>>>(d, d_begin, n_inst, total, b);
 }
 
-void launch_ss_combine_even(const SsInst* d, const int* d_begin, int n_inst, int total, const PadeB13& b,
+void launch_ss_combine_even(const SsInst* d, const int* d_begin, int n_inst, int total, const PadeB9& b,
                             hipStream_t s) {
   if (total > 0) combine_even_kernel<<<blocks(total, TPB), TPB, 0, s>>>(d, d_begin, n_inst, total, b);
 }
 
+// LDS one workgroup may use: the device's limit, read once (64 KiB if it cannot be read)
+static size_t solve_lds_limit() {
+  static const size_t limit = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      return (size_t)65536;
+    return (size_t)v;
+  }();
+  return limit;
+}
+
+int ss_solve_panel(int max_m) {
+  // LDS: NB x 2M panel rows + M x NB multipliers + NB column values
+  const size_t per_row = sizeof(double2) * (3 * (size_t)max_m + 1);
+  const int nb = (int)(solve_lds_limit() / per_row);
+  return std::max(1, std::min(SOLVE_NB_MAX, nb));
+}
+
 void launch_ss_solve(const SsInst* d, int n_inst, int max_m, hipStream_t s) {
-  if (n_inst > 0) solve_kernel<<<n_inst, SOLVE_TPB, 3 * (size_t)max_m * sizeof(double2), s>>>(d);
+  if (n_inst <= 0) return;
+  const int panel = ss_solve_panel(max_m);
+  const size_t lds = sizeof(double2) * ((size_t)panel * (3 * (size_t)max_m + 1));
+  if (lds > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(solve_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  solve_kernel<<<n_inst, SOLVE_TPB, lds, s>>>(d, panel);
 }
 
 void launch_ss_copy_back(const SsInst* d, const int* d_begin, int n_inst, int total, hipStream_t s) {
