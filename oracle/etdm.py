@@ -129,6 +129,32 @@ def expm_ss(A: np.ndarray) -> np.ndarray:
     return R
 
 
+def frechet_expm_ss(A: np.ndarray, E: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """exp(A) and its Frechet derivative L(A, E) = d/dh exp(A + h E) at h = 0 by scaling and
+    squaring (Eq. ss differentiated): with X = A / 2^s and r = q(X)^-1 p(X), the derivative of
+    every power X^j follows the product rule, L_r = q^-1 (L_p - L_q r), and each squaring
+    R <- R R carries L <- R L + L R."""
+    m, s = pade_degree_and_scaling(float(np.abs(A).sum(axis=0).max()))
+    X, Es = A / 2.0 ** s, E / 2.0 ** s
+    b = pade_coefficients(m)
+    n = A.shape[0]
+    dt = np.result_type(X, Es)
+    P, Q, LP, LQ = (np.zeros((n, n), dtype=dt) for _ in range(4))
+    Xj = np.eye(n, dtype=dt)
+    Lj = np.zeros((n, n), dtype=dt)  # derivative of X^j
+    for j in range(m + 1):
+        sign = (-1.0) ** j
+        P, Q = P + b[j] * Xj, Q + sign * b[j] * Xj
+        LP, LQ = LP + b[j] * Lj, LQ + sign * b[j] * Lj
+        Lj = X @ Lj + Es @ Xj
+        Xj = Xj @ X
+    R = np.linalg.solve(Q, P)
+    L = np.linalg.solve(Q, LP - LQ @ R)
+    for _ in range(s):
+        R, L = R @ R, R @ L + L @ R
+    return R, L
+
+
 def _sinc(x):
     """sin(x)/x with the value 1 at x = 0 (np.sinc is sin(pi x)/(pi x))."""
     return np.sinc(np.asarray(x) / np.pi)
@@ -272,6 +298,33 @@ def energy_grad_approx(wl, params, expm=None) -> Tuple[float, List[np.ndarray]]:
         if wl.kind == "real_ov":
             N = inst.N
             grads.append(dRe[:N, N:].copy())
+        else:
+            grads.append(np.triu(dRe, 1) + 1j * np.triu(dIm))
+    return E, grads
+
+
+def energy_grad_ss(wl, params) -> Tuple[float, List[np.ndarray]]:
+    """E(A) and the exact gradient with exp(A) and Y from scaling and squaring: since
+    exp(A) is unitary, Y = integral_0^1 e^{tA} L e^{-tA} dt = L(A, L) exp(A)^dagger with L(A, .)
+    the Frechet derivative of exp (no eigendecomposition).  Same layout as energy_grad."""
+    Cs, ds = _densities(wl, params, expm_ss)
+    ns = _hubbard_density(wl, ds)
+    E = energy(wl, params, expm_ss)
+    grads = []
+    for inst, a, C, n in zip(wl.instances, params, Cs, ns):
+        H = inst.h0_dense() + wl.hubbard_U * np.diag(n)
+        H_MO = C.conj().T @ H @ C
+        F = np.diag(inst.f)
+        L = inst.weight * (F @ H_MO - H_MO @ F)
+        U, LA = frechet_expm_ss(generator(wl.kind, a), L)
+        Y = LA @ U.conj().T
+        M = L.shape[0]
+        delta = np.eye(M)
+        dEda = 0.5 * (2.0 - delta) * Y.T
+        dRe = 2.0 * np.real(dEda)
+        dIm = -2.0 * np.imag(dEda)
+        if wl.kind == "real_ov":
+            grads.append(dRe[:inst.N, inst.N:].copy())
         else:
             grads.append(np.triu(dRe, 1) + 1j * np.triu(dIm))
     return E, grads

@@ -314,6 +314,40 @@ def test_scaling_and_squaring_configuration_matches_eigendecomposition():
         assert max(np.abs(a - b).max() for a, b in zip(G1, G2)) < 1e-11 * max(1.0, scale)
 
 
+@pytest.mark.parametrize("scale", [0.01, 1.0, 20.0])
+def test_frechet_expm_ss(scale):
+    """The Frechet derivative from scaling and squaring equals the upper-right block of
+    exp([[A, E], [0, A]]) (through eigh-free SciPy expm of the doubled matrix), SciPy's
+    expm_frechet, and a central difference of expm_ss."""
+    rng = np.random.default_rng(33)
+    M = 12
+    X = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+    A = scale * (X - X.conj().T) / np.sqrt(M)
+    E = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+    U, L = O.frechet_expm_ss(A, E)
+    big = np.block([[A, E], [np.zeros_like(A), A]])
+    ref = scipy.linalg.expm(big)[:M, M:]
+    tol = 1e-12 * max(1.0, scale)
+    assert np.abs(U - O.expm_ss(A)).max() < 1e-14 * max(1.0, scale)
+    assert np.abs(L - ref).max() < tol * np.abs(ref).max()
+    assert np.abs(L - scipy.linalg.expm_frechet(A, E, compute_expm=False)).max() < tol * np.abs(ref).max()
+    h = 1e-5
+    fd = (O.expm_ss(A + h * E) - O.expm_ss(A - h * E)) / (2 * h)
+    assert np.abs(L - fd).max() < 1e-7 * np.abs(ref).max()
+
+
+def test_exact_gradient_by_scaling_and_squaring():
+    """Y = L(A, L) exp(A)^dagger reproduces the eigenbasis gradient (complex, fractional
+    occupations, coupled k-points) also for rotations that need squarings."""
+    wl = tiny_complex(9, nk_side=2, kT=0.2)
+    for scale in (1.0, 30.0):
+        p = [scale * a for a in O.parity_params(wl)]
+        E1, G1 = O.energy_grad(wl, p)
+        E2, G2 = O.energy_grad_ss(wl, p)
+        assert abs(E1 - E2) < 1e-12 * max(1.0, abs(E1))
+        assert max(np.abs(a - b).max() for a, b in zip(G1, G2)) < 1e-11 * max(1.0, scale)
+
+
 def _fd_directional(wl, params, d, h):
     kind = wl.kind
     v = O.flatten(kind, params)
