@@ -112,7 +112,8 @@ typedef struct {
                              Other values: ETDM_E_ARG */
   int32_t expm_method;    /* 0 = exp(A) through the eigendecomposition of iA (Eq. ed, Eq. uinv);
                              1 = scaling and squaring with the [9/9] Pade approximant
-                             (Eq. ss): COMPLEX_FULL with gradient = 1 and M <= 1024 only
+                             (Eq. ss), and with gradient = 0 the exact gradient through its
+                             Frechet derivative: COMPLEX_FULL with M <= 1024 only
                              (ETDM_E_ARG / ETDM_E_SHAPE otherwise); one stream
                              synchronization per evaluation reads the number of squarings,
                              so its evaluations are not replayed from graphs */

@@ -264,6 +264,9 @@ struct ZBuf {
   double *Hk, *V, *w, *Vp, *Ue, *C, *T, *d, *e, *L, *LV, *W1, *Y;
   double *n0, *eps;
   double *sX, *sX2, *sX4, *sX6, *sX8, *sT, *sU, *sZ;  // scaling and squaring (Eq. ss) workspace
+  // its Frechet derivative (exact gradient): scaled direction, power derivatives,
+  // combinations, the copies of q(X) and r(X), ping-pong R and L of the squarings
+  double *sEs, *sM2, *sM4, *sM6, *sM8, *sLT, *sLV, *sLU, *sZc, *sR0, *sRa, *sLa;
 };
 
 // Accumulated HIP-event timing of one stage of the launch sequence.
@@ -286,11 +289,11 @@ const char* kOvNames[O_COUNT] = {"gemm_P",  "eigh_lds",  "eigh_global", "spectra
                                  "pair_hadamard", "gemm_Y1", "gemm_Y2",    "gemm_grad",       "nonfinite_scan",
                                  "gemm_Q1"};
 enum ZStage { Z_IA, Z_EIG, Z_PHASE, Z_UE, Z_C, Z_T, Z_ROWS, Z_HUBN, Z_APPLY, Z_ENERGY, Z_HMO, Z_COMM, Z_LV, Z_LT,
-              Z_DD, Z_W1, Z_Y, Z_GRAD, Z_SS_SCALE, Z_SS_PADE, Z_SS_SOLVE, Z_SS_SQUARE, Z_COUNT };
+              Z_DD, Z_W1, Z_Y, Z_GRAD, Z_SS_SCALE, Z_SS_PADE, Z_SS_SOLVE, Z_SS_SQUARE, Z_SS_FRECHET, Z_COUNT };
 const char* kZNames[Z_COUNT] = {"z_build_iA", "z_eigh",   "z_phase",  "zgemm_expA", "zgemm_C",   "zgemm_H0C",
                                 "z_rows",     "z_hub_n",  "z_hub_apply", "z_energy", "zgemm_HMO", "z_commutator",
                                 "zgemm_LV",   "zgemm_VhLV", "z_divdiff", "zgemm_W1",  "zgemm_Y",   "z_grad",
-                                "ss_scaling", "ss_pade",  "ss_solve", "ss_square"};
+                                "ss_scaling", "ss_pade",  "ss_solve", "ss_square", "ss_frechet"};
 
 }  // namespace
 
@@ -382,6 +385,17 @@ struct etdm_handle {
   int ss_max_m = 0;
   PadeB9 ss_b{};
   Stage ss_X2, ss_X4, ss_X6, ss_X8, ss_U, ss_sq0, ss_sq1;
+  // exact gradient on the ss path
+  SsDeriv* d_ssd = nullptr;
+  SsInst* d_ss2 = nullptr;  // second solve: [q(X) copy | right-hand side]
+  const double** d_ss_q = nullptr;
+  double** d_ss_qc = nullptr;
+  const double** d_ss_r = nullptr;
+  double** d_ss_r0 = nullptr;
+  const double** d_ss_lu = nullptr;
+  Stage fr_M2a, fr_M2b, fr_M4a, fr_M4b, fr_M6a, fr_M6b, fr_M8a, fr_M8b, fr_LUa, fr_LUb, fr_N;
+  Stage fr_sq[2][3];  // per parity of the squaring step: R L, + L R, R R
+  Stage fr_Y[2];      // Y = L_s exp(A)^H, by the parity of s
   std::vector<Stage*> timer_stage;  // per timed stage: its GEMM launch, or null
   std::vector<Stage*> tune_extra;   // further stages with a kernel choice (inside a timed stage)
   // tracing
@@ -578,6 +592,10 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       b.sT = pl.take(ssz);
       b.sU = pl.take(ssz);
       b.sZ = pl.take(ssz);
+      const int64_t fz = h->expm_ss && !h->grad_approx ? MM2 : 0;
+      for (double** q : {&b.sEs, &b.sM2, &b.sM4, &b.sM6, &b.sM8, &b.sLT, &b.sLV, &b.sLU, &b.sZc, &b.sR0, &b.sRa,
+                         &b.sLa})
+        *q = pl.take(fz);
     }
     h->ss_norms = pl.take(h->expm_ss ? h->n_inst : 0);
     h->ss_s_dev = reinterpret_cast<int*>(pl.take(h->expm_ss ? 1 : 0));
@@ -928,7 +946,18 @@ etdm_status build_z_plan(etdm_handle* h) {
   h->z_HC0.init(OP_N, OP_N, GP_FP64, true);
   for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_X8, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
     st->init(OP_N, OP_N, GP_FP64, true);
-  std::vector<SsInst> ss;
+  const bool ss_exact = h->expm_ss && !h->grad_approx;
+  std::vector<Stage*> fr_all = {&h->fr_M2a, &h->fr_M2b, &h->fr_M4a, &h->fr_M4b, &h->fr_M6a, &h->fr_M6b,
+                                &h->fr_M8a, &h->fr_M8b, &h->fr_LUa, &h->fr_LUb, &h->fr_N};
+  for (int k = 0; k < 2; ++k)
+    for (int c = 0; c < 3; ++c) fr_all.push_back(&h->fr_sq[k][c]);
+  for (Stage* st : fr_all) st->init(OP_N, OP_N, GP_FP64, true);
+  h->fr_Y[0].init(OP_N, OP_C, GP_FP64, true);
+  h->fr_Y[1].init(OP_N, OP_C, GP_FP64, true);
+  std::vector<SsInst> ss, ss2;
+  std::vector<SsDeriv> ssd;
+  std::vector<const double*> ss_q, ss_r, ss_lu;
+  std::vector<double*> ss_qc, ss_r0;
   for (int i = 0; i < h->n_inst; ++i) {
     const int M = h->M[i];
     const ZBuf& b = h->zb[i];
@@ -995,7 +1024,7 @@ etdm_status build_z_plan(etdm_handle* h) {
     h->z_C.add(prob(M, M, M, b.C0, M, b.Ue, M, b.C, M));     // C = C0 exp(A)
     h->z_T.add(prob(M, M, M, b.H0, M, b.C, M, b.T, M));      // H0 C
     h->z_HMO.add(prob(M, M, M, b.C, M, b.T, M, b.L, M));     // H_MO = C^H H C
-    if (!h->grad_approx) {  // Y through the eigenbasis (the exact gradient only)
+    if (!h->grad_approx && !h->expm_ss) {  // Y through the eigenbasis (the exact gradient only)
       h->z_LV.add(prob(M, M, M, b.L, M, b.V, M, b.LV, M));     // L V
       h->z_Lt.add(prob(M, M, M, b.V, M, b.LV, M, b.L, M));     // V^H L V
       h->z_W1.add(prob(M, M, M, b.L, M, b.V, M, b.W1, M));     // (. o D) V^H
@@ -1003,16 +1032,55 @@ etdm_status build_z_plan(etdm_handle* h) {
     }
     h->z_HC0.add(prob(M, M, M, b.H0, M, b.C0, M, b.LV, M));  // preconditioner: H0 C0 (into LV)
     if (h->expm_ss) {
-      // Eq. ss: the even powers, U = X T, the squarings (ping-pong Ue <-> X)
-      ss.push_back(SsInst{b.A, b.sX, b.sX2, b.sX4, b.sX6, b.sX8, b.sT, b.sU, b.sZ, b.Ue, M});
+      // Eq. ss: the even powers, U = X T, the squarings (ping-pong between Ue and X, or a
+      // buffer of the derivative phase when X is still needed there)
+      double* sq = ss_exact ? b.sRa : b.sX;
+      ss.push_back(SsInst{b.A, b.sX, b.sX2, b.sX4, b.sX6, b.sX8, b.sT, b.sU, b.sZ, b.Ue, sq, M});
       h->ss_X2.add(prob(M, M, M, b.sX, M, b.sX, M, b.sX2, M));
       h->ss_X4.add(prob(M, M, M, b.sX2, M, b.sX2, M, b.sX4, M));
       h->ss_X6.add(prob(M, M, M, b.sX4, M, b.sX2, M, b.sX6, M));
       h->ss_X8.add(prob(M, M, M, b.sX4, M, b.sX4, M, b.sX8, M));
       h->ss_U.add(prob(M, M, M, b.sX, M, b.sT, M, b.sU, M));  // U = X (b9 X8 + ... + b1 I)
-      h->ss_sq0.add(prob(M, M, M, b.Ue, M, b.Ue, M, b.sX, M));
-      h->ss_sq1.add(prob(M, M, M, b.sX, M, b.sX, M, b.Ue, M));
+      h->ss_sq0.add(prob(M, M, M, b.Ue, M, b.Ue, M, sq, M));
+      h->ss_sq1.add(prob(M, M, M, sq, M, sq, M, b.Ue, M));
       h->ss_max_m = std::max(h->ss_max_m, M);
+    }
+    if (ss_exact) {
+      // Frechet derivative of exp at A in the direction L; Y = L_s exp(A)^H
+      ss2.push_back(SsInst{b.A, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, b.sZc, b.sLV, nullptr, M});
+      ssd.push_back(SsDeriv{b.L, b.sEs, b.sM2, b.sM4, b.sM6, b.sM8, b.sLT, b.sLV, M});
+      ss_q.push_back(b.sZ);
+      ss_qc.push_back(b.sZc);
+      ss_r.push_back(b.Ue);
+      ss_r0.push_back(b.sR0);
+      ss_lu.push_back(b.sLU);
+      auto acc = [&](GemmProb p, double* D) {  // C = A B + D (D may be C)
+        p.beta = 1.0;
+        p.D = D;
+        p.ldd = M;
+        return p;
+      };
+      h->fr_M2a.add(prob(M, M, M, b.sX, M, b.sEs, M, b.sM2, M));
+      h->fr_M2b.add(acc(prob(M, M, M, b.sEs, M, b.sX, M, b.sM2, M), b.sM2));
+      h->fr_M4a.add(prob(M, M, M, b.sX2, M, b.sM2, M, b.sM4, M));
+      h->fr_M4b.add(acc(prob(M, M, M, b.sM2, M, b.sX2, M, b.sM4, M), b.sM4));
+      h->fr_M6a.add(prob(M, M, M, b.sX4, M, b.sM2, M, b.sM6, M));
+      h->fr_M6b.add(acc(prob(M, M, M, b.sM4, M, b.sX2, M, b.sM6, M), b.sM6));
+      h->fr_M8a.add(prob(M, M, M, b.sX4, M, b.sM4, M, b.sM8, M));
+      h->fr_M8b.add(acc(prob(M, M, M, b.sM4, M, b.sX4, M, b.sM8, M), b.sM8));
+      h->fr_LUa.add(prob(M, M, M, b.sX, M, b.sLT, M, b.sLU, M));
+      h->fr_LUb.add(acc(prob(M, M, M, b.sEs, M, b.sT, M, b.sLU, M), b.sLU));
+      // right-hand side (LU + LV) - (LV - LU) r, with LT = LV - LU and LV = LU + LV
+      h->fr_N.add(acc(prob(M, M, M, b.sLT, M, b.sR0, M, b.sLV, M, -1.0), b.sLV));
+      double* Rb[2] = {b.sR0, b.sRa};
+      double* Lb[2] = {b.sLV, b.sLa};
+      for (int k = 0; k < 2; ++k) {
+        double *R = Rb[k], *L = Lb[k], *Rn = Rb[1 - k], *Ln = Lb[1 - k];
+        h->fr_sq[k][0].add(prob(M, M, M, R, M, L, M, Ln, M));
+        h->fr_sq[k][1].add(acc(prob(M, M, M, L, M, R, M, Ln, M), Ln));
+        h->fr_sq[k][2].add(prob(M, M, M, R, M, R, M, Rn, M));
+        h->fr_Y[k].add(prob(M, M, M, L, M, b.Ue, M, b.Y, M));
+      }
     }
   }
   if (h->expm_ss) {
@@ -1022,6 +1090,18 @@ etdm_status build_z_plan(etdm_handle* h) {
     for (int j = 0; j < 9; ++j) h->ss_b.b[j + 1] = h->ss_b.b[j] * (9 - j) / ((18.0 - j) * (j + 1));
     for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_X8, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
       CHECK(upload_stage(h, *st));
+  }
+  if (ss_exact) {
+    CHECK(upload(h, &h->d_ss2, ss2));
+    CHECK(upload(h, &h->d_ssd, ssd));
+    CHECK(upload(h, &h->d_ss_q, ss_q));
+    CHECK(upload(h, &h->d_ss_qc, ss_qc));
+    CHECK(upload(h, &h->d_ss_r, ss_r));
+    CHECK(upload(h, &h->d_ss_r0, ss_r0));
+    CHECK(upload(h, &h->d_ss_lu, ss_lu));
+    for (Stage* st : fr_all) CHECK(upload_stage(h, *st));
+    CHECK(upload_stage(h, h->fr_Y[0]));
+    CHECK(upload_stage(h, h->fr_Y[1]));
   }
   h->n_eig_glb = (int)eg.size();
   for (const EighProb& e : eg) h->eig_nmax = std::max(h->eig_nmax, e.n);
@@ -1067,6 +1147,13 @@ etdm_status build_z_plan(etdm_handle* h) {
     }
     h->timers[Z_SS_SQUARE].flops = stage_flops(h->ss_sq0);  // per squaring
     h->timers[Z_SS_SQUARE].bytes = stage_bytes(h->ss_sq0);
+    // Frechet phase without its squaring steps (three products per halving on top)
+    for (Stage* st : {&h->fr_M2a, &h->fr_M2b, &h->fr_M4a, &h->fr_M4b, &h->fr_M6a, &h->fr_M6b, &h->fr_M8a,
+                      &h->fr_M8b, &h->fr_LUa, &h->fr_LUb, &h->fr_N, &h->fr_Y[0]}) {
+      h->timers[Z_SS_FRECHET].flops += stage_flops(*st);
+      h->timers[Z_SS_FRECHET].bytes += stage_bytes(*st);
+    }
+    h->timers[Z_SS_FRECHET].flops += h->timers[Z_SS_SOLVE].flops;
   }
   Stage* stages[] = {&h->z_Ue, &h->z_C, &h->z_T,   &h->z_HMO, &h->z_LV,
                      &h->z_Lt, &h->z_W1, &h->z_Y, &h->z_HC0, &h->z_HG, &h->z_HNS};
@@ -1317,7 +1404,13 @@ void ss_exponential(etdm_handle* h, hipStream_t s) {
     h->ss_U.launch(s);
     launch_ss_combine_even(h->d_ss, h->b_mat, h->n_inst, h->tot_mat, h->ss_b, s);
   }
-  { TIMED(Z_SS_SOLVE); launch_ss_solve(h->d_ss, h->n_inst, h->ss_max_m, s); }
+  {
+    TIMED(Z_SS_SOLVE);
+    const bool exact = !h->grad_approx;  // keep q(X) and r(X) for the Frechet derivative
+    if (exact) launch_ss_copy(h->d_ss_q, h->d_ss_qc, h->b_mat, h->n_inst, h->tot_mat, s);
+    launch_ss_solve(h->d_ss, h->n_inst, h->ss_max_m, s);
+    if (exact) launch_ss_copy(h->d_ss_r, h->d_ss_r0, h->b_mat, h->n_inst, h->tot_mat, s);
+  }
   {
     TIMED(Z_SS_SQUARE);
     for (int k = 0; k < sq; ++k) (k % 2 == 0 ? h->ss_sq0 : h->ss_sq1).launch(s);
@@ -1374,6 +1467,24 @@ void z_energy_grad(etdm_handle* h, hipStream_t s) {
   }
   { TIMED(Z_HMO); h->z_HMO.launch(s); }
   { TIMED(Z_COMM); launch_z_commutator(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s); }
+  if (h->expm_ss && !h->grad_approx) {
+    // Y = L(A, L) exp(A)^H through the Frechet derivative of the scaling and squaring
+    TIMED(Z_SS_FRECHET);
+    const int sq = *h->ss_s_host;  // this evaluation's halvings
+    launch_ss_deriv_scale(h->d_ssd, h->b_mat, h->n_inst, h->tot_mat, h->ss_s_dev, s);
+    for (Stage* st : {&h->fr_M2a, &h->fr_M2b, &h->fr_M4a, &h->fr_M4b, &h->fr_M6a, &h->fr_M6b, &h->fr_M8a,
+                      &h->fr_M8b})
+      st->launch(s);
+    launch_ss_deriv_combine(h->d_ssd, h->b_mat, h->n_inst, h->tot_mat, h->ss_b, s);
+    h->fr_LUa.launch(s);
+    h->fr_LUb.launch(s);
+    launch_ss_deriv_rhs(h->d_ssd, h->d_ss_lu, h->b_mat, h->n_inst, h->tot_mat, s);
+    h->fr_N.launch(s);
+    launch_ss_solve(h->d_ss2, h->n_inst, h->ss_max_m, s);
+    for (int k = 0; k < sq; ++k)
+      for (int c = 0; c < 3; ++c) h->fr_sq[k % 2][c].launch(s);
+    h->fr_Y[sq % 2].launch(s);
+  }
   if (!h->z_LV.probs.empty()) {
     TIMED(Z_LV);
     h->z_LV.launch(s);
@@ -1382,7 +1493,7 @@ void z_energy_grad(etdm_handle* h, hipStream_t s) {
     TIMED(Z_LT);
     h->z_Lt.launch(s);
   }
-  if (!h->grad_approx) {
+  if (!h->grad_approx && !h->expm_ss) {
     TIMED(Z_DD);
     launch_z_divdiff(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s);
   }
@@ -1661,7 +1772,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (d->gemm_tuning < 0 || d->gemm_tuning > 6) return ETDM_E_ARG;
   if (d->gradient != 0 && d->gradient != 1) return ETDM_E_ARG;
   if (d->expm_method != 0 && d->expm_method != 1) return ETDM_E_ARG;
-  if (d->expm_method == 1 && (d->kind != ETDM_COMPLEX_FULL || d->gradient != 1)) return ETDM_E_ARG;
+  if (d->expm_method == 1 && d->kind != ETDM_COMPLEX_FULL) return ETDM_E_ARG;
   if (d->kind == ETDM_REAL_OV && (!d->N || d->couple)) return ETDM_E_ARG;
   if (d->h0_format != 0 && d->h0_format != 1) return ETDM_E_ARG;
   if (d->h0_format == 1 && (d->kind != ETDM_REAL_OV || d->bsr_block < 1 || d->bsr_block > BSR_MAX_BS ||

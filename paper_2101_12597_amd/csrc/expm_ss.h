@@ -31,6 +31,20 @@ struct SsInst {
   double *X, *X2, *X4, *X6, *X8;
   double *T, *U, *Z;  // T = odd polynomial in X^2, U = X T, Z = q(X)
   double* R;          // p(X) in, q(X)^-1 p(X) out (the exp(A) buffer)
+  double* Sq;         // partner of R in the squarings (the result sits there after an odd count)
+  int32_t M;
+};
+
+// Frechet derivative L(A, E) of exp at the same A (Eq. ss differentiated), for the
+// exact gradient Y = L(A, L) exp(A)^H: with Es = E / 2^s the derivatives of the
+// powers are M2 = X Es + Es X, M4 = X2 M2 + M2 X2, M6 = X4 M2 + M4 X2,
+// M8 = X4 M4 + M4 X4 (grouped GEMMs); LT, LV are the odd / even combinations,
+// LU = X LT + Es T, L_r = q^-1 (L_p - L_q r) with L_p - L_q r = (LU + LV) - (LV - LU) r,
+// and each squaring carries L <- R L + L R.
+struct SsDeriv {
+  const double* L;  // direction E (the commutator L of the energy)
+  double *Es, *M2, *M4, *M6, *M8;
+  double *LT, *LV;  // odd / even combinations; LT then holds LV - LU, LV the right-hand side
   int32_t M;
 };
 
@@ -54,7 +68,19 @@ int ss_solve_panel(int max_m);
 // R <- Z^-1 R by block Gauss-Jordan elimination without pivoting, panels of
 // ss_solve_panel(max_m) rows (one workgroup per instance); Z is overwritten.
 void launch_ss_solve(const SsInst* d, int n_inst, int max_m, hipStream_t s);
-// R <- X (after an odd number of squarings the result sits in X)
+// Es = E / 2^s
+void launch_ss_deriv_scale(const SsDeriv* d, const int* d_begin, int n_inst, int total, const int* s_dev,
+                           hipStream_t s);
+// LT = b9 M8 + b7 M6 + b5 M4 + b3 M2,  LV = b8 M8 + b6 M6 + b4 M4 + b2 M2
+void launch_ss_deriv_combine(const SsDeriv* d, const int* d_begin, int n_inst, int total, const PadeB9& b,
+                             hipStream_t s);
+// with LU (in `lu` of instance i at the same offsets): LT <- LV - LU, LV <- LU + LV
+void launch_ss_deriv_rhs(const SsDeriv* d, const double* const* lu, const int* d_begin, int n_inst, int total,
+                         hipStream_t s);
+// dst <- src elementwise over every instance's M x M complex matrix
+void launch_ss_copy(const double* const* src, double* const* dst, const int* d_begin, int n_inst, int total,
+                    hipStream_t s);
+// R <- Sq (after an odd number of squarings the result sits in Sq)
 void launch_ss_copy_back(const SsInst* d, const int* d_begin, int n_inst, int total, hipStream_t s);
 
 }  // namespace etdm

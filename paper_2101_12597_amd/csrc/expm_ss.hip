@@ -194,13 +194,64 @@ __global__ __launch_bounds__(SOLVE_TPB) void solve_kernel(const SsInst* __restri
   }
 }
 
+__global__ void deriv_scale_kernel(const SsDeriv* __restrict__ di, const int* __restrict__ begin, int n, int total,
+                                   const int* s_dev) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = instance_of(begin, n, idx);
+  const SsDeriv& z = di[ii];
+  const int e = idx - begin[ii];
+  const double sc = ldexp(1.0, -*s_dev);
+  const double2 l = reinterpret_cast<const double2*>(z.L)[e];
+  reinterpret_cast<double2*>(z.Es)[e] = make_double2(sc * l.x, sc * l.y);
+}
+
+__global__ void deriv_combine_kernel(const SsDeriv* __restrict__ di, const int* __restrict__ begin, int n,
+                                     int total, PadeB9 b) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = instance_of(begin, n, idx);
+  const SsDeriv& z = di[ii];
+  const int e = idx - begin[ii];
+  const double2 m2 = reinterpret_cast<const double2*>(z.M2)[e];
+  const double2 m4 = reinterpret_cast<const double2*>(z.M4)[e];
+  const double2 m6 = reinterpret_cast<const double2*>(z.M6)[e];
+  const double2 m8 = reinterpret_cast<const double2*>(z.M8)[e];
+  reinterpret_cast<double2*>(z.LT)[e] = make_double2(b.b[9] * m8.x + b.b[7] * m6.x + b.b[5] * m4.x + b.b[3] * m2.x,
+                                                     b.b[9] * m8.y + b.b[7] * m6.y + b.b[5] * m4.y + b.b[3] * m2.y);
+  reinterpret_cast<double2*>(z.LV)[e] = make_double2(b.b[8] * m8.x + b.b[6] * m6.x + b.b[4] * m4.x + b.b[2] * m2.x,
+                                                     b.b[8] * m8.y + b.b[6] * m6.y + b.b[4] * m4.y + b.b[2] * m2.y);
+}
+
+__global__ void deriv_rhs_kernel(const SsDeriv* __restrict__ di, const double* const* __restrict__ lu,
+                                 const int* __restrict__ begin, int n, int total) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = instance_of(begin, n, idx);
+  const SsDeriv& z = di[ii];
+  const int e = idx - begin[ii];
+  const double2 u = reinterpret_cast<const double2*>(lu[ii])[e];
+  const double2 v = reinterpret_cast<const double2*>(z.LV)[e];
+  reinterpret_cast<double2*>(z.LT)[e] = make_double2(v.x - u.x, v.y - u.y);
+  reinterpret_cast<double2*>(z.LV)[e] = make_double2(v.x + u.x, v.y + u.y);
+}
+
+__global__ void copy_kernel(const double* const* __restrict__ src, double* const* __restrict__ dst,
+                            const int* __restrict__ begin, int n, int total) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = instance_of(begin, n, idx);
+  const int e = idx - begin[ii];
+  reinterpret_cast<double2*>(dst[ii])[e] = reinterpret_cast<const double2*>(src[ii])[e];
+}
+
 __global__ void copy_back_kernel(const SsInst* __restrict__ si, const int* __restrict__ begin, int n, int total) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   const int ii = instance_of(begin, n, idx);
   const SsInst& z = si[ii];
   const int e = idx - begin[ii];
-  reinterpret_cast<double2*>(z.R)[e] = reinterpret_cast<const double2*>(z.X)[e];
+  reinterpret_cast<double2*>(z.R)[e] = reinterpret_cast<const double2*>(z.Sq)[e];
 }
 
 }  // namespace
@@ -252,6 +303,26 @@ void launch_ss_solve(const SsInst* d, int n_inst, int max_m, hipStream_t s) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(solve_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
   solve_kernel<<<n_inst, SOLVE_TPB, lds, s>>>(d, panel);
+}
+
+void launch_ss_deriv_scale(const SsDeriv* d, const int* d_begin, int n_inst, int total, const int* s_dev,
+                           hipStream_t s) {
+  if (total > 0) deriv_scale_kernel<<<blocks(total, TPB), TPB, 0, s>>>(d, d_begin, n_inst, total, s_dev);
+}
+
+void launch_ss_deriv_combine(const SsDeriv* d, const int* d_begin, int n_inst, int total, const PadeB9& b,
+                             hipStream_t s) {
+  if (total > 0) deriv_combine_kernel<<<blocks(total, TPB), TPB, 0, s>>>(d, d_begin, n_inst, total, b);
+}
+
+void launch_ss_deriv_rhs(const SsDeriv* d, const double* const* lu, const int* d_begin, int n_inst, int total,
+                         hipStream_t s) {
+  if (total > 0) deriv_rhs_kernel<<<blocks(total, TPB), TPB, 0, s>>>(d, lu, d_begin, n_inst, total);
+}
+
+void launch_ss_copy(const double* const* src, double* const* dst, const int* d_begin, int n_inst, int total,
+                    hipStream_t s) {
+  if (total > 0) copy_kernel<<<blocks(total, TPB), TPB, 0, s>>>(src, dst, d_begin, n_inst, total);
 }
 
 void launch_ss_copy_back(const SsInst* d, const int* d_begin, int n_inst, int total, hipStream_t s) {

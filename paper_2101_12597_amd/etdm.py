@@ -180,7 +180,8 @@ class Handle:
                   5 = packed 128 x 64, 6 = packed 64 x 128
     gradient : "exact" (Eq. gradients) or "approx" (G ~ L^T, Eq. app_grad)
     expm : "eig" (eigendecomposition of iA, Eq. ed) or "ss" (scaling and squaring with a
-           Pade approximant, Eq. ss; complex kind with the approximate gradient)
+           Pade approximant, Eq. ss, and its Frechet derivative for the exact gradient;
+           complex kind)
     """
 
     def __init__(self, M: Sequence[int], N: Optional[Sequence[int]], kind: str, precision: str,

@@ -1,7 +1,8 @@
 """exp(A) by scaling and squaring with a diagonal Pade approximant (Sec. 3.4, Eq. ss)
 on the complex path, with the approximate gradient G ~ L^T of the paper's "ss"
-configuration: against the oracle's expm_ss and energy_grad_approx(expm=expm_ss), and
-against the eigendecomposition path.  FP64 tolerances: energies 1e-12 relative,
+configuration (against the oracle's expm_ss and energy_grad_approx(expm=expm_ss)) and
+with the exact gradient through the Frechet derivative of exp (against the oracle's
+energy_grad_ss and the eigenbasis gradient); and against the eigendecomposition path.  FP64 tolerances: energies 1e-12 relative,
 gradients 1e-10 relative, unitaries 1e-13 absolute times 2^s for the s squarings (the
 GPU scales to theta_9 and uses degree 9: up to two squarings more than the oracle's
 degree-13 choice)."""
@@ -76,3 +77,46 @@ def test_ss_zero_rotation_and_lbfgs():
     h.close()
     assert infos[-1]["E"] < infos[0]["E"]
     assert all(b["E"] <= a["E"] + 1e-6 * abs(a["E"]) for a, b in zip(infos, infos[1:]))
+
+
+@pytest.mark.parametrize("which", ["tiny", "odd", "config4_8k", "config4_8k_large"])
+def test_ss_exact_gradient_matches_oracle(which):
+    """Y = L(A, L) exp(A)^H with the Frechet derivative from the same scaling and squaring."""
+    wl, scale = _workload(which)
+    params = [scale * p for p in O.parity_params(wl)]
+    print(f"[case] ss exact gradient {which}", flush=True)
+    h, _ = make_handle(wl, "fp64", expm="ss")
+    E, G = energy_grad(h, wl, params)
+    h.close()
+    E_ref, G_ref = O.energy_grad_ss(wl, params)
+    assert abs(E[-1] - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
+    assert rel_err(G, G_ref) < 1e-10 * max(1.0, scale)
+    E_eig, G_eig = O.energy_grad(wl, params)
+    assert rel_err(G, G_eig) < 1e-10 * max(1.0, scale)
+
+
+def test_ss_exact_lbfgs_steps():
+    """L-BFGS with the exact gradient on the ss path: energies do not increase (beyond the
+    approximate-Wolfe allowance) and every returned G is the oracle's exact gradient at
+    the returned A.  (Whole trajectories of this case drift apart under rounding-level
+    perturbations, so they are not compared with the eigendecomposition path's.)"""
+    import torch
+    from workloads.pack import unpack_params
+    wl = tiny_complex(8, nk_side=2, kT=0.3)
+    print("[case] ss exact L-BFGS", flush=True)
+    h, _ = make_handle(wl, "fp64", expm="ss")
+    A = torch.zeros(h.n_param, dtype=torch.float64, device="cuda:0")
+    E = torch.empty(h.n_inst + 1, dtype=torch.float64, device="cuda:0")
+    G = torch.empty_like(A)
+    prev = None
+    for _ in range(6):
+        info = h.lbfgs_step(A, E, G)
+        assert not info["flags"] & 1
+        params = unpack_params(wl, A.cpu().numpy())
+        E_ref, G_ref = O.energy_grad(wl, params)
+        assert abs(info["E"] - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
+        assert rel_err(unpack_params(wl, G.cpu().numpy()), G_ref) < 1e-10
+        if prev is not None:
+            assert info["E"] <= prev + 1e-6 * abs(prev)
+        prev = info["E"]
+    h.close()
