@@ -330,6 +330,68 @@ def energy_grad_ss(wl, params) -> Tuple[float, List[np.ndarray]]:
     return E, grads
 
 
+# ----------------------------------------------------------------------------
+# an orbital-dependent term (Sec. 2: the L of a functional that depends on the
+# orbitals as well as on the density, the PZ-SIC form)
+# ----------------------------------------------------------------------------
+#
+# Model (stands in for PZ-SIC, whose orbital densities need grids): every orbital k
+# interacts with its own site density n^(k)_mu = |C_mu_k|^2 (orthonormal basis),
+#   E_odd = -(lam / 2) sum_k w f_k sum_mu |C_mu_k|^4,
+# an orbital potential V^k = diag(-lam |C_mu_k|^2), V_mk = <m|V^k|k>.
+
+
+def orbital_potential_elements(C: np.ndarray, lam: float) -> np.ndarray:
+    """V[m, k] = <m|V^k|k> = sum_mu conj(C_mu_m) (-lam |C_mu_k|^2) C_mu_k."""
+    v = -lam * np.abs(C) ** 2
+    return C.conj().T @ (v * C)
+
+
+def energy_odd(wl, params, lam: float, expm=None) -> float:
+    """E(A) of energy() plus the orbital-dependent model term."""
+    Cs, _ = _densities(wl, params, expm)
+    E = energy(wl, params, expm)
+    for inst, C in zip(wl.instances, Cs):
+        E += -0.5 * lam * inst.weight * float((inst.f[None, :] * np.abs(C) ** 4).sum())
+    return E
+
+
+def energy_grad_odd(wl, params, lam: float, printed_indices: bool = False) -> Tuple[float, List[np.ndarray]]:
+    """E and the exact gradient with the orbital-dependent term (complex full
+    parametrization; the ov form assumes unitary invariance).  For an energy that
+    depends on the orbitals C, with Gamma = dE/dC^* and G = Gamma^dagger C, the L of
+    Eq. gradients is G - G^dagger; the density part gives w [F, H_MO] and the model term
+      L_mk += w (f_m conj(V_km) - f_k V_mk).
+    printed_indices=True uses f_k conj(V_km) - f_m V_mk instead (the index placement
+    as printed), which the finite-difference pins reject."""
+    assert wl.kind == "complex_full"
+    Cs, ds = _densities(wl, params)
+    ns = _hubbard_density(wl, ds)
+    E = energy_odd(wl, params, lam)
+    grads = []
+    for inst, a, C, n in zip(wl.instances, params, Cs, ns):
+        H = inst.h0_dense() + wl.hubbard_U * np.diag(n)
+        H_MO = C.conj().T @ H @ C
+        F = np.diag(inst.f)
+        V = orbital_potential_elements(C, lam)
+        f = inst.f
+        if printed_indices:
+            odd = f[None, :] * V.T.conj() - f[:, None] * V
+        else:
+            odd = f[:, None] * V.T.conj() - f[None, :] * V
+        L = inst.weight * (F @ H_MO - H_MO @ F + odd)
+        w, Vec = eig_iA(generator(wl.kind, a))
+        Lt = Vec.conj().T @ L @ Vec
+        Y = Vec @ (Lt * divided_difference_factor(w)) @ Vec.conj().T
+        M = L.shape[0]
+        delta = np.eye(M)
+        dEda = 0.5 * (2.0 - delta) * Y.T
+        dRe = 2.0 * np.real(dEda)
+        dIm = -2.0 * np.imag(dEda)
+        grads.append(np.triu(dRe, 1) + 1j * np.triu(dIm))
+    return E, grads
+
+
 def unitary(wl, params) -> List[np.ndarray]:
     """exp(A) per instance (the etdm_expm output)."""
     return [expm_eig(generator(wl.kind, a)) for a in params]

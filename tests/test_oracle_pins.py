@@ -348,6 +348,48 @@ def test_exact_gradient_by_scaling_and_squaring():
         assert max(np.abs(a - b).max() for a, b in zip(G1, G2)) < 1e-11 * max(1.0, scale)
 
 
+def _fd_odd(wl, params, lam, d, h=1e-3):
+    """Richardson central difference of energy_odd along d (flat free variables)."""
+    v = O.flatten(wl.kind, params)
+
+    def E(t):
+        return O.energy_odd(wl, O.unflatten(wl.kind, wl, v + t * d), lam)
+    d1 = (E(h) - E(-h)) / (2 * h)
+    d2 = (E(h / 2) - E(-h / 2)) / h
+    return (4 * d2 - d1) / 3
+
+
+def test_orbital_dependent_gradient_matches_finite_differences():
+    """The L of the orbital-dependent model term, derived as G - G^dagger, gives the
+    finite-difference gradient (fractional occupations, coupled k-points, far from
+    A = 0); the index placement as printed does not; lam = 0 is energy_grad."""
+    wl = tiny_complex(7, nk_side=2, kT=0.3)
+    p = [3.0 * a for a in O.parity_params(wl)]
+    lam = 0.7
+    E, G = O.energy_grad_odd(wl, p, lam)
+    _, Gp = O.energy_grad_odd(wl, p, lam, printed_indices=True)
+    g, gp = O.flatten(wl.kind, G), O.flatten(wl.kind, Gp)
+    rng = np.random.default_rng(41)
+    worst_printed = 0.0
+    for _ in range(4):
+        d = rng.standard_normal(g.size)
+        fd = _fd_odd(wl, p, lam, d)
+        assert abs(fd - g @ d) < 1e-8 * (np.abs(g).sum() + 1.0), (fd, g @ d)
+        worst_printed = max(worst_printed, abs(fd - gp @ d))
+    assert worst_printed > 1e-3
+    E0, G0 = O.energy_grad_odd(wl, p, 0.0)
+    E1, G1 = O.energy_grad(wl, p)
+    assert abs(E0 - E1) < 1e-12 and max(np.abs(a - b).max() for a, b in zip(G0, G1)) < 1e-13
+    # not invariant under rotations among the occupied orbitals (the ov form cannot carry it)
+    inst = wl.instances[0]
+    occ = np.flatnonzero(inst.f > 0.5)
+    a = np.zeros((inst.M, inst.M), dtype=complex)
+    a[occ[0], occ[1]] = 0.4
+    zero = O.zero_params(wl)
+    rot = [a] + zero[1:]
+    assert abs(O.energy_odd(wl, rot, lam) - O.energy_odd(wl, zero, lam)) > 1e-6
+
+
 def _fd_directional(wl, params, d, h):
     kind = wl.kind
     v = O.flatten(kind, params)
