@@ -66,12 +66,14 @@ def parse():
     ap.add_argument("--expm", default="eig", choices=("eig", "ss"),
                     help="exp(A) through eigh(iA) (Eq. ed) or scaling and squaring with a Pade "
                          "approximant (Eq. ss; complex workloads with --gradient approx)")
+    ap.add_argument("--odd-lambda", type=float, default=0.0,
+                    help="strength of the orbital-dependent model term (complex workloads)")
     ap.add_argument("--gradient", default="exact", choices=("exact", "approx"),
                     help="exact dE/dA (Eq. gradients) or the approximation G ~ L^T (Eq. app_grad)")
     return ap.parse_args()
 
 
-def build_handle(wl, precision, gemm_tuning=0, gradient="exact", expm="eig"):
+def build_handle(wl, precision, gemm_tuning=0, gradient="exact", expm="eig", odd_lambda=0.0):
     import torch
     from paper_2101_12597_amd import Handle
     from workloads.pack import pack
@@ -81,7 +83,7 @@ def build_handle(wl, precision, gemm_tuning=0, gradient="exact", expm="eig"):
     C0 = torch.from_numpy(pk["C0"]).to(dev)
     h = Handle(pk["M"], pk["N"], wl.kind, precision, wl.hubbard_U, H0, C0, pk["f"],
                couple=wl.couple, weights=pk["weights"], bsr=pk["bsr"], gemm_tuning=gemm_tuning,
-               gradient=gradient, expm=expm)
+               gradient=gradient, expm=expm, odd_lambda=odd_lambda)
     A = torch.from_numpy(pk["A"]).to(dev)
     E = torch.empty(h.n_inst + 1, dtype=torch.float64, device=dev)
     G = torch.empty_like(A)
@@ -139,7 +141,7 @@ def gemm_kernel_table(h, prof):
     return out
 
 
-def oracle_reference(wl, params, gradient="exact", expm="eig"):
+def oracle_reference(wl, params, gradient="exact", expm="eig", odd_lambda=0.0):
     """Per-instance E and g from the FP64 oracle and its wall time: the definition path
     (eigendecomposition of iA), or for M > 2000 the structured path (the M x M complex
     eigendecomposition would take minutes per evaluation)."""
@@ -163,6 +165,9 @@ def oracle_reference(wl, params, gradient="exact", expm="eig"):
                 e, (g,) = O.energy_grad_approx(sub, [p], expm=O.expm_ss if expm == "ss" else None)
         Es.append(e)
         gs.append(g)
+    if odd_lambda != 0.0:  # the orbital-dependent term (complex workloads, exact gradient)
+        e, gs = O.energy_grad_odd(wl, params, odd_lambda)
+        return np.array([e]), gs, time.perf_counter() - t0
     if wl.couple:
         if gradient == "exact":
             e, gs = O.energy_grad(wl, params)
@@ -225,7 +230,7 @@ def main():
     wl = make_config(cfg)
     params = O.parity_params(wl)
     log("creating the handle")
-    h, A, E, G = build_handle(wl, prec, args.gemm_tuning, args.gradient, args.expm)
+    h, A, E, G = build_handle(wl, prec, args.gemm_tuning, args.gradient, args.expm, args.odd_lambda)
     log("stage profile")
 
     # which stage dominates: time every stage over a few evaluations
@@ -253,7 +258,7 @@ def main():
     E_gpu = E.cpu().numpy()
     g_gpu = unpack_params(wl, G.cpu().numpy())
     log("oracle reference")
-    Es, gs, t_oracle = oracle_reference(wl, params, args.gradient, args.expm)
+    Es, gs, t_oracle = oracle_reference(wl, params, args.gradient, args.expm, args.odd_lambda)
     if wl.couple:
         dE = abs(E_gpu[-1] - Es[0]) / wl.n_electrons
         g_all, r_all = np.concatenate([x.ravel() for x in g_gpu]), np.concatenate([x.ravel() for x in gs])
@@ -300,7 +305,8 @@ def main():
         "dtype": DTYPE[prec],
         "data": "synthetic",
         "config": {"workload": WORKLOADS[cfg], "precision": prec, "instances": len(wl.instances),
-                   "electrons": wl.n_electrons, "gradient": args.gradient, "expm": args.expm},
+                   "electrons": wl.n_electrons, "gradient": args.gradient, "expm": args.expm,
+                   "odd_lambda": args.odd_lambda},
         "tflops": total_flops / sec / 1e12,
         "ms_per_step_eager": sec_eager * 1e3,
         "roofline": roof,
@@ -310,7 +316,7 @@ def main():
         "gemm_kernels": gemm_kernel_table(h, prof),
     }
     if not args.no_fp64_compare and prec != "fp64":
-        h64, A64, E64, G64 = build_handle(wl, "fp64", args.gemm_tuning, args.gradient, args.expm)
+        h64, A64, E64, G64 = build_handle(wl, "fp64", args.gemm_tuning, args.gradient, args.expm, args.odd_lambda)
         h64.set_graph(True)
         sec64, _ = timed_run(h64, A64, E64, G64, max(5, args.steps // 2), 2)
         out["fp64_path"] = {"value": 1.0 / sec64, "ms_per_step": sec64 * 1e3, "speedup": sec64 / sec}
@@ -338,7 +344,7 @@ def main():
     if not args.no_cpu_baseline:
         reps, total = 1, t_oracle
         while total < 10.0 and reps < 8:
-            _, _, t = oracle_reference(wl, params, args.gradient, args.expm)
+            _, _, t = oracle_reference(wl, params, args.gradient, args.expm, args.odd_lambda)
             total += t
             reps += 1
         path = ("structured occupied-virtual path" if max(i.M for i in wl.instances) > 2000

@@ -117,6 +117,11 @@ typedef struct {
                              (ETDM_E_ARG / ETDM_E_SHAPE otherwise); one stream
                              synchronization per evaluation reads the number of squarings,
                              so its evaluations are not replayed from graphs */
+  double odd_lambda;      /* strength of an orbital-dependent model term (the PZ-SIC form of
+                             L in Sec. 2): E += -(lambda/2) sum_k w f_k sum_mu |C_mu_k|^4,
+                             L_mk += w (f_m conj(V_km) - f_k V_mk), V^k = diag(-lambda
+                             |C_mu_k|^2).  0 = off; nonzero needs COMPLEX_FULL (the ov form
+                             assumes unitary invariance).  Non-finite: ETDM_E_ARG */
 } etdm_desc;
 
 /* Create a handle.  H0: device, dense float64 (REAL_OV) or complex float64

@@ -267,6 +267,7 @@ struct ZBuf {
   // its Frechet derivative (exact gradient): scaled direction, power derivatives,
   // combinations, the copies of q(X) and r(X), ping-pong R and L of the squarings
   double *sEs, *sM2, *sM4, *sM6, *sM8, *sLT, *sLV, *sLU, *sZc, *sR0, *sRa, *sLa;
+  double *oVC, *oW, *oE;  // orbital-dependent term: -lam |C|^2 o C, (.)^H C, per-row |C|^4 sums
 };
 
 // Accumulated HIP-event timing of one stage of the launch sequence.
@@ -289,11 +290,12 @@ const char* kOvNames[O_COUNT] = {"gemm_P",  "eigh_lds",  "eigh_global", "spectra
                                  "pair_hadamard", "gemm_Y1", "gemm_Y2",    "gemm_grad",       "nonfinite_scan",
                                  "gemm_Q1"};
 enum ZStage { Z_IA, Z_EIG, Z_PHASE, Z_UE, Z_C, Z_T, Z_ROWS, Z_HUBN, Z_APPLY, Z_ENERGY, Z_HMO, Z_COMM, Z_LV, Z_LT,
-              Z_DD, Z_W1, Z_Y, Z_GRAD, Z_SS_SCALE, Z_SS_PADE, Z_SS_SOLVE, Z_SS_SQUARE, Z_SS_FRECHET, Z_COUNT };
+              Z_DD, Z_W1, Z_Y, Z_GRAD, Z_SS_SCALE, Z_SS_PADE, Z_SS_SOLVE, Z_SS_SQUARE, Z_SS_FRECHET, Z_ODD, Z_COUNT };
 const char* kZNames[Z_COUNT] = {"z_build_iA", "z_eigh",   "z_phase",  "zgemm_expA", "zgemm_C",   "zgemm_H0C",
                                 "z_rows",     "z_hub_n",  "z_hub_apply", "z_energy", "zgemm_HMO", "z_commutator",
                                 "zgemm_LV",   "zgemm_VhLV", "z_divdiff", "zgemm_W1",  "zgemm_Y",   "z_grad",
-                                "ss_scaling", "ss_pade",  "ss_solve", "ss_square", "ss_frechet"};
+                                "ss_scaling", "ss_pade",  "ss_solve", "ss_square", "ss_frechet",
+                                "z_orbital_term"};
 
 }  // namespace
 
@@ -396,6 +398,8 @@ struct etdm_handle {
   Stage fr_M2a, fr_M2b, fr_M4a, fr_M4b, fr_M6a, fr_M6b, fr_M8a, fr_M8b, fr_LUa, fr_LUb, fr_N;
   Stage fr_sq[2][3];  // per parity of the squaring step: R L, + L R, R R
   Stage fr_Y[2];      // Y = L_s exp(A)^H, by the parity of s
+  double odd_lam = 0.0;  // orbital-dependent model term (0: off)
+  Stage z_odd;           // W = VC^H C
   std::vector<Stage*> timer_stage;  // per timed stage: its GEMM launch, or null
   std::vector<Stage*> tune_extra;   // further stages with a kernel choice (inside a timed stage)
   // tracing
@@ -596,6 +600,10 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       for (double** q : {&b.sEs, &b.sM2, &b.sM4, &b.sM6, &b.sM8, &b.sLT, &b.sLV, &b.sLU, &b.sZc, &b.sR0, &b.sRa,
                          &b.sLa})
         *q = pl.take(fz);
+      const bool odd = h->odd_lam != 0.0;
+      b.oVC = pl.take(odd ? MM2 : 0);
+      b.oW = pl.take(odd ? MM2 : 0);
+      b.oE = pl.take(odd ? M : 0);
     }
     h->ss_norms = pl.take(h->expm_ss ? h->n_inst : 0);
     h->ss_s_dev = reinterpret_cast<int*>(pl.take(h->expm_ss ? 1 : 0));
@@ -944,6 +952,7 @@ etdm_status build_z_plan(etdm_handle* h) {
   h->z_W1.init(OP_N, OP_C, GP_FP64, true);
   h->z_Y.init(OP_N, OP_N, GP_FP64, true);
   h->z_HC0.init(OP_N, OP_N, GP_FP64, true);
+  h->z_odd.init(OP_C, OP_N, GP_FP64, true);
   for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_X8, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
     st->init(OP_N, OP_N, GP_FP64, true);
   const bool ss_exact = h->expm_ss && !h->grad_approx;
@@ -979,6 +988,13 @@ etdm_status build_z_plan(etdm_handle* h) {
     z.f = b.f;
     z.M = M;
     z.weight = h->w[i];
+    if (h->odd_lam != 0.0) {
+      z.VC = b.oVC;
+      z.W = b.oW;
+      z.eodd = b.oE;
+      z.lam = h->odd_lam;
+      h->z_odd.add(prob(M, M, M, b.oVC, M, b.C, M, b.oW, M));  // W[m][k] = <m|V^m|k>
+    }
     zi.push_back(z);
     bmat.push_back(h->tot_mat);
     h->tot_mat += M * M;
@@ -1118,6 +1134,7 @@ etdm_status build_z_plan(etdm_handle* h) {
     gs[Z_LT] = &h->z_Lt;
     gs[Z_W1] = &h->z_W1;
     gs[Z_Y] = &h->z_Y;
+    gs[Z_ODD] = &h->z_odd;
     h->timer_stage.assign(gs, gs + Z_COUNT);
     for (int i = 0; i < Z_COUNT; ++i)
       if (gs[i]) {
@@ -1155,8 +1172,8 @@ etdm_status build_z_plan(etdm_handle* h) {
     }
     h->timers[Z_SS_FRECHET].flops += h->timers[Z_SS_SOLVE].flops;
   }
-  Stage* stages[] = {&h->z_Ue, &h->z_C, &h->z_T,   &h->z_HMO, &h->z_LV,
-                     &h->z_Lt, &h->z_W1, &h->z_Y, &h->z_HC0, &h->z_HG, &h->z_HNS};
+  Stage* stages[] = {&h->z_Ue, &h->z_C, &h->z_T,   &h->z_HMO, &h->z_LV,  &h->z_Lt,
+                     &h->z_W1, &h->z_Y, &h->z_HC0, &h->z_HG,  &h->z_HNS, &h->z_odd};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
   for (int bk = 0; bk < h->herm_nblk; ++bk) {
     h->z_WY1[bk].init(OP_C, OP_N, GP_FP64, true);
@@ -1454,6 +1471,11 @@ void z_energy_grad(etdm_handle* h, hipStream_t s) {
   { TIMED(Z_C); h->z_C.launch(s); }
   { TIMED(Z_T); h->z_T.launch(s); }
   { TIMED(Z_ROWS); launch_z_rows(h->d_z, h->b_rows, h->n_inst, h->tot_rows, s); }
+  if (h->odd_lam != 0.0) {
+    TIMED(Z_ODD);
+    launch_z_odd_rows(h->d_z, h->b_rows, h->n_inst, h->tot_rows, s);
+    h->z_odd.launch(s);
+  }
   if (h->couple) {
     TIMED(Z_HUBN);
     launch_z_hubbard_density(h->d_z, h->n_inst, 1, h->nvec, h->M[0], s);
@@ -1467,6 +1489,10 @@ void z_energy_grad(etdm_handle* h, hipStream_t s) {
   }
   { TIMED(Z_HMO); h->z_HMO.launch(s); }
   { TIMED(Z_COMM); launch_z_commutator(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s); }
+  if (h->odd_lam != 0.0) {
+    TIMED(Z_ODD);
+    launch_z_odd_L(h->d_z, h->b_mat, h->n_inst, h->tot_mat, s);
+  }
   if (h->expm_ss && !h->grad_approx) {
     // Y = L(A, L) exp(A)^H through the Frechet derivative of the scaling and squaring
     TIMED(Z_SS_FRECHET);
@@ -1773,6 +1799,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (d->gradient != 0 && d->gradient != 1) return ETDM_E_ARG;
   if (d->expm_method != 0 && d->expm_method != 1) return ETDM_E_ARG;
   if (d->expm_method == 1 && d->kind != ETDM_COMPLEX_FULL) return ETDM_E_ARG;
+  if (!std::isfinite(d->odd_lambda) || (d->odd_lambda != 0.0 && d->kind != ETDM_COMPLEX_FULL)) return ETDM_E_ARG;
   if (d->kind == ETDM_REAL_OV && (!d->N || d->couple)) return ETDM_E_ARG;
   if (d->h0_format != 0 && d->h0_format != 1) return ETDM_E_ARG;
   if (d->h0_format == 1 && (d->kind != ETDM_REAL_OV || d->bsr_block < 1 || d->bsr_block > BSR_MAX_BS ||
@@ -1796,6 +1823,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   h->gemm_tuning = d->gemm_tuning;
   h->grad_approx = d->gradient;
   h->expm_ss = d->expm_method;
+  h->odd_lam = d->odd_lambda;
   h->U = d->hubbard_U;
   h->couple = d->couple ? 1 : 0;
   h->h0_format = d->h0_format;
@@ -2083,6 +2111,11 @@ uint64_t ckpt_layout(const etdm_handle* h) {
   mix(h->prec);
   mix(h->grad_approx);
   mix(h->expm_ss);
+  {
+    int64_t bits;
+    std::memcpy(&bits, &h->odd_lam, sizeof(bits));
+    mix(bits);
+  }
   mix(h->n_inst);
   for (int i = 0; i < h->n_inst; ++i) {
     mix(h->M[i]);

@@ -123,14 +123,55 @@ __global__ __launch_bounds__(256) void z_energy_kernel(const ZInst* __restrict__
                                                        double* E) {
   __shared__ double red[16];
   const ZInst& z = zi[blockIdx.x];
-  double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+  double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0, s3 = 0.0, c3 = 0.0;
   for (int mu = threadIdx.x; mu < z.M; mu += blockDim.x) {
     neumaier_add(s1, c1, z.e[mu]);
     if (!couple) neumaier_add(s2, c2, z.d[mu] * z.d[mu]);
+    if (z.eodd) neumaier_add(s3, c3, z.eodd[mu]);
   }
   const double band = block_sum_neumaier(s1, c1, red);
   const double hub = block_sum_neumaier(s2, c2, red);
-  if (threadIdx.x == 0) E[blockIdx.x] = z.weight * band + (couple ? 0.0 : 0.5 * U * hub);
+  const double odd = block_sum_neumaier(s3, c3, red);
+  if (threadIdx.x == 0)
+    E[blockIdx.x] = z.weight * band + (couple ? 0.0 : 0.5 * U * hub) - 0.5 * z.lam * z.weight * odd;
+}
+
+// orbital-dependent model term, one wave per row mu: VC[mu][k] = -lam |C_mu_k|^2 C_mu_k and
+// eodd[mu] = sum_k f_k |C_mu_k|^4
+__global__ __launch_bounds__(256) void z_odd_rows_kernel(const ZInst* __restrict__ zi, const int* __restrict__ begin,
+                                                         int n_inst, int total_rows) {
+  const int lane = threadIdx.x & 63;
+  const int row_g = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row_g >= total_rows) return;
+  const int ii = zfind(begin, n_inst, row_g);
+  const ZInst& z = zi[ii];
+  const int M = z.M, mu = row_g - begin[ii];
+  const double2* C = reinterpret_cast<const double2*>(z.C) + (size_t)mu * M;
+  double2* VC = reinterpret_cast<double2*>(z.VC) + (size_t)mu * M;
+  double e = 0.0;
+  for (int k = lane; k < M; k += 64) {
+    const double2 c = C[k];
+    const double a = c.x * c.x + c.y * c.y;
+    VC[k] = make_double2(-z.lam * a * c.x, -z.lam * a * c.y);
+    e += z.f[k] * a * a;
+  }
+  for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
+  if (lane == 0) z.eodd[mu] = e;
+}
+
+// L[m][k] += w (f_m W[m][k] - f_k conj(W[k][m])), W[m][k] = <m|V^m|k>
+__global__ void z_odd_L_kernel(const ZInst* __restrict__ zi, const int* __restrict__ begin, int n_inst, int total) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = zfind(begin, n_inst, idx);
+  const ZInst& z = zi[ii];
+  const int M = z.M, e = idx - begin[ii];
+  const int m = e / M, k = e - m * M;
+  const double2 wmk = reinterpret_cast<const double2*>(z.W)[e];
+  const double2 wkm = reinterpret_cast<const double2*>(z.W)[(size_t)k * M + m];
+  double2& l = reinterpret_cast<double2*>(z.L)[e];
+  l.x += z.weight * (z.f[m] * wmk.x - z.f[k] * wkm.x);
+  l.y += z.weight * (z.f[m] * wmk.y + z.f[k] * wkm.y);
 }
 
 // L[m][k] = w (f_m - f_k) H_MO[m][k], in place
@@ -208,6 +249,12 @@ void launch_z_energy(const ZInst* d, int n, int couple, double U, double* E, hip
 }
 void launch_z_commutator(const ZInst* d, const int* b, int n, int total, hipStream_t s) {
   if (total > 0) z_commutator_kernel<<<zb(total, 256), 256, 0, s>>>(d, b, n, total);
+}
+void launch_z_odd_rows(const ZInst* d, const int* b, int n, int rows, hipStream_t s) {
+  if (rows > 0) z_odd_rows_kernel<<<zb(rows, 4), 256, 0, s>>>(d, b, n, rows);
+}
+void launch_z_odd_L(const ZInst* d, const int* b, int n, int total, hipStream_t s) {
+  if (total > 0) z_odd_L_kernel<<<zb(total, 256), 256, 0, s>>>(d, b, n, total);
 }
 void launch_z_divdiff(const ZInst* d, const int* b, int n, int total, hipStream_t s) {
   if (total > 0) z_divdiff_kernel<<<zb(total, 256), 256, 0, s>>>(d, b, n, total);

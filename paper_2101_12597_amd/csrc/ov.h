@@ -89,6 +89,12 @@ struct ZInst {
   const double* f;   // occupations [M]
   int32_t M;
   double weight;
+  // orbital-dependent model term (null eodd: off): VC = -lam |C|^2 o C, W = VC^H C,
+  // eodd[mu] = sum_k f_k |C_mu_k|^4
+  double* VC;
+  const double* W;
+  double* eodd;
+  double lam;
 };
 
 void launch_z_build_iA(const ZInst* d, const int* d_begin, int n_inst, int total, hipStream_t s);
@@ -99,6 +105,10 @@ void launch_z_apply_hubbard(const ZInst* d, const int* d_begin, int n_inst, int 
                             hipStream_t s);
 void launch_z_energy(const ZInst* d, int n_inst, int couple, double U, double* E, hipStream_t s);
 void launch_z_commutator(const ZInst* d, const int* d_begin, int n_inst, int total, hipStream_t s);
+// orbital-dependent model term: VC and eodd per row (one wave per row)
+void launch_z_odd_rows(const ZInst* d, const int* d_begin_rows, int n_inst, int total_rows, hipStream_t s);
+// L[m][k] += w (f_m W[m][k] - f_k conj(W[k][m]))
+void launch_z_odd_L(const ZInst* d, const int* d_begin, int n_inst, int total, hipStream_t s);
 void launch_z_divdiff(const ZInst* d, const int* d_begin, int n_inst, int total, hipStream_t s);
 void launch_z_grad(const ZInst* d, const int* d_begin, int n_inst, int total, int* status, hipStream_t s);
 

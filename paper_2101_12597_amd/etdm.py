@@ -53,6 +53,7 @@ class _Desc(ctypes.Structure):
         ("gemm_tuning", ctypes.c_int32),
         ("gradient", ctypes.c_int32),
         ("expm_method", ctypes.c_int32),
+        ("odd_lambda", ctypes.c_double),
     ]
 
 
@@ -182,12 +183,14 @@ class Handle:
     expm : "eig" (eigendecomposition of iA, Eq. ed) or "ss" (scaling and squaring with a
            Pade approximant, Eq. ss, and its Frechet derivative for the exact gradient;
            complex kind)
+    odd_lambda : strength of the orbital-dependent model term (complex kind; 0 = off)
     """
 
     def __init__(self, M: Sequence[int], N: Optional[Sequence[int]], kind: str, precision: str,
                  hubbard_U: float, H0, C0, f: np.ndarray, couple: bool = False,
                  weights: Optional[Sequence[float]] = None, bsr=None, stream=None,
-                 gemm_tuning: int = 0, gradient: str = "exact", expm: str = "eig"):
+                 gemm_tuning: int = 0, gradient: str = "exact", expm: str = "eig",
+                 odd_lambda: float = 0.0):
         L = load_library()
         self._L = L
         n = len(M)
@@ -212,6 +215,7 @@ class Handle:
         if expm not in ("eig", "ss"):
             raise ValueError("expm must be 'eig' or 'ss'")
         d.expm_method = 1 if expm == "ss" else 0
+        d.odd_lambda = float(odd_lambda)
         if bsr is not None:
             blk, rp, ci = bsr
             self._rp = np.ascontiguousarray(rp, dtype=np.int32)

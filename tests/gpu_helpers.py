@@ -12,7 +12,8 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
-def make_handle(wl, precision="fp64", use_bsr=False, gemm_tuning=0, gradient="exact", expm="eig"):
+def make_handle(wl, precision="fp64", use_bsr=False, gemm_tuning=0, gradient="exact", expm="eig",
+                odd_lambda=0.0):
     torch, dev = torch_dev()
     from paper_2101_12597_amd import Handle
     pk = pack(wl, use_bsr=use_bsr)
@@ -20,7 +21,7 @@ def make_handle(wl, precision="fp64", use_bsr=False, gemm_tuning=0, gradient="ex
     C0 = torch.from_numpy(pk["C0"]).to(dev)
     h = Handle(pk["M"], pk["N"], wl.kind, precision, wl.hubbard_U, H0, C0, pk["f"],
                couple=wl.couple, weights=pk["weights"], bsr=pk["bsr"], gemm_tuning=gemm_tuning,
-               gradient=gradient, expm=expm)
+               gradient=gradient, expm=expm, odd_lambda=odd_lambda)
     torch.cuda.synchronize()
     return h, pk
 

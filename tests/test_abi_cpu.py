@@ -54,11 +54,11 @@ def test_host_only_calls(repo_root):
 
 @pytest.mark.parametrize("field,bad", [("gemm_tuning", -1), ("gemm_tuning", 7), ("gradient", -1),
                                        ("gradient", 2), ("expm_method", -1), ("expm_method", 2),
-                                       ("expm_method", 1)])
+                                       ("expm_method", 1), ("odd_lambda", 0.5), ("odd_lambda", float("nan"))])
 def test_create_rejects_bad_mode_fields(repo_root, field, bad):
     """gemm_tuning outside 0..6, gradient or expm_method outside {0, 1}, and scaling and
-    squaring on the real kind (it needs COMPLEX_FULL with the approximate gradient) are
-    argument errors, found before any device call."""
+    squaring or the orbital-dependent term on the real kind (both need COMPLEX_FULL),
+    and a non-finite term strength are argument errors, found before any device call."""
     from paper_2101_12597_amd import LIB_PATH, load_library
     from paper_2101_12597_amd.etdm import _Desc
     if not os.path.exists(LIB_PATH):
