@@ -200,17 +200,37 @@ def divided_difference_factor(w: np.ndarray) -> np.ndarray:
     return np.exp(-0.5j * x) * _sinc(0.5 * x)
 
 
+def overlap_sqrt(inst):
+    """S^(1/2) of a non-orthogonal basis (principal square root through eigh), or None."""
+    if inst.S is None:
+        return None
+    s, V = np.linalg.eigh(inst.S)
+    return (V * np.sqrt(s)[None, :]) @ V.conj().T
+
+
 def _densities(wl, params, expm=None):
-    """Current orbitals C = C0 exp(A) and the diagonals of rho = C F C^dagger; exp(A) by
-    the eigendecomposition of iA unless another exponential is given."""
+    """Current orbitals C = C0 exp(A) and the site populations n_mu: the diagonal of
+    rho = C F C^dagger, or in a non-orthogonal basis (C^dagger S C = I, Sec. 2) the Lowdin
+    populations, the diagonal of S^(1/2) rho S^(1/2) (reading: the model's site density
+    with S != I).  exp(A) by the eigendecomposition of iA unless another is given."""
     expm = expm or expm_eig
     Cs, ds = [], []
     for inst, a in zip(wl.instances, params):
         A = generator(wl.kind, a)
         C = inst.C0 @ expm(A)
         Cs.append(C)
-        ds.append((np.abs(C) ** 2 * inst.f[None, :]).sum(axis=1))
+        Sh = overlap_sqrt(inst)
+        Cd = C if Sh is None else Sh @ C
+        ds.append((np.abs(Cd) ** 2 * inst.f[None, :]).sum(axis=1))
     return Cs, ds
+
+
+def _hamiltonian(inst, n, hubbard_U):
+    """H = dE/drho^T: H0 + U diag(n), or H0 + U S^(1/2) diag(n) S^(1/2) with an overlap."""
+    Sh = overlap_sqrt(inst)
+    if Sh is None:
+        return inst.h0_dense() + hubbard_U * np.diag(n)
+    return inst.h0_dense() + hubbard_U * (Sh * n[None, :]) @ Sh
 
 
 def _hubbard_density(wl, ds):
@@ -253,7 +273,7 @@ def energy_grad(wl, params) -> Tuple[float, List[np.ndarray]]:
     grads = []
     for inst, a, C, n in zip(wl.instances, params, Cs, ns):
         A = generator(wl.kind, a)
-        H = inst.h0_dense() + wl.hubbard_U * np.diag(n)
+        H = _hamiltonian(inst, n, wl.hubbard_U)
         H_MO = C.conj().T @ H @ C
         F = np.diag(inst.f)
         L = inst.weight * (F @ H_MO - H_MO @ F)
@@ -286,7 +306,7 @@ def energy_grad_approx(wl, params, expm=None) -> Tuple[float, List[np.ndarray]]:
     E = energy(wl, params, expm)
     grads = []
     for inst, C, n in zip(wl.instances, Cs, ns):
-        H = inst.h0_dense() + wl.hubbard_U * np.diag(n)
+        H = _hamiltonian(inst, n, wl.hubbard_U)
         H_MO = C.conj().T @ H @ C
         F = np.diag(inst.f)
         L = inst.weight * (F @ H_MO - H_MO @ F)
@@ -312,7 +332,7 @@ def energy_grad_ss(wl, params) -> Tuple[float, List[np.ndarray]]:
     E = energy(wl, params, expm_ss)
     grads = []
     for inst, a, C, n in zip(wl.instances, params, Cs, ns):
-        H = inst.h0_dense() + wl.hubbard_U * np.diag(n)
+        H = _hamiltonian(inst, n, wl.hubbard_U)
         H_MO = C.conj().T @ H @ C
         F = np.diag(inst.f)
         L = inst.weight * (F @ H_MO - H_MO @ F)
@@ -370,7 +390,7 @@ def energy_grad_odd(wl, params, lam: float, printed_indices: bool = False) -> Tu
     E = energy_odd(wl, params, lam)
     grads = []
     for inst, a, C, n in zip(wl.instances, params, Cs, ns):
-        H = inst.h0_dense() + wl.hubbard_U * np.diag(n)
+        H = _hamiltonian(inst, n, wl.hubbard_U)
         H_MO = C.conj().T @ H @ C
         F = np.diag(inst.f)
         V = orbital_potential_elements(C, lam)
@@ -415,7 +435,7 @@ def y_matrix(wl, params, idx: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     ns = _hubbard_density(wl, ds)
     inst, a, C, n = wl.instances[idx], params[idx], Cs[idx], ns[idx]
     A = generator(wl.kind, a)
-    H = inst.h0_dense() + wl.hubbard_U * np.diag(n)
+    H = _hamiltonian(inst, n, wl.hubbard_U)
     H_MO = C.conj().T @ H @ C
     F = np.diag(inst.f)
     L = inst.weight * (F @ H_MO - H_MO @ F)
@@ -473,6 +493,7 @@ def energy_grad_ov(inst, B: np.ndarray, hubbard_U: float, want_parts: bool = Fal
     """
     N, Nv = B.shape
     M = N + Nv
+    assert inst.S is None, "the structured path takes an orthonormal basis"
     f_occ = float(inst.f[0])
     assert np.all(inst.f[:N] == f_occ) and np.all(inst.f[N:] == 0.0)
     s, X = np.linalg.eigh(B @ B.T)
@@ -551,7 +572,7 @@ def orbital_energies(wl) -> List[np.ndarray]:
     ns = _hubbard_density(wl, ds)
     out = []
     for inst, C, n in zip(wl.instances, Cs, ns):
-        H = inst.h0_dense() + wl.hubbard_U * np.diag(n)
+        H = _hamiltonian(inst, n, wl.hubbard_U)
         out.append(np.real(np.diag(C.conj().T @ H @ C)))
     return out
 

@@ -11,5 +11,6 @@ from .gen import (  # noqa: F401
     make_config,
     tiny_real,
     tiny_complex,
+    with_overlap,
     CONFIG_NAMES,
 )

@@ -82,6 +82,7 @@ class Instance:
     weight: float = 1.0
     H0: Optional[np.ndarray] = None  # dense [M, M]
     H0_bsr: Optional[BSR] = None
+    S: Optional[np.ndarray] = None  # overlap of a non-orthogonal basis [M, M] (None: S = I)
 
     def h0_dense(self) -> np.ndarray:
         if self.H0 is not None:
@@ -293,6 +294,31 @@ def tiny_real(M: int, N: int, seed: int = 0, scale: float = 0.05, hubbard_U: flo
         C0 = haar_orthogonal(M, rng_for(100 + seed, i, 1))
         B = ov_parameters(N, M - N, rng_for(100 + seed, i, 2), scale)
         wl.instances.append(Instance(M=M, N=N, f=binary_occupations(M, N), C0=C0, A=B, H0=H0))
+    return wl
+
+
+def with_overlap(wl: Workload, strength: float = 0.15, seed: int = 0) -> Workload:
+    """The same workload in a non-orthogonal basis: per instance an overlap
+    S = I + strength * (symmetric / Hermitian with exponentially decaying entries),
+    kept positive definite, and reference orbitals C0 = L^-H Q with S = L L^H (Cholesky)
+    and Q the instance's orthonormal C0, so that C0^H S C0 = I.  H0 is reused as the
+    Hamiltonian in the non-orthogonal basis."""
+    for i, inst in enumerate(wl.instances):
+        rng = rng_for(300 + seed, i, 0)
+        M = inst.M
+        R = rng.standard_normal((M, M))
+        if wl.kind != "real_ov":
+            R = R + 1j * rng.standard_normal((M, M))
+        dist = np.abs(np.arange(M)[:, None] - np.arange(M)[None, :])
+        R = R * np.exp(-dist / 3.0) / np.sqrt(M)
+        S = np.eye(M) + strength * (R + R.conj().T) / 2.0
+        lo = np.linalg.eigvalsh(S).min()
+        if lo < 0.2:
+            S = S + (0.2 - lo) * np.eye(M)
+        L = np.linalg.cholesky(S)
+        inst.S = S
+        inst.C0 = np.linalg.solve(L.conj().T, inst.C0)
+    wl.name += " (non-orthogonal basis)"
     return wl
 
 

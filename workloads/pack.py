@@ -36,6 +36,8 @@ def pack(wl, use_bsr: bool = False) -> Dict[str, object]:
         out["bsr"] = None
     out["A"] = pack_params(wl, [inst.A if wl.kind == "real_ov" else np.triu(inst.A)
                                 for inst in wl.instances])
+    out["S"] = (np.concatenate([_flat(inst.S) for inst in wl.instances])
+                if any(inst.S is not None for inst in wl.instances) else None)
     return out
 
 
