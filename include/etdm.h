@@ -122,6 +122,16 @@ typedef struct {
                              L_mk += w (f_m conj(V_km) - f_k V_mk), V^k = diag(-lambda
                              |C_mu_k|^2).  0 = off; nonzero needs COMPLEX_FULL (the ov form
                              assumes unitary invariance).  Non-finite: ETDM_E_ARG */
+  const void *overlap;    /* NULL: orthonormal basis.  Else device, the overlap S of a
+                             non-orthogonal basis (Sec. 2: C^H S C = I), layout of a dense H0
+                             (M x M per instance, float64 or complex), Hermitian positive
+                             definite; C0 must be S-orthonormal and H0 (dense only) is in the
+                             same basis.  The site populations of the Hubbard term become
+                             diag(S^1/2 rho S^1/2).  etdm_create applies the Lowdin transform
+                             H0 <- S^-1/2 H0 S^-1/2, C0 <- S^1/2 C0 once (Newton-Schulz for
+                             S^+-1/2); afterwards the handle works in that orthonormal basis.
+                             ETDM_E_ARG if S is not positive definite to working accuracy
+                             or with a block-sparse H0 */
 } etdm_desc;
 
 /* Create a handle.  H0: device, dense float64 (REAL_OV) or complex float64

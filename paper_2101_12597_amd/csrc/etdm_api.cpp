@@ -18,6 +18,7 @@
 #include "eigh_large.h"
 #include "lbfgs.h"
 #include "expm_ss.h"
+#include "overlap.h"
 
 using namespace etdm;
 
@@ -399,6 +400,7 @@ struct etdm_handle {
   Stage fr_sq[2][3];  // per parity of the squaring step: R L, + L R, R R
   Stage fr_Y[2];      // Y = L_s exp(A)^H, by the parity of s
   double odd_lam = 0.0;  // orbital-dependent model term (0: off)
+  int has_overlap = 0;   // created from a non-orthogonal basis (H0, C0 Lowdin-transformed)
   Stage z_odd;           // W = VC^H C
   std::vector<Stage*> timer_stage;  // per timed stage: its GEMM launch, or null
   std::vector<Stage*> tune_extra;   // further stages with a kernel choice (inside a timed stage)
@@ -1745,6 +1747,107 @@ etdm_status lb_start(etdm_handle* h, double beta0, int set_beta, hipStream_t s) 
   return ETDM_OK;
 }
 
+// Lowdin transform of a non-orthogonal basis (overlap S, device, dense-H0 layout):
+// S^1/2 and S^-1/2 by the coupled Newton-Schulz iteration on S / c, then
+// H0 <- S^-1/2 H0 S^-1/2 and C0 <- S^1/2 C0 in the instance buffers.  Creation-time
+// work with its own workspace, freed before returning.
+etdm_status apply_overlap(etdm_handle* h, const void* S, hipStream_t s) {
+  const bool cplx = h->kind != ETDM_REAL_OV;
+  const int64_t esz = cplx ? 2 : 1;  // doubles per element
+  int64_t doubles = 0;
+  int total = 0;
+  std::vector<int> begin;
+  for (int i = 0; i < h->n_inst; ++i) {
+    doubles += 7 * (int64_t)h->M[i] * h->M[i] * esz + 1;
+    begin.push_back(total);
+    total += h->M[i] * h->M[i];
+  }
+  double* ws = nullptr;
+  double* resid_host = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&ws), (size_t)(doubles + h->n_inst) * sizeof(double)) != hipSuccess)
+    return fail(h, ETDM_E_NOMEM, "overlap workspace");
+  if (hipHostMalloc(reinterpret_cast<void**>(&resid_host), h->n_inst * sizeof(double)) != hipSuccess) {
+    hipFree(ws);
+    return fail(h, ETDM_E_NOMEM, "overlap workspace");
+  }
+  struct Release {  // waits for the stream, also on an early error return
+    double *a, *b;
+    hipStream_t s;
+    ~Release() {
+      (void)hipStreamSynchronize(s);
+      hipFree(a);
+      hipHostFree(b);
+    }
+  } release{ws, resid_host, s};
+  double* resid_dev = ws + doubles;
+  std::vector<OvlInst> tab[2];
+  Stage prodP[2], prodY[2], prodZ[2], finW[2], finH[2], finC[2];
+  for (int p = 0; p < 2; ++p)
+    for (Stage* st : {&prodP[p], &prodY[p], &prodZ[p], &finW[p], &finH[p], &finC[p]})
+      st->init(OP_N, OP_N, GP_FP64, cplx);
+  std::vector<double*> c0s, pbuf;
+  const double* Sp = static_cast<const double*>(S);
+  double* cur = ws;
+  for (int i = 0; i < h->n_inst; ++i) {
+    const int M = h->M[i];
+    const int64_t mm = (int64_t)M * M * esz;
+    double *Y0 = cur, *Y1 = cur + mm, *Z0 = cur + 2 * mm, *Z1 = cur + 3 * mm, *P = cur + 4 * mm, *T = cur + 5 * mm,
+           *W = cur + 6 * mm, *c = cur + 7 * mm;
+    cur += 7 * mm + 1;
+    double* H0 = cplx ? h->zb[i].H0 : h->ov[i].H0;
+    double* C0 = cplx ? h->zb[i].C0 : h->ov[i].C0;
+    tab[0].push_back(OvlInst{Sp, Y0, Z0, P, T, c, M});
+    tab[1].push_back(OvlInst{Sp, Y1, Z1, P, T, c, M});
+    Sp += mm;
+    double* Yb[2] = {Y0, Y1};
+    double* Zb[2] = {Z0, Z1};
+    for (int p = 0; p < 2; ++p) {
+      prodP[p].add(prob(M, M, M, Zb[p], M, Yb[p], M, P, M));          // P = Z Y
+      prodY[p].add(prob(M, M, M, Yb[p], M, T, M, Yb[1 - p], M));      // Y <- Y T
+      prodZ[p].add(prob(M, M, M, T, M, Zb[p], M, Zb[1 - p], M));      // Z <- T Z
+      finW[p].add(prob(M, M, M, Zb[p], M, H0, M, W, M));              // S^-1/2 H0
+      finH[p].add(prob(M, M, M, W, M, Zb[p], M, H0, M));              // (.) S^-1/2
+      finC[p].add(prob(M, M, M, Yb[p], M, C0, M, P, M));              // S^1/2 C0, via P
+    }
+    c0s.push_back(C0);
+    pbuf.push_back(P);
+  }
+  OvlInst* d_tab[2] = {nullptr, nullptr};
+  int* d_begin = nullptr;
+  for (int p = 0; p < 2; ++p) {
+    CHECK(upload(h, &d_tab[p], tab[p]));
+    for (Stage* st : {&prodP[p], &prodY[p], &prodZ[p], &finW[p], &finH[p], &finC[p]}) CHECK(upload_stage(h, *st));
+  }
+  CHECK(upload(h, &d_begin, begin));
+  launch_ovl_start(d_tab[0], d_begin, h->n_inst, total, cplx, s);
+  int p = 0;
+  bool converged = false;
+  for (int it = 0; it < 80 && !converged; ++it) {
+    prodP[p].launch(s);
+    launch_ovl_step(d_tab[p], h->n_inst, cplx, resid_dev, s);
+    HIPCHK(h, hipMemcpyAsync(resid_host, resid_dev, h->n_inst * sizeof(double), hipMemcpyDeviceToHost, s));
+    prodY[p].launch(s);
+    prodZ[p].launch(s);
+    HIPCHK(h, hipStreamSynchronize(s));
+    p = 1 - p;
+    double r = 0.0;
+    for (int i = 0; i < h->n_inst; ++i) r = std::isfinite(resid_host[i]) ? std::max(r, resid_host[i]) : 1e300;
+    if (r > 1e6) break;  // diverging: not positive definite
+    converged = r <= 1e-10;
+  }
+  if (!converged) return fail(h, ETDM_E_ARG, "overlap not positive definite to working accuracy");
+  launch_ovl_finish(d_tab[p], d_begin, h->n_inst, total, cplx, s);
+  finW[p].launch(s);
+  finH[p].launch(s);
+  finC[p].launch(s);
+  for (int i = 0; i < h->n_inst; ++i)
+    HIPCHK(h, hipMemcpyAsync(c0s[i], pbuf[i], (size_t)h->M[i] * h->M[i] * esz * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(s));
+  return ETDM_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1800,6 +1903,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (d->expm_method != 0 && d->expm_method != 1) return ETDM_E_ARG;
   if (d->expm_method == 1 && d->kind != ETDM_COMPLEX_FULL) return ETDM_E_ARG;
   if (!std::isfinite(d->odd_lambda) || (d->odd_lambda != 0.0 && d->kind != ETDM_COMPLEX_FULL)) return ETDM_E_ARG;
+  if (d->overlap && d->h0_format != 0) return ETDM_E_ARG;
   if (d->kind == ETDM_REAL_OV && (!d->N || d->couple)) return ETDM_E_ARG;
   if (d->h0_format != 0 && d->h0_format != 1) return ETDM_E_ARG;
   if (d->h0_format == 1 && (d->kind != ETDM_REAL_OV || d->bsr_block < 1 || d->bsr_block > BSR_MAX_BS ||
@@ -1824,6 +1928,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   h->grad_approx = d->gradient;
   h->expm_ss = d->expm_method;
   h->odd_lam = d->odd_lambda;
+  h->has_overlap = d->overlap != nullptr;
   h->U = d->hubbard_U;
   h->couple = d->couple ? 1 : 0;
   h->h0_format = d->h0_format;
@@ -1935,6 +2040,10 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
     h0 += (size_t)nnzb * bs * bs * sizeof(double);
     row_off += nbr + 1;
     blk_off += nnzb;
+  }
+  if (d->overlap) {
+    const etdm_status so = apply_overlap(h, d->overlap, s);
+    if (so != ETDM_OK) return bail(so);
   }
   etdm_status st = real ? build_ov_plan(h) : build_z_plan(h);
   if (st == ETDM_OK) {
@@ -2111,6 +2220,7 @@ uint64_t ckpt_layout(const etdm_handle* h) {
   mix(h->prec);
   mix(h->grad_approx);
   mix(h->expm_ss);
+  mix(h->has_overlap);
   {
     int64_t bits;
     std::memcpy(&bits, &h->odd_lam, sizeof(bits));

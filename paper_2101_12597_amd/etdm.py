@@ -54,6 +54,7 @@ class _Desc(ctypes.Structure):
         ("gradient", ctypes.c_int32),
         ("expm_method", ctypes.c_int32),
         ("odd_lambda", ctypes.c_double),
+        ("overlap", ctypes.c_void_p),
     ]
 
 
@@ -184,13 +185,15 @@ class Handle:
            Pade approximant, Eq. ss, and its Frechet derivative for the exact gradient;
            complex kind)
     odd_lambda : strength of the orbital-dependent model term (complex kind; 0 = off)
+    overlap : device tensor, the overlap S of a non-orthogonal basis (layout of a dense H0),
+              or None for an orthonormal basis
     """
 
     def __init__(self, M: Sequence[int], N: Optional[Sequence[int]], kind: str, precision: str,
                  hubbard_U: float, H0, C0, f: np.ndarray, couple: bool = False,
                  weights: Optional[Sequence[float]] = None, bsr=None, stream=None,
                  gemm_tuning: int = 0, gradient: str = "exact", expm: str = "eig",
-                 odd_lambda: float = 0.0):
+                 odd_lambda: float = 0.0, overlap=None):
         L = load_library()
         self._L = L
         n = len(M)
@@ -216,6 +219,7 @@ class Handle:
             raise ValueError("expm must be 'eig' or 'ss'")
         d.expm_method = 1 if expm == "ss" else 0
         d.odd_lambda = float(odd_lambda)
+        d.overlap = _dptr(overlap) if overlap is not None else None
         if bsr is not None:
             blk, rp, ci = bsr
             self._rp = np.ascontiguousarray(rp, dtype=np.int32)

@@ -19,9 +19,10 @@ def make_handle(wl, precision="fp64", use_bsr=False, gemm_tuning=0, gradient="ex
     pk = pack(wl, use_bsr=use_bsr)
     H0 = torch.from_numpy(pk["H0"]).to(dev)
     C0 = torch.from_numpy(pk["C0"]).to(dev)
+    S = torch.from_numpy(pk["S"]).to(dev) if pk.get("S") is not None else None
     h = Handle(pk["M"], pk["N"], wl.kind, precision, wl.hubbard_U, H0, C0, pk["f"],
                couple=wl.couple, weights=pk["weights"], bsr=pk["bsr"], gemm_tuning=gemm_tuning,
-               gradient=gradient, expm=expm, odd_lambda=odd_lambda)
+               gradient=gradient, expm=expm, odd_lambda=odd_lambda, overlap=S)
     torch.cuda.synchronize()
     return h, pk
 
