@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--expm", default="eig", choices=("eig", "ss"),
                     help="exp(A) through eigh(iA) (Eq. ed) or scaling and squaring with a Pade "
                          "approximant (Eq. ss; complex workloads with --gradient approx)")
+    ap.add_argument("--overlap", action="store_true",
+                    help="the workload in a non-orthogonal basis (dense-H0 workloads)")
     ap.add_argument("--odd-lambda", type=float, default=0.0,
                     help="strength of the orbital-dependent model term (complex workloads)")
     ap.add_argument("--gradient", default="exact", choices=("exact", "approx"),
@@ -81,13 +83,14 @@ def build_handle(wl, precision, gemm_tuning=0, gradient="exact", expm="eig", odd
     dev = torch.device("cuda:0")
     H0 = torch.from_numpy(pk["H0"]).to(dev)
     C0 = torch.from_numpy(pk["C0"]).to(dev)
+    S = torch.from_numpy(pk["S"]).to(dev) if pk.get("S") is not None else None
     h = Handle(pk["M"], pk["N"], wl.kind, precision, wl.hubbard_U, H0, C0, pk["f"],
                couple=wl.couple, weights=pk["weights"], bsr=pk["bsr"], gemm_tuning=gemm_tuning,
-               gradient=gradient, expm=expm, odd_lambda=odd_lambda)
+               gradient=gradient, expm=expm, odd_lambda=odd_lambda, overlap=S)
     A = torch.from_numpy(pk["A"]).to(dev)
     E = torch.empty(h.n_inst + 1, dtype=torch.float64, device=dev)
     G = torch.empty_like(A)
-    del H0, C0
+    del H0, C0, S
     torch.cuda.synchronize()
     return h, A, E, G
 
@@ -228,9 +231,14 @@ def main():
     prec = args.precision or DEFAULT_PREC[cfg]
     log(f"generating config {cfg}")
     wl = make_config(cfg)
+    if args.overlap:
+        from workloads import with_overlap
+        wl = with_overlap(wl)
     params = O.parity_params(wl)
     log("creating the handle")
+    t_create = time.perf_counter()
     h, A, E, G = build_handle(wl, prec, args.gemm_tuning, args.gradient, args.expm, args.odd_lambda)
+    t_create = time.perf_counter() - t_create
     log("stage profile")
 
     # which stage dominates: time every stage over a few evaluations
@@ -306,7 +314,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[cfg], "precision": prec, "instances": len(wl.instances),
                    "electrons": wl.n_electrons, "gradient": args.gradient, "expm": args.expm,
-                   "odd_lambda": args.odd_lambda},
+                   "odd_lambda": args.odd_lambda, "overlap": args.overlap},
+        "create_ms": t_create * 1e3,
         "tflops": total_flops / sec / 1e12,
         "ms_per_step_eager": sec_eager * 1e3,
         "roofline": roof,
