@@ -342,6 +342,12 @@ struct etdm_handle {
   std::vector<EighLarge> eig_large;  // real problems above the LDS size
   const double** d_n0ptr = nullptr;
   double* d_wts = nullptr;
+  // preconditioner set-up of the whole batch (per-instance table, element offsets of
+  // the free variables), and the ov reference update C0 <- [C_occ | C_virt]
+  PrecInst* d_prec = nullptr;
+  int* b_prec = nullptr;
+  int tot_prec = 0;
+  C0Inst* d_c0up = nullptr;
   // grouped GEMM launches
   Stage s_PQ, s_Q1, s_F3mu, s_C, s_Z, s_V, s_Lov, s_R, s_Gam1, s_Gam, s_Y1, s_Y2, s_G;  // real: energy+gradient
   // Q1 = C0_v B^T does not depend on the eigendecomposition: it runs on a side
@@ -926,6 +932,27 @@ etdm_status build_ov_plan(etdm_handle* h) {
   CHECK(upload(h, &h->b_spec, bspec));
   CHECK(upload(h, &h->d_rows, rows));
   CHECK(upload(h, &h->b_rows, brows));
+  {
+    // preconditioner set-up and reference update of the whole batch
+    std::vector<PrecInst> pi;
+    std::vector<C0Inst> ci;
+    std::vector<int> bprec, bmm;
+    for (int i = 0; i < h->n_inst; ++i) {
+      const int M = h->M[i], N = h->N[i];
+      const OvBuf& b = h->ov[i];
+      pi.push_back(PrecInst{b.C0, b.HC0, b.f, b.n0, b.n0, b.eps, h->hd + h->par_off[i], h->wv + h->par_off[i], M, N,
+                            h->w[i]});
+      ci.push_back(C0Inst{b.C0, b.Cocc, b.Cvirt, M, N});
+      bprec.push_back(h->tot_prec);
+      h->tot_prec += N * (M - N);
+      bmm.push_back(h->tot_mat);
+      h->tot_mat += M * M;
+    }
+    CHECK(upload(h, &h->d_prec, pi));
+    CHECK(upload(h, &h->b_prec, bprec));
+    CHECK(upload(h, &h->d_c0up, ci));
+    CHECK(upload(h, &h->b_mat, bmm));
+  }
   CHECK(upload(h, &h->d_energy, en));
   CHECK(upload(h, &h->d_pair, pair));
   CHECK(upload(h, &h->b_pair, bpair));
@@ -1188,6 +1215,18 @@ etdm_status build_z_plan(etdm_handle* h) {
   CHECK(upload(h, &h->d_z, zi));
   CHECK(upload(h, &h->b_mat, bmat));
   CHECK(upload(h, &h->b_rows, brows));
+  {
+    // preconditioner set-up of the whole batch (H0 C0 lands in LV)
+    std::vector<PrecInst> pi;
+    for (int i = 0; i < h->n_inst; ++i) {
+      const ZBuf& b = h->zb[i];
+      pi.push_back(PrecInst{b.C0, b.LV, b.f, b.n0, h->couple ? h->nvec : b.n0, b.eps, h->hd + h->par_off[i],
+                            h->wv + h->par_off[i], h->M[i], h->N[i], h->w[i]});
+    }
+    h->tot_prec = h->tot_mat;
+    h->b_prec = h->b_mat;
+    CHECK(upload(h, &h->d_prec, pi));
+  }
   CHECK(upload(h, &h->d_eig_glb, eg));
   if (!eh.empty()) {
     CHECK(upload(h, &h->d_eig_herm, eh));
@@ -1393,12 +1432,7 @@ void ov_new_reference(etdm_handle* h, hipStream_t s) {
   h->s_C.launch(s);
   h->s_Z.launch(s);
   h->s_V.launch(s);
-  for (int i = 0; i < h->n_inst; ++i) {
-    const OvBuf& b = h->ov[i];
-    const int M = h->M[i], N = h->N[i];
-    launch_copy_block(b.C0, M, b.Cocc, N, M, N, 1.0, s);
-    launch_copy_block(b.C0 + N, M, b.Cvirt, M - N, M, M - N, 1.0, s);
-  }
+  launch_c0_update(h->d_c0up, h->b_mat, h->n_inst, h->tot_mat, s);
   if (h->h0_format == 0) h->s_HC0.launch(s);  // H0 C0 for the new reference
 }
 
@@ -1610,30 +1644,18 @@ etdm_status check_status(etdm_handle* h, hipStream_t s) {
 // reference orbitals: eps_i = diag(C0^H H(rho0) C0),
 // h_ij = w * max(0, -2 (eps_i - eps_j)(f_i - f_j)).
 void build_hdiag(etdm_handle* h, hipStream_t s) {
-  if (h->kind == ETDM_REAL_OV) {
+  const bool real = h->kind == ETDM_REAL_OV;
+  if (real) {
     h->s_HC0.launch(s);
     if (h->h0_format == 1)
       for (int i = 0; i < h->n_inst; ++i)
         launch_bsr_spmm(h->ov[i].H0_bsr, h->ov[i].C0, h->M[i], h->M[i], h->ov[i].HC0, h->M[i], s);
-    for (int i = 0; i < h->n_inst; ++i) {
-      const int M = h->M[i], N = h->N[i];
-      const OvBuf& b = h->ov[i];
-      launch_occ_density(b.C0, b.f, M, 0, b.n0, s);
-      launch_column_eps(b.C0, b.HC0, b.n0, h->U, M, 0, b.eps, s);
-      launch_hdiag_ov(h->hd + h->par_off[i], b.eps, b.f, M, N, h->w[i], s);
-      launch_fill(h->wv + h->par_off[i], (int64_t)N * (M - N), h->w[i], s);
-    }
-    return;
+  } else {
+    h->z_HC0.launch(s);
   }
-  h->z_HC0.launch(s);
-  for (int i = 0; i < h->n_inst; ++i) launch_occ_density(h->zb[i].C0, h->zb[i].f, h->M[i], 1, h->zb[i].n0, s);
-  if (h->couple) launch_weighted_vsum(h->d_n0ptr, h->d_wts, h->n_inst, h->M[0], h->nvec, s);
-  for (int i = 0; i < h->n_inst; ++i) {
-    const ZBuf& b = h->zb[i];
-    const int M = h->M[i];
-    launch_column_eps(b.C0, b.LV, h->couple ? h->nvec : b.n0, h->U, M, 1, b.eps, s);
-    launch_hdiag_z(h->hd + h->par_off[i], h->wv + h->par_off[i], b.eps, b.f, M, h->w[i], s);
-  }
+  const bool coupled = !real && h->couple;
+  launch_prec_setup(h->d_prec, h->b_rows, h->tot_rows, h->b_prec, h->tot_prec, h->n_inst, real ? 0 : 1, h->U,
+                    coupled ? h->d_n0ptr : nullptr, h->d_wts, h->nvec, coupled ? h->M[0] : 0, s);
 }
 
 void new_reference(etdm_handle* h, hipStream_t s) {

@@ -5,6 +5,7 @@
 #include <algorithm>
 
 #include "expm_ss.h"
+#include "reduce.h"
 
 namespace etdm {
 namespace {
@@ -14,16 +15,6 @@ constexpr int SOLVE_TPB = 1024;
 constexpr int SOLVE_NB_MAX = 16;
 
 inline int blocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
-
-__device__ __forceinline__ int instance_of(const int* __restrict__ begin, int n, int idx) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (begin[mid] <= idx) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
 // element (i, j) of the skew-Hermitian generator from the upper triangle of the
 // parameters: a_ij (i < j), i Im a_jj on the diagonal, -conj(a_ji) below

@@ -11,16 +11,6 @@
 
 namespace etdm {
 
-__device__ __forceinline__ int zfind(const int* __restrict__ begin, int n, int idx) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (begin[mid] <= idx) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ double sincz(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
 
 // H = iA from the upper triangle (incl. the diagonal) of A; Re of the diagonal is ignored.
@@ -28,7 +18,7 @@ __global__ void z_build_iA_kernel(const ZInst* __restrict__ zi, const int* __res
                                   int total) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int ii = zfind(begin, n_inst, idx);
+  const int ii = instance_of(begin, n_inst, idx);
   const ZInst& z = zi[ii];
   const int M = z.M, e = idx - begin[ii];
   const int i = e / M, j = e - i * M;
@@ -52,7 +42,7 @@ __global__ void z_phase_kernel(const ZInst* __restrict__ zi, const int* __restri
                                int total) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int ii = zfind(begin, n_inst, idx);
+  const int ii = instance_of(begin, n_inst, idx);
   const ZInst& z = zi[ii];
   const int M = z.M, e = idx - begin[ii];
   const int p = e % M;
@@ -68,7 +58,7 @@ __global__ __launch_bounds__(256) void z_rows_kernel(const ZInst* __restrict__ z
   const int lane = threadIdx.x & 63;
   const int row_g = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row_g >= total_rows) return;
-  const int ii = zfind(begin, n_inst, row_g);
+  const int ii = instance_of(begin, n_inst, row_g);
   const ZInst& z = zi[ii];
   const int M = z.M, mu = row_g - begin[ii];
   const double2* C = reinterpret_cast<const double2*>(z.C) + (size_t)mu * M;
@@ -106,7 +96,7 @@ __global__ __launch_bounds__(256) void z_apply_hubbard_kernel(const ZInst* __res
   const int lane = threadIdx.x & 63;
   const int row_g = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row_g >= total_rows) return;
-  const int ii = zfind(begin, n_inst, row_g);
+  const int ii = instance_of(begin, n_inst, row_g);
   const ZInst& z = zi[ii];
   const int M = z.M, mu = row_g - begin[ii];
   const double un = U * z.n[mu];
@@ -143,7 +133,7 @@ __global__ __launch_bounds__(256) void z_odd_rows_kernel(const ZInst* __restrict
   const int lane = threadIdx.x & 63;
   const int row_g = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row_g >= total_rows) return;
-  const int ii = zfind(begin, n_inst, row_g);
+  const int ii = instance_of(begin, n_inst, row_g);
   const ZInst& z = zi[ii];
   const int M = z.M, mu = row_g - begin[ii];
   const double2* C = reinterpret_cast<const double2*>(z.C) + (size_t)mu * M;
@@ -163,7 +153,7 @@ __global__ __launch_bounds__(256) void z_odd_rows_kernel(const ZInst* __restrict
 __global__ void z_odd_L_kernel(const ZInst* __restrict__ zi, const int* __restrict__ begin, int n_inst, int total) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int ii = zfind(begin, n_inst, idx);
+  const int ii = instance_of(begin, n_inst, idx);
   const ZInst& z = zi[ii];
   const int M = z.M, e = idx - begin[ii];
   const int m = e / M, k = e - m * M;
@@ -179,7 +169,7 @@ __global__ void z_commutator_kernel(const ZInst* __restrict__ zi, const int* __r
                                     int total) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int ii = zfind(begin, n_inst, idx);
+  const int ii = instance_of(begin, n_inst, idx);
   const ZInst& z = zi[ii];
   const int M = z.M, e = idx - begin[ii];
   const int m = e / M, k = e - m * M;
@@ -194,7 +184,7 @@ __global__ void z_divdiff_kernel(const ZInst* __restrict__ zi, const int* __rest
                                  int total) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int ii = zfind(begin, n_inst, idx);
+  const int ii = instance_of(begin, n_inst, idx);
   const ZInst& z = zi[ii];
   const int M = z.M, e = idx - begin[ii];
   const int p = e / M, q = e - p * M;
@@ -213,7 +203,7 @@ __global__ void z_grad_kernel(const ZInst* __restrict__ zi, const int* __restric
                               int total, int* status) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int ii = zfind(begin, n_inst, idx);
+  const int ii = instance_of(begin, n_inst, idx);
   const ZInst& z = zi[ii];
   const int M = z.M, e = idx - begin[ii];
   const int i = e / M, j = e - i * M;
@@ -264,76 +254,93 @@ void launch_z_grad(const ZInst* d, const int* b, int n, int total, int* status, 
 }
 
 // ---------------------------------------------------------------------------
-// Preconditioner set-up of the L-BFGS driver (FP64)
+// Preconditioner set-up of the L-BFGS driver (FP64), whole batch per launch
 // ---------------------------------------------------------------------------
-__global__ void hdiag_ov_kernel(double* h, const double* eps, const double* f, int M, int N, double w) {
-  const int Nv = M - N;
-  int64_t total = (int64_t)N * Nv;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(idx / Nv), j = N + (int)(idx - (int64_t)i * Nv);
-    h[idx] = w * fmax(0.0, -2.0 * (eps[i] - eps[j]) * (f[i] - f[j]));
+// n0_mu = sum_i f_i |C0_mu_i|^2, one wave per row of the batch
+__global__ __launch_bounds__(256) void prec_density_kernel(const PrecInst* __restrict__ pi,
+                                                           const int* __restrict__ begin, int n_inst,
+                                                           int total_rows, int cplx) {
+  const int lane = threadIdx.x & 63;
+  const int row_g = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row_g >= total_rows) return;
+  const int ii = instance_of(begin, n_inst, row_g);
+  const PrecInst& q = pi[ii];
+  const int M = q.M, mu = row_g - begin[ii];
+  double s = 0.0;
+  for (int i = lane; i < M; i += 64) {
+    if (cplx) {
+      const double2 c = reinterpret_cast<const double2*>(q.C0)[(size_t)mu * M + i];
+      s += q.f[i] * (c.x * c.x + c.y * c.y);
+    } else {
+      const double c = q.C0[(size_t)mu * M + i];
+      s += q.f[i] * c * c;
+    }
   }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) q.n0[mu] = s;
 }
 
-__global__ void hdiag_z_kernel(double* h, double* wv, const double* eps, const double* f, int M, double w) {
-  int64_t total = (int64_t)M * M;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(idx / M), j = (int)(idx - (int64_t)i * M);
-    const double v = w * fmax(0.0, -2.0 * (eps[i] - eps[j]) * (f[i] - f[j]));
-    h[2 * idx] = (i < j) ? v : 0.0;       // Re a_ij, i < j
-    h[2 * idx + 1] = (i <= j) ? v : 0.0;  // Im a_ij, i <= j
-    wv[2 * idx] = (i < j) ? w : 1.0;
-    wv[2 * idx + 1] = (i <= j) ? w : 1.0;
+// eps_i = Re sum_mu conj(C0_mu_i) ((H0 C0)_mu_i + U n_mu C0_mu_i), one thread per column
+__global__ void prec_eps_kernel(const PrecInst* __restrict__ pi, const int* __restrict__ begin, int n_inst,
+                                int total_cols, double U, int cplx) {
+  const int col_g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col_g >= total_cols) return;
+  const int ii = instance_of(begin, n_inst, col_g);
+  const PrecInst& q = pi[ii];
+  const int M = q.M, i = col_g - begin[ii];
+  double s = 0.0;
+  for (int mu = 0; mu < M; ++mu) {
+    if (cplx) {
+      const double2 c = reinterpret_cast<const double2*>(q.C0)[(size_t)mu * M + i];
+      const double2 h = reinterpret_cast<const double2*>(q.HC0)[(size_t)mu * M + i];
+      s += c.x * h.x + c.y * h.y + U * q.nH[mu] * (c.x * c.x + c.y * c.y);
+    } else {
+      const double c = q.C0[(size_t)mu * M + i];
+      s += c * (q.HC0[(size_t)mu * M + i] + U * q.nH[mu] * c);
+    }
   }
+  q.eps[i] = s;
+}
+
+// h = w max(0, -2 (eps_i - eps_j)(f_i - f_j)) and the weight w over the free variables:
+// REAL_OV rows i < N, columns j >= N; complex: Re part for i < j, Im part for i <= j,
+// 0 (and weight 1) elsewhere
+__global__ void prec_hdiag_kernel(const PrecInst* __restrict__ pi, const int* __restrict__ begin, int n_inst,
+                                  int total, int cplx) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = instance_of(begin, n_inst, idx);
+  const PrecInst& q = pi[ii];
+  const int e = idx - begin[ii];
+  if (!cplx) {
+    const int Nv = q.M - q.N;
+    const int i = e / Nv, j = q.N + (e - i * Nv);
+    q.hd[e] = q.w * fmax(0.0, -2.0 * (q.eps[i] - q.eps[j]) * (q.f[i] - q.f[j]));
+    q.wv[e] = q.w;
+    return;
+  }
+  const int i = e / q.M, j = e - i * q.M;
+  const double v = q.w * fmax(0.0, -2.0 * (q.eps[i] - q.eps[j]) * (q.f[i] - q.f[j]));
+  q.hd[2 * e] = (i < j) ? v : 0.0;
+  q.hd[2 * e + 1] = (i <= j) ? v : 0.0;
+  q.wv[2 * e] = (i < j) ? q.w : 1.0;
+  q.wv[2 * e + 1] = (i <= j) ? q.w : 1.0;
+}
+
+// C0 <- [C_occ | C_virt] for every instance (the reference update of the ov form)
+__global__ void c0_update_kernel(const C0Inst* __restrict__ ci, const int* __restrict__ begin, int n_inst,
+                                 int total) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = instance_of(begin, n_inst, idx);
+  const C0Inst& q = ci[ii];
+  const int e = idx - begin[ii], mu = e / q.M, j = e - mu * q.M;
+  q.C0[e] = j < q.N ? q.Cocc[(size_t)mu * q.N + j] : q.Cvirt[(size_t)mu * (q.M - q.N) + (j - q.N)];
 }
 
 __global__ void fill_kernel(double* x, int64_t n, double v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] = v;
-}
-
-// ---------------------------------------------------------------------------
-// set-up kernels: orbital energies of the preconditioner
-// ---------------------------------------------------------------------------
-// n0_mu = sum_i f_i |C0_mu_i|^2 (row of a real or complex M x M matrix)
-__global__ __launch_bounds__(256) void occ_density_kernel(const double* C0, const double* f, int M, int cplx,
-                                                          double* out) {
-  const int lane = threadIdx.x & 63;
-  const int mu = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (mu >= M) return;
-  double s = 0.0;
-  for (int i = lane; i < M; i += 64) {
-    if (cplx) {
-      double2 c = reinterpret_cast<const double2*>(C0)[(size_t)mu * M + i];
-      s += f[i] * (c.x * c.x + c.y * c.y);
-    } else {
-      double c = C0[(size_t)mu * M + i];
-      s += f[i] * c * c;
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) out[mu] = s;
-}
-
-// eps_i = Re sum_mu conj(C0_mu_i) ((H0 C0)_mu_i + U n0_mu C0_mu_i); one thread per column
-__global__ void column_eps_kernel(const double* C0, const double* HC0, const double* n0, double U, int M,
-                                  int cplx, double* eps) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  double s = 0.0;
-  for (int mu = 0; mu < M; ++mu) {
-    if (cplx) {
-      double2 c = reinterpret_cast<const double2*>(C0)[(size_t)mu * M + i];
-      double2 h = reinterpret_cast<const double2*>(HC0)[(size_t)mu * M + i];
-      s += c.x * h.x + c.y * h.y + U * n0[mu] * (c.x * c.x + c.y * c.y);
-    } else {
-      double c = C0[(size_t)mu * M + i];
-      s += c * (HC0[(size_t)mu * M + i] + U * n0[mu] * c);
-    }
-  }
-  eps[i] = s;
 }
 
 // out[mu] = sum_k w_k x_k[mu], fixed order over k
@@ -347,26 +354,25 @@ __global__ void weighted_vsum_kernel(const double* const* xs, const double* ws, 
 
 static inline int vgrid(int64_t n) { return (int)std::min<int64_t>(2048, std::max<int64_t>(1, (n + 255) / 256)); }
 
-void launch_hdiag_ov(double* h, const double* eps, const double* f, int M, int N, double w, hipStream_t s) {
-  int64_t n = (int64_t)N * (M - N);
-  if (n > 0) hdiag_ov_kernel<<<vgrid(n), 256, 0, s>>>(h, eps, f, M, N, w);
-}
-void launch_hdiag_z(double* h, double* wv, const double* eps, const double* f, int M, double w, hipStream_t s) {
-  int64_t n = (int64_t)M * M;
-  if (n > 0) hdiag_z_kernel<<<vgrid(n), 256, 0, s>>>(h, wv, eps, f, M, w);
-}
 void launch_fill(double* x, int64_t n, double v, hipStream_t s) {
   if (n > 0) fill_kernel<<<vgrid(n), 256, 0, s>>>(x, n, v);
 }
 
-void launch_occ_density(const double* C0, const double* f, int M, int cplx, double* out, hipStream_t s) {
-  if (M > 0) occ_density_kernel<<<zb(M, 4), 256, 0, s>>>(C0, f, M, cplx, out);
-}
-void launch_column_eps(const double* C0, const double* HC0, const double* n0, double U, int M, int cplx,
-                       double* eps, hipStream_t s) {
-  if (M > 0) column_eps_kernel<<<zb(M, 256), 256, 0, s>>>(C0, HC0, n0, U, M, cplx, eps);
-}
 
+void launch_prec_setup(const PrecInst* d, const int* d_rows, int total_rows, const int* d_elems, int total_elems,
+                       int n_inst, int cplx, double U, const double* const* coupled_n0, const double* coupled_w,
+                       double* coupled_n, int couple_M, hipStream_t s) {
+  if (n_inst <= 0) return;
+  if (total_rows > 0) prec_density_kernel<<<zb(total_rows, 4), 256, 0, s>>>(d, d_rows, n_inst, total_rows, cplx);
+  if (coupled_n0 && couple_M > 0)
+    weighted_vsum_kernel<<<zb(couple_M, 256), 256, 0, s>>>(coupled_n0, coupled_w, n_inst, couple_M, coupled_n);
+  if (total_rows > 0) prec_eps_kernel<<<zb(total_rows, 256), 256, 0, s>>>(d, d_rows, n_inst, total_rows, U, cplx);
+  if (total_elems > 0)
+    prec_hdiag_kernel<<<zb(total_elems, 256), 256, 0, s>>>(d, d_elems, n_inst, total_elems, cplx);
+}
+void launch_c0_update(const C0Inst* d, const int* d_begin, int n_inst, int total, hipStream_t s) {
+  if (total > 0) c0_update_kernel<<<zb(total, 256), 256, 0, s>>>(d, d_begin, n_inst, total);
+}
 void launch_weighted_vsum(const double* const* xs, const double* ws, int n, int M, double* out, hipStream_t s) {
   if (M > 0) weighted_vsum_kernel<<<zb(M, 256), 256, 0, s>>>(xs, ws, n, M, out);
 }

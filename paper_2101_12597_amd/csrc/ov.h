@@ -115,15 +115,37 @@ void launch_z_grad(const ZInst* d, const int* d_begin, int n_inst, int total, in
 // ---------------------------------------------------------------------------
 // Preconditioner set-up of the L-BFGS driver (FP64)
 // ---------------------------------------------------------------------------
-// h = w * max(0, -2 (eps_i - eps_j)(f_i - f_j)) over the free variables (REAL_OV layout)
-void launch_hdiag_ov(double* h, const double* eps, const double* f, int M, int N, double w, hipStream_t s);
-// same for the complex layout (interleaved: Re part for i < j, Im part for i <= j, 0 elsewhere)
-void launch_hdiag_z(double* h, double* wv, const double* eps, const double* f, int M, double w, hipStream_t s);
+// Per instance of the preconditioner set-up: n0 = diag(C0 F C0^H), eps_i =
+// Re (C0^H H(n) C0)_ii with H(n) = H0 + U diag(nH) (nH: own n0 or the coupled sum),
+// h and w over the instance's slice of the free variables.
+struct PrecInst {
+  const double* C0;
+  const double* HC0;  // H0 C0
+  const double* f;
+  double* n0;
+  const double* nH;
+  double* eps;
+  double* hd;
+  double* wv;
+  int32_t M, N;
+  double w;
+};
+// One instance of the ov reference update C0 <- [C_occ | C_virt].
+struct C0Inst {
+  double* C0;
+  const double* Cocc;
+  const double* Cvirt;
+  int32_t M, N;
+};
+// The whole batch: densities (rows offsets d_rows), optionally the coupled sum
+// coupled_n = sum_k w_k n0_k (couple_M > 0), orbital energies, then h and w over the
+// free variables (element offsets d_elems: N (M - N) real, M^2 complex per instance).
+void launch_prec_setup(const PrecInst* d, const int* d_rows, int total_rows, const int* d_elems, int total_elems,
+                       int n_inst, int cplx, double U, const double* const* coupled_n0, const double* coupled_w,
+                       double* coupled_n, int couple_M, hipStream_t s);
+void launch_c0_update(const C0Inst* d, const int* d_begin, int n_inst, int total, hipStream_t s);
 void launch_fill(double* x, int64_t n, double v, hipStream_t s);
 
 void launch_weighted_vsum(const double* const* xs, const double* ws, int n, int M, double* out, hipStream_t s);
-void launch_occ_density(const double* C0, const double* f, int M, int cplx, double* out, hipStream_t s);
-void launch_column_eps(const double* C0, const double* HC0, const double* n0, double U, int M, int cplx,
-                       double* eps, hipStream_t s);
 
 }  // namespace etdm

@@ -3,6 +3,7 @@
 #include <algorithm>
 
 #include "overlap.h"
+#include "reduce.h"
 
 namespace etdm {
 namespace {
@@ -10,16 +11,6 @@ namespace {
 constexpr int TPB = 256;
 
 inline int blocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
-
-__device__ __forceinline__ int instance_of(const int* __restrict__ begin, int n, int idx) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (begin[mid] <= idx) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
 __device__ double block_max(double v) {
   __shared__ double red[TPB];

@@ -1,12 +1,25 @@
-// Compensated (Neumaier) summation for the FP64 reductions: a running sum and
-// its correction term, combined across a wavefront by butterfly shuffles and
-// across the waves of a workgroup in a fixed order, so a reduction gives the same
-// bits on every run.
+// Device helpers shared by the batched kernels: the owner lookup of a flat
+// element in a batch of instances, and compensated (Neumaier) summation for the
+// FP64 reductions (a running sum and its correction term, combined across a
+// wavefront by butterfly shuffles and across the waves of a workgroup in a fixed
+// order, so a reduction gives the same bits on every run).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace etdm {
+
+// Instance that owns flat element idx of a batch laid out back to back:
+// begin[] holds the ascending first element of each of the n instances.
+__device__ __forceinline__ int instance_of(const int* __restrict__ begin, int n, int idx) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= idx) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 __device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
   double t = s + x;
