@@ -218,8 +218,8 @@ def blas_threads():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}); "
-              "the multi-GPU layout is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}): the path is a "
+              "single-device one; sharding across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

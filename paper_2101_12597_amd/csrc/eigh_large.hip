@@ -1028,7 +1028,7 @@ __global__ __launch_bounds__(256) void tb_res_scan(EighLarge e) {
 
 // which = 0: *ok = 0 unless max|G - I| <= 1e-6;  which = 1: unless the residual
 // max <= 1e-11 ||sym(P)||_F.
-__global__ void tb_verdict(EighLarge e, int which) {
+__global__ void tb_decide(EighLarge e, int which) {
   if (threadIdx.x != 0 || !*e.ok) return;
   const unsigned long long* b = reinterpret_cast<const unsigned long long*>(e.scan);
   if (which == 0) {
@@ -1080,12 +1080,12 @@ __global__ __launch_bounds__(256) void tb_wy_t(EighLarge e) {
 
 void launch_tb_orth_check(const EighLarge& e, hipStream_t s) {
   tb_orth_scan<<<256, 256, 0, s>>>(e);
-  tb_verdict<<<1, 64, 0, s>>>(e, 0);
+  tb_decide<<<1, 64, 0, s>>>(e, 0);
 }
 
 void launch_tb_final_check(const EighLarge& e, hipStream_t s) {
   tb_res_scan<<<256, 256, 0, s>>>(e);
-  tb_verdict<<<1, 64, 0, s>>>(e, 1);
+  tb_decide<<<1, 64, 0, s>>>(e, 1);
 }
 
 void launch_tb_reduce(const EighLarge& e, hipStream_t s) {
