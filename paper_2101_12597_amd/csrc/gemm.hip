@@ -354,6 +354,7 @@ __device__ __forceinline__ double2 ld_zop(const double2* __restrict__ X, int64_t
 template <int OPA, int OPB>
 __global__ __launch_bounds__(NTHREADS) void zgemm_k4(const GemmProb* __restrict__ probs, const int* __restrict__ tile_prob) {
   constexpr int BK = 16;
+  static_assert(BM * BK % NTHREADS == 0 && BN * BK % NTHREADS == 0, "whole k-tiles per thread");
   __shared__ double Ar[BK][BM + 1], Ai[BK][BM + 1];
   __shared__ double Br[BK][BN + 1], Bi[BK][BN + 1];
   const GemmProb& p = probs[tile_prob[blockIdx.x]];
@@ -376,24 +377,50 @@ __global__ __launch_bounds__(NTHREADS) void zgemm_k4(const GemmProb* __restrict_
     const int K = seg ? p.k2 : p.k;
     const double alpha = seg ? p.alpha2 : p.alpha;
     if (K <= 0) continue;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-      for (int e = threadIdx.x; e < BM * BK; e += NTHREADS) {
+    // software pipeline: the next k-tile's global loads are issued into registers
+    // before the MFMAs of the current one
+    constexpr int EA = BM * BK / NTHREADS, EB = BN * BK / NTHREADS;
+    double2 ra[EA], rb[EB];
+    auto fetch = [&](int k0) {
+#pragma unroll
+      for (int u = 0; u < EA; ++u) {
+        const int e = threadIdx.x + u * NTHREADS;
         int mm, kk;
         if (OPA != OP_N) { kk = e / BM; mm = e % BM; }
         else { mm = e / BK; kk = e % BK; }
-        double2 v = ld_zop<OPA>(A, lda, row0 + mm, k0 + kk, p.m, K);
-        Ar[kk][mm] = alpha * v.x;
-        Ai[kk][mm] = alpha * v.y;
+        ra[u] = ld_zop<OPA>(A, lda, row0 + mm, k0 + kk, p.m, K);
       }
-      for (int e = threadIdx.x; e < BN * BK; e += NTHREADS) {
+#pragma unroll
+      for (int u = 0; u < EB; ++u) {
+        const int e = threadIdx.x + u * NTHREADS;
         int nn, kk;
         if (OPB != OP_N) { nn = e / BK; kk = e % BK; }
         else { kk = e / BN; nn = e % BN; }
-        double2 v = ld_zop<OPB>(B, ldb, k0 + kk, col0 + nn, K, p.n);
-        Br[kk][nn] = v.x;
-        Bi[kk][nn] = v.y;
+        rb[u] = ld_zop<OPB>(B, ldb, k0 + kk, col0 + nn, K, p.n);
+      }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+      for (int u = 0; u < EA; ++u) {
+        const int e = threadIdx.x + u * NTHREADS;
+        int mm, kk;
+        if (OPA != OP_N) { kk = e / BM; mm = e % BM; }
+        else { mm = e / BK; kk = e % BK; }
+        Ar[kk][mm] = alpha * ra[u].x;
+        Ai[kk][mm] = alpha * ra[u].y;
+      }
+#pragma unroll
+      for (int u = 0; u < EB; ++u) {
+        const int e = threadIdx.x + u * NTHREADS;
+        int nn, kk;
+        if (OPB != OP_N) { nn = e / BK; kk = e % BK; }
+        else { kk = e / BN; nn = e % BN; }
+        Br[kk][nn] = rb[u].x;
+        Bi[kk][nn] = rb[u].y;
       }
       __syncthreads();
+      if (k0 + BK < K) fetch(k0 + BK);
 #pragma unroll
       for (int ks = 0; ks < BK; ks += 4) {
         double ar[2], ai[2], nai[2], br[2], bi[2];
