@@ -66,7 +66,9 @@ void launch_ss_combine_even(const SsInst* d, const int* d_begin, int n_inst, int
 // Panel width of the solve for matrices up to max_m (its LDS stays within 64 KiB).
 int ss_solve_panel(int max_m);
 // R <- Z^-1 R by block Gauss-Jordan elimination without pivoting, panels of
-// ss_solve_panel(max_m) rows (one workgroup per instance); Z is overwritten.
+// ss_solve_panel(max_m) rows: per panel one launch reduces the panel rows (one
+// workgroup per instance) and one updates the other rows (several workgroups per
+// instance); Z is overwritten.
 void launch_ss_solve(const SsInst* d, int n_inst, int max_m, hipStream_t s);
 // Es = E / 2^s
 void launch_ss_deriv_scale(const SsDeriv* d, const int* d_begin, int n_inst, int total, const int* s_dev,

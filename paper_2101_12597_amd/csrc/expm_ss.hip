@@ -13,6 +13,7 @@ namespace {
 constexpr int TPB = 256;
 constexpr int SOLVE_TPB = 1024;
 constexpr int SOLVE_NB_MAX = 16;
+constexpr int SOLVE_GROUPS = 8;  // workgroups per instance in the row updates (16 measured slower)
 
 inline int blocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
@@ -114,74 +115,93 @@ __device__ __forceinline__ double2 cinv(double2 d) {
 }
 
 // Block Gauss-Jordan elimination on [Z | R] without pivoting (Z has a positive
-// definite Hermitian part).  Per panel of nb rows k0..k1: the panel rows (columns
-// k0.. of Z and all of R) and the multipliers Z[:, k0:k1] go to LDS; the panel is
-// reduced to D^-1 (panel rows) in LDS; every other row i gets
-// row_i -= Z[i, k0:k1] (D^-1 panel rows), so [Z | R] is read and written once per
-// panel rather than once per column.
-__global__ __launch_bounds__(SOLVE_TPB) void solve_kernel(const SsInst* __restrict__ si, int NB) {
+// definite Hermitian part), one panel of nb rows k0..k0+nb at a time in two launches:
+//   panel_kernel   (one workgroup per instance) the panel rows (columns k0.. of Z and
+//                  all of R) are reduced to D^-1 (panel rows) in LDS and written back;
+//   update_kernel  (SOLVE_GROUPS workgroups per instance, whole rows each) every other
+//                  row i takes row_i -= Z[i, k0:k0+nb] (D^-1 panel rows), its multipliers
+//                  read before the row is rewritten.
+// [Z | R] is streamed once per panel, by the whole chip.
+__global__ __launch_bounds__(SOLVE_TPB) void panel_kernel(const SsInst* __restrict__ si, int k0, int NB) {
   const SsInst& z = si[blockIdx.x];
   const int M = z.M;
+  if (k0 >= M) return;
   double2* __restrict__ Q = reinterpret_cast<double2*>(z.Z);
   double2* __restrict__ R = reinterpret_cast<double2*>(z.R);
   extern __shared__ double2 sh[];
-  double2* P = sh;                        // panel rows, NB x W (W <= 2M)
-  double2* F = sh + (size_t)NB * 2 * M;   // multipliers, M x NB
-  double2* fc = F + (size_t)M * NB;       // one column of the panel, NB
-  for (int k0 = 0; k0 < M; k0 += NB) {
-    const int nb = min(NB, M - k0);
-    const int wq = M - k0, W = wq + M;
-    for (int t = threadIdx.x; t < nb * W; t += blockDim.x) {
-      const int r = t / W, c = t - r * W;
-      P[t] = c < wq ? Q[(size_t)(k0 + r) * M + k0 + c] : R[(size_t)(k0 + r) * M + (c - wq)];
-    }
-    for (int t = threadIdx.x; t < M * nb; t += blockDim.x) {
-      const int i = t / nb, c = t - i * nb;
-      F[t] = Q[(size_t)i * M + k0 + c];
+  const int nb = min(NB, M - k0);
+  const int wq = M - k0, W = wq + M;
+  double2* P = sh;              // panel rows, nb x W
+  double2* fc = sh + nb * W;    // one column of the panel
+  for (int t = threadIdx.x; t < nb * W; t += blockDim.x) {
+    const int r = t / W, c = t - r * W;
+    P[t] = c < wq ? Q[(size_t)(k0 + r) * M + k0 + c] : R[(size_t)(k0 + r) * M + (c - wq)];
+  }
+  __syncthreads();
+  for (int c = 0; c < nb; ++c) {
+    if ((int)threadIdx.x < nb) fc[threadIdx.x] = P[threadIdx.x * W + c];
+    __syncthreads();
+    const double2 inv = cinv(fc[c]);
+    for (int t = threadIdx.x; t < W; t += blockDim.x) P[c * W + t] = cmul(P[c * W + t], inv);
+    __syncthreads();
+    for (int t = threadIdx.x; t < (nb - 1) * W; t += blockDim.x) {
+      int r = t / W;
+      const int col = t - r * W;
+      r += r >= c;
+      const double2 f = fc[r], q = P[c * W + col];
+      P[r * W + col].x -= f.x * q.x - f.y * q.y;
+      P[r * W + col].y -= f.x * q.y + f.y * q.x;
     }
     __syncthreads();
-    // the panel: D^-1 (panel rows) by Gauss-Jordan on its nb x nb block
-    for (int c = 0; c < nb; ++c) {
-      if ((int)threadIdx.x < nb) fc[threadIdx.x] = P[threadIdx.x * W + c];
-      __syncthreads();
-      const double2 inv = cinv(fc[c]);
-      for (int t = threadIdx.x; t < W; t += blockDim.x) P[c * W + t] = cmul(P[c * W + t], inv);
-      __syncthreads();
-      for (int t = threadIdx.x; t < (nb - 1) * W; t += blockDim.x) {
-        int r = t / W;
-        const int col = t - r * W;
-        r += r >= c;
-        const double2 f = fc[r], p = P[c * W + col];
-        P[r * W + col].x -= f.x * p.x - f.y * p.y;
-        P[r * W + col].y -= f.x * p.y + f.y * p.x;
-      }
-      __syncthreads();
+  }
+  for (int t = threadIdx.x; t < nb * W; t += blockDim.x) {
+    const int r = t / W, c = t - r * W;
+    if (c < wq) Q[(size_t)(k0 + r) * M + k0 + c] = P[t];
+    else R[(size_t)(k0 + r) * M + (c - wq)] = P[t];
+  }
+}
+
+__global__ __launch_bounds__(TPB) void update_kernel(const SsInst* __restrict__ si, int k0, int NB) {
+  const int g = blockIdx.x % SOLVE_GROUPS;
+  const SsInst& z = si[blockIdx.x / SOLVE_GROUPS];
+  const int M = z.M;
+  if (k0 >= M) return;
+  double2* __restrict__ Q = reinterpret_cast<double2*>(z.Z);
+  double2* __restrict__ R = reinterpret_cast<double2*>(z.R);
+  extern __shared__ double2 sh[];
+  const int nb = min(NB, M - k0);
+  const int wq = M - k0, W = wq + M;
+  // this workgroup's block of the M - nb rows outside the panel
+  const int rows = M - nb, r0 = g * rows / SOLVE_GROUPS, r1 = (g + 1) * rows / SOLVE_GROUPS, nr = r1 - r0;
+  if (nr <= 0) return;
+  double2* P = sh;               // reduced panel rows, nb x W
+  double2* F = sh + nb * W;      // multipliers of the block's rows, nr x nb
+  for (int t = threadIdx.x; t < nb * W; t += blockDim.x) {
+    const int r = t / W, c = t - r * W;
+    P[t] = c < wq ? Q[(size_t)(k0 + r) * M + k0 + c] : R[(size_t)(k0 + r) * M + (c - wq)];
+  }
+  for (int t = threadIdx.x; t < nr * nb; t += blockDim.x) {
+    const int r = t / nb, c = t - r * nb;
+    const int i = r0 + r < k0 ? r0 + r : r0 + r + nb;
+    F[t] = Q[(size_t)i * M + k0 + c];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nr * W; t += blockDim.x) {
+    const int r = t / W, col = t - r * W;
+    const int i = r0 + r < k0 ? r0 + r : r0 + r + nb;
+    double2* dst = col < wq ? &Q[(size_t)i * M + k0 + col] : &R[(size_t)i * M + (col - wq)];
+    if (col < nb) {
+      *dst = make_double2(0.0, 0.0);
+      continue;
     }
-    // the other rows, one pass
-    for (int64_t t = threadIdx.x; t < (int64_t)(M - nb) * W; t += blockDim.x) {
-      int r = (int)(t / W);
-      const int col = (int)(t - (int64_t)r * W);
-      const int i = r < k0 ? r : r + nb;
-      double2* dst = col < wq ? &Q[(size_t)i * M + k0 + col] : &R[(size_t)i * M + (col - wq)];
-      if (col < nb) {
-        *dst = make_double2(0.0, 0.0);
-        continue;
-      }
-      double2 acc = *dst;
-      const double2* f = F + (size_t)i * nb;
-      for (int u = 0; u < nb; ++u) {
-        const double2 p = P[u * W + col];
-        acc.x -= f[u].x * p.x - f[u].y * p.y;
-        acc.y -= f[u].x * p.y + f[u].y * p.x;
-      }
-      *dst = acc;
+    double2 acc = *dst;
+    const double2* f = F + r * nb;
+    for (int u = 0; u < nb; ++u) {
+      const double2 q = P[u * W + col];
+      acc.x -= f[u].x * q.x - f[u].y * q.y;
+      acc.y -= f[u].x * q.y + f[u].y * q.x;
     }
-    for (int t = threadIdx.x; t < nb * W; t += blockDim.x) {
-      const int r = t / W, c = t - r * W;
-      if (c < wq) Q[(size_t)(k0 + r) * M + k0 + c] = P[t];
-      else R[(size_t)(k0 + r) * M + (c - wq)] = P[t];
-    }
-    __syncthreads();
+    *dst = acc;
   }
 }
 
@@ -280,20 +300,27 @@ static size_t solve_lds_limit() {
 }
 
 int ss_solve_panel(int max_m) {
-  // LDS: NB x 2M panel rows + M x NB multipliers + NB column values
-  const size_t per_row = sizeof(double2) * (3 * (size_t)max_m + 1);
+  // LDS: nb panel rows of up to 2M complex, and per panel row one multiplier of each of
+  // the block's rows (at most M / SOLVE_GROUPS + 1) or one column value
+  const size_t per_row = sizeof(double2) * (2 * (size_t)max_m + (size_t)max_m / SOLVE_GROUPS + 2);
   const int nb = (int)(solve_lds_limit() / per_row);
   return std::max(1, std::min(SOLVE_NB_MAX, nb));
 }
 
 void launch_ss_solve(const SsInst* d, int n_inst, int max_m, hipStream_t s) {
-  if (n_inst <= 0) return;
-  const int panel = ss_solve_panel(max_m);
-  const size_t lds = sizeof(double2) * ((size_t)panel * (3 * (size_t)max_m + 1));
-  if (lds > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(solve_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-  solve_kernel<<<n_inst, SOLVE_TPB, lds, s>>>(d, panel);
+  if (n_inst <= 0 || max_m <= 0) return;
+  const int nb = ss_solve_panel(max_m);
+  const size_t lds = sizeof(double2) * ((size_t)nb * (2 * (size_t)max_m + (size_t)max_m / SOLVE_GROUPS + 2));
+  if (lds > 65536) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(panel_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(update_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  for (int k0 = 0; k0 < max_m; k0 += nb) {
+    panel_kernel<<<n_inst, SOLVE_TPB, lds, s>>>(d, k0, nb);
+    update_kernel<<<n_inst * SOLVE_GROUPS, TPB, lds, s>>>(d, k0, nb);
+  }
 }
 
 void launch_ss_deriv_scale(const SsDeriv* d, const int* d_begin, int n_inst, int total, const int* s_dev,
