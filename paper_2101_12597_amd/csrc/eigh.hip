@@ -208,7 +208,6 @@ __device__ __forceinline__ void tl_store(double* C, int n, const tl_d4 (&acc)[TL
 }
 
 constexpr int TL_NCH = 5;                     // row chunks of the matrix-vector products
-constexpr int TL_RB = 4;                      // rows per group of the rank-2 / rank-1 updates
 constexpr int TL_PMLD = 2 * EIGH_LDS_MAX;     // stride of their partial sums
 // LDS bytes of eigh_tridiag_lds for size n
 static size_t tl_lds_bytes(int n) {
@@ -225,7 +224,7 @@ static size_t tl_lds_bytes(int n) {
 //      sums (coalesced row reads, v broadcast from registers with readlane), by
 //      3 x TL_NCH wavefronts over row chunks, partial sums to LDS;
 //   C: K = -tau p.v / 2, w = tau p + K v; A_t -= v w^T + w v^T (8 wavefronts),
-//      QT[k+1:, :] -= tau v u^T (8 wavefronts), one row per loop trip.
+//      QT[k+1:, :] -= tau v u^T (8 wavefronts), rows in groups of 8 loads.
 // On return vd[0..n-1], ve[0..n-2] hold T.
 __device__ void tl_tridiag(double* A, double* QT, double* vd, double* ve, double* Pm, int n) {
   const int lane = threadIdx.x & 63;
@@ -257,21 +256,42 @@ __device__ void tl_tridiag(double* A, double* QT, double* vd, double* ve, double
       const double* base = o < L ? A + (k + 1) * n + (k + 1 + o)
                                  : (o < L + n ? QT + (k + 1) * n + (o - L) : A + (k + 1) * n + (k + 1));
       double acc0 = 0.0, acc1 = 0.0;
-      int jj = jb;
-      for (; jj + 1 < je; jj += 2) {
-        const double va = jj < 64 ? tl_readlane(v0, jj) : tl_readlane(v1, jj - 64);
-        const double vb = jj + 1 < 64 ? tl_readlane(v0, jj + 1) : tl_readlane(v1, jj - 63);
-        acc0 += base[jj * n] * va;
-        acc1 += base[(jj + 1) * n] * vb;
-      }
-      if (jj < je) acc0 += base[jj * n] * (jj < 64 ? tl_readlane(v0, jj) : tl_readlane(v1, jj - 64));
+      // rows below 64 take v from v0, the rest from v1: two branch-free ranges with
+      // eight loads in flight per group
+      auto range = [&](const double vs, int lo, int hi, int off) {
+        int jj = lo;
+        for (; jj + 8 <= hi; jj += 8) {
+          double a[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a[u] = base[(jj + u) * n];
+#pragma unroll
+          for (int u = 0; u < 8; u += 2) {
+            acc0 += a[u] * tl_readlane(vs, jj + u - off);
+            acc1 += a[u + 1] * tl_readlane(vs, jj + u + 1 - off);
+          }
+        }
+        for (; jj < hi; ++jj) acc0 += base[jj * n] * tl_readlane(vs, jj - off);
+      };
+      range(v0, jb, min(je, 64), 0);
+      range(v1, max(jb, 64), je, 64);
       if (o < L + n) Pm[ch * TL_PMLD + o] = acc0 + acc1;
     }
     __syncthreads();
     double p0 = 0.0, p1 = 0.0;
-    for (int ch = 0; ch < TL_NCH; ++ch) {
-      if (lane < L) p0 += Pm[ch * TL_PMLD + lane];
-      if (lane + 64 < L) p1 += Pm[ch * TL_PMLD + lane + 64];
+    {  // all partial sums loaded before the first add; entries past L are not p
+      double pa[TL_NCH], pb[TL_NCH];
+#pragma unroll
+      for (int ch = 0; ch < TL_NCH; ++ch) {
+        pa[ch] = Pm[ch * TL_PMLD + lane];
+        pb[ch] = Pm[ch * TL_PMLD + lane + 64];
+      }
+#pragma unroll
+      for (int ch = 0; ch < TL_NCH; ++ch) {
+        p0 += pa[ch];
+        p1 += pb[ch];
+      }
+      if (lane >= L) p0 = 0.0;
+      if (lane + 64 >= L) p1 = 0.0;
     }
     p0 *= tau;
     p1 *= tau;
@@ -280,57 +300,63 @@ __device__ void tl_tridiag(double* A, double* QT, double* vd, double* ve, double
     const int grp = wave >> 3, cb = wave & 1, rc = (wave >> 1) & 3;
     const int col = 64 * cb + lane;
     const int rb = rc * L / 4, re = (rc + 1) * L / 4;
-    // rows in groups of TL_RB: their loads are issued before any of their stores
+    // rows below 64 take v, w from v0, w0, the rest from v1, w1: branch-free ranges in
+    // groups of 8 rows whose loads are issued before any of their stores
     if (grp == 0) {
       const int j = k + 1 + min(col, L - 1);
       const double vj = cb ? v1 : v0, wj = cb ? w1 : w0;
-      int ii = rb;
-      for (; ii + TL_RB <= re; ii += TL_RB) {
-        double x[TL_RB];
+      auto rows = [&](const double vs, const double ws, int lo, int hi, int off) {
+        int ii = lo;
+        for (; ii + 8 <= hi; ii += 8) {
+          double x[8];
 #pragma unroll
-        for (int u = 0; u < TL_RB; ++u) x[u] = A[(k + 1 + ii + u) * n + j];
+          for (int u = 0; u < 8; ++u) x[u] = A[(k + 1 + ii + u) * n + j];
 #pragma unroll
-        for (int u = 0; u < TL_RB; ++u) {
-          const int r = ii + u;
-          const double vi = r < 64 ? tl_readlane(v0, r) : tl_readlane(v1, r - 64);
-          const double wi = r < 64 ? tl_readlane(w0, r) : tl_readlane(w1, r - 64);
-          x[u] -= vi * wj + wi * vj;
+          for (int u = 0; u < 8; ++u)
+            x[u] -= tl_readlane(vs, ii + u - off) * wj + tl_readlane(ws, ii + u - off) * vj;
+          if (col < L)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) A[(k + 1 + ii + u) * n + j] = x[u];
         }
-        if (col < L)
-#pragma unroll
-          for (int u = 0; u < TL_RB; ++u) A[(k + 1 + ii + u) * n + j] = x[u];
-      }
-      for (; ii < re; ++ii) {
-        const double vi = ii < 64 ? tl_readlane(v0, ii) : tl_readlane(v1, ii - 64);
-        const double wi = ii < 64 ? tl_readlane(w0, ii) : tl_readlane(w1, ii - 64);
-        double* a = A + (k + 1 + ii) * n + j;
-        const double x = *a - (vi * wj + wi * vj);
-        if (col < L) *a = x;
-      }
+        for (; ii < hi; ++ii) {
+          double* a = A + (k + 1 + ii) * n + j;
+          const double x = *a - (tl_readlane(vs, ii - off) * wj + tl_readlane(ws, ii - off) * vj);
+          if (col < L) *a = x;
+        }
+      };
+      rows(v0, w0, rb, min(re, 64), 0);
+      rows(v1, w1, max(rb, 64), re, 64);
     } else {
-      double ur = 0.0;
       const int r = min(col, n - 1);
-      for (int ch = 0; ch < TL_NCH; ++ch) ur += Pm[ch * TL_PMLD + L + r];
-      int jj = rb;
-      for (; jj + TL_RB <= re; jj += TL_RB) {
-        double x[TL_RB];
+      double ur = 0.0;
+      {
+        double pu[TL_NCH];
 #pragma unroll
-        for (int u = 0; u < TL_RB; ++u) x[u] = QT[(k + 1 + jj + u) * n + r];
+        for (int ch = 0; ch < TL_NCH; ++ch) pu[ch] = Pm[ch * TL_PMLD + L + r];
 #pragma unroll
-        for (int u = 0; u < TL_RB; ++u) {
-          const int c = jj + u;
-          x[u] -= tau * (c < 64 ? tl_readlane(v0, c) : tl_readlane(v1, c - 64)) * ur;
+        for (int ch = 0; ch < TL_NCH; ++ch) ur += pu[ch];
+      }
+      const double tu = tau * ur;
+      auto rows = [&](const double vs, int lo, int hi, int off) {
+        int jj = lo;
+        for (; jj + 8 <= hi; jj += 8) {
+          double x[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) x[u] = QT[(k + 1 + jj + u) * n + r];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) x[u] -= tl_readlane(vs, jj + u - off) * tu;
+          if (col < n)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) QT[(k + 1 + jj + u) * n + r] = x[u];
         }
-        if (col < n)
-#pragma unroll
-          for (int u = 0; u < TL_RB; ++u) QT[(k + 1 + jj + u) * n + r] = x[u];
-      }
-      for (; jj < re; ++jj) {
-        const double tv = tau * (jj < 64 ? tl_readlane(v0, jj) : tl_readlane(v1, jj - 64));
-        double* q = QT + (k + 1 + jj) * n + r;
-        const double x = *q - tv * ur;
-        if (col < n) *q = x;
-      }
+        for (; jj < hi; ++jj) {
+          double* q = QT + (k + 1 + jj) * n + r;
+          const double x = *q - tl_readlane(vs, jj - off) * tu;
+          if (col < n) *q = x;
+        }
+      };
+      rows(v0, rb, min(re, 64), 0);
+      rows(v1, max(rb, 64), re, 64);
     }
     __syncthreads();
   }
