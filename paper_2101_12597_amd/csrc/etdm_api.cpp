@@ -392,6 +392,8 @@ struct etdm_handle {
   int* ss_s_dev = nullptr;
   int* ss_s_host = nullptr;  // pinned: the batch's number of squarings
   int ss_max_m = 0;
+  int ss_nb = 0;                 // panel width of the solve
+  std::vector<Stage> ss_up[2];   // per panel: the rank-nb row updates of the two solves
   PadeB9 ss_b{};
   Stage ss_X2, ss_X4, ss_X6, ss_X8, ss_U, ss_sq0, ss_sq1;
   // exact gradient on the ss path
@@ -1129,6 +1131,42 @@ etdm_status build_z_plan(etdm_handle* h) {
     }
   }
   if (h->expm_ss) {
+    // Gauss-Jordan row updates of each panel: the rows above and below it take
+    // -Z[rows, panel] (reduced panel rows) over the Z columns right of the panel and
+    // over all of R, in place (C = -A B + C); no problem writes what another reads
+    h->ss_nb = ss_solve_panel(h->ss_max_m);
+    auto solve_updates = [&](const std::vector<SsInst>& v, std::vector<Stage>& ups) -> etdm_status {
+      const int nb = h->ss_nb;
+      ups.assign(ceil_div(h->ss_max_m, nb), Stage());
+      for (size_t pn = 0; pn < ups.size(); ++pn) {
+        Stage& st = ups[pn];
+        st.init(OP_N, OP_N, GP_FP64, true);
+        const int k0 = (int)pn * nb;
+        for (const SsInst& z : v) {
+          const int M = z.M;
+          if (k0 >= M) continue;
+          const int w = std::min(nb, M - k0), e = k0 + w;
+          const int r0[2] = {0, e}, nr[2] = {k0, M - e};
+          for (int q = 0; q < 2; ++q) {
+            const double* F = z.Z + 2 * ((size_t)r0[q] * M + k0);
+            double* cz = z.Z + 2 * ((size_t)r0[q] * M + e);
+            double* cr = z.R + 2 * (size_t)r0[q] * M;
+            GemmProb pz = prob(nr[q], M - e, w, F, M, z.Z + 2 * ((size_t)k0 * M + e), M, cz, M, -1.0);
+            GemmProb pr = prob(nr[q], M, w, F, M, z.R + 2 * (size_t)k0 * M, M, cr, M, -1.0);
+            pz.beta = pr.beta = 1.0;
+            pz.D = cz;
+            pr.D = cr;
+            pz.ldd = pr.ldd = M;
+            st.add(pz);
+            st.add(pr);
+          }
+        }
+        CHECK(upload_stage(h, st));
+      }
+      return ETDM_OK;
+    };
+    CHECK(solve_updates(ss, h->ss_up[0]));
+    if (ss_exact) CHECK(solve_updates(ss2, h->ss_up[1]));
     CHECK(upload(h, &h->d_ss, ss));
     // numerator coefficients of the [9/9] approximant: b_0 = 1, b_{j+1} = b_j (m - j) / ((2m - j)(j + 1))
     h->ss_b.b[0] = 1.0;
@@ -1438,6 +1476,15 @@ void ov_new_reference(etdm_handle* h, hipStream_t s) {
 
 // exp(A) by scaling and squaring (Eq. ss) into Ue.  The number of squarings is the
 // batch's, read by the host (one synchronization).
+// R <- Z^-1 R of every instance: per panel the panel rows are reduced, then the
+// other rows take the rank-nb update on the matrix cores
+void ss_solve(etdm_handle* h, const SsInst* d, std::vector<Stage>& ups, hipStream_t s) {
+  for (size_t pn = 0; pn < ups.size(); ++pn) {
+    launch_ss_panel(d, h->n_inst, h->ss_max_m, (int)pn * h->ss_nb, h->ss_nb, s);
+    ups[pn].launch(s);
+  }
+}
+
 void ss_exponential(etdm_handle* h, hipStream_t s) {
   {
     TIMED(Z_SS_SCALE);
@@ -1461,7 +1508,7 @@ void ss_exponential(etdm_handle* h, hipStream_t s) {
     TIMED(Z_SS_SOLVE);
     const bool exact = !h->grad_approx;  // keep q(X) and r(X) for the Frechet derivative
     if (exact) launch_ss_copy(h->d_ss_q, h->d_ss_qc, h->b_mat, h->n_inst, h->tot_mat, s);
-    launch_ss_solve(h->d_ss, h->n_inst, h->ss_max_m, s);
+    ss_solve(h, h->d_ss, h->ss_up[0], s);
     if (exact) launch_ss_copy(h->d_ss_r, h->d_ss_r0, h->b_mat, h->n_inst, h->tot_mat, s);
   }
   {
@@ -1542,7 +1589,7 @@ void z_energy_grad(etdm_handle* h, hipStream_t s) {
     h->fr_LUb.launch(s);
     launch_ss_deriv_rhs(h->d_ssd, h->d_ss_lu, h->b_mat, h->n_inst, h->tot_mat, s);
     h->fr_N.launch(s);
-    launch_ss_solve(h->d_ss2, h->n_inst, h->ss_max_m, s);
+    ss_solve(h, h->d_ss2, h->ss_up[1], s);
     for (int k = 0; k < sq; ++k)
       for (int c = 0; c < 3; ++c) h->fr_sq[k % 2][c].launch(s);
     h->fr_Y[sq % 2].launch(s);

@@ -23,7 +23,7 @@ namespace etdm {
 
 constexpr double SS_THETA9 = 2.097847961257068;  // 1-norm bound of the degree-9 approximant
 constexpr int SS_MAX_HALVINGS = 64;
-constexpr int SS_MAX_M = 1024;  // LDS of the solve: 3 rows of M complex
+constexpr int SS_MAX_M = 1024;  // largest M of the scaling-and-squaring path
 
 // Per instance: M x M complex matrices (interleaved re, im), row-major.
 struct SsInst {
@@ -63,13 +63,16 @@ void launch_ss_combine_odd(const SsInst* d, const int* d_begin, int n_inst, int 
 // V = b8 X8 + b6 X6 + b4 X4 + b2 X2 + b0 I and U:  Z = V - U,  R = V + U
 void launch_ss_combine_even(const SsInst* d, const int* d_begin, int n_inst, int total, const PadeB9& b,
                             hipStream_t s);
-// Panel width of the solve for matrices up to max_m (its LDS stays within 64 KiB).
+// Panel width nb of the solve (32, two k-tiles of the complex GEMM; the same for every M).
 int ss_solve_panel(int max_m);
-// R <- Z^-1 R by block Gauss-Jordan elimination without pivoting, panels of
-// ss_solve_panel(max_m) rows: per panel one launch reduces the panel rows (one
-// workgroup per instance) and one updates the other rows (several workgroups per
-// instance); Z is overwritten.
-void launch_ss_solve(const SsInst* d, int n_inst, int max_m, hipStream_t s);
+// One panel of R <- Z^-1 R by block Gauss-Jordan elimination without pivoting: the
+// rows k0..k0+nb of [Z | R] (columns k0.. of Z, all of R) are reduced by the inverse
+// of their diagonal block, several workgroups per instance over the columns
+// (instances with M <= k0 are left alone).  The caller then updates every other row i with
+// row_i -= Z[i, k0:k0+nb] (reduced panel rows), over the columns of Z right of the
+// panel and all of R (grouped complex GEMMs, C = -A B + C), before the next panel.
+// After the last panel R holds the solution; Z is overwritten.
+void launch_ss_panel(const SsInst* d, int n_inst, int max_m, int k0, int nb, hipStream_t s);
 // Es = E / 2^s
 void launch_ss_deriv_scale(const SsDeriv* d, const int* d_begin, int n_inst, int total, const int* s_dev,
                            hipStream_t s);

@@ -11,9 +11,9 @@ namespace etdm {
 namespace {
 
 constexpr int TPB = 256;
-constexpr int SOLVE_TPB = 1024;
-constexpr int SOLVE_NB_MAX = 16;
-constexpr int SOLVE_GROUPS = 8;  // workgroups per instance in the row updates (16 measured slower)
+constexpr int SOLVE_NB = 32;     // panel rows: two k-tiles of the complex GEMM that updates the rest
+constexpr int SOLVE_COLS = 32;   // columns right of the diagonal block per panel workgroup (one wavefront)
+constexpr int SOLVE_TPB = SOLVE_NB + SOLVE_COLS;  // one column of the panel per thread
 
 inline int blocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
@@ -115,94 +115,99 @@ __device__ __forceinline__ double2 cinv(double2 d) {
 }
 
 // Block Gauss-Jordan elimination on [Z | R] without pivoting (Z has a positive
-// definite Hermitian part), one panel of nb rows k0..k0+nb at a time in two launches:
-//   panel_kernel   (one workgroup per instance) the panel rows (columns k0.. of Z and
-//                  all of R) are reduced to D^-1 (panel rows) in LDS and written back;
-//   update_kernel  (SOLVE_GROUPS workgroups per instance, whole rows each) every other
-//                  row i takes row_i -= Z[i, k0:k0+nb] (D^-1 panel rows), its multipliers
-//                  read before the row is rewritten.
-// [Z | R] is streamed once per panel, by the whole chip.
-__global__ __launch_bounds__(SOLVE_TPB) void panel_kernel(const SsInst* __restrict__ si, int k0, int NB) {
-  const SsInst& z = si[blockIdx.x];
+// definite Hermitian part), one panel of nb <= SOLVE_NB rows k0..k0+nb at a time:
+//   panel_kernel  the panel rows (columns k0.. of Z, all of R) are reduced by the
+//                 inverse of their diagonal block D.  Workgroup g of an instance holds
+//                 D's columns and its own SOLVE_COLS columns right of D, one column of
+//                 nb rows per thread in registers; step c scales row c by 1 / D_cc and
+//                 subtracts it from the other rows, the pivot column shared through LDS
+//                 (two buffers: the next one is written while the current one is read).
+//                 Only the columns right of D are written back.
+//   then every other row i takes row_i -= Z[i, k0:k0+nb] (reduced panel rows) over the
+//   columns right of the panel, a rank-nb update that the caller launches as grouped
+//   complex GEMMs.  Columns of Z left of the panel (D included) are never read again
+//   and are not written.
+__global__ __launch_bounds__(SOLVE_TPB) void panel_kernel(const SsInst* __restrict__ si, int k0, int NB,
+                                                          int groups) {
+  const SsInst& z = si[blockIdx.x / groups];
+  const int g = blockIdx.x % groups;
   const int M = z.M;
   if (k0 >= M) return;
+  const int nb = min(min(NB, SOLVE_NB), M - k0), wq = M - k0, W = wq + M;
+  const int c0 = nb + g * SOLVE_COLS;  // first column of this workgroup right of D
+  if (c0 >= W) return;                 // whole workgroup
   double2* __restrict__ Q = reinterpret_cast<double2*>(z.Z);
   double2* __restrict__ R = reinterpret_cast<double2*>(z.R);
-  extern __shared__ double2 sh[];
-  const int nb = min(NB, M - k0);
-  const int wq = M - k0, W = wq + M;
-  double2* P = sh;              // panel rows, nb x W
-  double2* fc = sh + nb * W;    // one column of the panel
-  for (int t = threadIdx.x; t < nb * W; t += blockDim.x) {
-    const int r = t / W, c = t - r * W;
-    P[t] = c < wq ? Q[(size_t)(k0 + r) * M + k0 + c] : R[(size_t)(k0 + r) * M + (c - wq)];
+  __shared__ double2 piv[2][SOLVE_NB];
+  const int t = threadIdx.x;
+  // panel column (counted from k0 across [Z | R]) of this thread
+  const int col = t < SOLVE_NB ? t : c0 + (t - SOLVE_NB);
+  const bool act = t < SOLVE_NB ? t < nb : col < W;
+  double2 x[SOLVE_NB];
+#pragma unroll
+  for (int r = 0; r < SOLVE_NB; ++r) {
+    x[r] = make_double2(0.0, 0.0);
+    if (act && r < nb)
+      x[r] = col < wq ? Q[(size_t)(k0 + r) * M + k0 + col] : R[(size_t)(k0 + r) * M + (col - wq)];
   }
+  if (t == 0)
+#pragma unroll
+    for (int r = 0; r < SOLVE_NB; ++r) piv[0][r] = x[r];
   __syncthreads();
-  for (int c = 0; c < nb; ++c) {
-    if ((int)threadIdx.x < nb) fc[threadIdx.x] = P[threadIdx.x * W + c];
-    __syncthreads();
-    const double2 inv = cinv(fc[c]);
-    for (int t = threadIdx.x; t < W; t += blockDim.x) P[c * W + t] = cmul(P[c * W + t], inv);
-    __syncthreads();
-    for (int t = threadIdx.x; t < (nb - 1) * W; t += blockDim.x) {
-      int r = t / W;
-      const int col = t - r * W;
-      r += r >= c;
-      const double2 f = fc[r], q = P[c * W + col];
-      P[r * W + col].x -= f.x * q.x - f.y * q.y;
-      P[r * W + col].y -= f.x * q.y + f.y * q.x;
+  // steps in blocks of 8, unrolled; after each block the register array turns by 8
+  // rows, so step c always finds its pivot row in x[c % 8] and the code stays small.
+  // The turn precedes the block's last pivot-column write, so every published column
+  // is in the order its readers hold; after the SOLVE_NB / 8 blocks x[r] is row r again.
+  static_assert(SOLVE_NB % 8 == 0, "whole blocks of 8 steps");
+  for (int o = 0; o < SOLVE_NB / 8; ++o) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int c = 8 * o + i;
+      // the update runs for every c (no merges of the register array); a step past
+      // nb has multiplier 0 and leaves x alone (its pivot row holds zeros)
+      const double2* f = piv[c & 1];
+      const double2 d = f[i];
+      const double rd = c < nb ? 1.0 / (d.x * d.x + d.y * d.y) : 0.0;
+      const double2 xi = x[i];
+      const double2 q = make_double2((xi.x * d.x + xi.y * d.y) * rd, (xi.y * d.x - xi.x * d.y) * rd);
+#pragma unroll
+      for (int rb = 0; rb < SOLVE_NB; rb += 8) {  // pivot column read 8 entries at a time
+        double2 fb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) fb[u] = f[rb + u];  // rows past nb hold zeros
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int r = rb + u;
+          if (r == i) continue;
+          x[r].x = fma(-fb[u].x, q.x, fma(fb[u].y, q.y, x[r].x));
+          x[r].y = fma(-fb[u].x, q.y, fma(-fb[u].y, q.x, x[r].y));
+        }
+      }
+      x[i] = q;
+      if (i == 7) {
+        double2 head[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) head[r] = x[r];
+#pragma unroll
+        for (int r = 0; r < SOLVE_NB - 8; ++r) x[r] = x[r + 8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) x[SOLVE_NB - 8 + r] = head[r];
+      }
+      if (c < nb) {
+        if (t == c + 1 && c + 1 < nb)
+#pragma unroll
+          for (int r = 0; r < SOLVE_NB; ++r) piv[(c + 1) & 1][r] = x[r];
+        __syncthreads();
+      }
     }
-    __syncthreads();
   }
-  for (int t = threadIdx.x; t < nb * W; t += blockDim.x) {
-    const int r = t / W, c = t - r * W;
-    if (c < wq) Q[(size_t)(k0 + r) * M + k0 + c] = P[t];
-    else R[(size_t)(k0 + r) * M + (c - wq)] = P[t];
-  }
-}
-
-__global__ __launch_bounds__(TPB) void update_kernel(const SsInst* __restrict__ si, int k0, int NB) {
-  const int g = blockIdx.x % SOLVE_GROUPS;
-  const SsInst& z = si[blockIdx.x / SOLVE_GROUPS];
-  const int M = z.M;
-  if (k0 >= M) return;
-  double2* __restrict__ Q = reinterpret_cast<double2*>(z.Z);
-  double2* __restrict__ R = reinterpret_cast<double2*>(z.R);
-  extern __shared__ double2 sh[];
-  const int nb = min(NB, M - k0);
-  const int wq = M - k0, W = wq + M;
-  // this workgroup's block of the M - nb rows outside the panel
-  const int rows = M - nb, r0 = g * rows / SOLVE_GROUPS, r1 = (g + 1) * rows / SOLVE_GROUPS, nr = r1 - r0;
-  if (nr <= 0) return;
-  double2* P = sh;               // reduced panel rows, nb x W
-  double2* F = sh + nb * W;      // multipliers of the block's rows, nr x nb
-  for (int t = threadIdx.x; t < nb * W; t += blockDim.x) {
-    const int r = t / W, c = t - r * W;
-    P[t] = c < wq ? Q[(size_t)(k0 + r) * M + k0 + c] : R[(size_t)(k0 + r) * M + (c - wq)];
-  }
-  for (int t = threadIdx.x; t < nr * nb; t += blockDim.x) {
-    const int r = t / nb, c = t - r * nb;
-    const int i = r0 + r < k0 ? r0 + r : r0 + r + nb;
-    F[t] = Q[(size_t)i * M + k0 + c];
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < nr * W; t += blockDim.x) {
-    const int r = t / W, col = t - r * W;
-    const int i = r0 + r < k0 ? r0 + r : r0 + r + nb;
-    double2* dst = col < wq ? &Q[(size_t)i * M + k0 + col] : &R[(size_t)i * M + (col - wq)];
-    if (col < nb) {
-      *dst = make_double2(0.0, 0.0);
-      continue;
-    }
-    double2 acc = *dst;
-    const double2* f = F + r * nb;
-    for (int u = 0; u < nb; ++u) {
-      const double2 q = P[u * W + col];
-      acc.x -= f[u].x * q.x - f[u].y * q.y;
-      acc.y -= f[u].x * q.y + f[u].y * q.x;
-    }
-    *dst = acc;
-  }
+  if (t >= SOLVE_NB && act)
+#pragma unroll
+    for (int r = 0; r < SOLVE_NB; ++r)
+      if (r < nb) {
+        if (col < wq) Q[(size_t)(k0 + r) * M + k0 + col] = x[r];
+        else R[(size_t)(k0 + r) * M + (col - wq)] = x[r];
+      }
 }
 
 __global__ void deriv_scale_kernel(const SsDeriv* __restrict__ di, const int* __restrict__ begin, int n, int total,
@@ -287,40 +292,13 @@ void launch_ss_combine_even(const SsInst* d, const int* d_begin, int n_inst, int
   if (total > 0) combine_even_kernel<<<blocks(total, TPB), TPB, 0, s>>>(d, d_begin, n_inst, total, b);
 }
 
-// LDS one workgroup may use: the device's limit, read once (64 KiB if it cannot be read)
-static size_t solve_lds_limit() {
-  static const size_t limit = [] {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
-      return (size_t)65536;
-    return (size_t)v;
-  }();
-  return limit;
-}
+int ss_solve_panel(int) { return SOLVE_NB; }
 
-int ss_solve_panel(int max_m) {
-  // LDS: nb panel rows of up to 2M complex, and per panel row one multiplier of each of
-  // the block's rows (at most M / SOLVE_GROUPS + 1) or one column value
-  const size_t per_row = sizeof(double2) * (2 * (size_t)max_m + (size_t)max_m / SOLVE_GROUPS + 2);
-  const int nb = (int)(solve_lds_limit() / per_row);
-  return std::max(1, std::min(SOLVE_NB_MAX, nb));
-}
-
-void launch_ss_solve(const SsInst* d, int n_inst, int max_m, hipStream_t s) {
-  if (n_inst <= 0 || max_m <= 0) return;
-  const int nb = ss_solve_panel(max_m);
-  const size_t lds = sizeof(double2) * ((size_t)nb * (2 * (size_t)max_m + (size_t)max_m / SOLVE_GROUPS + 2));
-  if (lds > 65536) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(panel_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(update_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  }
-  for (int k0 = 0; k0 < max_m; k0 += nb) {
-    panel_kernel<<<n_inst, SOLVE_TPB, lds, s>>>(d, k0, nb);
-    update_kernel<<<n_inst * SOLVE_GROUPS, TPB, lds, s>>>(d, k0, nb);
-  }
+void launch_ss_panel(const SsInst* d, int n_inst, int max_m, int k0, int nb, hipStream_t s) {
+  if (n_inst <= 0 || max_m <= 0 || nb <= 0 || nb > SOLVE_NB) return;
+  // columns right of the diagonal block: at most 2 max_m - 1
+  const int groups = blocks(2 * (int64_t)max_m - 1, SOLVE_COLS);
+  panel_kernel<<<n_inst * groups, SOLVE_TPB, 0, s>>>(d, k0, nb, groups);
 }
 
 void launch_ss_deriv_scale(const SsDeriv* d, const int* d_begin, int n_inst, int total, const int* s_dev,
