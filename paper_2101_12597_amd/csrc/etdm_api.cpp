@@ -615,7 +615,7 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       b.oW = pl.take(odd ? MM2 : 0);
       b.oE = pl.take(odd ? M : 0);
     }
-    h->ss_norms = pl.take(h->expm_ss ? h->n_inst : 0);
+    h->ss_norms = pl.take(h->expm_ss ? (int64_t)h->n_inst * SS_NORM_TILES : 0);
     h->ss_s_dev = reinterpret_cast<int*>(pl.take(h->expm_ss ? 1 : 0));
   }
   const int64_t np = h->n_param;

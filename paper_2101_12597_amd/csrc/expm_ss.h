@@ -24,6 +24,7 @@ namespace etdm {
 constexpr double SS_THETA9 = 2.097847961257068;  // 1-norm bound of the degree-9 approximant
 constexpr int SS_MAX_HALVINGS = 64;
 constexpr int SS_MAX_M = 1024;  // largest M of the scaling-and-squaring path
+constexpr int SS_NORM_TILES = (SS_MAX_M + 63) / 64;  // column tiles of the 1-norm per instance
 
 // Per instance: M x M complex matrices (interleaved re, im), row-major.
 struct SsInst {
@@ -53,7 +54,8 @@ struct PadeB9 {
   double b[10];
 };
 
-// 1-norm of every generator, then the batch's halvings s (device int).
+// 1-norm of every generator (largest column sum per tile of 64 columns; norms holds
+// n_inst * SS_NORM_TILES doubles), then the batch's halvings s (device int).
 void launch_ss_scaling(const SsInst* d, int n_inst, double* norms, int* s_dev, hipStream_t s);
 // X = A / 2^s as a full matrix
 void launch_ss_build(const SsInst* d, const int* d_begin, int n_inst, int total, const int* s_dev, hipStream_t s);

@@ -30,37 +30,82 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 
 // one workgroup per instance: the largest column sum of |A_ij|
-__global__ __launch_bounds__(TPB) void norm1_kernel(const SsInst* __restrict__ si, double* norms) {
-  const SsInst& z = si[blockIdx.x];
-  const int M = z.M;
-  double mx = 0.0;
-  for (int j = threadIdx.x; j < M; j += blockDim.x) {
-    double c = 0.0;
-    for (int i = 0; i < M; ++i) {
-      const double2 a = generator_at(z.A, M, i, j);
-      c += sqrt(a.x * a.x + a.y * a.y);
-    }
-    mx = fmax(mx, c);
-  }
-  __shared__ double red[TPB];
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int w = TPB / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) norms[blockIdx.x] = red[0];
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
 }
 
-// the fewest halvings that bring every instance's 1-norm under theta_9
-__global__ void scaling_kernel(const double* norms, int n_inst, int* s_dev) {
-  int s = 0;
-  for (int i = 0; i < n_inst; ++i) {
-    const double v = norms[i];
-    if (!isfinite(v)) continue;  // non-finite input: caught by the energy and gradient scans
-    while (s < SS_MAX_HALVINGS && ldexp(v, -s) > SS_THETA9) ++s;
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+  return v;
+}
+
+// Largest column 1-norm over one tile of 64 columns of a generator, read from the
+// stored upper triangle: column j of the generator has |a_ij| (i < j) above the
+// diagonal, |Im a_jj| on it and |a_ji| (i > j) below, which is row j of the upper
+// triangle.  Four wavefronts: the column parts row by row (lanes over columns) and the
+// row parts of the tile's 64 rows (lanes over the row); every read is coalesced.
+__global__ __launch_bounds__(TPB) void norm1_kernel(const SsInst* __restrict__ si, double* norms) {
+  static_assert(TPB == 256, "four wavefronts");
+  const SsInst& z = si[blockIdx.x / SS_NORM_TILES];
+  const int M = z.M, j0 = (blockIdx.x % SS_NORM_TILES) * 64;
+  if (j0 >= M) {
+    if (threadIdx.x == 0) norms[blockIdx.x] = 0.0;
+    return;
   }
-  *s_dev = s;
+  const double2* __restrict__ A = reinterpret_cast<const double2*>(z.A);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = j0 + lane;
+  __shared__ double cs[4][64];
+  __shared__ double rs[64];
+  double col = 0.0;
+  if (j < M) {
+    for (int i = wave; i < j; i += 4) {
+      const double2 a = A[(size_t)i * M + j];
+      col += sqrt(a.x * a.x + a.y * a.y);
+    }
+    if (wave == 0) col += fabs(A[(size_t)j * M + j].y);
+  }
+  cs[wave][lane] = col;
+  for (int rr = wave; rr < 64; rr += 4) {
+    const int r = j0 + rr;
+    double p = 0.0;
+    if (r < M)
+      for (int i = r + 1 + lane; i < M; i += 64) {
+        const double2 a = A[(size_t)r * M + i];
+        p += sqrt(a.x * a.x + a.y * a.y);
+      }
+    p = wave_sum(p);
+    if (lane == 0) rs[rr] = p;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const double t = j < M ? ((cs[0][lane] + cs[1][lane]) + (cs[2][lane] + cs[3][lane])) + rs[lane] : 0.0;
+    const double m = wave_max(t);
+    if (lane == 0) norms[blockIdx.x] = m;
+  }
+}
+
+// the fewest halvings s that bring every finite norm under theta_9: from the largest one
+__global__ __launch_bounds__(TPB) void scaling_kernel(const double* __restrict__ norms, int n, int* s_dev) {
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n; i += TPB) {
+    const double v = norms[i];
+    if (isfinite(v)) mx = fmax(mx, v);  // non-finite input: caught by the energy and gradient scans
+  }
+  mx = wave_max(mx);
+  __shared__ double wm[TPB / 64];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < TPB / 64; ++w) mx = fmax(mx, wm[w]);
+    mx = fmax(mx, wm[0]);
+    int s = 0;
+    while (s < SS_MAX_HALVINGS && ldexp(mx, -s) > SS_THETA9) ++s;
+    *s_dev = s;
+  }
 }
 
 __global__ void build_kernel(const SsInst* __restrict__ si, const int* __restrict__ begin, int n, int total,
@@ -274,8 +319,8 @@ __global__ void copy_back_kernel(const SsInst* __restrict__ si, const int* __res
 
 void launch_ss_scaling(const SsInst* d, int n_inst, double* norms, int* s_dev, hipStream_t s) {
   if (n_inst <= 0) return;
-  norm1_kernel<<<n_inst, TPB, 0, s>>>(d, norms);
-  scaling_kernel<<<1, 1, 0, s>>>(norms, n_inst, s_dev);
+  norm1_kernel<<<n_inst * SS_NORM_TILES, TPB, 0, s>>>(d, norms);
+  scaling_kernel<<<1, TPB, 0, s>>>(norms, n_inst * SS_NORM_TILES, s_dev);
 }
 
 void launch_ss_build(const SsInst* d, const int* d_begin, int n_inst, int total, const int* s_dev, hipStream_t s) {
