@@ -351,14 +351,24 @@ __device__ __forceinline__ double2 ld_zop(const double2* __restrict__ X, int64_t
   return v;
 }
 
+// Workgroups are handed to the 8 XCDs in turn (workgroup b runs on XCD b mod 8). This
+// maps them to tiles so that each XCD takes one contiguous range of the tile list: the
+// tiles of one problem, which share its A rows and B columns, then meet in one L2.
+__device__ __forceinline__ int xcd_tile(int b, int total) {
+  constexpr int XCDS = 8;
+  const int x = b % XCDS, q = b / XCDS, base = total / XCDS, rem = total % XCDS;
+  return x * base + min(x, rem) + q;
+}
+
 template <int OPA, int OPB>
 __global__ __launch_bounds__(NTHREADS) void zgemm_k4(const GemmProb* __restrict__ probs, const int* __restrict__ tile_prob) {
   constexpr int BK = 16;
   static_assert(BM * BK % NTHREADS == 0 && BN * BK % NTHREADS == 0, "whole k-tiles per thread");
   __shared__ double Ar[BK][BM + 1], Ai[BK][BM + 1];
   __shared__ double Br[BK][BN + 1], Bi[BK][BN + 1];
-  const GemmProb& p = probs[tile_prob[blockIdx.x]];
-  const int t = blockIdx.x - p.tile_begin;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const GemmProb& p = probs[tile_prob[tile]];
+  const int t = tile - p.tile_begin;
   const int row0 = (t / p.tiles_n) * BM, col0 = (t % p.tiles_n) * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -370,6 +380,9 @@ __global__ __launch_bounds__(NTHREADS) void zgemm_k4(const GemmProb* __restrict_
       cr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
       ci[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     }
+  const bool live_m[2] = {row0 + wm < p.m, row0 + wm + 16 < p.m};
+  const bool live_n[2] = {col0 + wn < p.n, col0 + wn + 16 < p.n};
+  const bool interior = live_m[1] && live_n[1];
   for (int seg = 0; seg < 2; ++seg) {
     const double2* A = reinterpret_cast<const double2*>(seg ? p.A2 : p.A);
     const double2* B = reinterpret_cast<const double2*>(seg ? p.B2 : p.B);
@@ -421,24 +434,31 @@ __global__ __launch_bounds__(NTHREADS) void zgemm_k4(const GemmProb* __restrict_
       }
       __syncthreads();
       if (k0 + BK < K) fetch(k0 + BK);
+      // 16 x 16 sub-tiles wholly outside C (the ragged edge) take no MFMAs; the test is
+      // uniform per wavefront, and interior tiles run the unguarded loop
+      auto step = [&](auto guarded) {
 #pragma unroll
-      for (int ks = 0; ks < BK; ks += 4) {
-        double ar[2], ai[2], nai[2], br[2], bi[2];
-        for (int i = 0; i < 2; ++i) {
-          ar[i] = Ar[ks + lk][wm + i * 16 + lr];
-          ai[i] = Ai[ks + lk][wm + i * 16 + lr];
-          nai[i] = -ai[i];
-          br[i] = Br[ks + lk][wn + i * 16 + lr];
-          bi[i] = Bi[ks + lk][wn + i * 16 + lr];
-        }
-        for (int i = 0; i < 2; ++i)
-          for (int j = 0; j < 2; ++j) {
-            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
-            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
+        for (int ks = 0; ks < BK; ks += 4) {
+          double ar[2], ai[2], nai[2], br[2], bi[2];
+          for (int i = 0; i < 2; ++i) {
+            ar[i] = Ar[ks + lk][wm + i * 16 + lr];
+            ai[i] = Ai[ks + lk][wm + i * 16 + lr];
+            nai[i] = -ai[i];
+            br[i] = Br[ks + lk][wn + i * 16 + lr];
+            bi[i] = Bi[ks + lk][wn + i * 16 + lr];
           }
-      }
+          for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+              if (decltype(guarded)::value && !(live_m[i] && live_n[j])) continue;
+              cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
+              cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cr[i][j], 0, 0, 0);
+              ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
+              ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
+            }
+        }
+      };
+      if (interior) step(std::false_type{});
+      else step(std::true_type{});
       __syncthreads();
     }
   }
