@@ -22,6 +22,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "reduce.h"
 
 namespace etdm {
 
@@ -125,8 +126,9 @@ __global__ __launch_bounds__(NTHREADS) void gemm_k4(const GemmProb* __restrict__
   constexpr int BK = K4_BK;
   __shared__ T As[K4_LDS];
   __shared__ T Bs[K4_LDS];
-  const GemmProb& p = probs[tile_prob[blockIdx.x]];
-  const int t = blockIdx.x - p.tile_begin;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const GemmProb& p = probs[tile_prob[tile]];
+  const int t = tile - p.tile_begin;
   const int row0 = (t / p.tiles_n) * BM, col0 = (t % p.tiles_n) * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -136,6 +138,9 @@ __global__ __launch_bounds__(NTHREADS) void gemm_k4(const GemmProb* __restrict__
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+  const bool live_m[2] = {row0 + wm < p.m, row0 + wm + 16 < p.m};
+  const bool live_n[2] = {col0 + wn < p.n, col0 + wn + 16 < p.n};
+  const bool interior = live_m[1] && live_n[1];
 
   for (int seg = 0; seg < 2; ++seg) {
     const double* A = seg ? p.A2 : p.A;
@@ -185,22 +190,27 @@ __global__ __launch_bounds__(NTHREADS) void gemm_k4(const GemmProb* __restrict__
       commit();
       __syncthreads();
       if (k0 + BK < K) fetch(k0 + BK);
+      // 16 x 16 sub-tiles wholly outside C take no MFMAs (wavefront-uniform test;
+      // interior tiles run the unguarded loop)
+      auto step = [&](auto guarded) {
 #pragma unroll
-      for (int ks = 0; ks < BK; ks += 4) {
-        const T a0 = As[a_lds<TA>(ks + lk, wm + lr)], a1 = As[a_lds<TA>(ks + lk, wm + 16 + lr)];
-        const T b0 = Bs[b_lds<TB>(ks + lk, wn + lr)], b1 = Bs[b_lds<TB>(ks + lk, wn + 16 + lr)];
-        if constexpr (sizeof(T) == 8) {
-          c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c[0][0], 0, 0, 0);
-          c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, c[0][1], 0, 0, 0);
-          c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, c[1][0], 0, 0, 0);
-          c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c[1][1], 0, 0, 0);
-        } else {
-          c[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, c[0][0], 0, 0, 0);
-          c[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, c[0][1], 0, 0, 0);
-          c[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, c[1][0], 0, 0, 0);
-          c[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, c[1][1], 0, 0, 0);
+        for (int ks = 0; ks < BK; ks += 4) {
+          const T a[2] = {As[a_lds<TA>(ks + lk, wm + lr)], As[a_lds<TA>(ks + lk, wm + 16 + lr)]};
+          const T b[2] = {Bs[b_lds<TB>(ks + lk, wn + lr)], Bs[b_lds<TB>(ks + lk, wn + 16 + lr)]};
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              if (decltype(guarded)::value && !(live_m[i] && live_n[j])) continue;
+              if constexpr (sizeof(T) == 8)
+                c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], c[i][j], 0, 0, 0);
+              else
+                c[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], c[i][j], 0, 0, 0);
+            }
         }
-      }
+      };
+      if (interior) step(std::false_type{});
+      else step(std::true_type{});
       __syncthreads();
       if constexpr (sizeof(T) == 4) {
         since_flush += BK;
@@ -247,8 +257,9 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf16split(const GemmProb* __res
   // reads its 8 consecutive k values of one row as a single 16-byte vector
   __shared__ __attribute__((aligned(16))) __bf16 As[NS][BK / 8][BM][8];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[NS][BK / 8][BN][8];
-  const GemmProb& p = probs[tile_prob[blockIdx.x]];
-  const int t = blockIdx.x - p.tile_begin;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const GemmProb& p = probs[tile_prob[tile]];
+  const int t = tile - p.tile_begin;
   const int row0 = (t / p.tiles_n) * BM, col0 = (t % p.tiles_n) * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -349,15 +360,6 @@ __device__ __forceinline__ double2 ld_zop(const double2* __restrict__ X, int64_t
   double2 v = X[(int64_t)c * ld + r];
   if (OP == OP_C) v.y = -v.y;
   return v;
-}
-
-// Workgroups are handed to the 8 XCDs in turn (workgroup b runs on XCD b mod 8). This
-// maps them to tiles so that each XCD takes one contiguous range of the tile list: the
-// tiles of one problem, which share its A rows and B columns, then meet in one L2.
-__device__ __forceinline__ int xcd_tile(int b, int total) {
-  constexpr int XCDS = 8;
-  const int x = b % XCDS, q = b / XCDS, base = total / XCDS, rem = total % XCDS;
-  return x * base + min(x, rem) + q;
 }
 
 template <int OPA, int OPB>

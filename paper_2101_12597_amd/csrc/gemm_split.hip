@@ -32,6 +32,7 @@
 // MFMAs; tiles are ordered in groups of X_GROUP tile rows and dealt out so that
 // each XCD works on a contiguous range.
 #include "common.h"
+#include "reduce.h"
 
 namespace etdm {
 
@@ -113,13 +114,6 @@ __device__ __forceinline__ void x6_tile(const SplitProb& p, int lt, int& tm, int
   const int idx = lt - g * per_group;
   tm = g * X_GROUP + idx % gr;
   tn = idx / gr;
-}
-
-// logical tile of workgroup b: workgroups are dealt to the 8 XCDs in turn, so
-// consecutive logical tiles are given to the workgroups of one XCD (shared L2)
-__device__ __forceinline__ int xcd_tile(int b, int total) {
-  const int t8 = total & ~7;
-  return b < t8 ? (b & 7) * (t8 >> 3) + (b >> 3) : b;
 }
 
 template <int TPM, int TPN>

@@ -50,4 +50,13 @@ __device__ inline double block_sum_neumaier(double s, double c, double* red) {
   return S + Cc;
 }
 
+// Workgroups are handed to the 8 XCDs in turn (workgroup b runs on XCD b mod 8). This
+// maps them to tiles so that each XCD takes one contiguous range of the tile list: the
+// tiles of one problem, which share its A rows and B columns, then meet in one L2.
+__device__ __forceinline__ int xcd_tile(int b, int total) {
+  constexpr int XCDS = 8;
+  const int x = b % XCDS, q = b / XCDS, base = total / XCDS, rem = total % XCDS;
+  return x * base + min(x, rem) + q;
+}
+
 }  // namespace etdm
