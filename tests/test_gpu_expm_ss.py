@@ -120,3 +120,39 @@ def test_ss_exact_lbfgs_steps():
             assert info["E"] <= prev + 1e-6 * abs(prev)
         prev = info["E"]
     h.close()
+
+
+def _ragged_batch():
+    """Three uncoupled instances of different M in one batch: M = 70 and 45 take three
+    and two panels of the blocked solve (the last ones ragged) while M = 33 leaves off
+    after its second panel of one row, and every panel spans several column groups."""
+    parts = [tiny_complex(M, nk_side=1, kT=0.1, seed=s) for M, s in ((70, 1), (45, 2), (33, 3))]
+    wl = parts[0]
+    wl.instances = [p.instances[0] for p in parts]
+    wl.couple = False
+    wl.name = "ragged complex M = 70, 45, 33"
+    return wl
+
+
+@pytest.mark.parametrize("scale", [1.0, 20.0])
+def test_ss_ragged_batch(scale):
+    wl = _ragged_batch()
+    params = [scale * p for p in O.parity_params(wl)]
+    s_max = max(O.pade_degree_and_scaling(float(np.abs(O.generator(wl.kind, p)).sum(axis=0).max()))[1]
+                for p in params)
+    print(f"[case] ss ragged batch, scale {scale} (oracle halvings up to {s_max})", flush=True)
+    h, _ = make_handle(wl, "fp64", gradient="approx", expm="ss")
+    E, G = energy_grad(h, wl, params)
+    U = expm(h, wl, params)
+    h.close()
+    E_ref, G_ref = O.energy_grad_approx(wl, params, expm=O.expm_ss)
+    assert abs(E[-1] - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
+    assert rel_err(G, G_ref) < 1e-10
+    for u, p in zip(U, params):
+        assert np.abs(u - O.expm_ss(O.generator(wl.kind, p))).max() < 1e-13 * 2.0 ** (s_max + 2)
+    h, _ = make_handle(wl, "fp64", expm="ss")
+    E, G = energy_grad(h, wl, params)
+    h.close()
+    E_ref, G_ref = O.energy_grad_ss(wl, params)
+    assert abs(E[-1] - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
+    assert rel_err(G, G_ref) < 1e-10 * max(1.0, scale)
