@@ -404,8 +404,8 @@ struct etdm_handle {
   const double** d_ss_r = nullptr;
   double** d_ss_r0 = nullptr;
   const double** d_ss_lu = nullptr;
-  Stage fr_M2a, fr_M2b, fr_M4a, fr_M4b, fr_M6a, fr_M6b, fr_M8a, fr_M8b, fr_LUa, fr_LUb, fr_N;
-  Stage fr_sq[2][3];  // per parity of the squaring step: R L, + L R, R R
+  Stage fr_M2, fr_M4, fr_M6, fr_M8, fr_LU, fr_N;  // sums of two products: one launch, two K segments
+  Stage fr_sq[2][2];  // per parity of the squaring step: R L + L R, R R
   Stage fr_Y[2];      // Y = L_s exp(A)^H, by the parity of s
   double odd_lam = 0.0;  // orbital-dependent model term (0: off)
   int has_overlap = 0;   // created from a non-orthogonal basis (H0, C0 Lowdin-transformed)
@@ -987,10 +987,9 @@ etdm_status build_z_plan(etdm_handle* h) {
   for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_X8, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
     st->init(OP_N, OP_N, GP_FP64, true);
   const bool ss_exact = h->expm_ss && !h->grad_approx;
-  std::vector<Stage*> fr_all = {&h->fr_M2a, &h->fr_M2b, &h->fr_M4a, &h->fr_M4b, &h->fr_M6a, &h->fr_M6b,
-                                &h->fr_M8a, &h->fr_M8b, &h->fr_LUa, &h->fr_LUb, &h->fr_N};
+  std::vector<Stage*> fr_all = {&h->fr_M2, &h->fr_M4, &h->fr_M6, &h->fr_M8, &h->fr_LU, &h->fr_N};
   for (int k = 0; k < 2; ++k)
-    for (int c = 0; c < 3; ++c) fr_all.push_back(&h->fr_sq[k][c]);
+    for (int c = 0; c < 2; ++c) fr_all.push_back(&h->fr_sq[k][c]);
   for (Stage* st : fr_all) st->init(OP_N, OP_N, GP_FP64, true);
   h->fr_Y[0].init(OP_N, OP_C, GP_FP64, true);
   h->fr_Y[1].init(OP_N, OP_C, GP_FP64, true);
@@ -1107,25 +1106,29 @@ etdm_status build_z_plan(etdm_handle* h) {
         p.ldd = M;
         return p;
       };
-      h->fr_M2a.add(prob(M, M, M, b.sX, M, b.sEs, M, b.sM2, M));
-      h->fr_M2b.add(acc(prob(M, M, M, b.sEs, M, b.sX, M, b.sM2, M), b.sM2));
-      h->fr_M4a.add(prob(M, M, M, b.sX2, M, b.sM2, M, b.sM4, M));
-      h->fr_M4b.add(acc(prob(M, M, M, b.sM2, M, b.sX2, M, b.sM4, M), b.sM4));
-      h->fr_M6a.add(prob(M, M, M, b.sX4, M, b.sM2, M, b.sM6, M));
-      h->fr_M6b.add(acc(prob(M, M, M, b.sM4, M, b.sX2, M, b.sM6, M), b.sM6));
-      h->fr_M8a.add(prob(M, M, M, b.sX4, M, b.sM4, M, b.sM8, M));
-      h->fr_M8b.add(acc(prob(M, M, M, b.sM4, M, b.sX4, M, b.sM8, M), b.sM8));
-      h->fr_LUa.add(prob(M, M, M, b.sX, M, b.sLT, M, b.sLU, M));
-      h->fr_LUb.add(acc(prob(M, M, M, b.sEs, M, b.sT, M, b.sLU, M), b.sLU));
+      // C = A B + A2 B2 in one launch (the second product as the second K segment)
+      auto sum2 = [&](const double* A, const double* B, const double* A2, const double* B2, double* C) {
+        GemmProb p = prob(M, M, M, A, M, B, M, C, M);
+        p.A2 = A2;
+        p.B2 = B2;
+        p.lda2 = p.ldb2 = M;
+        p.k2 = M;
+        p.alpha2 = 1.0;
+        return p;
+      };
+      h->fr_M2.add(sum2(b.sX, b.sEs, b.sEs, b.sX, b.sM2));
+      h->fr_M4.add(sum2(b.sX2, b.sM2, b.sM2, b.sX2, b.sM4));
+      h->fr_M6.add(sum2(b.sX4, b.sM2, b.sM4, b.sX2, b.sM6));
+      h->fr_M8.add(sum2(b.sX4, b.sM4, b.sM4, b.sX4, b.sM8));
+      h->fr_LU.add(sum2(b.sX, b.sLT, b.sEs, b.sT, b.sLU));
       // right-hand side (LU + LV) - (LV - LU) r, with LT = LV - LU and LV = LU + LV
       h->fr_N.add(acc(prob(M, M, M, b.sLT, M, b.sR0, M, b.sLV, M, -1.0), b.sLV));
       double* Rb[2] = {b.sR0, b.sRa};
       double* Lb[2] = {b.sLV, b.sLa};
       for (int k = 0; k < 2; ++k) {
         double *R = Rb[k], *L = Lb[k], *Rn = Rb[1 - k], *Ln = Lb[1 - k];
-        h->fr_sq[k][0].add(prob(M, M, M, R, M, L, M, Ln, M));
-        h->fr_sq[k][1].add(acc(prob(M, M, M, L, M, R, M, Ln, M), Ln));
-        h->fr_sq[k][2].add(prob(M, M, M, R, M, R, M, Rn, M));
+        h->fr_sq[k][0].add(sum2(R, L, L, R, Ln));
+        h->fr_sq[k][1].add(prob(M, M, M, R, M, R, M, Rn, M));
         h->fr_Y[k].add(prob(M, M, M, L, M, b.Ue, M, b.Y, M));
       }
     }
@@ -1232,8 +1235,7 @@ etdm_status build_z_plan(etdm_handle* h) {
     h->timers[Z_SS_SQUARE].flops = stage_flops(h->ss_sq0);  // per squaring
     h->timers[Z_SS_SQUARE].bytes = stage_bytes(h->ss_sq0);
     // Frechet phase without its squaring steps (three products per halving on top)
-    for (Stage* st : {&h->fr_M2a, &h->fr_M2b, &h->fr_M4a, &h->fr_M4b, &h->fr_M6a, &h->fr_M6b, &h->fr_M8a,
-                      &h->fr_M8b, &h->fr_LUa, &h->fr_LUb, &h->fr_N, &h->fr_Y[0]}) {
+    for (Stage* st : {&h->fr_M2, &h->fr_M4, &h->fr_M6, &h->fr_M8, &h->fr_LU, &h->fr_N, &h->fr_Y[0]}) {
       h->timers[Z_SS_FRECHET].flops += stage_flops(*st);
       h->timers[Z_SS_FRECHET].bytes += stage_bytes(*st);
     }
@@ -1581,17 +1583,14 @@ void z_energy_grad(etdm_handle* h, hipStream_t s) {
     TIMED(Z_SS_FRECHET);
     const int sq = *h->ss_s_host;  // this evaluation's halvings
     launch_ss_deriv_scale(h->d_ssd, h->b_mat, h->n_inst, h->tot_mat, h->ss_s_dev, s);
-    for (Stage* st : {&h->fr_M2a, &h->fr_M2b, &h->fr_M4a, &h->fr_M4b, &h->fr_M6a, &h->fr_M6b, &h->fr_M8a,
-                      &h->fr_M8b})
-      st->launch(s);
+    for (Stage* st : {&h->fr_M2, &h->fr_M4, &h->fr_M6, &h->fr_M8}) st->launch(s);
     launch_ss_deriv_combine(h->d_ssd, h->b_mat, h->n_inst, h->tot_mat, h->ss_b, s);
-    h->fr_LUa.launch(s);
-    h->fr_LUb.launch(s);
+    h->fr_LU.launch(s);
     launch_ss_deriv_rhs(h->d_ssd, h->d_ss_lu, h->b_mat, h->n_inst, h->tot_mat, s);
     h->fr_N.launch(s);
     ss_solve(h, h->d_ss2, h->ss_up[1], s);
     for (int k = 0; k < sq; ++k)
-      for (int c = 0; c < 3; ++c) h->fr_sq[k % 2][c].launch(s);
+      for (int c = 0; c < 2; ++c) h->fr_sq[k % 2][c].launch(s);
     h->fr_Y[sq % 2].launch(s);
   }
   if (!h->z_LV.probs.empty()) {
