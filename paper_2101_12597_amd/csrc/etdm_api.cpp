@@ -395,7 +395,7 @@ struct etdm_handle {
   int ss_nb = 0;                 // panel width of the solve
   std::vector<Stage> ss_up[2];   // per panel: the rank-nb row updates of the two solves
   PadeB9 ss_b{};
-  Stage ss_X2, ss_X4, ss_X6, ss_X8, ss_U, ss_sq0, ss_sq1;
+  Stage ss_X2, ss_X4, ss_X68, ss_U, ss_sq0, ss_sq1;  // X6 and X8 in one launch
   // exact gradient on the ss path
   SsDeriv* d_ssd = nullptr;
   SsInst* d_ss2 = nullptr;  // second solve: [q(X) copy | right-hand side]
@@ -404,8 +404,8 @@ struct etdm_handle {
   const double** d_ss_r = nullptr;
   double** d_ss_r0 = nullptr;
   const double** d_ss_lu = nullptr;
-  Stage fr_M2, fr_M4, fr_M6, fr_M8, fr_LU, fr_N;  // sums of two products: one launch, two K segments
-  Stage fr_sq[2][2];  // per parity of the squaring step: R L + L R, R R
+  Stage fr_M2, fr_M4, fr_M68, fr_LU, fr_N;  // sums of two products: one launch, two K segments (M6, M8 together)
+  Stage fr_sq[2];     // per parity of the squaring step: L R + R L and R R in one launch
   Stage fr_Y[2];      // Y = L_s exp(A)^H, by the parity of s
   double odd_lam = 0.0;  // orbital-dependent model term (0: off)
   int has_overlap = 0;   // created from a non-orthogonal basis (H0, C0 Lowdin-transformed)
@@ -984,12 +984,10 @@ etdm_status build_z_plan(etdm_handle* h) {
   h->z_Y.init(OP_N, OP_N, GP_FP64, true);
   h->z_HC0.init(OP_N, OP_N, GP_FP64, true);
   h->z_odd.init(OP_C, OP_N, GP_FP64, true);
-  for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_X8, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
+  for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X68, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
     st->init(OP_N, OP_N, GP_FP64, true);
   const bool ss_exact = h->expm_ss && !h->grad_approx;
-  std::vector<Stage*> fr_all = {&h->fr_M2, &h->fr_M4, &h->fr_M6, &h->fr_M8, &h->fr_LU, &h->fr_N};
-  for (int k = 0; k < 2; ++k)
-    for (int c = 0; c < 2; ++c) fr_all.push_back(&h->fr_sq[k][c]);
+  std::vector<Stage*> fr_all = {&h->fr_M2, &h->fr_M4, &h->fr_M68, &h->fr_LU, &h->fr_N, &h->fr_sq[0], &h->fr_sq[1]};
   for (Stage* st : fr_all) st->init(OP_N, OP_N, GP_FP64, true);
   h->fr_Y[0].init(OP_N, OP_C, GP_FP64, true);
   h->fr_Y[1].init(OP_N, OP_C, GP_FP64, true);
@@ -1084,8 +1082,8 @@ etdm_status build_z_plan(etdm_handle* h) {
       ss.push_back(SsInst{b.A, b.sX, b.sX2, b.sX4, b.sX6, b.sX8, b.sT, b.sU, b.sZ, b.Ue, sq, M});
       h->ss_X2.add(prob(M, M, M, b.sX, M, b.sX, M, b.sX2, M));
       h->ss_X4.add(prob(M, M, M, b.sX2, M, b.sX2, M, b.sX4, M));
-      h->ss_X6.add(prob(M, M, M, b.sX4, M, b.sX2, M, b.sX6, M));
-      h->ss_X8.add(prob(M, M, M, b.sX4, M, b.sX4, M, b.sX8, M));
+      h->ss_X68.add(prob(M, M, M, b.sX4, M, b.sX2, M, b.sX6, M));
+      h->ss_X68.add(prob(M, M, M, b.sX4, M, b.sX4, M, b.sX8, M));
       h->ss_U.add(prob(M, M, M, b.sX, M, b.sT, M, b.sU, M));  // U = X (b9 X8 + ... + b1 I)
       h->ss_sq0.add(prob(M, M, M, b.Ue, M, b.Ue, M, sq, M));
       h->ss_sq1.add(prob(M, M, M, sq, M, sq, M, b.Ue, M));
@@ -1118,8 +1116,8 @@ etdm_status build_z_plan(etdm_handle* h) {
       };
       h->fr_M2.add(sum2(b.sX, b.sEs, b.sEs, b.sX, b.sM2));
       h->fr_M4.add(sum2(b.sX2, b.sM2, b.sM2, b.sX2, b.sM4));
-      h->fr_M6.add(sum2(b.sX4, b.sM2, b.sM4, b.sX2, b.sM6));
-      h->fr_M8.add(sum2(b.sX4, b.sM4, b.sM4, b.sX4, b.sM8));
+      h->fr_M68.add(sum2(b.sX4, b.sM2, b.sM4, b.sX2, b.sM6));
+      h->fr_M68.add(sum2(b.sX4, b.sM4, b.sM4, b.sX4, b.sM8));
       h->fr_LU.add(sum2(b.sX, b.sLT, b.sEs, b.sT, b.sLU));
       // right-hand side (LU + LV) - (LV - LU) r, with LT = LV - LU and LV = LU + LV
       h->fr_N.add(acc(prob(M, M, M, b.sLT, M, b.sR0, M, b.sLV, M, -1.0), b.sLV));
@@ -1127,8 +1125,8 @@ etdm_status build_z_plan(etdm_handle* h) {
       double* Lb[2] = {b.sLV, b.sLa};
       for (int k = 0; k < 2; ++k) {
         double *R = Rb[k], *L = Lb[k], *Rn = Rb[1 - k], *Ln = Lb[1 - k];
-        h->fr_sq[k][0].add(sum2(R, L, L, R, Ln));
-        h->fr_sq[k][1].add(prob(M, M, M, R, M, R, M, Rn, M));
+        h->fr_sq[k].add(sum2(R, L, L, R, Ln));
+        h->fr_sq[k].add(prob(M, M, M, R, M, R, M, Rn, M));
         h->fr_Y[k].add(prob(M, M, M, L, M, b.Ue, M, b.Y, M));
       }
     }
@@ -1174,7 +1172,7 @@ etdm_status build_z_plan(etdm_handle* h) {
     // numerator coefficients of the [9/9] approximant: b_0 = 1, b_{j+1} = b_j (m - j) / ((2m - j)(j + 1))
     h->ss_b.b[0] = 1.0;
     for (int j = 0; j < 9; ++j) h->ss_b.b[j + 1] = h->ss_b.b[j] * (9 - j) / ((18.0 - j) * (j + 1));
-    for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_X8, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
+    for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X68, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
       CHECK(upload_stage(h, *st));
   }
   if (ss_exact) {
@@ -1228,14 +1226,14 @@ etdm_status build_z_plan(etdm_handle* h) {
         h->timers[Z_SS_SOLVE].bytes += 32.0 * M * M;
       }
     }
-    for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X6, &h->ss_X8, &h->ss_U}) {
+    for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X68, &h->ss_U}) {
       h->timers[Z_SS_PADE].flops += stage_flops(*st);
       h->timers[Z_SS_PADE].bytes += stage_bytes(*st);
     }
     h->timers[Z_SS_SQUARE].flops = stage_flops(h->ss_sq0);  // per squaring
     h->timers[Z_SS_SQUARE].bytes = stage_bytes(h->ss_sq0);
     // Frechet phase without its squaring steps (three products per halving on top)
-    for (Stage* st : {&h->fr_M2, &h->fr_M4, &h->fr_M6, &h->fr_M8, &h->fr_LU, &h->fr_N, &h->fr_Y[0]}) {
+    for (Stage* st : {&h->fr_M2, &h->fr_M4, &h->fr_M68, &h->fr_LU, &h->fr_N, &h->fr_Y[0]}) {
       h->timers[Z_SS_FRECHET].flops += stage_flops(*st);
       h->timers[Z_SS_FRECHET].bytes += stage_bytes(*st);
     }
@@ -1500,8 +1498,7 @@ void ss_exponential(etdm_handle* h, hipStream_t s) {
     launch_ss_build(h->d_ss, h->b_mat, h->n_inst, h->tot_mat, h->ss_s_dev, s);
     h->ss_X2.launch(s);
     h->ss_X4.launch(s);
-    h->ss_X6.launch(s);
-    h->ss_X8.launch(s);
+    h->ss_X68.launch(s);
     launch_ss_combine_odd(h->d_ss, h->b_mat, h->n_inst, h->tot_mat, h->ss_b, s);
     h->ss_U.launch(s);
     launch_ss_combine_even(h->d_ss, h->b_mat, h->n_inst, h->tot_mat, h->ss_b, s);
@@ -1583,14 +1580,13 @@ void z_energy_grad(etdm_handle* h, hipStream_t s) {
     TIMED(Z_SS_FRECHET);
     const int sq = *h->ss_s_host;  // this evaluation's halvings
     launch_ss_deriv_scale(h->d_ssd, h->b_mat, h->n_inst, h->tot_mat, h->ss_s_dev, s);
-    for (Stage* st : {&h->fr_M2, &h->fr_M4, &h->fr_M6, &h->fr_M8}) st->launch(s);
+    for (Stage* st : {&h->fr_M2, &h->fr_M4, &h->fr_M68}) st->launch(s);
     launch_ss_deriv_combine(h->d_ssd, h->b_mat, h->n_inst, h->tot_mat, h->ss_b, s);
     h->fr_LU.launch(s);
     launch_ss_deriv_rhs(h->d_ssd, h->d_ss_lu, h->b_mat, h->n_inst, h->tot_mat, s);
     h->fr_N.launch(s);
     ss_solve(h, h->d_ss2, h->ss_up[1], s);
-    for (int k = 0; k < sq; ++k)
-      for (int c = 0; c < 2; ++c) h->fr_sq[k % 2][c].launch(s);
+    for (int k = 0; k < sq; ++k) h->fr_sq[k % 2].launch(s);
     h->fr_Y[sq % 2].launch(s);
   }
   if (!h->z_LV.probs.empty()) {
