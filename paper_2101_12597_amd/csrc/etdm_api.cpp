@@ -353,7 +353,8 @@ struct etdm_handle {
   // Q1 = C0_v B^T does not depend on the eigendecomposition: it runs on a side
   // stream beside the eigensolver (forked and joined by events)
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;    // Q1 beside the eigensolver
+  hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;  // Z1, C_virt beside C_occ, rows and energy
   Stage s_Uov, s_Uvv, s_HC0;                                                   // real: expm, preconditioner
   Stage z_Ue, z_C, z_T, z_HMO, z_LV, z_Lt, z_W1, z_Y, z_HC0;                   // complex
   // L-BFGS: scalars and decisions in lb_st (device); the host keeps the iteration
@@ -382,7 +383,6 @@ struct etdm_handle {
   hipGraphExec_t graph2_exec = nullptr;
   int* ok_host = nullptr;               // pinned: acceptance flags of the large instances
   // packed operands of the FP64 / BF16x6 stages (shared: stages run in order)
-  char* pack_arena = nullptr;
   int gemm_tuning = 0;
   int grad_approx = 0;  // 1: G ~ L^T (Eq. app_grad) instead of the exact gradient
   // exp(A) by scaling and squaring (Eq. ss) instead of the eigendecomposition
@@ -649,9 +649,10 @@ etdm_status upload_stage(etdm_handle* h, Stage& s) {
   return upload(h, &s.d_tile_prob, s.tile_prob);
 }
 
-// Packed operands for every FP64 / BF16x6 stage: one arena of the largest
-// stage's size (the stages of a launch sequence run one after another, and a
-// stage runs one variant at a time).
+// Packed operands for every FP64 / BF16x6 stage of the list: one arena of the largest
+// stage's size (the stages of one stream run one after another, and a stage runs one
+// variant at a time).  Stages that can run on different streams at the same time take
+// arenas of their own (one call each).
 etdm_status plan_packed_stages(etdm_handle* h, Stage* const* stages, size_t n) {
   size_t bytes = 0;
   for (size_t i = 0; i < n; ++i)
@@ -661,12 +662,12 @@ etdm_status plan_packed_stages(etdm_handle* h, Stage* const* stages, size_t n) {
   void* p = nullptr;
   HIPCHK(h, hipMalloc(&p, bytes));
   h->dev_allocs.push_back(p);
-  h->pack_arena = reinterpret_cast<char*>(p);
+  char* arena = reinterpret_cast<char*>(p);
   for (size_t i = 0; i < n; ++i) {
     Stage& sg = *stages[i];
     if (!sg.can_pack()) continue;
     for (int v = V_P11; v < V_COUNT; ++v) {
-      sg.plan_pack(v, h->pack_arena);
+      sg.plan_pack(v, arena);
       PackPlan& q = sg.pk[v - 1];
       CHECK(upload(h, &q.d_jobs, q.jobs));
       CHECK(upload(h, &q.d_chunk_job, q.chunk_job));
@@ -929,6 +930,16 @@ etdm_status build_ov_plan(etdm_handle* h) {
     }
     CHECK(upload(h, &h->d_lchk, lchk));
   }
+  // Q1, Z1 and C_virt can run on the side stream beside main-stream stages (the
+  // eigensolver's products, C_occ): they pack into an arena of their own
+  Stage* const side_stages[] = {&h->s_Q1, &h->s_Z, &h->s_V};
+  packable.erase(std::remove_if(packable.begin(), packable.end(),
+                                [&](Stage* st) {
+                                  return std::find(std::begin(side_stages), std::end(side_stages), st) !=
+                                         std::end(side_stages);
+                                }),
+                 packable.end());
+  CHECK(plan_packed_stages(h, side_stages, 3));
   CHECK(plan_packed_stages(h, packable.data(), packable.size()));
   CHECK(upload(h, &h->d_spec, spec));
   CHECK(upload(h, &h->b_spec, bspec));
@@ -1320,6 +1331,8 @@ void free_handle(etdm_handle* h) {
   if (h->side) hipStreamDestroy(h->side);
   if (h->ev_fork) hipEventDestroy(h->ev_fork);
   if (h->ev_join) hipEventDestroy(h->ev_join);
+  if (h->ev_fork2) hipEventDestroy(h->ev_fork2);
+  if (h->ev_join2) hipEventDestroy(h->ev_join2);
   free_timers(h);
   if (h->base) hipFree(h->base);
   for (void* p : h->dev_allocs) hipFree(p);
@@ -1402,8 +1415,21 @@ void ov_energy_grad(etdm_handle* h, hipStream_t s) {
 
 // After the exponential part: C, H0 C_occ, the energy, L and the gradient.
 void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
+  // Z1 and C_virt need only the spectral factors and Q1: on the side stream, beside
+  // C_occ, the rows and the energy (in order while stages are timed); joined before L_ov
+  const bool fork = h->side && h->tmask == 0;
+  if (fork) {
+    hipEventRecord(h->ev_fork2, s);
+    hipStreamWaitEvent(h->side, h->ev_fork2, 0);
+    h->s_Z.launch(h->side);
+    h->s_V.launch(h->side);
+    hipEventRecord(h->ev_join2, h->side);
+  }
   { TIMED(O_C); h->s_C.launch(s); }
-  { TIMED(O_Z); h->s_Z.launch(s); }
+  if (!fork) {
+    TIMED(O_Z);
+    h->s_Z.launch(s);
+  }
   {
     // block-sparse H0: T = H0 C_occ here (dense H0: T was formed with C_occ)
     if (h->h0_format == 1) {
@@ -1414,13 +1440,17 @@ void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
       }
     }
   }
-  { TIMED(O_V); h->s_V.launch(s); }
+  if (!fork) {
+    TIMED(O_V);
+    h->s_V.launch(s);
+  }
   { TIMED(O_ROWS); launch_ov_rows(h->d_rows, h->b_rows, h->n_inst, h->tot_rows, h->U, s); }
   {
     TIMED(O_ENERGY);
     launch_ov_energy(h->d_energy, h->n_inst, h->U, h->E_ws, s);
     launch_total_energy(h->E_ws, h->n_inst, 0.0, nullptr, 0, h->U, h->status, s);
   }
+  if (fork) hipStreamWaitEvent(s, h->ev_join2, 0);
   { TIMED(O_LOV); h->s_Lov.launch(s); }
   if (!h->s_R.probs.empty()) {
     TIMED(O_R);
@@ -2125,7 +2155,9 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (st == ETDM_OK && real && stage_flops(h->s_Q1) >= 1e8 &&
       (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
        hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-       hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess))
+       hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&h->ev_fork2, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&h->ev_join2, hipEventDisableTiming) != hipSuccess))
     st = ETDM_E_HIP;
   if (st != ETDM_OK) return bail(st);
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) return bail(ETDM_E_HIP);
