@@ -284,12 +284,12 @@ struct StageTimer {
 
 // stage indices of the two paths
 enum OvStage { O_PQ, O_EIGL, O_EIGG, O_SPEC, O_F3MU, O_C, O_Z, O_T, O_V, O_ROWS, O_ENERGY, O_LOV, O_R, O_GAM1,
-               O_GAM, O_PAIR, O_Y1, O_Y2, O_G, O_SCAN, O_Q1, O_COUNT };
+               O_GAM, O_PAIR, O_Y1, O_Y2, O_G, O_SCAN, O_Q1, O_CONG, O_COUNT };
 const char* kOvNames[O_COUNT] = {"gemm_P",  "eigh_lds",  "eigh_global", "spectral_tables", "gemm_funcs_mu",
                                  "gemm_Cocc",  "gemm_Z1",   "gemm_H0C",    "gemm_Cvirt",      "rows_density_hubbard",
                                  "energy_reduce", "gemm_Lov", "gemm_R",    "gemm_Gam1",       "gemm_Gam",
                                  "pair_hadamard", "gemm_Y1", "gemm_Y2",    "gemm_grad",       "nonfinite_scan",
-                                 "gemm_Q1"};
+                                 "gemm_Q1", "ov_congruence"};
 enum ZStage { Z_IA, Z_EIG, Z_PHASE, Z_UE, Z_C, Z_T, Z_ROWS, Z_HUBN, Z_APPLY, Z_ENERGY, Z_HMO, Z_COMM, Z_LV, Z_LT,
               Z_DD, Z_W1, Z_Y, Z_GRAD, Z_SS_SCALE, Z_SS_PADE, Z_SS_SOLVE, Z_SS_SQUARE, Z_SS_FRECHET, Z_ODD, Z_COUNT };
 const char* kZNames[Z_COUNT] = {"z_build_iA", "z_eigh",   "z_phase",  "zgemm_expA", "zgemm_C",   "zgemm_H0C",
@@ -318,10 +318,13 @@ struct etdm_handle {
   std::vector<void*> dev_allocs;
   int *b_spec = nullptr, *b_rows = nullptr, *b_pair = nullptr, *b_mat = nullptr;
   int tot_spec = 0, tot_rows = 0, tot_pair = 0, tot_mat = 0;
+  int n_pair = 0;  // entries of d_pair / b_pair: the instances whose gradient chain runs as GEMMs
   OvSpec* d_spec = nullptr;
   OvRows* d_rows = nullptr;
   OvEnergy* d_energy = nullptr;
   OvPair* d_pair = nullptr;
+  OvCong* d_cong = nullptr;  // gradient chain of the small instances, one workgroup each
+  int n_cong = 0;
   ZInst* d_z = nullptr;
   EighProb *d_eig_lds = nullptr, *d_eig_glb = nullptr;
   int n_eig_lds = 0, n_eig_glb = 0, eig_nmax = 1;
@@ -747,6 +750,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
   std::vector<OvRows> rows;
   std::vector<OvEnergy> en;
   std::vector<OvPair> pair;
+  std::vector<OvCong> cong;
   std::vector<int> bspec, brows, bpair;
   std::vector<EighProb> el, eg;
   std::vector<HermCheck> lchk;
@@ -832,16 +836,21 @@ etdm_status build_ov_plan(etdm_handle* h) {
     } else {
     // L_ov = w f_occ T^T C_virt (the weight makes this the gradient of w E)
     h->s_Lov.add(prob(N, Nv, M, b.T, N, b.Cvirt, Nv, b.Lov, Nv, h->w[i] * h->focc[i]));
-    // Gam = X^T (L_ov B^T) X
+    // Gam = X^T (L_ov B^T) X, Nm = Gam o mu1 + Gam^T o mu2, Y2 = X Nm X^T: one workgroup
+    // per instance where X fits the LDS, else grouped GEMMs around the pair kernel
     h->s_R.add(prob(N, N, Nv, b.Lov, Nv, b.B, Nv, b.R, N));
-    h->s_Gam1.add(prob(N, N, N, b.X, N, b.R, N, b.Gam1, N));
-    h->s_Gam.add(prob(N, N, N, b.Gam1, N, b.X, N, b.Gam, N));
-    pair.push_back(OvPair{b.Gam, b.mu1, b.mu2, b.Nm, N});
-    bpair.push_back(h->tot_pair);
-    h->tot_pair += N * N;
-    // Y2 = X Nm X^T ; G = -2 (sinc L_ov + Y2 B)
-    h->s_Y1.add(prob(N, N, N, b.X, N, b.Nm, N, b.Y1, N));
-    h->s_Y2.add(prob(N, N, N, b.Y1, N, b.X, N, b.Y2, N));
+    if (N <= EIGH_LDS_MAX) {
+      cong.push_back(OvCong{b.X, b.R, b.mu1, b.mu2, b.Y2, N});
+    } else {
+      h->s_Gam1.add(prob(N, N, N, b.X, N, b.R, N, b.Gam1, N));
+      h->s_Gam.add(prob(N, N, N, b.Gam1, N, b.X, N, b.Gam, N));
+      pair.push_back(OvPair{b.Gam, b.mu1, b.mu2, b.Nm, N});
+      bpair.push_back(h->tot_pair);
+      h->tot_pair += N * N;
+      h->s_Y1.add(prob(N, N, N, b.X, N, b.Nm, N, b.Y1, N));
+      h->s_Y2.add(prob(N, N, N, b.Y1, N, b.X, N, b.Y2, N));
+    }
+    // G = -2 (sinc L_ov + Y2 B)
     h->s_G.add(with_second(prob(N, Nv, N, Fs, N, b.Lov, Nv, b.G, Nv, -2.0), N, b.Y2, N, b.B, Nv, -2.0));
     }
     // exp(A) blocks: U_ov = sinc B, W B (into Lov), U_vo = -B^T sinc, U_vv = I + B^T (W B)
@@ -896,8 +905,13 @@ etdm_status build_ov_plan(etdm_handle* h) {
       }
       h->timers[O_ROWS].bytes += 8.0 * (3.0 * M * N + 2.0 * M);
       h->timers[O_SPEC].bytes += 8.0 * (4.0 * N * N + 4.0 * N * OV_NQ);
-      h->timers[O_PAIR].flops += 3.0 * N * N;
-      h->timers[O_PAIR].bytes += 8.0 * 5.0 * N * N;
+      if (!h->grad_approx && N <= EIGH_LDS_MAX) {  // four N^3 products, X R mu1 mu2 in, Y2 out
+        h->timers[O_CONG].flops += 8.0 * N * N * N + 3.0 * N * N;
+        h->timers[O_CONG].bytes += 8.0 * 5.0 * N * N;
+      } else {
+        h->timers[O_PAIR].flops += 3.0 * N * N;
+        h->timers[O_PAIR].bytes += 8.0 * 5.0 * N * N;
+      }
       h->timers[O_ENERGY].bytes += 16.0 * M;
     }
     h->timers[O_SCAN].bytes = 8.0 * h->n_param;
@@ -968,6 +982,9 @@ etdm_status build_ov_plan(etdm_handle* h) {
   }
   CHECK(upload(h, &h->d_energy, en));
   CHECK(upload(h, &h->d_pair, pair));
+  h->n_pair = (int)pair.size();
+  CHECK(upload(h, &h->d_cong, cong));
+  h->n_cong = (int)cong.size();
   CHECK(upload(h, &h->b_pair, bpair));
   CHECK(upload(h, &h->d_eig_lds, el));
   CHECK(upload(h, &h->d_eig_glb, eg));
@@ -1456,6 +1473,10 @@ void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
     TIMED(O_R);
     h->s_R.launch(s);
   }
+  if (h->n_cong > 0) {
+    TIMED(O_CONG);
+    launch_ov_congruence(h->d_cong, h->n_cong, s);
+  }
   if (!h->s_Gam1.probs.empty()) {
     TIMED(O_GAM1);
     h->s_Gam1.launch(s);
@@ -1466,7 +1487,7 @@ void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
   }
   if (h->tot_pair > 0) {
     TIMED(O_PAIR);
-    launch_ov_pair(h->d_pair, h->b_pair, h->n_inst, h->tot_pair, s);
+    launch_ov_pair(h->d_pair, h->b_pair, h->n_pair, h->tot_pair, s);
   }
   if (!h->s_Y1.probs.empty()) {
     TIMED(O_Y1);

@@ -57,6 +57,19 @@ struct OvPair {
   int32_t N;
 };
 
+// The gradient chain of one instance with N <= EIGH_LDS_MAX in one workgroup (Eq.
+// gradients): Gam = X^T R X, Nm = Gam o mu1 + Gam^T o mu2, Y2 = X Nm X^T.  X and one
+// working matrix sit in LDS; the four N x N x N products run on the FP64 matrix cores.
+struct OvCong {
+  const double* X;    // [N x N] eigenvectors of P
+  const double* R;    // [N x N] L_ov B^T
+  const double* mu1;  // [N x N] pair integrals
+  const double* mu2;
+  double* Y2;         // [N x N] out
+  int32_t N;
+};
+void launch_ov_congruence(const OvCong* d, int n_inst, hipStream_t s);
+
 void launch_ov_spectral(const OvSpec* d, const int* d_begin, int n_inst, int total, const double* gl_t,
                         const double* gl_w, hipStream_t s);
 void launch_ov_rows(const OvRows* d, const int* d_begin, int n_inst, int total_rows, double U, hipStream_t s);

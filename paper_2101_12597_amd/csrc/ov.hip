@@ -174,6 +174,109 @@ __global__ void ov_pair_kernel(const OvPair* __restrict__ pr, const int* __restr
   q.Nm[e] = q.Gam[e] * q.mu1[e] + q.Gam[(size_t)l * N + k] * q.mu2[e];
 }
 
+// Gradient chain of a small instance (N <= EIGH_LDS_MAX), one workgroup of CG_NT
+// threads: X and the working matrix W in LDS with leading dimension N + 1 (an odd
+// stride spreads the row-strided operand reads over the banks); each product is a grid
+// of 16 x 16 tiles, wavefront w owning tiles w, w + 16, w + 32, on mfma_f64_16x16x4.
+constexpr int CG_NT = 1024;
+constexpr int CG_MAXT = 3;                                     // ceil(88 / 16)^2 = 36 tiles <= 16 x 3
+constexpr int CG_PER = (EIGH_LDS_MAX * EIGH_LDS_MAX + CG_NT - 1) / CG_NT;  // elements per thread
+typedef double cg_d4 __attribute__((ext_vector_type(4)));
+
+// acc = op(A) op(B), n x n LDS matrices with leading dimension ld
+template <bool AT, bool BT>
+__device__ void cg_mm(const double* A, const double* B, int n, int ld, cg_d4 (&acc)[CG_MAXT]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nt = (n + 15) >> 4, lr = lane & 15, lk = lane >> 4;
+  for (int s = 0; s < CG_MAXT; ++s) {
+    acc[s] = cg_d4{0.0, 0.0, 0.0, 0.0};
+    const int t = wave + 16 * s;
+    if (t >= nt * nt) continue;  // uniform in the wavefront
+    const int row = (t / nt) * 16 + lr, col = (t % nt) * 16 + lr;
+    for (int k0 = 0; k0 < n; k0 += 4) {
+      const int k = k0 + lk;
+      double a = 0.0, b = 0.0;
+      if (k < n) {
+        if (row < n) a = AT ? A[k * ld + row] : A[row * ld + k];
+        if (col < n) b = BT ? B[col * ld + k] : B[k * ld + col];
+      }
+      acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
+    }
+  }
+}
+
+// (i, j) of accumulator element r of tile slot s of this lane; false outside n x n
+__device__ __forceinline__ bool cg_elem(int n, int s, int r, int& i, int& j) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nt = (n + 15) >> 4, t = wave + 16 * s;
+  if (t >= nt * nt) return false;
+  i = (t / nt) * 16 + (lane >> 4) + 4 * r;
+  j = (t % nt) * 16 + (lane & 15);
+  return i < n && j < n;
+}
+
+__device__ __forceinline__ void cg_store(double* C, int n, int ld, const cg_d4 (&acc)[CG_MAXT]) {
+  for (int s = 0; s < CG_MAXT; ++s)
+    for (int r = 0; r < 4; ++r) {
+      int i, j;
+      if (cg_elem(n, s, r, i, j)) C[i * ld + j] = acc[s][r];
+    }
+}
+
+__global__ __launch_bounds__(CG_NT) void ov_congruence_kernel(const OvCong* __restrict__ cg) {
+  extern __shared__ double sm[];
+  const OvCong& q = cg[blockIdx.x];
+  const int n = q.N, ld = n + 1, tid = threadIdx.x;
+  if (n <= 0) return;
+  double* sX = sm;
+  double* sW = sm + n * ld;
+  for (int e = tid; e < n * n; e += CG_NT) {
+    const int i = e / n, j = e - i * n;
+    sX[i * ld + j] = q.X[e];
+    sW[i * ld + j] = q.R[e];
+  }
+  __syncthreads();
+  cg_d4 acc[CG_MAXT];
+  cg_mm<true, false>(sX, sW, n, ld, acc);  // Gam1 = X^T R
+  __syncthreads();
+  cg_store(sW, n, ld, acc);
+  __syncthreads();
+  cg_mm<false, false>(sW, sX, n, ld, acc);  // Gam = Gam1 X
+  __syncthreads();
+  cg_store(sW, n, ld, acc);
+  __syncthreads();
+  double nm[CG_PER];  // Nm = Gam o mu1 + Gam^T o mu2, this thread's elements
+#pragma unroll
+  for (int u = 0; u < CG_PER; ++u) {
+    const int e = tid + u * CG_NT;
+    nm[u] = 0.0;
+    if (e < n * n) {
+      const int k = e / n, l = e - k * n;
+      nm[u] = sW[k * ld + l] * q.mu1[e] + sW[l * ld + k] * q.mu2[e];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < CG_PER; ++u) {
+    const int e = tid + u * CG_NT;
+    if (e < n * n) {
+      const int k = e / n, l = e - k * n;
+      sW[k * ld + l] = nm[u];
+    }
+  }
+  __syncthreads();
+  cg_mm<false, false>(sX, sW, n, ld, acc);  // Y1 = X Nm
+  __syncthreads();
+  cg_store(sW, n, ld, acc);
+  __syncthreads();
+  cg_mm<false, true>(sW, sX, n, ld, acc);  // Y2 = Y1 X^T
+  for (int s = 0; s < CG_MAXT; ++s)
+    for (int r = 0; r < 4; ++r) {
+      int i, j;
+      if (cg_elem(n, s, r, i, j)) q.Y2[(size_t)i * n + j] = acc[s][r];
+    }
+}
+
 // Non-finite scan of a gradient range (sets ST_NONFINITE).
 __global__ void nonfinite_scan_kernel(const double* __restrict__ g, int64_t n, int* status) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -294,6 +397,17 @@ void launch_total_energy(double* E, int n_inst, double extra_hub, const double* 
 }
 void launch_ov_pair(const OvPair* d, const int* d_begin, int n_inst, int total, hipStream_t s) {
   if (total > 0) ov_pair_kernel<<<nblk(total, 256), 256, 0, s>>>(d, d_begin, n_inst, total);
+}
+void launch_ov_congruence(const OvCong* d, int n_inst, hipStream_t s) {
+  if (n_inst <= 0) return;
+  const size_t bytes = 2 * sizeof(double) * EIGH_LDS_MAX * (EIGH_LDS_MAX + 1);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ov_congruence_kernel),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    attr = true;
+  }
+  ov_congruence_kernel<<<n_inst, CG_NT, bytes, s>>>(d);
 }
 void launch_nonfinite_scan(const double* g, int64_t n, int* status, hipStream_t s) {
   if (n > 0) nonfinite_scan_kernel<<<(int)std::min<int64_t>(1024, (n + 255) / 256), 256, 0, s>>>(g, n, status);
