@@ -34,6 +34,20 @@ def ragged_workload(scale=0.3):
     return wl
 
 
+def lds_edge_workload(scale=0.3):
+    """Instances at the size limit of the one-workgroup paths (N = 87, 88) and just past
+    it (N = 89), where the eigendecomposition of P and the gradient chain after R move
+    from one workgroup per instance in LDS to the chip-wide kernels."""
+    shapes = [(176, 88), (178, 89), (150, 87), (120, 80)]
+    wl = Workload(901, "lds edge", "real_ov", 0.5, False)
+    for i, (M, N) in enumerate(shapes):
+        H0 = chain_hamiltonian(M, rng_for(901, i, 0))
+        C0 = haar_orthogonal(M, rng_for(901, i, 1))
+        B = ov_parameters(N, M - N, rng_for(901, i, 2), scale)
+        wl.instances.append(Instance(M=M, N=N, f=binary_occupations(M, N), C0=C0, A=B, H0=H0))
+    return wl
+
+
 def per_instance_errors(wl, E_gpu, g_gpu, E_ref, g_ref_list):
     out = []
     for k, inst in enumerate(wl.instances):
@@ -73,6 +87,19 @@ def test_real_ov_fp64_matches_oracle(which):
         if gr.size:
             assert np.abs(gk - gr).max() <= 1e-10 * max(np.abs(gr).max(), 1.0), k
     h.close()
+
+
+@pytest.mark.parametrize("precision,tol_e,tol_g", [("fp64", 1e-12, 1e-10), ("mixed", 1e-8, 1e-6)])
+def test_lds_size_edge(precision, tol_e, tol_g):
+    wl = lds_edge_workload()
+    params = O.parity_params(wl)
+    print(f"[case] N = 87, 88, 89 {precision}", flush=True)
+    h, _ = make_handle(wl, precision)
+    E, g = energy_grad(h, wl, params)
+    h.close()
+    E_ref, g_ref = oracle_per_instance(wl, params)
+    for k, (dE, dg) in enumerate(per_instance_errors(wl, E, g, E_ref, g_ref)):
+        assert dE <= tol_e and dg <= tol_g, (k, wl.instances[k].N, dE, dg)
 
 
 # The five kernels of the FP64 and BF16x6 GEMM stages, forced (2 = packed
