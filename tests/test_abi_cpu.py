@@ -78,3 +78,29 @@ def test_create_rejects_bad_mode_fields(repo_root, field, bad):
     dummy = ctypes.c_void_p(8)  # never dereferenced: validation fails first
     assert lib.etdm_create(ctypes.byref(h), ctypes.byref(d), dummy, dummy, f, None) == -1
     assert h.value is None
+
+
+def test_create_rejects_scaling_and_squaring_beyond_its_size(repo_root):
+    """Scaling and squaring serves complex instances up to M = 1024 (the column tiles of
+    its norm and the panels of its solve are sized for that); a larger one is a shape
+    error, found before any device call."""
+    from paper_2101_12597_amd import LIB_PATH, load_library
+    from paper_2101_12597_amd.etdm import _Desc
+    if not os.path.exists(LIB_PATH):
+        pytest.skip("libetdm.so not built")
+    lib = load_library()
+    m = 1025
+    M = (ctypes.c_int32 * 1)(m)
+    N = (ctypes.c_int32 * 1)(m)
+    f = (ctypes.c_double * m)(*([2.0] * 8 + [0.0] * (m - 8)))
+    d = _Desc()
+    d.n_inst = 1
+    d.M = M
+    d.N = N
+    d.kind = 1  # ETDM_COMPLEX_FULL
+    d.precision = 0  # ETDM_FP64
+    d.expm_method = 1
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(8)  # never dereferenced: validation fails first
+    assert lib.etdm_create(ctypes.byref(h), ctypes.byref(d), dummy, dummy, f, None) == -2  # ETDM_E_SHAPE
+    assert h.value is None

@@ -156,3 +156,29 @@ def test_ss_ragged_batch(scale):
     E_ref, G_ref = O.energy_grad_ss(wl, params)
     assert abs(E[-1] - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
     assert rel_err(G, G_ref) < 1e-10 * max(1.0, scale)
+
+
+def test_ss_largest_size():
+    """M = 1024, the largest size of the path: 16 column tiles of the norm, 32 panels of the
+    solve with 63 column groups each, and 16 x 16 tiles in every product; exp(A) and both
+    gradients against the oracle (same tolerances: the oracle's degree-13 exponential and
+    the eigenbasis agree to 3e-15 at this size)."""
+    wl = tiny_complex(1024, nk_side=1, kT=0.1)
+    params = O.parity_params(wl)
+    s_max = max(O.pade_degree_and_scaling(float(np.abs(O.generator(wl.kind, p)).sum(axis=0).max()))[1]
+                for p in params)
+    print(f"[case] ss M = 1024 (oracle halvings up to {s_max})", flush=True)
+    h, _ = make_handle(wl, "fp64", gradient="approx", expm="ss")
+    E, G = energy_grad(h, wl, params)
+    U = expm(h, wl, params)
+    h.close()
+    E_ref, G_ref = O.energy_grad_approx(wl, params, expm=O.expm_ss)
+    assert abs(E[-1] - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
+    assert rel_err(G, G_ref) < 1e-10
+    assert np.abs(U[0] - O.expm_ss(O.generator(wl.kind, params[0]))).max() < 1e-13 * 2.0 ** (s_max + 2)
+    h, _ = make_handle(wl, "fp64", expm="ss")
+    E, G = energy_grad(h, wl, params)
+    h.close()
+    E_ref, G_ref = O.energy_grad_ss(wl, params)
+    assert abs(E[-1] - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
+    assert rel_err(G, G_ref) < 1e-10
