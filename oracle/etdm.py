@@ -367,12 +367,21 @@ def orbital_potential_elements(C: np.ndarray, lam: float) -> np.ndarray:
     return C.conj().T @ (v * C)
 
 
+def _lowdin_orbitals(inst, C):
+    """The orbitals' coefficients on the orthonormalized sites: S^(1/2) C with an overlap
+    (reading: the orbital densities of the model term are Lowdin site densities, as the
+    site density of the Hubbard term is), C itself without one."""
+    Sh = overlap_sqrt(inst)
+    return C if Sh is None else Sh @ C
+
+
 def energy_odd(wl, params, lam: float, expm=None) -> float:
     """E(A) of energy() plus the orbital-dependent model term."""
     Cs, _ = _densities(wl, params, expm)
     E = energy(wl, params, expm)
     for inst, C in zip(wl.instances, Cs):
-        E += -0.5 * lam * inst.weight * float((inst.f[None, :] * np.abs(C) ** 4).sum())
+        Cl = _lowdin_orbitals(inst, C)
+        E += -0.5 * lam * inst.weight * float((inst.f[None, :] * np.abs(Cl) ** 4).sum())
     return E
 
 
@@ -393,7 +402,9 @@ def energy_grad_odd(wl, params, lam: float, printed_indices: bool = False) -> Tu
         H = _hamiltonian(inst, n, wl.hubbard_U)
         H_MO = C.conj().T @ H @ C
         F = np.diag(inst.f)
-        V = orbital_potential_elements(C, lam)
+        # with an overlap C = C0 exp(A) on orthonormalized sites is S^(1/2) C0 exp(A), and
+        # S^(1/2) C0 is orthonormal: the term's part of L keeps its form with S^(1/2) C
+        V = orbital_potential_elements(_lowdin_orbitals(inst, C), lam)
         f = inst.f
         if printed_indices:
             odd = f[None, :] * V.T.conj() - f[:, None] * V

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import etdm as O
-from workloads import make_config, tiny_complex
+from workloads import make_config, tiny_complex, with_overlap
 from workloads.pack import unpack_params
 
 from gpu_helpers import energy_grad, make_handle, rel_err
@@ -20,13 +20,15 @@ LAM = 0.7
 def _workload(which):
     if which == "tiny":
         return tiny_complex(12, nk_side=2, kT=0.3), 3.0
+    if which == "tiny_overlap":  # Lowdin coefficients in the term, as in the site density
+        return with_overlap(tiny_complex(12, nk_side=2, kT=0.3)), 2.0
     wl = make_config(4, nk=8)
     wl.instances = wl.instances[:8]
     return wl, 1.0
 
 
 @pytest.mark.parametrize("which,expm", [("tiny", "eig"), ("tiny", "ss"), ("config4_8k", "eig"),
-                                        ("config4_8k", "ss")])
+                                        ("config4_8k", "ss"), ("tiny_overlap", "eig"), ("tiny_overlap", "ss")])
 def test_orbital_term_matches_oracle(which, expm):
     wl, scale = _workload(which)
     params = [scale * p for p in O.parity_params(wl)]

@@ -390,6 +390,27 @@ def test_orbital_dependent_gradient_matches_finite_differences():
     assert abs(O.energy_odd(wl, rot, lam) - O.energy_odd(wl, zero, lam)) > 1e-6
 
 
+def test_orbital_dependent_gradient_with_overlap_matches_finite_differences():
+    """In a non-orthogonal basis the model term uses the Lowdin coefficients S^(1/2) C;
+    its gradient still matches finite differences, and the term differs from one built
+    on the raw coefficients."""
+    from workloads import with_overlap
+    wl = with_overlap(tiny_complex(7, nk_side=2, kT=0.3))
+    p = [2.0 * a for a in O.parity_params(wl)]
+    lam = 0.7
+    E, G = O.energy_grad_odd(wl, p, lam)
+    g = O.flatten(wl.kind, G)
+    rng = np.random.default_rng(43)
+    for _ in range(4):
+        d = rng.standard_normal(g.size)
+        fd = _fd_odd(wl, p, lam, d)
+        assert abs(fd - g @ d) < 1e-8 * (np.abs(g).sum() + 1.0), (fd, g @ d)
+    Cs, _ = O._densities(wl, p)
+    raw = sum(-0.5 * lam * inst.weight * float((inst.f[None, :] * np.abs(C) ** 4).sum())
+              for inst, C in zip(wl.instances, Cs))
+    assert abs((E - O.energy(wl, p)) - raw) > 1e-6
+
+
 @pytest.mark.parametrize("kind", ["real_ov", "complex"])
 def test_non_orthogonal_basis_gradient_matches_finite_differences(kind):
     """With an overlap S != I (C0^H S C0 = I) the energy uses Lowdin populations and
