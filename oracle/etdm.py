@@ -294,22 +294,28 @@ def energy_grad(wl, params) -> Tuple[float, List[np.ndarray]]:
     return E, grads
 
 
-def energy_grad_approx(wl, params, expm=None) -> Tuple[float, List[np.ndarray]]:
+def energy_grad_approx(wl, params, expm=None, lam: float = 0.0) -> Tuple[float, List[np.ndarray]]:
     """E(A) and the approximate gradient G ~ L^T of Sec. 3.4, Eq. app_grad: the first
     term of the gradient expansion, with L = w [F, H_MO] at the current orbitals
     C = C0 exp(A).  It replaces Y by L in energy_grad (exact at A = 0, where the
     divided-difference factors are all 1); same layout of the returned gradients.
     expm selects the exponential (expm_ss: the scaling-and-squaring configuration).
+    lam != 0 adds the orbital-dependent model term (complex kind) to E and its part to L,
+    as in energy_grad_odd.
     """
     Cs, ds = _densities(wl, params, expm)
     ns = _hubbard_density(wl, ds)
-    E = energy(wl, params, expm)
+    E = energy(wl, params, expm) if lam == 0.0 else energy_odd(wl, params, lam, expm)
     grads = []
     for inst, C, n in zip(wl.instances, Cs, ns):
         H = _hamiltonian(inst, n, wl.hubbard_U)
         H_MO = C.conj().T @ H @ C
         F = np.diag(inst.f)
         L = inst.weight * (F @ H_MO - H_MO @ F)
+        if lam != 0.0:
+            assert wl.kind == "complex_full"
+            V = orbital_potential_elements(_lowdin_orbitals(inst, C), lam)
+            L = L + inst.weight * (inst.f[:, None] * V.T.conj() - inst.f[None, :] * V)
         M = L.shape[0]
         delta = np.eye(M)
         dEda = 0.5 * (2.0 - delta) * L.T  # G = 2 / (2 - delta) dE/da ~ L^T

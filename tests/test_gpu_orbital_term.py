@@ -62,3 +62,19 @@ def test_orbital_term_lbfgs_steps():
             assert info["E"] <= prev + 1e-6 * abs(prev)
         prev = info["E"]
     h.close()
+
+
+@pytest.mark.parametrize("which,expm", [("tiny", "eig"), ("tiny", "ss"), ("tiny_overlap", "eig"),
+                                        ("tiny_overlap", "ss")])
+def test_orbital_term_approx_gradient(which, expm):
+    """G ~ L^T with the term's part in L, against the oracle's energy_grad_approx(lam=...)
+    (equal to the exact gradient at A = 0, where the oracle pins it)."""
+    wl, scale = _workload(which)
+    params = [scale * p for p in O.parity_params(wl)]
+    print(f"[case] orbital-dependent term, approximate gradient {which} {expm}", flush=True)
+    h, _ = make_handle(wl, "fp64", gradient="approx", expm=expm, odd_lambda=LAM)
+    E, G = energy_grad(h, wl, params)
+    h.close()
+    E_ref, G_ref = O.energy_grad_approx(wl, params, expm=O.expm_ss if expm == "ss" else None, lam=LAM)
+    assert abs(E[-1] - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
+    assert rel_err(G, G_ref) < 1e-10

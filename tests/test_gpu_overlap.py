@@ -51,3 +51,18 @@ def test_overlap_not_positive_definite_is_rejected():
     with pytest.raises(EtdmError) as e:
         make_handle(wl, "fp64")
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("which,expm", [("real", "eig"), ("config1", "eig"), ("complex", "eig"), ("complex", "ss")])
+def test_overlap_approx_gradient_matches_oracle(which, expm):
+    """The approximate gradient G ~ L^T in a non-orthogonal basis, against the oracle's
+    energy_grad_approx (Lowdin site densities)."""
+    wl = _workload(which)
+    params = O.parity_params(wl)
+    print(f"[case] non-orthogonal basis, approximate gradient {which} {expm}", flush=True)
+    h, _ = make_handle(wl, "fp64", gradient="approx", expm=expm)
+    E, G = energy_grad(h, wl, params)
+    h.close()
+    E_ref, G_ref = O.energy_grad_approx(wl, params, expm=O.expm_ss if expm == "ss" else None)
+    assert abs(E[-1] - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
+    assert rel_err(G, G_ref) < 1e-10

@@ -390,6 +390,28 @@ def test_orbital_dependent_gradient_matches_finite_differences():
     assert abs(O.energy_odd(wl, rot, lam) - O.energy_odd(wl, zero, lam)) > 1e-6
 
 
+@pytest.mark.parametrize("overlap", [False, True])
+def test_approx_gradient_with_orbital_term_is_exact_at_zero(overlap):
+    """G ~ L^T with the orbital-dependent term: at A = 0 every divided-difference factor
+    is 1, so it equals the exact gradient of energy_grad_odd (pinned by finite
+    differences), with and without an overlap; away from A = 0 the two differ."""
+    from workloads import with_overlap
+    wl = tiny_complex(7, nk_side=2, kT=0.3)
+    if overlap:
+        wl = with_overlap(wl)
+    lam = 0.7
+    zero = O.zero_params(wl)
+    Ea, Ga = O.energy_grad_approx(wl, zero, lam=lam)
+    Ee, Ge = O.energy_grad_odd(wl, zero, lam)
+    assert abs(Ea - Ee) < 1e-13 * max(1.0, abs(Ee))
+    assert max(np.abs(a - b).max() for a, b in zip(Ga, Ge)) < 1e-13
+    assert max(np.abs(g).max() for g in Ge) > 1e-3
+    p = [3.0 * a for a in O.parity_params(wl)]
+    _, Ga = O.energy_grad_approx(wl, p, lam=lam)
+    _, Ge = O.energy_grad_odd(wl, p, lam)
+    assert max(np.abs(a - b).max() for a, b in zip(Ga, Ge)) > 1e-3
+
+
 def test_orbital_dependent_gradient_with_overlap_matches_finite_differences():
     """In a non-orthogonal basis the model term uses the Lowdin coefficients S^(1/2) C;
     its gradient still matches finite differences, and the term differs from one built
