@@ -66,3 +66,31 @@ def test_overlap_approx_gradient_matches_oracle(which, expm):
     E_ref, G_ref = O.energy_grad_approx(wl, params, expm=O.expm_ss if expm == "ss" else None)
     assert abs(E[-1] - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
     assert rel_err(G, G_ref) < 1e-10
+
+
+@pytest.mark.parametrize("which", ["real", "complex"])
+def test_overlap_lbfgs_steps(which):
+    """L-BFGS on a handle with an overlap: energies do not increase (beyond the
+    approximate-Wolfe allowance), and E and G at every returned A are the oracle's in the
+    non-orthogonal basis (no reference reset within these steps, so the reference is the
+    caller's C0)."""
+    import torch
+    from workloads.pack import unpack_params
+    wl = _workload(which)
+    print(f"[case] non-orthogonal basis, L-BFGS {which}", flush=True)
+    h, _ = make_handle(wl, "fp64")
+    A = torch.zeros(h.n_param, dtype=torch.float64, device="cuda:0")
+    E = torch.empty(h.n_inst + 1, dtype=torch.float64, device="cuda:0")
+    G = torch.empty_like(A)
+    prev = None
+    for _ in range(6):
+        info = h.lbfgs_step(A, E, G)
+        assert not info["flags"] & 1
+        params = unpack_params(wl, A.cpu().numpy())
+        E_ref, G_ref = O.energy_grad(wl, params)
+        assert abs(info["E"] - E_ref) <= 1e-12 * max(1.0, abs(E_ref))
+        assert rel_err(unpack_params(wl, G.cpu().numpy()), G_ref) < 1e-10
+        if prev is not None:
+            assert info["E"] <= prev + 1e-6 * abs(prev)
+        prev = info["E"]
+    h.close()
