@@ -11,7 +11,7 @@ import pytest
 
 from oracle import etdm as O
 from oracle import lbfgs as LB
-from workloads import make_config, tiny_complex, tiny_real
+from workloads import make_config, tiny_complex, tiny_real, with_overlap
 from workloads.pack import unpack_params
 
 from gpu_helpers import make_handle
@@ -50,6 +50,10 @@ def _workload(which):
         return make_config(1)
     if which == "tiny_real":
         return tiny_real(24, 7, seed=5, scale=0.0)
+    if which == "tiny_real_overlap":
+        return with_overlap(tiny_real(24, 7, seed=5, scale=0.0))
+    if which == "tiny_complex_overlap":
+        return with_overlap(tiny_complex(8, nk_side=2, kT=0.3))
     return tiny_complex(8, nk_side=2, kT=0.3)
 
 
@@ -160,7 +164,8 @@ def test_graph_replay_matches_eager(which, precision):
         assert np.array_equal(a0, a1) and np.array_equal(e0, e1)
 
 
-@pytest.mark.parametrize("which,precision", [("config1", "fp64"), ("config2", "mixed"), ("tiny_complex", "fp64")])
+@pytest.mark.parametrize("which,precision", [("config1", "fp64"), ("config2", "mixed"), ("tiny_complex", "fp64"),
+                                             ("tiny_real_overlap", "fp64"), ("tiny_complex_overlap", "fp64")])
 def test_checkpoint_resume_is_bitwise(which, precision):
     """get_state after 4 iterations; the next 5 (crossing reference resets every 3
     iterations) are repeated bit for bit after set_state, on the same handle and on
