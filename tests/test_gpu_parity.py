@@ -275,17 +275,22 @@ def test_config4_all_kpoints():
 # block Jacobi fallback: config 3's instance is accepted by the tridiagonal path,
 # the ragged batch's rank-deficient N = 96 instance goes through the fallback.
 @pytest.mark.parametrize("which,precision", [("config2", "mixed"), ("config4", "fp64"), ("config3", "mixed"),
-                                             ("ragged", "fp64")])
+                                             ("ragged", "fp64"), ("config4_odd", "fp64"),
+                                             ("config2_approx", "mixed")])
 def test_graph_replay_matches_eager(which, precision):
     """The captured launch sequence reproduces the eager results bitwise on every
-    replay, with other GPU work and changing parameters between replays."""
+    replay, with other GPU work and changing parameters between replays (also with the
+    orbital-dependent term's kernels and with the approximate gradient's sequence)."""
     import torch
     wl = {"config2": lambda: make_config(2), "config4": lambda: make_config(4, nk=8),
-          "config3": lambda: make_config(3), "ragged": lambda: ragged_workload()}[which]()
+          "config3": lambda: make_config(3), "ragged": lambda: ragged_workload(),
+          "config4_odd": lambda: make_config(4, nk=8), "config2_approx": lambda: make_config(2)}[which]()
     params = O.parity_params(wl)
     params2 = [0.5 * p for p in params]
     print(f"[case] graph replay {which} {precision}", flush=True)
-    h, _ = make_handle(wl, precision, use_bsr=which == "config3")
+    h, _ = make_handle(wl, precision, use_bsr=which == "config3",
+                       odd_lambda=0.7 if which == "config4_odd" else 0.0,
+                       gradient="approx" if which == "config2_approx" else "exact")
     ref1 = energy_grad(h, wl, params)
     ref2 = energy_grad(h, wl, params2)
     h.set_graph(True)
