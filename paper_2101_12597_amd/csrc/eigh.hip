@@ -720,6 +720,7 @@ __global__ __launch_bounds__(NT) void jacobi_complex(const EighProb* __restrict_
 // (Q_b = I - Y_b T_b Y_b^H; herm_wy_t_kernel forms T_b) on the matrix cores.
 // ---------------------------------------------------------------------------
 constexpr int HT_NCH = 5;  // row chunks of the matrix-vector product
+constexpr int HT_YC = 32;  // rows per LDS chunk of the WY Gram matrix
 
 static size_t ht_lds_bytes(int n) {
   return sizeof(double) * (6 * (size_t)n + 4 * (size_t)n + 2 * HT_NCH * (size_t)n + TL_XS) +
@@ -903,13 +904,34 @@ __global__ __launch_bounds__(256) void herm_wy_t_kernel(const HermWY* __restrict
   __shared__ double2 g[HT_NB][HT_NB + 1];
   __shared__ double2 T[HT_NB][HT_NB + 1];
   __shared__ double2 col[HT_NB];
-  for (int q = threadIdx.x; q < HT_NB * HT_NB; q += 256) {
-    const int r = q / HT_NB, c = q - r * HT_NB;
-    double2 acc = make_double2(0.0, 0.0);
-    if (r < c && c < m)  // rows above k0 + r + 1 of column k0 + r are zero
-      for (int i = k0 + 1 + r; i < n; ++i)
-        acc = cadd(acc, cconjmul(Y[(size_t)i * n + k0 + r], Y[(size_t)i * n + k0 + c]));
-    g[r][c] = acc;
+  __shared__ double2 ys[HT_YC][HT_NB + 1];  // a chunk of rows of the block's columns
+  // Gram g = Y_b^H Y_b (strictly upper part): the block's columns are staged through LDS
+  // HT_YC rows at a time (coalesced loads, all in flight), each thread summing its
+  // (HT_NB x HT_NB) / 256 entries; rows above k0 + r + 1 of column k0 + r are zero
+  constexpr int PER = HT_NB * HT_NB / 256;
+  static_assert(HT_NB * HT_NB % 256 == 0, "whole entries per thread");
+  double2 acc[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) acc[u] = make_double2(0.0, 0.0);
+  for (int i0 = k0 + 1; i0 < n; i0 += HT_YC) {
+    for (int q = threadIdx.x; q < HT_YC * HT_NB; q += 256) {
+      const int rr = q / HT_NB, cc = q - rr * HT_NB, i = i0 + rr;
+      ys[rr][cc] = i < n && cc < m ? Y[(size_t)i * n + k0 + cc] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int q = threadIdx.x + 256 * u, r = q / HT_NB, c = q - r * HT_NB;
+      if (r < c && c < m)
+        for (int rr = 0; rr < HT_YC; ++rr)
+          if (i0 + rr >= k0 + 1 + r) acc[u] = cadd(acc[u], cconjmul(ys[rr][r], ys[rr][c]));
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = threadIdx.x + 256 * u, r = q / HT_NB, c = q - r * HT_NB;
+    g[r][c] = acc[u];
     T[r][c] = make_double2(0.0, 0.0);
   }
   __syncthreads();
