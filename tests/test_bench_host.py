@@ -38,3 +38,15 @@ def test_traffic_figure_follows_the_source_hash(tmp_path, monkeypatch):
     # a missing source likewise
     os.remove(os.path.join(root, "src", "b.h"))
     assert bench.measured_traffic("eigh_lds", 2, "mixed") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    """The path runs on one GPU: --gpus N with N > 1 exits with status 2 and says so,
+    before any device or oracle work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.abspath(bench.__file__))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr and r.stdout == ""
