@@ -721,6 +721,7 @@ __global__ __launch_bounds__(NT) void jacobi_complex(const EighProb* __restrict_
 // ---------------------------------------------------------------------------
 constexpr int HT_NCH = 5;  // row chunks of the matrix-vector product
 constexpr int HT_YC = 32;  // rows per LDS chunk of the WY Gram matrix
+constexpr int HC_GROUPS = 8;  // workgroups per instance of the orthogonality check
 
 static size_t ht_lds_bytes(int n) {
   return sizeof(double) * (6 * (size_t)n + 4 * (size_t)n + 2 * HT_NCH * (size_t)n + TL_XS) +
@@ -951,11 +952,14 @@ __global__ __launch_bounds__(256) void herm_wy_t_kernel(const HermWY* __restrict
   for (int q = threadIdx.x; q < HT_NB * HT_NB; q += 256) Tb[q] = T[q / HT_NB][q % HT_NB];
 }
 
+// HC_GROUPS workgroups per instance, each over one slice of G; a slice that fails
+// clears the flag (every writer writes 0)
 __global__ __launch_bounds__(256) void herm_check_kernel(const HermCheck* __restrict__ chk) {
-  const HermCheck c = chk[blockIdx.x];
-  const int n = c.n;
+  const HermCheck c = chk[blockIdx.x / HC_GROUPS];
+  const int n = c.n, grp = blockIdx.x % HC_GROUPS;
+  const int chunk = (n * n + HC_GROUPS - 1) / HC_GROUPS, e0 = grp * chunk, e1 = min(n * n, e0 + chunk);
   double m = 0.0;
-  for (int e = threadIdx.x; e < n * n; e += 256) {
+  for (int e = e0 + threadIdx.x; e < e1; e += 256) {
     const int i = e / n;
     const double g = c.G[e], dlt = (e == i * n + i) ? 1.0 : 0.0;
     m = fmax(m, tl_err(fabs(g - dlt)));
@@ -1017,7 +1021,7 @@ void launch_eigh_herm_tridiag(const EighProb* d_probs, int nprob, int nmax, int*
 }
 
 void launch_herm_check(const HermCheck* d, int nprob, hipStream_t s) {
-  if (nprob > 0) herm_check_kernel<<<nprob, 256, 0, s>>>(d);
+  if (nprob > 0) herm_check_kernel<<<nprob * HC_GROUPS, 256, 0, s>>>(d);
 }
 
 void launch_herm_wy_t(const HermWY* d, int nprob, int nblk, hipStream_t s) {
