@@ -465,12 +465,19 @@ def y_matrix(wl, params, idx: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
 # structured occupied-virtual path (real B, binary occupations)
 # ----------------------------------------------------------------------------
 
-_GL_NODES = 96
+_GL_NODES = 48
 
 
-def _gauss_legendre_01(n: int = _GL_NODES):
-    x, wq = np.polynomial.legendre.leggauss(n)
-    return 0.5 * (x + 1.0), 0.5 * wq
+def _gauss_legendre_01(sig_max: float = 0.0):
+    """Composite Gauss-Legendre rule on [0, 1] for the pair integrals.  Their integrands
+    are products of two oscillations, so their frequency is at most 2 sig_max: the
+    interval is cut into pieces over which that phase advances by at most 40 rad, with
+    48 nodes per piece (a 48-node rule is exact to rounding for phases well beyond 40)."""
+    pieces = max(1, int(np.ceil(2.0 * max(float(sig_max), 0.0) / 40.0)))
+    x, wq = np.polynomial.legendre.leggauss(_GL_NODES)
+    h = 1.0 / pieces
+    t = ((np.arange(pieces)[:, None] + 0.5 * (x[None, :] + 1.0)) * h).ravel()
+    return t, np.tile(0.5 * h * wq, pieces)
 
 
 def ov_pair_integrals(sig: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
@@ -479,12 +486,10 @@ def ov_pair_integrals(sig: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
       mu1[k, l] = -integral_0^1 (t^2/2) cos(t s_k) sinc(t s_l / 2)^2 dt
       mu2[k, l] =  integral_0^1 t^2 sinc(t s_k) sinc(t s_l) dt
 
-    with s = singular values of B.  Both integrands are entire; 96 nodes are exact
-    to rounding for s <= 40 (checked at call time).
+    with s = singular values of B.  Both integrands are entire; the composite rule grows
+    with the largest angle, so any rotation angle is covered.
     """
-    if sig.size and sig.max() > 40.0:
-        raise ValueError("rotation angles above 40 rad: quadrature table too short")
-    t, wq = _gauss_legendre_01()
+    t, wq = _gauss_legendre_01(sig.max() if sig.size else 0.0)
     ts = t[None, :] * sig[:, None]  # [N, nodes]
     cos_t = np.cos(ts)
     sinc_t = _sinc(ts)

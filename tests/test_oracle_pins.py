@@ -557,6 +557,60 @@ def test_pair_integrals_limits_and_closed_forms():
     assert np.abs(mu2[2:, 2:] - Ks / (sk * sl)).max() < 1e-14
 
 
+def _mp_pair_integrals(a, b):
+    """mu1 and mu2 of one pair of angles by mpmath's tanh-sinh quadrature at 30 digits,
+    on pieces of at most 6 rad of the faster oscillation."""
+    import mpmath as mp
+    with mp.workdps(30):
+        a, b = mp.mpf(a), mp.mpf(b)
+        sinc = lambda x: mp.sin(x) / x if x != 0 else mp.mpf(1)
+        n = int(max(a, b) / 6) + 2
+        pts = [mp.mpf(i) / n for i in range(n + 1)]
+        m1 = -mp.quad(lambda t: t * t / 2 * mp.cos(t * a) * sinc(t * b / 2) ** 2, pts)
+        m2 = mp.quad(lambda t: t * t * sinc(t * a) * sinc(t * b), pts)
+    return float(m1), float(m2)
+
+
+def test_pair_integrals_match_high_precision_quadrature_at_any_angle():
+    """Rotation angles far beyond one turn (L-BFGS trial steps reach hundreds of rad):
+    the oracle's composite rule against 30-digit quadrature, pairs of small, moderate and
+    large angles in both orders."""
+    sig = np.array([0.0, 0.3, 7.0, 45.0, 180.0, 450.0])
+    mu1, mu2 = O.ov_pair_integrals(sig)
+    pairs = [(0, 0), (1, 2), (2, 1), (3, 1), (1, 3), (4, 0), (0, 4), (3, 4), (4, 3), (5, 5),
+             (5, 2), (2, 5), (5, 1)]
+    for k, l in pairs:
+        m1, m2 = _mp_pair_integrals(sig[k], sig[l])
+        assert abs(mu1[k, l] - m1) < 1e-15, (sig[k], sig[l], mu1[k, l], m1)
+        assert abs(mu2[k, l] - m2) < 1e-15, (sig[k], sig[l], mu2[k, l], m2)
+
+
+def test_pair_integrals_closed_forms_at_large_angles():
+    sig = np.array([1.0, 3.5, 41.0, 99.0, 230.0, 600.0])
+    mu1, mu2 = O.ov_pair_integrals(sig)
+    sk, sl = sig[:, None], sig[None, :]
+    sincf = lambda x: np.sinc(x / np.pi)
+    Kc = 0.5 * (sincf(sk - sl) + sincf(sk + sl))
+    Ks = 0.5 * (sincf(sk - sl) - sincf(sk + sl))
+    assert np.abs(mu1 - (Kc - sincf(sk)) / sl ** 2).max() < 1e-15
+    assert np.abs(mu2 - Ks / (sk * sl)).max() < 1e-15
+
+
+@pytest.mark.parametrize("M,N,scale", [(30, 6, 30.0), (12, 4, 100.0)])
+def test_structured_ov_equals_dense_at_large_angles(M, N, scale):
+    """sigma_max of about 200 and 380 rad: the structured path still equals the definition
+    path.  Both lose accuracy as the angles grow (the eigendecompositions' errors scale with
+    |A| and |A|^2), hence the looser bound than at small angles."""
+    wl = tiny_real(M, N, seed=M + N, scale=scale)
+    p = O.parity_params(wl)
+    sig = np.sqrt(np.linalg.eigvalsh(p[0] @ p[0].T).clip(0.0))
+    assert sig.max() > 150.0
+    E, (g,) = O.energy_grad(wl, p)
+    E2, (g2,) = O.energy_grad_ov_workload(wl, p)
+    assert abs(E - E2) < 1e-12 * abs(E)
+    assert np.abs(g - g2).max() < 1e-11 * np.abs(g).max()
+
+
 # ---------------------------------------------------------------------------
 # minima
 # ---------------------------------------------------------------------------
