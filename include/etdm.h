@@ -72,16 +72,25 @@ typedef enum {
 typedef enum { ETDM_REAL_OV = 0, ETDM_COMPLEX_FULL = 1 } etdm_kind;
 
 /* Arithmetic of the dense contractions.  The eigendecomposition, the spectral
- * and divided-difference factors and the energy reduction are FP64 in every mode. */
+ * and divided-difference factors and the energy reduction are FP64 in every mode.
+ * REAL_OV: P = B B^T, V = X^T B (X: eigenvectors of P) and the N x N spectral
+ * products are FP64 in every mode as well; every later product is taken in the
+ * eigenbasis of P, where its terms stay bounded at any rotation angle, so the split
+ * modes keep their accuracy for large A. */
 typedef enum {
   ETDM_FP64 = 0,   /* FP64 MFMA */
   ETDM_FP32 = 1,   /* operands rounded to FP32, FP32 MFMA, FP64 flush every K chunk */
   ETDM_BF16X3 = 2, /* 2-way BF16 split (hi+lo), 3 products, FP32 MFMA accumulation */
   ETDM_BF16X6 = 3, /* 3-way BF16 split (hi+mid+lo), 6 products */
-  ETDM_MIXED = 4   /* by role: the contractions that E depends on (P, C0_v B^T, C_occ,
-                      H0 C_occ) in FP64, the gradient-only ones (Z1, C_virt, L_ov,
-                      L_ov B^T, G) as ETDM_BF16X6 */
+  ETDM_MIXED = 4   /* by role: the gradient-only contractions (C_virt, L_ov, L_ov V^T,
+                      the eigenbasis products of the gradient, G) as ETDM_BF16X6; the
+                      ones E depends on (C0_o X, C0_v V^T, C_occ, H0 C_occ) in FP64, or
+                      as ETDM_BF16X6 when every instance has N >=
+                      ETDM_MIXED_SPLIT_E_MIN_N (the split's rounding of the orbitals
+                      then stays far below 1e-8 Ha per electron) */
 } etdm_precision;
+
+#define ETDM_MIXED_SPLIT_E_MIN_N 512
 
 typedef struct {
   int32_t n_inst;         /* number of instances (molecules or k-points), >= 1 */

@@ -499,7 +499,7 @@ def ov_pair_integrals(sig: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
     return mu1, mu2
 
 
-def energy_grad_ov(inst, B: np.ndarray, hubbard_U: float, want_parts: bool = False):
+def energy_grad_ov(inst, B: np.ndarray, hubbard_U: float, want_parts: bool = False, progress=None):
     """E and dE/dB for one real instance with A = [[0, B], [-B^T, 0]] and binary f.
 
     Derived from Eq. gradients with the singular-value basis of B: in the basis
@@ -511,8 +511,11 @@ def energy_grad_ov(inst, B: np.ndarray, hubbard_U: float, want_parts: bool = Fal
       Nm[k, l] = Gam[k, l] mu1[k, l] + Gam[l, k] mu2[k, l],
       dE/dB = -2 Y_ov.
 
-    H0 may be dense or block-sparse (scipy.sparse is used for the product).
+    H0 may be dense or block-sparse (scipy.sparse is used for the product).  progress,
+    if given, is called with a short message after each large step (long runs report
+    where they are).
     """
+    note = progress or (lambda msg: None)
     N, Nv = B.shape
     M = N + Nv
     assert inst.S is None, "the structured path takes an orthonormal basis"
@@ -520,18 +523,22 @@ def energy_grad_ov(inst, B: np.ndarray, hubbard_U: float, want_parts: bool = Fal
     assert np.all(inst.f[:N] == f_occ) and np.all(inst.f[N:] == 0.0)
     s, X = np.linalg.eigh(B @ B.T)
     sig = np.sqrt(np.clip(s, 0.0, None))
+    note("oracle: eigendecomposition of B B^T")
     cosP = (X * np.cos(sig)) @ X.T
     sincP = (X * _sinc(sig)) @ X.T
     WP = (X * (-0.5 * _sinc(0.5 * sig) ** 2)) @ X.T
     C0o, C0v = inst.C0[:, :N], inst.C0[:, N:]
     Q1 = C0v @ B.T
+    note("oracle: C0_v B^T")
     Cocc = C0o @ cosP - Q1 @ sincP
     Cvirt = C0v + (C0o @ sincP + Q1 @ WP) @ B
+    note("oracle: rotated orbitals")
     d = f_occ * (Cocc ** 2).sum(axis=1)
     T0 = _h0_times(inst, Cocc)
     E = f_occ * float((Cocc * T0).sum()) + 0.5 * hubbard_U * float((d ** 2).sum())
     T = T0 + hubbard_U * d[:, None] * Cocc
     Lov = f_occ * (T.T @ Cvirt)
+    note("oracle: L_ov")
     Gam = X.T @ (Lov @ B.T) @ X
     mu1, mu2 = ov_pair_integrals(sig)
     Nm = Gam * mu1 + Gam.T * mu2

@@ -253,10 +253,10 @@ struct OvBuf {
   EighLargeState* eig_st;
   BsrMat H0_bsr;   // block-sparse H0 (h0_format = 1; then H0 is null)
   int64_t bsr_nnz; // stored entries of H0_bsr
-  double *P, *X, *s, *Xcsw, *F3, *T1s, *T2, *T3s, *T3, *mu1, *mu2;
-  double *Q1, *Cocc, *Z1, *Cvirt, *T, *d, *e, *Lov, *R, *Gam1, *Gam, *Nm, *Y1, *Y2;
+  double *P, *X, *s, *fac, *XT, *XsnT, *tab, *Xcsw, *F3, *mu1, *mu2;
+  double *V, *sincP, *CX, *CV, *Cocc, *Cvirt, *T, *d, *e, *Lov, *LV, *Gam, *Nm, *XNm;
   double *HC0, *n0, *eps;
-  double* HQ1;  // dense H0: H0 Q1 = (H0 C0)_v B^T (HC0 is then kept for the current C0)
+  double *HX, *HV;  // dense H0: (H0 C0)_o X and (H0 C0)_v V^T (HC0 is kept for the current C0)
 };
 
 struct ZBuf {
@@ -283,13 +283,13 @@ struct StageTimer {
 };
 
 // stage indices of the two paths
-enum OvStage { O_PQ, O_EIGL, O_EIGG, O_SPEC, O_F3MU, O_C, O_Z, O_T, O_V, O_ROWS, O_ENERGY, O_LOV, O_R, O_GAM1,
-               O_GAM, O_PAIR, O_Y1, O_Y2, O_G, O_SCAN, O_Q1, O_CONG, O_COUNT };
-const char* kOvNames[O_COUNT] = {"gemm_P",  "eigh_lds",  "eigh_global", "spectral_tables", "gemm_funcs_mu",
-                                 "gemm_Cocc",  "gemm_Z1",   "gemm_H0C",    "gemm_Cvirt",      "rows_density_hubbard",
-                                 "energy_reduce", "gemm_Lov", "gemm_R",    "gemm_Gam1",       "gemm_Gam",
-                                 "pair_hadamard", "gemm_Y1", "gemm_Y2",    "gemm_grad",       "nonfinite_scan",
-                                 "gemm_Q1", "ov_congruence"};
+enum OvStage { O_PQ, O_EIGL, O_EIGG, O_SPEC, O_VF, O_CXV, O_ROT, O_C, O_T, O_V, O_ROWS, O_ENERGY, O_LOV, O_LV,
+               O_CONG, O_GAM, O_PAIR, O_XNM, O_G, O_SCAN, O_COUNT };
+const char* kOvNames[O_COUNT] = {"gemm_P",      "eigh_lds",      "eigh_global", "spectral",
+                                 "gemm_V_funcs", "gemm_CXV",     "eigenbasis_combine", "gemm_Cocc",
+                                 "gemm_H0C",    "gemm_Cvirt",    "rows_density_hubbard", "energy_reduce",
+                                 "gemm_Lov",    "gemm_LV",       "ov_congruence", "gemm_Gam",
+                                 "pair_hadamard", "gemm_XNm",    "gemm_grad",   "nonfinite_scan"};
 enum ZStage { Z_IA, Z_EIG, Z_PHASE, Z_UE, Z_C, Z_T, Z_ROWS, Z_HUBN, Z_APPLY, Z_ENERGY, Z_HMO, Z_COMM, Z_LV, Z_LT,
               Z_DD, Z_W1, Z_Y, Z_GRAD, Z_SS_SCALE, Z_SS_PADE, Z_SS_SOLVE, Z_SS_SQUARE, Z_SS_FRECHET, Z_ODD, Z_COUNT };
 const char* kZNames[Z_COUNT] = {"z_build_iA", "z_eigh",   "z_phase",  "zgemm_expA", "zgemm_C",   "zgemm_H0C",
@@ -316,10 +316,11 @@ struct etdm_handle {
   double *gl_t = nullptr, *gl_w = nullptr;
   // device descriptor arrays (allocated separately)
   std::vector<void*> dev_allocs;
-  int *b_spec = nullptr, *b_rows = nullptr, *b_pair = nullptr, *b_mat = nullptr;
-  int tot_spec = 0, tot_rows = 0, tot_pair = 0, tot_mat = 0;
+  int *b_spec = nullptr, *b_rows = nullptr, *b_pair = nullptr, *b_mat = nullptr, *b_rot = nullptr;
+  int tot_spec = 0, tot_rows = 0, tot_pair = 0, tot_mat = 0, tot_rot = 0;
   int n_pair = 0;  // entries of d_pair / b_pair: the instances whose gradient chain runs as GEMMs
   OvSpec* d_spec = nullptr;
+  OvRot* d_rot = nullptr;
   OvRows* d_rows = nullptr;
   OvEnergy* d_energy = nullptr;
   OvPair* d_pair = nullptr;
@@ -352,13 +353,12 @@ struct etdm_handle {
   int tot_prec = 0;
   C0Inst* d_c0up = nullptr;
   // grouped GEMM launches
-  Stage s_PQ, s_Q1, s_F3mu, s_C, s_Z, s_V, s_Lov, s_R, s_Gam1, s_Gam, s_Y1, s_Y2, s_G;  // real: energy+gradient
-  // Q1 = C0_v B^T does not depend on the eigendecomposition: it runs on a side
-  // stream beside the eigensolver (forked and joined by events)
+  Stage s_PQ, s_VF, s_CXV, s_C, s_V, s_Lov, s_LV, s_Gam, s_XNm, s_G;  // real: energy+gradient
+  // C_virt runs on a side stream beside C_occ, the rows and the energy (forked and
+  // joined by events)
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;    // Q1 beside the eigensolver
-  hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;  // Z1, C_virt beside C_occ, rows and energy
-  Stage s_Uov, s_Uvv, s_HC0;                                                   // real: expm, preconditioner
+  hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;
+  Stage s_F3, s_Uov, s_Uvv, s_HC0;  // real: expm, preconditioner
   Stage z_Ue, z_C, z_T, z_HMO, z_LV, z_Lt, z_W1, z_Y, z_HC0;                   // complex
   // L-BFGS: scalars and decisions in lb_st (device); the host keeps the iteration
   // and evaluation counts and reads lb_sum (pinned) once per line-search probe
@@ -536,32 +536,33 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       b.P = pl.take(N * N);
       b.X = pl.take(N * N);
       b.s = pl.take(N);
+      b.fac = pl.take(3 * N);
+      b.XT = pl.take(N * N);
+      b.XsnT = pl.take(N * N);
+      b.tab = pl.take(4 * N * OV_NQ);
       b.Xcsw = pl.take(3 * N * N);
       b.F3 = pl.take(3 * N * N);
-      b.T1s = pl.take(N * OV_NQ);
-      b.T2 = pl.take(N * OV_NQ);
-      b.T3s = pl.take(N * OV_NQ);
-      b.T3 = pl.take(N * OV_NQ);
       b.mu1 = pl.take(N * N);
       b.mu2 = pl.take(N * N);
-      b.Q1 = pl.take(M * N);
+      b.V = pl.take(N * Nv);
+      b.sincP = pl.take(N * N);
+      b.CX = pl.take(M * N);
+      b.CV = pl.take(M * N);
       b.Cocc = pl.take(M * N);
-      b.Z1 = pl.take(M * N);
       b.Cvirt = pl.take(M * Nv);
       b.T = pl.take(M * N);
       b.d = pl.take(M);
       b.e = pl.take(M);
       b.Lov = pl.take(N * Nv);
-      b.R = pl.take(N * N);
-      b.Gam1 = pl.take(N * N);
+      b.LV = pl.take(N * N);
       b.Gam = pl.take(N * N);
       b.Nm = pl.take(N * N);
-      b.Y1 = pl.take(N * N);
-      b.Y2 = pl.take(N * N);
+      b.XNm = pl.take(N * N);
       // Dense H0: HC0 = H0 C0 is kept for the current reference (T = H0 C_occ is formed
       // from it); block-sparse H0: the preconditioner's H0 C0 shares the expm output
       b.HC0 = h->h0_format == 0 ? pl.take(M * M) : b.U;
-      b.HQ1 = h->h0_format == 0 ? pl.take(M * N) : nullptr;
+      b.HX = h->h0_format == 0 ? pl.take(M * N) : nullptr;
+      b.HV = h->h0_format == 0 ? pl.take(M * N) : nullptr;
       b.n0 = pl.take(M);
       b.eps = pl.take(M);
       b.eig_ws = nullptr;
@@ -726,32 +727,41 @@ etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
 }
 
 // ----- plan of the real occupied-virtual path ------------------------------
+// Every product after the eigendecomposition is taken in the eigenbasis of P (see
+// ov.hip): V = X^T B, CX = C0_o X, CV = C0_v V^T, then the combination kernel and
+// C_occ = CX' X^T, C_virt = C0_v + CV' V, and on the gradient side LV = L_ov V^T,
+// Gam = X^T LV, XNm = X Nm, dE/dB = -2 (sinc sqrt(P) L_ov + XNm V).
 etdm_status build_ov_plan(etdm_handle* h) {
-  // precision by role: ep for the contractions E depends on, gp for the gradient-only ones
-  const int ep = h->prec == ETDM_MIXED ? GP_FP64 : h->prec;
+  // precision by role: ep for the contractions E depends on, gp for the gradient-only
+  // ones.  P = B B^T, V = X^T B and the N x N spectral products stay FP64 in every
+  // mode (the eigendecomposition and every later product depend on them).  In the
+  // mixed mode the energy side runs split when every instance is large enough for the
+  // split's rounding of the orbitals to stay far below 1e-8 Ha per electron.
+  bool all_large = h->n_inst > 0;
+  for (int i = 0; i < h->n_inst; ++i) all_large = all_large && h->N[i] >= ETDM_MIXED_SPLIT_E_MIN_N;
+  const int ep = h->prec == ETDM_MIXED ? (all_large ? GP_BF16X6 : GP_FP64) : h->prec;
   const int gp = h->prec == ETDM_MIXED ? GP_BF16X6 : h->prec;
-  h->s_PQ.init(OP_N, OP_T, ep);
-  h->s_Q1.init(OP_N, OP_T, ep);
-  h->s_F3mu.init(OP_N, OP_T, GP_FP64);
-  h->s_C.init(OP_N, OP_N, ep);
-  h->s_Z.init(OP_N, OP_N, gp);
+  h->s_PQ.init(OP_N, OP_T, GP_FP64);
+  h->s_VF.init(OP_T, OP_N, GP_FP64);
+  h->s_CXV.init(OP_N, OP_T, ep);
+  h->s_C.init(OP_N, OP_T, ep);
   h->s_V.init(OP_N, OP_N, gp);
   h->s_Lov.init(OP_T, OP_N, gp);
-  h->s_R.init(OP_N, OP_T, gp);
-  h->s_Gam1.init(OP_T, OP_N, GP_FP64);
-  h->s_Gam.init(OP_N, OP_N, GP_FP64);
-  h->s_Y1.init(OP_N, OP_N, GP_FP64);
-  h->s_Y2.init(OP_N, OP_T, GP_FP64);
+  h->s_LV.init(OP_N, OP_T, gp);
+  h->s_Gam.init(OP_T, OP_N, gp);
+  h->s_XNm.init(OP_N, OP_N, gp);
   h->s_G.init(OP_N, OP_N, gp);
-  h->s_Uov.init(OP_N, OP_N, ep);
-  h->s_Uvv.init(OP_T, OP_N, ep);
-  h->s_HC0.init(OP_N, OP_N, ep);
+  h->s_F3.init(OP_N, OP_T, GP_FP64);
+  h->s_Uov.init(OP_N, OP_N, GP_FP64);
+  h->s_Uvv.init(OP_T, OP_N, GP_FP64);
+  h->s_HC0.init(OP_N, OP_N, GP_FP64);
   std::vector<OvSpec> spec;
+  std::vector<OvRot> rot;
   std::vector<OvRows> rows;
   std::vector<OvEnergy> en;
   std::vector<OvPair> pair;
   std::vector<OvCong> cong;
-  std::vector<int> bspec, brows, bpair;
+  std::vector<int> bspec, brot, brows, bpair;
   std::vector<EighProb> el, eg;
   std::vector<HermCheck> lchk;
   for (int i = 0; i < h->n_inst; ++i) {
@@ -760,11 +770,8 @@ etdm_status build_ov_plan(etdm_handle* h) {
     const double* Fc = b.F3;
     const double* Fs = b.F3 + (size_t)N * N;
     const double* Wm = b.F3 + 2 * (size_t)N * N;
-    // P = B B^T, Q1 = C0_v B^T
+    // P = B B^T
     h->s_PQ.add(prob(N, N, Nv, b.B, Nv, b.B, Nv, b.P, N));
-    h->s_Q1.add(prob(M, N, Nv, b.C0 + N, M, b.B, Nv, b.Q1, N));
-    // dense H0: H0 Q1 = (H0 C0)_v B^T, also independent of the eigendecomposition
-    if (b.H0) h->s_Q1.add(prob(M, N, Nv, b.HC0 + N, M, b.B, Nv, b.HQ1, N));
     // P = X diag(s) X^T
     if (N <= EIGH_LDS_MAX) {
       el.push_back(EighProb{b.P, b.X, b.s, N, 1});
@@ -809,22 +816,34 @@ etdm_status build_ov_plan(etdm_handle* h) {
         h->s_LWY3[bk].add(up);
       }
     }
-    spec.push_back(OvSpec{b.s, b.X, b.Xcsw, b.T1s, b.T2, b.T3s, b.T3, N});
+    spec.push_back(OvSpec{b.s, b.X, b.fac, b.XT, b.XsnT, b.tab, b.Xcsw, N});
     bspec.push_back(h->tot_spec);
-    h->tot_spec += N * N + N * OV_NQ;
-    // [cos; sinc; W](sqrt P) = Xcsw X^T and the two quadrature products
-    h->s_F3mu.add(prob(3 * N, N, N, b.Xcsw, N, b.X, N, b.F3, N));
-    if (!h->grad_approx) {  // the pair integrals enter only the exact gradient
-      h->s_F3mu.add(prob(N, N, OV_NQ, b.T1s, OV_NQ, b.T2, OV_NQ, b.mu1, N));
-      h->s_F3mu.add(prob(N, N, OV_NQ, b.T3s, OV_NQ, b.T3, OV_NQ, b.mu2, N));
+    h->tot_spec += ov_spectral_blocks(N);
+    // V = X^T B; sinc sqrt(P) = (X diag sinc) X^T and the two quadrature products of
+    // the pair integrals (tables node-major): the exact gradient only
+    h->s_VF.add(prob(N, Nv, N, b.X, N, b.B, Nv, b.V, Nv));
+    if (!h->grad_approx) {
+      const double* tq = b.tab;
+      const size_t q = (size_t)OV_NQ * N;
+      h->s_VF.add(prob(N, N, N, b.XsnT, N, b.XT, N, b.sincP, N));
+      h->s_VF.add(prob(N, N, OV_NQ, tq, N, tq + q, N, b.mu1, N));
+      h->s_VF.add(prob(N, N, OV_NQ, tq + 2 * q, N, tq + 3 * q, N, b.mu2, N));
     }
-    // C_occ = C0_o cos - Q1 sinc, Z1 = C0_o sinc + Q1 W
-    h->s_C.add(with_second(prob(M, N, N, b.C0, M, Fc, N, b.Cocc, N), N, b.Q1, N, Fs, N, -1.0));
-    // dense H0: T = H0 C_occ = (H0 C0)_o cos - (H0 Q1) sinc, in the same launch
-    if (b.H0) h->s_C.add(with_second(prob(M, N, N, b.HC0, M, Fc, N, b.T, N), N, b.HQ1, N, Fs, N, -1.0));
-    h->s_Z.add(with_second(prob(M, N, N, b.C0, M, Fs, N, b.Z1, N), N, b.Q1, N, Wm, N, 1.0));
-    // C_virt = C0_v + Z1 B, T0 = H0 C_occ
-    h->s_V.add(with_addend(prob(M, Nv, N, b.Z1, N, b.B, Nv, b.Cvirt, Nv), b.C0 + N, M, 1.0));
+    // CX = C0_o X (B operand X^T), CV = C0_v V^T; dense H0 also (H0 C0)_o X, (H0 C0)_v V^T
+    h->s_CXV.add(prob(M, N, N, b.C0, M, b.XT, N, b.CX, N));
+    h->s_CXV.add(prob(M, N, Nv, b.C0 + N, M, b.V, Nv, b.CV, N));
+    if (b.H0) {
+      h->s_CXV.add(prob(M, N, N, b.HC0, M, b.XT, N, b.HX, N));
+      h->s_CXV.add(prob(M, N, Nv, b.HC0 + N, M, b.V, Nv, b.HV, N));
+    }
+    rot.push_back(OvRot{b.CX, b.CV, b.HX, b.HV, b.fac, M, N});
+    brot.push_back(h->tot_rot);
+    h->tot_rot += M * N;
+    // C_occ = CX' X^T (dense H0: T = H0 C_occ = HX' X^T in the same launch),
+    // C_virt = C0_v + CV' V
+    h->s_C.add(prob(M, N, N, b.CX, N, b.X, N, b.Cocc, N));
+    if (b.H0) h->s_C.add(prob(M, N, N, b.HX, N, b.X, N, b.T, N));
+    h->s_V.add(with_addend(prob(M, Nv, N, b.CV, N, b.V, Nv, b.Cvirt, Nv), b.C0 + N, M, 1.0));
 
     rows.push_back(OvRows{b.Cocc, b.T, b.d, b.e, M, N, h->focc[i]});
     brows.push_back(h->tot_rows);
@@ -834,31 +853,33 @@ etdm_status build_ov_plan(etdm_handle* h) {
       // G ~ L^T (Eq. app_grad): g = -2 L_ov, straight from the L_ov product
       h->s_Lov.add(prob(N, Nv, M, b.T, N, b.Cvirt, Nv, b.G, Nv, -2.0 * h->w[i] * h->focc[i]));
     } else {
-    // L_ov = w f_occ T^T C_virt (the weight makes this the gradient of w E)
-    h->s_Lov.add(prob(N, Nv, M, b.T, N, b.Cvirt, Nv, b.Lov, Nv, h->w[i] * h->focc[i]));
-    // Gam = X^T (L_ov B^T) X, Nm = Gam o mu1 + Gam^T o mu2, Y2 = X Nm X^T: one workgroup
-    // per instance where X fits the LDS, else grouped GEMMs around the pair kernel
-    h->s_R.add(prob(N, N, Nv, b.Lov, Nv, b.B, Nv, b.R, N));
-    if (N <= EIGH_LDS_MAX) {
-      cong.push_back(OvCong{b.X, b.R, b.mu1, b.mu2, b.Y2, N});
-    } else {
-      h->s_Gam1.add(prob(N, N, N, b.X, N, b.R, N, b.Gam1, N));
-      h->s_Gam.add(prob(N, N, N, b.Gam1, N, b.X, N, b.Gam, N));
-      pair.push_back(OvPair{b.Gam, b.mu1, b.mu2, b.Nm, N});
-      bpair.push_back(h->tot_pair);
-      h->tot_pair += N * N;
-      h->s_Y1.add(prob(N, N, N, b.X, N, b.Nm, N, b.Y1, N));
-      h->s_Y2.add(prob(N, N, N, b.Y1, N, b.X, N, b.Y2, N));
+      // L_ov = w f_occ T^T C_virt (the weight makes this the gradient of w E)
+      h->s_Lov.add(prob(N, Nv, M, b.T, N, b.Cvirt, Nv, b.Lov, Nv, h->w[i] * h->focc[i]));
+      // LV = L_ov V^T; Gam = X^T LV, Nm = Gam o mu1 + Gam^T o mu2, XNm = X Nm: one
+      // workgroup per instance where X fits the LDS, else grouped GEMMs around the
+      // pair kernel
+      h->s_LV.add(prob(N, N, Nv, b.Lov, Nv, b.V, Nv, b.LV, N));
+      if (N <= EIGH_LDS_MAX) {
+        cong.push_back(OvCong{b.s, b.X, b.LV, b.mu1, b.mu2, b.XNm, N});
+      } else {
+        h->s_Gam.add(prob(N, N, N, b.X, N, b.LV, N, b.Gam, N));
+        pair.push_back(OvPair{b.s, b.Gam, b.mu1, b.mu2, b.Nm, N});
+        bpair.push_back(h->tot_pair);
+        h->tot_pair += N * N;
+        h->s_XNm.add(prob(N, N, N, b.X, N, b.Nm, N, b.XNm, N));
+      }
+      // G = -2 (sinc sqrt(P) L_ov + XNm V)
+      h->s_G.add(with_second(prob(N, Nv, N, b.sincP, N, b.Lov, Nv, b.G, Nv, -2.0), N, b.XNm, N, b.V, Nv, -2.0));
     }
-    // G = -2 (sinc L_ov + Y2 B)
-    h->s_G.add(with_second(prob(N, Nv, N, Fs, N, b.Lov, Nv, b.G, Nv, -2.0), N, b.Y2, N, b.B, Nv, -2.0));
-    }
-    // exp(A) blocks: U_ov = sinc B, W B (into Lov), U_vo = -B^T sinc, U_vv = I + B^T (W B)
+    // exp(A): [cos; sinc; W](sqrt P) = Xcsw X^T, U_ov = sinc B, W B (into Lov),
+    // U_vo = -B^T sinc, U_vv = I + B^T (W B)
+    h->s_F3.add(prob(3 * N, N, N, b.Xcsw, N, b.X, N, b.F3, N));
     h->s_Uov.add(prob(N, Nv, N, Fs, N, b.B, Nv, b.U + N, M));
     h->s_Uov.add(prob(N, Nv, N, Wm, N, b.B, Nv, b.Lov, Nv));
     h->s_Uvv.add(prob(Nv, N, N, b.B, Nv, Fs, N, b.U + (size_t)N * M, M, -1.0));
     h->s_Uvv.add(with_addend(prob(Nv, Nv, N, b.B, Nv, b.Lov, Nv, b.U + (size_t)N * M + N, M),
                              b.U + (size_t)N * M + N, M, 1.0));
+    (void)Fc;
     // preconditioner: H0 C0
     if (b.H0) h->s_HC0.add(prob(M, M, M, b.H0, M, b.C0, M, b.HC0, M));
   }
@@ -870,17 +891,14 @@ etdm_status build_ov_plan(etdm_handle* h) {
     for (int i = 0; i < O_COUNT; ++i) h->timers[i].name = kOvNames[i];
     Stage* gs[O_COUNT] = {};
     gs[O_PQ] = &h->s_PQ;
-    gs[O_Q1] = &h->s_Q1;
-    gs[O_F3MU] = &h->s_F3mu;
+    gs[O_VF] = &h->s_VF;
+    gs[O_CXV] = &h->s_CXV;
     gs[O_C] = &h->s_C;
-    gs[O_Z] = &h->s_Z;
     gs[O_V] = &h->s_V;
     gs[O_LOV] = &h->s_Lov;
-    gs[O_R] = &h->s_R;
-    gs[O_GAM1] = &h->s_Gam1;
+    gs[O_LV] = &h->s_LV;
     gs[O_GAM] = &h->s_Gam;
-    gs[O_Y1] = &h->s_Y1;
-    gs[O_Y2] = &h->s_Y2;
+    gs[O_XNM] = &h->s_XNm;
     gs[O_G] = &h->s_G;
     h->timer_stage.assign(gs, gs + O_COUNT);
     for (int i = 0; i < O_COUNT; ++i)
@@ -898,27 +916,31 @@ etdm_status build_ov_plan(etdm_handle* h) {
     }
     for (int i = 0; i < h->n_inst; ++i) {
       const double M = h->M[i], N = h->N[i];
+      const bool dense = h->h0_format == 0;
       h->timers[O_ROWS].flops += 6.0 * M * N;
       if (h->h0_format == 1) {
         h->timers[O_T].flops += 2.0 * (double)h->ov[i].bsr_nnz * N;
         h->timers[O_T].bytes += 8.0 * ((double)h->ov[i].bsr_nnz + 2.0 * M * N);
       }
       h->timers[O_ROWS].bytes += 8.0 * (3.0 * M * N + 2.0 * M);
-      h->timers[O_SPEC].bytes += 8.0 * (4.0 * N * N + 4.0 * N * OV_NQ);
-      if (!h->grad_approx && N <= EIGH_LDS_MAX) {  // four N^3 products, X R mu1 mu2 in, Y2 out
-        h->timers[O_CONG].flops += 8.0 * N * N * N + 3.0 * N * N;
+      // X read; X^T, (X diag sinc)^T, the four node-major tables and the factors written
+      h->timers[O_SPEC].bytes += 8.0 * (3.0 * N * N + 4.0 * N * OV_NQ + 4.0 * N);
+      // CX, CV (and HX, HV) read and written
+      h->timers[O_ROT].flops += (dense ? 6.0 : 4.0) * M * N;
+      h->timers[O_ROT].bytes += 8.0 * (dense ? 7.0 : 4.0) * M * N;
+      if (!h->grad_approx && N <= EIGH_LDS_MAX) {  // two N^3 products; X LV mu1 mu2 in, XNm out
+        h->timers[O_CONG].flops += 4.0 * N * N * N + 3.0 * N * N;
         h->timers[O_CONG].bytes += 8.0 * 5.0 * N * N;
       } else {
         h->timers[O_PAIR].flops += 3.0 * N * N;
-        h->timers[O_PAIR].bytes += 8.0 * 5.0 * N * N;
+        h->timers[O_PAIR].bytes += 8.0 * 4.0 * N * N;
       }
       h->timers[O_ENERGY].bytes += 16.0 * M;
     }
     h->timers[O_SCAN].bytes = 8.0 * h->n_param;
   }
-  Stage* stages[] = {&h->s_PQ,  &h->s_Q1,   &h->s_F3mu, &h->s_C,  &h->s_Z,   &h->s_V,   &h->s_Lov,
-                     &h->s_R,   &h->s_Gam1, &h->s_Gam, &h->s_Y1, &h->s_Y2, &h->s_G,  &h->s_Uov,
-                     &h->s_Uvv, &h->s_HC0};
+  Stage* stages[] = {&h->s_PQ,  &h->s_VF, &h->s_CXV, &h->s_C,  &h->s_V,   &h->s_Lov, &h->s_LV,
+                     &h->s_Gam, &h->s_XNm, &h->s_G,  &h->s_F3, &h->s_Uov, &h->s_Uvv, &h->s_HC0};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
   std::vector<Stage*> packable(stages, stages + sizeof(stages) / sizeof(stages[0]));
   if (!h->eig_large.empty()) {
@@ -944,19 +966,16 @@ etdm_status build_ov_plan(etdm_handle* h) {
     }
     CHECK(upload(h, &h->d_lchk, lchk));
   }
-  // Q1, Z1 and C_virt can run on the side stream beside main-stream stages (the
-  // eigensolver's products, C_occ): they pack into an arena of their own
-  Stage* const side_stages[] = {&h->s_Q1, &h->s_Z, &h->s_V};
-  packable.erase(std::remove_if(packable.begin(), packable.end(),
-                                [&](Stage* st) {
-                                  return std::find(std::begin(side_stages), std::end(side_stages), st) !=
-                                         std::end(side_stages);
-                                }),
-                 packable.end());
-  CHECK(plan_packed_stages(h, side_stages, 3));
+  // C_virt can run on the side stream beside main-stream stages (C_occ): it packs
+  // into an arena of its own
+  Stage* const side_stages[] = {&h->s_V};
+  packable.erase(std::remove(packable.begin(), packable.end(), &h->s_V), packable.end());
+  CHECK(plan_packed_stages(h, side_stages, 1));
   CHECK(plan_packed_stages(h, packable.data(), packable.size()));
   CHECK(upload(h, &h->d_spec, spec));
   CHECK(upload(h, &h->b_spec, bspec));
+  CHECK(upload(h, &h->d_rot, rot));
+  CHECK(upload(h, &h->b_rot, brot));
   CHECK(upload(h, &h->d_rows, rows));
   CHECK(upload(h, &h->b_rows, brows));
   {
@@ -1346,8 +1365,6 @@ void free_handle(etdm_handle* h) {
   if (h->ss_s_host) hipHostFree(h->ss_s_host);
   if (h->lb_sum) hipHostFree(h->lb_sum);
   if (h->side) hipStreamDestroy(h->side);
-  if (h->ev_fork) hipEventDestroy(h->ev_fork);
-  if (h->ev_join) hipEventDestroy(h->ev_join);
   if (h->ev_fork2) hipEventDestroy(h->ev_fork2);
   if (h->ev_join2) hipEventDestroy(h->ev_join2);
   free_timers(h);
@@ -1360,36 +1377,19 @@ void free_handle(etdm_handle* h) {
 
 #define TIMED(id) Timed timed_scope_(h, id, s)
 
-// Exponential part, front: P, Q1, the small eigensolver and the tridiagonal path
-// of the large instances up to their acceptance checks.  fallback selects what
+// Exponential part, front: P, the small eigensolver and the tridiagonal path of
+// the large instances up to their acceptance checks.  fallback selects what
 // follows for the large instances: 0 nothing (the caller decides), 1 the Jacobi
 // sweeps launched until the host sees them converge, 2 all sweeps launched (each
 // returns at once when the tridiagonal result was accepted; for graph capture).
 void ov_front(etdm_handle* h, hipStream_t s, int fallback) {
   { TIMED(O_PQ); h->s_PQ.launch(s); }
-  // Q1 on the side stream, beside the eigensolver (in order while stages are timed).
-  // With large instances it starts after the cooperative reductions, whose
-  // workgroups must all be resident at once.
-  const bool fork = h->side && h->tmask == 0 && !h->s_Q1.probs.empty();  // (side: only when it pays)
-  if (!fork) {
-    TIMED(O_Q1);
-    h->s_Q1.launch(s);
-  }
-  auto launch_q1 = [&]() {
-    if (!fork) return;
-    hipEventRecord(h->ev_fork, s);
-    hipStreamWaitEvent(h->side, h->ev_fork, 0);
-    h->s_Q1.launch(h->side);
-    hipEventRecord(h->ev_join, h->side);
-  };
-  if (h->eig_large.empty()) launch_q1();
   { TIMED(O_EIGL); launch_eigh_real_lds(h->d_eig_lds, h->n_eig_lds, h->status, s); }
   if (!h->eig_large.empty()) {
     TIMED(O_EIGG);
     // reduction to tridiagonal form and its eigenpairs, the orthogonality check and
     // one Newton-Schulz step, the compact-WY back-transform, the residual against P
     for (const EighLarge& e : h->eig_large) launch_tb_reduce(e, s);
-    launch_q1();
     for (const EighLarge& e : h->eig_large) launch_tb_eigenpairs(e, s);
     h->s_LG.launch(s);
     for (const EighLarge& e : h->eig_large) launch_tb_orth_check(e, s);
@@ -1408,58 +1408,70 @@ void ov_front(etdm_handle* h, hipStream_t s, int fallback) {
     if (fallback)
       for (const EighLarge& e : h->eig_large) launch_eigh_large(e, LARGE_EIGH_MAX_SWEEPS, h->status, s, fallback == 1);
   }
-  if (fork) hipStreamWaitEvent(s, h->ev_join, 0);
 }
 
-void ov_back_exp(etdm_handle* h, hipStream_t s) {
-  { TIMED(O_SPEC); launch_ov_spectral(h->d_spec, h->b_spec, h->n_inst, h->tot_spec, h->gl_t, h->gl_w, s); }
-  { TIMED(O_F3MU); h->s_F3mu.launch(s); }
+// After the eigendecomposition: the spectral factors and eigenbasis copies, then
+// V = X^T B with sinc sqrt(P) and the pair-integral products (energy and gradient),
+// or the matrix functions [cos; sinc; W](sqrt P) of exp(A) itself.
+void ov_basis(etdm_handle* h, hipStream_t s, int want_exp) {
+  {
+    TIMED(O_SPEC);
+    launch_ov_spectral(h->d_spec, h->b_spec, h->n_inst, h->tot_spec, h->gl_t, h->gl_w, want_exp, s);
+  }
+  if (want_exp) {
+    h->s_F3.launch(s);
+  } else {
+    TIMED(O_VF);
+    h->s_VF.launch(s);
+  }
 }
 
-void ov_exponential_part(etdm_handle* h, hipStream_t s) {
+void ov_front_fallback(etdm_handle* h, hipStream_t s) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   hipStreamIsCapturing(s, &cs);
   ov_front(h, s, cs == hipStreamCaptureStatusNone ? 1 : 2);
-  ov_back_exp(h, s);
 }
 
-void ov_energy_grad_rest(etdm_handle* h, hipStream_t s);
-
-void ov_energy_grad(etdm_handle* h, hipStream_t s) {
-  ov_exponential_part(h, s);
-  ov_energy_grad_rest(h, s);
-}
-
-// After the exponential part: C, H0 C_occ, the energy, L and the gradient.
-void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
-  // Z1 and C_virt need only the spectral factors and Q1: on the side stream, beside
-  // C_occ, the rows and the energy (in order while stages are timed); joined before L_ov
-  const bool fork = h->side && h->tmask == 0;
+// The rotated orbitals: CX = C0_o X, CV = C0_v V^T, their combination, then C_occ
+// (and dense T) on s; C_virt on the side stream when fork (joined by ev_join2), else
+// on s after C_occ.
+void ov_orbitals(etdm_handle* h, hipStream_t s, bool fork) {
+  { TIMED(O_CXV); h->s_CXV.launch(s); }
+  { TIMED(O_ROT); launch_ov_rot(h->d_rot, h->b_rot, h->n_inst, h->tot_rot, s); }
   if (fork) {
     hipEventRecord(h->ev_fork2, s);
     hipStreamWaitEvent(h->side, h->ev_fork2, 0);
-    h->s_Z.launch(h->side);
     h->s_V.launch(h->side);
     hipEventRecord(h->ev_join2, h->side);
   }
   { TIMED(O_C); h->s_C.launch(s); }
   if (!fork) {
-    TIMED(O_Z);
-    h->s_Z.launch(s);
-  }
-  {
-    // block-sparse H0: T = H0 C_occ here (dense H0: T was formed with C_occ)
-    if (h->h0_format == 1) {
-      TIMED(O_T);
-      for (int i = 0; i < h->n_inst; ++i) {
-        const OvBuf& b = h->ov[i];
-        launch_bsr_spmm(b.H0_bsr, b.Cocc, h->N[i], h->N[i], b.T, h->N[i], s);
-      }
-    }
-  }
-  if (!fork) {
     TIMED(O_V);
     h->s_V.launch(s);
+  }
+}
+
+void ov_energy_grad_rest(etdm_handle* h, hipStream_t s);
+
+void ov_energy_grad(etdm_handle* h, hipStream_t s) {
+  ov_front_fallback(h, s);
+  ov_basis(h, s, 0);
+  ov_energy_grad_rest(h, s);
+}
+
+// After the spectral products: C, H0 C_occ, the energy, L and the gradient.
+void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
+  // C_virt on the side stream, beside C_occ, the rows and the energy (in order while
+  // stages are timed); joined before L_ov
+  const bool fork = h->side && h->tmask == 0;
+  ov_orbitals(h, s, fork);
+  if (h->h0_format == 1) {
+    // block-sparse H0: T = H0 C_occ here (dense H0: T was formed with C_occ)
+    TIMED(O_T);
+    for (int i = 0; i < h->n_inst; ++i) {
+      const OvBuf& b = h->ov[i];
+      launch_bsr_spmm(b.H0_bsr, b.Cocc, h->N[i], h->N[i], b.T, h->N[i], s);
+    }
   }
   { TIMED(O_ROWS); launch_ov_rows(h->d_rows, h->b_rows, h->n_inst, h->tot_rows, h->U, s); }
   {
@@ -1469,17 +1481,13 @@ void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
   }
   if (fork) hipStreamWaitEvent(s, h->ev_join2, 0);
   { TIMED(O_LOV); h->s_Lov.launch(s); }
-  if (!h->s_R.probs.empty()) {
-    TIMED(O_R);
-    h->s_R.launch(s);
+  if (!h->s_LV.probs.empty()) {
+    TIMED(O_LV);
+    h->s_LV.launch(s);
   }
   if (h->n_cong > 0) {
     TIMED(O_CONG);
     launch_ov_congruence(h->d_cong, h->n_cong, s);
-  }
-  if (!h->s_Gam1.probs.empty()) {
-    TIMED(O_GAM1);
-    h->s_Gam1.launch(s);
   }
   if (!h->s_Gam.probs.empty()) {
     TIMED(O_GAM);
@@ -1489,13 +1497,9 @@ void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
     TIMED(O_PAIR);
     launch_ov_pair(h->d_pair, h->b_pair, h->n_pair, h->tot_pair, s);
   }
-  if (!h->s_Y1.probs.empty()) {
-    TIMED(O_Y1);
-    h->s_Y1.launch(s);
-  }
-  if (!h->s_Y2.probs.empty()) {
-    TIMED(O_Y2);
-    h->s_Y2.launch(s);
+  if (!h->s_XNm.probs.empty()) {
+    TIMED(O_XNM);
+    h->s_XNm.launch(s);
   }
   if (!h->s_G.probs.empty()) {
     TIMED(O_G);
@@ -1505,7 +1509,8 @@ void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
 }
 
 void ov_expm(etdm_handle* h, hipStream_t s) {
-  ov_exponential_part(h, s);
+  ov_front_fallback(h, s);
+  ov_basis(h, s, 1);
   for (int i = 0; i < h->n_inst; ++i) {
     const OvBuf& b = h->ov[i];
     const int M = h->M[i], N = h->N[i];
@@ -1517,10 +1522,9 @@ void ov_expm(etdm_handle* h, hipStream_t s) {
 }
 
 void ov_new_reference(etdm_handle* h, hipStream_t s) {
-  ov_exponential_part(h, s);
-  h->s_C.launch(s);
-  h->s_Z.launch(s);
-  h->s_V.launch(s);
+  ov_front_fallback(h, s);
+  ov_basis(h, s, 0);
+  ov_orbitals(h, s, false);
   launch_c0_update(h->d_c0up, h->b_mat, h->n_inst, h->tot_mat, s);
   if (h->h0_format == 0) h->s_HC0.launch(s);  // H0 C0 for the new reference
 }
@@ -1705,7 +1709,7 @@ etdm_status run_energy_grad(etdm_handle* h, hipStream_t s) {
     if (split) {
       CHECK(capture(h, &h->graph, &h->graph_exec, [](etdm_handle* hh, hipStream_t ss) { ov_front(hh, ss, 0); }));
       CHECK(capture(h, &h->graph2, &h->graph2_exec, [](etdm_handle* hh, hipStream_t ss) {
-        ov_back_exp(hh, ss);
+        ov_basis(hh, ss, 0);
         ov_energy_grad_rest(hh, ss);
       }));
     } else {
@@ -1799,7 +1803,7 @@ void lb_seq_front(etdm_handle* h, hipStream_t s) {
 }
 
 void lb_seq_back(etdm_handle* h, hipStream_t s) {
-  ov_back_exp(h, s);
+  ov_basis(h, s, 0);
   ov_energy_grad_rest(h, s);
   lb_post(h, s);
 }
@@ -2171,12 +2175,10 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
       hipHostMalloc(reinterpret_cast<void**>(&h->ss_s_host), sizeof(int)) != hipSuccess)
     st = ETDM_E_NOMEM;
   if (st == ETDM_OK && real && h->h0_format == 0) h->s_HC0.launch(s);  // H0 C0 of the reference
-  // the side stream only where Q1 is worth a fork and join (on one small molecule
+  // the side stream only where C_virt is worth a fork and join (on one small molecule
   // they cost more than they hide)
-  if (st == ETDM_OK && real && stage_flops(h->s_Q1) >= 1e8 &&
+  if (st == ETDM_OK && real && stage_flops(h->s_V) >= 1e8 &&
       (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
-       hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-       hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess ||
        hipEventCreateWithFlags(&h->ev_fork2, hipEventDisableTiming) != hipSuccess ||
        hipEventCreateWithFlags(&h->ev_join2, hipEventDisableTiming) != hipSuccess))
     st = ETDM_E_HIP;

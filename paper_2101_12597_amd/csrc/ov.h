@@ -8,6 +8,9 @@
 namespace etdm {
 
 constexpr int OV_NQ = 48;
+// The 48-node rule of the pair integrals is exact to rounding while both angles are at
+// most OV_SIGQ (it still is at 60 rad); pairs with a larger angle take closed forms.
+constexpr double OV_SIGQ = 40.0;
 constexpr int BSR_MAX_BS = 32;  // largest block size of a block-sparse H0
 
 // block-sparse rows, square blocks (device arrays)
@@ -19,18 +22,40 @@ struct BsrMat {
 };
 // T = H C (C: M x ncols row-major, ld ldc; T: ld ldt)
 void launch_bsr_spmm(const BsrMat& H, const double* C, int64_t ldc, int ncols, double* T, int64_t ldt,
-                     hipStream_t s);  // Gauss-Legendre nodes for the pair integrals (exact to rounding for sigma <= ~40)
+                     hipStream_t s);
 
+// Spectral factors and eigenbasis copies of one instance (the spectral kernel):
+// per angle sigma_k = sqrt(max(s_k, 0)) the factors cos, sinc and W = -1/2 sinc^2(sigma/2),
+// the transposes X^T and (X diag(sinc))^T the eigenbasis products take, the quadrature
+// tables of the pair integrals stored node-major, and for exp(A) the scaled copies
+// [X diag(cos); X diag(sinc); X diag(W)].
 struct OvSpec {
   const double* s;  // eigenvalues of P [N]
-  const double* X;  // eigenvectors [N x N]
-  double* Xcsw;     // [3N x N]
-  double* T1s;      // [N x NQ]
-  double* T2;
-  double* T3s;
-  double* T3;
+  const double* X;  // eigenvectors [N x N] (column k belongs to s_k)
+  double* fac;      // [3 x N]: cos, sinc, W of each angle
+  double* XT;       // [N x N] X^T
+  double* XsnT;     // [N x N] (X diag(sinc))^T
+  double* tab;      // [4 x OV_NQ x N]: T1s, T2, T3s, T3 (node-major)
+  double* Xcsw;     // [3N x N], written only when the exponential itself is wanted
   int32_t N;
 };
+// per instance: ceil(N/32)^2 transpose tiles, then the table and factor blocks
+int ov_spectral_blocks(int N);
+
+// The eigenbasis combination of the rotated orbitals (Eq. uinv in the basis of the
+// eigenvectors of P), per column k with the factors of sigma_k, in place:
+//   CX <- CX cos - CV sinc      (then C_occ = CX X^T)
+//   CV <- CX sinc + CV W        (then C_virt = C0_v + CV V)
+//   HX <- HX cos - HV sinc      (dense H0: then T = H0 C_occ = HX X^T)
+struct OvRot {
+  double* CX;  // [M x N] C0_o X
+  double* CV;  // [M x N] C0_v V^T, V = X^T B
+  double* HX;  // [M x N] (H0 C0)_o X, or null
+  const double* HV;  // [M x N] (H0 C0)_v V^T
+  const double* fac;
+  int32_t M, N;
+};
+void launch_ov_rot(const OvRot* d, const int* d_begin, int n_inst, int total, hipStream_t s);
 
 struct OvRows {
   const double* Cocc;  // [M x N]
@@ -50,6 +75,7 @@ struct OvEnergy {
 };
 
 struct OvPair {
+  const double* s;  // eigenvalues of P [N] (squared rotation angles)
   const double* Gam;
   const double* mu1;
   const double* mu2;
@@ -57,21 +83,23 @@ struct OvPair {
   int32_t N;
 };
 
-// The gradient chain of one instance with N <= EIGH_LDS_MAX in one workgroup (Eq.
-// gradients): Gam = X^T R X, Nm = Gam o mu1 + Gam^T o mu2, Y2 = X Nm X^T.  X and one
-// working matrix sit in LDS; the four N x N x N products run on the FP64 matrix cores.
+// The middle of the gradient chain of one instance with N <= EIGH_LDS_MAX in one
+// workgroup (Eq. gradients): Gam = X^T LV, Nm = Gam o mu1 + Gam^T o mu2, XNm = X Nm.
+// X and one working matrix sit in LDS; the two N x N x N products run on the FP64
+// matrix cores.
 struct OvCong {
+  const double* s;    // [N] eigenvalues of P (squared rotation angles)
   const double* X;    // [N x N] eigenvectors of P
-  const double* R;    // [N x N] L_ov B^T
+  const double* LV;   // [N x N] L_ov V^T
   const double* mu1;  // [N x N] pair integrals
   const double* mu2;
-  double* Y2;         // [N x N] out
+  double* XNm;        // [N x N] out
   int32_t N;
 };
 void launch_ov_congruence(const OvCong* d, int n_inst, hipStream_t s);
 
-void launch_ov_spectral(const OvSpec* d, const int* d_begin, int n_inst, int total, const double* gl_t,
-                        const double* gl_w, hipStream_t s);
+void launch_ov_spectral(const OvSpec* d, const int* d_begin, int n_inst, int total_blocks, const double* gl_t,
+                        const double* gl_w, int want_exp, hipStream_t s);
 void launch_ov_rows(const OvRows* d, const int* d_begin, int n_inst, int total_rows, double U, hipStream_t s);
 void launch_ov_energy(const OvEnergy* d, int n_inst, double U, double* E, hipStream_t s);
 void launch_total_energy(double* E, int n_inst, double extra_hub, const double* hub_vec, int hub_n, double U,

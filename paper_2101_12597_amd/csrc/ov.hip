@@ -9,8 +9,22 @@
 //   Nm[k][l] = Gam[k][l] mu1[k][l] + Gam[l][k] mu2[k][l],
 //   mu1[k][l] = -int_0^1 (t^2/2) cos(t sigma_k) sinc^2(t sigma_l / 2) dt,
 //   mu2[k][l] =  int_0^1 t^2 sinc(t sigma_k) sinc(t sigma_l) dt.
+//
+// Every product is taken in the eigenbasis of P, through V = X^T B (row k is
+// sigma_k times a unit vector):
+//   C_occ  = (C0_o X cos - C0_v V^T sinc) X^T,
+//   C_virt = C0_v + (C0_o X sinc + C0_v V^T W) V,
+//   Gam    = X^T (L_ov V^T),   dE/dB = -2 (sinc sqrt(P) L_ov + (X Nm) V),
+// where the diagonal factors act on column k.  Each term of these sums is then
+// bounded independently of the angles (sinc(s) s = sin s, W(s) s^2 = cos s - 1), so a
+// split-precision product, whose error is relative to the sum of the absolute values of
+// its terms, keeps its accuracy at any rotation angle.  Products with B itself in
+// another basis (B^T W B, L_ov B^T) would sum terms of size sigma_max that cancel.
+//
 // The two pair integrals are evaluated by Gauss-Legendre quadrature written as
-// two rank-NQ matrix products (tables built here, products on the GEMM kernel).
+// two rank-NQ matrix products (tables built here, products on the GEMM kernel) while
+// both angles are at most OV_SIGQ; a pair with a larger angle takes closed forms
+// (ov_pair_large), so rotations of any size are covered.
 #include "ov.h"
 
 namespace etdm {
@@ -27,40 +41,176 @@ __device__ __forceinline__ int find_range(const int* __restrict__ begin, int n, 
   return lo;
 }
 
-// per-angle spectral factors fn = [cos sigma | sinc sigma | -1/2 sinc^2(sigma/2)]
-// and the scaled eigenvector copies Xcsw = [X diag(fn0); X diag(fn1); X diag(fn2)],
-// plus the quadrature tables.  One thread per element of the N x N or N x NQ ranges.
-__global__ void ov_spectral_kernel(const OvSpec* __restrict__ specs, const int* __restrict__ begin,
-                                   int n_inst, int total, const double* __restrict__ gl_t,
-                                   const double* __restrict__ gl_w) {
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int ii = find_range(begin, n_inst, idx);
+// Pair integrals of a pair with max(a, b) > OV_SIGQ (a = sigma_k, b = sigma_l).
+// With Kc = int_0^1 cos(ta) cos(tb) dt and Ks = int_0^1 sin(ta) sin(tb) dt,
+//   mu1 = -(sinc a - Kc) / b^2,   mu2 = Ks / (a b),
+// exact identities that lose accuracy only when the angle they divide by is small.
+// There the small angle is expanded instead: sinc^2(x) = sum_n c_n x^(2n) with
+// c_n = (-1)^n 2^(2n+1) / (2n+2)! and sinc(x) = sum_n (-1)^n x^(2n) / (2n+1)!, which
+// leaves the moments C_m = int_0^1 t^m cos(tL) dt and S_m = int_0^1 t^m sin(tL) dt of
+// the large angle L > OV_SIGQ.  Integration by parts gives them upward,
+//   S_m = (m C_{m-1} - cos L) / L,   C_m = (sin L - m S_{m-1}) / L,
+// which is stable for m < L.  OV_NSER terms reach rounding for a small angle below
+// OV_TAU (the largest term left out is below 1e-19 relative).
+constexpr double OV_TAU = 0.5;
+constexpr int OV_NSER = 9;
+
+__device__ void ov_pair_large(double a, double b, double& m1, double& m2) {
+  const double lo = fmin(a, b), L = fmax(a, b);
+  const bool ser1 = b < OV_TAU;   // then L = a
+  const bool ser2 = lo < OV_TAU;  // (ser1 implies ser2)
+  if (!ser1) m1 = -(sincd(a) - 0.5 * (sincd(a - b) + sincd(a + b))) / (b * b);
+  if (!ser2) m2 = (sincd(a - b) - sincd(a + b)) / (2.0 * a * b);
+  if (!ser2) return;
+  double sL, cL;
+  sincos(L, &sL, &cL);
+  const double rL = 1.0 / L;
+  double Cm = sL * rL, Sm = (1.0 - cL) * rL;  // m = 0
+  double acc1 = 0.0, acc2 = 0.0;
+  double p1 = 1.0, c1 = 1.0;        // (b/2)^(2n), c_n
+  double p2 = 1.0, c2 = 1.0;        // lo^(2n), (-1)^n / (2n+1)!
+  const double x1 = 0.25 * b * b, x2 = lo * lo;
+  for (int m = 1; m <= 2 * OV_NSER + 2; ++m) {
+    const double Sn = (m * Cm - cL) * rL;
+    const double Cn = (sL - m * Sm) * rL;
+    Sm = Sn;
+    Cm = Cn;
+    if (m & 1) {  // m = 2n + 1: a term of mu2
+      acc2 += c2 * p2 * Sm;
+      p2 *= x2;
+      c2 *= -1.0 / ((m + 1.0) * (m + 2.0));
+    } else {      // m = 2n + 2: a term of mu1
+      acc1 += c1 * p1 * Cm;
+      p1 *= x1;
+      c1 *= -4.0 / ((m + 1.0) * (m + 2.0));
+    }
+  }
+  if (ser1) m1 = -0.5 * acc1;
+  m2 = acc2 * rL;
+}
+
+// mu1, mu2 of pair (k, l): the quadrature tables below OV_SIGQ, closed forms above
+__device__ __forceinline__ void ov_pair_values(const double* __restrict__ s, const double* __restrict__ mu1,
+                                               const double* __restrict__ mu2, int k, int l, int e, double& m1,
+                                               double& m2) {
+  const double a = sqrt(fmax(s[k], 0.0)), b = sqrt(fmax(s[l], 0.0));
+  if (fmax(a, b) > OV_SIGQ) {
+    ov_pair_large(a, b, m1, m2);
+  } else {
+    m1 = mu1[e];
+    m2 = mu2[e];
+  }
+}
+
+// Spectral pass of one instance, three kinds of 256-thread blocks:
+//  * 32 x 32 tiles of X: X^T and (X diag(sinc))^T through an LDS transpose, and for
+//    exp(A) the row-major copies [X diag(cos); X diag(sinc); X diag(W)];
+//  * the quadrature tables, node-major ([q][j][k], k fastest):
+//      T1s = cos(t_j s_k)(-w_j t_j^2 / 2), T2 = sinc^2(t_j s_k / 2),
+//      T3s = sinc(t_j s_k) w_j t_j^2,       T3 = sinc(t_j s_k);
+//  * the per-angle factors [cos | sinc | W].
+constexpr int SP_TILE = 32;
+
+int ov_spectral_blocks(int N) {
+  const int nt = (N + SP_TILE - 1) / SP_TILE;
+  return nt * nt + (OV_NQ * N + 255) / 256 + (N + 255) / 256;
+}
+
+__device__ __forceinline__ void spectral_factors(double sk, double& c, double& sn, double& w) {
+  const double sig = sqrt(fmax(sk, 0.0));
+  const double h = sincd(0.5 * sig);
+  c = cos(sig);
+  sn = sincd(sig);
+  w = -0.5 * h * h;
+}
+
+__global__ __launch_bounds__(256) void ov_spectral_kernel(const OvSpec* __restrict__ specs,
+                                                          const int* __restrict__ begin, int n_inst,
+                                                          const double* __restrict__ gl_t,
+                                                          const double* __restrict__ gl_w, int want_exp) {
+  __shared__ double tile[SP_TILE][SP_TILE + 1];
+  __shared__ double fsn[SP_TILE];
+  const int ii = find_range(begin, n_inst, blockIdx.x);
   const OvSpec& sp = specs[ii];
-  const int N = sp.N;
-  int e = idx - begin[ii];
-  if (e < N * N) {
-    const int i = e / N, k = e - i * N;
-    const double sig = sqrt(fmax(sp.s[k], 0.0));
-    const double x = sp.X[(size_t)i * N + k];
-    const double h = sincd(0.5 * sig);
-    sp.Xcsw[(size_t)i * N + k] = x * cos(sig);
-    sp.Xcsw[(size_t)(N + i) * N + k] = x * sincd(sig);
-    sp.Xcsw[(size_t)(2 * N + i) * N + k] = x * (-0.5 * h * h);
+  const int N = sp.N, t = threadIdx.x;
+  if (N <= 0) return;
+  const int nt = (N + SP_TILE - 1) / SP_TILE;
+  int b = blockIdx.x - begin[ii];
+  if (b < nt * nt) {
+    const int i0 = (b / nt) * SP_TILE, k0 = (b % nt) * SP_TILE;
+    const int lc = t & (SP_TILE - 1), lr = t >> 5;  // 8 rows per pass
+    const int k = k0 + lc;
+    double c = 0.0, sn = 0.0, w = 0.0;
+    if (k < N) spectral_factors(sp.s[k], c, sn, w);
+    if (lr == 0) fsn[lc] = sn;
+    for (int r = lr; r < SP_TILE; r += 8) {
+      const int i = i0 + r;
+      double x = 0.0;
+      if (i < N && k < N) {
+        x = sp.X[(size_t)i * N + k];
+        if (want_exp) {
+          sp.Xcsw[(size_t)i * N + k] = x * c;
+          sp.Xcsw[(size_t)(N + i) * N + k] = x * sn;
+          sp.Xcsw[(size_t)(2 * N + i) * N + k] = x * w;
+        }
+      }
+      tile[r][lc] = x;
+    }
+    __syncthreads();
+    // transposed: output row k0 + r, column i0 + lc
+    for (int r = lr; r < SP_TILE; r += 8) {
+      const int ko = k0 + r, io = i0 + lc;
+      if (ko < N && io < N) {
+        const double x = tile[lc][r];
+        sp.XT[(size_t)ko * N + io] = x;
+        sp.XsnT[(size_t)ko * N + io] = x * fsn[r];
+      }
+    }
     return;
   }
-  e -= N * N;
-  const int k = e / OV_NQ, j = e - k * OV_NQ;
-  const double sig = sqrt(fmax(sp.s[k], 0.0));
-  const double t = gl_t[j], w = gl_w[j];
-  const double ts = t * sig;
-  const double h = sincd(0.5 * ts);
-  const double sc = sincd(ts);
-  const size_t o = (size_t)k * OV_NQ + j;
-  sp.T1s[o] = cos(ts) * (-0.5 * w * t * t);
-  sp.T2[o] = h * h;
-  sp.T3s[o] = sc * (w * t * t);
-  sp.T3[o] = sc;
+  b -= nt * nt;
+  const int ntab = (OV_NQ * N + 255) / 256;
+  if (b < ntab) {
+    const int idx = b * 256 + t;
+    if (idx >= OV_NQ * N) return;
+    const int j = idx / N, k = idx - j * N;
+    const double sig = sqrt(fmax(sp.s[k], 0.0));
+    const double tj = gl_t[j], wj = gl_w[j];
+    const double ts = tj * sig;
+    const double h = sincd(0.5 * ts);
+    const double sc = sincd(ts);
+    const size_t q = (size_t)OV_NQ * N;
+    sp.tab[idx] = cos(ts) * (-0.5 * wj * tj * tj);
+    sp.tab[q + idx] = h * h;
+    sp.tab[2 * q + idx] = sc * (wj * tj * tj);
+    sp.tab[3 * q + idx] = sc;
+    return;
+  }
+  b -= ntab;
+  const int k = b * 256 + t;
+  if (k >= N) return;
+  double c, sn, w;
+  spectral_factors(sp.s[k], c, sn, w);
+  sp.fac[k] = c;
+  sp.fac[N + k] = sn;
+  sp.fac[2 * N + k] = w;
+}
+
+// In-place eigenbasis combination (see OvRot), one thread per element of M x N.
+__global__ void ov_rot_kernel(const OvRot* __restrict__ rots, const int* __restrict__ begin, int n_inst,
+                              int total) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = find_range(begin, n_inst, idx);
+  const OvRot& q = rots[ii];
+  const int N = q.N;
+  const int e = idx - begin[ii];
+  const int k = e % N;
+  const double c = q.fac[k], sn = q.fac[N + k], w = q.fac[2 * N + k];
+  const double cx = q.CX[e], cv = q.CV[e];
+  q.CX[e] = cx * c - cv * sn;
+  q.CV[e] = cx * sn + cv * w;
+  if (q.HX) q.HX[e] = q.HX[e] * c - q.HV[e] * sn;
 }
 
 // Row pass over the occupied orbitals: d_mu = f sum_i C_mu_i^2 (diagonal of rho),
@@ -171,7 +321,9 @@ __global__ void ov_pair_kernel(const OvPair* __restrict__ pr, const int* __restr
   const int N = q.N;
   const int e = idx - begin[ii];
   const int k = e / N, l = e - k * N;
-  q.Nm[e] = q.Gam[e] * q.mu1[e] + q.Gam[(size_t)l * N + k] * q.mu2[e];
+  double m1, m2;
+  ov_pair_values(q.s, q.mu1, q.mu2, k, l, e, m1, m2);
+  q.Nm[e] = q.Gam[e] * m1 + q.Gam[(size_t)l * N + k] * m2;
 }
 
 // Gradient chain of a small instance (N <= EIGH_LDS_MAX), one workgroup of CG_NT
@@ -233,15 +385,11 @@ __global__ __launch_bounds__(CG_NT) void ov_congruence_kernel(const OvCong* __re
   for (int e = tid; e < n * n; e += CG_NT) {
     const int i = e / n, j = e - i * n;
     sX[i * ld + j] = q.X[e];
-    sW[i * ld + j] = q.R[e];
+    sW[i * ld + j] = q.LV[e];
   }
   __syncthreads();
   cg_d4 acc[CG_MAXT];
-  cg_mm<true, false>(sX, sW, n, ld, acc);  // Gam1 = X^T R
-  __syncthreads();
-  cg_store(sW, n, ld, acc);
-  __syncthreads();
-  cg_mm<false, false>(sW, sX, n, ld, acc);  // Gam = Gam1 X
+  cg_mm<true, false>(sX, sW, n, ld, acc);  // Gam = X^T LV
   __syncthreads();
   cg_store(sW, n, ld, acc);
   __syncthreads();
@@ -252,7 +400,9 @@ __global__ __launch_bounds__(CG_NT) void ov_congruence_kernel(const OvCong* __re
     nm[u] = 0.0;
     if (e < n * n) {
       const int k = e / n, l = e - k * n;
-      nm[u] = sW[k * ld + l] * q.mu1[e] + sW[l * ld + k] * q.mu2[e];
+      double m1, m2;
+      ov_pair_values(q.s, q.mu1, q.mu2, k, l, e, m1, m2);
+      nm[u] = sW[k * ld + l] * m1 + sW[l * ld + k] * m2;
     }
   }
   __syncthreads();
@@ -265,15 +415,11 @@ __global__ __launch_bounds__(CG_NT) void ov_congruence_kernel(const OvCong* __re
     }
   }
   __syncthreads();
-  cg_mm<false, false>(sX, sW, n, ld, acc);  // Y1 = X Nm
-  __syncthreads();
-  cg_store(sW, n, ld, acc);
-  __syncthreads();
-  cg_mm<false, true>(sW, sX, n, ld, acc);  // Y2 = Y1 X^T
+  cg_mm<false, false>(sX, sW, n, ld, acc);  // XNm = X Nm
   for (int s = 0; s < CG_MAXT; ++s)
     for (int r = 0; r < 4; ++r) {
       int i, j;
-      if (cg_elem(n, s, r, i, j)) q.Y2[(size_t)i * n + j] = acc[s][r];
+      if (cg_elem(n, s, r, i, j)) q.XNm[(size_t)i * n + j] = acc[s][r];
     }
 }
 
@@ -381,9 +527,12 @@ __global__ __launch_bounds__(256) void bsr_spmm_kernel(BsrMat H, const double* _
 
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
-void launch_ov_spectral(const OvSpec* d, const int* d_begin, int n_inst, int total, const double* gl_t,
-                        const double* gl_w, hipStream_t s) {
-  if (total > 0) ov_spectral_kernel<<<nblk(total, 256), 256, 0, s>>>(d, d_begin, n_inst, total, gl_t, gl_w);
+void launch_ov_spectral(const OvSpec* d, const int* d_begin, int n_inst, int total_blocks, const double* gl_t,
+                        const double* gl_w, int want_exp, hipStream_t s) {
+  if (total_blocks > 0) ov_spectral_kernel<<<total_blocks, 256, 0, s>>>(d, d_begin, n_inst, gl_t, gl_w, want_exp);
+}
+void launch_ov_rot(const OvRot* d, const int* d_begin, int n_inst, int total, hipStream_t s) {
+  if (total > 0) ov_rot_kernel<<<nblk(total, 256), 256, 0, s>>>(d, d_begin, n_inst, total);
 }
 void launch_ov_rows(const OvRows* d, const int* d_begin, int n_inst, int total_rows, double U, hipStream_t s) {
   if (total_rows > 0) ov_rows_kernel<<<nblk(total_rows, 4), 256, 0, s>>>(d, d_begin, n_inst, total_rows, U);
