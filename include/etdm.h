@@ -141,6 +141,8 @@ typedef struct {
                              S^+-1/2); afterwards the handle works in that orthonormal basis.
                              ETDM_E_ARG if S is not positive definite to working accuracy
                              or with a block-sparse H0 */
+  int32_t want_rho;       /* 1: the handle also holds an M x M workspace per instance for
+                             etdm_density; 0: etdm_density returns ETDM_E_STATE */
 } etdm_desc;
 
 /* Create a handle.  H0: device, dense float64 (REAL_OV) or complex float64
@@ -164,6 +166,18 @@ etdm_status etdm_expm(etdm_handle *h, const void *A, void *U, void *stream);
  * instance; with `couple` the Hubbard energy is in the total only) followed
  * by the batch total. */
 etdm_status etdm_energy_grad(etdm_handle *h, const void *A, double *E, void *G, void *stream);
+
+/* Density matrix rho = C F C^dagger of the orbitals C = C0 exp(A) (Sec. 2, the
+ * definition of rho_mu_nu from the orbitals and their occupations), per instance.
+ * REAL_OV: rho = f_occ C_occ C_occ^T, a symmetric rank-N product on the matrix cores
+ * (row panels of the upper triangle, then mirrored), in the arithmetic of the
+ * contractions E depends on (etdm_precision); COMPLEX_FULL: rho_k = C_k diag(f_k) C_k^H
+ * per k-point (k-point weights not applied), FP64.  Only diag(rho) enters E and H(rho)
+ * of the model functional; this is the full matrix for inspection and comparison.
+ * A: device, parameter layout.  rho: device, M x M per instance packed back to back
+ * (float64 / complex float64), overwritten.  Needs desc.want_rho = 1 at creation
+ * (ETDM_E_STATE otherwise).  Asynchronous on `stream`. */
+etdm_status etdm_density(etdm_handle *h, const void *A, void *rho, void *stream);
 
 /* Replace the reference orbitals C0 <- C0 exp(A) (Sec. 3.4, reference update).
  * Erases the L-BFGS memory. */

@@ -429,6 +429,16 @@ def energy_grad_odd(wl, params, lam: float, printed_indices: bool = False) -> Tu
     return E, grads
 
 
+def density_matrices(wl, params) -> List[np.ndarray]:
+    """rho = C F C^dagger per instance, C = C0 exp(A) (Sec. 2, the density matrix of the
+    orbitals and their occupations; k-point weights not applied)."""
+    out = []
+    for inst, a in zip(wl.instances, params):
+        C = inst.C0 @ expm_eig(generator(wl.kind, a))
+        out.append((C * inst.f[None, :]) @ C.conj().T)
+    return out
+
+
 def unitary(wl, params) -> List[np.ndarray]:
     """exp(A) per instance (the etdm_expm output)."""
     return [expm_eig(generator(wl.kind, a)) for a in params]

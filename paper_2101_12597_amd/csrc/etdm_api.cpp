@@ -410,6 +410,18 @@ struct etdm_handle {
   Stage fr_M2, fr_M4, fr_M68, fr_LU, fr_N;  // sums of two products: one launch, two K segments (M6, M8 together)
   Stage fr_sq[2];     // per parity of the squaring step: L R + R L and R R in one launch
   Stage fr_Y[2];      // Y = L_s exp(A)^H, by the parity of s
+  // full density matrix output (etdm_density): workspace, the SYRK row panels (real)
+  // or the complex product, and the symmetric fill / column scaling descriptors
+  int want_rho = 0;
+  double* rho_ws = nullptr;
+  int64_t rho_doubles = 0;
+  Stage s_rho, z_rho;
+  SymFill* d_fill = nullptr;
+  int* b_fill = nullptr;
+  int tot_fill = 0;
+  ScaleCols* d_scale = nullptr;
+  int* b_scale = nullptr;
+  int tot_scale = 0;
   double odd_lam = 0.0;  // orbital-dependent model term (0: off)
   int has_overlap = 0;   // created from a non-orthogonal basis (H0, C0 Lowdin-transformed)
   Stage z_odd;           // W = VC^H C
@@ -633,6 +645,10 @@ size_t plan_buffers(etdm_handle* h, char* base) {
   h->Yv = pl.take(np * LB_MMAX);
   h->partial = pl.take(std::max<int64_t>(3 * LB_DOT_BLOCKS, h->n_inst));
   h->lb_st = reinterpret_cast<LbState*>(pl.take((sizeof(LbState) + 7) / 8));
+  h->rho_doubles = 0;
+  if (h->want_rho)
+    for (int i = 0; i < h->n_inst; ++i) h->rho_doubles += (real ? 1 : 2) * (int64_t)h->M[i] * h->M[i];
+  h->rho_ws = h->want_rho ? pl.take(h->rho_doubles) : nullptr;
   return pl.off;
 }
 
@@ -755,6 +771,10 @@ etdm_status build_ov_plan(etdm_handle* h) {
   h->s_Uov.init(OP_N, OP_N, GP_FP64);
   h->s_Uvv.init(OP_T, OP_N, GP_FP64);
   h->s_HC0.init(OP_N, OP_N, GP_FP64);
+  h->s_rho.init(OP_N, OP_T, ep);
+  std::vector<SymFill> fill;
+  std::vector<int> bfill;
+  int64_t rho_off = 0;
   std::vector<OvSpec> spec;
   std::vector<OvRot> rot;
   std::vector<OvRows> rows;
@@ -882,6 +902,19 @@ etdm_status build_ov_plan(etdm_handle* h) {
     (void)Fc;
     // preconditioner: H0 C0
     if (b.H0) h->s_HC0.add(prob(M, M, M, b.H0, M, b.C0, M, b.HC0, M));
+    // density output: rho = f_occ C_occ C_occ^T by row panels of the upper triangle
+    // (panel r: rows [r0, r0 + RB) against columns [r0, M)), then the symmetric fill
+    if (h->want_rho) {
+      constexpr int RB = 512;
+      double* rho = h->rho_ws + rho_off;
+      for (int r0 = 0; r0 < M; r0 += RB)
+        h->s_rho.add(prob(std::min(RB, M - r0), M - r0, N, b.Cocc + (size_t)r0 * N, N, b.Cocc + (size_t)r0 * N, N,
+                          rho + (size_t)r0 * M + r0, M, h->focc[i]));
+      fill.push_back(SymFill{rho, rho_off, M});
+      bfill.push_back(h->tot_fill);
+      h->tot_fill += ceil_div(M, 32) * ceil_div(M, 32);
+      rho_off += (int64_t)M * M;
+    }
   }
   h->n_eig_lds = (int)el.size();
   h->n_eig_glb = (int)eg.size();
@@ -939,8 +972,8 @@ etdm_status build_ov_plan(etdm_handle* h) {
     }
     h->timers[O_SCAN].bytes = 8.0 * h->n_param;
   }
-  Stage* stages[] = {&h->s_PQ,  &h->s_VF, &h->s_CXV, &h->s_C,  &h->s_V,   &h->s_Lov, &h->s_LV,
-                     &h->s_Gam, &h->s_XNm, &h->s_G,  &h->s_F3, &h->s_Uov, &h->s_Uvv, &h->s_HC0};
+  Stage* stages[] = {&h->s_PQ, &h->s_VF, &h->s_CXV, &h->s_C,  &h->s_V,   &h->s_Lov, &h->s_LV, &h->s_Gam,
+                     &h->s_XNm, &h->s_G, &h->s_F3,  &h->s_Uov, &h->s_Uvv, &h->s_HC0, &h->s_rho};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
   std::vector<Stage*> packable(stages, stages + sizeof(stages) / sizeof(stages[0]));
   if (!h->eig_large.empty()) {
@@ -976,6 +1009,8 @@ etdm_status build_ov_plan(etdm_handle* h) {
   CHECK(upload(h, &h->b_spec, bspec));
   CHECK(upload(h, &h->d_rot, rot));
   CHECK(upload(h, &h->b_rot, brot));
+  CHECK(upload(h, &h->d_fill, fill));
+  CHECK(upload(h, &h->b_fill, bfill));
   CHECK(upload(h, &h->d_rows, rows));
   CHECK(upload(h, &h->b_rows, brows));
   {
@@ -1031,6 +1066,11 @@ etdm_status build_z_plan(etdm_handle* h) {
   h->z_Y.init(OP_N, OP_N, GP_FP64, true);
   h->z_HC0.init(OP_N, OP_N, GP_FP64, true);
   h->z_odd.init(OP_C, OP_N, GP_FP64, true);
+  h->z_rho.init(OP_N, OP_C, GP_FP64, true);
+  std::vector<ScaleCols> scale;
+  std::vector<SymFill> fill;
+  std::vector<int> bscale, bfill;
+  int64_t rho_off = 0;
   for (Stage* st : {&h->ss_X2, &h->ss_X4, &h->ss_X68, &h->ss_U, &h->ss_sq0, &h->ss_sq1})
     st->init(OP_N, OP_N, GP_FP64, true);
   const bool ss_exact = h->expm_ss && !h->grad_approx;
@@ -1073,6 +1113,17 @@ etdm_status build_z_plan(etdm_handle* h) {
     zi.push_back(z);
     bmat.push_back(h->tot_mat);
     h->tot_mat += M * M;
+    if (h->want_rho) {
+      // rho_k = (C diag f) C^H: the scaled copy in W1 (free outside the gradient)
+      scale.push_back(ScaleCols{b.C, b.f, b.W1, M});
+      bscale.push_back(h->tot_scale);
+      h->tot_scale += M * M;
+      h->z_rho.add(prob(M, M, M, b.W1, M, b.C, M, h->rho_ws + rho_off, M));
+      fill.push_back(SymFill{h->rho_ws + rho_off, rho_off, M});
+      bfill.push_back(h->tot_fill);
+      h->tot_fill += ceil_div(M, 32) * ceil_div(M, 32);
+      rho_off += 2 * (int64_t)M * M;
+    }
     brows.push_back(h->tot_rows);
     h->tot_rows += M;
     if (M <= HT_MAX) {
@@ -1286,9 +1337,13 @@ etdm_status build_z_plan(etdm_handle* h) {
     }
     h->timers[Z_SS_FRECHET].flops += h->timers[Z_SS_SOLVE].flops;
   }
-  Stage* stages[] = {&h->z_Ue, &h->z_C, &h->z_T,   &h->z_HMO, &h->z_LV,  &h->z_Lt,
-                     &h->z_W1, &h->z_Y, &h->z_HC0, &h->z_HG,  &h->z_HNS, &h->z_odd};
+  Stage* stages[] = {&h->z_Ue, &h->z_C,   &h->z_T,  &h->z_HMO, &h->z_LV,  &h->z_Lt, &h->z_W1,
+                     &h->z_Y,  &h->z_HC0, &h->z_HG, &h->z_HNS, &h->z_odd, &h->z_rho};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
+  CHECK(upload(h, &h->d_scale, scale));
+  CHECK(upload(h, &h->b_scale, bscale));
+  CHECK(upload(h, &h->d_fill, fill));
+  CHECK(upload(h, &h->b_fill, bfill));
   for (int bk = 0; bk < h->herm_nblk; ++bk) {
     h->z_WY1[bk].init(OP_C, OP_N, GP_FP64, true);
     h->z_WY2[bk].init(OP_N, OP_N, GP_FP64, true);
@@ -2023,6 +2078,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (d->expm_method == 1 && d->kind != ETDM_COMPLEX_FULL) return ETDM_E_ARG;
   if (!std::isfinite(d->odd_lambda) || (d->odd_lambda != 0.0 && d->kind != ETDM_COMPLEX_FULL)) return ETDM_E_ARG;
   if (d->overlap && d->h0_format != 0) return ETDM_E_ARG;
+  if (d->want_rho != 0 && d->want_rho != 1) return ETDM_E_ARG;
   if (d->kind == ETDM_REAL_OV && (!d->N || d->couple)) return ETDM_E_ARG;
   if (d->h0_format != 0 && d->h0_format != 1) return ETDM_E_ARG;
   if (d->h0_format == 1 && (d->kind != ETDM_REAL_OV || d->bsr_block < 1 || d->bsr_block > BSR_MAX_BS ||
@@ -2048,6 +2104,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   h->expm_ss = d->expm_method;
   h->odd_lam = d->odd_lambda;
   h->has_overlap = d->overlap != nullptr;
+  h->want_rho = d->want_rho ? 1 : 0;
   h->U = d->hubbard_U;
   h->couple = d->couple ? 1 : 0;
   h->h0_format = d->h0_format;
@@ -2226,6 +2283,30 @@ etdm_status etdm_expm(etdm_handle* h, const void* A, void* U, void* stream) {
       HIPCHK(h, hipMemcpyAsync(u, h->zb[i].Ue, b, hipMemcpyDeviceToDevice, s));
       u += b;
     }
+  }
+  HIPCHK(h, hipGetLastError());
+  return ETDM_OK;
+}
+
+etdm_status etdm_density(etdm_handle* h, const void* A, void* rho, void* stream) {
+  if (!h) return ETDM_E_ARG;
+  if (!h->want_rho) return fail(h, ETDM_E_STATE, "the handle was created without want_rho");
+  if ((!A && h->n_param > 0) || !rho) return fail(h, ETDM_E_ARG, "null A or rho");
+  hipStream_t s = S(stream);
+  const size_t pb = (size_t)h->n_param * sizeof(double);
+  if (pb) HIPCHK(h, hipMemcpyAsync(h->par_ws, A, pb, hipMemcpyDeviceToDevice, s));
+  if (h->kind == ETDM_REAL_OV) {
+    ov_front_fallback(h, s);
+    ov_basis(h, s, 0);
+    ov_orbitals(h, s, false);
+    h->s_rho.launch(s);
+    launch_sym_fill(h->d_fill, h->b_fill, h->n_inst, h->tot_fill, static_cast<double*>(rho), 0, s);
+  } else {
+    z_exponential_part(h, s);
+    h->z_C.launch(s);
+    launch_scale_cols(h->d_scale, h->b_scale, h->n_inst, h->tot_scale, s);
+    h->z_rho.launch(s);
+    launch_sym_fill(h->d_fill, h->b_fill, h->n_inst, h->tot_fill, static_cast<double*>(rho), 1, s);
   }
   HIPCHK(h, hipGetLastError());
   return ETDM_OK;

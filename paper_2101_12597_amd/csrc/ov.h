@@ -57,6 +57,26 @@ struct OvRot {
 };
 void launch_ov_rot(const OvRot* d, const int* d_begin, int n_inst, int total, hipStream_t s);
 
+// Symmetric (Hermitian) fill of the density output: dst + dst_off (M x M) from the
+// upper triangle of src, dst[i][j] = src[i][j] for i <= j and conj(src[j][i]) below,
+// with a real diagonal (complex: interleaved pairs, offsets count doubles), in 32 x 32
+// tiles; begin = prefix sum of the ceil(M/32)^2 tiles of each instance.
+struct SymFill {
+  const double* src;
+  int64_t dst_off;
+  int32_t M;
+};
+void launch_sym_fill(const SymFill* d, const int* d_begin, int n_inst, int total_tiles, double* dst, int cplx,
+                     hipStream_t s);
+// out = C diag(f) (complex M x M, f real), one thread per element.
+struct ScaleCols {
+  const double* C;
+  const double* f;
+  double* out;
+  int32_t M;
+};
+void launch_scale_cols(const ScaleCols* d, const int* d_begin, int n_inst, int total, hipStream_t s);
+
 struct OvRows {
   const double* Cocc;  // [M x N]
   double* T;           // [M x N]: H0 Cocc in, H Cocc out

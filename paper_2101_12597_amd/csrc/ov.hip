@@ -213,6 +213,57 @@ __global__ void ov_rot_kernel(const OvRot* __restrict__ rots, const int* __restr
   if (q.HX) q.HX[e] = q.HX[e] * c - q.HV[e] * sn;
 }
 
+template <typename T>
+__device__ __forceinline__ T sf_conj(T v) { return v; }
+template <>
+__device__ __forceinline__ double2 sf_conj<double2>(double2 v) { return make_double2(v.x, -v.y); }
+template <typename T>
+__device__ __forceinline__ T sf_real(T v) { return v; }
+template <>
+__device__ __forceinline__ double2 sf_real<double2>(double2 v) { return make_double2(v.x, 0.0); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void sym_fill_kernel(const SymFill* __restrict__ fills,
+                                                       const int* __restrict__ begin, int n_inst,
+                                                       double* __restrict__ dst) {
+  __shared__ T tile[SP_TILE][SP_TILE + 1];
+  const int ii = find_range(begin, n_inst, blockIdx.x);
+  const SymFill& q = fills[ii];
+  const int M = q.M, nt = (M + SP_TILE - 1) / SP_TILE;
+  const int b = blockIdx.x - begin[ii];
+  const int bi = b / nt, bj = b - bi * nt;
+  const int lo = min(bi, bj), hi = max(bi, bj);
+  const int lc = threadIdx.x & (SP_TILE - 1), lr = threadIdx.x >> 5;
+  const T* src = reinterpret_cast<const T*>(q.src);
+  for (int r = lr; r < SP_TILE; r += 8) {  // the upper tile (lo, hi)
+    const int i = lo * SP_TILE + r, j = hi * SP_TILE + lc;
+    T v{};
+    if (i < M && j < M) v = src[(size_t)i * M + j];
+    tile[r][lc] = v;
+  }
+  __syncthreads();
+  T* out = reinterpret_cast<T*>(dst + q.dst_off);
+  for (int r = lr; r < SP_TILE; r += 8) {
+    const int i = bi * SP_TILE + r, j = bj * SP_TILE + lc;
+    if (i >= M || j >= M) continue;
+    const bool upper = bi < bj || (bi == bj && r <= lc);
+    const T v = upper ? tile[r][lc] : sf_conj(tile[lc][r]);
+    out[(size_t)i * M + j] = i == j ? sf_real(v) : v;
+  }
+}
+
+__global__ void scale_cols_kernel(const ScaleCols* __restrict__ sc, const int* __restrict__ begin, int n_inst,
+                                  int total) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int ii = find_range(begin, n_inst, idx);
+  const ScaleCols& q = sc[ii];
+  const int e = idx - begin[ii];
+  const double fk = q.f[e % q.M];
+  const double2 c = reinterpret_cast<const double2*>(q.C)[e];
+  reinterpret_cast<double2*>(q.out)[e] = make_double2(c.x * fk, c.y * fk);
+}
+
 // Row pass over the occupied orbitals: d_mu = f sum_i C_mu_i^2 (diagonal of rho),
 // e_mu = sum_i C_mu_i (H0 C)_mu_i, then T = H0 C + U diag(d) C in place.
 // One wavefront per row; lanes stride over columns, reduced in a fixed order.
@@ -533,6 +584,15 @@ void launch_ov_spectral(const OvSpec* d, const int* d_begin, int n_inst, int tot
 }
 void launch_ov_rot(const OvRot* d, const int* d_begin, int n_inst, int total, hipStream_t s) {
   if (total > 0) ov_rot_kernel<<<nblk(total, 256), 256, 0, s>>>(d, d_begin, n_inst, total);
+}
+void launch_sym_fill(const SymFill* d, const int* d_begin, int n_inst, int total_tiles, double* dst, int cplx,
+                     hipStream_t s) {
+  if (total_tiles <= 0) return;
+  if (cplx) sym_fill_kernel<double2><<<total_tiles, 256, 0, s>>>(d, d_begin, n_inst, dst);
+  else sym_fill_kernel<double><<<total_tiles, 256, 0, s>>>(d, d_begin, n_inst, dst);
+}
+void launch_scale_cols(const ScaleCols* d, const int* d_begin, int n_inst, int total, hipStream_t s) {
+  if (total > 0) scale_cols_kernel<<<nblk(total, 256), 256, 0, s>>>(d, d_begin, n_inst, total);
 }
 void launch_ov_rows(const OvRows* d, const int* d_begin, int n_inst, int total_rows, double U, hipStream_t s) {
   if (total_rows > 0) ov_rows_kernel<<<nblk(total_rows, 4), 256, 0, s>>>(d, d_begin, n_inst, total_rows, U);

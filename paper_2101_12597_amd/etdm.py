@@ -55,6 +55,7 @@ class _Desc(ctypes.Structure):
         ("expm_method", ctypes.c_int32),
         ("odd_lambda", ctypes.c_double),
         ("overlap", ctypes.c_void_p),
+        ("want_rho", ctypes.c_int32),
     ]
 
 
@@ -81,7 +82,7 @@ EXPORTS = [
     "etdm_create", "etdm_destroy", "etdm_expm", "etdm_energy_grad", "etdm_set_reference",
     "etdm_lbfgs_defaults", "etdm_lbfgs_step", "etdm_sync_status", "etdm_status_string",
     "etdm_last_error", "etdm_param_count", "etdm_set_timing", "etdm_reset_timing",
-    "etdm_stage_count", "etdm_stage_info", "etdm_stage_kernel", "etdm_set_graph",
+    "etdm_stage_count", "etdm_stage_info", "etdm_stage_kernel", "etdm_set_graph", "etdm_density",
 ]
 
 _lib = None
@@ -105,6 +106,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.etdm_expm.restype = i32
     L.etdm_energy_grad.argtypes = [vp, vp, vp, vp, vp]
     L.etdm_energy_grad.restype = i32
+    L.etdm_density.argtypes = [vp, vp, vp, vp]
+    L.etdm_density.restype = i32
     L.etdm_set_reference.argtypes = [vp, vp, vp]
     L.etdm_set_reference.restype = i32
     L.etdm_lbfgs_defaults.argtypes = [ctypes.POINTER(LbfgsParams)]
@@ -187,13 +190,14 @@ class Handle:
     odd_lambda : strength of the orbital-dependent model term (complex kind; 0 = off)
     overlap : device tensor, the overlap S of a non-orthogonal basis (layout of a dense H0),
               or None for an orthonormal basis
+    want_rho : also hold the workspace of density() (M x M per instance)
     """
 
     def __init__(self, M: Sequence[int], N: Optional[Sequence[int]], kind: str, precision: str,
                  hubbard_U: float, H0, C0, f: np.ndarray, couple: bool = False,
                  weights: Optional[Sequence[float]] = None, bsr=None, stream=None,
                  gemm_tuning: int = 0, gradient: str = "exact", expm: str = "eig",
-                 odd_lambda: float = 0.0, overlap=None):
+                 odd_lambda: float = 0.0, overlap=None, want_rho: bool = False):
         L = load_library()
         self._L = L
         n = len(M)
@@ -220,6 +224,7 @@ class Handle:
         d.expm_method = 1 if expm == "ss" else 0
         d.odd_lambda = float(odd_lambda)
         d.overlap = _dptr(overlap) if overlap is not None else None
+        d.want_rho = int(bool(want_rho))
         if bsr is not None:
             blk, rp, ci = bsr
             self._rp = np.ascontiguousarray(rp, dtype=np.int32)
@@ -260,6 +265,15 @@ class Handle:
     def expm(self, A, U, stream=None):
         self._check_param(A)
         self._check(self._L.etdm_expm(self._h, _dptr(A), _dptr(U), _stream_ptr(stream)), "etdm_expm")
+
+    def density(self, A, rho, stream=None):
+        """rho = C F C^dagger of C = C0 exp(A), M x M per instance packed (float64 units:
+        M^2 per real instance, 2 M^2 per complex one)."""
+        self._check_param(A)
+        n = sum((1 if self.kind == REAL_OV else 2) * int(m) * int(m) for m in self.M)
+        if rho.dtype.itemsize * rho.numel() != 8 * n:
+            raise ValueError(f"rho must hold {n} float64 units")
+        self._check(self._L.etdm_density(self._h, _dptr(A), _dptr(rho), _stream_ptr(stream)), "etdm_density")
 
     def set_reference(self, A, stream=None):
         self._check_param(A)

@@ -13,7 +13,7 @@ def torch_dev():
 
 
 def make_handle(wl, precision="fp64", use_bsr=False, gemm_tuning=0, gradient="exact", expm="eig",
-                odd_lambda=0.0):
+                odd_lambda=0.0, want_rho=False):
     torch, dev = torch_dev()
     from paper_2101_12597_amd import Handle
     pk = pack(wl, use_bsr=use_bsr)
@@ -22,7 +22,7 @@ def make_handle(wl, precision="fp64", use_bsr=False, gemm_tuning=0, gradient="ex
     S = torch.from_numpy(pk["S"]).to(dev) if pk.get("S") is not None else None
     h = Handle(pk["M"], pk["N"], wl.kind, precision, wl.hubbard_U, H0, C0, pk["f"],
                couple=wl.couple, weights=pk["weights"], bsr=pk["bsr"], gemm_tuning=gemm_tuning,
-               gradient=gradient, expm=expm, odd_lambda=odd_lambda, overlap=S)
+               gradient=gradient, expm=expm, odd_lambda=odd_lambda, overlap=S, want_rho=want_rho)
     torch.cuda.synchronize()
     return h, pk
 
@@ -45,6 +45,18 @@ def expm(h, wl, params):
     h.expm(A, U)
     h.sync_status()
     return unpack_square(wl, U.cpu().numpy())
+
+
+def density(h, wl, params):
+    """rho = C F C^dagger per instance through etdm_density, as host arrays."""
+    torch, dev = torch_dev()
+    A = torch.from_numpy(pack_params(wl, params)).to(dev)
+    cplx = wl.kind != "real_ov"
+    n = sum((2 if cplx else 1) * i.M * i.M for i in wl.instances)
+    rho = torch.empty(n, dtype=torch.float64, device=dev)
+    h.density(A, rho)
+    h.sync_status()
+    return unpack_square(wl, rho.cpu().numpy())
 
 
 def rel_err(a, b):

@@ -8,7 +8,7 @@ from oracle import scf
 from workloads import make_config, tiny_complex, tiny_real
 from workloads.pack import pack_params, unpack_params
 
-from gpu_helpers import make_handle
+from gpu_helpers import density, make_handle
 
 pytestmark = pytest.mark.gpu
 
@@ -28,13 +28,24 @@ def _run_lbfgs(h, wl, max_iter=333, gtol=1e-8):
 
 
 def test_config1_lbfgs_reaches_scf_minimum():
+    """Config 1 from A = 0 to |g| < 1e-8: the energy and the density matrix at the minimum
+    equal the Roothaan SCF fixed point (the minimizer A is not unique, rho is)."""
     wl = make_config(1)
     inst = wl.instances[0]
     rho0 = inst.C0 @ np.diag(inst.f) @ inst.C0.T
-    E_scf, _, _ = scf.scf_minimum(inst.H0, inst.N, 2.0, wl.hubbard_U, rho0)
+    E_scf, rho_scf, _ = scf.scf_minimum(inst.H0, inst.N, 2.0, wl.hubbard_U, rho0)
     print("[case] config1 L-BFGS fp64", flush=True)
-    h, _ = make_handle(wl, "fp64")
+    h, _ = make_handle(wl, "fp64", want_rho=True)
     info, A, E = _run_lbfgs(h, wl)
+    # the final A refers to the handle's current reference orbitals (after its resets):
+    # rho through etdm_density at that A
+    import torch
+    rho = torch.empty(64 * 64, dtype=torch.float64, device="cuda:0")
+    h.density(A, rho)
+    h.sync_status()
+    rho = rho.cpu().numpy().reshape(64, 64)
+    assert np.abs(rho - rho_scf).max() < 1e-7
+    assert np.abs(rho @ rho - 2.0 * rho).max() < 1e-12
     st, _ = LB.minimize(make_config(1))
     print(f"[result] gpu iters={info['iter']} evals={info['n_evals']} E={info['E']!r}; "
           f"oracle iters={st.n_iter} evals={st.n_evals} E={st.f!r}")
@@ -69,7 +80,6 @@ def test_autograd_function_matches_oracle_and_fd(kind):
     if kind == "complex":
         A = A.view(torch.complex128)
     A.requires_grad_(True)
-    E = etdm_energy(A.view(torch.float64) if kind == "complex" else A, h) if False else None
     # the Function works on the float64 parameter view; complex tensors go through view_as_real
     Af = A.detach().view(torch.float64).clone().requires_grad_(True) if kind == "complex" else A
     E = etdm_energy(Af, h)
@@ -98,4 +108,47 @@ def test_autograd_function_matches_oracle_and_fd(kind):
             return etdm_energy(torch.from_numpy(v).cuda(), h).item()
     fd = (Eat(vec + hstep * d) - Eat(vec - hstep * d)) / (2 * hstep)
     assert abs(fd - g @ d) < 1e-6 * max(1.0, abs(fd))
+    h.close()
+
+
+def test_autograd_config4_kpoint_batch_matches_oracle_and_fd():
+    """The autograd Function on a batch of k-points at the config 4 shape (8 of the 64
+    k-points, M = 208, complex, fractional occupations, k-coupled Hubbard density): its
+    backward gradient against the oracle's and against central differences of the GPU
+    energy along random directions of the free variables."""
+    import torch
+    from paper_2101_12597_amd import etdm_energy
+    wl = make_config(4, nk=8)
+    wl.instances = wl.instances[:8]
+    params = O.parity_params(wl)
+    print("[case] autograd config 4, 8 k-points", flush=True)
+    h, _ = make_handle(wl, "fp64")
+    vec = pack_params(wl, params)
+    Af = torch.from_numpy(vec).cuda().requires_grad_(True)
+    E = etdm_energy(Af, h)
+    E.backward()
+    g = Af.grad.detach().cpu().numpy()
+    E_ref, g_ref = O.energy_grad(wl, params)
+    g_ref_vec = pack_params(wl, g_ref)
+    assert abs(E.item() - E_ref) < 1e-12 * abs(E_ref)
+    assert np.linalg.norm(g - g_ref_vec) < 1e-10 * np.linalg.norm(g_ref_vec)
+    M = wl.instances[0].M
+    mask = np.zeros((M, M, 2))
+    iu = np.triu_indices(M, 1)
+    mask[iu[0], iu[1], 0] = 1.0
+    iu0 = np.triu_indices(M, 0)
+    mask[iu0[0], iu0[1], 1] = 1.0
+    mask = np.tile(mask.ravel(), len(wl.instances))
+    rng = np.random.default_rng(4)
+    hstep = 1e-4
+
+    def Eat(v):
+        with torch.no_grad():
+            return etdm_energy(torch.from_numpy(v).cuda(), h).item()
+    for _ in range(3):
+        d = rng.standard_normal(vec.size) * mask
+        d /= np.linalg.norm(d)
+        fd = (Eat(vec + hstep * d) - Eat(vec - hstep * d)) / (2 * hstep)
+        # truncation of order h^2 times the third derivative, rounding of order eps |E| / h
+        assert abs(fd - g @ d) < 1e-6 * max(1.0, abs(fd)), (fd, g @ d)
     h.close()

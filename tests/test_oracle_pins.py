@@ -611,6 +611,43 @@ def test_structured_ov_equals_dense_at_large_angles(M, N, scale):
     assert np.abs(g - g2).max() < 1e-11 * np.abs(g).max()
 
 
+@pytest.mark.parametrize("case", ["real", "complex"])
+def test_density_matrix_properties(case):
+    """rho = C F C^dagger: Hermitian, its eigenvalues are the occupations (C is unitary),
+    its trace is the electron count, its diagonal is the site density of the energy, and
+    E = Tr(rho H0) + (U/2) sum diag(rho)^2 equals the oracle's energy."""
+    wl = tiny_real(11, 4, seed=21, scale=0.6) if case == "real" else tiny_complex(7, nk_side=2, kT=0.3)
+    if case == "complex":
+        wl.hubbard_U = 0.5
+        wl.couple = False
+    p = O.parity_params(wl)
+    rhos = O.density_matrices(wl, p)
+    E = 0.0
+    for inst, rho in zip(wl.instances, rhos):
+        assert np.abs(rho - rho.conj().T).max() < 1e-14
+        ev = np.sort(np.linalg.eigvalsh(rho))
+        assert np.abs(ev - np.sort(inst.f)).max() < 1e-13
+        assert abs(np.trace(rho).real - inst.f.sum()) < 1e-13
+        d = np.real(np.diag(rho))
+        E += inst.weight * float(np.real(np.sum(rho.T * inst.h0_dense()))) + 0.5 * wl.hubbard_U * float((d ** 2).sum())
+    assert abs(E - O.energy(wl, p)) < 1e-12 * abs(E)
+    # at A = 0 the reference density
+    z = O.zero_params(wl)
+    for inst, rho in zip(wl.instances, O.density_matrices(wl, z)):
+        assert np.abs(rho - (inst.C0 * inst.f) @ inst.C0.conj().T).max() < 1e-15
+
+
+def test_density_matrix_of_one_rotation_by_hand():
+    """M = 2, N = 1, f = (2, 0), C0 = I, B = [[theta]]: C = [[cos, sin], [-sin, cos]], so
+    rho = 2 [[cos^2, -cos sin], [-cos sin, sin^2]]."""
+    th = 0.7
+    inst = Instance(M=2, N=1, f=np.array([2.0, 0.0]), C0=np.eye(2), A=np.array([[th]]), H0=np.eye(2))
+    wl = Workload(0, "2-level", "real_ov", 0.0, False, [inst])
+    (rho,) = O.density_matrices(wl, [np.array([[th]])])
+    c, s_ = np.cos(th), np.sin(th)
+    assert np.abs(rho - 2.0 * np.array([[c * c, -c * s_], [-c * s_, s_ * s_]])).max() < 1e-15
+
+
 # ---------------------------------------------------------------------------
 # minima
 # ---------------------------------------------------------------------------
