@@ -343,6 +343,11 @@ size_t eigh_large_workspace(int n, size_t* npad_out) {
          3 * (size_t)n;
 }
 
+// dynamic LDS of the reduction kernels: more than half of a CU's LDS, so that no two
+// workgroups share a CU
+static size_t tb_reduce_lds(int n) { return std::max<size_t>(sizeof(double) * 4 * (size_t)n, 96 * 1024); }
+static void tb_cap_grid(EighLarge& e, int cu_count);
+
 void eigh_large_layout(EighLarge& e, double* ws, EighLargeState* st, int cu_count) {
   size_t npad = 0;
   eigh_large_workspace(e.n, &npad);
@@ -373,6 +378,7 @@ void eigh_large_layout(EighLarge& e, double* ws, EighLargeState* st, int cu_coun
   e.bb = reinterpret_cast<int*>(e.bhi + n);
   e.st = st;
   e.grid = std::max(1, std::min(std::min(cu_count, n / 8), 64 * TB_GRP));
+  tb_cap_grid(e, cu_count);
 }
 
 // workgroup sum of TB_NT threads, returned to every thread
@@ -1007,7 +1013,11 @@ __global__ __launch_bounds__(256) void tb_orth_scan(EighLarge e) {
 }
 
 // Residual of the accepted result against sym(P): max |R - X diag(w)| (R = sym(P) X
-// in Aw) into scan[1], ||sym(P)||_F^2 partial sums into scan[2].
+// in Aw) into scan[1] (a max: exact in any order); the partial sums of ||sym(P)||_F^2
+// into partial[block], summed in a fixed order by tb_decide, so that the accept-or-
+// fall-back decision does not depend on the order the workgroups finish in.
+constexpr int TB_RES_BLOCKS = 256;  // <= PREP_BLOCKS: the partials share the Jacobi scratch
+static_assert(TB_RES_BLOCKS <= PREP_BLOCKS, "residual partials exceed the scratch");
 __global__ __launch_bounds__(256) void tb_res_scan(EighLarge e) {
   __shared__ double red[4];
   if (!*e.ok) return;
@@ -1022,7 +1032,7 @@ __global__ __launch_bounds__(256) void tb_res_scan(EighLarge e) {
   f = block_sum<256>(f, red);
   if (threadIdx.x == 0) {
     atomicMax(reinterpret_cast<unsigned long long*>(e.scan) + 1, (unsigned long long)__double_as_longlong(r));
-    atomicAdd(e.scan + 2, f);
+    e.partial[blockIdx.x] = f;
   }
 }
 
@@ -1034,7 +1044,9 @@ __global__ void tb_decide(EighLarge e, int which) {
   if (which == 0) {
     if (!(__longlong_as_double((long long)b[0]) <= 1e-6)) *e.ok = 0;
   } else {
-    if (!(__longlong_as_double((long long)b[1]) <= 1e-11 * sqrt(e.scan[2]))) *e.ok = 0;
+    double f = 0.0;
+    for (int q = 0; q < TB_RES_BLOCKS; ++q) f += e.partial[q];
+    if (!(__longlong_as_double((long long)b[1]) <= 1e-11 * sqrt(f))) *e.ok = 0;
   }
 }
 
@@ -1078,21 +1090,47 @@ __global__ __launch_bounds__(256) void tb_wy_t(EighLarge e) {
   }
 }
 
+// rows in registers when they fit: n <= TR_NT TR_Q columns, <= TR_R rows per workgroup
+static bool tb_use_reg(const EighLarge& e) {
+  return e.n <= TR_NT * TR_Q && e.grid > 0 && (e.n + e.grid - 1) / e.grid <= TR_R;
+}
+
+// The reduction's grid barrier needs every workgroup resident at once: cap the grid at
+// what the occupancy of the kernel to be launched allows on cu_count CUs (0 when it
+// cannot run at all: then only the block Jacobi solver runs).
+static void tb_cap_grid(EighLarge& e, int cu_count) {
+  const bool reg = tb_use_reg(e);
+  const size_t lds = tb_reduce_lds(e.n);
+  // the dynamic LDS above the default limit must be allowed before the query
+  hipFuncSetAttribute(reg ? reinterpret_cast<const void*>(&tb_reduce_reg) : reinterpret_cast<const void*>(&tb_reduce),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                   reg ? reinterpret_cast<const void*>(&tb_reduce_reg)
+                                                       : reinterpret_cast<const void*>(&tb_reduce),
+                                                   reg ? TR_NT : TB_NT, lds) != hipSuccess)
+    per_cu = 0;
+  const int cap = std::max(per_cu, 0) * cu_count;
+  if (e.grid > cap) {
+    e.grid = cap;
+    // fewer workgroups can move the register path past its rows-per-workgroup limit
+    if (e.grid > 0 && reg && !tb_use_reg(e)) tb_cap_grid(e, cu_count);
+  }
+}
+
 void launch_tb_orth_check(const EighLarge& e, hipStream_t s) {
   tb_orth_scan<<<256, 256, 0, s>>>(e);
   tb_decide<<<1, 64, 0, s>>>(e, 0);
 }
 
 void launch_tb_final_check(const EighLarge& e, hipStream_t s) {
-  tb_res_scan<<<256, 256, 0, s>>>(e);
+  tb_res_scan<<<TB_RES_BLOCKS, 256, 0, s>>>(e);
   tb_decide<<<1, 64, 0, s>>>(e, 1);
 }
 
 void launch_tb_reduce(const EighLarge& e, hipStream_t s) {
   const int n = e.n;
-  const size_t red_lds = sizeof(double) * 4 * (size_t)n;
-  // more than half of a CU's LDS, so that no two workgroups share a CU
-  const size_t lds = std::max<size_t>(red_lds, 96 * 1024);
+  const size_t lds = tb_reduce_lds(n);
   const size_t eig_lds = sizeof(double) * 3 * (size_t)n;
   static size_t attr_r = 0, attr_e = 0;
   if (lds > attr_r) {
@@ -1114,8 +1152,8 @@ void launch_tb_reduce(const EighLarge& e, hipStream_t s) {
     attr_g = lds;
   }
   tb_init<<<1, 256, 0, s>>>(e);
-  // rows in registers when they fit: n <= TR_NT TR_Q columns, <= TR_R rows per workgroup
-  if (n <= TR_NT * TR_Q && (n + e.grid - 1) / e.grid <= TR_R)
+  if (e.grid < 1) return;  // no resident grid possible: *ok stays 0, the Jacobi solver runs
+  if (tb_use_reg(e))
     tb_reduce_reg<<<e.grid, TR_NT, lds, s>>>(e);
   else
     tb_reduce<<<e.grid, TB_NT, lds, s>>>(e);
