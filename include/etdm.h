@@ -179,6 +179,28 @@ etdm_status etdm_energy_grad(etdm_handle *h, const void *A, double *E, void *G, 
  * (ETDM_E_STATE otherwise).  Asynchronous on `stream`. */
 etdm_status etdm_density(etdm_handle *h, const void *A, void *rho, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): etdm_energy_grad for ONE real
+ * occupied-virtual instance with a dense H0, in FP64, without a handle.  Every
+ * intermediate and every launch descriptor lives in a library-owned static device
+ * array of ETDM_STATIC_SCRATCH_BYTES (one per GPU, held until the process ends); the
+ * call allocates nothing and may be captured in a HIP graph.
+ * Sizes: 1 <= N < M <= ETDM_STATIC_MAX_M and N <= ETDM_STATIC_MAX_N, else ETDM_E_SHAPE.
+ * H0, C0: device, M x M float64 (H0 symmetric, C0 orthogonal, occupied columns first).
+ * B: device, N x (M - N), the parameters of A = [[0, B], [-B^T, 0]].  f_occ: occupation
+ * of the first N orbitals (the others are empty).  E: device [2] = the energy and the
+ * total (equal for one instance).  G: device N x (M - N), dE/dB.  status: device int32,
+ * cleared by the call, then ORed with 1 (eigensolver sweep limit) and 2 (non-finite E
+ * or G).  Asynchronous on `stream`.  Calls on one GPU share its array and overwrite
+ * it: calls that overlap in time on one GPU (other streams, other threads) race, so
+ * the caller must order them. */
+#define ETDM_STATIC_SCRATCH_BYTES (4 << 20)
+#define ETDM_STATIC_MAX_M 400
+#define ETDM_STATIC_MAX_N 88
+etdm_status etdm_energy_grad_static(int32_t M, int32_t N, double f_occ, double hubbard_U, const double *H0,
+                                    const double *C0, const double *B, double *E, double *G,
+                                    int32_t *status, void *stream);
+
 /* Replace the reference orbitals C0 <- C0 exp(A) (Sec. 3.4, reference update).
  * Erases the L-BFGS memory. */
 etdm_status etdm_set_reference(etdm_handle *h, const void *A, void *stream);

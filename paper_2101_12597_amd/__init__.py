@@ -13,6 +13,7 @@ from .etdm import (  # noqa: F401
     EtdmError,
     Handle,
     LbfgsParams,
+    energy_grad_static,
     etdm_energy,
     lbfgs_defaults,
     load_library,

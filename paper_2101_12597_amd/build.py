@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libetdm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["gemm.hip", "gemm_split.hip", "eigh.hip", "eigh_large.hip", "ov.hip", "full.hip", "lbfgs.hip", "expm_ss.hip", "overlap.hip",
+SOURCES = ["gemm.hip", "gemm_split.hip", "eigh.hip", "eigh_large.hip", "ov.hip", "full.hip", "lbfgs.hip", "expm_ss.hip", "overlap.hip", "noalloc.hip",
            "etdm_api.cpp"]
 
 COMMON_FLAGS = [

@@ -83,6 +83,7 @@ EXPORTS = [
     "etdm_lbfgs_defaults", "etdm_lbfgs_step", "etdm_sync_status", "etdm_status_string",
     "etdm_last_error", "etdm_param_count", "etdm_set_timing", "etdm_reset_timing",
     "etdm_stage_count", "etdm_stage_info", "etdm_stage_kernel", "etdm_set_graph", "etdm_density",
+    "etdm_energy_grad_static",
 ]
 
 _lib = None
@@ -106,6 +107,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.etdm_expm.restype = i32
     L.etdm_energy_grad.argtypes = [vp, vp, vp, vp, vp]
     L.etdm_energy_grad.restype = i32
+    L.etdm_energy_grad_static.argtypes = [i32, i32, dbl, dbl, vp, vp, vp, vp, vp, vp, vp]
+    L.etdm_energy_grad_static.restype = i32
     L.etdm_density.argtypes = [vp, vp, vp, vp]
     L.etdm_density.restype = i32
     L.etdm_set_reference.argtypes = [vp, vp, vp]
@@ -150,6 +153,24 @@ def lbfgs_defaults() -> LbfgsParams:
     p = LbfgsParams()
     load_library().etdm_lbfgs_defaults(ctypes.byref(p))
     return p
+
+
+def energy_grad_static(M: int, N: int, f_occ: float, hubbard_U: float, H0, C0, B, E, G, status,
+                       stream=None) -> None:
+    """etdm_energy_grad_static: E and dE/dB of one real occupied-virtual instance (dense
+    H0, FP64) with every intermediate in the library's static device array (no handle, no
+    allocation).  H0, C0: M x M float64; B, G: N x (M - N) float64; E: 2 float64 (the
+    energy and the total); status: 1 int32 (0, or 1 eigensolver / 2 non-finite bits)."""
+    import torch
+    L = load_library()
+    for t, n, dt in ((H0, M * M, torch.float64), (C0, M * M, torch.float64), (B, N * (M - N), torch.float64),
+                     (G, N * (M - N), torch.float64), (E, 2, torch.float64), (status, 1, torch.int32)):
+        if t.dtype != dt or t.numel() != n:
+            raise ValueError(f"expected {n} elements of {dt}, got {t.numel()} of {t.dtype}")
+    st = L.etdm_energy_grad_static(int(M), int(N), float(f_occ), float(hubbard_U), _dptr(H0), _dptr(C0), _dptr(B),
+                                   _dptr(E), _dptr(G), _dptr(status), _stream_ptr(stream))
+    if st != 0:
+        raise EtdmError(st, "etdm_energy_grad_static")
 
 
 def _stream_ptr(stream) -> int:
