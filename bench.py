@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--cpu-only", action="store_true", help="time the oracle only (no GPU work)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="BLAS threads of the oracle (0: all)")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-parity", action="store_true",
+                    help="skip the oracle (parity and CPU baseline), e.g. for profiling runs")
     ap.add_argument("--lbfgs-iters", type=int, default=None,
                     help="also time this many L-BFGS iterations (default 3 on config 5, else 0)")
     ap.add_argument("--lbfgs-reset-norm", type=float, default=0.0,
@@ -368,12 +370,19 @@ def main():
     h.sync_status()
     E_gpu = E.cpu().numpy()
     g_gpu = unpack_params(wl, G.cpu().numpy())
-    log("oracle reference")
-    with blas_limit(args.cpu_threads):
-        oracle_threads = blas_threads()
-        Es, gs, t_oracle, route = oracle_reference(wl, params, args.gradient, args.expm, args.odd_lambda,
-                                                   progress=log if cfg == 5 else None)
-    if wl.couple or len(Es) == 1 and len(wl.instances) > 1:
+    if args.no_parity:
+        dE = dg = de = None
+        route = None
+        args.no_cpu_baseline = True
+    else:
+        log("oracle reference")
+        with blas_limit(args.cpu_threads):
+            oracle_threads = blas_threads()
+            Es, gs, t_oracle, route = oracle_reference(wl, params, args.gradient, args.expm, args.odd_lambda,
+                                                       progress=log if cfg == 5 else None)
+    if args.no_parity:
+        pass
+    elif wl.couple or len(Es) == 1 and len(wl.instances) > 1:
         dE = abs(E_gpu[-1] - Es[0]) / wl.n_electrons
         g_all, r_all = np.concatenate([x.ravel() for x in g_gpu]), np.concatenate([x.ravel() for x in gs])
         dg = float(np.linalg.norm(g_all - r_all) / np.linalg.norm(r_all))

@@ -254,7 +254,7 @@ struct OvBuf {
   BsrMat H0_bsr;   // block-sparse H0 (h0_format = 1; then H0 is null)
   int64_t bsr_nnz; // stored entries of H0_bsr
   double *P, *X, *s, *fac, *XT, *XsnT, *tab, *Xcsw, *F3, *mu1, *mu2;
-  double *V, *sincP, *CX, *CV, *Cocc, *Cvirt, *T, *d, *e, *Lov, *LV, *Gam, *Nm, *XNm;
+  double *V, *sincP, *CX, *CV, *Cocc, *Cvirt, *T, *d, *e, *Lov, *TCV, *LV, *Gam, *Nm, *XNm;
   double *HC0, *n0, *eps;
   double *HX, *HV;  // dense H0: (H0 C0)_o X and (H0 C0)_v V^T (HC0 is kept for the current C0)
 };
@@ -284,12 +284,13 @@ struct StageTimer {
 
 // stage indices of the two paths
 enum OvStage { O_PQ, O_EIGL, O_EIGG, O_SPEC, O_VF, O_CXV, O_ROT, O_C, O_T, O_V, O_ROWS, O_ENERGY, O_LOV, O_LV,
-               O_CONG, O_GAM, O_PAIR, O_XNM, O_G, O_SCAN, O_COUNT };
-const char* kOvNames[O_COUNT] = {"gemm_P",      "eigh_lds",      "eigh_global", "spectral",
+               O_CONG, O_GAM, O_PAIR, O_XNM, O_G, O_SCAN, O_EIGP, O_EIGB, O_COUNT };
+const char* kOvNames[O_COUNT] = {"gemm_P",      "eigh_lds",      "eigh_reduce", "spectral",
                                  "gemm_V_funcs", "gemm_CXV",     "eigenbasis_combine", "gemm_Cocc",
-                                 "gemm_H0C",    "gemm_Cvirt",    "rows_density_hubbard", "energy_reduce",
+                                 "gemm_H0C",    "gemm_TC",       "rows_density_hubbard", "energy_reduce",
                                  "gemm_Lov",    "gemm_LV",       "ov_congruence", "gemm_Gam",
-                                 "pair_hadamard", "gemm_XNm",    "gemm_grad",   "nonfinite_scan"};
+                                 "pair_hadamard", "gemm_XNm",    "gemm_grad",   "nonfinite_scan",
+                                 "eigh_tridiag_pairs", "eigh_backtransform"};
 enum ZStage { Z_IA, Z_EIG, Z_PHASE, Z_UE, Z_C, Z_T, Z_ROWS, Z_HUBN, Z_APPLY, Z_ENERGY, Z_HMO, Z_COMM, Z_LV, Z_LT,
               Z_DD, Z_W1, Z_Y, Z_GRAD, Z_SS_SCALE, Z_SS_PADE, Z_SS_SOLVE, Z_SS_SQUARE, Z_SS_FRECHET, Z_ODD, Z_COUNT };
 const char* kZNames[Z_COUNT] = {"z_build_iA", "z_eigh",   "z_phase",  "zgemm_expA", "zgemm_C",   "zgemm_H0C",
@@ -353,12 +354,8 @@ struct etdm_handle {
   int tot_prec = 0;
   C0Inst* d_c0up = nullptr;
   // grouped GEMM launches
-  Stage s_PQ, s_VF, s_CXV, s_C, s_V, s_Lov, s_LV, s_Gam, s_XNm, s_G;  // real: energy+gradient
-  // C_virt runs on a side stream beside C_occ, the rows and the energy (forked and
-  // joined by events)
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;
-  Stage s_F3, s_Uov, s_Uvv, s_HC0;  // real: expm, preconditioner
+  Stage s_PQ, s_VF, s_CXV, s_C, s_TC, s_Lov, s_LV, s_Gam, s_XNm, s_G;  // real: energy+gradient
+  Stage s_V, s_F3, s_Uov, s_Uvv, s_HC0;  // real: C_virt (reference update), expm, preconditioner
   Stage z_Ue, z_C, z_T, z_HMO, z_LV, z_Lt, z_W1, z_Y, z_HC0;                   // complex
   // L-BFGS: scalars and decisions in lb_st (device); the host keeps the iteration
   // and evaluation counts and reads lb_sum (pinned) once per line-search probe
@@ -419,6 +416,10 @@ struct etdm_handle {
   SymFill* d_fill = nullptr;
   int* b_fill = nullptr;
   int tot_fill = 0;
+  // P = B B^T by row panels of the upper triangle (large N): its mirror, in place
+  SymFill* d_pfill = nullptr;
+  int* b_pfill = nullptr;
+  int tot_pfill = 0, n_pfill = 0;
   ScaleCols* d_scale = nullptr;
   int* b_scale = nullptr;
   int tot_scale = 0;
@@ -566,6 +567,7 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       b.d = pl.take(M);
       b.e = pl.take(M);
       b.Lov = pl.take(N * Nv);
+      b.TCV = pl.take(N * N);
       b.LV = pl.take(N * N);
       b.Gam = pl.take(N * N);
       b.Nm = pl.take(N * N);
@@ -745,7 +747,7 @@ etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
 // ----- plan of the real occupied-virtual path ------------------------------
 // Every product after the eigendecomposition is taken in the eigenbasis of P (see
 // ov.hip): V = X^T B, CX = C0_o X, CV = C0_v V^T, then the combination kernel and
-// C_occ = CX' X^T, C_virt = C0_v + CV' V, and on the gradient side LV = L_ov V^T,
+// C_occ = CX' X^T, L_ov = w f (T^T C0_v + (T^T CV') V), and on the gradient side LV = L_ov V^T,
 // Gam = X^T LV, XNm = X Nm, dE/dB = -2 (sinc sqrt(P) L_ov + XNm V).
 etdm_status build_ov_plan(etdm_handle* h) {
   // precision by role: ep for the contractions E depends on, gp for the gradient-only
@@ -762,7 +764,8 @@ etdm_status build_ov_plan(etdm_handle* h) {
   h->s_CXV.init(OP_N, OP_T, ep);
   h->s_C.init(OP_N, OP_T, ep);
   h->s_V.init(OP_N, OP_N, gp);
-  h->s_Lov.init(OP_T, OP_N, gp);
+  h->s_TC.init(OP_T, OP_N, gp);
+  h->s_Lov.init(OP_N, OP_N, gp);
   h->s_LV.init(OP_N, OP_T, gp);
   h->s_Gam.init(OP_T, OP_N, gp);
   h->s_XNm.init(OP_N, OP_N, gp);
@@ -772,8 +775,8 @@ etdm_status build_ov_plan(etdm_handle* h) {
   h->s_Uvv.init(OP_T, OP_N, GP_FP64);
   h->s_HC0.init(OP_N, OP_N, GP_FP64);
   h->s_rho.init(OP_N, OP_T, ep);
-  std::vector<SymFill> fill;
-  std::vector<int> bfill;
+  std::vector<SymFill> fill, pfill;
+  std::vector<int> bfill, bpfill;
   int64_t rho_off = 0;
   std::vector<OvSpec> spec;
   std::vector<OvRot> rot;
@@ -790,8 +793,19 @@ etdm_status build_ov_plan(etdm_handle* h) {
     const double* Fc = b.F3;
     const double* Fs = b.F3 + (size_t)N * N;
     const double* Wm = b.F3 + 2 * (size_t)N * N;
-    // P = B B^T
-    h->s_PQ.add(prob(N, N, Nv, b.B, Nv, b.B, Nv, b.P, N));
+    // P = B B^T; for large N only the row panels of the upper triangle, mirrored after
+    // the product (the eigensolvers read both triangles)
+    if (N >= 512) {
+      constexpr int RB = 512;
+      for (int r0 = 0; r0 < N; r0 += RB)
+        h->s_PQ.add(prob(std::min(RB, N - r0), N - r0, Nv, b.B + (size_t)r0 * Nv, Nv, b.B + (size_t)r0 * Nv, Nv,
+                         b.P + (size_t)r0 * N + r0, N));
+      pfill.push_back(SymFill{b.P, (int64_t)(b.P - reinterpret_cast<double*>(h->base)), N});
+      bpfill.push_back(h->tot_pfill);
+      h->tot_pfill += ceil_div(N, 32) * ceil_div(N, 32);
+    } else {
+      h->s_PQ.add(prob(N, N, Nv, b.B, Nv, b.B, Nv, b.P, N));
+    }
     // P = X diag(s) X^T
     if (N <= EIGH_LDS_MAX) {
       el.push_back(EighProb{b.P, b.X, b.s, N, 1});
@@ -859,8 +873,9 @@ etdm_status build_ov_plan(etdm_handle* h) {
     rot.push_back(OvRot{b.CX, b.CV, b.HX, b.HV, b.fac, M, N});
     brot.push_back(h->tot_rot);
     h->tot_rot += M * N;
-    // C_occ = CX' X^T (dense H0: T = H0 C_occ = HX' X^T in the same launch),
-    // C_virt = C0_v + CV' V
+    // C_occ = CX' X^T (dense H0: T = H0 C_occ = HX' X^T in the same launch);
+    // C_virt = C0_v + CV' V is formed only for a reference update (L_ov below does
+    // not need it)
     h->s_C.add(prob(M, N, N, b.CX, N, b.X, N, b.Cocc, N));
     if (b.H0) h->s_C.add(prob(M, N, N, b.HX, N, b.X, N, b.T, N));
     h->s_V.add(with_addend(prob(M, Nv, N, b.CV, N, b.V, Nv, b.Cvirt, Nv), b.C0 + N, M, 1.0));
@@ -869,12 +884,18 @@ etdm_status build_ov_plan(etdm_handle* h) {
     brows.push_back(h->tot_rows);
     h->tot_rows += M;
     en.push_back(OvEnergy{b.d, b.e, M, h->focc[i], h->w[i]});
+    // L_ov = w f_occ T^T C_virt (the weight makes this the gradient of w E) without
+    // C_virt: T^T C_virt = T^T C0_v + (T^T CV') V, so T^T [C0_v | CV'] (one launch,
+    // into Lov and TCV), then L_ov = w f_occ (TCV V + T^T C0_v)
+    h->s_TC.add(prob(N, Nv, M, b.T, N, b.C0 + N, M, b.Lov, Nv));
+    h->s_TC.add(prob(N, N, M, b.T, N, b.CV, N, b.TCV, N));
     if (h->grad_approx) {
       // G ~ L^T (Eq. app_grad): g = -2 L_ov, straight from the L_ov product
-      h->s_Lov.add(prob(N, Nv, M, b.T, N, b.Cvirt, Nv, b.G, Nv, -2.0 * h->w[i] * h->focc[i]));
+      const double a = -2.0 * h->w[i] * h->focc[i];
+      h->s_Lov.add(with_addend(prob(N, Nv, N, b.TCV, N, b.V, Nv, b.G, Nv, a), b.Lov, Nv, a));
     } else {
-      // L_ov = w f_occ T^T C_virt (the weight makes this the gradient of w E)
-      h->s_Lov.add(prob(N, Nv, M, b.T, N, b.Cvirt, Nv, b.Lov, Nv, h->w[i] * h->focc[i]));
+      const double a = h->w[i] * h->focc[i];
+      h->s_Lov.add(with_addend(prob(N, Nv, N, b.TCV, N, b.V, Nv, b.Lov, Nv, a), b.Lov, Nv, a));
       // LV = L_ov V^T; Gam = X^T LV, Nm = Gam o mu1 + Gam^T o mu2, XNm = X Nm: one
       // workgroup per instance where X fits the LDS, else grouped GEMMs around the
       // pair kernel
@@ -927,7 +948,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
     gs[O_VF] = &h->s_VF;
     gs[O_CXV] = &h->s_CXV;
     gs[O_C] = &h->s_C;
-    gs[O_V] = &h->s_V;
+    gs[O_V] = &h->s_TC;
     gs[O_LOV] = &h->s_Lov;
     gs[O_LV] = &h->s_LV;
     gs[O_GAM] = &h->s_Gam;
@@ -943,9 +964,23 @@ etdm_status build_ov_plan(etdm_handle* h) {
       h->timers[O_EIGL].flops += 9.0 * e.n * (double)e.n * e.n;
       h->timers[O_EIGL].bytes += 16.0 * e.n * (double)e.n + 8.0 * e.n;
     }
+    // the large solver in three stages: the reduction to tridiagonal form (4/3 n^3, P
+    // read and T written), the eigenpairs of T (O(n^2): the vectors written), and the
+    // back-transform with its checks (the GEMMs' own counts)
     for (const EighLarge& e : h->eig_large) {
-      h->timers[O_EIGG].flops += 9.0 * e.n * (double)e.n * e.n;
-      h->timers[O_EIGG].bytes += 16.0 * e.n * (double)e.n + 8.0 * e.n;
+      const double n = e.n;
+      h->timers[O_EIGG].flops += 4.0 / 3.0 * n * n * n;
+      h->timers[O_EIGG].bytes += 8.0 * n * n + 16.0 * n;
+      h->timers[O_EIGP].bytes += 8.0 * n * n + 24.0 * n;
+    }
+    {
+      std::vector<const Stage*> bt = {&h->s_LG, &h->s_LNS, &h->s_LR, &h->s_LGram};
+      for (size_t bk = 0; bk < h->s_LWY1.size(); ++bk)
+        for (const Stage* st : {&h->s_LWY1[bk], &h->s_LWY2[bk], &h->s_LWY3[bk]}) bt.push_back(st);
+      for (const Stage* st : bt) {
+        h->timers[O_EIGB].flops += stage_flops(*st);
+        h->timers[O_EIGB].bytes += stage_bytes(*st);
+      }
     }
     for (int i = 0; i < h->n_inst; ++i) {
       const double M = h->M[i], N = h->N[i];
@@ -972,8 +1007,8 @@ etdm_status build_ov_plan(etdm_handle* h) {
     }
     h->timers[O_SCAN].bytes = 8.0 * h->n_param;
   }
-  Stage* stages[] = {&h->s_PQ, &h->s_VF, &h->s_CXV, &h->s_C,  &h->s_V,   &h->s_Lov, &h->s_LV, &h->s_Gam,
-                     &h->s_XNm, &h->s_G, &h->s_F3,  &h->s_Uov, &h->s_Uvv, &h->s_HC0, &h->s_rho};
+  Stage* stages[] = {&h->s_PQ, &h->s_VF, &h->s_CXV, &h->s_C,   &h->s_TC,  &h->s_Lov, &h->s_LV, &h->s_Gam,
+                     &h->s_XNm, &h->s_G, &h->s_V,   &h->s_F3, &h->s_Uov, &h->s_Uvv, &h->s_HC0, &h->s_rho};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
   std::vector<Stage*> packable(stages, stages + sizeof(stages) / sizeof(stages[0]));
   if (!h->eig_large.empty()) {
@@ -999,11 +1034,6 @@ etdm_status build_ov_plan(etdm_handle* h) {
     }
     CHECK(upload(h, &h->d_lchk, lchk));
   }
-  // C_virt can run on the side stream beside main-stream stages (C_occ): it packs
-  // into an arena of its own
-  Stage* const side_stages[] = {&h->s_V};
-  packable.erase(std::remove(packable.begin(), packable.end(), &h->s_V), packable.end());
-  CHECK(plan_packed_stages(h, side_stages, 1));
   CHECK(plan_packed_stages(h, packable.data(), packable.size()));
   CHECK(upload(h, &h->d_spec, spec));
   CHECK(upload(h, &h->b_spec, bspec));
@@ -1011,6 +1041,9 @@ etdm_status build_ov_plan(etdm_handle* h) {
   CHECK(upload(h, &h->b_rot, brot));
   CHECK(upload(h, &h->d_fill, fill));
   CHECK(upload(h, &h->b_fill, bfill));
+  CHECK(upload(h, &h->d_pfill, pfill));
+  h->n_pfill = (int)pfill.size();
+  CHECK(upload(h, &h->b_pfill, bpfill));
   CHECK(upload(h, &h->d_rows, rows));
   CHECK(upload(h, &h->b_rows, brows));
   {
@@ -1419,9 +1452,6 @@ void free_handle(etdm_handle* h) {
   if (h->ok_host) hipHostFree(h->ok_host);
   if (h->ss_s_host) hipHostFree(h->ss_s_host);
   if (h->lb_sum) hipHostFree(h->lb_sum);
-  if (h->side) hipStreamDestroy(h->side);
-  if (h->ev_fork2) hipEventDestroy(h->ev_fork2);
-  if (h->ev_join2) hipEventDestroy(h->ev_join2);
   free_timers(h);
   if (h->base) hipFree(h->base);
   for (void* p : h->dev_allocs) hipFree(p);
@@ -1438,14 +1468,24 @@ void free_handle(etdm_handle* h) {
 // sweeps launched until the host sees them converge, 2 all sweeps launched (each
 // returns at once when the tridiagonal result was accepted; for graph capture).
 void ov_front(etdm_handle* h, hipStream_t s, int fallback) {
-  { TIMED(O_PQ); h->s_PQ.launch(s); }
+  {
+    TIMED(O_PQ);
+    h->s_PQ.launch(s);
+    launch_sym_fill(h->d_pfill, h->b_pfill, h->n_pfill, h->tot_pfill, reinterpret_cast<double*>(h->base), 0, s);
+  }
   { TIMED(O_EIGL); launch_eigh_real_lds(h->d_eig_lds, h->n_eig_lds, h->status, s); }
   if (!h->eig_large.empty()) {
-    TIMED(O_EIGG);
     // reduction to tridiagonal form and its eigenpairs, the orthogonality check and
     // one Newton-Schulz step, the compact-WY back-transform, the residual against P
-    for (const EighLarge& e : h->eig_large) launch_tb_reduce(e, s);
-    for (const EighLarge& e : h->eig_large) launch_tb_eigenpairs(e, s);
+    {
+      TIMED(O_EIGG);
+      for (const EighLarge& e : h->eig_large) launch_tb_reduce(e, s);
+    }
+    {
+      TIMED(O_EIGP);
+      for (const EighLarge& e : h->eig_large) launch_tb_eigenpairs(e, s);
+    }
+    TIMED(O_EIGB);
     h->s_LG.launch(s);
     for (const EighLarge& e : h->eig_large) launch_tb_orth_check(e, s);
     h->s_LNS.launch(s);
@@ -1488,22 +1528,12 @@ void ov_front_fallback(etdm_handle* h, hipStream_t s) {
 }
 
 // The rotated orbitals: CX = C0_o X, CV = C0_v V^T, their combination, then C_occ
-// (and dense T) on s; C_virt on the side stream when fork (joined by ev_join2), else
-// on s after C_occ.
-void ov_orbitals(etdm_handle* h, hipStream_t s, bool fork) {
+// (and dense T), and C_virt when asked (a reference update).
+void ov_orbitals(etdm_handle* h, hipStream_t s, bool want_cvirt) {
   { TIMED(O_CXV); h->s_CXV.launch(s); }
   { TIMED(O_ROT); launch_ov_rot(h->d_rot, h->b_rot, h->n_inst, h->tot_rot, s); }
-  if (fork) {
-    hipEventRecord(h->ev_fork2, s);
-    hipStreamWaitEvent(h->side, h->ev_fork2, 0);
-    h->s_V.launch(h->side);
-    hipEventRecord(h->ev_join2, h->side);
-  }
   { TIMED(O_C); h->s_C.launch(s); }
-  if (!fork) {
-    TIMED(O_V);
-    h->s_V.launch(s);
-  }
+  if (want_cvirt) h->s_V.launch(s);
 }
 
 void ov_energy_grad_rest(etdm_handle* h, hipStream_t s);
@@ -1516,10 +1546,7 @@ void ov_energy_grad(etdm_handle* h, hipStream_t s) {
 
 // After the spectral products: C, H0 C_occ, the energy, L and the gradient.
 void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
-  // C_virt on the side stream, beside C_occ, the rows and the energy (in order while
-  // stages are timed); joined before L_ov
-  const bool fork = h->side && h->tmask == 0;
-  ov_orbitals(h, s, fork);
+  ov_orbitals(h, s, false);
   if (h->h0_format == 1) {
     // block-sparse H0: T = H0 C_occ here (dense H0: T was formed with C_occ)
     TIMED(O_T);
@@ -1534,7 +1561,7 @@ void ov_energy_grad_rest(etdm_handle* h, hipStream_t s) {
     launch_ov_energy(h->d_energy, h->n_inst, h->U, h->E_ws, s);
     launch_total_energy(h->E_ws, h->n_inst, 0.0, nullptr, 0, h->U, h->status, s);
   }
-  if (fork) hipStreamWaitEvent(s, h->ev_join2, 0);
+  { TIMED(O_V); h->s_TC.launch(s); }
   { TIMED(O_LOV); h->s_Lov.launch(s); }
   if (!h->s_LV.probs.empty()) {
     TIMED(O_LV);
@@ -1579,7 +1606,7 @@ void ov_expm(etdm_handle* h, hipStream_t s) {
 void ov_new_reference(etdm_handle* h, hipStream_t s) {
   ov_front_fallback(h, s);
   ov_basis(h, s, 0);
-  ov_orbitals(h, s, false);
+  ov_orbitals(h, s, true);
   launch_c0_update(h->d_c0up, h->b_mat, h->n_inst, h->tot_mat, s);
   if (h->h0_format == 0) h->s_HC0.launch(s);  // H0 C0 for the new reference
 }
@@ -2232,13 +2259,6 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
       hipHostMalloc(reinterpret_cast<void**>(&h->ss_s_host), sizeof(int)) != hipSuccess)
     st = ETDM_E_NOMEM;
   if (st == ETDM_OK && real && h->h0_format == 0) h->s_HC0.launch(s);  // H0 C0 of the reference
-  // the side stream only where C_virt is worth a fork and join (on one small molecule
-  // they cost more than they hide)
-  if (st == ETDM_OK && real && stage_flops(h->s_V) >= 1e8 &&
-      (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
-       hipEventCreateWithFlags(&h->ev_fork2, hipEventDisableTiming) != hipSuccess ||
-       hipEventCreateWithFlags(&h->ev_join2, hipEventDisableTiming) != hipSuccess))
-    st = ETDM_E_HIP;
   if (st != ETDM_OK) return bail(st);
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) return bail(ETDM_E_HIP);
   *out = h;
