@@ -862,8 +862,13 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
 
 // Eigenvalue brackets of T: workgroup b takes eigenvalues [b m, (b+1) m) (m = TE_CH):
 // brackets on the unreduced blocks and multisection down to TB_BISECT_TOL ||T||,
-// written to lo / hi (and the block bounds) for the vector kernel.
-constexpr double TB_BISECT_TOL = 1e-13;
+// written to lo / hi (and the block bounds) for the vector kernel.  The brackets are
+// narrowed to a few ulps of ||T||, so that the vector kernel's first twisted
+// factorization is taken within TB_RQI_TOL eps ||T|| of the eigenvalue and needs no
+// second one (a multisection round over all eigenvalues costs less than a factorization
+// pass, whose pivots go through global memory).
+constexpr double TB_BISECT_TOL = 2e-15;
+constexpr double TB_RQI_TOL = 8.0;
 
 __global__ __launch_bounds__(TE_NT) void tb_bisect(EighLarge e) {
   extern __shared__ double sm[];
@@ -953,9 +958,10 @@ __global__ __launch_bounds__(TE_NT) void tb_bisect(EighLarge e) {
 
 // Eigenvectors of T: one lane per eigenvalue (64 per workgroup), twisted
 // factorizations with Rayleigh-quotient corrections; the pivots and the vector
-// are kept in column j of Zw (lanes read and write consecutive addresses), and the
-// residual max|T z - lambda z| is checked.
+// are kept in column j of Zw (lanes read and write consecutive addresses; the loads
+// are issued TV_PF indices ahead), and the residual max|T z - lambda z| is checked.
 constexpr int TV_NT = 64;
+constexpr int TV_PF = 32;
 
 __global__ __launch_bounds__(TV_NT) void tb_vectors(EighLarge e) {
   extern __shared__ double sm[];
@@ -982,7 +988,8 @@ __global__ __launch_bounds__(TV_NT) void tb_vectors(EighLarge e) {
   double res = 0.0;
   if (j < n) {
     const int b0 = e.bb[2 * j], b1 = e.bb[2 * j + 1];
-    const double lam = tl_vector<8>(d, ee, e2, b0, b1, e.blo[j], e.bhi[j], tn, pivmin, e.Zw, n, j, n);
+    const double lam =
+        tl_vector<TV_PF>(d, ee, e2, b0, b1, e.blo[j], e.bhi[j], tn, pivmin, e.Zw, n, j, n, TB_RQI_TOL);
     e.w[j] = lam;
     for (int i = b0; i < b1; ++i) {
       double t = (d[i] - lam) * e.Zw[(size_t)i * n + j];

@@ -328,11 +328,13 @@ __device__ inline double tl_twisted_pf(const double* d, const double* e, const d
 }
 
 // Eigenvector of T (size n) for eigenvalue j (bracket lo..hi) into column j of Z
-// (leading dimension ld), with Rayleigh-quotient corrections; returns the eigenvalue.
+// (leading dimension ld), with Rayleigh-quotient corrections while the correction
+// exceeds rqi_tol eps ||T||; returns the eigenvalue (the last correction applied).
 // PF = 0: plain loops (Z in LDS), else loads PF indices ahead (Z in global memory).
 template <int PF>
 __device__ inline double tl_vector(const double* vd, const double* ve, const double* ve2, int b0, int b1, double lo,
-                            double hi, double tn, double pivmin, double* Z, int n, int j, int ld) {
+                            double hi, double tn, double pivmin, double* Z, int n, int j, int ld,
+                            double rqi_tol = 2.0) {
   const double eps = DBL_EPSILON;
   for (int i = 0; i < b0; ++i) Z[i * ld + j] = 0.0;
   for (int i = b1; i < n; ++i) Z[i * ld + j] = 0.0;
@@ -346,7 +348,7 @@ __device__ inline double tl_vector(const double* vd, const double* ve, const dou
     else return tl_twisted(vd, ve, ve2, b0, b1, at, pivmin, Z, ld, j);
   };
   double dl = twisted(lam);
-  for (int it = 0; it < TL_RQI_MAX && fabs(dl) > 2.0 * eps * tn; ++it) {
+  for (int it = 0; it < TL_RQI_MAX && fabs(dl) > rqi_tol * eps * tn; ++it) {
     const double nl = lam + dl;
     if (!(nl >= lo && nl <= hi)) break;
     lam = nl;
