@@ -326,8 +326,8 @@ __global__ void bjl_finish(EighLarge e, int* status) {
 constexpr int TB_NT = 256;      // threads of the reduction
 constexpr int TB_RMAX = 2;      // own rows per pass (all their loads issued before any store)
 constexpr int TB_CMAX = 10;     // columns per thread and row and chunk (TB_NT * TB_CMAX columns per chunk)
-constexpr int TB_GRP = 16;      // workgroups per first-level barrier counter
-constexpr int TB_BAR_WORDS = 64 + 32 * 64;  // barrier words (group counters 128 bytes apart)
+constexpr int TB_GRP = 16;      // the grid has at most 64 TB_GRP workgroups
+constexpr int TB_BAR_WORDS = 64 + 32 * 64;  // synchronization words: [2] abort, [64 ..) arrival flags
 constexpr unsigned long long TB_SPIN = 20000000ull;  // 0.2 s of the 100 MHz wall clock
 constexpr int TE_CH = 16;       // eigenvalues per workgroup in the eigenpair kernel
 constexpr int TE_NT = 1024;
@@ -392,53 +392,47 @@ __device__ __forceinline__ double tb_sum(double v, double* red) {
   return t;
 }
 
-// Grid barrier in two levels: workgroups arrive on the counter of their group of
-// TB_GRP (bar[64 + 32 grp], on separate 128-byte lines), the last of a group on
-// the top counter bar[0], the last of all bumps the generation word bar[1], which
-// the others poll with device-coherent loads; false when the grid is aborting
-// (bar[2]).  Only p and the look-ahead rows cross workgroups, and they are stored
-// and loaded with device-scope atomics; every thread waits for its stores to
-// complete before its workgroup arrives, so no cache writeback or invalidation is
-// needed (the rows of A never leave their workgroup).
+// Grid synchronization by arrival flags.  Every thread waits for its own stores to
+// complete (only p and the look-ahead rows cross workgroups, stored and loaded with
+// device-scope atomics, so no cache writeback or invalidation is needed); then the
+// workgroup publishes the number of steps it has finished in its own word
+// bar[TB_FLAG0 + g], and its wave 0 polls all the flags (a few loads per lane) until
+// each has reached that number.  One store and one polled read per step, with no
+// read-modify-write on a shared word.  Every wait is bounded: past TB_SPIN the abort
+// word bar[2] is set and every workgroup leaves (false).
+constexpr int TB_FLAG0 = 64;  // flags bar[64 .. 64 + grid), grid <= 64 TB_GRP
+static_assert(TB_FLAG0 + 64 * TB_GRP <= TB_BAR_WORDS, "barrier words too few for the flags");
 __device__ bool tb_grid_sync(unsigned* bar, unsigned& gen) {
   __shared__ int s_go;
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  if (threadIdx.x == 0) {
+  const unsigned want = gen + 1;
+  if (threadIdx.x < 64) {
+    const int G = gridDim.x, lane = threadIdx.x;
     int go = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
-    if (go) {
-      const int G = gridDim.x, grp = blockIdx.x / TB_GRP, ngrp = (G + TB_GRP - 1) / TB_GRP;
-      const unsigned gsize = (unsigned)min(TB_GRP, G - grp * TB_GRP);
-      bool last = false;
-      unsigned* gc = &bar[64 + 32 * grp];
-      if (atomicAdd(gc, 1u) == gsize - 1) {
-        atomicExch(gc, 0u);
-        if (atomicAdd(&bar[0], 1u) == (unsigned)ngrp - 1) {
-          atomicExch(&bar[0], 0u);
-          atomicAdd(&bar[1], 1u);
-          last = true;
-        }
+    if (lane == 0) __hip_atomic_store(&bar[TB_FLAG0 + blockIdx.x], want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long t0 = wall_clock64();
+    while (go) {
+      unsigned mn = 0xffffffffu;
+      for (int w = lane; w < G; w += 64)
+        mn = min(mn, __hip_atomic_load(&bar[TB_FLAG0 + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      for (int o = 32; o > 0; o >>= 1) mn = min(mn, (unsigned)__shfl_xor((int)mn, o));
+      if (mn >= want) break;
+      if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        go = 0;
+        break;
       }
-      if (!last) {
-        const unsigned long long t0 = wall_clock64();
-        while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-          if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-            go = 0;
-            break;
-          }
-          if (wall_clock64() - t0 > TB_SPIN) {
-            atomicExch(&bar[2], 1u);
-            go = 0;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
+      if (wall_clock64() - t0 > TB_SPIN) {
+        if (lane == 0) atomicExch(&bar[2], 1u);
+        go = 0;
+        break;
       }
+      __builtin_amdgcn_s_sleep(1);
     }
-    s_go = go;
+    if (lane == 0) s_go = go;
   }
   __syncthreads();
-  ++gen;
+  gen = want;
   return s_go != 0;
 }
 

@@ -18,6 +18,8 @@ from gpu_helpers import make_handle
 
 pytestmark = pytest.mark.gpu
 
+ALPHA_TOL = 1e-6  # relative agreement of a well-conditioned line-search step
+
 
 def _tensors(h):
     import torch
@@ -75,11 +77,14 @@ def test_each_step_matches_oracle_from_the_same_state(which):
 
     * The accepted point satisfies strong Wolfe, or approximate Wolfe with the
       energy condition, along the GPU's own direction (x_new - x) / alpha.
-    * Same fallbacks; same evaluation count and step within 1e-6 relative, widened
-      by the oracle's own spread when its inputs move by 1e-12 relative: a cubic
-      step through nearly equal energies amplifies rounding, so in ill-conditioned
-      searches (tiny steps) rounding alone changes the result, and whole
-      trajectories drift apart and are not compared.
+    * Same fallbacks; same evaluation count and step within ALPHA_TOL relative.  A
+      cubic step through nearly equal energies amplifies rounding, so a search is
+      called ill-conditioned when the oracle's own step moves by more than
+      ALPHA_TOL / 1000 relative (or its evaluation count changes) as its inputs move
+      by 1e-12 relative: there rounding alone decides the step, its comparison is
+      skipped with the measured spread printed as the reason, and at least a third
+      of the steps must be compared.  Whole trajectories drift apart for the same
+      reason and are not compared.
     * The returned (A, E, G) matches the oracle's E and gradient at that A."""
     iters = 15
     wl = _workload(which)
@@ -110,6 +115,7 @@ def test_each_step_matches_oracle_from_the_same_state(which):
     f, g = fun(x)
     beta, S, Y = cfg.beta0, [], []
     evals_before = 1
+    skipped = 0
     for k, (info, a_k, e_k, g_k) in enumerate(gpu):
         x_new, g_new = _flat(wl, a_k), _flat(wl, g_k)
         f_new, alpha = float(e_k[-1]), info["alpha"]
@@ -128,9 +134,14 @@ def test_each_step_matches_oracle_from_the_same_state(which):
         assert not ref["failed"]
         assert bool(info["flags"] & 2) == ref["fallback"], (k, info, ref)
         spread = abs(pert["alpha"] - ref["alpha"]) / abs(ref["alpha"])
-        if pert["evals"] == ref["evals"]:
+        if pert["evals"] != ref["evals"] or spread > 1e-3 * ALPHA_TOL:
+            print(f"[skip alpha] step {k}: ill-conditioned search, the oracle's step moves by "
+                  f"{spread:.2e} relative (evals {ref['evals']} -> {pert['evals']}) under 1e-12 "
+                  f"input noise", flush=True)
+            skipped += 1
+        else:
             assert n_ev == ref["evals"], (k, info, ref)
-        assert abs(alpha - ref["alpha"]) <= (1e-6 + 1e3 * spread) * abs(ref["alpha"]), (k, info, ref, spread)
+            assert abs(alpha - ref["alpha"]) <= ALPHA_TOL * abs(ref["alpha"]), (k, info, ref, spread)
         # the returned point: E and gradient of the oracle at the GPU's A
         e_ref, g_ref = fun(x_new)
         assert abs(f_new - e_ref) <= 1e-12 * max(1.0, abs(e_ref)), k
@@ -144,6 +155,7 @@ def test_each_step_matches_oracle_from_the_same_state(which):
             beta = float(np.dot(y_k, y_k)) / float(np.dot(s_k, y_k))
         x, f, g = x_new, f_new, g_new
         evals_before = info["n_evals"]
+    assert 3 * (iters - skipped) >= iters, f"only {iters - skipped} of {iters} steps well-conditioned"
 
 
 @pytest.mark.parametrize("which,precision", [("config1", "fp64"), ("config3", "mixed"), ("tiny_complex", "fp64")])
