@@ -32,15 +32,15 @@ struct EighLarge {
   double* Ps;       // n x n symmetric part of P (for the final residual check)
   double* d;        // n: diagonal of T
   double* e;        // n: off-diagonal of T
-  double* pv;       // 2 x n: tau A v of a step (two buffers by step parity)
-  double* rowbuf;   // 2 x n: look-ahead rows (two buffers by parity)
+  double* pv;       // 3 x n: tau A v of a step (buffers by step mod 3; tb_reduce uses two)
+  double* rowbuf;   // 3 x n: look-ahead rows (buffers by row index mod 3; tb_reduce uses two)
   double* W1;       // nkc x TB_NBW x n compact-WY scratch: the partial products Y_b^T X of
                     // the TB_KC-row chunks of a block, stacked (chunk c at row c m_b)
   double* W2;       // TB_NBW x n
   double* Tw;       // ceil((n-1)/TB_NBW) blocks of TB_NBW x (nkc TB_NBW) compact-WY factors:
                     // T_b (m_b x m_b) repeated nkc times side by side (at columns c m_b)
   double* Gw;       // the same number of Gram matrices Y_b^T Y_b (m_b x m_b, ld m_b)
-  unsigned* bar;    // grid barrier words: [0] top arrivals, [1] generation, [2] abort, group counters
+  unsigned* bar;    // grid synchronization words: [2] abort, [64 ..) arrival flags of the workgroups
   int* ok;          // 1 when the tridiagonal result passed its checks
   double* scan;     // 4: maxima / sums of the grid-wide checks
   double* blo;      // n: eigenvalue brackets of T

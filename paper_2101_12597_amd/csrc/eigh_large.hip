@@ -319,9 +319,10 @@ __global__ void bjl_finish(EighLarge e, int* status) {
 //   before the owner changes it) -> reflector k + 1, computed identically by every
 //   workgroup; then each owner updates its rows i >= k + 2 (columns >= k + 2) and
 //   in the same pass accumulates p_{k+1,i} = tau_{k+1} sum_j a_ij v_{k+1,j}.
-// One grid barrier per step; A is read and written once per step.  The barrier
-// waits are bounded: a wait longer than TB_SPIN sets the abort word, every
-// workgroup leaves, *ok stays 0 and the Jacobi sweeps take over.
+// One grid barrier per step (tb_reduce; the register-resident tb_reduce_reg polls
+// the exchanged slots instead); A is read and written once per step.  The waits are
+// bounded: a wait longer than TB_SPIN sets the abort word, every workgroup leaves,
+// *ok stays 0 and the Jacobi sweeps take over.
 // ---------------------------------------------------------------------------
 constexpr int TB_NT = 256;      // threads of the reduction
 constexpr int TB_RMAX = 2;      // own rows per pass (all their loads issued before any store)
@@ -329,6 +330,10 @@ constexpr int TB_CMAX = 10;     // columns per thread and row and chunk (TB_NT *
 constexpr int TB_GRP = 16;      // the grid has at most 64 TB_GRP workgroups
 constexpr int TB_BAR_WORDS = 64 + 32 * 64;  // synchronization words: [2] abort, [64 ..) arrival flags
 constexpr unsigned long long TB_SPIN = 20000000ull;  // 0.2 s of the 100 MHz wall clock
+// Slots of p and of the look-ahead rows (register-resident reduction) that hold no
+// value of the current step carry this signalling-NaN pattern; arithmetic never
+// produces a signalling NaN.
+constexpr unsigned long long TR_EMPTY = 0x7ff4a5a5a5a5a5a5ull;
 constexpr int TE_CH = 16;       // eigenvalues per workgroup in the eigenpair kernel
 constexpr int TE_NT = 1024;
 
@@ -338,7 +343,7 @@ size_t eigh_large_workspace(int n, size_t* npad_out) {
   const size_t half = npad / BLK / 2;
   const size_t nblk = (size_t)(n - 1 + TB_NBW - 1) / TB_NBW;
   const size_t nkc = (size_t)std::max(1, (n - 1 + TB_KC - 1) / TB_KC);
-  return 2 * npad * npad + half * SUB * SUB + PREP_BLOCKS + 2 * (size_t)n * n + 6 * (size_t)n +
+  return 2 * npad * npad + half * SUB * SUB + PREP_BLOCKS + 2 * (size_t)n * n + 8 * (size_t)n +
          (nkc + 1) * TB_NBW * n + nblk * TB_NBW * TB_NBW * (nkc + 1) + TB_BAR_WORDS / 2 + 2 + 4 +
          3 * (size_t)n;
 }
@@ -363,9 +368,9 @@ void eigh_large_layout(EighLarge& e, double* ws, EighLargeState* st, int cu_coun
   e.d = e.Ps + (size_t)n * n;
   e.e = e.d + n;
   e.pv = e.e + n;
-  e.rowbuf = e.pv + 2 * n;
+  e.rowbuf = e.pv + 3 * n;
   e.nkc = std::max(1, (n - 1 + TB_KC - 1) / TB_KC);
-  e.W1 = e.rowbuf + 2 * n;
+  e.W1 = e.rowbuf + 3 * n;
   e.W2 = e.W1 + (size_t)e.nkc * TB_NBW * n;
   e.Tw = e.W2 + (size_t)TB_NBW * n;
   const size_t nblk = (size_t)(n - 1 + TB_NBW - 1) / TB_NBW;
@@ -523,8 +528,13 @@ __device__ void tb_rows(double* A, int n, int ilo, int jlo, bool upd, const doub
   }
 }
 
-__global__ void tb_init(EighLarge e) {
+// polled: the slots of p and of the look-ahead rows of the register-resident reduction
+// start empty
+__global__ void tb_init(EighLarge e, int polled) {
   for (int q = threadIdx.x; q < TB_BAR_WORDS; q += blockDim.x) e.bar[q] = 0u;
+  if (polled)
+    for (int q = threadIdx.x; q < 6 * e.n; q += blockDim.x)
+      reinterpret_cast<unsigned long long*>(e.pv)[q] = TR_EMPTY;
   if (threadIdx.x < 4) e.scan[threadIdx.x] = 0.0;
   if (threadIdx.x == 0) *e.ok = 0;
 }
@@ -673,14 +683,83 @@ __device__ __forceinline__ void tr_store_reflector(EighLarge& e, const double (&
   }
 }
 
+__device__ __forceinline__ void tr_clear(double* p) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), TR_EMPTY, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Entries j = tid + TR_NT q, lo <= j < n, of p and rb (zero elsewhere), each polled
+// until it is no longer empty.  False for the whole workgroup when the grid aborts or
+// a wait exceeds TB_SPIN (which sets the abort word).
+__device__ bool tr_take(const double* p, const double* rb, int lo, int n, double (&pj)[TR_Q], double (&rj)[TR_Q],
+                        unsigned* bar) {
+  unsigned pend = 0u;
+#pragma unroll
+  for (int q = 0; q < TR_Q; ++q) {
+    const int j = threadIdx.x + TR_NT * q;
+    pj[q] = 0.0;
+    rj[q] = 0.0;
+    if (j >= lo && j < n) pend |= 3u << (2 * q);
+  }
+  int fail = 0;
+  const unsigned long long t0 = wall_clock64();
+  while (pend) {
+#pragma unroll
+    for (int q = 0; q < TR_Q; ++q) {
+      const int j = threadIdx.x + TR_NT * q;
+      if (pend & (1u << (2 * q))) {
+        const double x = tb_get(&p[j]);
+        if ((unsigned long long)__double_as_longlong(x) != TR_EMPTY) {
+          pj[q] = x;
+          pend &= ~(1u << (2 * q));
+        }
+      }
+      if (pend & (2u << (2 * q))) {
+        const double x = tb_get(&rb[j]);
+        if ((unsigned long long)__double_as_longlong(x) != TR_EMPTY) {
+          rj[q] = x;
+          pend &= ~(2u << (2 * q));
+        }
+      }
+    }
+    if (!pend) break;
+    if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+      fail = 1;
+      break;
+    }
+    if (wall_clock64() - t0 > TB_SPIN) {
+      atomicExch(&bar[2], 1u);
+      fail = 1;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return !__syncthreads_or(fail);
+}
+
+// The reduction with the rows of A in registers (n <= TR_NT TR_Q, at most TR_R rows
+// per workgroup).  No grid barrier: the only data that cross workgroups are p and
+// the look-ahead rows, and readers poll those slots directly.  p_k sits in buffer
+// k mod 3, row k in row buffer k mod 3; the slots are emptied again by their writers
+// once every reader is known to be done with them:
+//   * step k begins when all of p_k (rows >= k + 1) is in, so every workgroup that
+//     read p_{k-1} (all own a row >= k + 1) has finished doing so: each owner then
+//     empties its slots of buffer (k + 2) mod 3, and the owner of row k + 3 empties
+//     row buffer k mod 3 (row k, read in step k - 1);
+//   * those stores complete before the owner stores p_{k+1}, and a reader of
+//     p_{k+2} or of row k + 3 (step k + 2, k + 1... later) has read that owner's
+//     p_{k+1} entry first, so it sees the empty slot or the new value, never the old.
+// A workgroup leaves after the last step that updates one of its rows; the owner of
+// row n - 1 takes every step and stores the reflectors and T.
 __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
   extern __shared__ double sm[];
   __shared__ double red1[TR_W], red2[TR_W], red3[TR_W][TR_R];
   __shared__ double s_pk1, s_alpha;
   __shared__ double pown[TR_R];
   const int n = e.n, G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool keeper = g == (n - 1) % G;  // owns row n - 1
+  const int last_row = g + G * ((n - 1 - g) / G);
   double* vfull = sm;  // the reflector of the step (n), read for the own rows
-  unsigned gen = 0;
   double a[TR_R][TR_Q];
   // own rows of A = sym(P), also kept in Ps for the final residual check
 #pragma unroll
@@ -706,13 +785,13 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
   }
   double beta;
   double tau = tr_reflector(row, 0, n, vc, red2, &s_alpha, beta);
-  if (g == 0) tr_store_reflector(e, vc, tau, beta, 0, row);
+  if (keeper) tr_store_reflector(e, vc, tau, beta, 0, row);
 #pragma unroll
   for (int q = 0; q < TR_Q; ++q) {
     const int j = tid + TR_NT * q;
     if (j < n) vfull[j] = vc[q];
   }
-  // p_0 = tau_0 A v_0 for the own rows i >= 1, and the look-ahead copy of row 1
+  // p_0 = tau_0 A v_0 for the own rows i >= 1 (buffer 0), and row 1 (row buffer 1)
   {
     double acc[TR_R];
 #pragma unroll
@@ -743,7 +822,7 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
       if (i >= 1 && i < n) tb_put(&e.pv[i], tau * t);
     }
   }
-  if (!tb_grid_sync(e.bar, gen)) return;
+  __syncthreads();
   double vown[TR_R];
 #pragma unroll
   for (int r = 0; r < TR_R; ++r) {
@@ -751,17 +830,24 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
     vown[r] = i < n ? vfull[i] : 0.0;
   }
 
-  for (int k = 0; k < n - 2; ++k) {
+  const int k_end = min(n - 2, last_row - 1);  // steps k < k_end update an own row
+  for (int k = 0; k < k_end; ++k) {
     // p_k and the look-ahead row k + 1 (as after step k - 1)
-    const double* p = e.pv + (size_t)(k & 1) * n;
-    const double* rb = e.rowbuf + (size_t)((k + 1) & 1) * n;
     double pj[TR_Q], rj[TR_Q];
+    if (!tr_take(e.pv + (size_t)(k % 3) * n, e.rowbuf + (size_t)((k + 1) % 3) * n, k + 1, n, pj, rj, e.bar))
+      return;
+    // slots no reader needs any more: own entries of p_{k-1}, and row k
+    {
+      double* pold = e.pv + (size_t)((k + 2) % 3) * n;
+      if (tid < TR_R && g + G * tid < n) tr_clear(&pold[g + G * tid]);
+      if (k + 3 < n && (k + 3) % G == g) {
+        double* rold = e.rowbuf + (size_t)(k % 3) * n;
 #pragma unroll
-    for (int q = 0; q < TR_Q; ++q) {
-      const int j = tid + TR_NT * q;
-      const bool on = j >= k + 1 && j < n;
-      pj[q] = on ? tb_get(&p[j]) : 0.0;
-      rj[q] = on ? tb_get(&rb[j]) : 0.0;
+        for (int q = 0; q < TR_Q; ++q) {
+          const int j = tid + TR_NT * q;
+          if (j < n) tr_clear(&rold[j]);
+        }
+      }
     }
     // w = p - (tau / 2) (p . v) v
     double part = 0.0;
@@ -791,7 +877,7 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
     double taun = 0.0;
     if (k + 1 <= n - 3) {
       taun = tr_reflector(row, k + 1, n, vn, red2, &s_alpha, beta);
-      if (g == 0) tr_store_reflector(e, vn, taun, beta, k + 1, row);
+      if (keeper) tr_store_reflector(e, vn, taun, beta, k + 1, row);
 #pragma unroll
       for (int q = 0; q < TR_Q; ++q) {
         const int j = tid + TR_NT * q;
@@ -802,15 +888,13 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
       for (int q = 0; q < TR_Q; ++q) {
         vn[q] = 0.0;
         const int j = tid + TR_NT * q;
-        if (g == 0 && j == n - 2) e.d[n - 2] = row[q];  // the last 2 x 2 block
-        if (g == 0 && j == n - 1) e.e[n - 2] = row[q];
+        if (keeper && j == n - 2) e.d[n - 2] = row[q];  // the last 2 x 2 block
+        if (keeper && j == n - 1) e.e[n - 2] = row[q];
       }
     }
     // own rows i >= k + 2, columns j >= k + 2: a_ij -= v_i w_j + w_i v_j, and the
     // partial sums of p_{k+1} = tau_{k+1} A v_{k+1}
     const int rnext = k + 2;
-    double* pn = e.pv + (size_t)((k + 1) & 1) * n;
-    double* rbn = e.rowbuf + (size_t)((k + 2) & 1) * n;
     double acc[TR_R];
 #pragma unroll
     for (int r = 0; r < TR_R; ++r) {
@@ -823,7 +907,6 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
           if (j >= rnext && j < n) {
             a[r][q] -= vown[r] * wv[q] + wown[r] * vc[q];
             acc[r] += a[r][q] * vn[q];
-            if (i == rnext) tb_put(&rbn[j], a[r][q]);
             if (k == n - 3 && i == n - 1 && j == n - 1) e.d[n - 1] = a[r][q];
           }
         }
@@ -833,25 +916,41 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
     if (lane == 0)
 #pragma unroll
       for (int r = 0; r < TR_R; ++r) red3[wave][r] = acc[r];
+    // the emptied slots are written before any p_{k+1} entry of this workgroup
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (tid < TR_R) {
       const int i = g + G * tid;
       double t = 0.0;
       for (int w = 0; w < TR_W; ++w) t += red3[w][tid];
       pown[tid] = taun * t;
-      if (i >= rnext && i < n) tb_put(&pn[i], taun * t);
+      if (i >= rnext && i < n) tb_put(&e.pv[(size_t)((k + 1) % 3) * n + i], taun * t);
+    }
+    // the look-ahead row k + 2, stored by its owner
+    if (rnext < n && rnext % G == g) {
+      double* rbn = e.rowbuf + (size_t)(rnext % 3) * n;
+      const int r = (rnext - g) / G;
+#pragma unroll
+      for (int rr = 0; rr < TR_R; ++rr)
+        if (rr == r)
+#pragma unroll
+          for (int q = 0; q < TR_Q; ++q) {
+            const int j = tid + TR_NT * q;
+            if (j >= rnext && j < n) tb_put(&rbn[j], a[rr][q]);
+          }
     }
 #pragma unroll
     for (int q = 0; q < TR_Q; ++q) vc[q] = vn[q];
     tau = taun;
-    if (!tb_grid_sync(e.bar, gen)) return;
 #pragma unroll
     for (int r = 0; r < TR_R; ++r) {
       const int i = g + G * r;
       vown[r] = i < n ? vfull[i] : 0.0;
     }
   }
-  if (g == 0 && tid == 0) *e.ok = 1;  // reached only when no barrier aborted
+  // reached only when no wait aborted
+  if (keeper && tid == 0 && __hip_atomic_load(&e.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+    *e.ok = 1;
 }
 
 // Eigenvalue brackets of T: workgroup b takes eigenvalues [b m, (b+1) m) (m = TE_CH):
@@ -1152,7 +1251,7 @@ void launch_tb_reduce(const EighLarge& e, hipStream_t s) {
                         (int)lds);
     attr_g = lds;
   }
-  tb_init<<<1, 256, 0, s>>>(e);
+  tb_init<<<1, 256, 0, s>>>(e, tb_use_reg(e) ? 1 : 0);
   if (e.grid < 1) return;  // no resident grid possible: *ok stays 0, the Jacobi solver runs
   if (tb_use_reg(e))
     tb_reduce_reg<<<e.grid, TR_NT, lds, s>>>(e);
@@ -1171,6 +1270,7 @@ void launch_tb_wy_t(const EighLarge& e, hipStream_t s) {
   const int nblk = (e.n - 1 + TB_NBW - 1) / TB_NBW;
   if (nblk > 0) tb_wy_t<<<nblk, 256, 0, s>>>(e);
 }
+
 
 static bool g_attr = false;
 
