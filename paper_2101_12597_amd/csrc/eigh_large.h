@@ -65,6 +65,10 @@ void eigh_large_layout(EighLarge& e, double* ws, EighLargeState* st, int cu_coun
 void launch_tb_reduce(const EighLarge& e, hipStream_t s);
 void launch_tb_eigenpairs(const EighLarge& e, hipStream_t s);
 void launch_tb_wy_t(const EighLarge& e, hipStream_t s);
+// X <- Q X in one launch (the panel of 16 columns of X per workgroup in registers),
+// after launch_tb_wy_t; for n up to tb_apply_wy_fits (else the grouped GEMM blocks).
+bool tb_apply_wy_fits(int n);
+void launch_tb_apply_wy(const EighLarge& e, hipStream_t s);
 // After G = Z^T Z has been formed in Aw: *ok = 0 unless max|G - I| <= 1e-6; Aw <- (3 I - G) / 2.
 void launch_tb_orth_check(const EighLarge& e, hipStream_t s);
 // After R = sym(P) X has been formed in Aw: *ok = 0 unless max|R - X diag(w)| <= 1e-11 ||sym(P)||_F.

@@ -1165,21 +1165,31 @@ __global__ __launch_bounds__(256) void tb_wy_t(EighLarge e) {
   __shared__ double g[TB_NBW][TB_NBW + 1];
   __shared__ double T[TB_NBW][TB_NBW + 1];
   __shared__ double col[TB_NBW];
+  __shared__ double taus[TB_NBW];
   for (int q = threadIdx.x; q < TB_NBW * TB_NBW; q += 256) {
     const int r = q / TB_NBW, c = q - r * TB_NBW;
     g[r][c] = (r < m && c < m) ? Gb[r * m + c] : 0.0;
     T[r][c] = 0.0;
   }
+  if (threadIdx.x < m) taus[threadIdx.x] = Y[(size_t)(k0 + threadIdx.x) * n + (n - 1)];
   __syncthreads();
   for (int c = 0; c < m; ++c) {
-    const double tau = Y[(size_t)(k0 + c) * n + (n - 1)];
+    const double tau = taus[c];
     const int r = threadIdx.x;
     if (r < c) col[r] = -tau * g[r][c];
     __syncthreads();
     if (r < c) {
-      double acc = 0.0;
-      for (int q = r; q < c; ++q) acc += T[r][q] * col[q];
-      T[r][c] = acc;
+      // four partial sums, so that the LDS loads of a group are in flight together
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int q = r;
+      for (; q + 4 <= c; q += 4) {
+        a0 += T[r][q] * col[q];
+        a1 += T[r][q + 1] * col[q + 1];
+        a2 += T[r][q + 2] * col[q + 2];
+        a3 += T[r][q + 3] * col[q + 3];
+      }
+      for (; q < c; ++q) a0 += T[r][q] * col[q];
+      T[r][c] = (a0 + a1) + (a2 + a3);
     }
     if (r == c) T[c][c] = tau;
     __syncthreads();
@@ -1187,6 +1197,182 @@ __global__ __launch_bounds__(256) void tb_wy_t(EighLarge e) {
   for (int q = threadIdx.x; q < e.nkc * m * m; q += 256) {
     const int c = q / (m * m), rem = q - c * m * m, r = rem / m, j = rem - r * m;
     Tb[(size_t)r * ldT + c * m + j] = T[r][j];
+  }
+}
+
+// X <- Q X, Q = H_0 H_1 ... H_{n-3} = prod_b (I - Y_b T_b Y_b^T) over the compact-WY
+// blocks of TB_NBW reflectors, last block first, in one launch.  The columns of X are
+// independent, so workgroup c keeps the 16-column panel c of X in registers for the
+// whole product and per block forms
+//   W = Y_b^T X_p  (partial sums of the wavefronts over their rows, then summed in a
+//                   fixed order, so that the result does not depend on timing),
+//   W2 = T_b W,    X_p -= Y_b W2,
+// the two large products on the FP64 matrix cores.  Wavefront w holds the 16-row
+// blocks w, w + WY_W, ... of the panel in the accumulator layout of
+// v_mfma_f64_16x16x4f64 (element r of lane l: row l / 16 + 4 r, column l % 16), which
+// is also the operand layout of the four k-steps of those 16 rows in W = Y_b^T X_p.
+// Only rows below k0 (the block's first reflector index) take part in block b, and the
+// row blocks are dealt out cyclically, so every wavefront has a share of them.
+//
+// The blocks Y_b are first copied (tb_wy_pack) into the free work matrix as
+// Yc[b][row][0 .. TB_NBW) with rows padded to a multiple of 16 and zeros outside
+// rows (k0, n) and reflectors [0, mb): the product kernel then loads without masks,
+// at offsets that are compile-time constants from one base per row block.
+constexpr int WY_NT = 512;
+constexpr int WY_W = WY_NT / 64;  // wavefronts
+constexpr int WY_RB = 18;         // row blocks per wavefront
+constexpr int WY_NMAX = 16 * WY_W * WY_RB;
+
+__global__ void tb_wy_pack(EighLarge e) {
+  if (!*e.ok) return;
+  const int n = e.n, np16 = (n + 15) & ~15, nblk = (n - 1 + TB_NBW - 1) / TB_NBW;
+  const int64_t total = (int64_t)nblk * np16 * TB_NBW;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(q % TB_NBW);
+    const int64_t rq = q / TB_NBW;
+    const int row = (int)(rq % np16), b = (int)(rq / np16);
+    const int k0 = b * TB_NBW, mb = min(TB_NBW, n - 1 - k0);
+    e.Aw[q] = (row > k0 && row < n && c < mb) ? e.Vw[(size_t)row * n + k0 + c] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(WY_NT) void tb_apply_wy(EighLarge e) {
+  if (!*e.ok) return;
+  __shared__ double part[WY_W][4][4][64];
+  __shared__ double Wl[TB_NBW][17];
+  __shared__ double W2l[TB_NBW][17];
+  __shared__ double Tl[TB_NBW][TB_NBW + 1];
+  const int n = e.n, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: row-block values are scalar
+  const int lr = lane & 15, lk = lane >> 4;
+  const int col = blockIdx.x * 16 + lr;
+  const int nrb = (n + 15) >> 4, np16 = nrb * 16;
+  d4v x[WY_RB];
+#pragma unroll
+  for (int t = 0; t < WY_RB; ++t) {
+    const int rb = wave + WY_W * t;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * rb + lk + 4 * r;
+      x[t][r] = (rb < nrb && row < n && col < n) ? e.X[(size_t)row * n + col] : 0.0;
+    }
+  }
+  const int nblk = (n - 1 + TB_NBW - 1) / TB_NBW;
+  const int ldT = e.nkc * TB_NBW;
+  // lane offsets (in doubles) of the two fragment patterns inside a row block of Yc
+  const int off_w = lk * TB_NBW + lr;  // W = Y_b^T X: row 4 ks + lk, reflector 16 it + lr
+  const int off_u = lr * TB_NBW + lk;  // X -= Y_b W2: row lr, reflector 4 u + lk
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int k0 = b * TB_NBW, mb = min(TB_NBW, n - 1 - k0), rlo = k0 + 1;
+    const double* Yc = e.Aw + (size_t)b * np16 * TB_NBW;
+    // W = Y_b^T X_p over this wavefront's rows; the loads of each step (half a row
+    // block) are issued before the products of the step before, and no instruction
+    // moves across steps (which bounds the registers held by loads in flight)
+    d4v acc[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) acc[it] = d4v{0.0, 0.0, 0.0, 0.0};
+    {
+      // steps of half a row block (k-steps 2 h, 2 h + 1)
+      double cur[8], nxt[8];
+      auto load_w = [&](int st, double (&buf)[8]) {
+        const int rb = min(wave + WY_W * (st >> 1), nrb - 1);
+        const double* y = Yc + (size_t)rb * 16 * TB_NBW + off_w + 8 * (st & 1) * TB_NBW;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+          for (int it = 0; it < 4; ++it) buf[4 * ks + it] = y[4 * ks * TB_NBW + 16 * it];
+      };
+      load_w(0, cur);
+#pragma unroll
+      for (int st = 0; st < 2 * WY_RB; ++st) {
+        if (st + 1 < 2 * WY_RB) load_w(st + 1, nxt);
+        const int t = st >> 1, rb = wave + WY_W * t;
+        if (rb < nrb && 16 * rb + 15 >= rlo) {  // uniform in the wavefront
+#pragma unroll
+          for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int it = 0; it < 4; ++it)
+              acc[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[4 * ks + it], x[t][2 * (st & 1) + ks], acc[it], 0,
+                                                             0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < 4; ++it)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[wave][it][r][lane] = acc[it][r];
+    __syncthreads();
+    // the wavefronts' partial sums, in order; W (64 x 16) element q: row q / 16, column q % 16
+    for (int q = threadIdx.x; q < TB_NBW * 16; q += WY_NT) {
+      const int i = q >> 4, j = q & 15, it = i >> 4, ii = i & 15;
+      const int r = ii >> 2, ln = (ii & 3) * 16 + j;
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < WY_W; ++w) sum += part[w][it][r][ln];
+      Wl[i][j] = sum;
+    }
+    __syncthreads();
+    // W2 = T_b W (T_b upper triangular, row i at Tw + i ldT), with T_b staged in LDS
+    // (all its loads in flight together)
+    {
+      const double* Tb = e.Tw + (size_t)b * TB_NBW * ldT;
+      for (int q = threadIdx.x; q < TB_NBW * TB_NBW; q += WY_NT) {
+        const int i = q / TB_NBW, c = q % TB_NBW;
+        Tl[i][c] = (i < mb && c < mb && c >= i) ? Tb[(size_t)i * ldT + c] : 0.0;
+      }
+      __syncthreads();
+      for (int q = threadIdx.x; q < TB_NBW * 16; q += WY_NT) {
+        const int i = q >> 4, j = q & 15;
+        double sum = 0.0;
+#pragma unroll 8
+        for (int c = 0; c < TB_NBW; ++c) sum += Tl[i][c] * Wl[c][j];
+        W2l[i][j] = sum;
+      }
+    }
+    __syncthreads();
+    // X_p -= Y_b W2 in steps of half a row block (32 reflectors), the loads of the
+    // next step issued before the products of this one
+    {
+      double cur[8], nxt[8];
+      auto load_u = [&](int st, double (&buf)[8]) {
+        const int rb = min(wave + WY_W * (st >> 1), nrb - 1);
+        const double* y = Yc + (size_t)rb * 16 * TB_NBW + off_u + 32 * (st & 1);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) buf[u] = -y[4 * u];
+      };
+      load_u(0, cur);
+#pragma unroll
+      for (int st = 0; st < 2 * WY_RB; ++st) {
+        if (st + 1 < 2 * WY_RB) load_u(st + 1, nxt);
+        const int t = st >> 1, rb = wave + WY_W * t;
+        if (rb < nrb && 16 * rb + 15 >= rlo) {  // uniform in the wavefront
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            x[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[u], W2l[32 * (st & 1) + 4 * u + lk][lr], x[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  {
+    // bounds and addresses formed anew (opaque copies), not held from the loads above
+    int nn = n, cb = col, lkb = lk;
+    asm volatile("" : "+s"(nn), "+v"(cb), "+v"(lkb));
+    double* Xc = e.X + cb;
+#pragma unroll
+    for (int t = 0; t < WY_RB; ++t) {
+      const int rb = wave + WY_W * t;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * rb + lkb + 4 * r;
+        if (row < nn && cb < nn) Xc[(size_t)row * nn] = x[t][r];
+      }
+    }
   }
 }
 
@@ -1271,6 +1457,13 @@ void launch_tb_wy_t(const EighLarge& e, hipStream_t s) {
   if (nblk > 0) tb_wy_t<<<nblk, 256, 0, s>>>(e);
 }
 
+bool tb_apply_wy_fits(int n) { return n >= 2 && n <= WY_NMAX; }
+
+void launch_tb_apply_wy(const EighLarge& e, hipStream_t s) {
+  if (!tb_apply_wy_fits(e.n)) return;
+  tb_wy_pack<<<1024, 256, 0, s>>>(e);
+  tb_apply_wy<<<(e.n + 15) / 16, WY_NT, 0, s>>>(e);
+}
 
 static bool g_attr = false;
 

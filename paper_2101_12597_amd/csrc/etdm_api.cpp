@@ -824,8 +824,11 @@ etdm_status build_ov_plan(etdm_handle* h) {
       h->s_LNS.add(prob(N, N, N, e.Zw, N, e.Aw, N, e.X, N));
       h->s_LR.add(prob(N, N, N, e.Ps, N, e.X, N, e.Aw, N));  // R = sym(P) X for the final check
       lchk.push_back(HermCheck{e.Aw, e.ok, N});
+      // X <- Q X: one fused launch when the panel fits its registers, else grouped
+      // GEMMs per compact-WY block
       const int nblk = (N - 1 + TB_NBW - 1) / TB_NBW;
-      if ((int)h->s_LWY1.size() < nblk) {
+      const bool fused_wy = tb_apply_wy_fits(N);
+      if (!fused_wy && (int)h->s_LWY1.size() < nblk) {
         h->s_LWY1.resize(nblk);
         h->s_LWY2.resize(nblk);
         h->s_LWY3.resize(nblk);
@@ -835,6 +838,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
         const int k0 = bk * TB_NBW, mb = std::min(TB_NBW, N - 1 - k0), R = N - 1 - k0;
         const double* Yb = e.Vw + (size_t)(k0 + 1) * N + k0;
         h->s_LGram.add(prob(mb, mb, R, Yb, N, Yb, N, e.Gw + (size_t)bk * TB_NBW * TB_NBW, mb));
+        if (fused_wy) continue;
         double* Xr = e.X + (size_t)(k0 + 1) * N;
         // W1 = Y_b^T X in K chunks of TB_KC rows (partial c at rows c mb), then
         // W2 = [T_b ... T_b] [W1_0; W1_1; ...] = T_b W1
@@ -980,6 +984,18 @@ etdm_status build_ov_plan(etdm_handle* h) {
       for (const Stage* st : bt) {
         h->timers[O_EIGB].flops += stage_flops(*st);
         h->timers[O_EIGB].bytes += stage_bytes(*st);
+      }
+      // the fused compact-WY product: W = Y_b^T X, T_b W and X -= Y_b W2 per block; X
+      // read and written once, each Y_b read once
+      for (const EighLarge& e : h->eig_large) {
+        if (!tb_apply_wy_fits(e.n)) continue;
+        const double n = e.n;
+        for (int k0 = 0; k0 < e.n - 1; k0 += TB_NBW) {
+          const double R = e.n - 1 - k0, mb = std::min(TB_NBW, e.n - 1 - k0);
+          h->timers[O_EIGB].flops += 4.0 * R * mb * n + mb * mb * n;
+          h->timers[O_EIGB].bytes += 8.0 * R * mb;
+        }
+        h->timers[O_EIGB].bytes += 16.0 * n * n;
       }
     }
     for (int i = 0; i < h->n_inst; ++i) {
@@ -1491,6 +1507,7 @@ void ov_front(etdm_handle* h, hipStream_t s, int fallback) {
     h->s_LNS.launch(s);
     h->s_LGram.launch(s);
     for (const EighLarge& e : h->eig_large) launch_tb_wy_t(e, s);
+    for (const EighLarge& e : h->eig_large) launch_tb_apply_wy(e, s);
     for (int bk = (int)h->s_LWY1.size() - 1; bk >= 0; --bk) {
       h->s_LWY1[bk].launch(s);
       h->s_LWY2[bk].launch(s);
