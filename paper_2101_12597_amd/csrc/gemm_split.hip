@@ -116,10 +116,15 @@ __device__ __forceinline__ void x6_tile(const SplitProb& p, int lt, int& tm, int
   tn = idx / gr;
 }
 
-template <int TPM, int TPN>
-__global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restrict__ probs,
-                                                      const int* __restrict__ tile_prob, int total) {
-  constexpr int NBM = 2 * TPM, NBN = 2 * TPN;
+// NT threads: 256 (four wavefronts in 2 x 2, each 32 TPM x 32 TPN) or 512 (eight in
+// 2 x 4, each 32 TPM x 16 TPN: fewer registers per wavefront, so that two of them
+// share a SIMD and hide each other's latencies)
+template <int TPM, int TPN, int NT>
+__global__ __launch_bounds__(NT) void gemm_x6_packed(const SplitProb* __restrict__ probs,
+                                                     const int* __restrict__ tile_prob, int total) {
+  constexpr int WC = NT / 128;  // wavefront columns (two wavefront rows)
+  constexpr int NBM = 2 * TPM, NBN = 4 * TPN / WC;
+  static_assert((TPM * 768) % NT == 0 && (TPN * 768) % NT == 0, "staging pieces per thread");
   extern __shared__ __attribute__((aligned(16))) __bf16 x6_lds[];
   const int tile = xcd_tile(blockIdx.x, total);
   const SplitProb& p = probs[tile_prob[tile]];
@@ -127,7 +132,7 @@ __global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restric
   x6_tile(p, tile - p.begin, tm, tn);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wrow = (wave >> 1) * 32 * TPM, wcol = (wave & 1) * 32 * TPN;  // sub-tile offsets
+  const int wrow = (wave / WC) * 32 * TPM, wcol = (wave % WC) * 16 * NBN;  // sub-tile offsets
   const int lr = lane & 15, lo = lane >> 4;
 
   // LDS: [buffer][A panels | B panels][slice][row][k]
@@ -139,28 +144,29 @@ __global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restric
 
   // staging: TPM (TPN) panels x 768 pieces of 16 bytes of A (B); thread t takes
   // pieces t + 256 u
-  i4 ra[3 * TPM], rb[3 * TPN];
+  constexpr int UA = TPM * 768 / NT, UB = TPN * 768 / NT;
+  i4 ra[UA], rb[UB];
   auto fetch = [&](int kt) {
 #pragma unroll
-    for (int u = 0; u < 3 * TPM; ++u) {
-      const int e = threadIdx.x + u * XNT;
+    for (int u = 0; u < UA; ++u) {
+      const int e = threadIdx.x + u * NT;
       const int pan = e / 768, w = e % 768;
       ra[u] = *reinterpret_cast<const i4*>(Ag + pan * pstride + (int64_t)kt * PK_CHUNK + w * 8);
     }
 #pragma unroll
-    for (int u = 0; u < 3 * TPN; ++u) {
-      const int e = threadIdx.x + u * XNT;
+    for (int u = 0; u < UB; ++u) {
+      const int e = threadIdx.x + u * NT;
       const int pan = e / 768, w = e % 768;
       rb[u] = *reinterpret_cast<const i4*>(Bg + pan * pstride + (int64_t)kt * PK_CHUNK + w * 8);
     }
   };
   auto commit = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 3 * TPM; ++u)
-      *reinterpret_cast<i4*>(x6_lds + buf * BUF + (threadIdx.x + u * XNT) * 8) = ra[u];
+    for (int u = 0; u < UA; ++u)
+      *reinterpret_cast<i4*>(x6_lds + buf * BUF + (threadIdx.x + u * NT) * 8) = ra[u];
 #pragma unroll
-    for (int u = 0; u < 3 * TPN; ++u)
-      *reinterpret_cast<i4*>(x6_lds + buf * BUF + OPERA + (threadIdx.x + u * XNT) * 8) = rb[u];
+    for (int u = 0; u < UB; ++u)
+      *reinterpret_cast<i4*>(x6_lds + buf * BUF + OPERA + (threadIdx.x + u * NT) * 8) = rb[u];
   };
 
   double acc[NBM][NBN][4];
@@ -228,6 +234,135 @@ __global__ __launch_bounds__(XNT) void gemm_x6_packed(const SplitProb* __restric
   }
 
   // epilogue: element r of lane l of block (i, j) is row 4 (l / 16) + r, column l % 16
+  const int row0 = tm * 64 * TPM + wrow, col0 = tn * 64 * TPN + wcol;
+#pragma unroll
+  for (int i = 0; i < NBM; ++i)
+#pragma unroll
+    for (int j = 0; j < NBN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + i * 16 + 4 * lo + r, col = col0 + j * 16 + lr;
+        if (row < p.m && col < p.n) {
+          double v = acc[i][j][r];
+          if (p.beta != 0.0) v += p.beta * p.D[(int64_t)row * p.ldd + col];
+          p.C[(int64_t)row * p.ldc + col] = v;
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// gemm_x6_ring<TPM, TPN>: the same product for tiles of TPM x TPN panels with eight
+// wavefronts (2 x 4, each 32 TPM x 16 TPN) and a ring of three LDS buffers filled
+// straight from global memory (global_load_lds_dwordx4: no staging registers), so
+// that the k-tiles kt + 1 and kt + 2 are in flight while kt is multiplied.  One
+// barrier per k-tile: after it, buffer kt is complete and every wavefront is done
+// with buffer kt - 1, which then takes k-tile kt + 2.
+// ---------------------------------------------------------------------------
+constexpr int RING_NT = 512;
+constexpr int RING_NBUF = 3;
+
+template <int TPM, int TPN>
+__global__ __launch_bounds__(RING_NT) void gemm_x6_ring(const SplitProb* __restrict__ probs,
+                                                        const int* __restrict__ tile_prob, int total) {
+  constexpr int WC = RING_NT / 128;  // wavefront columns (two wavefront rows)
+  constexpr int NBM = 2 * TPM, NBN = 4 * TPN / WC;
+  constexpr int OPERA = TPM * PK_CHUNK, BUF = (TPM + TPN) * PK_CHUNK;  // BF16 values
+  constexpr int GROUPS = (TPM + TPN) * PK_CHUNK / 512;  // 1 KB groups of a k-tile (64 lanes x 16 bytes)
+  constexpr int GPW = GROUPS / (RING_NT / 64);          // groups per wavefront
+  static_assert(GROUPS % (RING_NT / 64) == 0 && PK_CHUNK % 512 == 0, "k-tile groups per wavefront");
+  extern __shared__ __attribute__((aligned(16))) __bf16 ring_lds[];
+  const int tile = xcd_tile(blockIdx.x, total);
+  const SplitProb& p = probs[tile_prob[tile]];
+  int tm, tn;
+  x6_tile(p, tile - p.begin, tm, tn);
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wrow = (wave / WC) * 32 * TPM, wcol = (wave % WC) * 16 * NBN;
+  const int lr = lane & 15, lo = lane >> 4;
+  const int64_t pstride = (int64_t)p.ktiles * PK_CHUNK;
+  const __bf16* Ag = static_cast<const __bf16*>(p.A) + (int64_t)(TPM * tm) * pstride;
+  const __bf16* Bg = static_cast<const __bf16*>(p.B) + (int64_t)(TPN * tn) * pstride;
+
+  // k-tile kt into ring buffer buf: group g (1 KB) of the tile's operands is copied by
+  // wavefront g % 8, lane l taking its 16 bytes l
+  auto issue = [&](int kt, int buf) {
+#pragma unroll
+    for (int u = 0; u < GPW; ++u) {
+      const int g = wave + (RING_NT / 64) * u;
+      const int e = g * 64;  // first 16-byte piece of the group
+      const __bf16* src = e < TPM * (PK_CHUNK / 8)
+                              ? Ag + (e / (PK_CHUNK / 8)) * pstride + (int64_t)kt * PK_CHUNK + (e % (PK_CHUNK / 8)) * 8
+                              : Bg + ((e - TPM * (PK_CHUNK / 8)) / (PK_CHUNK / 8)) * pstride + (int64_t)kt * PK_CHUNK +
+                                    ((e - TPM * (PK_CHUNK / 8)) % (PK_CHUNK / 8)) * 8;
+      __builtin_amdgcn_global_load_lds(src + lane * 8, ring_lds + buf * BUF + e * 8, 16, 0, 0);
+    }
+  };
+
+  double acc[NBM][NBN][4];
+#pragma unroll
+  for (int i = 0; i < NBM; ++i)
+#pragma unroll
+    for (int j = 0; j < NBN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+  f4 c[NBM][NBN];
+#pragma unroll
+  for (int i = 0; i < NBM; ++i)
+#pragma unroll
+    for (int j = 0; j < NBN; ++j) c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  auto frag = [&](int off, int s, int blk) {
+    const int trow = off + blk * 16;
+    const int row = (trow & 63) + lr;
+    return (trow >> 6) * PK_CHUNK + (s * PK_R + row) * PK_K + pk_phys(lo, row) * 8;
+  };
+
+  const int nk = p.ktiles;
+  if (nk > 0) issue(0, 0);
+  if (nk > 1) issue(1, 1);
+  for (int kt = 0; kt < nk; ++kt) {
+    // this wavefront's pieces of k-tile kt are in (at most k-tile kt + 1 still
+    // loading), then a bare barrier: __syncthreads would also wait for the loads of
+    // kt + 1
+    if (kt + 1 < nk)
+      __builtin_amdgcn_s_waitcnt(0x0f70 | GPW);  // vmcnt(GPW); expcnt, lgkmcnt not waited on
+    else
+      __builtin_amdgcn_s_waitcnt(0x0f70);        // vmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    if (kt + 2 < nk) issue(kt + 2, (kt + 2) % RING_NBUF);
+    const __bf16* As = ring_lds + (kt % RING_NBUF) * BUF;
+    const __bf16* Bs = As + OPERA;
+    bf8 bv[PK_S][NBN];
+#pragma unroll
+    for (int s = 0; s < PK_S; ++s)
+#pragma unroll
+      for (int j = 0; j < NBN; ++j) bv[s][j] = *reinterpret_cast<const bf8*>(Bs + frag(wcol, s, j));
+#pragma unroll
+    for (int sa = PK_S - 1; sa >= 0; --sa) {
+      bf8 av[NBM];
+#pragma unroll
+      for (int i = 0; i < NBM; ++i) av[i] = *reinterpret_cast<const bf8*>(As + frag(wrow, sa, i));
+#pragma unroll
+      for (int sb = PK_S - 1 - sa; sb >= 0; --sb)
+#pragma unroll
+        for (int i = 0; i < NBM; ++i)
+#pragma unroll
+          for (int j = 0; j < NBN; ++j)
+            c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[sb][j], c[i][j], 0, 0, 0);
+    }
+    if ((kt + 1) % X_FLUSH == 0 || kt + 1 == nk) {
+#pragma unroll
+      for (int i = 0; i < NBM; ++i)
+#pragma unroll
+        for (int j = 0; j < NBN; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)c[i][j][r];
+          c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  }
+
   const int row0 = tm * 64 * TPM + wrow, col0 = tn * 64 * TPN + wcol;
 #pragma unroll
   for (int i = 0; i < NBM; ++i)
@@ -401,14 +536,24 @@ static void f64_packed(const SplitProb* d_probs, const int* d_tile_prob, int til
   gemm_f64_packed<TPM, TPN><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
 }
 template <int TPM, int TPN>
+static void x6_ring(const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
+  const size_t lds = (size_t)RING_NBUF * (TPM + TPN) * PK_CHUNK * sizeof(__bf16);
+  static bool attr = false;
+  if (!attr) {
+    set_lds_limit(gemm_x6_ring<TPM, TPN>, lds);
+    attr = true;
+  }
+  gemm_x6_ring<TPM, TPN><<<tiles, RING_NT, lds, s>>>(d_probs, d_tile_prob, tiles);
+}
+template <int TPM, int TPN, int NT = XNT>
 static void x6_packed(const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
   const size_t lds = (size_t)2 * (TPM + TPN) * PK_CHUNK * sizeof(__bf16);
   static bool attr = false;
   if (!attr) {
-    set_lds_limit(gemm_x6_packed<TPM, TPN>, lds);
+    set_lds_limit(gemm_x6_packed<TPM, TPN, NT>, lds);
     attr = true;
   }
-  gemm_x6_packed<TPM, TPN><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
+  gemm_x6_packed<TPM, TPN, NT><<<tiles, NT, lds, s>>>(d_probs, d_tile_prob, tiles);
 }
 
 void launch_gemm_f64_packed(int tpm, int tpn, const SplitProb* d_probs, const int* d_tile_prob, int tiles,
@@ -423,7 +568,7 @@ void launch_gemm_f64_packed(int tpm, int tpn, const SplitProb* d_probs, const in
 void launch_gemm_x6_packed(int tpm, int tpn, const SplitProb* d_probs, const int* d_tile_prob, int tiles,
                            hipStream_t s) {
   if (tiles <= 0) return;
-  if (tpm == 2 && tpn == 2) x6_packed<2, 2>(d_probs, d_tile_prob, tiles, s);
+  if (tpm == 2 && tpn == 2) x6_ring<2, 2>(d_probs, d_tile_prob, tiles, s);
   else if (tpm == 2) x6_packed<2, 1>(d_probs, d_tile_prob, tiles, s);
   else if (tpn == 2) x6_packed<1, 2>(d_probs, d_tile_prob, tiles, s);
   else x6_packed<1, 1>(d_probs, d_tile_prob, tiles, s);
