@@ -629,7 +629,7 @@ __global__ __launch_bounds__(TB_NT) void tb_reduce(EighLarge e) {
 // ---------------------------------------------------------------------------
 constexpr int TR_NT = 512;
 constexpr int TR_Q = 5;    // columns per thread
-constexpr int TR_R = 10;   // own rows per workgroup
+constexpr int TR_R = 9;    // own rows per workgroup
 constexpr int TR_W = TR_NT / 64;
 
 // Reflector c from register row c (entries j >= c + 1 valid): alpha = row[c+1],
@@ -751,12 +751,34 @@ __device__ bool tr_take(const double* p, const double* rb, int lo, int n, double
 //     p_{k+1} entry first, so it sees the empty slot or the new value, never the old.
 // A workgroup leaves after the last step that updates one of its rows; the owner of
 // row n - 1 takes every step and stores the reflectors and T.
+// The parts of reflector column c of Y that are not owned rows below row c + 1: the
+// zeros in rows (k0, c] of its compact-WY block, tau_c in the last column, d_c and e_c
+// of T (stored by the keeper after its p entries, off the critical path).  Every owner
+// of a row i > c stores v_i itself.
+__device__ __forceinline__ void tr_store_reflector_head(EighLarge& e, double tau, double beta, double dc, int c) {
+  // n as an opaque value here, so that the row offsets are not held across steps
+  int n = e.n;
+  asm volatile("" : "+s"(n));
+  const int k0 = (c / TB_NBW) * TB_NBW;
+#pragma unroll
+  for (int q = 0; q < TR_Q; ++q) {
+    const int j = threadIdx.x + TR_NT * q;
+    if (j >= k0 + 1 && j <= c) e.Vw[(size_t)j * n + c] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    e.Vw[(size_t)c * n + (n - 1)] = tau;
+    e.e[c] = beta;
+    e.d[c] = dc;
+  }
+}
+
 __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
   extern __shared__ double sm[];
   __shared__ double red1[TR_W], red2[TR_W], red3[TR_W][TR_R];
-  __shared__ double s_pk1, s_alpha;
-  __shared__ double pown[TR_R];
-  const int n = e.n, G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double s_pk1, s_alpha, s_dk;
+  __shared__ double pown[TR_R], vow[TR_R];  // p and v at the own rows updated in the next step
+  const int n = e.n, G = gridDim.x, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // scalar: LDS slots addressed without VGPRs
   const bool keeper = g == (n - 1) % G;  // owns row n - 1
   const int last_row = g + G * ((n - 1 - g) / G);
   double* vfull = sm;  // the reflector of the step (n), read for the own rows
@@ -815,20 +837,19 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
       for (int r = 0; r < TR_R; ++r) red3[wave][r] = acc[r];
     __syncthreads();
     if (tid < TR_R) {
-      const int i = g + G * tid;
+      int i = g + G * tid;
+      asm volatile("" : "+v"(i));
       double t = 0.0;
       for (int w = 0; w < TR_W; ++w) t += red3[w][tid];
-      pown[tid] = tau * t;
+      pown[tid] = (i >= 2 && i < n) ? tau * t : 0.0;  // rows updated in step 0
       if (i >= 1 && i < n) tb_put(&e.pv[i], tau * t);
     }
   }
-  __syncthreads();
-  double vown[TR_R];
-#pragma unroll
-  for (int r = 0; r < TR_R; ++r) {
-    const int i = g + G * r;
-    vown[r] = i < n ? vfull[i] : 0.0;
+  if (tid < TR_R) {
+    const int i = g + G * tid;
+    vow[tid] = (i >= 2 && i < n) ? vfull[i] : 0.0;  // rows updated in step 0
   }
+  __syncthreads();
 
   const int k_end = min(n - 2, last_row - 1);  // steps k < k_end update an own row
   for (int k = 0; k < k_end; ++k) {
@@ -839,7 +860,9 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
     // slots no reader needs any more: own entries of p_{k-1}, and row k
     {
       double* pold = e.pv + (size_t)((k + 2) % 3) * n;
-      if (tid < TR_R && g + G * tid < n) tr_clear(&pold[g + G * tid]);
+      int own = g + G * tid;  // opaque: formed here, not held in registers across the steps
+      asm volatile("" : "+v"(own));
+      if (tid < TR_R && own < n) tr_clear(&pold[own]);
       if (k + 3 < n && (k + 3) % G == g) {
         double* rold = e.rowbuf + (size_t)(k % 3) * n;
 #pragma unroll
@@ -870,14 +893,14 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
       wv[q] = pj[q] + K * vc[q];
       row[q] = rj[q] - (wv[q] + wk1 * vc[q]);  // row k + 1 after this step
     }
-    double wown[TR_R];
-#pragma unroll
-    for (int r = 0; r < TR_R; ++r) wown[r] = pown[r] + K * vown[r];
     // reflector k + 1 from row k + 1
     double taun = 0.0;
     if (k + 1 <= n - 3) {
       taun = tr_reflector(row, k + 1, n, vn, red2, &s_alpha, beta);
-      if (keeper) tr_store_reflector(e, vn, taun, beta, k + 1, row);
+      if (keeper)
+#pragma unroll
+        for (int q = 0; q < TR_Q; ++q)
+          if (tid + TR_NT * q == k + 1) s_dk = row[q];  // d_{k+1}
 #pragma unroll
       for (int q = 0; q < TR_Q; ++q) {
         const int j = tid + TR_NT * q;
@@ -894,25 +917,24 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
     }
     // own rows i >= k + 2, columns j >= k + 2: a_ij -= v_i w_j + w_i v_j, and the
     // partial sums of p_{k+1} = tau_{k+1} A v_{k+1}
+    // Branch-free: vow and pown are zero for rows below k + 2 (and past n), v_k and
+    // w_k are zero in columns below k + 1 (and past n), and v_{k+1} below k + 2, so
+    // only the trailing block changes, except column k + 1 of the own rows, which no
+    // later step reads.
     const int rnext = k + 2;
     double acc[TR_R];
 #pragma unroll
     for (int r = 0; r < TR_R; ++r) {
-      const int i = g + G * r;
+      const double vo = vow[r], wo = pown[r] + K * vo;
       acc[r] = 0.0;
-      if (i >= rnext && i < n) {
 #pragma unroll
-        for (int q = 0; q < TR_Q; ++q) {
-          const int j = tid + TR_NT * q;
-          if (j >= rnext && j < n) {
-            a[r][q] -= vown[r] * wv[q] + wown[r] * vc[q];
-            acc[r] += a[r][q] * vn[q];
-            if (k == n - 3 && i == n - 1 && j == n - 1) e.d[n - 1] = a[r][q];
-          }
-        }
+      for (int q = 0; q < TR_Q; ++q) {
+        a[r][q] -= vo * wv[q] + wo * vc[q];
+        acc[r] += a[r][q] * vn[q];
       }
-      acc[r] = tl_wave_sum(acc[r]);
     }
+#pragma unroll
+    for (int r = 0; r < TR_R; ++r) acc[r] = tl_wave_sum(acc[r]);
     if (lane == 0)
 #pragma unroll
       for (int r = 0; r < TR_R; ++r) red3[wave][r] = acc[r];
@@ -920,10 +942,11 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (tid < TR_R) {
-      const int i = g + G * tid;
+      int i = g + G * tid;
+      asm volatile("" : "+v"(i));
       double t = 0.0;
       for (int w = 0; w < TR_W; ++w) t += red3[w][tid];
-      pown[tid] = taun * t;
+      pown[tid] = (i >= rnext + 1 && i < n) ? taun * t : 0.0;  // rows updated in step k + 1
       if (i >= rnext && i < n) tb_put(&e.pv[(size_t)((k + 1) % 3) * n + i], taun * t);
     }
     // the look-ahead row k + 2, stored by its owner
@@ -942,11 +965,23 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
 #pragma unroll
     for (int q = 0; q < TR_Q; ++q) vc[q] = vn[q];
     tau = taun;
-#pragma unroll
-    for (int r = 0; r < TR_R; ++r) {
-      const int i = g + G * r;
-      vown[r] = i < n ? vfull[i] : 0.0;
+    // v_{k+1} at the own rows: kept for step k + 1, and stored as reflector column
+    // k + 1 (rows i >= k + 2); the rest of the column and T by the keeper
+    if (tid < TR_R) {
+      int i = g + G * tid;
+      asm volatile("" : "+v"(i));
+      vow[tid] = (i >= rnext + 1 && i < n) ? vfull[i] : 0.0;  // rows updated in step k + 1
+      if (k + 1 <= n - 3 && i >= k + 2 && i < n) e.Vw[(size_t)i * n + (k + 1)] = vfull[i];
     }
+    if (keeper && k + 1 <= n - 3) tr_store_reflector_head(e, taun, beta, s_dk, k + 1);
+  }
+  // the last diagonal entry of T: row n - 1, column n - 1 after the last step
+  if (keeper && tid == (n - 1) % TR_NT) {
+#pragma unroll
+    for (int r = 0; r < TR_R; ++r)
+#pragma unroll
+      for (int q = 0; q < TR_Q; ++q)
+        if (g + G * r == n - 1 && q == (n - 1) / TR_NT) e.d[n - 1] = a[r][q];
   }
   // reached only when no wait aborted
   if (keeper && tid == 0 && __hip_atomic_load(&e.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)

@@ -51,6 +51,29 @@ __device__ __forceinline__ double tl_quad_sum(double v) {
   v += tl_dpp<0x4E>(v);  // quad_perm [2,3,0,1]
   return v;
 }
+// N independent wavefront sums, each DPP stage applied to all N values before the
+// next (so that their latencies overlap); same lane order as tl_wave_sum
+template <int N>
+__device__ __forceinline__ void tl_wave_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] += tl_dpp<0xB1>(v[r]);
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] += tl_dpp<0x4E>(v[r]);
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] += tl_dpp<0x141>(v[r]);
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] += tl_dpp<0x140>(v[r]);
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] += tl_dpp<0x142, 0xa>(v[r]);
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] += tl_dpp<0x143, 0xc>(v[r]);
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v[r]), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v[r]), 63);
+    v[r] = __hiloint2double(hi, lo);
+  }
+}
 __device__ __forceinline__ double tl_wave_sum(double v) {
   v = tl_quad_sum(v);
   v += tl_dpp<0x141>(v);       // row_half_mirror: sums of 8 lanes
