@@ -98,7 +98,9 @@ typedef struct {
   const int32_t *N;       /* host [n_inst]: REAL_OV: occupied count 0 <= N <= M;
                              COMPLEX_FULL: ignored */
   int32_t kind;           /* etdm_kind */
-  int32_t precision;      /* etdm_precision (COMPLEX_FULL supports ETDM_FP64 only) */
+  int32_t precision;      /* etdm_precision (COMPLEX_FULL: ETDM_FP64, ETDM_BF16X6 or ETDM_MIXED;
+                             its split products are real products of the real views of the
+                             interleaved complex operands) */
   double hubbard_U;       /* U_hub of the model functional */
   int32_t couple;         /* 1: Hubbard term on sum_k w_k diag(rho_k) (needs equal M) */
   const double *weights;  /* host [n_inst] k-point weights, NULL = all 1 */

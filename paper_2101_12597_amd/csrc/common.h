@@ -60,6 +60,11 @@ struct PackJob {
   int64_t ld;
   double alpha;
   int32_t trans, rows, K, kt0, ktiles, kt_n, begin;
+  // complex operands (interleaved, ld in complex elements) packed as their real view:
+  // cplx 1: op(A) (m x k) as the m x 2k matrix [Re a_il, Im a_il]; cplx 2: op(B) (k x n)
+  // as the rows of the 2k x 2n matrix [[Re, Im], [-Im, Re]] transposed, so that the real
+  // product of the two is the interleaved complex product; op is OP_N, OP_T or OP_C
+  int32_t cplx, op;
 };
 // C (m x n, FP64) = sum over k of A[i][k] B[j][k] + beta D for packed A (m rows) and
 // B (n rows) with ktiles k-tiles, in tiles of tpm x tpn panels (64 tpm rows, 64 tpn

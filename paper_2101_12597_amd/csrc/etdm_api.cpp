@@ -106,19 +106,27 @@ struct Stage {
     tile_prob.resize(tiles, (int32_t)probs.size());
     probs.push_back(p);
   }
-  bool can_pack() const { return !cplx && (prec == GP_BF16X6 || prec == GP_FP64) && !probs.empty(); }
+  // packed kernels: real FP64 / BF16x6, and complex BF16x6 through the real view of
+  // the complex product (the complex FP64 stages keep the grouped complex kernel)
+  bool can_pack() const {
+    return (cplx ? prec == GP_BF16X6 : (prec == GP_BF16X6 || prec == GP_FP64)) && !probs.empty();
+  }
+  // the real view of a problem: complex op(A) (m x k) -> m x 2k, op(B) (k x n) ->
+  // 2k x 2n, C (m x n) -> m x 2n doubles
+  int view_n(const GemmProb& p) const { return cplx ? 2 * p.n : p.n; }
   size_t chunk_bytes() const {
     return prec == GP_FP64 ? (size_t)PK_CHUNK_64 * sizeof(double) : (size_t)PK_CHUNK_X6 * sizeof(__bf16);
   }
-  static int ktiles(const GemmProb& p) {
-    return ceil_div(std::max(p.k, 0), PK_K) + ceil_div(std::max(p.k2, 0), PK_K);
+  int ktiles(const GemmProb& p) const {
+    const int f = cplx ? 2 : 1;
+    return ceil_div(f * std::max(p.k, 0), PK_K) + ceil_div(f * std::max(p.k2, 0), PK_K);
   }
   static int panels(int rows, int tp) { return tp * ceil_div(rows, PK_R * tp); }
   // bytes of the packed operands of all problems for packed variant v
   size_t pack_bytes(int v) const {
     size_t n = 0;
     for (const GemmProb& p : probs)
-      n += (size_t)(panels(p.m, kVarTpm[v]) + panels(p.n, kVarTpn[v])) * ktiles(p) * chunk_bytes();
+      n += (size_t)(panels(p.m, kVarTpm[v]) + panels(view_n(p), kVarTpn[v])) * ktiles(p) * chunk_bytes();
     return n;
   }
   // pack jobs and packed problems of packed variant v with the operands at arena
@@ -129,7 +137,7 @@ struct Stage {
     const size_t chunk = chunk_bytes();
     size_t off = 0;
     auto job = [&](const double* src, char* dst, int64_t ld, double alpha, bool trans, int rows, int K,
-                   int kt0, int kt, int np) {
+                   int kt0, int kt, int np, int zmode, int zop) {
       if (K <= 0) return;
       PackJob j;
       j.src = src;
@@ -137,6 +145,8 @@ struct Stage {
       j.ld = ld;
       j.alpha = alpha;
       j.trans = trans ? 1 : 0;
+      j.cplx = zmode;
+      j.op = zop;
       j.rows = rows;
       j.K = K;
       j.kt0 = kt0;
@@ -147,31 +157,34 @@ struct Stage {
       q.chunk_job.resize(q.chunks, (int32_t)q.jobs.size());
       q.jobs.push_back(j);
     };
+    const int f = cplx ? 2 : 1;  // doubles per element along k and n
     for (const GemmProb& p : probs) {
-      const int kt = ktiles(p), kt1 = ceil_div(std::max(p.k, 0), PK_K);
-      const int pa = panels(p.m, tpm), pb = panels(p.n, tpn);
+      const int kt = ktiles(p), kt1 = ceil_div(f * std::max(p.k, 0), PK_K);
+      const int nv = view_n(p);
+      const int pa = panels(p.m, tpm), pb = panels(nv, tpn);
       char* a = arena + off;
       off += (size_t)pa * kt * chunk;
       char* b = arena + off;
       off += (size_t)pb * kt * chunk;
       // op(A)[i][k] = TA ? A[k][i] : A[i][k];  op(B)^T[j][k] = TB ? B[j][k] : B[k][j]
-      job(p.A, a, p.lda, p.alpha, opA == OP_T, p.m, p.k, 0, kt, pa);
-      job(p.B, b, p.ldb, 1.0, opB != OP_T, p.n, p.k, 0, kt, pb);
-      job(p.A2, a, p.lda2, p.alpha2, opA == OP_T, p.m, p.k2, kt1, kt, pa);
-      job(p.B2, b, p.ldb2, 1.0, opB != OP_T, p.n, p.k2, kt1, kt, pb);
+      const int za = cplx ? 1 : 0, zb = cplx ? 2 : 0;
+      job(p.A, a, p.lda, p.alpha, opA == OP_T, p.m, f * p.k, 0, kt, pa, za, opA);
+      job(p.B, b, p.ldb, 1.0, opB != OP_T, nv, f * p.k, 0, kt, pb, zb, opB);
+      job(p.A2, a, p.lda2, p.alpha2, opA == OP_T, p.m, f * p.k2, kt1, kt, pa, za, opA);
+      job(p.B2, b, p.ldb2, 1.0, opB != OP_T, nv, f * p.k2, kt1, kt, pb, zb, opB);
       SplitProb sp;
       sp.A = a;
       sp.B = b;
       sp.D = p.D;
       sp.C = p.C;
-      sp.ldc = p.ldc;
-      sp.ldd = p.ldd;
+      sp.ldc = f * p.ldc;
+      sp.ldd = f * p.ldd;
       sp.beta = p.beta;
       sp.m = p.m;
-      sp.n = p.n;
+      sp.n = nv;
       sp.ktiles = kt;
       sp.tiles_m = ceil_div(p.m, PK_R * tpm);
-      sp.tiles_n = ceil_div(p.n, PK_R * tpn);
+      sp.tiles_n = ceil_div(nv, PK_R * tpn);
       sp.begin = q.tiles;
       q.tiles += sp.tiles_m * sp.tiles_n;
       q.tile_prob.resize(q.tiles, (int32_t)q.probs.size());
@@ -182,14 +195,15 @@ struct Stage {
   // problem fills them and its K is long enough to amortize the pack
   int variant_by_size() const {
     for (const GemmProb& p : probs)
-      if (p.m < 128 || p.n < 128 || p.k + std::max(p.k2, 0) < 256) return V_TILE64;
+      if (p.m < 128 || p.n < 128 || p.k + std::max(p.k2, 0) < 256) return cplx ? V_P11 : V_TILE64;
     return V_P22;
   }
   const char* variant_name() const {
     static const char* real[V_COUNT] = {"tile64", "packed64", "packed128x64", "packed64x128", "packed128"};
     static const char* f64[V_COUNT] = {"fp64_tile64", "fp64_packed64", "fp64_packed128x64", "fp64_packed64x128",
                                        "fp64_packed128"};
-    if (cplx) return "zgemm64";
+    static const char* zx6[V_COUNT] = {"", "zx6_packed64", "zx6_packed128x64", "zx6_packed64x128", "zx6_packed128"};
+    if (cplx) return prec == GP_BF16X6 ? zx6[variant] : "zgemm64";
     return prec == GP_FP64 ? f64[variant] : real[variant];
   }
   void launch(hipStream_t s) const {
@@ -698,7 +712,7 @@ etdm_status plan_packed_stages(etdm_handle* h, Stage* const* stages, size_t n) {
     }
     switch (h->gemm_tuning) {
       case 2: sg.variant = V_P22; break;
-      case 3: sg.variant = V_TILE64; break;
+      case 3: sg.variant = sg.cplx ? V_P11 : V_TILE64; break;  // complex BF16x6: packed only
       case 4: sg.variant = V_P11; break;
       case 5: sg.variant = V_P21; break;
       case 6: sg.variant = V_P12; break;
@@ -721,8 +735,10 @@ etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
   all.insert(all.end(), h->tune_extra.begin(), h->tune_extra.end());
   for (Stage* sg : all) {
     if (!sg || !sg->can_pack()) continue;
-    int best = V_TILE64;
-    for (int v = 0; v < V_COUNT && st == ETDM_OK; ++v) {
+    // a complex BF16x6 stage has no grouped split kernel: its packed variants only
+    const int v0 = sg->cplx ? V_P11 : V_TILE64;
+    int best = v0;
+    for (int v = v0; v < V_COUNT && st == ETDM_OK; ++v) {
       sg->variant = v;
       sg->launch(s);
       float ms = 0.f;
@@ -1105,14 +1121,21 @@ etdm_status build_z_plan(etdm_handle* h) {
   std::vector<const double*> n0ptr;
   h->z_HG.init(OP_T, OP_N, GP_FP64, false);
   h->z_HNS.init(OP_N, OP_N, GP_FP64, false);
-  h->z_Ue.init(OP_N, OP_C, GP_FP64, true);
-  h->z_C.init(OP_N, OP_N, GP_FP64, true);
-  h->z_T.init(OP_N, OP_N, GP_FP64, true);
-  h->z_HMO.init(OP_C, OP_N, GP_FP64, true);
-  h->z_LV.init(OP_N, OP_N, GP_FP64, true);
-  h->z_Lt.init(OP_C, OP_N, GP_FP64, true);
-  h->z_W1.init(OP_N, OP_C, GP_FP64, true);
-  h->z_Y.init(OP_N, OP_N, GP_FP64, true);
+  // precision by role, as on the real path: the gradient-only products (L V, V^H L V,
+  // the divided-difference product and Y) split in the mixed mode; the ones E depends
+  // on (exp(A), C, H0 C, H_MO) when every k-point has M >= ETDM_MIXED_SPLIT_E_MIN_N
+  bool all_large = h->n_inst > 0;
+  for (int i = 0; i < h->n_inst; ++i) all_large = all_large && h->M[i] >= ETDM_MIXED_SPLIT_E_MIN_N;
+  const int zep = h->prec == ETDM_BF16X6 || (h->prec == ETDM_MIXED && all_large) ? GP_BF16X6 : GP_FP64;
+  const int zgp = h->prec == ETDM_BF16X6 || h->prec == ETDM_MIXED ? GP_BF16X6 : GP_FP64;
+  h->z_Ue.init(OP_N, OP_C, zep, true);
+  h->z_C.init(OP_N, OP_N, zep, true);
+  h->z_T.init(OP_N, OP_N, zep, true);
+  h->z_HMO.init(OP_C, OP_N, zep, true);
+  h->z_LV.init(OP_N, OP_N, zgp, true);
+  h->z_Lt.init(OP_C, OP_N, zgp, true);
+  h->z_W1.init(OP_N, OP_C, zgp, true);
+  h->z_Y.init(OP_N, OP_N, zgp, true);
   h->z_HC0.init(OP_N, OP_N, GP_FP64, true);
   h->z_odd.init(OP_C, OP_N, GP_FP64, true);
   h->z_rho.init(OP_N, OP_C, GP_FP64, true);
@@ -1389,6 +1412,11 @@ etdm_status build_z_plan(etdm_handle* h) {
   Stage* stages[] = {&h->z_Ue, &h->z_C,   &h->z_T,  &h->z_HMO, &h->z_LV,  &h->z_Lt, &h->z_W1,
                      &h->z_Y,  &h->z_HC0, &h->z_HG, &h->z_HNS, &h->z_odd, &h->z_rho};
   for (Stage* sg : stages) CHECK(upload_stage(h, *sg));
+  {
+    // the split complex stages run packed (real view of the complex product)
+    Stage* zs[] = {&h->z_Ue, &h->z_C, &h->z_T, &h->z_HMO, &h->z_LV, &h->z_Lt, &h->z_W1, &h->z_Y};
+    CHECK(plan_packed_stages(h, zs, sizeof(zs) / sizeof(zs[0])));
+  }
   CHECK(upload(h, &h->d_scale, scale));
   CHECK(upload(h, &h->b_scale, bscale));
   CHECK(upload(h, &h->d_fill, fill));
@@ -2115,7 +2143,9 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
   if (d->n_inst < 1 || !d->M) return ETDM_E_ARG;
   if (d->kind != ETDM_REAL_OV && d->kind != ETDM_COMPLEX_FULL) return ETDM_E_ARG;
   if (d->precision < ETDM_FP64 || d->precision > ETDM_MIXED) return ETDM_E_ARG;
-  if (d->kind == ETDM_COMPLEX_FULL && d->precision != ETDM_FP64) return ETDM_E_ARG;
+  if (d->kind == ETDM_COMPLEX_FULL && d->precision != ETDM_FP64 && d->precision != ETDM_BF16X6 &&
+      d->precision != ETDM_MIXED)
+    return ETDM_E_ARG;
   if (d->gemm_tuning < 0 || d->gemm_tuning > 6) return ETDM_E_ARG;
   if (d->gradient != 0 && d->gradient != 1) return ETDM_E_ARG;
   if (d->expm_method != 0 && d->expm_method != 1) return ETDM_E_ARG;

@@ -59,6 +59,21 @@ __device__ __forceinline__ int pk_phys(int oct, int row) {
 // ---------------------------------------------------------------------------
 // split_pack: one workgroup per (panel, k-tile) chunk of one job
 // ---------------------------------------------------------------------------
+// element (r, q) of the real view of a complex operand (PackJob::cplx 1 or 2)
+__device__ __forceinline__ double pack_zview(const PackJob& j, int r, int q) {
+  if (j.cplx == 1) {  // op(A)[r][l], component d
+    const int l = q >> 1, d = q & 1;
+    const int64_t idx = j.op == OP_N ? (int64_t)r * j.ld + l : (int64_t)l * j.ld + r;
+    const double x = j.src[2 * idx + d];
+    return (j.op == OP_C && d) ? -x : x;
+  }
+  // op(B)[l][c] = re + i im: rows 2c (re, -im) and 2c + 1 (im, re) along k = 2l + d
+  const int cc = r >> 1, e = r & 1, l = q >> 1, d = q & 1;
+  const int64_t idx = j.op == OP_N ? (int64_t)l * j.ld + cc : (int64_t)cc * j.ld + l;
+  const double re = j.src[2 * idx], im = j.op == OP_C ? -j.src[2 * idx + 1] : j.src[2 * idx + 1];
+  return e == d ? re : (e ? im : -im);
+}
+
 __global__ __launch_bounds__(256) void split_pack(const PackJob* __restrict__ jobs,
                                                   const int* __restrict__ chunk_job) {
   __shared__ double t[PK_R][PK_K + 1];
@@ -66,7 +81,13 @@ __global__ __launch_bounds__(256) void split_pack(const PackJob* __restrict__ jo
   const int c = blockIdx.x - j.begin;
   const int panel = c / j.kt_n, q = c % j.kt_n;
   const int r0 = panel * PK_R, k0 = q * PK_K;
-  if (!j.trans) {
+  if (j.cplx) {
+    for (int e = threadIdx.x; e < PK_R * PK_K; e += 256) {
+      const int r = e / PK_K, k = e % PK_K;
+      const int gr = r0 + r, gk = k0 + k;
+      t[r][k] = (gr < j.rows && gk < j.K) ? pack_zview(j, gr, gk) : 0.0;
+    }
+  } else if (!j.trans) {
     for (int e = threadIdx.x; e < PK_R * PK_K; e += 256) {
       const int r = e / PK_K, k = e % PK_K;
       const int gr = r0 + r, gk = k0 + k;

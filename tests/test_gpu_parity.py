@@ -238,6 +238,40 @@ def test_complex_full_matches_oracle(case):
     h.close()
 
 
+# Split precision on the complex path: the products run as real products of the
+# interleaved complex operands' real views ([Re, Im] against [[Re, Im], [-Im, Re]])
+# through the packed BF16x6 kernels; mixed splits the gradient-side products (M = 208 is
+# below the size at which the energy side splits), bf16x6 splits every bulk product.
+@pytest.mark.parametrize("tuning", [0, 2, 4])
+@pytest.mark.parametrize("case,precision", [("tiny_fd", "bf16x6"), ("odd_size", "mixed"),
+                                            ("config4_8k", "mixed"), ("config4_8k", "bf16x6")])
+def test_complex_split_precision(case, precision, tuning):
+    if case == "tiny_fd":
+        wl = tiny_complex(12, nk_side=2, kT=0.3)
+        for inst in wl.instances:
+            inst.A = inst.A * 6.0
+    elif case == "odd_size":
+        wl = tiny_complex(13, nk_side=1, kT=0.1)
+    else:
+        wl = make_config(4, nk=8)
+        wl.instances = wl.instances[:8]
+    params = O.parity_params(wl)
+    print(f"[case] complex_full {precision} {case} tuning={tuning}", flush=True)
+    h, _ = make_handle(wl, precision, gemm_tuning=tuning)
+    kernels = [k["kernel"] for k in h.stage_kernels() if k["kernel"]]
+    split = [v for v in kernels if v.startswith("zx6_")]
+    assert len(split) == (4 if precision == "mixed" else 8), kernels
+    E, G = energy_grad(h, wl, params)
+    h.close()
+    E_ref, G_ref = O.energy_grad(wl, params)
+    dE = abs(E[-1] - E_ref) / wl.n_electrons
+    dg = rel_err(G, G_ref)
+    el = max(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300) for a, b in zip(G, G_ref))
+    print(f"[result] complex {precision} {case} tuning={tuning}: |dE|/Ne = {dE:.3e}, rel |dg| = {dg:.3e}, "
+          f"element-wise {el:.3e}")
+    assert dE < 1e-8 and dg < 1e-6 and el < ELEM_TOL[precision]
+
+
 def test_status_and_argument_errors():
     import torch
     from paper_2101_12597_amd import EtdmError
