@@ -50,7 +50,7 @@ WORKLOADS = {
     4: "config 4: crystal 4x4x4 k-grid, M=208, complex, Fermi-Dirac f, k-coupled Hubbard",
     5: "config 5: 576-water box M=13248 N=2304, block-sparse H0, real",
 }
-DEFAULT_PREC = {1: "fp64", 2: "mixed", 3: "mixed", 4: "fp64", 5: "mixed"}
+DEFAULT_PREC = {1: "fp64", 2: "mixed", 3: "mixed", 4: "mixed", 5: "mixed"}
 
 
 def log(msg):

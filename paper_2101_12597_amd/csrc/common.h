@@ -68,7 +68,9 @@ struct PackJob {
 };
 // C (m x n, FP64) = sum over k of A[i][k] B[j][k] + beta D for packed A (m rows) and
 // B (n rows) with ktiles k-tiles, in tiles of tpm x tpn panels (64 tpm rows, 64 tpn
-// columns); begin = prefix sum of tiles, the tile table maps workgroups to problems.
+// columns); begin = prefix sum of tiles.  The tile table of a launch of `total` tiles
+// holds 2 total entries: [0, total) tile -> problem, [total, 2 total) workgroup ->
+// tile (the order in which the plan deals the tiles out to the XCDs).
 struct SplitProb {
   const void* A;
   const void* B;

@@ -81,6 +81,34 @@ struct PackPlan {
   int chunks = 0, tiles = 0;
 };
 
+// Workgroup -> tile order of a packed launch of T tiles, appended to its tile table.
+// Workgroup b runs on XCD b mod 8.  The tiles (problem after problem, each in its
+// grouped order) are dealt to the XCDs in chunks of 8 consecutive tiles, chunk j to
+// XCD j mod 8, so that every XCD gets a share of every problem (the problems of one
+// launch can differ several-fold in K) while neighbouring tiles, which share operand
+// panels, stay on one XCD's L2; then the lists are evened out to the workgroup count
+// of each XCD.
+inline void append_tile_order(std::vector<int32_t>& table, int T) {
+  constexpr int XCDS = 8, CH = 8;
+  std::vector<std::vector<int32_t>> lst(XCDS);
+  for (int t = 0; t < T; ++t) lst[(t / CH) % XCDS].push_back(t);
+  std::vector<int> want(XCDS);
+  for (int x = 0; x < XCDS; ++x) want[x] = T > x ? (T - x + XCDS - 1) / XCDS : 0;
+  std::vector<int32_t> spill;
+  for (int x = 0; x < XCDS; ++x)
+    while ((int)lst[x].size() > want[x]) {
+      spill.push_back(lst[x].back());
+      lst[x].pop_back();
+    }
+  for (int x = 0; x < XCDS; ++x)
+    while ((int)lst[x].size() < want[x]) {
+      lst[x].push_back(spill.back());
+      spill.pop_back();
+    }
+  table.resize((size_t)2 * T);
+  for (int b = 0; b < T; ++b) table[(size_t)T + b] = lst[b % XCDS][b / XCDS];
+}
+
 struct Stage {
   std::vector<GemmProb> probs;
   std::vector<int32_t> tile_prob;  // workgroup -> problem
@@ -190,6 +218,7 @@ struct Stage {
       q.tile_prob.resize(q.tiles, (int32_t)q.probs.size());
       q.probs.push_back(sp);
     }
+    append_tile_order(q.tile_prob, q.tiles);
   }
   // the fixed rule when no timing is wanted: 128 x 128 packed tiles when every
   // problem fills them and its K is long enough to amortize the pack

@@ -147,7 +147,7 @@ __global__ __launch_bounds__(NT) void gemm_x6_packed(const SplitProb* __restrict
   constexpr int NBM = 2 * TPM, NBN = 4 * TPN / WC;
   static_assert((TPM * 768) % NT == 0 && (TPN * 768) % NT == 0, "staging pieces per thread");
   extern __shared__ __attribute__((aligned(16))) __bf16 x6_lds[];
-  const int tile = xcd_tile(blockIdx.x, total);
+  const int tile = tile_prob[total + blockIdx.x];  // the plan's workgroup -> tile order
   const SplitProb& p = probs[tile_prob[tile]];
   int tm, tn;
   x6_tile(p, tile - p.begin, tm, tn);
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(RING_NT) void gemm_x6_ring(const SplitProb* __restr
   constexpr int GPW = GROUPS / (RING_NT / 64);          // groups per wavefront
   static_assert(GROUPS % (RING_NT / 64) == 0 && PK_CHUNK % 512 == 0, "k-tile groups per wavefront");
   extern __shared__ __attribute__((aligned(16))) __bf16 ring_lds[];
-  const int tile = xcd_tile(blockIdx.x, total);
+  const int tile = tile_prob[total + blockIdx.x];  // the plan's workgroup -> tile order
   const SplitProb& p = probs[tile_prob[tile]];
   int tm, tn;
   x6_tile(p, tile - p.begin, tm, tn);
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(XNT) void gemm_f64_packed(const SplitProb* __restri
                                                        const int* __restrict__ tile_prob, int total) {
   constexpr int NBM = 2 * TPM, NBN = 2 * TPN;
   extern __shared__ __attribute__((aligned(16))) double f64_lds[];
-  const int tile = xcd_tile(blockIdx.x, total);
+  const int tile = tile_prob[total + blockIdx.x];  // the plan's workgroup -> tile order
   const SplitProb& p = probs[tile_prob[tile]];
   int tm, tn;
   x6_tile(p, tile - p.begin, tm, tn);
