@@ -79,6 +79,27 @@ struct PackPlan {
   SplitProb* d_probs = nullptr;
   int32_t* d_tile_prob = nullptr;
   int chunks = 0, tiles = 0;
+  // operands that change only with the reference orbitals (C0, H0 C0, a dense H0),
+  // packed into an arena of their own when the reference changes, not per launch
+  std::vector<PackJob> sjobs;
+  std::vector<int32_t> schunk_job;
+  PackJob* d_sjobs = nullptr;
+  int32_t* d_schunk_job = nullptr;
+  int schunks = 0;
+};
+
+// Address ranges of the operands that change only with the reference orbitals.
+struct StaticRanges {
+  std::vector<std::pair<const double*, const double*>> r;
+  void add(const double* p, int64_t n) {
+    if (p && n > 0) r.push_back({p, p + n});
+  }
+  bool has(const double* p) const {
+    if (!p) return true;  // an absent operand does not make its panel dynamic
+    for (const auto& x : r)
+      if (p >= x.first && p < x.second) return true;
+    return false;
+  }
 };
 
 // Workgroup -> tile order of a packed launch of T tiles, appended to its tile table.
@@ -118,6 +139,9 @@ struct Stage {
   int opA = OP_N, opB = OP_N, prec = GP_FP64;
   bool cplx = false;
   int variant = V_TILE64;
+  char* arena = nullptr;                     // shared arena of the per-launch packs
+  bool has_static = false;                   // the chosen variant packs static operands apart
+  bool no_static = false;                    // forms a static operand itself (H0 C0): packs all per launch
   PackPlan pk[V_COUNT - 1];                  // the packed variants V_P11 .. V_P22
   float tuned_ms[V_COUNT] = {};              // plan-time launch times per variant (0: not timed)
   void init(int a, int b, int p, bool c = false) {
@@ -157,16 +181,36 @@ struct Stage {
       n += (size_t)(panels(p.m, kVarTpm[v]) + panels(view_n(p), kVarTpn[v])) * ktiles(p) * chunk_bytes();
     return n;
   }
-  // pack jobs and packed problems of packed variant v with the operands at arena
-  void plan_pack(int v, char* arena) {
+  // an operand panel (both K segments) is static when every source it packs is
+  bool a_static(const GemmProb& p, const StaticRanges* sr) const {
+    return sr && p.A && sr->has(p.A) && (p.k2 <= 0 || sr->has(p.A2));
+  }
+  bool b_static(const GemmProb& p, const StaticRanges* sr) const {
+    return sr && p.B && sr->has(p.B) && (p.k2 <= 0 || sr->has(p.B2));
+  }
+  // bytes of the static operand panels of packed variant v
+  size_t static_bytes(int v, const StaticRanges* sr) const {
+    size_t n = 0;
+    for (const GemmProb& p : probs) {
+      if (a_static(p, sr)) n += (size_t)panels(p.m, kVarTpm[v]) * ktiles(p) * chunk_bytes();
+      if (b_static(p, sr)) n += (size_t)panels(view_n(p), kVarTpn[v]) * ktiles(p) * chunk_bytes();
+    }
+    return n;
+  }
+  // pack jobs and packed problems of packed variant v with the operands at arena; with
+  // sr, the static operand panels go to sarena and their jobs to the static list
+  void plan_pack(int v, char* arena, const StaticRanges* sr = nullptr, char* sarena = nullptr) {
     const int tpm = kVarTpm[v], tpn = kVarTpn[v];
     PackPlan& q = pk[v - 1];
     q = PackPlan();
     const size_t chunk = chunk_bytes();
-    size_t off = 0;
+    size_t off = 0, soff = 0;
     auto job = [&](const double* src, char* dst, int64_t ld, double alpha, bool trans, int rows, int K,
-                   int kt0, int kt, int np, int zmode, int zop) {
+                   int kt0, int kt, int np, int zmode, int zop, bool stat) {
       if (K <= 0) return;
+      std::vector<PackJob>& jobs = stat ? q.sjobs : q.jobs;
+      std::vector<int32_t>& cj = stat ? q.schunk_job : q.chunk_job;
+      int& nch = stat ? q.schunks : q.chunks;
       PackJob j;
       j.src = src;
       j.dst = dst;
@@ -180,26 +224,27 @@ struct Stage {
       j.kt0 = kt0;
       j.ktiles = kt;
       j.kt_n = ceil_div(K, PK_K);
-      j.begin = q.chunks;
-      q.chunks += np * j.kt_n;
-      q.chunk_job.resize(q.chunks, (int32_t)q.jobs.size());
-      q.jobs.push_back(j);
+      j.begin = nch;
+      nch += np * j.kt_n;
+      cj.resize(nch, (int32_t)jobs.size());
+      jobs.push_back(j);
     };
     const int f = cplx ? 2 : 1;  // doubles per element along k and n
     for (const GemmProb& p : probs) {
       const int kt = ktiles(p), kt1 = ceil_div(f * std::max(p.k, 0), PK_K);
       const int nv = view_n(p);
       const int pa = panels(p.m, tpm), pb = panels(nv, tpn);
-      char* a = arena + off;
-      off += (size_t)pa * kt * chunk;
-      char* b = arena + off;
-      off += (size_t)pb * kt * chunk;
+      const bool sa = sarena && a_static(p, sr), sb = sarena && b_static(p, sr);
+      char* a = sa ? sarena + soff : arena + off;
+      (sa ? soff : off) += (size_t)pa * kt * chunk;
+      char* b = sb ? sarena + soff : arena + off;
+      (sb ? soff : off) += (size_t)pb * kt * chunk;
       // op(A)[i][k] = TA ? A[k][i] : A[i][k];  op(B)^T[j][k] = TB ? B[j][k] : B[k][j]
       const int za = cplx ? 1 : 0, zb = cplx ? 2 : 0;
-      job(p.A, a, p.lda, p.alpha, opA == OP_T, p.m, f * p.k, 0, kt, pa, za, opA);
-      job(p.B, b, p.ldb, 1.0, opB != OP_T, nv, f * p.k, 0, kt, pb, zb, opB);
-      job(p.A2, a, p.lda2, p.alpha2, opA == OP_T, p.m, f * p.k2, kt1, kt, pa, za, opA);
-      job(p.B2, b, p.ldb2, 1.0, opB != OP_T, nv, f * p.k2, kt1, kt, pb, zb, opB);
+      job(p.A, a, p.lda, p.alpha, opA == OP_T, p.m, f * p.k, 0, kt, pa, za, opA, sa);
+      job(p.B, b, p.ldb, 1.0, opB != OP_T, nv, f * p.k, 0, kt, pb, zb, opB, sb);
+      job(p.A2, a, p.lda2, p.alpha2, opA == OP_T, p.m, f * p.k2, kt1, kt, pa, za, opA, sa);
+      job(p.B2, b, p.ldb2, 1.0, opB != OP_T, nv, f * p.k2, kt1, kt, pb, zb, opB, sb);
       SplitProb sp;
       sp.A = a;
       sp.B = b;
@@ -234,6 +279,15 @@ struct Stage {
     static const char* zx6[V_COUNT] = {"", "zx6_packed64", "zx6_packed128x64", "zx6_packed64x128", "zx6_packed128"};
     if (cplx) return prec == GP_BF16X6 ? zx6[variant] : "zgemm64";
     return prec == GP_FP64 ? f64[variant] : real[variant];
+  }
+  // the static operand panels of the chosen variant (after a reference change)
+  void pack_static(hipStream_t s) const {
+    if (!has_static || variant == V_TILE64) return;
+    const PackPlan& q = pk[variant - 1];
+    if (prec == GP_FP64)
+      launch_copy_pack64(q.d_sjobs, q.d_schunk_job, q.schunks, s);
+    else
+      launch_split_pack(q.d_sjobs, q.d_schunk_job, q.schunks, s);
   }
   void launch(hipStream_t s) const {
     if (probs.empty()) return;
@@ -471,6 +525,9 @@ struct etdm_handle {
   Stage z_odd;           // W = VC^H C
   std::vector<Stage*> timer_stage;  // per timed stage: its GEMM launch, or null
   std::vector<Stage*> tune_extra;   // further stages with a kernel choice (inside a timed stage)
+  std::vector<Stage*> packed_stages;  // every stage with packed variants
+  std::vector<Stage*> static_stages;  // those whose chosen variant packs static operands apart
+  StaticRanges static_ranges;         // C0, H0 C0 and a dense H0 of every instance
   // tracing
   std::vector<StageTimer> timers;
   int64_t tmask = 0;
@@ -618,6 +675,11 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       // Dense H0: HC0 = H0 C0 is kept for the current reference (T = H0 C_occ is formed
       // from it); block-sparse H0: the preconditioner's H0 C0 shares the expm output
       b.HC0 = h->h0_format == 0 ? pl.take(M * M) : b.U;
+      h->static_ranges.add(b.C0, (int64_t)M * M);
+      if (h->h0_format == 0) {
+        h->static_ranges.add(b.H0, (int64_t)M * M);
+        h->static_ranges.add(b.HC0, (int64_t)M * M);
+      }
       b.HX = h->h0_format == 0 ? pl.take(M * N) : nullptr;
       b.HV = h->h0_format == 0 ? pl.take(M * N) : nullptr;
       b.n0 = pl.take(M);
@@ -639,6 +701,8 @@ size_t plan_buffers(etdm_handle* h, char* base) {
       b.G = h->grad_ws + h->par_off[i];
       b.C0 = pl.take(MM2);
       b.H0 = pl.take(MM2);
+      h->static_ranges.add(b.C0, (int64_t)MM2);
+      h->static_ranges.add(b.H0, (int64_t)MM2);
       b.f = pl.take(M);
       b.Hk = pl.take(MM2);
       b.V = pl.take(MM2);
@@ -731,6 +795,8 @@ etdm_status plan_packed_stages(etdm_handle* h, Stage* const* stages, size_t n) {
   for (size_t i = 0; i < n; ++i) {
     Stage& sg = *stages[i];
     if (!sg.can_pack()) continue;
+    sg.arena = arena;
+    h->packed_stages.push_back(&sg);
     for (int v = V_P11; v < V_COUNT; ++v) {
       sg.plan_pack(v, arena);
       PackPlan& q = sg.pk[v - 1];
@@ -789,6 +855,35 @@ etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
   return ETDM_OK;
 }
 
+// After the kernel choice: the stages whose chosen packed variant reads operands that
+// change only with the reference orbitals get those panels packed into an arena of
+// their own, once per reference (pack_static), instead of on every launch.
+etdm_status plan_static(etdm_handle* h) {
+  for (Stage* sg : h->packed_stages) {
+    if (sg->variant == V_TILE64 || sg->probs.empty() || sg->no_static) continue;
+    const size_t sb = sg->static_bytes(sg->variant, &h->static_ranges);
+    if (sb == 0) continue;
+    void* p = nullptr;
+    HIPCHK(h, hipMalloc(&p, sb));
+    h->dev_allocs.push_back(p);
+    sg->plan_pack(sg->variant, sg->arena, &h->static_ranges, reinterpret_cast<char*>(p));
+    PackPlan& q = sg->pk[sg->variant - 1];
+    CHECK(upload(h, &q.d_jobs, q.jobs));
+    CHECK(upload(h, &q.d_chunk_job, q.chunk_job));
+    CHECK(upload(h, &q.d_probs, q.probs));
+    CHECK(upload(h, &q.d_tile_prob, q.tile_prob));
+    CHECK(upload(h, &q.d_sjobs, q.sjobs));
+    CHECK(upload(h, &q.d_schunk_job, q.schunk_job));
+    sg->has_static = true;
+    h->static_stages.push_back(sg);
+  }
+  return ETDM_OK;
+}
+
+void pack_static(etdm_handle* h, hipStream_t s) {
+  for (const Stage* sg : h->static_stages) sg->pack_static(s);
+}
+
 // ----- plan of the real occupied-virtual path ------------------------------
 // Every product after the eigendecomposition is taken in the eigenbasis of P (see
 // ov.hip): V = X^T B, CX = C0_o X, CV = C0_v V^T, then the combination kernel and
@@ -819,6 +914,7 @@ etdm_status build_ov_plan(etdm_handle* h) {
   h->s_Uov.init(OP_N, OP_N, GP_FP64);
   h->s_Uvv.init(OP_T, OP_N, GP_FP64);
   h->s_HC0.init(OP_N, OP_N, GP_FP64);
+  h->s_HC0.no_static = true;  // it forms H0 C0 from C0 right after C0 changes
   h->s_rho.init(OP_N, OP_T, ep);
   std::vector<SymFill> fill, pfill;
   std::vector<int> bfill, bpfill;
@@ -1166,6 +1262,7 @@ etdm_status build_z_plan(etdm_handle* h) {
   h->z_W1.init(OP_N, OP_C, zgp, true);
   h->z_Y.init(OP_N, OP_N, zgp, true);
   h->z_HC0.init(OP_N, OP_N, GP_FP64, true);
+  h->z_HC0.no_static = true;  // it forms H0 C0 from C0 right after C0 changes
   h->z_odd.init(OP_C, OP_N, GP_FP64, true);
   h->z_rho.init(OP_N, OP_C, GP_FP64, true);
   std::vector<ScaleCols> scale;
@@ -1683,6 +1780,7 @@ void ov_new_reference(etdm_handle* h, hipStream_t s) {
   ov_orbitals(h, s, true);
   launch_c0_update(h->d_c0up, h->b_mat, h->n_inst, h->tot_mat, s);
   if (h->h0_format == 0) h->s_HC0.launch(s);  // H0 C0 for the new reference
+  pack_static(h, s);
 }
 
 // exp(A) by scaling and squaring (Eq. ss) into Ue.  The number of squarings is the
@@ -1920,6 +2018,7 @@ void new_reference(etdm_handle* h, hipStream_t s) {
   h->z_C.launch(s);
   for (int i = 0; i < h->n_inst; ++i)
     hipMemcpyAsync(h->zb[i].C0, h->zb[i].C, 2 * sizeof(double) * h->M[i] * h->M[i], hipMemcpyDeviceToDevice, s);
+  pack_static(h, s);
 }
 
 // ----- L-BFGS driver ---------------------------------------------------------------
@@ -2335,6 +2434,8 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
       hipHostMalloc(reinterpret_cast<void**>(&h->ss_s_host), sizeof(int)) != hipSuccess)
     st = ETDM_E_NOMEM;
   if (st == ETDM_OK && real && h->h0_format == 0) h->s_HC0.launch(s);  // H0 C0 of the reference
+  if (st == ETDM_OK) st = plan_static(h);
+  if (st == ETDM_OK) pack_static(h, s);
   if (st != ETDM_OK) return bail(st);
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) return bail(ETDM_E_HIP);
   *out = h;
@@ -2618,6 +2719,7 @@ etdm_status etdm_lbfgs_set_state(etdm_handle* h, const void* state, void* stream
     in += b;
   }
   build_hdiag(h, s);  // preconditioner (and H0 C0) of the restored reference orbitals
+  pack_static(h, s);   // and the packed panels of the restored reference
   HIPCHK(h, hipMemcpyAsync(h->lb_sum, h->lb_st, sizeof(LbState), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(s));
