@@ -334,8 +334,16 @@ constexpr unsigned long long TB_SPIN = 20000000ull;  // 0.2 s of the 100 MHz wal
 // value of the current step carry this signalling-NaN pattern; arithmetic never
 // produces a signalling NaN.
 constexpr unsigned long long TR_EMPTY = 0x7ff4a5a5a5a5a5a5ull;
-constexpr int TE_CH = 16;       // eigenvalues per workgroup in the eigenpair kernel
-constexpr int TE_NT = 1024;
+// Multisection: TE_CH eigenvalues per workgroup of TE_NT threads, TE_C chains per lane:
+// TE_C floor(TE_NT / TE_CH) = 25 points per eigenvalue and round (4.7 bits).  A Sturm
+// count is a chain of n dependent pivots (a reciprocal and a few FP64 operations each)
+// that occupies its SIMD's issue slots: one chain per lane (two measured 1.5x slower)
+// and about one wavefront per SIMD (n = 2304: 461 workgroups of two wavefronts, d and
+// e^2 in 37 KB of LDS) keep the round short.
+constexpr int TE_CH = 5;
+constexpr int TE_NT = 128;
+constexpr int TE_C = 1;
+static size_t tb_bisect_lds(int n) { return sizeof(double) * 2 * (size_t)n; }
 
 size_t eigh_large_workspace(int n, size_t* npad_out) {
   const size_t npad = (size_t)((n + SUB - 1) / SUB) * SUB;
@@ -691,8 +699,10 @@ __device__ __forceinline__ void tr_clear(double* p) {
 // Entries j = tid + TR_NT q, lo <= j < n, of p and rb (zero elsewhere), each polled
 // until it is no longer empty.  False for the whole workgroup when the grid aborts or
 // a wait exceeds TB_SPIN (which sets the abort word).
+// Also forms this wavefront's part of p . v_k into red1[wave] (and p_{k+1} into *pk1)
+// before the workgroup barrier that ends the wait, so that one barrier serves both.
 __device__ bool tr_take(const double* p, const double* rb, int lo, int n, double (&pj)[TR_Q], double (&rj)[TR_Q],
-                        unsigned* bar) {
+                        unsigned* bar, const double (&vc)[TR_Q], double* red1, double* pk1) {
   unsigned pend = 0u;
 #pragma unroll
   for (int q = 0; q < TR_Q; ++q) {
@@ -734,6 +744,14 @@ __device__ bool tr_take(const double* p, const double* rb, int lo, int n, double
     }
     __builtin_amdgcn_s_sleep(1);
   }
+  double part = 0.0;
+#pragma unroll
+  for (int q = 0; q < TR_Q; ++q) {
+    part += pj[q] * vc[q];
+    if ((int)threadIdx.x + TR_NT * q == lo) *pk1 = pj[q];
+  }
+  part = tl_wave_sum(part);
+  if ((threadIdx.x & 63) == 0) red1[threadIdx.x >> 6] = part;
   return !__syncthreads_or(fail);
 }
 
@@ -855,7 +873,8 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
   for (int k = 0; k < k_end; ++k) {
     // p_k and the look-ahead row k + 1 (as after step k - 1)
     double pj[TR_Q], rj[TR_Q];
-    if (!tr_take(e.pv + (size_t)(k % 3) * n, e.rowbuf + (size_t)((k + 1) % 3) * n, k + 1, n, pj, rj, e.bar))
+    if (!tr_take(e.pv + (size_t)(k % 3) * n, e.rowbuf + (size_t)((k + 1) % 3) * n, k + 1, n, pj, rj, e.bar, vc,
+                 red1, &s_pk1))
       return;
     // slots no reader needs any more: own entries of p_{k-1}, and row k
     {
@@ -872,16 +891,7 @@ __global__ __launch_bounds__(TR_NT) void tb_reduce_reg(EighLarge e) {
         }
       }
     }
-    // w = p - (tau / 2) (p . v) v
-    double part = 0.0;
-#pragma unroll
-    for (int q = 0; q < TR_Q; ++q) {
-      part += pj[q] * vc[q];
-      if (tid + TR_NT * q == k + 1) s_pk1 = pj[q];
-    }
-    part = tl_wave_sum(part);
-    if (lane == 0) red1[wave] = part;
-    __syncthreads();
+    // w = p - (tau / 2) (p . v) v, with p . v summed over the wavefronts' parts
     double dot = 0.0;
 #pragma unroll
     for (int w = 0; w < TR_W; ++w) dot += red1[w];
@@ -1003,60 +1013,68 @@ __global__ __launch_bounds__(TE_NT) void tb_bisect(EighLarge e) {
   __shared__ double red[TE_NT / 64];
   __shared__ double lo_s[TE_CH], hi_s[TE_CH];
   __shared__ int b0_s[TE_CH], b1_s[TE_CH];
-  __shared__ double xs[TE_NT];
-  __shared__ int cnt[TE_NT];
+  __shared__ double xs[TE_C * TE_NT];
+  __shared__ int cnt[TE_C * TE_NT];
   if (!*e.ok) return;  // the reduction aborted
   const int n = e.n, tid = threadIdx.x;
   double* d = sm;
-  double* ee = d + n;
-  double* e2 = ee + n;
-  for (int i = tid; i < n; i += TE_NT) {
-    d[i] = e.d[i];
-    ee[i] = i < n - 1 ? e.e[i] : 0.0;
-  }
-  __syncthreads();
+  double* e2 = d + n;
   double tn_loc = 0.0, e2_loc = 0.0;
   for (int i = tid; i < n; i += TE_NT) {
-    const double el = i > 0 ? fabs(ee[i - 1]) : 0.0, er = i < n - 1 ? fabs(ee[i]) : 0.0;
-    tn_loc = fmax(tn_loc, fabs(d[i]) + el + er);
-    e2[i] = ee[i] * ee[i];
-    e2_loc = fmax(e2_loc, e2[i]);
+    const double di = e.d[i], el = i > 0 ? fabs(e.e[i - 1]) : 0.0, er = i < n - 1 ? fabs(e.e[i]) : 0.0;
+    d[i] = di;
+    e2[i] = er * er;
+    tn_loc = fmax(tn_loc, fabs(di) + el + er);
+    e2_loc = fmax(e2_loc, er * er);
   }
   const double tn = block_max<TE_NT>(tn_loc, red);
   const double pivmin = DBL_MIN * fmax(1.0, block_max<TE_NT>(e2_loc, red));
   const double eps = DBL_EPSILON, split = eps * tn;
   const int j0 = blockIdx.x * TE_CH, m = min(TE_CH, n - j0);
-  if (tid < m) {
-    const int j = j0 + tid;
-    int b0 = j, b1 = j + 1;
-    while (b0 > 0 && fabs(ee[b0 - 1]) > split) --b0;
-    while (b1 < n && fabs(ee[b1 - 1]) > split) ++b1;
+  // per eigenvalue j: its unreduced block [b0, b1) (b0 the last split index <= j, b1 the
+  // first one > j; index i is a split where |e_{i-1}| <= eps ||T||) and the Gershgorin
+  // bounds of that block, by the whole workgroup
+  for (int jj = 0; jj < m; ++jj) {
+    const int j = j0 + jj;
+    double lo_i = 0.0, hi_i = n;
+    for (int i = tid + 1; i < n; i += TE_NT)
+      if (fabs(e.e[i - 1]) <= split) {
+        if (i <= j) lo_i = fmax(lo_i, (double)i);
+        else hi_i = fmin(hi_i, (double)i);
+      }
+    const int b0 = (int)block_max<TE_NT>(lo_i, red), b1 = (int)-block_max<TE_NT>(-hi_i, red);
     double gl = INFINITY, gu = -INFINITY;
-    for (int i = b0; i < b1; ++i) {
-      const double rr = (i > b0 ? fabs(ee[i - 1]) : 0.0) + (i < b1 - 1 ? fabs(ee[i]) : 0.0);
+    for (int i = b0 + tid; i < b1; i += TE_NT) {
+      const double rr = (i > b0 ? fabs(e.e[i - 1]) : 0.0) + (i < b1 - 1 ? fabs(e.e[i]) : 0.0);
       gl = fmin(gl, d[i] - rr);
       gu = fmax(gu, d[i] + rr);
     }
-    const double margin = 8.0 * n * eps * tn + 4.0 * pivmin;
-    lo_s[tid] = gl - margin;
-    hi_s[tid] = gu + margin;
-    b0_s[tid] = b0;
-    b1_s[tid] = b1;
+    gl = -block_max<TE_NT>(-gl, red);
+    gu = block_max<TE_NT>(gu, red);
+    if (tid == 0) {
+      const double margin = 8.0 * n * eps * tn + 4.0 * pivmin;
+      lo_s[jj] = gl - margin;
+      hi_s[jj] = gu + margin;
+      b0_s[jj] = b0;
+      b1_s[jj] = b1;
+    }
   }
   __syncthreads();
-  const int T = max(1, (TE_NT / 2) / max(m, 1)), K = 2 * T;
+  const int T = max(1, TE_NT / max(m, 1)), K = TE_C * T;
   for (int it = 0; it < TL_MAXIT; ++it) {
     if (tid < m * T) {
       const int jj = tid / T, q = tid - jj * T;
       const double lo = lo_s[jj], hi = hi_s[jj], wd = hi - lo;
-      const double x0 = lo + wd * ((double)(2 * q + 1) / (double)(K + 1));
-      const double x1 = lo + wd * ((double)(2 * q + 2) / (double)(K + 1));
-      int c0, c1;
-      tl_sturm2(d, e2, b0_s[jj], b1_s[jj], x0, x1, pivmin, c0, c1);
-      xs[2 * tid] = x0;
-      xs[2 * tid + 1] = x1;
-      cnt[2 * tid] = c0;
-      cnt[2 * tid + 1] = c1;
+      double x[TE_C];
+      int c[TE_C];
+#pragma unroll
+      for (int u = 0; u < TE_C; ++u) x[u] = lo + wd * ((double)(TE_C * q + u + 1) / (double)(K + 1));
+      tl_sturm_n<TE_C>(d, e2, b0_s[jj], b1_s[jj], x, pivmin, c);
+#pragma unroll
+      for (int u = 0; u < TE_C; ++u) {
+        xs[TE_C * tid + u] = x[u];
+        cnt[TE_C * tid + u] = c[u];
+      }
     }
     __syncthreads();
     int more = 0;
@@ -1089,7 +1107,7 @@ __global__ __launch_bounds__(TE_NT) void tb_bisect(EighLarge e) {
 // are kept in column j of Zw (lanes read and write consecutive addresses; the loads
 // are issued TV_PF indices ahead), and the residual max|T z - lambda z| is checked.
 constexpr int TV_NT = 64;
-constexpr int TV_PF = 32;
+constexpr int TV_PF = 16;
 
 __global__ __launch_bounds__(TV_NT) void tb_vectors(EighLarge e) {
   extern __shared__ double sm[];
@@ -1119,11 +1137,33 @@ __global__ __launch_bounds__(TV_NT) void tb_vectors(EighLarge e) {
     const double lam =
         tl_vector<TV_PF>(d, ee, e2, b0, b1, e.blo[j], e.bhi[j], tn, pivmin, e.Zw, n, j, n, TB_RQI_TOL);
     e.w[j] = lam;
-    for (int i = b0; i < b1; ++i) {
-      double t = (d[i] - lam) * e.Zw[(size_t)i * n + j];
-      if (i > b0) t += ee[i - 1] * e.Zw[(size_t)(i - 1) * n + j];
-      if (i < b1 - 1) t += ee[i] * e.Zw[(size_t)(i + 1) * n + j];
-      res = fmax(res, tl_err(fabs(t)));
+    // residual |T z - lam z| over the block, z read once with the loads of the next
+    // TV_PF entries in flight while the current ones are used
+    const double* Zc = e.Zw + j;
+    double cur[TV_PF], nxt[TV_PF];
+#pragma unroll
+    for (int u = 0; u < TV_PF; ++u) cur[u] = b0 + u < b1 ? Zc[(size_t)(b0 + u) * n] : 0.0;
+    double zprev = 0.0;
+    for (int i0 = b0; i0 < b1; i0 += TV_PF) {
+#pragma unroll
+      for (int u = 0; u < TV_PF; ++u) {
+        const int i = i0 + TV_PF + u;
+        nxt[u] = i < b1 ? Zc[(size_t)i * n] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < TV_PF; ++u) {
+        const int i = i0 + u;
+        if (i < b1) {
+          const double zi = cur[u], znext = u + 1 < TV_PF ? cur[u + 1] : nxt[0];
+          double t = (d[i] - lam) * zi;
+          if (i > b0) t += ee[i - 1] * zprev;
+          if (i < b1 - 1) t += ee[i] * znext;
+          res = fmax(res, tl_err(fabs(t)));
+          zprev = zi;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TV_PF; ++u) cur[u] = nxt[u];
     }
   }
   res = tl_wave_max(res);
@@ -1483,7 +1523,7 @@ void launch_tb_reduce(const EighLarge& e, hipStream_t s) {
 void launch_tb_eigenpairs(const EighLarge& e, hipStream_t s) {
   const int n = e.n;
   const size_t eig_lds = sizeof(double) * 3 * (size_t)n;
-  tb_bisect<<<(n + TE_CH - 1) / TE_CH, TE_NT, eig_lds, s>>>(e);
+  tb_bisect<<<(n + TE_CH - 1) / TE_CH, TE_NT, tb_bisect_lds(n), s>>>(e);
   tb_vectors<<<(n + TV_NT - 1) / TV_NT, TV_NT, eig_lds, s>>>(e);
 }
 

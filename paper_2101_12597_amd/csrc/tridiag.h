@@ -30,8 +30,8 @@ __device__ inline double block_max(double v, double* red) {
   __syncthreads();
   if (lane == 0) red[wave] = v;
   __syncthreads();
-  double s = 0.0;
-  for (int w = 0; w < NT / 64; ++w) s = fmax(s, red[w]);
+  double s = red[0];  // any sign
+  for (int w = 1; w < NT / 64; ++w) s = fmax(s, red[w]);
   return s;
 }
 
@@ -140,6 +140,46 @@ __device__ inline void tl_sturm2(const double* d, const double* e2, int b0, int 
     if (fabs(q1) < pivmin) q1 = -pivmin;
     c0 += q0 < 0.0;
     c1 += q1 < 0.0;
+  }
+}
+
+// numbers of eigenvalues below x[c] (c < C) of the unreduced block [b0, b1): C
+// independent pivot chains in lockstep, so that their latencies overlap
+template <int C>
+__device__ inline void tl_sturm_n(const double* d, const double* e2, int b0, int b1, const double (&x)[C],
+                                  double pivmin, int (&cnt)[C]) {
+  double q[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    q[c] = d[b0] - x[c];
+    if (fabs(q[c]) < pivmin) q[c] = -pivmin;
+    cnt[c] = q[c] < 0.0;
+  }
+  int i = b0 + 1;
+  for (; i + 8 <= b1; i += 8) {
+    double dd[8], ee[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      dd[u] = d[i + u];
+      ee[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        q[c] = (dd[u] - x[c]) - ee[u] * tl_rcp(q[c]);
+        if (fabs(q[c]) < pivmin) q[c] = -pivmin;
+        cnt[c] += q[c] < 0.0;
+      }
+  }
+  for (; i < b1; ++i) {
+    const double dd = d[i], ee = e2[i - 1];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      q[c] = (dd - x[c]) - ee * tl_rcp(q[c]);
+      if (fabs(q[c]) < pivmin) q[c] = -pivmin;
+      cnt[c] += q[c] < 0.0;
+    }
   }
 }
 
