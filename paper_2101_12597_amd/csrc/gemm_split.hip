@@ -282,15 +282,15 @@ __global__ __launch_bounds__(NT) void gemm_x6_packed(const SplitProb* __restrict
 constexpr int RING_NT = 512;
 constexpr int RING_NBUF = 3;
 
-template <int TPM, int TPN>
-__global__ __launch_bounds__(RING_NT) void gemm_x6_ring(const SplitProb* __restrict__ probs,
-                                                        const int* __restrict__ tile_prob, int total) {
-  constexpr int WC = RING_NT / 128;  // wavefront columns (two wavefront rows)
+template <int TPM, int TPN, int NT>
+__global__ __launch_bounds__(NT) void gemm_x6_ring(const SplitProb* __restrict__ probs,
+                                                   const int* __restrict__ tile_prob, int total) {
+  constexpr int WC = NT / 128;  // wavefront columns (two wavefront rows)
   constexpr int NBM = 2 * TPM, NBN = 4 * TPN / WC;
   constexpr int OPERA = TPM * PK_CHUNK, BUF = (TPM + TPN) * PK_CHUNK;  // BF16 values
   constexpr int GROUPS = (TPM + TPN) * PK_CHUNK / 512;  // 1 KB groups of a k-tile (64 lanes x 16 bytes)
-  constexpr int GPW = GROUPS / (RING_NT / 64);          // groups per wavefront
-  static_assert(GROUPS % (RING_NT / 64) == 0 && PK_CHUNK % 512 == 0, "k-tile groups per wavefront");
+  constexpr int GPW = GROUPS / (NT / 64);               // groups per wavefront
+  static_assert(GROUPS % (NT / 64) == 0 && PK_CHUNK % 512 == 0, "k-tile groups per wavefront");
   extern __shared__ __attribute__((aligned(16))) __bf16 ring_lds[];
   const int tile = tile_prob[total + blockIdx.x];  // the plan's workgroup -> tile order
   const SplitProb& p = probs[tile_prob[tile]];
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(RING_NT) void gemm_x6_ring(const SplitProb* __restr
   auto issue = [&](int kt, int buf) {
 #pragma unroll
     for (int u = 0; u < GPW; ++u) {
-      const int g = wave + (RING_NT / 64) * u;
+      const int g = wave + (NT / 64) * u;
       const int e = g * 64;  // first 16-byte piece of the group
       const __bf16* src = e < TPM * (PK_CHUNK / 8)
                               ? Ag + (e / (PK_CHUNK / 8)) * pstride + (int64_t)kt * PK_CHUNK + (e % (PK_CHUNK / 8)) * 8
@@ -556,15 +556,15 @@ static void f64_packed(const SplitProb* d_probs, const int* d_tile_prob, int til
   }
   gemm_f64_packed<TPM, TPN><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
 }
-template <int TPM, int TPN>
+template <int TPM, int TPN, int NT = RING_NT>
 static void x6_ring(const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
   const size_t lds = (size_t)RING_NBUF * (TPM + TPN) * PK_CHUNK * sizeof(__bf16);
   static bool attr = false;
   if (!attr) {
-    set_lds_limit(gemm_x6_ring<TPM, TPN>, lds);
+    set_lds_limit(gemm_x6_ring<TPM, TPN, NT>, lds);
     attr = true;
   }
-  gemm_x6_ring<TPM, TPN><<<tiles, RING_NT, lds, s>>>(d_probs, d_tile_prob, tiles);
+  gemm_x6_ring<TPM, TPN, NT><<<tiles, NT, lds, s>>>(d_probs, d_tile_prob, tiles);
 }
 template <int TPM, int TPN, int NT = XNT>
 static void x6_packed(const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
