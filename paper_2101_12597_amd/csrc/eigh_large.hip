@@ -1102,12 +1102,144 @@ __global__ __launch_bounds__(TE_NT) void tb_bisect(EighLarge e) {
   }
 }
 
-// Eigenvectors of T: one lane per eigenvalue (64 per workgroup), twisted
-// factorizations with Rayleigh-quotient corrections; the pivots and the vector
-// are kept in column j of Zw (lanes read and write consecutive addresses; the loads
-// are issued TV_PF indices ahead), and the residual max|T z - lambda z| is checked.
+// Eigenvectors of T: two lanes per eigenvalue (32 eigenvalues per workgroup of 64).
+// The twisted factorization of T - lam I splits into independent halves, so the even
+// lane of a pair takes the forward pivots D+ (into column j of Zw) and the vector
+// above the twist, the odd lane the backward pivots D- (into column j of Aw, free at
+// this point) and the vector below it; the twist index (the smallest
+// |gamma_i| = |D+_i + D-_i - (d_i - lam)|) and the norm are combined across the pair.
+// Both lanes take the same Rayleigh-quotient corrections while they exceed
+// TB_RQI_TOL eps ||T|| (the bracket bounds every step), so the pair stays in step.
+// Lanes read and write consecutive addresses of the row i of Zw / Aw; the loads are
+// issued TV_PF indices ahead.  The residual max|T z - lambda z| is checked.
 constexpr int TV_NT = 64;
 constexpr int TV_PF = 16;
+
+// The twisted factorization at lam for the pair's eigenvalue (this lane: odd or even);
+// writes z / ||z|| into Z (column pointer, ld n) and returns gamma_r / ||z||^2.
+__device__ double tv_twisted(const double* d, const double* ee, const double* e2, int b0, int b1, double lam,
+                             double pivmin, double* Z, double* W, int n, bool odd) {
+  // 1. pivots: D+ forward from b0 (even lane, into Z), D- backward from b1 - 1 (odd, into W)
+  {
+    double* P = odd ? W : Z;
+    int i = odd ? b1 - 1 : b0;
+    double D = tl_piv(d[i] - lam, pivmin);
+    P[(size_t)i * n] = D;
+    for (int t = 1; t < b1 - b0; ++t) {
+      i = odd ? b1 - 1 - t : b0 + t;
+      D = tl_piv((d[i] - lam) - (odd ? e2[i] : e2[i - 1]) * tl_rcp(D), pivmin);
+      P[(size_t)i * n] = D;
+    }
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the partner lane reads these pivots
+  // 2. twist index: each lane scans half of the block, the pair keeps the smaller
+  //    |gamma| (the larger index on a tie)
+  const int mid = (b0 + b1) >> 1, ia = odd ? mid : b0, ib = odd ? b1 : mid;
+  int r = ib - 1;
+  double best = INFINITY, gr = 0.0;
+  {
+    double cz[TV_PF], cw[TV_PF];
+#pragma unroll
+    for (int u = 0; u < TV_PF; ++u) {
+      const int i = ia + u;
+      cz[u] = i < ib ? Z[(size_t)i * n] : 0.0;
+      cw[u] = i < ib ? W[(size_t)i * n] : 0.0;
+    }
+    for (int i0 = ia; i0 < ib; i0 += TV_PF) {
+      double nz[TV_PF], nw[TV_PF];
+#pragma unroll
+      for (int u = 0; u < TV_PF; ++u) {
+        const int i = i0 + TV_PF + u;
+        nz[u] = i < ib ? Z[(size_t)i * n] : 0.0;
+        nw[u] = i < ib ? W[(size_t)i * n] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < TV_PF; ++u) {
+        const int i = i0 + u;
+        if (i < ib) {
+          const double g = cz[u] + cw[u] - (d[i] - lam);
+          if (fabs(g) <= best) {
+            best = fabs(g);
+            gr = g;
+            r = i;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TV_PF; ++u) {
+        cz[u] = nz[u];
+        cw[u] = nw[u];
+      }
+    }
+  }
+  {
+    const double ob = __shfl_xor(best, 1), og = __shfl_xor(gr, 1);
+    const int orr = __shfl_xor(r, 1);
+    if (ob < best || (ob == best && orr > r)) {
+      best = ob;
+      gr = og;
+      r = orr;
+    }
+  }
+  // 3. z_r = 1 and the one-sided recurrences: above the twist (even lane)
+  //    z_i = -(e_i / D+_i) z_{i+1}, below it (odd lane) z_i = -(e_{i-1} / D-_i) z_{i-1}
+  const int len = odd ? b1 - 1 - r : r - b0, step = odd ? 1 : -1;
+  const double* src = odd ? W : Z;
+  double part = 0.0;
+  {
+    double z = 1.0, cur[TV_PF];
+#pragma unroll
+    for (int u = 0; u < TV_PF; ++u) cur[u] = u < len ? src[(size_t)(r + step * (1 + u)) * n] : 1.0;
+    for (int t0 = 0; t0 < len; t0 += TV_PF) {
+      double nxt[TV_PF];
+#pragma unroll
+      for (int u = 0; u < TV_PF; ++u) {
+        const int t = t0 + TV_PF + u;
+        nxt[u] = t < len ? src[(size_t)(r + step * (1 + t)) * n] : 1.0;
+      }
+#pragma unroll
+      for (int u = 0; u < TV_PF; ++u) {
+        const int t = t0 + u;
+        if (t < len) {
+          const int i = r + step * (1 + t);
+          z = -((odd ? ee[i - 1] : ee[i]) * tl_rcp(cur[u])) * z;
+          Z[(size_t)i * n] = z;
+          part += z * z;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TV_PF; ++u) cur[u] = nxt[u];
+    }
+  }
+  if (!odd) Z[(size_t)r * n] = 1.0;
+  const double po = __shfl_xor(part, 1);
+  const double nrm = 1.0 + (odd ? po + part : part + po);  // the same order on both lanes
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the partner lane scales these entries
+  // 4. normalization, each lane one half of the block
+  const double sc = 1.0 / sqrt(nrm);
+  {
+    double cur[TV_PF];
+#pragma unroll
+    for (int u = 0; u < TV_PF; ++u) cur[u] = ia + u < ib ? Z[(size_t)(ia + u) * n] : 0.0;
+    for (int i0 = ia; i0 < ib; i0 += TV_PF) {
+      double nxt[TV_PF];
+#pragma unroll
+      for (int u = 0; u < TV_PF; ++u) {
+        const int i = i0 + TV_PF + u;
+        nxt[u] = i < ib ? Z[(size_t)i * n] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < TV_PF; ++u) {
+        const int i = i0 + u;
+        if (i < ib) Z[(size_t)i * n] = cur[u] * sc;
+      }
+#pragma unroll
+      for (int u = 0; u < TV_PF; ++u) cur[u] = nxt[u];
+    }
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // before the partner reads z or pivots again
+  return gr / nrm;
+}
 
 __global__ __launch_bounds__(TV_NT) void tb_vectors(EighLarge e) {
   extern __shared__ double sm[];
@@ -1130,31 +1262,53 @@ __global__ __launch_bounds__(TV_NT) void tb_vectors(EighLarge e) {
   const double pivmin = DBL_MIN * fmax(1.0, tl_wave_max(e2_loc));
   const double scale = sqrt(tl_wave_sum(fro));
   __syncthreads();
-  const int j = blockIdx.x * TV_NT + tid;
+  const bool odd = tid & 1;
+  const int j = blockIdx.x * (TV_NT / 2) + (tid >> 1);
   double res = 0.0;
-  if (j < n) {
+  if (j < n) {  // uniform within the pair
     const int b0 = e.bb[2 * j], b1 = e.bb[2 * j + 1];
-    const double lam =
-        tl_vector<TV_PF>(d, ee, e2, b0, b1, e.blo[j], e.bhi[j], tn, pivmin, e.Zw, n, j, n, TB_RQI_TOL);
-    e.w[j] = lam;
-    // residual |T z - lam z| over the block, z read once with the loads of the next
-    // TV_PF entries in flight while the current ones are used
-    const double* Zc = e.Zw + j;
+    double* Z = e.Zw + j;
+    double* W = e.Aw + j;
+    const int mid = (b0 + b1) >> 1;
+    // zeros outside the block, each lane one side
+    for (int i = odd ? b1 : 0; i < (odd ? n : b0); ++i) Z[(size_t)i * n] = 0.0;
+    const double lo = e.blo[j], hi = e.bhi[j];
+    double lam = 0.5 * (lo + hi);
+    if (b1 - b0 == 1) {
+      if (!odd) Z[(size_t)b0 * n] = 1.0;
+      lam = d[b0];
+    } else {
+      double dl = tv_twisted(d, ee, e2, b0, b1, lam, pivmin, Z, W, n, odd);
+      for (int it = 0; it < TL_RQI_MAX && fabs(dl) > TB_RQI_TOL * DBL_EPSILON * tn; ++it) {
+        const double nl = lam + dl;
+        if (!(nl >= lo && nl <= hi)) break;
+        lam = nl;
+        dl = tv_twisted(d, ee, e2, b0, b1, lam, pivmin, Z, W, n, odd);
+      }
+      const double nl = lam + dl;
+      lam = (nl >= lo && nl <= hi) ? nl : lam;
+    }
+    if (!odd) e.w[j] = lam;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // residual |T z - lam z| over this lane's half of the block, z read once with the
+    // loads of the next TV_PF entries in flight
+    const int ia = odd ? mid : b0, ib = odd ? b1 : mid;
     double cur[TV_PF], nxt[TV_PF];
 #pragma unroll
-    for (int u = 0; u < TV_PF; ++u) cur[u] = b0 + u < b1 ? Zc[(size_t)(b0 + u) * n] : 0.0;
-    double zprev = 0.0;
-    for (int i0 = b0; i0 < b1; i0 += TV_PF) {
+    for (int u = 0; u < TV_PF; ++u) cur[u] = ia + u < ib ? Z[(size_t)(ia + u) * n] : 0.0;
+    double zprev = ia > b0 ? Z[(size_t)(ia - 1) * n] : 0.0;
+    const double zend = ib < b1 ? Z[(size_t)ib * n] : 0.0;
+    for (int i0 = ia; i0 < ib; i0 += TV_PF) {
 #pragma unroll
       for (int u = 0; u < TV_PF; ++u) {
         const int i = i0 + TV_PF + u;
-        nxt[u] = i < b1 ? Zc[(size_t)i * n] : 0.0;
+        nxt[u] = i < ib ? Z[(size_t)i * n] : zend;
       }
 #pragma unroll
       for (int u = 0; u < TV_PF; ++u) {
         const int i = i0 + u;
-        if (i < b1) {
-          const double zi = cur[u], znext = u + 1 < TV_PF ? cur[u + 1] : nxt[0];
+        if (i < ib) {
+          const double zi = cur[u], znext = u + 1 < TV_PF ? (i + 1 < ib ? cur[u + 1] : zend) : nxt[0];
           double t = (d[i] - lam) * zi;
           if (i > b0) t += ee[i - 1] * zprev;
           if (i < b1 - 1) t += ee[i] * znext;
@@ -1524,7 +1678,7 @@ void launch_tb_eigenpairs(const EighLarge& e, hipStream_t s) {
   const int n = e.n;
   const size_t eig_lds = sizeof(double) * 3 * (size_t)n;
   tb_bisect<<<(n + TE_CH - 1) / TE_CH, TE_NT, tb_bisect_lds(n), s>>>(e);
-  tb_vectors<<<(n + TV_NT - 1) / TV_NT, TV_NT, eig_lds, s>>>(e);
+  tb_vectors<<<(n + TV_NT / 2 - 1) / (TV_NT / 2), TV_NT, eig_lds, s>>>(e);
 }
 
 void launch_tb_wy_t(const EighLarge& e, hipStream_t s) {
