@@ -428,6 +428,102 @@ __global__ __launch_bounds__(256) void copy_pack64(const PackJob* __restrict__ j
   for (int e = threadIdx.x; e < PK_R * PK_K; e += 256) base[e] = t[e % PK_R][e / PK_R];
 }
 
+// gemm_f64_ring<TPM, TPN>: the FP64 product on packed operands with eight wavefronts
+// (2 x 4, each 32 TPM x 16 TPN) and two LDS buffers filled straight from global memory
+// (global_load_lds_dwordx4): k-tile kt + 1 loads while kt is multiplied (an FP64 k-tile
+// keeps the matrix cores busy for thousands of cycles, so one tile ahead hides the
+// load latency), one bare barrier per k-tile.
+constexpr int RING64_NT = 512;
+
+template <int TPM, int TPN>
+__global__ __launch_bounds__(RING64_NT) void gemm_f64_ring(const SplitProb* __restrict__ probs,
+                                                           const int* __restrict__ tile_prob, int total) {
+  constexpr int NT = RING64_NT, WC = NT / 128;
+  constexpr int NBM = 2 * TPM, NBN = 4 * TPN / WC;
+  constexpr int OPERA = TPM * PK_CHUNK_64, BUF = (TPM + TPN) * PK_CHUNK_64;  // doubles
+  constexpr int GROUPS = (TPM + TPN) * PK_CHUNK_64 / 128;  // 1 KB groups (64 lanes x 16 bytes)
+  constexpr int GPW = GROUPS / (NT / 64);
+  static_assert(GROUPS % (NT / 64) == 0 && PK_CHUNK_64 % 128 == 0, "k-tile groups per wavefront");
+  extern __shared__ __attribute__((aligned(16))) double r64_lds[];
+  const int tile = tile_prob[total + blockIdx.x];  // the plan's workgroup -> tile order
+  const SplitProb& p = probs[tile_prob[tile]];
+  int tm, tn;
+  x6_tile(p, tile - p.begin, tm, tn);
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wrow = (wave / WC) * 32 * TPM, wcol = (wave % WC) * 16 * NBN;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t pstride = (int64_t)p.ktiles * PK_CHUNK_64;
+  const double* Ag = static_cast<const double*>(p.A) + (int64_t)(TPM * tm) * pstride;
+  const double* Bg = static_cast<const double*>(p.B) + (int64_t)(TPN * tn) * pstride;
+
+  // k-tile kt into buffer buf: group g (128 doubles) copied by wavefront g % 8, lane l
+  // taking its two doubles l
+  auto issue = [&](int kt, int buf) {
+#pragma unroll
+    for (int u = 0; u < GPW; ++u) {
+      const int g = wave + (NT / 64) * u;
+      const int e = g * 128;  // first double of the group
+      const double* src = e < TPM * PK_CHUNK_64
+                              ? Ag + (e / PK_CHUNK_64) * pstride + (int64_t)kt * PK_CHUNK_64 + (e % PK_CHUNK_64)
+                              : Bg + ((e - TPM * PK_CHUNK_64) / PK_CHUNK_64) * pstride + (int64_t)kt * PK_CHUNK_64 +
+                                    ((e - TPM * PK_CHUNK_64) % PK_CHUNK_64);
+      __builtin_amdgcn_global_load_lds(src + lane * 2, r64_lds + buf * BUF + e, 16, 0, 0);
+    }
+  };
+  auto at = [&](int k, int off, int blk) {
+    const int trow = off + blk * 16;
+    return (trow >> 6) * PK_CHUNK_64 + k * PK_R + (trow & 63) + lr;
+  };
+
+  d4 c[NBM][NBN];
+#pragma unroll
+  for (int i = 0; i < NBM; ++i)
+#pragma unroll
+    for (int j = 0; j < NBN; ++j) c[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int nk = p.ktiles;
+  if (nk > 0) issue(0, 0);
+  for (int kt = 0; kt < nk; ++kt) {
+    // this wavefront's pieces of k-tile kt are in (nothing else is loading), then a bare
+    // barrier: every piece of kt is in and every wavefront is done with buffer kt - 1
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0); expcnt, lgkmcnt not waited on
+    __builtin_amdgcn_s_barrier();
+    if (kt + 1 < nk) issue(kt + 1, (kt + 1) & 1);
+    const double* As = r64_lds + (kt & 1) * BUF;
+    const double* Bs = As + OPERA;
+#pragma unroll
+    for (int ks = 0; ks < PK_K; ks += 4) {
+      double av[NBM], bv[NBN];
+#pragma unroll
+      for (int i = 0; i < NBM; ++i) av[i] = As[at(ks + lk, wrow, i)];
+#pragma unroll
+      for (int j = 0; j < NBN; ++j) bv[j] = Bs[at(ks + lk, wcol, j)];
+#pragma unroll
+      for (int i = 0; i < NBM; ++i)
+#pragma unroll
+        for (int j = 0; j < NBN; ++j) c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c[i][j], 0, 0, 0);
+    }
+  }
+
+  // epilogue: element r of lane l of block (i, j) is row l / 16 + 4 r, column l % 16
+  const int row0 = tm * 64 * TPM + wrow, col0 = tn * 64 * TPN + wcol;
+#pragma unroll
+  for (int i = 0; i < NBM; ++i)
+#pragma unroll
+    for (int j = 0; j < NBN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + i * 16 + lk + 4 * r, col = col0 + j * 16 + lr;
+        if (row < p.m && col < p.n) {
+          double v = c[i][j][r];
+          if (p.beta != 0.0) v += p.beta * p.D[(int64_t)row * p.ldd + col];
+          p.C[(int64_t)row * p.ldc + col] = v;
+        }
+      }
+}
+
 template <int TPM, int TPN>
 __global__ __launch_bounds__(XNT) void gemm_f64_packed(const SplitProb* __restrict__ probs,
                                                        const int* __restrict__ tile_prob, int total) {
@@ -577,10 +673,21 @@ static void x6_packed(const SplitProb* d_probs, const int* d_tile_prob, int tile
   gemm_x6_packed<TPM, TPN, NT><<<tiles, NT, lds, s>>>(d_probs, d_tile_prob, tiles);
 }
 
+template <int TPM, int TPN>
+static void f64_ring(const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
+  const size_t lds = (size_t)2 * (TPM + TPN) * PK_CHUNK_64 * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    set_lds_limit(gemm_f64_ring<TPM, TPN>, lds);
+    attr = true;
+  }
+  gemm_f64_ring<TPM, TPN><<<tiles, RING64_NT, lds, s>>>(d_probs, d_tile_prob, tiles);
+}
+
 void launch_gemm_f64_packed(int tpm, int tpn, const SplitProb* d_probs, const int* d_tile_prob, int tiles,
                             hipStream_t s) {
   if (tiles <= 0) return;
-  if (tpm == 2 && tpn == 2) f64_packed<2, 2>(d_probs, d_tile_prob, tiles, s);
+  if (tpm == 2 && tpn == 2) f64_ring<2, 2>(d_probs, d_tile_prob, tiles, s);
   else if (tpm == 2) f64_packed<2, 1>(d_probs, d_tile_prob, tiles, s);
   else if (tpn == 2) f64_packed<1, 2>(d_probs, d_tile_prob, tiles, s);
   else f64_packed<1, 1>(d_probs, d_tile_prob, tiles, s);
