@@ -54,45 +54,110 @@ __global__ __launch_bounds__(TPB) void dot_partial(const double* __restrict__ x,
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// partials of base_slot . v for one two-loop step
-__global__ __launch_bounds__(TPB) void slot_dot_partial(const LbState* st, int k, int pass,
-                                                        const double* __restrict__ base,
-                                                        const double* __restrict__ v, int64_t n, double* partial) {
-  const int i = two_loop_slot(*st, k, pass);
-  if (i < 0) return;
-  const double* __restrict__ x = base + (int64_t)i * n;
+// Stage t of the two-loop recursion with c = st.count stored pairs, each step's
+// update fused with the next step's dot product (one pass over the vectors each):
+//   t < c         first loop, step t (newest to oldest): v = g at t = 0, else
+//                 v = q + coef y (q = g at t = 1) of step t - 1, kept in q; partials
+//                 of s.v for step t
+//   t == c        end of the first loop: v as above, r = H0 v with the diagonal
+//                 preconditioner of Eq. prec_3; partials of y.r for the first step of
+//                 the second loop (or, with c = 0, r is the direction)
+//   c < t <= 2c   second loop, step t - c - 1 (oldest to newest): p += coef s; partials
+//                 of y.p for the next step, or after the last step the direction
+// The direction is written as p = -H g with the partials of g.p (its slope) and the
+// unit-step trial point xt = x + p.  Stages beyond 2c return at once.
+__global__ __launch_bounds__(TPB) void two_loop_stage(const LbState* __restrict__ st, int t,
+                                                      const double* __restrict__ g, double* __restrict__ q,
+                                                      double* __restrict__ p, const double* __restrict__ S,
+                                                      const double* __restrict__ Y, const double* __restrict__ h,
+                                                      const double* __restrict__ w, double gamma,
+                                                      const double* __restrict__ x, double* __restrict__ xt,
+                                                      int64_t n, double* partial) {
+  const int c = st->count;
+  if (t > 2 * c) return;
   __shared__ double red[16];
-  double s = 0.0, c = 0.0;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
-    neumaier_add(s, c, x[j] * v[j]);
-  const double t = block_sum_neumaier(s, c, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
-}
-
-// pass 0: alpha_i = s_i.q / s_i.y_i, coef = -alpha_i;  pass 1: coef = alpha_i - y_i.r / s_i.y_i
-__global__ __launch_bounds__(TPB) void two_loop_scalar(LbState* st, int k, int pass, const double* partial) {
-  const int i = two_loop_slot(*st, k, pass);
-  if (i < 0) return;
-  const double t = sum_partials(partial);
-  if (threadIdx.x == 0) {
-    if (pass == 0) {
-      st->al[i] = t / st->ys[i];
-      st->coef = -st->al[i];
+  double s = 0.0, e = 0.0;
+  const int64_t j0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, dj = (int64_t)gridDim.x * blockDim.x;
+  if (t <= c) {
+    // v of the first loop: g, or the previous step's update
+    const double* __restrict__ src = t <= 1 ? g : q;
+    const double* __restrict__ yv = t >= 1 ? Y + (int64_t)two_loop_slot(*st, t - 1, 0) * n : nullptr;
+    const double cf = st->coef;
+    if (t < c) {
+      const double* __restrict__ sv = S + (int64_t)two_loop_slot(*st, t, 0) * n;
+      for (int64_t j = j0; j < n; j += dj) {
+        double v = src[j];
+        if (yv) {
+          v = v + cf * yv[j];
+          q[j] = v;
+        }
+        neumaier_add(s, e, sv[j] * v);
+      }
     } else {
-      st->coef = st->al[i] - t / st->ys[i];
+      const double beta = st->beta;
+      const double* __restrict__ y1 = c > 0 ? Y + (int64_t)two_loop_slot(*st, 0, 1) * n : nullptr;
+      for (int64_t j = j0; j < n; j += dj) {
+        double v = src[j];
+        if (yv) v = v + cf * yv[j];
+        const double r = v / ((1.0 - gamma) * h[j] + gamma * beta * w[j]);
+        if (y1) {
+          p[j] = r;
+          neumaier_add(s, e, y1[j] * r);
+        } else {
+          p[j] = -r;
+          neumaier_add(s, e, g[j] * -r);
+          xt[j] = x[j] - r;
+        }
+      }
+    }
+  } else {
+    const int k = t - c - 1;
+    const double cf = st->coef;
+    const double* __restrict__ sv = S + (int64_t)two_loop_slot(*st, k, 1) * n;
+    if (k < c - 1) {
+      const double* __restrict__ yn = Y + (int64_t)two_loop_slot(*st, k + 1, 1) * n;
+      for (int64_t j = j0; j < n; j += dj) {
+        const double v = p[j] + cf * sv[j];
+        p[j] = v;
+        neumaier_add(s, e, yn[j] * v);
+      }
+    } else {
+      for (int64_t j = j0; j < n; j += dj) {
+        const double v = -(p[j] + cf * sv[j]);
+        p[j] = v;
+        neumaier_add(s, e, g[j] * v);
+        xt[j] = x[j] + v;
+      }
     }
   }
+  const double tot = block_sum_neumaier(s, e, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// y += coef * base_slot
-__global__ void slot_axpy(const LbState* st, int k, int pass, double* __restrict__ y,
-                          const double* __restrict__ base, int64_t n) {
-  const int i = two_loop_slot(*st, k, pass);
-  if (i < 0) return;
-  const double c = st->coef;
-  const double* __restrict__ x = base + (int64_t)i * n;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
-    y[j] = y[j] + c * x[j];
+// The scalar after stage t: first loop alpha_i = s_i.q / s_i.y_i and coef = -alpha_i;
+// second loop coef = alpha_i - y_i.r / s_i.y_i for the next step; after the last stage
+// the slope of the direction, which is replaced by preconditioned steepest descent
+// (and the memory erased) when it does not descend.
+__global__ __launch_bounds__(TPB) void two_loop_scalar(LbState* st, int t, const double* partial) {
+  const int c = st->count;
+  if (t > 2 * c) return;
+  const double d = sum_partials(partial);
+  if (threadIdx.x != 0) return;
+  int i = -1;  // slot whose scalar follows, or -1 after the last stage
+  if (t < c) {
+    i = two_loop_slot(*st, t, 0);
+    st->al[i] = d / st->ys[i];
+    st->coef = -st->al[i];
+    return;
+  }
+  if (t < 2 * c) i = two_loop_slot(*st, t - c, 1);
+  if (i >= 0) {
+    st->coef = st->al[i] - d / st->ys[i];
+    return;
+  }
+  st->dphi0 = d;
+  st->steepest = (d < 0.0) ? 0 : 1;
+  if (st->steepest) st->count = 0;
 }
 
 // r = sign * q / ((1 - gamma) h + gamma beta w); skipped when `only_if` points at a zero flag
@@ -103,11 +168,6 @@ __global__ void precond(double* __restrict__ r, const double* __restrict__ q, co
   const double beta = st->beta;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
     r[j] = sign * (q[j] / ((1.0 - gamma) * h[j] + gamma * beta * w[j]));
-}
-
-__global__ void negate(double* __restrict__ p, int64_t n) {
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
-    p[j] = -p[j];
 }
 
 __global__ __launch_bounds__(TPB) void start_state(LbState* st, const double* E_total, double beta0, int set_beta,
@@ -126,16 +186,6 @@ __global__ __launch_bounds__(TPB) void start_state(LbState* st, const double* E_
   st->steepest = 0;
   st->evals = 0;
   st->xmax2 = 0.0;
-}
-
-// slope of the two-loop direction; a direction that does not descend is replaced
-// by preconditioned steepest descent and the memory is erased
-__global__ __launch_bounds__(TPB) void descent_test(LbState* st, const double* partial) {
-  const double d = sum_partials(partial);
-  if (threadIdx.x != 0) return;
-  st->dphi0 = d;
-  st->steepest = (d < 0.0) ? 0 : 1;
-  if (st->steepest) st->count = 0;
 }
 
 __global__ void force_steepest(LbState* st) {
@@ -164,10 +214,11 @@ __global__ __launch_bounds__(TPB) void search_begin(LbState* st, const double* p
   st->status = 0;
 }
 
-// xtrial = x + alpha p while the search continues
+// xtrial = x + alpha p while the search continues; skipped when `only_if` points at
+// a zero flag
 __global__ void trial_point(double* __restrict__ xt, const double* __restrict__ x, const double* __restrict__ p,
-                            int64_t n, const LbState* st) {
-  if (st->result != LR_CONT) return;
+                            int64_t n, const LbState* st, const int32_t* only_if) {
+  if (st->result != LR_CONT || (only_if && *only_if == 0)) return;
   const double a = st->alpha;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
     xt[j] = x[j] + a * p[j];
@@ -419,25 +470,15 @@ void launch_lb_direction(LbState* st, const LbParams& P, const double* x, const 
                          const double* S, const double* Y, const double* hd, const double* wv, int64_t n,
                          double* partial, double* xtrial, hipStream_t s) {
   const int vg = vgrid(n);
-  (void)hipMemcpyAsync(q, g, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s);
-  for (int k = 0; k < P.m; ++k) {  // newest to oldest
-    slot_dot_partial<<<LB_DOT_BLOCKS, TPB, 0, s>>>(st, k, 0, S, q, n, partial);
-    two_loop_scalar<<<1, TPB, 0, s>>>(st, k, 0, partial);
-    slot_axpy<<<vg, TPB, 0, s>>>(st, k, 0, q, Y, n);
+  for (int t = 0; t <= 2 * P.m; ++t) {
+    two_loop_stage<<<LB_DOT_BLOCKS, TPB, 0, s>>>(st, t, g, q, p, S, Y, hd, wv, P.gamma, x, xtrial, n, partial);
+    two_loop_scalar<<<1, TPB, 0, s>>>(st, t, partial);
   }
-  precond<<<vg, TPB, 0, s>>>(p, q, hd, wv, n, P.gamma, 1.0, st, nullptr);
-  for (int k = 0; k < P.m; ++k) {  // oldest to newest
-    slot_dot_partial<<<LB_DOT_BLOCKS, TPB, 0, s>>>(st, k, 1, Y, p, n, partial);
-    two_loop_scalar<<<1, TPB, 0, s>>>(st, k, 1, partial);
-    slot_axpy<<<vg, TPB, 0, s>>>(st, k, 1, p, S, n);
-  }
-  negate<<<vg, TPB, 0, s>>>(p, n);
-  dot_partial<<<LB_DOT_BLOCKS, TPB, 0, s>>>(g, p, n, nullptr, partial);
-  descent_test<<<1, TPB, 0, s>>>(st, partial);
+  // preconditioned steepest descent when the two-loop direction does not descend
   precond<<<vg, TPB, 0, s>>>(p, g, hd, wv, n, P.gamma, -1.0, st, &st->steepest);
   dot_partial<<<LB_DOT_BLOCKS, TPB, 0, s>>>(g, p, n, &st->steepest, partial);
   search_begin<<<1, TPB, 0, s>>>(st, partial);
-  trial_point<<<vg, TPB, 0, s>>>(xtrial, x, p, n, st);
+  trial_point<<<vg, TPB, 0, s>>>(xtrial, x, p, n, st, &st->steepest);
 }
 
 void launch_lb_restart(LbState* st, const LbParams& P, const double* x, const double* g, double* p,
@@ -448,7 +489,7 @@ void launch_lb_restart(LbState* st, const LbParams& P, const double* x, const do
   precond<<<vg, TPB, 0, s>>>(p, g, hd, wv, n, P.gamma, -1.0, st, nullptr);
   dot_partial<<<LB_DOT_BLOCKS, TPB, 0, s>>>(g, p, n, nullptr, partial);
   search_begin<<<1, TPB, 0, s>>>(st, partial);
-  trial_point<<<vg, TPB, 0, s>>>(xtrial, x, p, n, st);
+  trial_point<<<vg, TPB, 0, s>>>(xtrial, x, p, n, st, nullptr);
 }
 
 void launch_lb_after_probe(LbState* st, const LbParams& P, double* x, double* g, const double* p,
@@ -458,7 +499,7 @@ void launch_lb_after_probe(LbState* st, const LbParams& P, double* x, double* g,
   const int vg = vgrid(n);
   dot_partial<<<LB_DOT_BLOCKS, TPB, 0, s>>>(gw, p, n, nullptr, partial);
   search_step<<<1, TPB, 0, s>>>(st, P, partial, E_total, status);
-  trial_point<<<vg, TPB, 0, s>>>(xtrial, x, p, n, st);
+  trial_point<<<vg, TPB, 0, s>>>(xtrial, x, p, n, st, nullptr);
   pair_partial<<<LB_DOT_BLOCKS, TPB, 0, s>>>(st, p, gw, g, n, partial);
   pair_final<<<1, TPB, 0, s>>>(st, partial);
   advance<<<vg, TPB, 0, s>>>(st, x, g, p, gw, S, Y, n);
