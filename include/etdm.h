@@ -111,7 +111,13 @@ typedef struct {
   const int32_t *bsr_col_idx; /* host, per instance row_ptr[last] entries, concatenated */
   int32_t gemm_tuning;    /* kernel choice of the real FP64 and BF16x6 GEMM stages:
                              0 = time the ETDM_GEMM_VARIANTS kernels on the handle's
-                             buffers in etdm_create and keep the fastest; 1 = fixed rule
+                             buffers in etdm_create and keep the fastest, once per stage
+                             signature (device architecture and compute units, precision,
+                             operand ops, every problem's shape) in a process: a later
+                             handle with the same stage takes the cached choice and times;
+                             with the environment variable ETDM_TUNE_CACHE naming a file,
+                             choices are also read from it and appended to it, so they
+                             carry over between processes; 1 = fixed rule
                              (packed 128 x 128 tiles when every problem of the stage is at
                              least 128 x 128 with K >= 256, else grouped 64 x 64); forced:
                              2 = packed 128 x 128, 3 = grouped 64 x 64, 4 = packed 64 x 64,

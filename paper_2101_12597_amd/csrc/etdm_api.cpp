@@ -7,7 +7,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -440,6 +443,7 @@ struct etdm_handle {
   std::vector<Stage> s_LWY1, s_LWY2, s_LWY3;
   HermCheck* d_lchk = nullptr;
   int cu_count = 1;
+  std::string arch;  // device architecture name (tuning cache key)
   std::vector<Stage> z_WY1, z_WY2, z_WY3;  // per block of reflectors: W1 = Y^H V, W2 = T W1, V -= Y W2
   std::vector<EighLarge> eig_large;  // real problems above the LDS size
   const double** d_n0ptr = nullptr;
@@ -817,9 +821,74 @@ etdm_status plan_packed_stages(etdm_handle* h, Stage* const* stages, size_t n) {
   return ETDM_OK;
 }
 
+// Tuning cache: the kernel choice of a stage keyed by the device (architecture
+// name, compute units) and the stage signature (precision, operand ops, real or
+// complex, and every problem's m, n, k, k2 and beta != 0, hashed with FNV-1a).
+// Process-wide; with ETDM_TUNE_CACHE naming a file, entries are also read from it
+// (once per file name) and appended to it, one line each:
+//   <key> <variant> <ms of the ETDM_GEMM_VARIANTS kernels>
+struct TuneEntry {
+  int variant;
+  float ms[V_COUNT];
+};
+static_assert(V_COUNT == 5, "the cache line format lists five kernel times");
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+std::string g_tune_file;  // the file already read
+
+std::string tune_key(const etdm_handle* h, const Stage& sg) {
+  uint64_t x = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      x ^= (uint64_t)((v >> (8 * b)) & 0xff);
+      x *= 1099511628211ull;
+    }
+  };
+  mix(sg.prec);
+  mix(sg.opA);
+  mix(sg.opB);
+  mix(sg.cplx);
+  mix((int64_t)sg.probs.size());
+  for (const GemmProb& p : sg.probs) {
+    mix(p.m);
+    mix(p.n);
+    mix(p.k);
+    mix(p.k2);
+    mix(p.beta != 0.0);
+  }
+  char buf[64];
+  snprintf(buf, sizeof buf, "/%d/%016llx", h->cu_count, (unsigned long long)x);
+  return (h->arch.empty() ? std::string("unknown") : h->arch) + buf;
+}
+
+// with g_tune_mu held
+void tune_file_load() {
+  const char* path = getenv("ETDM_TUNE_CACHE");
+  if (!path || !*path || g_tune_file == path) return;
+  g_tune_file = path;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char key[256];
+  TuneEntry e;
+  while (fscanf(f, "%255s %d %f %f %f %f %f", key, &e.variant, &e.ms[0], &e.ms[1], &e.ms[2], &e.ms[3], &e.ms[4]) ==
+         2 + V_COUNT)
+    if (e.variant >= 0 && e.variant < V_COUNT) g_tune[key] = e;
+  fclose(f);
+}
+
+void tune_file_append(const std::string& key, const TuneEntry& e) {
+  const char* path = getenv("ETDM_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s %d %.6g %.6g %.6g %.6g %.6g\n", key.c_str(), e.variant, e.ms[0], e.ms[1], e.ms[2], e.ms[3], e.ms[4]);
+  fclose(f);
+}
+
 // Plan-time choice among the kernels of an FP64 / BF16x6 stage: each runs on the
 // handle's own buffers (every evaluation overwrites what they write), one warm-up
-// and three timed launches, and the fastest is kept.
+// and three timed launches, and the fastest is kept, unless the tuning cache holds
+// the stage already.
 etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
   if (h->gemm_tuning != 0) return ETDM_OK;
   hipEvent_t e0, e1;
@@ -830,6 +899,17 @@ etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
   all.insert(all.end(), h->tune_extra.begin(), h->tune_extra.end());
   for (Stage* sg : all) {
     if (!sg || !sg->can_pack()) continue;
+    const std::string key = tune_key(h, *sg);
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      tune_file_load();
+      const auto it = g_tune.find(key);
+      if (it != g_tune.end()) {
+        sg->variant = it->second.variant;
+        std::copy(it->second.ms, it->second.ms + V_COUNT, sg->tuned_ms);
+        continue;
+      }
+    }
     // a complex BF16x6 stage has no grouped split kernel: its packed variants only
     const int v0 = sg->cplx ? V_P11 : V_TILE64;
     int best = v0;
@@ -847,6 +927,11 @@ etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
     }
     if (st != ETDM_OK) break;
     sg->variant = best;
+    TuneEntry e;
+    e.variant = best;
+    std::copy(sg->tuned_ms, sg->tuned_ms + V_COUNT, e.ms);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (g_tune.emplace(key, e).second) tune_file_append(key, e);
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -2299,6 +2384,10 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
     int dev = 0, cus = 1;
     if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
       h->cu_count = std::max(1, cus);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) h->arch = prop.gcnArchName;
+    for (char& c : h->arch)
+      if (c == ' ') c = '_';
   }
   h->prec = d->precision;
   h->gemm_tuning = d->gemm_tuning;
