@@ -20,7 +20,7 @@
 // with two K segments (C = a1 A1 B1 + a2 A2 B2) packs [a1 A1 | a2 A2] and
 // [B1; B2] along k, so the GEMM sees one K.
 //
-// gemm_x6_packed<TPM, TPN> / gemm_f64_packed<TPM, TPN>: C = op(A) op(B) + beta D
+// gemm_x6_packed<TPM, TPN>: C = op(A) op(B) + beta D
 // for packed op(A) and op(B)^T (both rows x K).  A workgroup of 4 wavefronts
 // computes a tile of TPM x TPN panels (64 TPM x 64 TPN, TPM and TPN in {1, 2});
 // each wavefront owns a 32 TPM x 32 TPN quarter as 2 TPM x 2 TPN blocks of
@@ -30,7 +30,10 @@
 // them into FP64 registers every X_FLUSH k-tiles.  The k-tiles are
 // double-buffered in LDS with the next one fetched into registers during the
 // MFMAs; tiles are ordered in groups of X_GROUP tile rows and dealt out so that
-// each XCD works on a contiguous range.
+// each XCD works on a contiguous range.  gemm_x6_ring (128 x 128 BF16x6) and
+// gemm_f64_ring (FP64, every tile shape) fill their LDS buffers straight from global
+// memory instead (global_load_lds_dwordx4), with eight (FP64 64 x 64: four)
+// wavefronts.
 #include "common.h"
 #include "reduce.h"
 
@@ -401,7 +404,7 @@ __global__ __launch_bounds__(NT) void gemm_x6_ring(const SplitProb* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// copy_pack64 / gemm_f64_packed
+// copy_pack64 / gemm_f64_ring
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void copy_pack64(const PackJob* __restrict__ jobs,
                                                    const int* __restrict__ chunk_job) {
@@ -428,22 +431,21 @@ __global__ __launch_bounds__(256) void copy_pack64(const PackJob* __restrict__ j
   for (int e = threadIdx.x; e < PK_R * PK_K; e += 256) base[e] = t[e % PK_R][e / PK_R];
 }
 
-// gemm_f64_ring<TPM, TPN>: the FP64 product on packed operands with eight wavefronts
-// (2 x 4, each 32 TPM x 16 TPN) and two LDS buffers filled straight from global memory
-// (global_load_lds_dwordx4): k-tile kt + 1 loads while kt is multiplied (an FP64 k-tile
-// keeps the matrix cores busy for thousands of cycles, so one tile ahead hides the
-// load latency), one bare barrier per k-tile.
-constexpr int RING64_NT = 512;
-
-template <int TPM, int TPN>
-__global__ __launch_bounds__(RING64_NT) void gemm_f64_ring(const SplitProb* __restrict__ probs,
-                                                           const int* __restrict__ tile_prob, int total) {
-  constexpr int NT = RING64_NT, WC = NT / 128;
+// gemm_f64_ring<TPM, TPN, NT>: the FP64 product on packed operands with NT / 64
+// wavefronts (2 x NT / 128, each 32 TPM x 128 TPN / (NT / 128)) and two LDS buffers
+// filled straight from global memory (global_load_lds_dwordx4): k-tile kt + 1 loads
+// while kt is multiplied (an FP64 k-tile keeps the matrix cores busy for thousands of
+// cycles, so one tile ahead hides the load latency), one bare barrier per k-tile.
+template <int TPM, int TPN, int NT>
+__global__ __launch_bounds__(NT) void gemm_f64_ring(const SplitProb* __restrict__ probs,
+                                                    const int* __restrict__ tile_prob, int total) {
+  constexpr int WC = NT / 128;
   constexpr int NBM = 2 * TPM, NBN = 4 * TPN / WC;
   constexpr int OPERA = TPM * PK_CHUNK_64, BUF = (TPM + TPN) * PK_CHUNK_64;  // doubles
   constexpr int GROUPS = (TPM + TPN) * PK_CHUNK_64 / 128;  // 1 KB groups (64 lanes x 16 bytes)
   constexpr int GPW = GROUPS / (NT / 64);
   static_assert(GROUPS % (NT / 64) == 0 && PK_CHUNK_64 % 128 == 0, "k-tile groups per wavefront");
+  static_assert(NBN >= 1 && 4 * TPN % WC == 0, "wavefront columns");
   extern __shared__ __attribute__((aligned(16))) double r64_lds[];
   const int tile = tile_prob[total + blockIdx.x];  // the plan's workgroup -> tile order
   const SplitProb& p = probs[tile_prob[tile]];
@@ -524,107 +526,6 @@ __global__ __launch_bounds__(RING64_NT) void gemm_f64_ring(const SplitProb* __re
       }
 }
 
-template <int TPM, int TPN>
-__global__ __launch_bounds__(XNT) void gemm_f64_packed(const SplitProb* __restrict__ probs,
-                                                       const int* __restrict__ tile_prob, int total) {
-  constexpr int NBM = 2 * TPM, NBN = 2 * TPN;
-  extern __shared__ __attribute__((aligned(16))) double f64_lds[];
-  const int tile = tile_prob[total + blockIdx.x];  // the plan's workgroup -> tile order
-  const SplitProb& p = probs[tile_prob[tile]];
-  int tm, tn;
-  x6_tile(p, tile - p.begin, tm, tn);
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wrow = (wave >> 1) * 32 * TPM, wcol = (wave & 1) * 32 * TPN;
-  const int lr = lane & 15, lk = lane >> 4;
-
-  // LDS: [buffer][A panels | B panels][k][row]
-  constexpr int OPERA = TPM * PK_CHUNK_64, OPERB = TPN * PK_CHUNK_64;
-  constexpr int BUF = OPERA + OPERB;
-  const int64_t pstride = (int64_t)p.ktiles * PK_CHUNK_64;
-  const double* Ag = static_cast<const double*>(p.A) + (int64_t)(TPM * tm) * pstride;
-  const double* Bg = static_cast<const double*>(p.B) + (int64_t)(TPN * tn) * pstride;
-
-  // staging: TPM (TPN) panels x 1024 pieces of 16 bytes of A (B); thread t takes
-  // pieces t + 256 u
-  i4 ra[4 * TPM], rb[4 * TPN];
-  auto fetch = [&](int kt) {
-#pragma unroll
-    for (int u = 0; u < 4 * TPM; ++u) {
-      const int e = threadIdx.x + u * XNT;
-      const int pan = e >> 10, w = e & 1023;
-      ra[u] = *reinterpret_cast<const i4*>(Ag + pan * pstride + (int64_t)kt * PK_CHUNK_64 + w * 2);
-    }
-#pragma unroll
-    for (int u = 0; u < 4 * TPN; ++u) {
-      const int e = threadIdx.x + u * XNT;
-      const int pan = e >> 10, w = e & 1023;
-      rb[u] = *reinterpret_cast<const i4*>(Bg + pan * pstride + (int64_t)kt * PK_CHUNK_64 + w * 2);
-    }
-  };
-  auto commit = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < 4 * TPM; ++u)
-      *reinterpret_cast<i4*>(f64_lds + buf * BUF + (threadIdx.x + u * XNT) * 2) = ra[u];
-#pragma unroll
-    for (int u = 0; u < 4 * TPN; ++u)
-      *reinterpret_cast<i4*>(f64_lds + buf * BUF + OPERA + (threadIdx.x + u * XNT) * 2) = rb[u];
-  };
-  // element offset of (k, tile row off + 16 blk + lane row) inside an operand's panels
-  auto at = [&](int k, int off, int blk) {
-    const int trow = off + blk * 16;
-    return (trow >> 6) * PK_CHUNK_64 + k * PK_R + (trow & 63) + lr;
-  };
-
-  d4 c[NBM][NBN];
-#pragma unroll
-  for (int i = 0; i < NBM; ++i)
-#pragma unroll
-    for (int j = 0; j < NBN; ++j) c[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-
-  if (p.ktiles > 0) {
-    fetch(0);
-    commit(0);
-  }
-  __syncthreads();
-  for (int kt = 0; kt < p.ktiles; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < p.ktiles) fetch(kt + 1);
-    const double* As = f64_lds + buf * BUF;
-    const double* Bs = f64_lds + buf * BUF + OPERA;
-#pragma unroll
-    for (int ks = 0; ks < PK_K; ks += 4) {
-      double av[NBM], bv[NBN];
-#pragma unroll
-      for (int i = 0; i < NBM; ++i) av[i] = As[at(ks + lk, wrow, i)];
-#pragma unroll
-      for (int j = 0; j < NBN; ++j) bv[j] = Bs[at(ks + lk, wcol, j)];
-#pragma unroll
-      for (int i = 0; i < NBM; ++i)
-#pragma unroll
-        for (int j = 0; j < NBN; ++j) c[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], c[i][j], 0, 0, 0);
-    }
-    if (kt + 1 < p.ktiles) commit(buf ^ 1);
-    __syncthreads();
-  }
-
-  // epilogue: element r of lane l of block (i, j) is row l / 16 + 4 r, column l % 16
-  const int row0 = tm * 64 * TPM + wrow, col0 = tn * 64 * TPN + wcol;
-#pragma unroll
-  for (int i = 0; i < NBM; ++i)
-#pragma unroll
-    for (int j = 0; j < NBN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + i * 16 + lk + 4 * r, col = col0 + j * 16 + lr;
-        if (row < p.m && col < p.n) {
-          double v = c[i][j][r];
-          if (p.beta != 0.0) v += p.beta * p.D[(int64_t)row * p.ldd + col];
-          p.C[(int64_t)row * p.ldc + col] = v;
-        }
-      }
-}
-
 void launch_split_pack(const PackJob* d_jobs, const int* d_chunk_job, int chunks, hipStream_t s) {
   if (chunks <= 0) return;
   split_pack<<<chunks, 256, 0, s>>>(d_jobs, d_chunk_job);
@@ -642,16 +543,6 @@ static void set_lds_limit(K kernel, size_t bytes) {
 }
 
 // tile shapes (tpm, tpn) in {(1,1), (2,1), (1,2), (2,2)}
-template <int TPM, int TPN>
-static void f64_packed(const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
-  const size_t lds = (size_t)2 * (TPM + TPN) * PK_CHUNK_64 * sizeof(double);
-  static bool attr = false;
-  if (!attr) {
-    set_lds_limit(gemm_f64_packed<TPM, TPN>, lds);
-    attr = true;
-  }
-  gemm_f64_packed<TPM, TPN><<<tiles, XNT, lds, s>>>(d_probs, d_tile_prob, tiles);
-}
 template <int TPM, int TPN, int NT = RING_NT>
 static void x6_ring(const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
   const size_t lds = (size_t)RING_NBUF * (TPM + TPN) * PK_CHUNK * sizeof(__bf16);
@@ -673,24 +564,24 @@ static void x6_packed(const SplitProb* d_probs, const int* d_tile_prob, int tile
   gemm_x6_packed<TPM, TPN, NT><<<tiles, NT, lds, s>>>(d_probs, d_tile_prob, tiles);
 }
 
-template <int TPM, int TPN>
+template <int TPM, int TPN, int NT>
 static void f64_ring(const SplitProb* d_probs, const int* d_tile_prob, int tiles, hipStream_t s) {
   const size_t lds = (size_t)2 * (TPM + TPN) * PK_CHUNK_64 * sizeof(double);
   static bool attr = false;
   if (!attr) {
-    set_lds_limit(gemm_f64_ring<TPM, TPN>, lds);
+    set_lds_limit(gemm_f64_ring<TPM, TPN, NT>, lds);
     attr = true;
   }
-  gemm_f64_ring<TPM, TPN><<<tiles, RING64_NT, lds, s>>>(d_probs, d_tile_prob, tiles);
+  gemm_f64_ring<TPM, TPN, NT><<<tiles, NT, lds, s>>>(d_probs, d_tile_prob, tiles);
 }
 
 void launch_gemm_f64_packed(int tpm, int tpn, const SplitProb* d_probs, const int* d_tile_prob, int tiles,
                             hipStream_t s) {
   if (tiles <= 0) return;
-  if (tpm == 2 && tpn == 2) f64_ring<2, 2>(d_probs, d_tile_prob, tiles, s);
-  else if (tpm == 2) f64_packed<2, 1>(d_probs, d_tile_prob, tiles, s);
-  else if (tpn == 2) f64_packed<1, 2>(d_probs, d_tile_prob, tiles, s);
-  else f64_packed<1, 1>(d_probs, d_tile_prob, tiles, s);
+  if (tpm == 2 && tpn == 2) f64_ring<2, 2, 512>(d_probs, d_tile_prob, tiles, s);
+  else if (tpm == 2) f64_ring<2, 1, 512>(d_probs, d_tile_prob, tiles, s);
+  else if (tpn == 2) f64_ring<1, 2, 512>(d_probs, d_tile_prob, tiles, s);
+  else f64_ring<1, 1, 256>(d_probs, d_tile_prob, tiles, s);
 }
 
 void launch_gemm_x6_packed(int tpm, int tpn, const SplitProb* d_probs, const int* d_tile_prob, int tiles,
