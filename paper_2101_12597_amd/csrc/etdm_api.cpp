@@ -232,22 +232,64 @@ struct Stage {
       cj.resize(nch, (int32_t)jobs.size());
       jobs.push_back(j);
     };
+    // Packed operand regions already planned: a real single-segment operand whose rows
+    // are a panel-aligned part of a region's rows of the same source (the same
+    // matrix, ld, scale, orientation and K) reads that region instead of packing again
+    // (the row panels of P = B B^T, an operand shared by two products of a stage).
+    // (rows past the operand's own are read but only feed masked results; every panel
+    // read lies inside the region's panels)
+    struct Region {
+      const double* src;
+      int64_t ld;
+      double alpha;
+      bool trans, stat;
+      int rows, panels, K, kt;
+      char* dst;
+    };
+    std::vector<Region> regions;
+    auto reuse = [&](const double* src, int64_t ld, double alpha, bool trans, int rows, int np, int K, int kt,
+                     bool stat) -> char* {
+      for (const Region& r : regions) {
+        if (r.ld != ld || r.alpha != alpha || r.trans != trans || r.K != K || r.kt != kt || r.stat != stat) continue;
+        const int64_t step = trans ? 1 : ld, d = src - r.src;
+        if (d < 0 || d % step != 0) continue;
+        const int64_t at = d / step;
+        if (at % PK_R != 0 || at + rows > r.rows || at / PK_R + np > r.panels) continue;
+        return r.dst + (size_t)(at / PK_R) * kt * chunk;
+      }
+      return nullptr;
+    };
     const int f = cplx ? 2 : 1;  // doubles per element along k and n
     for (const GemmProb& p : probs) {
       const int kt = ktiles(p), kt1 = ceil_div(f * std::max(p.k, 0), PK_K);
       const int nv = view_n(p);
       const int pa = panels(p.m, tpm), pb = panels(nv, tpn);
       const bool sa = sarena && a_static(p, sr), sb = sarena && b_static(p, sr);
-      char* a = sa ? sarena + soff : arena + off;
-      (sa ? soff : off) += (size_t)pa * kt * chunk;
-      char* b = sb ? sarena + soff : arena + off;
-      (sb ? soff : off) += (size_t)pb * kt * chunk;
+      const bool one = !cplx && p.k2 <= 0 && p.k > 0;  // candidates for a shared region
+      char* a = one ? reuse(p.A, p.lda, p.alpha, opA == OP_T, p.m, pa, p.k, kt, sa) : nullptr;
+      const bool a_new = a == nullptr;
+      if (a_new) {
+        a = sa ? sarena + soff : arena + off;
+        (sa ? soff : off) += (size_t)pa * kt * chunk;
+        if (one) regions.push_back(Region{p.A, p.lda, p.alpha, opA == OP_T, sa, p.m, pa, p.k, kt, a});
+      }
+      char* b = one ? reuse(p.B, p.ldb, 1.0, opB != OP_T, nv, pb, p.k, kt, sb) : nullptr;
+      const bool b_new = b == nullptr;
+      if (b_new) {
+        b = sb ? sarena + soff : arena + off;
+        (sb ? soff : off) += (size_t)pb * kt * chunk;
+        if (one) regions.push_back(Region{p.B, p.ldb, 1.0, opB != OP_T, sb, nv, pb, p.k, kt, b});
+      }
       // op(A)[i][k] = TA ? A[k][i] : A[i][k];  op(B)^T[j][k] = TB ? B[j][k] : B[k][j]
       const int za = cplx ? 1 : 0, zb = cplx ? 2 : 0;
-      job(p.A, a, p.lda, p.alpha, opA == OP_T, p.m, f * p.k, 0, kt, pa, za, opA, sa);
-      job(p.B, b, p.ldb, 1.0, opB != OP_T, nv, f * p.k, 0, kt, pb, zb, opB, sb);
-      job(p.A2, a, p.lda2, p.alpha2, opA == OP_T, p.m, f * p.k2, kt1, kt, pa, za, opA, sa);
-      job(p.B2, b, p.ldb2, 1.0, opB != OP_T, nv, f * p.k2, kt1, kt, pb, zb, opB, sb);
+      if (a_new) {
+        job(p.A, a, p.lda, p.alpha, opA == OP_T, p.m, f * p.k, 0, kt, pa, za, opA, sa);
+        job(p.A2, a, p.lda2, p.alpha2, opA == OP_T, p.m, f * p.k2, kt1, kt, pa, za, opA, sa);
+      }
+      if (b_new) {
+        job(p.B, b, p.ldb, 1.0, opB != OP_T, nv, f * p.k, 0, kt, pb, zb, opB, sb);
+        job(p.B2, b, p.ldb2, 1.0, opB != OP_T, nv, f * p.k2, kt1, kt, pb, zb, opB, sb);
+      }
       SplitProb sp;
       sp.A = a;
       sp.B = b;
