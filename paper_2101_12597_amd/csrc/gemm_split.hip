@@ -11,8 +11,8 @@
 //   op(X) (rows x K) -> panels of PK_R = 64 rows, each a run of k-tiles of
 //   PK_K = 32.  A BF16x6 chunk (one panel, one k-tile) holds [slice][row][k]
 //   values, 3 x 64 x 32 x 2 bytes = 12 KB, contiguous; inside a row the four
-//   8-value octets are permuted by an XOR of the row index (pk_phys), so the
-//   MFMA fragment reads of 16 consecutive rows hit distinct LDS banks.  An FP64
+//   8-value octets are permuted by an XOR of the row index (pk_phys), so that the
+//   MFMA fragment reads of 16 consecutive rows do not conflict in the LDS.  An FP64
 //   chunk is [k][row], 64 x 32 x 8 bytes = 16 KB, so the 16 lanes that share a
 //   k of a v_mfma_f64_16x16x4f64 fragment read 128 consecutive bytes.
 //
@@ -51,11 +51,11 @@ constexpr int XNT = 256;
 constexpr int X_FLUSH = 4;                     // k-tiles between FP64 flushes (128 k)
 constexpr int X_GROUP = 4;                     // tile rows per group of the tile order
 
-// octet position inside a 64-byte row: conflict free for 8 and for 16
-// consecutive rows read at the same octet
-__device__ __forceinline__ int pk_phys(int oct, int row) {
-  return oct ^ (((row >> 1) ^ (row >> 3)) & 3);
-}
+// octet position inside a 64-byte row.  The MFMA fragment read of a wavefront takes
+// octet lane / 16 of rows r0 + lane % 16 (r0 a multiple of 16); with this permutation
+// (period 8 in the row) the LDS counters show no bank conflict for it on gfx950, while
+// XOR-ing in row bit 3 as well, or no permutation, conflicts.
+__device__ __forceinline__ int pk_phys(int oct, int row) { return oct ^ ((row >> 1) & 3); }
 
 }  // namespace
 
