@@ -30,10 +30,11 @@
 // them into FP64 registers every X_FLUSH k-tiles.  The k-tiles are
 // double-buffered in LDS with the next one fetched into registers during the
 // MFMAs; tiles are ordered in groups of X_GROUP tile rows and dealt out so that
-// each XCD works on a contiguous range.  gemm_x6_ring (128 x 128 BF16x6) and
-// gemm_f64_ring (FP64, every tile shape) fill their LDS buffers straight from global
-// memory instead (global_load_lds_dwordx4), with eight (FP64 64 x 64: four)
-// wavefronts.
+// each XCD works on a contiguous range.  gemm_x6_ring (BF16x6 128 x 128 with eight
+// wavefronts and 64 x 64 with four) and gemm_f64_ring (FP64, every tile shape) fill
+// their LDS buffers straight from global memory instead (global_load_lds_dwordx4);
+// the 128 x 64 and 64 x 128 BF16x6 tiles keep the register-staged kernel, whose two
+// workgroups per CU the ring's three buffers (108 KB) would not leave room for.
 #include "common.h"
 #include "reduce.h"
 
@@ -275,10 +276,11 @@ __global__ __launch_bounds__(NT) void gemm_x6_packed(const SplitProb* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// gemm_x6_ring<TPM, TPN>: the same product for tiles of TPM x TPN panels with eight
-// wavefronts (2 x 4, each 32 TPM x 16 TPN) and a ring of three LDS buffers filled
-// straight from global memory (global_load_lds_dwordx4: no staging registers), so
-// that the k-tiles kt + 1 and kt + 2 are in flight while kt is multiplied.  One
+// gemm_x6_ring<TPM, TPN, NT>: the same product for tiles of TPM x TPN panels with
+// NT / 64 wavefronts (2 x NT / 128, each 32 TPM x 128 TPN / (NT / 128)) and a ring of
+// three LDS buffers filled straight from global memory (global_load_lds_dwordx4: no
+// staging registers), so that the k-tiles kt + 1 and kt + 2 are in flight while kt is
+// multiplied.  One
 // barrier per k-tile: after it, buffer kt is complete and every wavefront is done
 // with buffer kt - 1, which then takes k-tile kt + 2.
 // ---------------------------------------------------------------------------
@@ -590,7 +592,7 @@ void launch_gemm_x6_packed(int tpm, int tpn, const SplitProb* d_probs, const int
   if (tpm == 2 && tpn == 2) x6_ring<2, 2>(d_probs, d_tile_prob, tiles, s);
   else if (tpm == 2) x6_packed<2, 1>(d_probs, d_tile_prob, tiles, s);
   else if (tpn == 2) x6_packed<1, 2>(d_probs, d_tile_prob, tiles, s);
-  else x6_packed<1, 1>(d_probs, d_tile_prob, tiles, s);
+  else x6_ring<1, 1, 256>(d_probs, d_tile_prob, tiles, s);
 }
 
 }  // namespace etdm
