@@ -899,7 +899,8 @@ std::string tune_key(const etdm_handle* h, const Stage& sg) {
     mix(p.beta != 0.0);
   }
   char buf[64];
-  snprintf(buf, sizeof buf, "/%d/%016llx", h->cu_count, (unsigned long long)x);
+  // t2: packed variants timed with their static operands packed apart
+  snprintf(buf, sizeof buf, "/%d/t2/%016llx", h->cu_count, (unsigned long long)x);
   return (h->arch.empty() ? std::string("unknown") : h->arch) + buf;
 }
 
@@ -927,10 +928,23 @@ void tune_file_append(const std::string& key, const TuneEntry& e) {
   fclose(f);
 }
 
+// The pack plan of packed variant v of a stage and its device copies; with sarena, the
+// static operand panels go there (their jobs are not part of a launch).
+etdm_status replan(etdm_handle* h, Stage& sg, int v, char* sarena) {
+  sg.plan_pack(v, sg.arena, sarena ? &h->static_ranges : nullptr, sarena);
+  PackPlan& q = sg.pk[v - 1];
+  CHECK(upload(h, &q.d_jobs, q.jobs));
+  CHECK(upload(h, &q.d_chunk_job, q.chunk_job));
+  CHECK(upload(h, &q.d_probs, q.probs));
+  return upload(h, &q.d_tile_prob, q.tile_prob);
+}
+
 // Plan-time choice among the kernels of an FP64 / BF16x6 stage: each runs on the
 // handle's own buffers (every evaluation overwrites what they write), one warm-up
 // and three timed launches, and the fastest is kept, unless the tuning cache holds
-// the stage already.
+// the stage already.  A packed variant is timed as it will run: operands that change
+// only with the reference orbitals packed apart (into a scratch arena here, whose
+// contents do not matter for the timing), the others packed by each launch.
 etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
   if (h->gemm_tuning != 0) return ETDM_OK;
   hipEvent_t e0, e1;
@@ -954,8 +968,15 @@ etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
     }
     // a complex BF16x6 stage has no grouped split kernel: its packed variants only
     const int v0 = sg->cplx ? V_P11 : V_TILE64;
+    size_t sbytes = 0;
+    if (!sg->no_static)
+      for (int v = V_P11; v < V_COUNT; ++v) sbytes = std::max(sbytes, sg->static_bytes(v, &h->static_ranges));
+    char* sarena = nullptr;
+    if (sbytes > 0 && hipMalloc(reinterpret_cast<void**>(&sarena), sbytes) != hipSuccess) sarena = nullptr;
     int best = v0;
     for (int v = v0; v < V_COUNT && st == ETDM_OK; ++v) {
+      if (sarena && v >= V_P11) st = replan(h, *sg, v, sarena);
+      if (st != ETDM_OK) break;
       sg->variant = v;
       sg->launch(s);
       float ms = 0.f;
@@ -966,6 +987,13 @@ etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
         st = ETDM_E_HIP;
       sg->tuned_ms[v] = ms / 3.f;
       if (sg->tuned_ms[v] < sg->tuned_ms[best]) best = v;
+    }
+    if (sarena) {
+      // back to the plans that pack every operand per launch (plan_static re-plans the
+      // chosen variant once the static panels have their own arena)
+      if (hipStreamSynchronize(s) != hipSuccess) st = ETDM_E_HIP;
+      for (int v = V_P11; v < V_COUNT && st == ETDM_OK; ++v) st = replan(h, *sg, v, nullptr);
+      hipFree(sarena);
     }
     if (st != ETDM_OK) break;
     sg->variant = best;
