@@ -1441,7 +1441,9 @@ __global__ __launch_bounds__(256) void tb_wy_t(EighLarge e) {
 // v_mfma_f64_16x16x4f64 (element r of lane l: row l / 16 + 4 r, column l % 16), which
 // is also the operand layout of the four k-steps of those 16 rows in W = Y_b^T X_p.
 // Only rows below k0 (the block's first reflector index) take part in block b, and the
-// row blocks are dealt out cyclically, so every wavefront has a share of them.
+// row blocks are dealt out cyclically, so every wavefront has a share of them; the
+// steps of the others issue no loads (each step waits for its loads, so an unused load
+// would cost a full L2 round trip).
 //
 // The blocks Y_b are first copied (tb_wy_pack) into the free work matrix as
 // Yc[b][row][0 .. TB_NBW) with rows padded to a multiple of 16 and zeros outside
@@ -1494,6 +1496,12 @@ __global__ __launch_bounds__(WY_NT) void tb_apply_wy(EighLarge e) {
   for (int b = nblk - 1; b >= 0; --b) {
     const int k0 = b * TB_NBW, mb = min(TB_NBW, n - 1 - k0), rlo = k0 + 1;
     const double* Yc = e.Aw + (size_t)b * np16 * TB_NBW;
+    // half row block st of this wavefront takes part in block b (uniform in the
+    // wavefront): its loads are issued only then, so the steps above row k0 cost nothing
+    auto active = [&](int st) {
+      const int rb = wave + WY_W * (st >> 1);
+      return rb < nrb && 16 * rb + 15 >= rlo;
+    };
     // W = Y_b^T X_p over this wavefront's rows; the loads of each step (half a row
     // block) are issued before the products of the step before, and no instruction
     // moves across steps (which bounds the registers held by loads in flight)
@@ -1511,12 +1519,12 @@ __global__ __launch_bounds__(WY_NT) void tb_apply_wy(EighLarge e) {
 #pragma unroll
           for (int it = 0; it < 4; ++it) buf[4 * ks + it] = y[4 * ks * TB_NBW + 16 * it];
       };
-      load_w(0, cur);
+      if (active(0)) load_w(0, cur);
 #pragma unroll
       for (int st = 0; st < 2 * WY_RB; ++st) {
-        if (st + 1 < 2 * WY_RB) load_w(st + 1, nxt);
-        const int t = st >> 1, rb = wave + WY_W * t;
-        if (rb < nrb && 16 * rb + 15 >= rlo) {  // uniform in the wavefront
+        if (st + 1 < 2 * WY_RB && active(st + 1)) load_w(st + 1, nxt);
+        const int t = st >> 1;
+        if (active(st)) {
 #pragma unroll
           for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
@@ -1572,12 +1580,12 @@ __global__ __launch_bounds__(WY_NT) void tb_apply_wy(EighLarge e) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) buf[u] = -y[4 * u];
       };
-      load_u(0, cur);
+      if (active(0)) load_u(0, cur);
 #pragma unroll
       for (int st = 0; st < 2 * WY_RB; ++st) {
-        if (st + 1 < 2 * WY_RB) load_u(st + 1, nxt);
-        const int t = st >> 1, rb = wave + WY_W * t;
-        if (rb < nrb && 16 * rb + 15 >= rlo) {  // uniform in the wavefront
+        if (st + 1 < 2 * WY_RB && active(st + 1)) load_u(st + 1, nxt);
+        const int t = st >> 1;
+        if (active(st)) {
 #pragma unroll
           for (int u = 0; u < 8; ++u)
             x[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[u], W2l[32 * (st & 1) + 4 * u + lk][lr], x[t], 0, 0, 0);
