@@ -540,6 +540,14 @@ __device__ void tb_rows(double* A, int n, int ilo, int jlo, bool upd, const doub
 // start empty
 __global__ void tb_init(EighLarge e, int polled) {
   for (int q = threadIdx.x; q < TB_BAR_WORDS; q += blockDim.x) e.bar[q] = 0u;
+  // The compact-WY blocks count n - 1 reflector columns, one more than the reduction
+  // forms: column n - 2 is an identity reflector, tau = 0 and a zero column, written
+  // here because the reflector matrix may hold anything from an earlier use.
+  const int n = e.n;
+  if (n >= 3) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) e.Vw[(size_t)j * n + (n - 2)] = 0.0;
+    if (threadIdx.x == 0) e.Vw[(size_t)(n - 2) * n + (n - 1)] = 0.0;
+  }
   if (polled)
     for (int q = threadIdx.x; q < 6 * e.n; q += blockDim.x)
       reinterpret_cast<unsigned long long*>(e.pv)[q] = TR_EMPTY;
@@ -1448,7 +1456,9 @@ __global__ __launch_bounds__(256) void tb_wy_t(EighLarge e) {
 // The blocks Y_b are first copied (tb_wy_pack) into the free work matrix as
 // Yc[b][row][0 .. TB_NBW) with rows padded to a multiple of 16 and zeros outside
 // rows (k0, n) and reflectors [0, mb): the product kernel then loads without masks,
-// at offsets that are compile-time constants from one base per row block.
+// at offsets that are compile-time constants from one base per row block.  The update
+// X_p -= Y_b W2 reads a second, negated copy in the order of its fragments
+// (tb_wy_pack_u), so that each of its loads is 512 contiguous bytes.
 constexpr int WY_NT = 512;
 constexpr int WY_W = WY_NT / 64;  // wavefronts
 constexpr int WY_RB = 18;         // row blocks per wavefront
@@ -1464,6 +1474,22 @@ __global__ void tb_wy_pack(EighLarge e) {
     const int row = (int)(rq % np16), b = (int)(rq / np16);
     const int k0 = b * TB_NBW, mb = min(TB_NBW, n - 1 - k0);
     e.Aw[q] = (row > k0 && row < n && c < mb) ? e.Vw[(size_t)row * n + k0 + c] : 0.0;
+  }
+}
+
+// The blocks again, negated and in the order of the update's fragments, into Vw (free
+// once the T factors are formed; npad^2 >= nblk np16 TB_NBW): for block b, row block rb,
+// half h, step u and lane l the value -Y_b[16 rb + l % 16][32 h + 4 u + l / 16], so
+// that every load of the update reads 512 consecutive bytes.
+__global__ void tb_wy_pack_u(EighLarge e) {
+  if (!*e.ok) return;
+  const int n = e.n, np16 = (n + 15) & ~15, nblk = (n - 1 + TB_NBW - 1) / TB_NBW;
+  const int64_t total = (int64_t)nblk * np16 * TB_NBW;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(q & 63), u = (int)((q >> 6) & 7), h = (int)((q >> 9) & 1);
+    const int64_t rbb = q >> 10;  // b np16 / 16 + rb
+    const int64_t row = 16 * rbb + (l & 15);  // row of block b's Yc, counted from block 0
+    e.Vw[q] = -e.Aw[row * TB_NBW + 32 * h + 4 * u + (l >> 4)];
   }
 }
 
@@ -1492,7 +1518,6 @@ __global__ __launch_bounds__(WY_NT) void tb_apply_wy(EighLarge e) {
   const int ldT = e.nkc * TB_NBW;
   // lane offsets (in doubles) of the two fragment patterns inside a row block of Yc
   const int off_w = lk * TB_NBW + lr;  // W = Y_b^T X: row 4 ks + lk, reflector 16 it + lr
-  const int off_u = lr * TB_NBW + lk;  // X -= Y_b W2: row lr, reflector 4 u + lk
   for (int b = nblk - 1; b >= 0; --b) {
     const int k0 = b * TB_NBW, mb = min(TB_NBW, n - 1 - k0), rlo = k0 + 1;
     const double* Yc = e.Aw + (size_t)b * np16 * TB_NBW;
@@ -1574,11 +1599,12 @@ __global__ __launch_bounds__(WY_NT) void tb_apply_wy(EighLarge e) {
     // next step issued before the products of this one
     {
       double cur[8], nxt[8];
+      const double* Yu = e.Vw + (size_t)b * np16 * TB_NBW;  // the negated blocks, fragment order
       auto load_u = [&](int st, double (&buf)[8]) {
         const int rb = min(wave + WY_W * (st >> 1), nrb - 1);
-        const double* y = Yc + (size_t)rb * 16 * TB_NBW + off_u + 32 * (st & 1);
+        const double* y = Yu + ((size_t)rb * 2 + (st & 1)) * 512 + lane;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) buf[u] = -y[4 * u];
+        for (int u = 0; u < 8; ++u) buf[u] = y[64 * u];
       };
       if (active(0)) load_u(0, cur);
 #pragma unroll
@@ -1699,6 +1725,7 @@ bool tb_apply_wy_fits(int n) { return n >= 2 && n <= WY_NMAX; }
 void launch_tb_apply_wy(const EighLarge& e, hipStream_t s) {
   if (!tb_apply_wy_fits(e.n)) return;
   tb_wy_pack<<<1024, 256, 0, s>>>(e);
+  tb_wy_pack_u<<<1024, 256, 0, s>>>(e);
   tb_apply_wy<<<(e.n + 15) / 16, WY_NT, 0, s>>>(e);
 }
 
