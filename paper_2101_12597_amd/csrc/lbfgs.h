@@ -12,7 +12,7 @@
 namespace etdm {
 
 constexpr int LB_MMAX = 8;           // largest memory length m
-constexpr int LB_DOT_BLOCKS = 512;   // workgroups of the vector reductions
+constexpr int LB_DOT_BLOCKS = 2048;  // workgroups of the vector reductions (8 per CU)
 
 // outcome of a line-search step
 enum LbResult : int32_t { LR_CONT = 0, LR_ACCEPT = 1, LR_FAIL = 2, LR_STATUS = 3 };
