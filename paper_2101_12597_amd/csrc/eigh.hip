@@ -221,12 +221,17 @@ static size_t tl_lds_bytes(int n) {
 // column k and is final); every wavefront computes the same reflector scalars
 // with a DPP sum.  Then, between two barriers:
 //   B: p = A_t v over the trailing columns and u = Q v over all rows, as column
-//      sums (coalesced row reads, v broadcast from registers with readlane), by
-//      3 x TL_NCH wavefronts over row chunks, partial sums to LDS;
+//      sums (coalesced row reads), by 3 x TL_NCH wavefronts over row chunks, partial
+//      sums to LDS;
 //   C: K = -tau p.v / 2, w = tau p + K v; A_t -= v w^T + w v^T (8 wavefronts),
 //      QT[k+1:, :] -= tau v u^T (8 wavefronts), rows in groups of 8 loads.
+// The entries of v and w that a row needs come from LDS copies (vw: 256 doubles), read
+// by all lanes at one address (a broadcast); every wavefront writes the same values
+// there, so its own reads never wait for another wavefront.
 // On return vd[0..n-1], ve[0..n-2] hold T.
-__device__ void tl_tridiag(double* A, double* QT, double* vd, double* ve, double* Pm, int n) {
+__device__ void tl_tridiag(double* A, double* QT, double* vd, double* ve, double* Pm, double* vw, int n) {
+  double* vsh = vw;        // v_{k+1+i}, i < L
+  double* wsh = vw + 128;  // w_{k+1+i}
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int k = 0; k < n - 2; ++k) {
@@ -249,6 +254,8 @@ __device__ void tl_tridiag(double* A, double* QT, double* vd, double* ve, double
     if (tau == 0.0) continue;  // the column is already reduced; nothing changes
     const double v0 = lane == 0 ? 1.0 : x0 * inv;  // v_{k+1+lane}
     const double v1 = x1 * inv;                    // v_{k+65+lane}
+    vsh[lane] = v0;
+    vsh[lane + 64] = v1;
     if (wave < 3 * TL_NCH) {
       const int ow = wave % 3, ch = wave / 3;
       const int o = 64 * ow + lane;  // output: o < L -> p_{k+1+o}, else u_{o-L}
@@ -256,24 +263,22 @@ __device__ void tl_tridiag(double* A, double* QT, double* vd, double* ve, double
       const double* base = o < L ? A + (k + 1) * n + (k + 1 + o)
                                  : (o < L + n ? QT + (k + 1) * n + (o - L) : A + (k + 1) * n + (k + 1));
       double acc0 = 0.0, acc1 = 0.0;
-      // rows below 64 take v from v0, the rest from v1: two branch-free ranges with
-      // eight loads in flight per group
-      auto range = [&](const double vs, int lo, int hi, int off) {
-        int jj = lo;
-        for (; jj + 8 <= hi; jj += 8) {
-          double a[8];
+      // groups of eight rows, their loads in flight together
+      int jj = jb;
+      for (; jj + 8 <= je; jj += 8) {
+        double a[8], vv[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) a[u] = base[(jj + u) * n];
-#pragma unroll
-          for (int u = 0; u < 8; u += 2) {
-            acc0 += a[u] * tl_readlane(vs, jj + u - off);
-            acc1 += a[u + 1] * tl_readlane(vs, jj + u + 1 - off);
-          }
+        for (int u = 0; u < 8; ++u) {
+          a[u] = base[(jj + u) * n];
+          vv[u] = vsh[jj + u];
         }
-        for (; jj < hi; ++jj) acc0 += base[jj * n] * tl_readlane(vs, jj - off);
-      };
-      range(v0, jb, min(je, 64), 0);
-      range(v1, max(jb, 64), je, 64);
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          acc0 += a[u] * vv[u];
+          acc1 += a[u + 1] * vv[u + 1];
+        }
+      }
+      for (; jj < je; ++jj) acc0 += base[jj * n] * vsh[jj];
       if (o < L + n) Pm[ch * TL_PMLD + o] = acc0 + acc1;
     }
     __syncthreads();
@@ -297,35 +302,35 @@ __device__ void tl_tridiag(double* A, double* QT, double* vd, double* ve, double
     p1 *= tau;
     const double K = -0.5 * tau * tl_wave_sum(p0 * v0 + p1 * v1);
     const double w0 = p0 + K * v0, w1 = p1 + K * v1;
+    wsh[lane] = w0;
+    wsh[lane + 64] = w1;
     const int grp = wave >> 3, cb = wave & 1, rc = (wave >> 1) & 3;
     const int col = 64 * cb + lane;
     const int rb = rc * L / 4, re = (rc + 1) * L / 4;
-    // rows below 64 take v, w from v0, w0, the rest from v1, w1: branch-free ranges in
     // groups of 8 rows whose loads are issued before any of their stores
     if (grp == 0) {
       const int j = k + 1 + min(col, L - 1);
       const double vj = cb ? v1 : v0, wj = cb ? w1 : w0;
-      auto rows = [&](const double vs, const double ws, int lo, int hi, int off) {
-        int ii = lo;
-        for (; ii + 8 <= hi; ii += 8) {
-          double x[8];
+      int ii = rb;
+      for (; ii + 8 <= re; ii += 8) {
+        double x[8], vv[8], ww[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) x[u] = A[(k + 1 + ii + u) * n + j];
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            x[u] -= tl_readlane(vs, ii + u - off) * wj + tl_readlane(ws, ii + u - off) * vj;
-          if (col < L)
-#pragma unroll
-            for (int u = 0; u < 8; ++u) A[(k + 1 + ii + u) * n + j] = x[u];
+        for (int u = 0; u < 8; ++u) {
+          x[u] = A[(k + 1 + ii + u) * n + j];
+          vv[u] = vsh[ii + u];
+          ww[u] = wsh[ii + u];
         }
-        for (; ii < hi; ++ii) {
-          double* a = A + (k + 1 + ii) * n + j;
-          const double x = *a - (tl_readlane(vs, ii - off) * wj + tl_readlane(ws, ii - off) * vj);
-          if (col < L) *a = x;
-        }
-      };
-      rows(v0, w0, rb, min(re, 64), 0);
-      rows(v1, w1, max(rb, 64), re, 64);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] -= vv[u] * wj + ww[u] * vj;
+        if (col < L)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) A[(k + 1 + ii + u) * n + j] = x[u];
+      }
+      for (; ii < re; ++ii) {
+        double* a = A + (k + 1 + ii) * n + j;
+        const double x = *a - (vsh[ii] * wj + wsh[ii] * vj);
+        if (col < L) *a = x;
+      }
     } else {
       const int r = min(col, n - 1);
       double ur = 0.0;
@@ -337,26 +342,25 @@ __device__ void tl_tridiag(double* A, double* QT, double* vd, double* ve, double
         for (int ch = 0; ch < TL_NCH; ++ch) ur += pu[ch];
       }
       const double tu = tau * ur;
-      auto rows = [&](const double vs, int lo, int hi, int off) {
-        int jj = lo;
-        for (; jj + 8 <= hi; jj += 8) {
-          double x[8];
+      int jj = rb;
+      for (; jj + 8 <= re; jj += 8) {
+        double x[8], vv[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) x[u] = QT[(k + 1 + jj + u) * n + r];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) x[u] -= tl_readlane(vs, jj + u - off) * tu;
-          if (col < n)
-#pragma unroll
-            for (int u = 0; u < 8; ++u) QT[(k + 1 + jj + u) * n + r] = x[u];
+        for (int u = 0; u < 8; ++u) {
+          x[u] = QT[(k + 1 + jj + u) * n + r];
+          vv[u] = vsh[jj + u];
         }
-        for (; jj < hi; ++jj) {
-          double* q = QT + (k + 1 + jj) * n + r;
-          const double x = *q - tl_readlane(vs, jj - off) * tu;
-          if (col < n) *q = x;
-        }
-      };
-      rows(v0, rb, min(re, 64), 0);
-      rows(v1, max(rb, 64), re, 64);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] -= vv[u] * tu;
+        if (col < n)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) QT[(k + 1 + jj + u) * n + r] = x[u];
+      }
+      for (; jj < re; ++jj) {
+        double* q = QT + (k + 1 + jj) * n + r;
+        const double x = *q - vsh[jj] * tu;
+        if (col < n) *q = x;
+      }
     }
     __syncthreads();
   }
@@ -521,7 +525,7 @@ __global__ __launch_bounds__(TL_NT) void eigh_tridiag_lds(const EighProb* __rest
   }
 
   // 1. tridiagonal T and Q^T
-  tl_tridiag(R1, R2, vd, ve, Pm, n);
+  tl_tridiag(R1, R2, vd, ve, Pm, xs, n);  // xs: free until the multisection
   __syncthreads();
 
   // 2. splitting, brackets, multisection down to TL_BISECT_TOL ||T||
