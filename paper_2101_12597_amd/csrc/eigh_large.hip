@@ -1586,12 +1586,15 @@ __global__ __launch_bounds__(WY_NT) void tb_apply_wy(EighLarge e) {
         Tl[i][c] = (i < mb && c < mb && c >= i) ? Tb[(size_t)i * ldT + c] : 0.0;
       }
       __syncthreads();
-      for (int q = threadIdx.x; q < TB_NBW * 16; q += WY_NT) {
-        const int i = q >> 4, j = q & 15;
-        double sum = 0.0;
-#pragma unroll 8
-        for (int c = 0; c < TB_NBW; ++c) sum += Tl[i][c] * Wl[c][j];
-        W2l[i][j] = sum;
+      // on the matrix cores: wavefront w < 4 forms rows [16 w, 16 w + 16) of W2
+      if (wave < 4) {
+        d4v c4 = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < TB_NBW / 4; ++ks)
+          c4 = __builtin_amdgcn_mfma_f64_16x16x4f64(Tl[16 * wave + lr][4 * ks + lk], Wl[4 * ks + lk][lr], c4, 0, 0,
+                                                    0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) W2l[16 * wave + lk + 4 * r][lr] = c4[r];
       }
     }
     __syncthreads();
