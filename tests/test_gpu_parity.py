@@ -428,6 +428,41 @@ def test_large_rotation_angles_prescribed_spectrum(precision, tol_e, tol_g):
     assert dE < tol_e and dg < tol_g and de < 10 * tol_g
 
 
+def test_large_rotation_angles_split_energy_side():
+    """The mixed mode with every instance at N >= 512, where the contractions E depends
+    on run as BF16x6 splits (V = X^T B stays FP64: split, it misses the gradient target
+    here by 3x): one
+    instance M = 1280, N = 512 with distinct prescribed angles from 0 to 420 rad (small
+    ones, the quadrature range, the closed forms beyond it), against the definition
+    path.  The angles are distinct: a many-fold multiple eigenvalue of P is a case for
+    the eigensolver, not for the products."""
+    M, N = 1280, 512
+    head = [0.0, 1e-7, 1e-3, 0.3, 0.49, 0.51]
+    tail = [150.0, 200.0, 300.0, 420.0]
+    angles = np.concatenate([head, np.linspace(0.7, 60.0, N - len(head) - len(tail)), tail])
+    wl = Workload(903, "prescribed angles, split energy side", "real_ov", 0.5, False)
+    H0 = chain_hamiltonian(M, rng_for(903, 0, 0))
+    C0 = haar_orthogonal(M, rng_for(903, 0, 1))
+    rng = rng_for(903, 0, 2)
+    sig = rng.permutation(angles)
+    X = haar_orthogonal(N, rng)
+    Z = haar_orthogonal(M - N, rng)[:, :N]
+    wl.instances.append(Instance(M=M, N=N, f=binary_occupations(M, N), C0=C0, A=(X * sig) @ Z.T, H0=H0))
+    params = O.parity_params(wl)
+    print("[case] prescribed angles up to 420 rad, M = 1280, N = 512, mixed", flush=True)
+    h, _ = make_handle(wl, "mixed")
+    names = [st["name"] for st in h.stage_info()]
+    kernels = {names[k["index"]]: k["kernel"] for k in h.stage_kernels() if k["kernel"]}
+    E, g = energy_grad(h, wl, params)
+    h.close()
+    assert not kernels["gemm_CXV"].startswith("fp64") and kernels["gemm_V_funcs"].startswith("fp64"), kernels
+    E_ref, g_ref = definition_oracle("prescribed_split", wl, params)
+    dE, dg, de = worst_errors(wl, E, g, E_ref, g_ref)
+    print(f"[result] prescribed angles, split energy side: |dE|/Ne = {dE:.3e}, rel |dg| = {dg:.3e}, "
+          f"element-wise {de:.3e}")
+    assert dE < 1e-8 and dg < 1e-6 and de < ELEM_TOL["mixed"]
+
+
 @pytest.mark.parametrize("precision,tol_e,tol_g", [("fp64", 1e-11, 1e-9), ("mixed", 1e-8, 1e-6)])
 def test_config3_scaled_to_large_angles(precision, tol_e, tol_g):
     """Config 3 with its parity-point B scaled so that the largest rotation angle is
