@@ -69,7 +69,8 @@ void launch_tb_wy_t(const EighLarge& e, hipStream_t s);
 // after launch_tb_wy_t; for n up to tb_apply_wy_fits (else the grouped GEMM blocks).
 bool tb_apply_wy_fits(int n);
 void launch_tb_apply_wy(const EighLarge& e, hipStream_t s);
-// After G = Z^T Z has been formed in Aw: *ok = 0 unless max|G - I| <= 1e-6; Aw <- (3 I - G) / 2.
+// After G = Z^T Z has been formed in Aw: *ok = 0 unless max|G - I| <= 1e-6; Aw <- (I - G) / 2
+// (the Newton-Schulz step is then X = Z + Z Aw).
 void launch_tb_orth_check(const EighLarge& e, hipStream_t s);
 // After R = sym(P) X has been formed in Aw: *ok = 0 unless max|R - X diag(w)| <= 1e-11 ||sym(P)||_F.
 void launch_tb_final_check(const EighLarge& e, hipStream_t s);

@@ -6,7 +6,7 @@
 //      barrier per step (below);
 //   2. tb_bisect: eigenvalue brackets of T by multisection on Sturm counts;
 //   3. tb_vectors: eigenvectors of T by twisted factorizations, one lane each;
-//   4. on the host stream: Z^T Z and one Newton-Schulz step (grouped GEMMs), the
+//   4. on the host stream: Z^T Z and one Newton-Schulz step (GEMMs), the
 //      back-transform X = Q Z in compact-WY blocks of TB_NBW reflectors, and a
 //      final residual check of sym(P) X = X diag(w).
 // Every check that fails leaves *ok = 0.
@@ -1333,7 +1333,8 @@ __global__ __launch_bounds__(TV_NT) void tb_vectors(EighLarge e) {
 }
 
 // Orthogonality of Z over many workgroups: max |G - I| (G = Z^T Z in Aw) into
-// scan[0] (atomic max on the bit pattern), and G <- (3 I - G) / 2.
+// scan[0] (atomic max on the bit pattern), and G <- (I - G) / 2, the factor of the
+// Newton-Schulz correction X = Z (3 I - G) / 2 = Z + Z (I - G) / 2.
 __global__ __launch_bounds__(256) void tb_orth_scan(EighLarge e) {
   __shared__ double red[4];
   if (!*e.ok) return;
@@ -1343,7 +1344,7 @@ __global__ __launch_bounds__(256) void tb_orth_scan(EighLarge e) {
     const int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
     const double g = e.Aw[idx], dlt = i == j ? 1.0 : 0.0;
     m = fmax(m, tl_err(fabs(g - dlt)));
-    e.Aw[idx] = 1.5 * dlt - 0.5 * g;
+    e.Aw[idx] = 0.5 * (dlt - g);
   }
   m = block_max<256>(m, red);
   if (threadIdx.x == 0) atomicMax(reinterpret_cast<unsigned long long*>(e.scan), (unsigned long long)__double_as_longlong(m));
