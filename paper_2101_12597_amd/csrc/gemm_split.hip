@@ -279,13 +279,19 @@ __global__ __launch_bounds__(NT) void gemm_x6_packed(const SplitProb* __restrict
 // gemm_x6_ring<TPM, TPN, NT>: the same product for tiles of TPM x TPN panels with
 // NT / 64 wavefronts (2 x NT / 128, each 32 TPM x 128 TPN / (NT / 128)) and a ring of
 // three LDS buffers filled straight from global memory (global_load_lds_dwordx4: no
-// staging registers), so that the k-tiles kt + 1 and kt + 2 are in flight while kt is
-// multiplied.  One
-// barrier per k-tile: after it, buffer kt is complete and every wavefront is done
-// with buffer kt - 1, which then takes k-tile kt + 2.
+// staging registers).  While k-tile kt is multiplied from registers, k-tile kt + 1 is
+// read from LDS into the registers its products free and k-tiles kt + 2 and kt + 3
+// are in flight.  One barrier per k-tile: after it, buffer kt + 1 is complete and
+// every wavefront is done with buffer kt, which then takes k-tile kt + 3.
 // ---------------------------------------------------------------------------
 constexpr int RING_NT = 512;
 constexpr int RING_NBUF = 3;
+
+// s_waitcnt immediate: vmcnt(vm) (6 bits, split over [3:0] and [15:14]), expcnt not
+// waited on, lgkmcnt(0) when lgkm0 else not waited on
+constexpr int ring_wait(int vm, bool lgkm0) {
+  return (vm & 15) | ((vm >> 4) << 14) | 0x0070 | (lgkm0 ? 0 : 0x0f00);
+}
 
 template <int TPM, int TPN, int NT>
 __global__ __launch_bounds__(NT) void gemm_x6_ring(const SplitProb* __restrict__ probs,
@@ -296,6 +302,7 @@ __global__ __launch_bounds__(NT) void gemm_x6_ring(const SplitProb* __restrict__
   constexpr int GROUPS = (TPM + TPN) * PK_CHUNK / 512;  // 1 KB groups of a k-tile (64 lanes x 16 bytes)
   constexpr int GPW = GROUPS / (NT / 64);               // groups per wavefront
   static_assert(GROUPS % (NT / 64) == 0 && PK_CHUNK % 512 == 0, "k-tile groups per wavefront");
+  static_assert(2 * GPW < 64, "vmcnt immediates of the ring waits");
   extern __shared__ __attribute__((aligned(16))) __bf16 ring_lds[];
   const int tile = tile_prob[total + blockIdx.x];  // the plan's workgroup -> tile order
   const SplitProb& p = probs[tile_prob[tile]];
@@ -344,39 +351,31 @@ __global__ __launch_bounds__(NT) void gemm_x6_ring(const SplitProb* __restrict__
     return (trow >> 6) * PK_CHUNK + (s * PK_R + row) * PK_K + pk_phys(lo, row) * 8;
   };
 
+  // the fragments of one k-tile for this wavefront's MFMAs
+  struct Frag {
+    bf8 b[PK_S][NBN];
+    bf8 a[PK_S][NBM];
+  };
+  auto load_b = [&](Frag& f, int buf, int s) {
+    const __bf16* Bs = ring_lds + buf * BUF + OPERA;
+#pragma unroll
+    for (int j = 0; j < NBN; ++j) f.b[s][j] = *reinterpret_cast<const bf8*>(Bs + frag(wcol, s, j));
+  };
+  auto load_a = [&](Frag& f, int buf, int s) {
+    const __bf16* As = ring_lds + buf * BUF;
+#pragma unroll
+    for (int i = 0; i < NBM; ++i) f.a[s][i] = *reinterpret_cast<const bf8*>(As + frag(wrow, s, i));
+  };
+  // the product of A slice sa with B slice sb
+  auto mma = [&](const Frag& f, int sa, int sb) {
+#pragma unroll
+    for (int i = 0; i < NBM; ++i)
+#pragma unroll
+      for (int j = 0; j < NBN; ++j)
+        c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.a[sa][i], f.b[sb][j], c[i][j], 0, 0, 0);
+  };
   const int nk = p.ktiles;
-  if (nk > 0) issue(0, 0);
-  if (nk > 1) issue(1, 1);
-  for (int kt = 0; kt < nk; ++kt) {
-    // this wavefront's pieces of k-tile kt are in (at most k-tile kt + 1 still
-    // loading), then a bare barrier: __syncthreads would also wait for the loads of
-    // kt + 1
-    if (kt + 1 < nk)
-      __builtin_amdgcn_s_waitcnt(0x0f70 | GPW);  // vmcnt(GPW); expcnt, lgkmcnt not waited on
-    else
-      __builtin_amdgcn_s_waitcnt(0x0f70);        // vmcnt(0)
-    __builtin_amdgcn_s_barrier();
-    if (kt + 2 < nk) issue(kt + 2, (kt + 2) % RING_NBUF);
-    const __bf16* As = ring_lds + (kt % RING_NBUF) * BUF;
-    const __bf16* Bs = As + OPERA;
-    bf8 bv[PK_S][NBN];
-#pragma unroll
-    for (int s = 0; s < PK_S; ++s)
-#pragma unroll
-      for (int j = 0; j < NBN; ++j) bv[s][j] = *reinterpret_cast<const bf8*>(Bs + frag(wcol, s, j));
-#pragma unroll
-    for (int sa = PK_S - 1; sa >= 0; --sa) {
-      bf8 av[NBM];
-#pragma unroll
-      for (int i = 0; i < NBM; ++i) av[i] = *reinterpret_cast<const bf8*>(As + frag(wrow, sa, i));
-#pragma unroll
-      for (int sb = PK_S - 1 - sa; sb >= 0; --sb)
-#pragma unroll
-        for (int i = 0; i < NBM; ++i)
-#pragma unroll
-          for (int j = 0; j < NBN; ++j)
-            c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[sb][j], c[i][j], 0, 0, 0);
-    }
+  auto flush = [&](int kt) {
     if ((kt + 1) % X_FLUSH == 0 || kt + 1 == nk) {
 #pragma unroll
       for (int i = 0; i < NBM; ++i)
@@ -386,6 +385,87 @@ __global__ __launch_bounds__(NT) void gemm_x6_ring(const SplitProb* __restrict__
           for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)c[i][j][r];
           c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
         }
+    }
+  };
+  // The six slice products of a k-tile, smallest terms first: (2,0) (1,1) (1,0) (0,2)
+  // (0,1) (0,0).  Step kt < nk - 1 runs them on k-tile kt's fragments (in registers,
+  // the last A slice possibly still arriving) and reads k-tile kt + 1's in between,
+  // each fragment once the one it replaces has had its last product, so that the
+  // next k-tile's reads overlap this one's MFMAs in the registers of one k-tile.
+  // After the first product: wait until this wavefront's reads of k-tile kt are in
+  // and its loads of kt + 1 have landed, then a bare barrier (__syncthreads would also
+  // wait for the loads of kt + 2).  After it every wavefront is done with buffer kt,
+  // which takes k-tile kt + 3, and k-tile kt + 1 is complete.  sched_barrier keeps
+  // the compiler from moving reads ahead of the products that free their registers.
+  auto step = [&](int kt, const Frag& cur, Frag& nxt) {
+    mma(cur, 2, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    if (kt + 2 < nk)
+      __builtin_amdgcn_s_waitcnt(ring_wait(GPW, true));
+    else
+      __builtin_amdgcn_s_waitcnt(ring_wait(0, true));
+    __builtin_amdgcn_s_barrier();
+    if (kt + 3 < nk) issue(kt + 3, kt % RING_NBUF);
+    const int nb = (kt + 1) % RING_NBUF;
+    load_b(nxt, nb, 0);
+    load_a(nxt, nb, 2);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(cur, 1, 1);
+    mma(cur, 1, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_a(nxt, nb, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(cur, 0, 2);
+    __builtin_amdgcn_sched_barrier(0);
+    load_b(nxt, nb, 2);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(cur, 0, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    load_b(nxt, nb, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(cur, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_a(nxt, nb, 0);
+    flush(kt);
+  };
+  auto last = [&](int kt, const Frag& cur) {
+    mma(cur, 2, 0);
+    mma(cur, 1, 1);
+    mma(cur, 1, 0);
+    mma(cur, 0, 2);
+    mma(cur, 0, 1);
+    mma(cur, 0, 0);
+    flush(kt);
+  };
+  Frag f0, f1;
+  if (nk > 0) {
+    issue(0, 0);
+    if (nk > 1) issue(1, 1);
+    if (nk > 2) issue(2, 2);
+    // this wavefront's loads of k-tile 0 landed (those of 1 and 2 may be in flight)
+    if (nk > 2)
+      __builtin_amdgcn_s_waitcnt(ring_wait(2 * GPW, false));
+    else if (nk > 1)
+      __builtin_amdgcn_s_waitcnt(ring_wait(GPW, false));
+    else
+      __builtin_amdgcn_s_waitcnt(ring_wait(0, false));
+    __builtin_amdgcn_s_barrier();
+#pragma unroll
+    for (int s = 0; s < PK_S; ++s) {
+      load_b(f0, 0, s);
+      load_a(f0, 0, PK_S - 1 - s);
+    }
+    int kt = 0;
+    for (; kt + 2 < nk; kt += 2) {
+      step(kt, f0, f1);
+      step(kt + 1, f1, f0);
+    }
+    // one or two k-tiles left, the last without a successor
+    if (kt + 1 < nk) {
+      step(kt, f0, f1);
+      last(kt + 1, f1);
+    } else {
+      last(kt, f0);
     }
   }
 
