@@ -1125,7 +1125,7 @@ constexpr int TV_PF = 16;
 
 // The twisted factorization at lam for the pair's eigenvalue (this lane: odd or even);
 // writes z / ||z|| into Z (column pointer, ld n) and returns gamma_r / ||z||^2.
-__device__ double tv_twisted(const double* d, const double* ee, const double* e2, int b0, int b1, double lam,
+__device__ __forceinline__ double tv_twisted(const double* d, const double* ee, const double* e2, int b0, int b1, double lam,
                              double pivmin, double* Z, double* W, int n, bool odd) {
   // 1. pivots: D+ forward from b0 (even lane, into Z), D- backward from b1 - 1 (odd, into W)
   {
