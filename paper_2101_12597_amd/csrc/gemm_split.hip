@@ -389,9 +389,10 @@ __global__ __launch_bounds__(NT) void gemm_x6_ring(const SplitProb* __restrict__
   };
   // The six slice products of a k-tile, smallest terms first: (2,0) (1,1) (1,0) (0,2)
   // (0,1) (0,0).  Step kt < nk - 1 runs them on k-tile kt's fragments (in registers,
-  // the last A slice possibly still arriving) and reads k-tile kt + 1's in between,
-  // each fragment once the one it replaces has had its last product, so that the
-  // next k-tile's reads overlap this one's MFMAs in the registers of one k-tile.
+  // the last A slice possibly still arriving) and reads k-tile kt + 1's in between:
+  // B slice 0 right after the barrier, every other fragment once the one it replaces
+  // has had its last product, so that the next k-tile's reads overlap this one's
+  // MFMAs in the registers of about one k-tile.
   // After the first product: wait until this wavefront's reads of k-tile kt are in
   // and its loads of kt + 1 have landed, then a bare barrier (__syncthreads would also
   // wait for the loads of kt + 2).  After it every wavefront is done with buffer kt,
