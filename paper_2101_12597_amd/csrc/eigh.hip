@@ -997,7 +997,7 @@ void launch_eigh_real_lds(const EighProb* d_probs, int nprob, int* d_status, hip
   const size_t bytes = tl_lds_bytes(EIGH_LDS_MAX);
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&eigh_tridiag_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&eigh_tridiag_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)bytes);
     attr = true;
   }
@@ -1017,7 +1017,7 @@ void launch_eigh_herm_tridiag(const EighProb* d_probs, int nprob, int nmax, int*
   const size_t bytes = ht_lds_bytes(nmax);
   static size_t attr = 0;
   if (bytes > attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&eigh_herm_tridiag), hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&eigh_herm_tridiag), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)bytes);
     attr = bytes;
   }

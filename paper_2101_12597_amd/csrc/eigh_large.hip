@@ -1655,7 +1655,7 @@ static void tb_cap_grid(EighLarge& e, int cu_count) {
   const bool reg = tb_use_reg(e);
   const size_t lds = tb_reduce_lds(e.n);
   // the dynamic LDS above the default limit must be allowed before the query
-  hipFuncSetAttribute(reg ? reinterpret_cast<const void*>(&tb_reduce_reg) : reinterpret_cast<const void*>(&tb_reduce),
+  (void)hipFuncSetAttribute(reg ? reinterpret_cast<const void*>(&tb_reduce_reg) : reinterpret_cast<const void*>(&tb_reduce),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
@@ -1687,20 +1687,20 @@ void launch_tb_reduce(const EighLarge& e, hipStream_t s) {
   const size_t eig_lds = sizeof(double) * 3 * (size_t)n;
   static size_t attr_r = 0, attr_e = 0;
   if (lds > attr_r) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_reduce), hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_reduce), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
     attr_r = lds;
   }
   if (eig_lds > attr_e) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_bisect), hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_bisect), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)eig_lds);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_vectors), hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_vectors), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)eig_lds);
     attr_e = eig_lds;
   }
   static size_t attr_g = 0;
   if (lds > attr_g) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_reduce_reg), hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&tb_reduce_reg), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
     attr_g = lds;
   }
@@ -1740,9 +1740,9 @@ void launch_eigh_large(const EighLarge& e, int max_sweeps, int* status, hipStrea
   const size_t inner_lds = sizeof(double) * (2 * SUB * SUB + SUB);
   const size_t upd_lds = sizeof(double) * 2 * SUB * LD;
   if (!g_attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&bjl_inner), hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&bjl_inner), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)inner_lds);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&bjl_update), hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&bjl_update), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)upd_lds);
     g_attr = true;
   }

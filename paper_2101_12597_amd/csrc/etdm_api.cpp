@@ -606,7 +606,7 @@ constexpr int TIMER_RING = 64;
 void timer_collect(StageTimer& t, int i) {
   if (!t.pending[i]) return;
   float ms = 0.f;
-  hipEventSynchronize(t.ev1[i]);
+  (void)hipEventSynchronize(t.ev1[i]);
   if (hipEventElapsedTime(&ms, t.ev0[i], t.ev1[i]) == hipSuccess) {
     t.total_ms += ms;
     ++t.launches;
@@ -627,12 +627,12 @@ struct Timed {
     StageTimer& t = h->timers[id];
     slot = t.next;
     timer_collect(t, slot);
-    hipEventRecord(t.ev0[slot], s);
+    (void)hipEventRecord(t.ev0[slot], s);
   }
   ~Timed() {
     if (!on) return;
     StageTimer& t = h->timers[id];
-    hipEventRecord(t.ev1[slot], s);
+    (void)hipEventRecord(t.ev1[slot], s);
     t.pending[slot] = 1;
     t.next = (slot + 1) % TIMER_RING;
   }
@@ -992,7 +992,7 @@ etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
       // chosen variant once the static panels have their own arena)
       if (hipStreamSynchronize(s) != hipSuccess) st = ETDM_E_HIP;
       for (int v = V_P11; v < V_COUNT && st == ETDM_OK; ++v) st = replan(h, *sg, v, nullptr);
-      hipFree(sarena);
+      (void)hipFree(sarena);
     }
     if (st != ETDM_OK) break;
     sg->variant = best;
@@ -1002,8 +1002,8 @@ etdm_status tune_stages(etdm_handle* h, hipStream_t s) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     if (g_tune.emplace(key, e).second) tune_file_append(key, e);
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != ETDM_OK) return fail(h, st, "GEMM kernel tuning failed");
   HIPCHK(h, hipGetLastError());
   return ETDM_OK;
@@ -1739,8 +1739,8 @@ etdm_status build_z_plan(etdm_handle* h) {
 
 void free_timers(etdm_handle* h) {
   for (StageTimer& t : h->timers) {
-    for (hipEvent_t e : t.ev0) hipEventDestroy(e);
-    for (hipEvent_t e : t.ev1) hipEventDestroy(e);
+    for (hipEvent_t e : t.ev0) (void)hipEventDestroy(e);
+    for (hipEvent_t e : t.ev1) (void)hipEventDestroy(e);
     t.ev0.clear();
     t.ev1.clear();
     t.pending.clear();
@@ -1749,22 +1749,22 @@ void free_timers(etdm_handle* h) {
 
 void free_lb_graphs(etdm_handle* h) {
   for (int i = 0; i < 3; ++i) {
-    if (h->lbg_exec[i]) hipGraphExecDestroy(h->lbg_exec[i]);
-    if (h->lbg[i]) hipGraphDestroy(h->lbg[i]);
+    if (h->lbg_exec[i]) (void)hipGraphExecDestroy(h->lbg_exec[i]);
+    if (h->lbg[i]) (void)hipGraphDestroy(h->lbg[i]);
     h->lbg_exec[i] = nullptr;
     h->lbg[i] = nullptr;
   }
-  if (h->lbg_back_exec) hipGraphExecDestroy(h->lbg_back_exec);
-  if (h->lbg_back) hipGraphDestroy(h->lbg_back);
+  if (h->lbg_back_exec) (void)hipGraphExecDestroy(h->lbg_back_exec);
+  if (h->lbg_back) (void)hipGraphDestroy(h->lbg_back);
   h->lbg_back_exec = nullptr;
   h->lbg_back = nullptr;
 }
 
 void free_graph(etdm_handle* h) {
-  if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
-  if (h->graph) hipGraphDestroy(h->graph);
-  if (h->graph2_exec) hipGraphExecDestroy(h->graph2_exec);
-  if (h->graph2) hipGraphDestroy(h->graph2);
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->graph2_exec) (void)hipGraphExecDestroy(h->graph2_exec);
+  if (h->graph2) (void)hipGraphDestroy(h->graph2);
   h->graph_exec = h->graph2_exec = nullptr;
   h->graph = h->graph2 = nullptr;
   free_lb_graphs(h);
@@ -1773,13 +1773,13 @@ void free_graph(etdm_handle* h) {
 void free_handle(etdm_handle* h) {
   if (!h) return;
   free_graph(h);
-  if (h->cap_stream) hipStreamDestroy(h->cap_stream);
-  if (h->ok_host) hipHostFree(h->ok_host);
-  if (h->ss_s_host) hipHostFree(h->ss_s_host);
-  if (h->lb_sum) hipHostFree(h->lb_sum);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->ok_host) (void)hipHostFree(h->ok_host);
+  if (h->ss_s_host) (void)hipHostFree(h->ss_s_host);
+  if (h->lb_sum) (void)hipHostFree(h->lb_sum);
   free_timers(h);
-  if (h->base) hipFree(h->base);
-  for (void* p : h->dev_allocs) hipFree(p);
+  if (h->base) (void)hipFree(h->base);
+  for (void* p : h->dev_allocs) (void)hipFree(p);
   delete h;
 }
 
@@ -1849,7 +1849,7 @@ void ov_basis(etdm_handle* h, hipStream_t s, int want_exp) {
 
 void ov_front_fallback(etdm_handle* h, hipStream_t s) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  hipStreamIsCapturing(s, &cs);
+  (void)hipStreamIsCapturing(s, &cs);
   ov_front(h, s, cs == hipStreamCaptureStatusNone ? 1 : 2);
 }
 
@@ -2172,7 +2172,7 @@ void new_reference(etdm_handle* h, hipStream_t s) {
   z_exponential_part(h, s);
   h->z_C.launch(s);
   for (int i = 0; i < h->n_inst; ++i)
-    hipMemcpyAsync(h->zb[i].C0, h->zb[i].C, 2 * sizeof(double) * h->M[i] * h->M[i], hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(h->zb[i].C0, h->zb[i].C, 2 * sizeof(double) * h->M[i] * h->M[i], hipMemcpyDeviceToDevice, s);
   pack_static(h, s);
 }
 
@@ -2296,7 +2296,7 @@ etdm_status apply_overlap(etdm_handle* h, const void* S, hipStream_t s) {
   if (hipMalloc(reinterpret_cast<void**>(&ws), (size_t)(doubles + h->n_inst) * sizeof(double)) != hipSuccess)
     return fail(h, ETDM_E_NOMEM, "overlap workspace");
   if (hipHostMalloc(reinterpret_cast<void**>(&resid_host), h->n_inst * sizeof(double)) != hipSuccess) {
-    hipFree(ws);
+    (void)hipFree(ws);
     return fail(h, ETDM_E_NOMEM, "overlap workspace");
   }
   struct Release {  // waits for the stream, also on an early error return
@@ -2304,8 +2304,8 @@ etdm_status apply_overlap(etdm_handle* h, const void* S, hipStream_t s) {
     hipStream_t s;
     ~Release() {
       (void)hipStreamSynchronize(s);
-      hipFree(a);
-      hipHostFree(b);
+      (void)hipFree(a);
+      (void)hipHostFree(b);
     }
   } release{ws, resid_host, s};
   double* resid_dev = ws + doubles;
@@ -2603,7 +2603,7 @@ etdm_status etdm_create(etdm_handle** out, const etdm_desc* d, const void* H0, c
 
 etdm_status etdm_destroy(etdm_handle* h) {
   if (!h) return ETDM_E_ARG;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   free_handle(h);
   return ETDM_OK;
 }
