@@ -664,7 +664,7 @@ void launch_gemm_f64_packed(int tpm, int tpn, const SplitProb* d_probs, const in
   if (tpm == 2 && tpn == 2) f64_ring<2, 2, 512>(d_probs, d_tile_prob, tiles, s);
   else if (tpm == 2) f64_ring<2, 1, 512>(d_probs, d_tile_prob, tiles, s);
   else if (tpn == 2) f64_ring<1, 2, 512>(d_probs, d_tile_prob, tiles, s);
-  else f64_ring<1, 1, 256>(d_probs, d_tile_prob, tiles, s);
+  else f64_ring<1, 1, 512>(d_probs, d_tile_prob, tiles, s);
 }
 
 void launch_gemm_x6_packed(int tpm, int tpn, const SplitProb* d_probs, const int* d_tile_prob, int tiles,
