@@ -31,7 +31,7 @@
 // double-buffered in LDS with the next one fetched into registers during the
 // MFMAs; tiles are ordered in groups of X_GROUP tile rows and dealt out so that
 // each XCD works on a contiguous range.  gemm_x6_ring (BF16x6 128 x 128 with eight
-// wavefronts and 64 x 64 with four) and gemm_f64_ring (FP64, every tile shape) fill
+// wavefronts, and 64 x 64 also with eight) and gemm_f64_ring (FP64, every tile shape) fill
 // their LDS buffers straight from global memory instead (global_load_lds_dwordx4);
 // the 128 x 64 and 64 x 128 BF16x6 tiles keep the register-staged kernel, whose two
 // workgroups per CU the ring's three buffers (108 KB) would not leave room for.
@@ -673,7 +673,7 @@ void launch_gemm_x6_packed(int tpm, int tpn, const SplitProb* d_probs, const int
   if (tpm == 2 && tpn == 2) x6_ring<2, 2>(d_probs, d_tile_prob, tiles, s);
   else if (tpm == 2) x6_packed<2, 1>(d_probs, d_tile_prob, tiles, s);
   else if (tpn == 2) x6_packed<1, 2>(d_probs, d_tile_prob, tiles, s);
-  else x6_ring<1, 1, 256>(d_probs, d_tile_prob, tiles, s);
+  else x6_ring<1, 1, 512>(d_probs, d_tile_prob, tiles, s);
 }
 
 }  // namespace etdm
